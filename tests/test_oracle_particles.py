@@ -1,0 +1,283 @@
+"""Pins of the oracle's creation-rate tables, Philox stream and particle passes
+(postulate II, rules 1 and 2 of Sec. 2.1, absorbing boundaries of Sec. 3)."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats as sst
+
+from paper_1806_00082_amd import inputs
+
+HB = inputs.HBAR_EVFS
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------------------- Philox
+def test_philox_known_answers(orc):
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        rows = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        out = orc.philox4x32_10(v[0:4], v[4:6])
+        assert [int(o) for o in out] == v[6:10]
+
+
+def test_philox_uniform(orc):
+    words = np.concatenate([orc.philox4x32_10([i, 7, 0, 1], [0, 0]) for i in range(4000)])
+    hist = np.bincount((words >> 28).astype(np.int64), minlength=16)
+    assert sst.chisquare(hist).pvalue > 1e-3
+
+
+# ----------------------------------------------------------------------------- tables
+def test_gamma_is_positive_part_sum(orc):
+    """eq.(1) on the grid: gamma = sum_m max(K, 0); K odd => gamma = sum_{m>0} |K|."""
+    mesh = inputs.Mesh1D(nx=400, dx=0.5, n_m=80)
+    V = inputs.gaussian_barrier_1d(mesh, 0.3, 2.0, 100.0)
+    K = orc.kernel_1d(V, mesh.n_m, HB)[0]
+    dt = 0.5
+    g, n0, thr, cdf = orc.gamma_tables(K, dt)
+    P = mesh.n_m // 2
+    ref = np.abs(K[:, P + 1:]).sum(axis=1)
+    assert np.allclose(g, ref, rtol=1e-13, atol=0)
+    # n0 + thr / 2^32 is gamma dt to within one part in 2^32
+    p = n0.astype(np.float64) + thr.astype(np.float64) / 2.0 ** 32
+    assert np.all(np.abs(p - g * dt) <= 2.0 ** -32 + 1e-15 * g * dt)
+
+
+def test_cdf_sampling_law(orc):
+    """The table's sampling law min{t : u < T[t]} for u uniform on [0, 2^32) gives each m the
+    probability (T[t] - T[t-1]) / 2^32, which must be K+(m)/gamma to one part in 2^31."""
+    V = inputs.random_potentials(3, 300, 0.5, seed=3)
+    for b in range(3):
+        K = orc.kernel_1d(V[b], 64, HB)[0]
+        g, n0, thr, cdf = orc.gamma_tables(K, 1.0)
+        for r in range(0, 300, 17):
+            if g[r] == 0:
+                assert np.all(cdf[r] == 0)
+                continue
+            T = cdf[r].astype(np.float64)
+            assert np.all(np.diff(cdf[r].astype(np.int64)) >= 0)
+            last = np.nonzero(K[r] > 0)[0].max()
+            assert np.all(cdf[r, last:] == 2 ** 32)
+            prob = np.diff(np.concatenate([[0.0], T])) / 2.0 ** 32
+            want = np.maximum(K[r], 0) / g[r]
+            assert np.max(np.abs(prob - want)) <= 2.0 ** -31
+
+
+def test_cdf_statistical(orc):
+    """Chi-square of many table draws against K+/gamma."""
+    mesh = inputs.Mesh1D(nx=100, dx=1.0, n_m=30)
+    V = inputs.gaussian_barrier_1d(mesh, 0.3, 3.0, 50.0)
+    K = orc.kernel_1d(V, mesh.n_m, HB)[0]
+    g, n0, thr, cdf = orc.gamma_tables(K, 1.0)
+    r = 47
+    u = np.random.default_rng(0).integers(0, 2 ** 32, 200000, dtype=np.uint64)
+    t = np.searchsorted(cdf[r], u, side="right")
+    obs = np.bincount(t, minlength=mesh.n_m)
+    exp = np.maximum(K[r], 0) / g[r] * len(u)
+    keep = exp > 0
+    assert obs[~keep].sum() == 0
+    assert sst.chisquare(obs[keep], exp[keep]).pvalue > 1e-3
+
+
+# ----------------------------------------------------------------------------- particles
+def _mesh1(nx=20, n_m=8, f64=True, vdt=0.25):
+    return {"dim": 1, "nx": nx, "ny": 1, "n_m": n_m, "n_k": 2 * n_m, "M_min": -n_m,
+            "pos_f64": f64, "vdt": vdt}
+
+
+def _forced_tables(n_rows, n_m, n0v, thrv, mprime):
+    """Tables that force n0v (+1 if thrv = 2^32-1 and u < thr) pairs with momentum m'."""
+    P = n_m // 2
+    n0 = np.full(n_rows, n0v, np.uint32)
+    thr = np.full(n_rows, thrv, np.uint32)
+    cdf = np.zeros((n_rows, n_m), np.uint64)
+    cdf[:, mprime + P:] = 2 ** 32
+    return n0, thr, cdf
+
+
+@pytest.mark.parametrize("f64", [True, False])
+def test_sp_init_bins(orc, f64):
+    mesh = _mesh1(nx=12, n_m=6, f64=f64)
+    bc = np.random.default_rng(1).integers(0, 5, 12 * 12).astype(np.int32)
+    p = orc.sp_init(mesh, bc, 1000, seed=3)
+    v = p.view()
+    assert p.n == bc.sum()
+    assert np.all(v["s"] == 1)
+    cell = np.floor(v["x"]).astype(np.int64)
+    b = cell * 12 + (v["M"] - mesh["M_min"])
+    assert np.array_equal(b, np.repeat(np.arange(len(bc)), bc))        # bin-major order
+    assert np.all(v["x"] >= cell) and np.all(v["x"] < cell + 1)
+
+
+def test_sp_step_forced_hand_traced(orc):
+    """Hand-traced: cell 5 forces exactly one pair with m' = +2 (n0 = 1, thr = 0, CDF
+    jumping at m' = 2); other cells have no row.  Children sit at the parent's position
+    with momenta M +/- 2 and signs +/- s; then everything drifts by M * vdt = M / 4 cells."""
+    mesh = _mesh1()
+    p = orc.Particles(1, 16, True)
+    p.x[:4] = [5.5, 2.25, 5.0, 19.9]
+    p.M[:4] = [1, -3, 0, 1]
+    p.s[:4] = [1, -1, -1, 1]
+    p.n = 4
+    slot = -np.ones(20, np.int32)
+    slot[5] = 0
+    tables = _forced_tables(1, 8, 1, 0, 2)
+    q, st = orc.sp_step(mesh, p, tables, slot, step=3, seed=9)
+    v = q.view()
+    assert q.n == 8 and st[orc.ST_PAIRS] == 2
+    # parents, drifted (19.9 + 0.25 leaves the domain)
+    assert list(v["x"][:4]) == [5.75, 1.5, 5.0, 20.15]
+    assert list(v["s"][:4]) == [1, -1, -1, 0]
+    # children of id 0 (x=5.5, M=1, s=+1) then of id 2 (x=5.0, M=0, s=-1)
+    assert list(v["M"][4:]) == [3, -1, 2, -2]
+    assert list(v["s"][4:]) == [1, -1, -1, 1]
+    assert list(v["x"][4:]) == [5.5 + 0.75, 5.5 - 0.25, 5.0 + 0.5, 5.0 - 0.5]
+    assert st[orc.ST_ABS_X] == 1 and st[orc.ST_ABS_M] == 0
+
+
+def test_sp_step_momentum_window_and_overflow(orc):
+    mesh = _mesh1()
+    p = orc.Particles(1, 6, True)
+    p.x[:2] = [5.5, 5.5]
+    p.M[:2] = [7, -8]
+    p.s[:2] = [1, 1]
+    p.n = 2
+    slot = -np.ones(20, np.int32)
+    slot[5] = 0
+    tables = _forced_tables(1, 8, 2, 0, 3)           # 2 pairs each: needs 2 + 8 = 10 > 6
+    before = p.view()
+    q, st = orc.sp_step(mesh, p, tables, slot, step=0, seed=1)
+    assert q is None and st[orc.ST_NEEDED] == 10
+    after = p.view()
+    for k in before:
+        assert np.array_equal(before[k], after[k])    # nothing written on overflow
+    p2 = orc.Particles(1, 10, True)
+    p2.x[:2], p2.M[:2], p2.s[:2], p2.n = [5.5, 5.5], [7, -8], [1, 1], 2
+    q, st = orc.sp_step(mesh, p2, tables, slot, step=0, seed=1)
+    v = q.view()
+    # window is [-8, 8): children 7+3=10 and -8-3=-11 are absorbed by momentum
+    assert q.n == 10
+    assert st[orc.ST_ABS_M] == 4
+    assert np.all(v["s"][[2, 4, 7, 9]] == 0)
+
+
+def test_sp_step_creation_statistics(orc):
+    """Many particles in one cell: mean pairs = gamma dt; net sign conserved by creation;
+    children's momentum offsets follow K+/gamma (postulate II)."""
+    mesh = inputs.Mesh1D(nx=100, dx=1.0, n_m=30)
+    V = inputs.gaussian_barrier_1d(mesh, 0.3, 3.0, 50.0)
+    K = orc.kernel_1d(V, mesh.n_m, HB)[0]
+    dt = 3.0
+    g, n0, thr, cdf = orc.gamma_tables(K, dt)
+    n = 60000
+    p = orc.Particles(1, 4 * n, True)
+    p.x[:n] = 47.5
+    p.M[:n] = 0
+    p.s[:n] = np.where(np.arange(n) % 3 == 0, -1, 1)
+    p.n = n
+    md = dict(mesh.as_dict(dt))
+    md["vdt"] = 0.0
+    q, st = orc.sp_step(md, p, (n0, thr, cdf), np.arange(100, dtype=np.int32), step=11, seed=5)
+    pairs = st[orc.ST_PAIRS]
+    mu = g[47] * dt * n
+    sd = math.sqrt(n * (g[47] * dt - math.floor(g[47] * dt)) * (1 - (g[47] * dt - math.floor(g[47] * dt))))
+    assert abs(pairs - mu) < 5 * sd + 1
+    v = q.view()
+    assert v["s"].astype(np.int64).sum() == p.s[:n].astype(np.int64).sum() + 0
+    Mc = v["M"][n::2]                                   # first child of each pair: M + m'
+    obs = np.bincount(Mc + 15, minlength=30)
+    exp = np.maximum(K[47], 0) / g[47] * len(Mc)
+    keep = exp > 0
+    assert obs[~keep].sum() == 0
+    assert sst.chisquare(obs[keep], exp[keep]).pvalue > 1e-4
+
+
+def test_annihilation_invariants(orc):
+    """Rule 2 per (cell, momentum) bin: net sign per bin conserved, no mixed bin left,
+    single-sign particles kept unchanged and in order, fresh particles inside their cell."""
+    rng = np.random.default_rng(2)
+    mesh = _mesh1(nx=10, n_m=4)
+    n = 3000
+    p = orc.Particles(1, n, True)
+    p.x[:n] = rng.uniform(0, 10, n)
+    p.M[:n] = rng.integers(-4, 4, n)
+    p.s[:n] = rng.choice([-1, 1, 1, 0], n)
+    p.n = n
+    q, hp, hm, st = orc.sp_annihilate(mesh, p, step=4, seed=8)
+    v = q.view()
+    cell = np.floor(p.x[:n]).astype(np.int64)
+    b_in = cell * 8 + (p.M[:n] + 4)
+    alive = p.s[:n] != 0
+    net_in = np.bincount(b_in[alive], weights=p.s[:n][alive], minlength=80)
+    # brute force over pairs: a bin is mixed iff it holds both signs
+    mixed = np.zeros(80, bool)
+    for bb in range(80):
+        sg = p.s[:n][alive & (b_in == bb)]
+        mixed[bb] = (sg > 0).any() and (sg < 0).any()
+    b_out = np.floor(v["x"]).astype(np.int64) * 8 + (v["M"] + 4)
+    net_out = np.bincount(b_out, weights=v["s"], minlength=80)
+    assert np.array_equal(net_in, net_out)
+    for bb in range(80):
+        sg = v["s"][b_out == bb]
+        assert not ((sg > 0).any() and (sg < 0).any())
+    keep = alive & ~mixed[b_in]
+    k = keep.sum()
+    assert st[orc.ST_KEPT] == k and st[orc.ST_MIXED] == mixed.sum()
+    assert np.array_equal(v["x"][:k], p.x[:n][keep])
+    assert np.array_equal(v["M"][:k], p.M[:n][keep])
+    assert np.array_equal(v["s"][:k], p.s[:n][keep])
+    # histogram returned is the input's
+    assert np.array_equal(hp - hm, net_in.astype(np.int64))
+    # regenerated: ascending bins, |net| each
+    regen_bins = b_out[k:]
+    assert np.all(np.diff(regen_bins) >= 0)
+    assert np.array_equal(np.bincount(regen_bins, minlength=80)[mixed], np.abs(net_in[mixed]).astype(np.int64))
+
+
+def test_free_drift_sheared_gaussian(orc):
+    """V = 0: K = 0, gamma = 0, no creation, no mixed bin, pure drift.  The histogram after
+    t steps follows the initial bin counts sheared by M vdt t with positions uniform in each
+    cell (exact expectation), checked by chi-square; the first two moments of x follow
+    E[x] = E[x0] + t E[v] and Var x = Var x0 + t^2 Var v + 2 t Cov(x0, v) exactly."""
+    mesh = inputs.Mesh1D(nx=100, dx=1.0, n_m=30, pos_f64=True)
+    dt, steps = 1.0, 40
+    V = np.zeros(mesh.nx)
+    K = orc.kernel_1d(V, mesh.n_m, HB)[0]
+    g, n0, thr, cdf = orc.gamma_tables(K, dt)
+    assert np.all(g == 0)
+    k0 = inputs.k_for_energy(0.1)
+    bc = inputs.packet_bin_counts_1d(mesh, 2e4, 25.0, 5.0, k0)
+    md = mesh.as_dict(dt)
+    p = orc.sp_init(md, bc, 3 * int(bc.sum()), seed=0)
+    x0 = p.x[: p.n].copy()
+    v0 = p.M[: p.n].astype(np.float64) * md["vdt"]
+    slot = np.arange(mesh.nx, dtype=np.int32)
+    for s in range(steps):
+        p, st = orc.sp_step(md, p, (n0, thr, cdf), slot, step=s, seed=0)
+        assert st[orc.ST_PAIRS] == 0
+        p, hp, hm, st = orc.sp_annihilate(md, p, step=s, seed=0)
+        assert st[orc.ST_MIXED] == 0
+    # no absorption for this packet within 40 fs: order is preserved, moments exact
+    assert p.n == len(x0)
+    x = p.x[: p.n]
+    assert abs(x.mean() - (x0.mean() + steps * v0.mean())) < 1e-9
+    var_ref = x0.var() + steps ** 2 * v0.var() + 2 * steps * np.cov(x0, v0, bias=True)[0, 1]
+    assert abs(x.var() - var_ref) < 1e-8
+    # chi-square of the cell histogram against the exact expectation
+    shift = np.arange(mesh.M_min, mesh.M_min + mesh.n_k) * md["vdt"] * steps
+    expc = np.zeros(mesh.nx + 2)
+    for b in np.nonzero(bc)[0]:
+        c0, kk = divmod(b, mesh.n_k)
+        lo = c0 + shift[kk]
+        for c in range(int(math.floor(lo)), int(math.floor(lo)) + 2):
+            ov = max(0.0, min(lo + 1, c + 1) - max(lo, c))
+            if 0 <= c < mesh.nx:
+                expc[c] += bc[b] * ov
+    obs = np.bincount(np.floor(x).astype(np.int64), minlength=mesh.nx)
+    e = expc[: mesh.nx]
+    keep = e > 5
+    chi = ((obs[keep] - e[keep]) ** 2 / e[keep]).sum()
+    assert sst.chi2.sf(chi, keep.sum() - 1) > 1e-3

@@ -1,0 +1,99 @@
+"""Pins of the oracle's trainable kernel network, eq.(5) of Sec. 2.3, and its gradients."""
+import numpy as np
+import pytest
+
+from paper_1806_00082_amd import inputs
+
+HB = inputs.HBAR_EVFS
+
+
+def test_n1_analytic_is_exact(orc):
+    """N = 1 with the analytic weights (w_l = -2 dx/(hbar L_C)) is eq.(4) itself."""
+    V = inputs.random_potentials(2, 200, 0.5, seed=4)
+    n_m = 64
+    wV, wT, W = orc.analytic_weights(n_m, 1, HB)
+    Kh = orc.surrogate_fwd(V, n_m, 1, wV, wT, W)
+    Kx = orc.full_to_half(orc.kernel_1d(V, n_m, HB))
+    assert np.max(np.abs(Kh - Kx)) <= 1e-12 * np.abs(Kx).max()
+
+
+@pytest.mark.parametrize("N", [2, 4, 8])
+def test_barycentric_exact_on_blockwise_constant(orc, N):
+    """sum_{p<N} sin(a + p d) = sin(a + (N-1)d/2) sin(N d/2)/sin(d/2), and for N = 2^L
+    sin(N d/2)/sin(d/2) = N prod_{s<L} cos(2^s d/2).  So when V is constant on every group
+    of N window cells, eq.(5) with wV = 1, wT = 1/N, W = c equals eq.(4) exactly."""
+    n_m, nx = 32, 160
+    P = n_m // 2
+    rng = np.random.default_rng(N)
+    blocks = rng.normal(size=nx // N)
+    V = np.repeat(blocks, N)                        # constant on [kN, kN+N)
+    wV, wT, W = orc.analytic_weights(n_m, N, HB)
+    Kh = orc.surrogate_fwd(V, n_m, N, wV, wT, W)[0]
+    Kx = orc.full_to_half(orc.kernel_1d(V, n_m, HB))[0]
+    aligned = [i for i in range(P, nx - P) if (i - P) % N == 0]
+    assert len(aligned) > 5
+    scale = np.abs(Kx[aligned]).max()
+    assert np.max(np.abs(Kh[aligned] - Kx[aligned])) <= 1e-12 * scale
+    # and it is only an approximation for a generic potential
+    V2 = rng.normal(size=nx)
+    Kh2 = orc.surrogate_fwd(V2, n_m, N, wV, wT, W)[0]
+    Kx2 = orc.full_to_half(orc.kernel_1d(V2, n_m, HB))[0]
+    assert np.max(np.abs(Kh2 - Kx2)) > 1e-3 * np.abs(Kx2).max()
+
+
+def test_n2_matches_printed_two_term_form(orc):
+    """N = 2 analytic weights give the two-term form derived in Sec. 2.3:
+    c cos(pi m / n_m) sum_g [V(2g) + V(2g+1)] sin((theta_2g + theta_2g+1)/2)."""
+    n_m, nx = 20, 50
+    P = n_m // 2
+    V = np.random.default_rng(12).normal(size=nx)
+    wV, wT, W = orc.analytic_weights(n_m, 2, HB)
+    Kh = orc.surrogate_fwd(V, n_m, 2, wV, wT, W)[0]
+    c = -2.0 / (HB * n_m)
+    i = 25
+    for m in range(1, P + 1):
+        acc = 0.0
+        for g in range(P):
+            o0, o1 = -P + 2 * g, -P + 2 * g + 1
+            th0, th1 = 2 * np.pi * o0 * m / n_m, 2 * np.pi * o1 * m / n_m
+            acc += (V[i + o0] + V[i + o1]) * np.sin(0.5 * (th0 + th1))
+        ref = c * np.cos(np.pi * m / n_m) * acc
+        assert abs(Kh[i, m - 1] - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("N", [1, 2, 4])
+def test_surrogate_gradients_finite_differences(orc, N):
+    """Analytic gradients of <E, Kh> against central differences of the forward."""
+    n_m, nx, B = 16, 40, 2
+    rng = np.random.default_rng(20 + N)
+    V = rng.normal(size=(B, nx))
+    wV = rng.normal(size=N)
+    wT = rng.normal(size=N) / N
+    W = rng.normal(size=n_m // N)
+    cells = np.array([0, 3, 17, 39, 20], np.int32)
+    E = rng.normal(size=(B, len(cells), n_m // 2))
+    dwV, dwT, dW, dV = orc.surrogate_bwd(V, n_m, N, wV, wT, W, E, cells=cells)
+
+    def f(wV_, wT_, W_, V_):
+        return np.sum(E * orc.surrogate_fwd(V_, n_m, N, wV_, wT_, W_, cells=cells))
+
+    h = 1e-6
+    for arr, grad, idx in ((wV, dwV, range(N)), (wT, dwT, range(N)), (W, dW, range(0, n_m // N, 3))):
+        for k in idx:
+            a = arr.copy()
+            a[k] += h
+            args_p = [wV, wT, W, V]
+            args_p[[id(wV), id(wT), id(W)].index(id(arr))] = a
+            fp = f(*args_p)
+            a[k] -= 2 * h
+            fm = f(*args_p)
+            fd = (fp - fm) / (2 * h)
+            assert abs(grad[k] - fd) <= 1e-6 * max(1.0, abs(fd))
+    for (b, l) in ((0, 0), (1, 5), (0, 20), (1, 39)):
+        Vp = V.copy()
+        Vp[b, l] += h
+        fp = f(wV, wT, W, Vp)
+        Vp[b, l] -= 2 * h
+        fm = f(wV, wT, W, Vp)
+        fd = (fp - fm) / (2 * h)
+        assert abs(dV[b, l] - fd) <= 1e-6 * max(1.0, abs(fd))
