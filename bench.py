@@ -1,0 +1,271 @@
+"""Benchmark of the signed-particle Wigner Monte Carlo hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-forms] [--no-cpu]
+
+Headline workload: the 1-D paper-shaped run (400 cells of 0.5 nm, L_C = 40 nm -> 80
+pseudo-momenta, Gaussian barrier 0.3 eV sigma 2 nm at 100 nm, Gaussian packet at 50 nm
+sigma 10 nm with 0.1 eV, 1e7 signed particles in FP32, dt = 0.5 fs, annihilation every
+step).  One step = kernel rows for newly occupied cells (every 8 steps) + creation tables +
+sp_step (creation at rate gamma, drift, absorbing boundaries) + sp_annihilate.  W warm-up
+steps, then exactly K timed steps (default W + K = the run's 400 steps).
+
+value = particle-steps/s = sum over timed steps of the particle count at the start of the
+step, divided by the time between the events bracketing the K steps (inputs resident in HBM).
+
+Also reported (same JSON line): kernel entries/s of eq.(4) on the precision batch (4096
+potentials x 2048 cells x 512 m) in FP64 and the BF16/FP16 (+split) forms with their
+normwise error against the FP64 path, and the learned eq.(5) forward on 1024-cell, 256-m
+potentials; the CPU oracle timed on a bounded sample of the headline run.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Wigner kernel entries/s + particle-steps/s; BF16/surrogate vs FP64 at stated err"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "fp16x3": 2500.0,
+               "fp32": 157.3}
+# algorithmic bytes (struct-of-arrays, FP32 positions): x 4 + M 4 + s 1
+B_PART = 9
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def run_headline(steps: int, warmup: int):
+    import torch
+    from paper_1806_00082_amd import _lib as L
+    from paper_1806_00082_amd import inputs, ops
+    from paper_1806_00082_amd.sim import Simulator
+
+    cfg = inputs.config_c2()
+    sim = Simulator(cfg, kernel="exact", prec="fp64", mode="occupied", refresh_every=8)
+    for _ in range(warmup):
+        sim.step()
+    dev = sim.dev
+    log_n = torch.zeros(steps, dtype=torch.int64, device=dev)          # N at step start
+    log_step = torch.zeros((steps, L.ST_COUNT), dtype=torch.int64, device=dev)
+    ev = [(_events(), _events()) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0, t1 = _events()
+    wall0 = time.perf_counter()
+    t0.record()
+    for k in range(steps):
+        s = sim.step_index
+        log_n[k].copy_(sim.a.d_n[0])
+        if sim.mode == "occupied" and s > 0 and s % sim.refresh_every == 0:
+            sim.refresh()
+        (e0, e1), (e2, e3) = ev[k]
+        e0.record()
+        ops.sp_step(sim.md, sim.seed, sim.cell_slot, sim.n0, sim.thr, sim.cdf, sim.a, s,
+                    sim.stats, sim.ws)
+        e1.record()
+        log_step[k].copy_(sim.stats)
+        e2.record()
+        ops.sp_annihilate(sim.md, sim.seed, sim.a, sim.b, sim.hist, s, sim.stats, sim.ws)
+        e3.record()
+        sim.a, sim.b = sim.b, sim.a
+        sim.step_index += 1
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    n_start = log_n.cpu().numpy()
+    st = log_step.cpu().numpy()
+    t_step = sum(a[0].elapsed_time(a[1]) for a, _ in ev)
+    t_ann = sum(b[0].elapsed_time(b[1]) for _, b in ev)
+    # algorithmic bytes: sp_step reads x, M, s and writes x (13 B) per particle and writes two
+    # 9-byte children per pair; sp_annihilate reads the ensemble twice (histogram, keep pass)
+    # and writes the survivors (27 B per particle) plus the 2 x n_bins int32 histogram.
+    bytes_step = float((n_start * 13).sum() + (st[:, L.ST_PAIRS] * 18).sum())
+    n_after = st[:, L.ST_N]
+    bytes_ann = float((n_after * 27).sum() + steps * 2 * 4 * ops.n_bins(sim.md) * 2)
+    passes = {
+        "sp_step": {"ms": t_step, "bytes": bytes_step},
+        "sp_annihilate": {"ms": t_ann, "bytes": bytes_ann},
+    }
+    dom = max(passes, key=lambda k: passes[k]["ms"])
+    ach = passes[dom]["bytes"] / (passes[dom]["ms"] * 1e-3) / 1e9
+    assert not sim.overflowed(), "particle buffer overflowed during the timed run"
+    return {
+        "cfg": cfg, "ms": ms, "wall_s": wall, "particle_steps": float(n_start.sum()),
+        "n_first": int(n_start[0]), "n_last": int(sim.count()),
+        "pairs": int(st[:, L.ST_PAIRS].sum()), "rows": sim.n_rows,
+        "passes": {k: {"ms_total": round(v["ms"], 3),
+                       "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)} for k, v in passes.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+
+
+def run_kernel_forms():
+    """eq.(4) on the precision batch in every form, error vs the FP64 path."""
+    import numpy as np
+    import torch
+    from paper_1806_00082_amd import inputs, ops
+
+    c3 = inputs.C3
+    B, nx, n_m = c3["B"], c3["nx"], c3["n_m"]
+    P = n_m // 2
+    V = torch.from_numpy(inputs.random_potentials(B, nx, c3["dx"], seed=c3["seed"])).cuda()
+    entries = B * nx * n_m
+    flops = 2.0 * (P - 1) ** 2 * B * nx
+    out = {"workload": "precision batch: 4096 potentials x 2048 cells x 512 m, half table"}
+    ref = ops.kernel_eval(V, n_m, layout="half")
+    refmax = ref.reshape(B, -1).abs().amax(dim=1)
+    for prec in ("fp64", "bf16", "fp16", "bf16x3", "fp16x3"):
+        buf = ref if prec == "fp64" else torch.empty((B * nx, P), dtype=torch.float32, device="cuda")
+        ops.kernel_eval(V, n_m, prec=prec, layout="half", out=buf)
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        reps = 3
+        e0.record()
+        for _ in range(reps):
+            ops.kernel_eval(V, n_m, prec=prec, layout="half", out=buf)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = flops / (ms * 1e-3) / 1e12
+        wbytes = B * nx * P * (8 if prec == "fp64" else 4)
+        rec = {"ms": round(ms, 3), "entries_per_s": entries / (ms * 1e-3),
+               "alg_TFLOPs": round(tf, 2), "mfma_frac": round(tf / PEAK_TFLOPS[prec], 4),
+               "write_GBps": round(wbytes / (ms * 1e-3) / 1e9, 1)}
+        if prec != "fp64":
+            err = 0.0
+            for b0 in range(0, B, 256):
+                d = (buf[b0 * nx:(b0 + 256) * nx].double() - ref[b0 * nx:(b0 + 256) * nx]).reshape(-1, nx * P)
+                err = max(err, float((d.abs().amax(dim=1) / refmax[b0:b0 + 256]).max()))
+            rec["normwise_err_vs_fp64"] = err
+            del buf
+        out[prec] = rec
+    del ref
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_surrogate_forms():
+    """eq.(5) forward (analytic barycentric weights) vs the exact kernel, 1024 cells x 256 m."""
+    import torch
+    from paper_1806_00082_amd import inputs, learn, ops
+
+    c4 = inputs.C4
+    nx, n_m, B = c4["nx"], c4["n_m"], 512
+    P = n_m // 2
+    V = torch.from_numpy(inputs.random_potentials(B, nx, c4["dx"], seed=c4["test_seed"])).cuda()
+    entries = B * nx * n_m
+    res = {"workload": f"{B} potentials x {nx} cells x {n_m} m, half table"}
+
+    def timeit(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    K = torch.empty((B * nx, P), dtype=torch.float64, device="cuda")
+    ms = timeit(lambda: ops.kernel_eval(V, n_m, layout="half", out=K))
+    res["exact_fp64"] = {"ms": round(ms, 3), "entries_per_s": entries / (ms * 1e-3)}
+    Kb = torch.empty((B * nx, P), dtype=torch.float32, device="cuda")
+    ms = timeit(lambda: ops.kernel_eval(V, n_m, prec="bf16", layout="half", out=Kb))
+    res["exact_bf16"] = {"ms": round(ms, 3), "entries_per_s": entries / (ms * 1e-3)}
+    kmax = K.reshape(B, -1).abs().amax(dim=1)
+    for N in (2, 4, 8):
+        w = learn.analytic_weights(n_m, N)
+        for prec in ("fp32", "bf16"):
+            ms = timeit(lambda: learn.surrogate_fwd(V, n_m, N, *w, prec=prec, out=Kb))
+            err = float(((Kb.double() - K).reshape(B, -1).abs().amax(dim=1) / kmax).max())
+            res[f"N{N}_H{n_m // N}_{prec}"] = {"ms": round(ms, 3), "entries_per_s": entries / (ms * 1e-3),
+                                              "normwise_err_vs_exact": err}
+    return res
+
+
+def run_cpu_baseline(sample_steps: int):
+    """The oracle (single-threaded C, one core) on the first steps of the headline run."""
+    import numpy as np
+    import oracle as orc
+    from paper_1806_00082_amd import inputs
+
+    cfg = inputs.config_c2()
+    md = cfg.mesh.as_dict(cfg.dt)
+    K = orc.kernel_1d(cfg.V, cfg.mesh.n_m, inputs.HBAR_EVFS)[0]
+    _, n0, thr, cdf = orc.gamma_tables(K, cfg.dt)
+    p = orc.sp_init(md, cfg.bin_counts, 3 * int(cfg.bin_counts.sum()), seed=cfg.seed)
+    slot = np.arange(md["nx"], dtype=np.int32)
+    ps = 0
+    t0 = time.perf_counter()
+    for s in range(sample_steps):
+        ps += p.n
+        p, _ = orc.sp_step(md, p, (n0, thr, cdf), slot, step=s, seed=cfg.seed)
+        p, _, _, _ = orc.sp_annihilate(md, p, step=s, seed=cfg.seed)
+    dt = time.perf_counter() - t0
+    return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample_steps} steps of the 1e7-particle run (sp_step + sp_annihilate), "
+                      f"{dt:.1f} s on one host core"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=390)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    h = run_headline(args.steps, args.warmup)
+    forms = {} if args.no_forms else {"kernel_eq4": run_kernel_forms(), "surrogate_eq5": run_surrogate_forms()}
+    cpu = None if args.no_cpu else run_cpu_baseline(args.cpu_steps)
+    value = h["particle_steps"] / (h["ms"] * 1e-3)
+    cfg = h["cfg"]
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32+fp32 (fp64 kernel and tables)",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "cells": cfg.mesh.nx, "dx_nm": cfg.mesh.dx,
+                   "n_m": cfg.mesh.n_m, "particles_initial": int(cfg.bin_counts.sum()),
+                   "dt_fs": cfg.dt, "annihilation": "every step", "kernel": "exact fp64, occupied cells"},
+        "run": {"n_first": h["n_first"], "n_last": h["n_last"], "pairs_created": h["pairs"],
+                "kernel_rows_evaluated": h["rows"], "wall_s": round(h["wall_s"], 3),
+                "passes": h["passes"]},
+        "roofline": h["roofline"],
+        "cpu_baseline": cpu,
+        "forms": forms,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

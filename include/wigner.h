@@ -1,0 +1,258 @@
+/*
+ * wigner.h -- C ABI of libwigner.so, the MI355X (gfx950) hot path of the signed-particle
+ * Wigner Monte Carlo method with a neural-network Wigner kernel (Sellier, Leygonie,
+ * Marceau Caron, arXiv:1806.00082).
+ *
+ * General conventions
+ *   - Every array argument is a DEVICE pointer owned by the caller; the library never
+ *     frees caller memory.  Scalars and the small parameter structs are host values.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Every call
+ *     only enqueues work on that stream and returns without synchronising.
+ *   - Return value: WK_OK (0) or a negative code.  Arguments are validated on the host
+ *     before anything is enqueued; on WK_EINVAL nothing is enqueued.  wk_last_error()
+ *     returns a thread-local description of the last failure.
+ *   - The library keeps, per device, read-only sine tables it builds on first use of a
+ *     given n_m (device memory held until the process ends).  Apart from that first use
+ *     no call allocates memory: scratch space is the caller's workspace argument.
+ *   - Results are deterministic: identical inputs give bit-identical outputs.
+ *
+ * Mesh and tables (Sec. 2.2 of the paper)
+ *   - 1-D: nx cells; V[b][i] is the potential (eV) at the centre of cell i of potential
+ *     b.  2-D: V[b][iy][ix].  Outside the mesh V takes the nearest edge value.
+ *   - n_m = L_C / dx pseudo-momenta per axis, even; P = n_m / 2; momentum index
+ *     m in [-P, P) counts Delta k = pi / L_C (Delta p = pi hbar / L_C).
+ *   - Full 1-D table  K[row][t], t in [0, n_m), m = t - P (n_m entries per row).
+ *     Half 1-D table  K[row][t], t in [0, P),   m = t + 1 (V_W is odd in m:
+ *     K(-m) = -K(m), K(0) = 0, and the full entry m = -P is -K(P)).
+ *     Full 2-D table  K[row][ty][tx], (m_x, m_y) = (tx - P, ty - P).
+ *   - Rows: row = b * n_cells + r for potential b and the r-th requested cell
+ *     (cells[r], or r itself when cells is NULL).  Values are in 1/fs.
+ *
+ * Particles (Sec. 2.1)
+ *   - Struct-of-arrays.  Positions are in units of the cell width (cell = floor(x)),
+ *     float or double per sp_geom.pos_f64.  1-D: M is int32; 2-D: M (x axis) and My are
+ *     int16.  s is int8: +1 / -1, 0 = absorbed (dropped by the next annihilation).
+ *   - The particle count lives in device memory (*d_n) so a time loop needs no host
+ *     synchronisation.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed,
+ *     counter (particle or bin id, step, block, stream tag); the stream of a particle
+ *     depends only on its index at the start of the step, never on the launch shape.
+ */
+#ifndef WIGNER_H
+#define WIGNER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WK_OK 0
+#define WK_EINVAL (-1)     /* bad argument; nothing enqueued */
+#define WK_ECAPACITY (-2)  /* particle buffer too small (see WK_ST_NEEDED) */
+#define WK_EHIP (-3)       /* HIP runtime error (message in wk_last_error) */
+
+#define WK_VERSION 1
+
+/* Arithmetic of the kernel contraction. */
+enum wk_prec {
+    WK_FP64 = 0,    /* FP64 MFMA, FP64 output */
+    WK_BF16 = 1,    /* BF16 operands, FP32 accumulate, FP32 output */
+    WK_FP16 = 2,    /* FP16 operands, FP32 accumulate, FP32 output */
+    WK_BF16X3 = 3,  /* hi/lo BF16 split, three products, FP32 accumulate and output */
+    WK_FP16X3 = 4   /* hi/lo FP16 split, three products, FP32 accumulate and output */
+};
+
+enum wk_layout { WK_FULL = 0, WK_HALF = 1 };
+
+typedef struct wk_mesh {
+    int32_t dim;   /* 1 or 2 */
+    int32_t nx;    /* cells along x */
+    int32_t ny;    /* cells along y (1 in 1-D) */
+    int32_t n_m;   /* pseudo-momenta per axis = L_C / dx, even, >= 2 */
+    double hbar;   /* reduced Planck constant in eV fs */
+} wk_mesh;
+
+typedef struct sp_geom {
+    int32_t dim;      /* 1 or 2 */
+    int32_t nx, ny;   /* cells per axis (ny = 1 in 1-D) */
+    int32_t n_m;      /* width of the kernel tables per axis (as wk_mesh.n_m) */
+    int32_t n_k;      /* particle momentum window per axis: [M_min, M_min + n_k) */
+    int32_t M_min;
+    int32_t pos_f64;  /* 1: double positions, 0: float positions */
+    int32_t reserved;
+    double vdt;       /* drift per step per unit momentum index, in cells */
+    uint64_t seed;    /* Philox key */
+} sp_geom;
+
+typedef struct sp_particles {
+    void* x;          /* [capacity] float or double */
+    void* y;          /* [capacity] (2-D only, else NULL) */
+    void* M;          /* [capacity] int32 (1-D) or int16 (2-D) */
+    void* My;         /* [capacity] int16 (2-D only, else NULL) */
+    int8_t* s;        /* [capacity] */
+    int64_t capacity; /* host value: number of slots */
+    int64_t* d_n;     /* device int64: current number of particles */
+} sp_particles;
+
+/* d_stats: device int64[WK_ST_COUNT].  Each call overwrites only its own entries. */
+enum wk_stat {
+    WK_ST_N = 0,          /* particles after the call */
+    WK_ST_PAIRS = 1,      /* pairs created (sp_step) */
+    WK_ST_ABS_X = 2,      /* absorbed at the domain boundary (sp_step) */
+    WK_ST_ABS_M = 3,      /* absorbed at the momentum window (sp_step) */
+    WK_ST_NEEDED = 4,     /* capacity sp_step needed when it overflowed, else 0 */
+    WK_ST_KEPT = 5,       /* particles of single-sign bins kept (sp_annihilate) */
+    WK_ST_REGEN = 6,      /* particles regenerated in mixed bins (sp_annihilate) */
+    WK_ST_MIXED = 7,      /* bins holding both signs (sp_annihilate) */
+    WK_ST_OVERFLOW = 8,   /* sticky: 1 once an overflow happened; later particle calls
+                             are then no-ops until the caller clears it */
+    WK_ST_OVERFLOW_STEP = 9, /* step index of that overflow */
+    WK_ST_COUNT = 16
+};
+
+const char* wk_last_error(void);
+int wk_version(void);
+/* Number of HIP devices visible (0 without a GPU); never fails. */
+int wk_device_count(void);
+
+/* ------------------------------------------------------------------ Wigner kernel
+ * wk_kernel_eval -- eq.(4) of Sec. 2.2 (the "N = 1" analytic network of Sec. 2.2):
+ *   K(i, m) = -2/(hbar n_m) sum_{j=1..P} sin(2 pi j m / n_m) [V(i+j) - V(i-j)]
+ * in 1-D, and its d = 2 form (weights 1/2 at |j_a| = P) in 2-D, evaluated only on the
+ * requested cells (the point of the method: no table over the whole phase space).
+ *   V       [B][nx] (1-D) or [B][ny][nx] (2-D), double.
+ *   cells   [n_cells] int32 cell ids (2-D: iy * nx + ix), or NULL for all cells
+ *           (then n_cells must be nx * ny).  Ids must lie in the mesh.
+ *   prec    enum wk_prec; 2-D supports WK_FP64, WK_BF16, WK_FP16.
+ *   layout  WK_FULL or WK_HALF (1-D only).
+ *   K_out   [B * n_cells][n_m] (full), [B * n_cells][P] (half) or
+ *           [B * n_cells][n_m][n_m] (2-D); double for WK_FP64, float otherwise.
+ */
+int wk_kernel_eval(const wk_mesh* mesh, const double* V, int32_t B, const int32_t* cells,
+                   int32_t n_cells, int32_t prec, int32_t layout, void* K_out, void* stream);
+
+/* wk_kernel_bwd -- adjoint of wk_kernel_eval (1-D, all cells, WK_FP64) with respect to V:
+ *   dV[b][l] += sum_{i,t} G[b][i][t] dK[b][i][t] / dV[b][l]
+ * (K is linear in V, eq.(4)).  G has the layout given by `layout`, double.  dV is
+ * accumulated into (not overwritten).  ws: workspace of wk_kernel_bwd_workspace() bytes. */
+size_t wk_kernel_bwd_workspace(const wk_mesh* mesh, int32_t B);
+int wk_kernel_bwd(const wk_mesh* mesh, const double* G, int32_t B, int32_t layout, double* dV,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ creation tables
+ * wk_gamma_tables -- eq.(1) on the grid and the integer sampling tables of postulate II:
+ *   gamma[r] = sum over the row, in ascending m, of max(K, 0)       (FP64, sequential)
+ *   p = gamma dt; n0[r] = floor(p); thr[r] = floor((p - n0) 2^32)
+ *   cdf[r][t] = floor(C_t / gamma 2^32) with C_t the running positive sum, and 2^32
+ *               from the last positive entry on (all 0 when gamma = 0).
+ * A particle then creates n0 pairs plus one with probability thr / 2^32, each with
+ * momentum offset index min{t : u < cdf[t]} for a uniform 32-bit u.
+ *   K      [n_rows][width] full table (width = n_m in 1-D, n_m^2 in 2-D), or the 1-D
+ *          half table when layout = WK_HALF; double (k_f64 = 1) or float (k_f64 = 0).
+ *   gamma  [n_rows] double, n0/thr [n_rows] uint32, cdf [n_rows][width] uint64. */
+int wk_gamma_tables(const wk_mesh* mesh, const void* K, int32_t k_f64, int32_t layout,
+                    int32_t n_rows, double dt, double* gamma, uint32_t* n0, uint32_t* thr,
+                    uint64_t* cdf, void* stream);
+
+/* ------------------------------------------------------------------ particles
+ * sp_init -- place the particles of an initial Wigner function given per-bin counts
+ * (eq.(6) turned into counts by the caller): for bins in ascending order, count[b]
+ * particles of sign +1 with the bin's momentum and positions uniform in the bin's cell.
+ * Bins: 1-D b = c * n_k + (M - M_min); 2-D b = ((cy*nx + cx)*n_k + (My-M_min))*n_k + (Mx-M_min).
+ *   bin_counts [n_bins] int32 >= 0.  Writes *out->d_n.  WK_ECAPACITY (reported in
+ *   d_stats[WK_ST_NEEDED], nothing written) if the total exceeds out->capacity.
+ *   ws: sp_workspace_size() bytes. */
+size_t sp_workspace_size(const sp_geom* g);
+int sp_init(const sp_geom* g, const int32_t* bin_counts, sp_particles* out, int64_t* d_stats,
+            void* ws, size_t ws_bytes, void* stream);
+
+/* sp_step -- one time step dt of postulate II (Sec. 2.1) with absorbing boundaries
+ * (Sec. 3), in place:
+ *   1. each particle (index id < n) in a cell with a table row creates
+ *      n0 + [u0 < thr] pairs; pair k draws t_k = min{t : u < cdf[t]}, momentum offset
+ *      m' = t_k - P (2-D: (t mod n_m - P, t / n_m - P)), and appends the children
+ *      (x, M + m', +s), (x, M - m', -s) at n + 2 * (pairs of lower ids) + 2k, 2k + 1;
+ *   2. every particle drifts: x <- fma(M, vdt, x) in the position precision;
+ *   3. particles leaving [0, nx) (x [0, ny)) or the momentum window get s = 0.
+ * Philox counter (id, step, 0, 1) gives u0 and the draws of pairs 0..2; pair k >= 3
+ * uses counter (id, step, 1 + (k-3)/4, 1), word (k-3) mod 4.
+ *   cell_slot [nx*ny] int32: table row of each cell, or -1 for no creation there.
+ *   n0, thr, cdf: from wk_gamma_tables.
+ * On overflow (n + 2 * pairs > capacity) nothing is written, d_stats[WK_ST_NEEDED] gets
+ * the required capacity and the sticky WK_ST_OVERFLOW flag is set; because the random
+ * stream is counter-based, re-running the step with a larger buffer is bit-identical. */
+int sp_step(const sp_geom* g, const int32_t* cell_slot, const uint32_t* n0, const uint32_t* thr,
+            const uint64_t* cdf, sp_particles* p, int64_t step, int64_t* d_stats, void* ws,
+            size_t ws_bytes, void* stream);
+
+/* sp_annihilate -- rule 2 of Sec. 2.1 on the (cell, momentum) grid, from `in` to `out`:
+ * output = the live particles of bins holding one sign only, unchanged and in input
+ * order, followed by, for each bin holding both signs in ascending bin order,
+ * |H+ - H-| particles of sign sgn(H+ - H-) with the bin's momentum and positions
+ * uniform in its cell (Philox counter (bin, step, r/4, 2), word r mod 4 in 1-D;
+ * (bin, step, r/2, 2), words 2(r mod 2), 2(r mod 2)+1 for x, y in 2-D).
+ *   hist [2][n_bins] int32 (caller-owned, left holding H+ then H- of the input: the
+ *   signed histogram of rule 1).  out->capacity must be >= in's count. */
+int sp_annihilate(const sp_geom* g, const sp_particles* in, sp_particles* out, int32_t* hist,
+                  int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes, void* stream);
+
+/* sp_density -- rule 1 read-out: rho[c] = sum_M (H+ - H-) / N0 (double [nx*ny]) from the
+ * histogram sp_annihilate left in `hist`. */
+int sp_density(const sp_geom* g, const int32_t* hist, double N0, double* rho, void* stream);
+
+/* sp_cells_to_evaluate -- the cells that need kernel rows next (Sec. 2.2: the kernel is
+ * evaluated only on the phase-space cells the particles occupy): every cell within `margin`
+ * cells per axis of a cell holding particles in `hist` (from sp_annihilate) whose
+ * cell_slot is still -1, written in ascending order to new_cells [nx*ny] (int32), their
+ * number to *d_count (device int64).  ws: sp_workspace_size() bytes. */
+int sp_cells_to_evaluate(const sp_geom* g, const int32_t* hist, int32_t margin,
+                         const int32_t* cell_slot, int32_t* new_cells, int64_t* d_count,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* sp_assign_slots -- cell_slot[new_cells[k]] = first_row + k for k < *d_count (device count,
+ * at most max_count). */
+int sp_assign_slots(const int32_t* new_cells, const int64_t* d_count, int32_t max_count,
+                    int32_t first_row, int32_t* cell_slot, void* stream);
+
+/* ------------------------------------------------------------------ learned kernel
+ * wk_surrogate_fwd -- the trainable network of eq.(5), Sec. 2.3 (1-D), half table
+ * m = 1..P:
+ *   Kh(i, m) = prod_{s < log2 N} cos(2^s pi m / n_m)
+ *              * sum_{g < n_m/N} W[g] A(i, g) sin(u_g m),
+ *   A(i, g) = sum_{p < N} wV[p] V(i + o(g,p)),  u_g = (2 pi / n_m) sum_p wT[p] o(g,p),
+ *   o(g, p) = -P + N g + p  (the window offsets of a cell grouped N at a time).
+ * With wV = 1, wT = 1/N, W = -2/(hbar n_m): N = 1 is eq.(4) exactly, N = 2 the
+ * barycentric form of Sec. 2.3.
+ *   N power of two dividing n_m; wV, wT [N] and W [n_m/N] float (device).
+ *   prec WK_FP64 (double out, reference arithmetic), WK_BF16 (bf16 products,
+ *   FP32 accumulate) or any other value for FP32 (training); K_out [B*n_cells][P]. */
+int wk_surrogate_fwd(const wk_mesh* mesh, int32_t N, const float* wV, const float* wT,
+                     const float* W, const double* V, int32_t B, const int32_t* cells,
+                     int32_t n_cells, int32_t prec, void* K_out, void* stream);
+
+/* wk_surrogate_bwd -- gradients of L = sum E * Kh with respect to wV, wT, W (written,
+ * float) and V (accumulated into dV [B][nx] double, may be NULL); E [B*n_cells][P] float.
+ * Deterministic two-level reductions.  ws: wk_surrogate_workspace() bytes. */
+size_t wk_surrogate_workspace(const wk_mesh* mesh, int32_t N, int32_t B, int32_t n_cells);
+int wk_surrogate_bwd(const wk_mesh* mesh, int32_t N, const float* wV, const float* wT,
+                     const float* W, const double* V, int32_t B, const int32_t* cells,
+                     int32_t n_cells, const float* E, float* dwV, float* dwT, float* dW,
+                     double* dV, void* ws, size_t ws_bytes, void* stream);
+
+/* wk_mse_grad -- mean squared error of the training loop of Sec. 3, on targets scaled by
+ * inv_scale (so that the loss is O(1) whatever the units): with n = count,
+ *   loss[0] = sum ((Kh - K) inv_scale)^2 / n            (double, written)
+ *   E       = 2 (Kh - K) inv_scale^2 / n = dloss/dKh     (float, written)
+ * Kh float, K (labels) double; both [count].  ws: >= 8 KiB of device scratch. */
+int wk_mse_grad(const float* Kh, const double* K, int64_t count, double inv_scale, float* E,
+                double* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* wk_sgd_update -- w[k] -= lr * grad[k] for k < n (float). */
+int wk_sgd_update(float* w, const float* grad, int32_t n, float lr, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WIGNER_H */

@@ -1,0 +1,522 @@
+// Wigner kernel of eq.(4) (Sec. 2.2) on requested cells as an MFMA contraction:
+//   K[row][t] = c * sum_jj D[row][jj] * S[jj][t],  c = -2 / (hbar n_m),
+//   D[row][jj] = V(i + jj + 1) - V(i - jj - 1)      (the potential difference operand),
+//   S[jj][t]   = sin(2 pi (jj+1)(t+1) / n_m)        (the sine table, m = t + 1).
+// D never exists in HBM: each workgroup builds its BM x BK slice in LDS from the potential
+// (nearest-edge value outside the mesh); S comes from a per-device table (L2 resident).
+#include "lowp.h"
+#include "wk_internal.h"
+
+namespace wk {
+
+constexpr int KE_BK = 16;     // contraction depth staged per LDS tile
+constexpr int KE_THREADS = 256;
+
+// Row r -> (offset of its potential in V, cell index) for the BM rows of a block.
+template <int BM>
+__device__ __forceinline__ void load_rows(long row0, long R, int n_cells, int nx,
+                                          const int32_t* __restrict__ cells, long* rbase,
+                                          int* rcell) {
+    for (int rr = threadIdx.x; rr < BM; rr += blockDim.x) {
+        const long r = row0 + rr;
+        long base = 0;
+        int cell = -1;
+        if (r < R) {
+            const long b = r / n_cells;
+            const int ci = (int)(r - b * n_cells);
+            cell = cells ? cells[ci] : ci;
+            if (cell < 0 || cell >= nx) cell = -2;  // id outside the mesh: row of NaN
+            base = b * (long)nx;
+        }
+        rbase[rr] = base;
+        rcell[rr] = cell;
+    }
+}
+
+// FP64 path: v_mfma_f64_16x16x4_f64.  Four waves in a 2 x 2 arrangement; each wave owns a
+// (16 WM) x (16 WN) output tile.  Operand layouts (16x16x4 f64): lane l holds
+// A[l % 16][l / 16], B[l / 16][l % 16], and C[l / 16 + 4 e][l % 16] for e < 4.
+template <int WM, int WN>
+__global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
+    const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
+    int P, int n_m, int Pk, int Pn, const double* __restrict__ S, double c, int layout,
+    double* __restrict__ out) {
+    constexpr int BM = 32 * WM, BN = 32 * WN, BK = KE_BK;
+    __shared__ double Ds[BM][BK + 1];
+    __shared__ long rbase[BM];
+    __shared__ int rcell[BM];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const long row0 = (long)blockIdx.x * BM;
+    const int col0 = blockIdx.y * BN;
+
+    load_rows<BM>(row0, R, n_cells, nx, cells, rbase, rcell);
+
+    f64x4 acc[WM][WN];
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    const int lr = lane & 15, lk = lane >> 4;
+    const double* Sw = S + (long)col0 + wc * WN * 16 + lr;
+
+    for (int k0 = 0; k0 < Pk; k0 += BK) {
+        double bfrag[BK / 4][WN];
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks)
+#pragma unroll
+            for (int tn = 0; tn < WN; ++tn)
+                bfrag[ks][tn] = Sw[(long)(k0 + 4 * ks + lk) * Pn + tn * 16];
+
+        __syncthreads();  // rows staged / previous tile consumed
+        for (int e = threadIdx.x; e < BM * BK; e += KE_THREADS) {
+            const int rr = e / BK, kk = e - rr * BK;
+            const int cell = rcell[rr];
+            const int j = k0 + kk + 1;
+            double d = cell == -2 ? __builtin_nan("") : 0.0;
+            if (cell >= 0 && j <= P) {
+                const double* Vb = V + rbase[rr];
+                const int ip = min(cell + j, nx - 1), im = max(cell - j, 0);
+                d = Vb[ip] - Vb[im];
+            }
+            Ds[rr][kk] = d;
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            double afrag[WM];
+#pragma unroll
+            for (int tm = 0; tm < WM; ++tm) afrag[tm] = Ds[(wr * WM + tm) * 16 + lr][4 * ks + lk];
+#pragma unroll
+            for (int tm = 0; tm < WM; ++tm)
+#pragma unroll
+                for (int tn = 0; tn < WN; ++tn)
+                    acc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(afrag[tm], bfrag[ks][tn],
+                                                                     acc[tm][tn], 0, 0, 0);
+        }
+    }
+
+#pragma unroll
+    for (int tm = 0; tm < WM; ++tm) {
+#pragma unroll
+        for (int tn = 0; tn < WN; ++tn) {
+            const int t = col0 + (wc * WN + tn) * 16 + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const long row = row0 + (wr * WM + tm) * 16 + lk + 4 * e;
+                if (row >= R || t >= P) continue;
+                const double k = c * acc[tm][tn][e];
+                if (layout == WK_HALF) {
+                    out[row * P + t] = k;
+                } else {
+                    double* o = out + row * (long)n_m;
+                    if (t < P - 1) {
+                        o[P + 1 + t] = k;
+                        o[P - 1 - t] = -k;
+                    } else {
+                        o[0] = -k;
+                        o[P] = 0.0;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Reduced-precision path: v_mfma_f32_16x16x32_{bf16,f16} with FP32 accumulation.  Layouts
+// (16x16x32): lane l holds A[l % 16][8 (l / 16) + q], B[8 (l / 16) + q][l % 16] for q < 8,
+// and C[4 (l / 16) + e][l % 16] for e < 4.  The potential differences are formed in FP64
+// and rounded to the 16-bit format (hi); the split forms also keep lo = d - hi, and sum
+// hi*hi + hi*lo + lo*hi (the lo*lo term is below FP32 accumulation error).
+// The sine table is read transposed, St[t][jj] (it is symmetric), so each lane's eight
+// B elements are one contiguous 16-byte load.
+constexpr int LP_BK = 32;
+
+template <int PREC>
+struct LowpTraits;
+template <>
+struct LowpTraits<WK_BF16> {
+    typedef bf16x8 vec;
+    static constexpr bool split = false, half = false;
+};
+template <>
+struct LowpTraits<WK_FP16> {
+    typedef f16x8 vec;
+    static constexpr bool split = false, half = true;
+};
+template <>
+struct LowpTraits<WK_BF16X3> {
+    typedef bf16x8 vec;
+    static constexpr bool split = true, half = false;
+};
+template <>
+struct LowpTraits<WK_FP16X3> {
+    typedef f16x8 vec;
+    static constexpr bool split = true, half = true;
+};
+
+template <bool HALF>
+__device__ __forceinline__ f32x4 mfma16(const s16x8& a, const s16x8& b, f32x4 c) {
+    if constexpr (HALF)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+template <bool HALF>
+__device__ __forceinline__ void split16(double d, uint16_t* hi, uint16_t* lo) {
+    if constexpr (HALF) {
+        *hi = f16_bits(d);
+        *lo = f16_bits(d - (double)f16_value(*hi));
+    } else {
+        *hi = bf16_bits(d);
+        *lo = bf16_bits(d - (double)bf16_value(*hi));
+    }
+}
+
+template <int PREC, int WM, int WN>
+__global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
+    const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
+    int P, int n_m, int Pk, const uint16_t* __restrict__ St_hi, const uint16_t* __restrict__ St_lo,
+    float c, int layout, float* __restrict__ out) {
+    typedef LowpTraits<PREC> TR;
+    constexpr int BM = 32 * WM, BN = 32 * WN, BK = LP_BK, LD = BK + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t Dh[BM][LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Dl[TR::split ? BM : 1][LD];
+    __shared__ long rbase[BM];
+    __shared__ int rcell[BM];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const long row0 = (long)blockIdx.x * BM;
+    const int col0 = blockIdx.y * BN;
+    const int lr = lane & 15, lk = lane >> 4;
+
+    load_rows<BM>(row0, R, n_cells, nx, cells, rbase, rcell);
+
+    f32x4 acc[WM][WN];
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < Pk; k0 += BK) {
+        s16x8 bh[WN], bl[WN];
+#pragma unroll
+        for (int tn = 0; tn < WN; ++tn) {
+            const long off = (long)(col0 + (wc * WN + tn) * 16 + lr) * Pk + k0 + 8 * lk;
+            bh[tn] = *reinterpret_cast<const s16x8*>(St_hi + off);
+            if constexpr (TR::split) bl[tn] = *reinterpret_cast<const s16x8*>(St_lo + off);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < BM * (BK / 8); e += KE_THREADS) {
+            const int rr = e / (BK / 8), kq = (e - rr * (BK / 8)) * 8;
+            const int cell = rcell[rr];
+            s16x8 hv, lv;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = k0 + kq + q + 1;
+                double d = cell == -2 ? __builtin_nan("") : 0.0;
+                if (cell >= 0 && j <= P) {
+                    const double* Vb = V + rbase[rr];
+                    d = Vb[min(cell + j, nx - 1)] - Vb[max(cell - j, 0)];
+                }
+                uint16_t h, l;
+                split16<TR::half>(d, &h, &l);
+                hv[q] = (short)h;
+                lv[q] = (short)l;
+            }
+            *reinterpret_cast<s16x8*>(&Dh[rr][kq]) = hv;
+            if constexpr (TR::split) *reinterpret_cast<s16x8*>(&Dl[rr][kq]) = lv;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tm = 0; tm < WM; ++tm) {
+            const int rr = (wr * WM + tm) * 16 + lr;
+            const s16x8 ah = *reinterpret_cast<const s16x8*>(&Dh[rr][8 * lk]);
+            s16x8 al;
+            if constexpr (TR::split) al = *reinterpret_cast<const s16x8*>(&Dl[rr][8 * lk]);
+#pragma unroll
+            for (int tn = 0; tn < WN; ++tn) {
+                acc[tm][tn] = mfma16<TR::half>(ah, bh[tn], acc[tm][tn]);
+                if constexpr (TR::split) {
+                    acc[tm][tn] = mfma16<TR::half>(ah, bl[tn], acc[tm][tn]);
+                    acc[tm][tn] = mfma16<TR::half>(al, bh[tn], acc[tm][tn]);
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int tm = 0; tm < WM; ++tm) {
+#pragma unroll
+        for (int tn = 0; tn < WN; ++tn) {
+            const int t = col0 + (wc * WN + tn) * 16 + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const long row = row0 + (wr * WM + tm) * 16 + 4 * lk + e;
+                if (row >= R || t >= P) continue;
+                const float k = c * acc[tm][tn][e];
+                if (layout == WK_HALF) {
+                    out[row * P + t] = k;
+                } else {
+                    float* o = out + row * (long)n_m;
+                    if (t < P - 1) {
+                        o[P + 1 + t] = k;
+                        o[P - 1 - t] = -k;
+                    } else {
+                        o[0] = -k;
+                        o[P] = 0.0f;
+                    }
+                }
+            }
+        }
+    }
+}
+
+static int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_t* cells,
+                       int n_cells, int layout, double* out, hipStream_t stream) {
+    constexpr int WM = 2, WN = 2, BM = 32 * WM, BN = 32 * WN;
+    const int n_m = mesh->n_m, P = n_m / 2;
+    const int Pk = round_up(P, KE_BK), Pn = round_up(P, BN);
+    int err = WK_OK;
+    const double* S = static_cast<const double*>(sine_table(n_m, 0, Pk, Pn, stream, &err));
+    if (!S) return err;
+    const long R = (long)B * n_cells;
+    if (R == 0) return WK_OK;
+    const double c = -2.0 / (mesh->hbar * (double)n_m);
+    dim3 grid((unsigned)((R + BM - 1) / BM), (unsigned)(Pn / BN));
+    hipLaunchKernelGGL((kernel_eval_f64<WM, WN>), grid, dim3(KE_THREADS), 0, stream, V, mesh->nx,
+                       R, n_cells, cells, P, n_m, Pk, Pn, S, c, layout, out);
+    return check_launch("kernel_eval_f64");
+}
+
+
+int kernel_eval_1d_lowp(const wk_mesh* mesh, const double* V, int B, const int32_t* cells,
+                        int n_cells, int prec, int layout, float* out, hipStream_t stream) {
+    constexpr int WM = 2, WN = 2, BM = 32 * WM, BN = 32 * WN;
+    const int n_m = mesh->n_m, P = n_m / 2;
+    const int Pk = round_up(P, LP_BK), Pn = round_up(P, BN);
+    const bool half = prec == WK_FP16 || prec == WK_FP16X3;
+    const bool split = prec == WK_BF16X3 || prec == WK_FP16X3;
+    int err = WK_OK;
+    // rows t (Pn of them), columns jj (Pk): St[t][jj] = S[jj][t]
+    const uint16_t* hi = static_cast<const uint16_t*>(sine_table(n_m, half ? 3 : 1, Pn, Pk, stream, &err));
+    if (!hi) return err;
+    const uint16_t* lo = hi;
+    if (split) {
+        lo = static_cast<const uint16_t*>(sine_table(n_m, half ? 4 : 2, Pn, Pk, stream, &err));
+        if (!lo) return err;
+    }
+    const long R = (long)B * n_cells;
+    const float c = (float)(-2.0 / (mesh->hbar * (double)n_m));
+    dim3 grid((unsigned)((R + BM - 1) / BM), (unsigned)(Pn / BN));
+    switch (prec) {
+        case WK_BF16:
+            hipLaunchKernelGGL((kernel_eval_lowp<WK_BF16, WM, WN>), grid, dim3(KE_THREADS), 0, stream,
+                               V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            break;
+        case WK_FP16:
+            hipLaunchKernelGGL((kernel_eval_lowp<WK_FP16, WM, WN>), grid, dim3(KE_THREADS), 0, stream,
+                               V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            break;
+        case WK_BF16X3:
+            hipLaunchKernelGGL((kernel_eval_lowp<WK_BF16X3, WM, WN>), grid, dim3(KE_THREADS), 0,
+                               stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            break;
+        default:
+            hipLaunchKernelGGL((kernel_eval_lowp<WK_FP16X3, WM, WN>), grid, dim3(KE_THREADS), 0,
+                               stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            break;
+    }
+    return check_launch("kernel_eval_lowp");
+}
+
+}  // namespace wk
+
+extern "C" int wk_kernel_eval(const wk_mesh* mesh, const double* V, int32_t B,
+                              const int32_t* cells, int32_t n_cells, int32_t prec, int32_t layout,
+                              void* K_out, void* stream) {
+    WK_REQUIRE(mesh != nullptr, "wk_kernel_eval: mesh is NULL");
+    WK_REQUIRE(mesh->dim == 1 || mesh->dim == 2, "wk_kernel_eval: dim must be 1 or 2");
+    WK_REQUIRE(mesh->nx > 0 && mesh->ny > 0, "wk_kernel_eval: empty mesh");
+    WK_REQUIRE(mesh->n_m >= 2 && (mesh->n_m % 2) == 0, "wk_kernel_eval: n_m must be even and >= 2");
+    WK_REQUIRE(mesh->hbar > 0.0, "wk_kernel_eval: hbar must be positive");
+    WK_REQUIRE(B >= 0 && n_cells >= 0, "wk_kernel_eval: negative size");
+    WK_REQUIRE(layout == WK_FULL || layout == WK_HALF, "wk_kernel_eval: bad layout");
+    if ((long)B * n_cells == 0) return WK_OK;
+    const long ncell = (long)mesh->nx * mesh->ny;
+    WK_REQUIRE(cells != nullptr || n_cells == ncell,
+               "wk_kernel_eval: with cells == NULL, n_cells must be the number of cells");
+    WK_REQUIRE(V != nullptr && K_out != nullptr, "wk_kernel_eval: NULL array");
+    if (mesh->dim == 1) {
+        WK_REQUIRE(mesh->ny == 1, "wk_kernel_eval: 1-D mesh needs ny == 1");
+        if (prec == WK_FP64)
+            return wk::kernel_eval_1d_f64(mesh, V, B, cells, n_cells, layout,
+                                          static_cast<double*>(K_out), wk::as_stream(stream));
+        if (prec >= WK_BF16 && prec <= WK_FP16X3)
+            return wk::kernel_eval_1d_lowp(mesh, V, B, cells, n_cells, prec, layout,
+                                           static_cast<float*>(K_out), wk::as_stream(stream));
+        return wk::fail(WK_EINVAL, "wk_kernel_eval: unknown precision");
+    }
+    return wk::fail(WK_EINVAL, "wk_kernel_eval: 2-D not supported");
+}
+
+// ----------------------------------------------------------------------------- adjoint
+// K is linear in V (eq.(4)), so dL/dV = (dK/dV)^T G, computed in three deterministic steps:
+//   1. fold the table gradient onto the unique momenta: G1[r][t] = dL/dK(m = t + 1)
+//      (full layout: G(m) - G(-m), and -G(-P) for m = P);
+//   2. GD[r][jj] = c * sum_t G1[r][t] S[t][jj]  (FP64 MFMA, the sine table is symmetric);
+//   3. dV[b][l] += sum_j GD[l - j][j] - sum_j GD[l + j][j], plus at the two edges the sums
+//      of every term whose clamped index lands there (per-row tails, then a fixed-order sum).
+namespace wk {
+
+template <int WM, int WN>
+__global__ __launch_bounds__(KE_THREADS) void kernel_bwd_gemm(
+    const double* __restrict__ G, long R, int P, int n_m, int layout, int Pk, int Pn,
+    const double* __restrict__ S, double c, double* __restrict__ GD) {
+    constexpr int BM = 32 * WM, BN = 32 * WN, BK = KE_BK;
+    __shared__ double As[BM][BK + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const long row0 = (long)blockIdx.x * BM;
+    const int col0 = blockIdx.y * BN;
+    const int lr = lane & 15, lk = lane >> 4;
+    f64x4 acc[WM][WN];
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const double* Sw = S + (long)col0 + wc * WN * 16 + lr;
+    for (int k0 = 0; k0 < Pk; k0 += BK) {
+        double bfrag[BK / 4][WN];
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks)
+#pragma unroll
+            for (int tn = 0; tn < WN; ++tn) bfrag[ks][tn] = Sw[(long)(k0 + 4 * ks + lk) * Pn + tn * 16];
+        __syncthreads();
+        for (int e = threadIdx.x; e < BM * BK; e += KE_THREADS) {
+            const int rr = e / BK, kk = e - rr * BK;
+            const long r = row0 + rr;
+            const int t = k0 + kk;
+            double g = 0.0;
+            if (r < R && t < P) {
+                if (layout == WK_HALF) {
+                    g = G[r * P + t];
+                } else {
+                    const double* gr = G + r * (long)n_m;
+                    g = t < P - 1 ? gr[P + 1 + t] - gr[P - 1 - t] : -gr[0];
+                }
+            }
+            As[rr][kk] = g;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            double afrag[WM];
+#pragma unroll
+            for (int tm = 0; tm < WM; ++tm) afrag[tm] = As[(wr * WM + tm) * 16 + lr][4 * ks + lk];
+#pragma unroll
+            for (int tm = 0; tm < WM; ++tm)
+#pragma unroll
+                for (int tn = 0; tn < WN; ++tn)
+                    acc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(afrag[tm], bfrag[ks][tn],
+                                                                     acc[tm][tn], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int tm = 0; tm < WM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < WN; ++tn) {
+            const int jj = col0 + (wc * WN + tn) * 16 + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const long row = row0 + (wr * WM + tm) * 16 + lk + 4 * e;
+                if (row < R && jj < P) GD[row * P + jj] = c * acc[tm][tn][e];
+            }
+        }
+}
+
+// Per row i of potential b: sums of GD over the offsets whose clamped index is an edge.
+__global__ void kernel_bwd_tails(const double* __restrict__ GD, long R, int nx, int P,
+                                 double* __restrict__ tail_hi, double* __restrict__ tail_lo) {
+    const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int i = (int)(r % nx);
+    const double* g = GD + r * P;
+    double hi = 0.0, lo = 0.0;
+    for (int j = 1; j <= P; ++j) {
+        if (i + j >= nx - 1) hi += g[j - 1];   // V(i + j) clamps to (or is) cell nx - 1
+        if (i - j <= 0) lo += g[j - 1];        // V(i - j) clamps to (or is) cell 0
+    }
+    tail_hi[r] = hi;
+    tail_lo[r] = lo;
+}
+
+__global__ void kernel_bwd_gather(const double* __restrict__ GD, int B, int nx, int P,
+                                  const double* __restrict__ tail_hi,
+                                  const double* __restrict__ tail_lo, double* __restrict__ dV) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)B * nx) return;
+    const long b = idx / nx;
+    const int l = (int)(idx - b * nx);
+    const double* g = GD + b * (long)nx * P;
+    double acc = 0.0;
+    if (l < nx - 1)
+        for (int j = 1; j <= P && l - j >= 0; ++j) acc += g[(long)(l - j) * P + (j - 1)];
+    if (l > 0)
+        for (int j = 1; j <= P && l + j <= nx - 1; ++j) acc -= g[(long)(l + j) * P + (j - 1)];
+    if (l == nx - 1)
+        for (int i = 0; i < nx; ++i) acc += tail_hi[b * nx + i];
+    if (l == 0)
+        for (int i = 0; i < nx; ++i) acc -= tail_lo[b * nx + i];
+    dV[idx] += acc;
+}
+
+}  // namespace wk
+
+extern "C" size_t wk_kernel_bwd_workspace(const wk_mesh* mesh, int32_t B) {
+    if (!mesh || mesh->n_m < 2 || B < 0 || mesh->nx <= 0) return 0;
+    const size_t R = (size_t)B * mesh->nx;
+    return sizeof(double) * (R * (size_t)(mesh->n_m / 2) + 2 * R) + 256;
+}
+
+extern "C" int wk_kernel_bwd(const wk_mesh* mesh, const double* G, int32_t B, int32_t layout,
+                             double* dV, void* ws, size_t ws_bytes, void* stream) {
+    using namespace wk;
+    WK_REQUIRE(mesh != nullptr, "wk_kernel_bwd: mesh is NULL");
+    WK_REQUIRE(mesh->dim == 1 && mesh->ny == 1 && mesh->nx > 0, "wk_kernel_bwd: 1-D meshes only");
+    WK_REQUIRE(mesh->n_m >= 2 && mesh->n_m % 2 == 0, "wk_kernel_bwd: n_m must be even");
+    WK_REQUIRE(mesh->hbar > 0.0, "wk_kernel_bwd: hbar must be positive");
+    WK_REQUIRE(layout == WK_FULL || layout == WK_HALF, "wk_kernel_bwd: bad layout");
+    WK_REQUIRE(B >= 0, "wk_kernel_bwd: negative batch");
+    if (B == 0) return WK_OK;
+    WK_REQUIRE(G && dV && ws, "wk_kernel_bwd: NULL array");
+    WK_REQUIRE(ws_bytes >= wk_kernel_bwd_workspace(mesh, B), "wk_kernel_bwd: workspace too small");
+    constexpr int WM = 2, WN = 2, BM = 32 * WM, BN = 32 * WN;
+    hipStream_t s = as_stream(stream);
+    const int n_m = mesh->n_m, P = n_m / 2, nx = mesh->nx;
+    const int Pk = round_up(P, KE_BK), Pn = round_up(P, BN);
+    int err = WK_OK;
+    const double* S = static_cast<const double*>(sine_table(n_m, 0, Pk, Pn, s, &err));
+    if (!S) return err;
+    const long R = (long)B * nx;
+    double* GD = static_cast<double*>(ws);
+    double* th = GD + R * P;
+    double* tl = th + R;
+    const double c = -2.0 / (mesh->hbar * (double)n_m);
+    hipLaunchKernelGGL((kernel_bwd_gemm<WM, WN>), dim3((unsigned)((R + BM - 1) / BM), Pn / BN),
+                       dim3(KE_THREADS), 0, s, G, R, P, n_m, layout, Pk, Pn, S, c, GD);
+    hipLaunchKernelGGL(kernel_bwd_tails, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, GD, R,
+                       nx, P, th, tl);
+    hipLaunchKernelGGL(kernel_bwd_gather, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, GD, B,
+                       nx, P, th, tl, dV);
+    return check_launch("wk_kernel_bwd");
+}

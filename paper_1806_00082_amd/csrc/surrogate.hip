@@ -1,0 +1,575 @@
+// The trainable reduced-width kernel network of eq.(5) (Sec. 2.3) and its hand-written
+// adjoint, plus the MSE gradient and SGD update of the training loop (Sec. 3).
+//
+//   Kh[r][t] = Pi(t) * sum_g A[r][g] Bm[g][t],                 m = t + 1, t < P
+//   A[r][g]  = sum_p wV[p] V(clamp(i_r + o(g,p))),             o(g,p) = -P + N g + p
+//   Bm[g][t] = W[g] sin(u_g m),  u_g = (2 pi / n_m) sum_p wT[p] o(g,p)
+//   Pi(t)    = prod_{s < log2 N} cos(2^s pi m / n_m)
+// A is a stride-N convolution of the potential (the f_V of Sec. 3) built per row tile in
+// LDS; Bm and Pi are tiny (H x P, P) and are formed once per call by surr_prep.
+#include <map>
+#include <mutex>
+
+#include "lowp.h"
+#include "wk_internal.h"
+
+namespace wk {
+
+constexpr int SU_THREADS = 256;
+constexpr int SU_BM = 32;            // rows per workgroup (FP32 / BF16 forward)
+constexpr int SD_BM = 16;            // rows per workgroup (FP64 forward, backward tiles)
+constexpr int SB_MAXBLK = 1024;      // workgroups of the backward (each loops over row tiles)
+constexpr int SU_MAXH = 256;         // largest hidden width supported
+constexpr int SU_MAXN = 64;          // largest group size supported
+
+__device__ __forceinline__ double two_pi_over(int n_m) { return 6.283185307179586476925286766559 / (double)n_m; }
+
+// Bm (H x Pn, zero padded) and Pi (Pn) in double and float.
+__global__ void surr_prep(int n_m, int N, int H, int Pn, const float* __restrict__ wT,
+                          const float* __restrict__ W, double* __restrict__ Bd,
+                          float* __restrict__ Bf, double* __restrict__ Pid, float* __restrict__ Pif,
+                          double* __restrict__ u_out) {
+    const int P = n_m / 2;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int L = 0;
+    while ((1 << L) < N) ++L;
+    if (idx < (long)H * Pn) {
+        const int g = (int)(idx / Pn), t = (int)(idx % Pn);
+        double u = 0.0;
+        for (int p = 0; p < N; ++p) u += (double)wT[p] * (two_pi_over(n_m) * (double)(-P + N * g + p));
+        const double v = t < P ? (double)W[g] * sin(u * (double)(t + 1)) : 0.0;
+        Bd[idx] = v;
+        Bf[idx] = (float)v;
+        if (t == 0) u_out[g] = u;
+    }
+    if (idx < Pn) {
+        double pr = 1.0;
+        if (idx < P)
+            for (int s = 0; s < L; ++s)
+                pr *= cospi((double)(1 << s) * (double)(idx + 1) / (double)n_m);
+        else
+            pr = 0.0;
+        Pid[idx] = pr;
+        Pif[idx] = (float)pr;
+    }
+}
+
+template <int BM, typename T>
+__device__ __forceinline__ void conv_rows(const double* __restrict__ V, int nx, long row0, long R,
+                                          int n_cells, const int32_t* __restrict__ cells, int P,
+                                          int N, int H, const float* __restrict__ wV, T* A,
+                                          int lda, int* rcell, long* rbase) {
+    __syncthreads();  // previous users of A / rcell are done
+    for (int rr = threadIdx.x; rr < BM; rr += blockDim.x) {
+        const long r = row0 + rr;
+        int cell = -1;
+        long base = 0;
+        if (r < R) {
+            const long b = r / n_cells;
+            const int ci = (int)(r - b * n_cells);
+            cell = cells ? cells[ci] : ci;
+            if (cell < 0 || cell >= nx) cell = -2;
+            base = b * (long)nx;
+        }
+        rcell[rr] = cell;
+        rbase[rr] = base;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < BM * H; e += blockDim.x) {
+        const int rr = e / H, g = e - rr * H;
+        const int cell = rcell[rr];
+        double a = cell == -2 ? __builtin_nan("") : 0.0;
+        if (cell >= 0) {
+            const double* Vb = V + rbase[rr];
+            a = 0.0;
+            for (int p = 0; p < N; ++p) {
+                const int l = min(max(cell - P + N * g + p, 0), nx - 1);
+                a += (double)wV[p] * Vb[l];
+            }
+        }
+        A[rr * lda + g] = (T)a;
+    }
+    __syncthreads();
+}
+
+// Reference-precision forward: FP64 FMAs, one thread per output.
+__global__ __launch_bounds__(SU_THREADS) void surr_fwd_f64(
+    const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
+    int P, int N, int H, int Pn, const float* __restrict__ wV, const double* __restrict__ Bd,
+    const double* __restrict__ Pid, double* __restrict__ out) {
+    extern __shared__ double smem_d[];
+    __shared__ int rcell[SD_BM];
+    __shared__ long rbase[SD_BM];
+    double* A = smem_d;  // [SD_BM][H + 1]
+    const long row0 = (long)blockIdx.x * SD_BM;
+    conv_rows<SD_BM, double>(V, nx, row0, R, n_cells, cells, P, N, H, wV, A, H + 1, rcell, rbase);
+    for (int e = threadIdx.x; e < SD_BM * P; e += blockDim.x) {
+        const int rr = e / P, t = e - rr * P;
+        const long r = row0 + rr;
+        if (r >= R) continue;
+        double acc = 0.0;
+        for (int g = 0; g < H; ++g) acc += A[rr * (H + 1) + g] * Bd[(long)g * Pn + t];
+        out[r * P + t] = Pid[t] * acc;
+    }
+}
+
+// FP32 forward on v_mfma_f32_16x16x4_f32 (lane l: A[l%16][l/16], B[l/16][l%16],
+// C[4(l/16)+e][l%16]).  Four waves split the columns; each wave covers all SU_BM rows.
+__global__ __launch_bounds__(SU_THREADS) void surr_fwd_f32(
+    const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
+    int P, int N, int H, int Hk, int Pn, const float* __restrict__ wV, const float* __restrict__ Bf,
+    const float* __restrict__ Pif, float* __restrict__ out) {
+    extern __shared__ float smem_f[];
+    __shared__ int rcell[SU_BM];
+    __shared__ long rbase[SU_BM];
+    float* A = smem_f;  // [SU_BM][Hk + 1], zero padded beyond H
+    const long row0 = (long)blockIdx.x * SU_BM;
+    for (int e = threadIdx.x; e < SU_BM * (Hk + 1); e += blockDim.x) A[e] = 0.f;
+    __syncthreads();
+    conv_rows<SU_BM, float>(V, nx, row0, R, n_cells, cells, P, N, H, wV, A, Hk + 1, rcell, rbase);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    // column tiles of 16 handed to waves round-robin
+    for (int ct = wave; ct * 16 < Pn; ct += 4) {
+        f32x4 acc[SU_BM / 16];
+#pragma unroll
+        for (int tm = 0; tm < SU_BM / 16; ++tm) acc[tm] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < Hk; k0 += 4) {
+            const int g = k0 + lk;
+            const float b = g < H ? Bf[(long)g * Pn + ct * 16 + lr] : 0.f;
+#pragma unroll
+            for (int tm = 0; tm < SU_BM / 16; ++tm) {
+                const float a = A[(tm * 16 + lr) * (Hk + 1) + g];
+                acc[tm] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[tm], 0, 0, 0);
+            }
+        }
+        const int t = ct * 16 + lr;
+        if (t < P) {
+            const float pi = Pif[t];
+#pragma unroll
+            for (int tm = 0; tm < SU_BM / 16; ++tm)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const long r = row0 + tm * 16 + 4 * lk + e;
+                    if (r < R) out[r * P + t] = pi * acc[tm][e];
+                }
+        }
+    }
+}
+
+// BF16 inference forward on v_mfma_f32_16x16x32_bf16 (operands rounded to bf16, FP32 sums).
+__global__ __launch_bounds__(SU_THREADS) void surr_fwd_bf16(
+    const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
+    int P, int N, int H, int Hk, int Pn, const float* __restrict__ wV, const float* __restrict__ Bf,
+    const float* __restrict__ Pif, float* __restrict__ out) {
+    extern __shared__ float smem_f[];
+    __shared__ int rcell[SU_BM];
+    __shared__ long rbase[SU_BM];
+    float* A = smem_f;  // [SU_BM][Hk + 1]
+    const long row0 = (long)blockIdx.x * SU_BM;
+    for (int e = threadIdx.x; e < SU_BM * (Hk + 1); e += blockDim.x) A[e] = 0.f;
+    __syncthreads();
+    conv_rows<SU_BM, float>(V, nx, row0, R, n_cells, cells, P, N, H, wV, A, Hk + 1, rcell, rbase);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int ct = wave; ct * 16 < Pn; ct += 4) {
+        f32x4 acc[SU_BM / 16];
+#pragma unroll
+        for (int tm = 0; tm < SU_BM / 16; ++tm) acc[tm] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < Hk; k0 += 32) {
+            s16x8 b;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int g = k0 + 8 * lk + q;
+                b[q] = (short)bf16_bits_f(g < H ? Bf[(long)g * Pn + ct * 16 + lr] : 0.f);
+            }
+#pragma unroll
+            for (int tm = 0; tm < SU_BM / 16; ++tm) {
+                s16x8 a;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    a[q] = (short)bf16_bits_f(A[(tm * 16 + lr) * (Hk + 1) + k0 + 8 * lk + q]);
+                acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                                 __builtin_bit_cast(bf16x8, b),
+                                                                 acc[tm], 0, 0, 0);
+            }
+        }
+        const int t = ct * 16 + lr;
+        if (t < P) {
+            const float pi = Pif[t];
+#pragma unroll
+            for (int tm = 0; tm < SU_BM / 16; ++tm)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const long r = row0 + tm * 16 + 4 * lk + e;
+                    if (r < R) out[r * P + t] = pi * acc[tm][e];
+                }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------- backward
+// Per workgroup of SU_BM rows: Et = E * Pi (LDS), GA = Et Bm^T (LDS and, for dV, global),
+// block partials of GB = A^T Et (H x P) and of dwV.  A fixed-order reduction over the
+// workgroups then forms dW, du (-> dwT) and dwV.  dV is a gather over rows (all-cells only).
+struct SurrWS {
+    float* GBpart;    // [nblk][H][P]
+    float* wVpart;    // [nblk][N]
+    float* GA;        // [R][H]   (only when dV is requested)
+    double* u;        // [H]
+    double* Bd;       // [H][Pn]
+    float* Bf;        // [H][Pn]
+    double* Pid;      // [Pn]
+    float* Pif;       // [Pn]
+};
+
+__global__ __launch_bounds__(SU_THREADS) void surr_bwd_block(
+    const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
+    int P, int N, int H, int Pn, const float* __restrict__ wV, const float* __restrict__ E,
+    SurrWS w, int want_GA) {
+    extern __shared__ float smem_f[];
+    __shared__ int rcell[SD_BM];
+    __shared__ long rbase[SD_BM];
+    float* A = smem_f;                       // [SD_BM][H + 1]
+    float* Et = A + SD_BM * (H + 1);         // [SD_BM][P + 1]
+    float* GA = Et + SD_BM * (P + 1);        // [SD_BM][H + 1]
+    float* gbp = w.GBpart + (long)blockIdx.x * H * P;   // this workgroup's private partials
+    float* wvp = w.wVpart + (long)blockIdx.x * N;
+    for (int e = threadIdx.x; e < H * P; e += blockDim.x) gbp[e] = 0.f;
+    for (int p = threadIdx.x; p < N; p += blockDim.x) wvp[p] = 0.f;
+    const long ntiles = (R + SD_BM - 1) / SD_BM;
+    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long row0 = tile * SD_BM;
+        conv_rows<SD_BM, float>(V, nx, row0, R, n_cells, cells, P, N, H, wV, A, H + 1, rcell, rbase);
+        for (int e = threadIdx.x; e < SD_BM * P; e += blockDim.x) {
+            const int rr = e / P, t = e - rr * P;
+            const long r = row0 + rr;
+            Et[rr * (P + 1) + t] = (r < R && rcell[rr] >= 0) ? E[r * P + t] * w.Pif[t] : 0.f;
+        }
+        __syncthreads();
+        // GA = Et Bm^T
+        for (int e = threadIdx.x; e < SD_BM * H; e += blockDim.x) {
+            const int rr = e / H, g = e - rr * H;
+            float acc = 0.f;
+            for (int t = 0; t < P; ++t) acc = fmaf(Et[rr * (P + 1) + t], w.Bf[(long)g * Pn + t], acc);
+            GA[rr * (H + 1) + g] = acc;
+            const long r = row0 + rr;
+            if (want_GA && r < R) w.GA[r * H + g] = acc;
+        }
+        __syncthreads();
+        // GB partial += A^T Et over this tile (each entry owned by one thread)
+        for (int e = threadIdx.x; e < H * P; e += blockDim.x) {
+            const int g = e / P, t = e - g * P;
+            float acc = gbp[e];
+            for (int rr = 0; rr < SD_BM; ++rr)
+                if (rcell[rr] >= 0) acc = fmaf(A[rr * (H + 1) + g], Et[rr * (P + 1) + t], acc);
+            gbp[e] = acc;
+        }
+        // dwV partial += sum_rows sum_g GA[r][g] V(clamp(i + o(g,p)))  (one wave per tap)
+        for (int p = threadIdx.x >> 6; p < N; p += SU_THREADS / 64) {
+            float acc = 0.f;
+            for (int e = threadIdx.x & 63; e < SD_BM * H; e += 64) {
+                const int rr = e / H, g = e - rr * H;
+                const int cell = rcell[rr];
+                if (cell < 0) continue;
+                const int l = min(max(cell - P + N * g + p, 0), nx - 1);
+                acc = fmaf(GA[rr * (H + 1) + g], (float)V[rbase[rr] + l], acc);
+            }
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            if ((threadIdx.x & 63) == 0) wvp[p] += acc;
+        }
+    }
+}
+
+__global__ void zero_grads(float* a, int na, float* b, int nb, float* c, int nc) {
+    for (int i = threadIdx.x; i < na; i += blockDim.x) a[i] = 0.f;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) b[i] = 0.f;
+    for (int i = threadIdx.x; i < nc; i += blockDim.x) c[i] = 0.f;
+}
+
+// Fixed-order sum of the block partials; one thread per (g, t) of GB, then dW, du, dwT, dwV.
+__global__ void surr_bwd_reduce_gb(int nblk, int H, int P, SurrWS w) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)H * P) return;
+    float acc = 0.f;
+    for (int k = 0; k < nblk; ++k) acc += w.GBpart[(long)k * H * P + e];
+    w.GBpart[e] = acc;  // block 0's slot now holds the total
+}
+
+__global__ void surr_bwd_params(int n_m, int N, int H, int P, int Pn, int nblk,
+                                const float* __restrict__ W, SurrWS w, float* __restrict__ dwV,
+                                float* __restrict__ dwT, float* __restrict__ dW) {
+    __shared__ double du_s[SU_MAXH];
+    const int tid = threadIdx.x;
+    for (int g = tid; g < H; g += blockDim.x) {
+        const double u = w.u[g];
+        double dw = 0.0, du = 0.0;
+        for (int t = 0; t < P; ++t) {
+            const double gb = (double)w.GBpart[(long)g * P + t];
+            const double m = (double)(t + 1);
+            dw += gb * sin(u * m);
+            du += gb * (double)W[g] * m * cos(u * m);
+        }
+        dW[g] = (float)dw;
+        du_s[g] = du;
+    }
+    __syncthreads();
+    const int Pm = n_m / 2;
+    for (int p = tid; p < N; p += blockDim.x) {
+        double acc = 0.0;
+        for (int g = 0; g < H; ++g) acc += du_s[g] * (two_pi_over(n_m) * (double)(-Pm + N * g + p));
+        dwT[p] = (float)acc;
+        double sv = 0.0;
+        for (int k = 0; k < nblk; ++k) sv += (double)w.wVpart[(long)k * N + p];
+        dwV[p] = (float)sv;
+    }
+}
+
+// dV[b][l] += sum over rows i of potential b, groups g and taps p with
+// clamp(i + o(g,p)) = l of GA[i][g] wV[p]  (all-cells layout: row = b * nx + i).
+__global__ void surr_bwd_dV(int B, int nx, int P, int N, int H, const float* __restrict__ wV,
+                            const float* __restrict__ GA, double* __restrict__ dV) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)B * nx) return;
+    const long b = idx / nx;
+    const int l = (int)(idx - b * nx);
+    const float* ga = GA + b * (long)nx * H;
+    double acc = 0.0;
+    for (int g = 0; g < H; ++g)
+        for (int p = 0; p < N; ++p) {
+            const int o = -P + N * g + p;
+            if (l > 0 && l < nx - 1) {
+                const int i = l - o;
+                if (i >= 0 && i < nx) acc += (double)ga[(long)i * H + g] * (double)wV[p];
+            } else {
+                // edge cell: every row whose (clamped) tap lands here
+                for (int i = 0; i < nx; ++i) {
+                    const int q = min(max(i + o, 0), nx - 1);
+                    if (q == l) acc += (double)ga[(long)i * H + g] * (double)wV[p];
+                }
+            }
+        }
+    dV[idx] += acc;
+}
+
+static int surr_check(const wk_mesh* mesh, int N, int* H) {
+    WK_REQUIRE(mesh && mesh->dim == 1 && mesh->ny == 1 && mesh->nx > 0, "surrogate: 1-D meshes only");
+    WK_REQUIRE(mesh->n_m >= 2 && mesh->n_m % 2 == 0, "surrogate: n_m must be even");
+    WK_REQUIRE(N >= 1 && (N & (N - 1)) == 0 && mesh->n_m % N == 0 && N <= SU_MAXN,
+               "surrogate: N must be a power of two dividing n_m");
+    *H = mesh->n_m / N;
+    WK_REQUIRE(*H <= SU_MAXH, "surrogate: hidden width too large");
+    return WK_OK;
+}
+
+static long surr_nblk(long R) {
+    const long t = (R + SD_BM - 1) / SD_BM;
+    return t < SB_MAXBLK ? t : SB_MAXBLK;
+}
+
+static size_t surr_ws_bytes(int H, int P, int N, long R, bool with_GA) {
+    const long nblk = surr_nblk(R);
+    const int Pn = (P + 15) / 16 * 16;
+    size_t b = 0;
+    b += sizeof(float) * (size_t)nblk * H * P;
+    b += sizeof(float) * (size_t)nblk * N;
+    b += with_GA ? sizeof(float) * (size_t)R * H : 0;
+    b += sizeof(double) * H + sizeof(double) * (size_t)H * Pn + sizeof(float) * (size_t)H * Pn;
+    b += sizeof(double) * Pn + sizeof(float) * Pn;
+    return b + 8 * 256;
+}
+
+static SurrWS surr_carve(void* ws, int H, int P, int N, long R, bool with_GA) {
+    const long nblk = surr_nblk(R);
+    const int Pn = (P + 15) / 16 * 16;
+    char* p = static_cast<char*>(ws);
+    auto take = [&](size_t n) {
+        char* q = p;
+        p += (n + 255) / 256 * 256;
+        return q;
+    };
+    SurrWS w;
+    w.GBpart = reinterpret_cast<float*>(take(sizeof(float) * (size_t)nblk * H * P));
+    w.wVpart = reinterpret_cast<float*>(take(sizeof(float) * (size_t)nblk * N));
+    w.GA = with_GA ? reinterpret_cast<float*>(take(sizeof(float) * (size_t)R * H)) : nullptr;
+    w.u = reinterpret_cast<double*>(take(sizeof(double) * H));
+    w.Bd = reinterpret_cast<double*>(take(sizeof(double) * (size_t)H * Pn));
+    w.Bf = reinterpret_cast<float*>(take(sizeof(float) * (size_t)H * Pn));
+    w.Pid = reinterpret_cast<double*>(take(sizeof(double) * Pn));
+    w.Pif = reinterpret_cast<float*>(take(sizeof(float) * Pn));
+    return w;
+}
+
+// Scratch for the forward's Bm/Pi tables: a per-device buffer grown on demand (prep data of
+// a few hundred KB at most).
+static void* fwd_scratch(size_t bytes, int* err) {
+    static std::mutex mu;
+    static std::map<int, std::pair<void*, size_t>> bufs;
+    int dev = 0;
+    *err = WK_OK;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *err = fail(WK_EHIP, "hipGetDevice failed");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    auto& e = bufs[dev];
+    if (e.second < bytes) {
+        if (e.first) (void)hipFree(e.first);
+        e.first = nullptr;
+        if (hipMalloc(&e.first, bytes) != hipSuccess) {
+            e.second = 0;
+            *err = fail(WK_EHIP, "surrogate scratch hipMalloc failed");
+            return nullptr;
+        }
+        e.second = bytes;
+    }
+    return e.first;
+}
+
+}  // namespace wk
+
+using namespace wk;
+
+extern "C" int wk_surrogate_fwd(const wk_mesh* mesh, int32_t N, const float* wV, const float* wT,
+                                const float* W, const double* V, int32_t B,
+                                const int32_t* cells, int32_t n_cells, int32_t prec, void* K_out,
+                                void* stream) {
+    int H;
+    int rc = surr_check(mesh, N, &H);
+    if (rc) return rc;
+    WK_REQUIRE(B >= 0 && n_cells >= 0, "wk_surrogate_fwd: negative size");
+    if ((long)B * n_cells == 0) return WK_OK;
+    WK_REQUIRE(cells != nullptr || n_cells == mesh->nx,
+               "wk_surrogate_fwd: with cells == NULL, n_cells must be nx");
+    WK_REQUIRE(wV && wT && W && V && K_out, "wk_surrogate_fwd: NULL array");
+    hipStream_t s = as_stream(stream);
+    const int P = mesh->n_m / 2, Pn = (P + 15) / 16 * 16;
+    const long R = (long)B * n_cells;
+    // prep tables live in a scratch area sized like the backward's prep section
+    const size_t prep = surr_ws_bytes(H, P, N, 0, false);
+    int err;
+    void* scratch = fwd_scratch(prep, &err);
+    if (!scratch) return err;
+    SurrWS w = surr_carve(scratch, H, P, N, 0, false);
+    const long np = (long)H * Pn > Pn ? (long)H * Pn : Pn;
+    hipLaunchKernelGGL(surr_prep, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, mesh->n_m, N,
+                       H, Pn, wT, W, w.Bd, w.Bf, w.Pid, w.Pif, w.u);
+    const dim3 grid((unsigned)((R + SU_BM - 1) / SU_BM));
+    if (prec == WK_FP64) {
+        const size_t sh = sizeof(double) * SD_BM * (H + 1);
+        hipLaunchKernelGGL(surr_fwd_f64, dim3((unsigned)((R + SD_BM - 1) / SD_BM)), dim3(SU_THREADS), sh, s, V, mesh->nx, R, n_cells,
+                           cells, P, N, H, Pn, wV, w.Bd, w.Pid, static_cast<double*>(K_out));
+    } else if (prec == WK_BF16) {
+        const int Hk = (H + 31) / 32 * 32;
+        const size_t sh = sizeof(float) * SU_BM * (Hk + 1);
+        hipLaunchKernelGGL(surr_fwd_bf16, grid, dim3(SU_THREADS), sh, s, V, mesh->nx, R, n_cells,
+                           cells, P, N, H, Hk, Pn, wV, w.Bf, w.Pif, static_cast<float*>(K_out));
+    } else {
+        const int Hk = (H + 3) / 4 * 4;
+        const size_t sh = sizeof(float) * SU_BM * (Hk + 1);
+        hipLaunchKernelGGL(surr_fwd_f32, grid, dim3(SU_THREADS), sh, s, V, mesh->nx, R, n_cells,
+                           cells, P, N, H, Hk, Pn, wV, w.Bf, w.Pif, static_cast<float*>(K_out));
+    }
+    return check_launch("wk_surrogate_fwd");
+}
+
+extern "C" size_t wk_surrogate_workspace(const wk_mesh* mesh, int32_t N, int32_t B, int32_t n_cells) {
+    int H;
+    if (surr_check(mesh, N, &H) != WK_OK || B < 0 || n_cells < 0) return 0;
+    return surr_ws_bytes(H, mesh->n_m / 2, N, (long)B * n_cells, true);
+}
+
+extern "C" int wk_surrogate_bwd(const wk_mesh* mesh, int32_t N, const float* wV, const float* wT,
+                                const float* W, const double* V, int32_t B, const int32_t* cells,
+                                int32_t n_cells, const float* E, float* dwV, float* dwT, float* dW,
+                                double* dV, void* ws, size_t ws_bytes, void* stream) {
+    int H;
+    int rc = surr_check(mesh, N, &H);
+    if (rc) return rc;
+    WK_REQUIRE(B >= 0 && n_cells >= 0, "wk_surrogate_bwd: negative size");
+    WK_REQUIRE(dwV && dwT && dW, "wk_surrogate_bwd: NULL gradient array");
+    WK_REQUIRE(cells != nullptr || n_cells == mesh->nx,
+               "wk_surrogate_bwd: with cells == NULL, n_cells must be nx");
+    WK_REQUIRE(dV == nullptr || cells == nullptr, "wk_surrogate_bwd: dV needs the all-cells layout");
+    const int P = mesh->n_m / 2, Pn = (P + 15) / 16 * 16;
+    const long R = (long)B * n_cells;
+    WK_REQUIRE(ws && ws_bytes >= surr_ws_bytes(H, P, N, R, true), "wk_surrogate_bwd: workspace too small");
+    WK_REQUIRE(R == 0 || (wV && wT && W && V && E), "wk_surrogate_bwd: NULL array");
+    hipStream_t s = as_stream(stream);
+    SurrWS w = surr_carve(ws, H, P, N, R, true);
+    const long np = (long)H * Pn;
+    hipLaunchKernelGGL(surr_prep, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, mesh->n_m, N,
+                       H, Pn, wT, W, w.Bd, w.Bf, w.Pid, w.Pif, w.u);
+    const long nblk = surr_nblk(R);
+    if (nblk > 0) {
+        const size_t sh = sizeof(float) * SD_BM * (2 * (H + 1) + (P + 1));
+        hipLaunchKernelGGL(surr_bwd_block, dim3((unsigned)nblk), dim3(SU_THREADS), sh, s, V,
+                           mesh->nx, R, n_cells, cells, P, N, H, Pn, wV, E, w, dV ? 1 : 0);
+        hipLaunchKernelGGL(surr_bwd_reduce_gb, dim3((unsigned)(((long)H * P + 255) / 256)), dim3(256),
+                           0, s, (int)nblk, H, P, w);
+        hipLaunchKernelGGL(surr_bwd_params, dim3(1), dim3(256), 0, s, mesh->n_m, N, H, P, Pn,
+                           (int)nblk, W, w, dwV, dwT, dW);
+    } else {
+        hipLaunchKernelGGL(zero_grads, dim3(1), dim3(256), 0, s, dwV, N, dwT, N, dW, H);
+    }
+    if (dV && R > 0)
+        hipLaunchKernelGGL(surr_bwd_dV, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, B,
+                           mesh->nx, P, N, H, wV, w.GA, dV);
+    return check_launch("wk_surrogate_bwd");
+}
+
+// ----------------------------------------------------------------------------- training ops
+namespace wk {
+__global__ void mse_partial(const float* __restrict__ Kh, const double* __restrict__ K, long n,
+                            double inv_scale, float* __restrict__ E, double* __restrict__ part) {
+    __shared__ double red[4];
+    const double inv_n = 1.0 / (double)n;
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double d = ((double)Kh[i] - K[i]) * inv_scale;
+        acc += d * d;
+        E[i] = (float)(2.0 * d * inv_scale * inv_n);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void mse_final(const double* __restrict__ part, int nb, long n, double* loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += part[k];
+    loss[0] = s / (double)n;
+}
+
+__global__ void sgd_kernel(float* w, const float* g, int n, float lr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w[i] = w[i] - lr * g[i];
+}
+}  // namespace wk
+
+extern "C" int wk_mse_grad(const float* Kh, const double* K, int64_t count, double inv_scale,
+                           float* E, double* loss, void* ws, size_t ws_bytes, void* stream) {
+    WK_REQUIRE(count >= 0, "wk_mse_grad: negative count");
+    WK_REQUIRE(loss && ws && ws_bytes >= 8 * 1024, "wk_mse_grad: NULL loss or small workspace");
+    WK_REQUIRE(count == 0 || (Kh && K && E), "wk_mse_grad: NULL array");
+    hipStream_t s = as_stream(stream);
+    if (count == 0) {
+        hipLaunchKernelGGL(mse_final, dim3(1), dim3(1), 0, s, static_cast<double*>(ws), 0, 1, loss);
+        return check_launch("wk_mse_grad");
+    }
+    const int nb = 1024;
+    hipLaunchKernelGGL(mse_partial, dim3(nb), dim3(256), 0, s, Kh, K, (long)count, inv_scale, E,
+                       static_cast<double*>(ws));
+    hipLaunchKernelGGL(mse_final, dim3(1), dim3(1), 0, s, static_cast<double*>(ws), nb, (long)count, loss);
+    return check_launch("wk_mse_grad");
+}
+
+extern "C" int wk_sgd_update(float* w, const float* grad, int32_t n, float lr, void* stream) {
+    WK_REQUIRE(n >= 0, "wk_sgd_update: negative size");
+    if (n == 0) return WK_OK;
+    WK_REQUIRE(w && grad, "wk_sgd_update: NULL array");
+    hipLaunchKernelGGL(sgd_kernel, dim3((n + 255) / 256), dim3(256), 0, as_stream(stream), w, grad, n, lr);
+    return check_launch("wk_sgd_update");
+}

@@ -1,0 +1,134 @@
+// Internal helpers of libwigner (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/wigner.h"
+
+namespace wk {
+
+// ----------------------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define WK_REQUIRE(cond, msg)                                \
+    do {                                                     \
+        if (!(cond)) return ::wk::fail(WK_EINVAL, (msg));    \
+    } while (0)
+
+#define WK_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::wk::fail(WK_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// Checks the launch that was just enqueued.
+int check_launch(const char* what);
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Device sine table for n_m (built on first use, per device, kept for the process).
+// Layout [Pk][Pn]: S[jj][t] = sin(2 pi (jj+1)(t+1) / n_m) for jj, t < P, zero padding.
+// kind 0: double; 1: bf16 hi; 2: bf16 lo; 3: fp16 hi; 4: fp16 lo (hi/lo of the double).
+const void* sine_table(int n_m, int kind, int Pk, int Pn, hipStream_t stream, int* err);
+
+// ----------------------------------------------------------------------------- device utils
+__device__ __forceinline__ long mod_pos(long a, long n) {
+    long r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// sin(2 pi k / n) after an exact integer reduction to the first quarter period, so that
+// zeros (k = 0, n/2) and oddness are exact.
+__device__ __forceinline__ double sin_2pi_ratio(long k, long n) {
+    long t = mod_pos(k, n);
+    if (t == 0 || 2 * t == n) return 0.0;
+    double sg = 1.0;
+    if (2 * t > n) {
+        t = n - t;
+        sg = -1.0;
+    }
+    if (4 * t > n) return sg * sinpi((double)(n - 2 * t) / (double)n);  // sin(pi - a) = sin a
+    return sg * sinpi(2.0 * (double)t / (double)n);
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, multipliers
+// 0xD2511F53 / 0xCD9E8D57, round keys bumped by 0x9E3779B9 / 0xBB67AE85.
+struct u32x4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ u32x4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint64_t seed) {
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t p0lo = 0xD2511F53u * c0, p0hi = __umulhi(0xD2511F53u, c0);
+        const uint32_t p1lo = 0xCD9E8D57u * c2, p1hi = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = p1hi ^ c1 ^ k0;
+        const uint32_t n2 = p0hi ^ c3 ^ k1;
+        c0 = n0;
+        c1 = p1lo;
+        c2 = n2;
+        c3 = p0lo;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    u32x4 o;
+    o.v[0] = c0;
+    o.v[1] = c1;
+    o.v[2] = c2;
+    o.v[3] = c3;
+    return o;
+}
+
+enum : uint32_t { TAG_CREATE = 1, TAG_ANNIH = 2, TAG_INIT = 3 };
+
+// Fraction bits fb such that cell + k 2^-fb is exact in the position type for any cell
+// index < n_max.
+inline int frac_bits_host(int n_max, int pos_f64) {
+    int k = 0;
+    while ((1L << k) < (long)n_max) ++k;
+    int fb = (pos_f64 ? 53 : 24) - k;
+    return fb > 32 ? 32 : fb;
+}
+
+// Wave-level inclusive scan of an int (64 lanes) through DPP-free shuffles.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide exclusive scan of one int per thread (blockDim.x = 256); returns the
+// exclusive prefix and writes the block total to *total.  Uses 4+1 ints of LDS.
+__device__ __forceinline__ int block_excl_scan_256(int v, int* total, int* lds5) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = wave_incl_scan(v);
+    if (lane == 63) lds5[w] = inc;
+    __syncthreads();
+    int base = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (k < w) base += lds5[k];
+    const int tot = lds5[0] + lds5[1] + lds5[2] + lds5[3];
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+}  // namespace wk

@@ -1,0 +1,215 @@
+"""Differentiation and learned-kernel forms.
+
+* ``WignerKernelFn``: eq.(4) as a torch.autograd.Function whose backward is the hand-written
+  adjoint kernel (wk_kernel_bwd) with respect to the potential samples.
+* ``SurrogateFn``: the trainable network of eq.(5) (Sec. 2.3) with the hand-written
+  backward (wk_surrogate_bwd) with respect to (V, wV, wT, W).
+* ``train_surrogate``: the supervised training of Sec. 3 -- random Gaussian-bell potentials,
+  exact kernels from the quadrature as labels, MSE, stochastic gradient descent -- with
+  every step (labels, forward, loss, backward, update) in the library's kernels.
+
+Weights are FP32 device tensors: wV, wT of length N and W of length n_m / N.  W is trained
+in units of the analytic weight c = -2/(hbar n_m) (the update is scaled by c^2), so all
+three groups are O(1) and one learning rate serves them.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib as L
+from . import ops
+from .inputs import HBAR_EVFS
+
+
+def analytic_weights(n_m: int, N: int, hbar: float = HBAR_EVFS, device="cuda"):
+    """wV = 1, wT = 1/N, W = -2/(hbar n_m): eq.(4) for N = 1, the barycentric form for N = 2."""
+    H = n_m // N
+    return (torch.ones(N, dtype=torch.float32, device=device),
+            torch.full((N,), 1.0 / N, dtype=torch.float32, device=device),
+            torch.full((H,), -2.0 / (hbar * n_m), dtype=torch.float32, device=device))
+
+
+# ----------------------------------------------------------------------------- raw calls
+def surrogate_fwd(V, n_m: int, N: int, wV, wT, W, cells=None, prec: str = "fp32",
+                  hbar: float = HBAR_EVFS, out=None):
+    """Half table [B * n_cells][P] of eq.(5); float32 (fp32, bf16) or float64 (fp64)."""
+    if V.dim() == 1:
+        V = V[None]
+    B, nx = V.shape
+    n_cells = nx if cells is None else int(cells.numel())
+    P = n_m // 2
+    p = {"fp64": L.WK_FP64, "bf16": L.WK_BF16}.get(prec, L.WK_FP16X3 + 1)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    if out is None:
+        out = torch.empty((B * n_cells, P), dtype=dt, device=V.device)
+    m = ops.mesh_struct(1, nx, 1, n_m, hbar)
+    c = None if cells is None else cells.to(torch.int32).contiguous()
+    L.check(L.lib().wk_surrogate_fwd(ctypes.byref(m), N, ops._ptr(wV), ops._ptr(wT), ops._ptr(W),
+                                     ops._ptr(V.contiguous()), B, ops._ptr(c), n_cells, p,
+                                     ops._ptr(out), ops._stream()), "wk_surrogate_fwd")
+    return out
+
+
+def surrogate_bwd(V, n_m: int, N: int, wV, wT, W, E, cells=None, want_dV: bool = False,
+                  hbar: float = HBAR_EVFS, ws=None):
+    if V.dim() == 1:
+        V = V[None]
+    B, nx = V.shape
+    n_cells = nx if cells is None else int(cells.numel())
+    m = ops.mesh_struct(1, nx, 1, n_m, hbar)
+    need = int(L.lib().wk_surrogate_workspace(ctypes.byref(m), N, B, n_cells))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=V.device)
+    dwV = torch.empty(N, dtype=torch.float32, device=V.device)
+    dwT = torch.empty(N, dtype=torch.float32, device=V.device)
+    dW = torch.empty(n_m // N, dtype=torch.float32, device=V.device)
+    dV = torch.zeros((B, nx), dtype=torch.float64, device=V.device) if want_dV else None
+    c = None if cells is None else cells.to(torch.int32).contiguous()
+    L.check(L.lib().wk_surrogate_bwd(ctypes.byref(m), N, ops._ptr(wV), ops._ptr(wT), ops._ptr(W),
+                                     ops._ptr(V.contiguous()), B, ops._ptr(c), n_cells,
+                                     ops._ptr(E.contiguous()), ops._ptr(dwV), ops._ptr(dwT),
+                                     ops._ptr(dW), ops._ptr(dV), ops._ptr(ws), ws.numel(),
+                                     ops._stream()), "wk_surrogate_bwd")
+    return dwV, dwT, dW, dV
+
+
+def mse_grad(Kh, K, inv_scale: float, E=None, loss=None, ws=None):
+    n = Kh.numel()
+    dev = Kh.device
+    if E is None:
+        E = torch.empty_like(Kh, dtype=torch.float32)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = torch.empty(8 * 1024, dtype=torch.uint8, device=dev)
+    L.check(L.lib().wk_mse_grad(ops._ptr(Kh), ops._ptr(K), n, float(inv_scale), ops._ptr(E),
+                                ops._ptr(loss), ops._ptr(ws), ws.numel(), ops._stream()),
+            "wk_mse_grad")
+    return E, loss
+
+
+def sgd_update(w, g, lr: float):
+    L.check(L.lib().wk_sgd_update(ops._ptr(w), ops._ptr(g), w.numel(), float(lr), ops._stream()),
+            "wk_sgd_update")
+
+
+# ----------------------------------------------------------------------------- autograd
+class WignerKernelFn(torch.autograd.Function):
+    """K = eq.(4)(V) on all cells (FP64), with the adjoint kernel as backward."""
+
+    @staticmethod
+    def forward(ctx, V, n_m: int, layout: str = "full", hbar: float = HBAR_EVFS):
+        ctx.shape = tuple(V.shape)
+        ctx.n_m, ctx.layout, ctx.hbar = n_m, layout, hbar
+        return ops.kernel_eval(V.detach(), n_m, layout=layout, hbar=hbar)
+
+    @staticmethod
+    def backward(ctx, G):
+        B, nx = ctx.shape if len(ctx.shape) == 2 else (1, ctx.shape[0])
+        dV = ops.kernel_bwd(G.contiguous().to(torch.float64), nx, ctx.n_m, B, layout=ctx.layout,
+                            hbar=ctx.hbar)
+        return dV.reshape(ctx.shape), None, None, None
+
+
+class SurrogateFn(torch.autograd.Function):
+    """Kh = eq.(5)(V; wV, wT, W) on all cells (FP32), with the hand-written backward."""
+
+    @staticmethod
+    def forward(ctx, V, wV, wT, W, n_m: int, N: int, hbar: float = HBAR_EVFS):
+        ctx.save_for_backward(V, wV, wT, W)
+        ctx.n_m, ctx.N, ctx.hbar = n_m, N, hbar
+        return surrogate_fwd(V.detach(), n_m, N, wV.detach(), wT.detach(), W.detach(),
+                             prec="fp32", hbar=hbar)
+
+    @staticmethod
+    def backward(ctx, E):
+        V, wV, wT, W = ctx.saved_tensors
+        dwV, dwT, dW, dV = surrogate_bwd(V, ctx.n_m, ctx.N, wV, wT, W,
+                                         E.contiguous().to(torch.float32),
+                                         want_dV=ctx.needs_input_grad[0], hbar=ctx.hbar)
+        if dV is not None:
+            dV = dV.reshape(V.shape).to(V.dtype)
+        return dV, dwV, dwT, dW, None, None, None
+
+
+# ----------------------------------------------------------------------------- training
+@dataclass
+class TrainResult:
+    wV: torch.Tensor
+    wT: torch.Tensor
+    W: torch.Tensor
+    losses: list = field(default_factory=list)     # mean batch loss per epoch
+    steps: int = 0
+    seconds: float = 0.0
+
+
+def train_surrogate(V_train: torch.Tensor, n_m: int, N: int, epochs: int, batch: int,
+                    lr: float, hbar: float = HBAR_EVFS, init=None, labels=None,
+                    seed: int = 0, log=None) -> TrainResult:
+    """SGD on the MSE between eq.(5) and the exact eq.(4) half tables (Sec. 3).
+
+    V_train: [n_pot][nx] float64 device tensor.  labels: optional precomputed exact half
+    tables [n_pot][nx][P] (float64); otherwise each batch's labels are computed on the fly
+    with the FP64 kernel contraction.  Batches are drawn by a seeded permutation per epoch.
+    """
+    dev = V_train.device
+    n_pot, nx = V_train.shape
+    c = -2.0 / (hbar * n_m)
+    inv_scale = 1.0 / abs(c)
+    wV, wT, W = [t.clone() for t in (init or analytic_weights(n_m, N, hbar, dev))]
+    P = n_m // 2
+    Kh = torch.empty((batch * nx, P), dtype=torch.float32, device=dev)
+    Klab = torch.empty((batch * nx, P), dtype=torch.float64, device=dev)
+    E = torch.empty_like(Kh)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    mse_ws = torch.empty(8 * 1024, dtype=torch.uint8, device=dev)
+    m = ops.mesh_struct(1, nx, 1, n_m, hbar)
+    ws = torch.empty(int(L.lib().wk_surrogate_workspace(ctypes.byref(m), N, batch, nx)),
+                     dtype=torch.uint8, device=dev)
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(seed)
+    res = TrainResult(wV, wT, W)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for ep in range(epochs):
+        perm = torch.randperm(n_pot, generator=gen)
+        ep_loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        nb = 0
+        for k in range(0, n_pot - batch + 1, batch):
+            idx = perm[k:k + batch].to(dev)
+            Vb = V_train.index_select(0, idx)
+            if labels is None:
+                ops.kernel_eval(Vb, n_m, layout="half", hbar=hbar, out=Klab)
+                lab = Klab
+            else:
+                lab = labels.index_select(0, idx).reshape(batch * nx, P)
+            surrogate_fwd(Vb, n_m, N, wV, wT, W, prec="fp32", hbar=hbar, out=Kh)
+            mse_grad(Kh, lab, inv_scale, E=E, loss=loss, ws=mse_ws)
+            dwV, dwT, dW, _ = surrogate_bwd(Vb, n_m, N, wV, wT, W, E, hbar=hbar, ws=ws)
+            sgd_update(wV, dwV, lr)
+            sgd_update(wT, dwT, lr)
+            sgd_update(W, dW, lr * c * c)
+            ep_loss += loss
+            nb += 1
+            res.steps += 1
+        res.losses.append(float((ep_loss / max(nb, 1)).item()))
+        if log:
+            log(f"epoch {ep}: loss {res.losses[-1]:.6e}")
+    ev1.record()
+    torch.cuda.synchronize()
+    res.seconds = ev0.elapsed_time(ev1) / 1e3
+    return res
+
+
+def surrogate_error(V: torch.Tensor, n_m: int, N: int, wV, wT, W, hbar: float = HBAR_EVFS,
+                    prec: str = "fp32") -> float:
+    """Normwise error max|Kh - K| / max|K| per potential (max over the batch), exact K in FP64."""
+    B, nx = V.shape
+    K = ops.kernel_eval(V, n_m, layout="half", hbar=hbar).reshape(B, -1)
+    Kh = surrogate_fwd(V, n_m, N, wV, wT, W, prec=prec, hbar=hbar).reshape(B, -1).to(torch.float64)
+    err = (Kh - K).abs().amax(dim=1) / K.abs().amax(dim=1).clamp_min(1e-300)
+    return float(err.max().item())

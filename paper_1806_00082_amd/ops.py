@@ -1,0 +1,198 @@
+"""Torch-facing wrappers of the C ABI: argument marshalling only.
+
+Torch provides device memory and the current stream; every computation happens in the
+HIP kernels of libwigner.so.  Tensors must already live on the HIP device.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+from .inputs import HBAR_EVFS
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise L.WignerError("libwigner works on device tensors only")
+
+
+def mesh_struct(dim: int, nx: int, ny: int, n_m: int, hbar: float = HBAR_EVFS) -> L.WkMesh:
+    return L.WkMesh(dim, nx, ny, n_m, hbar)
+
+
+# ----------------------------------------------------------------------------- kernel
+def kernel_eval(V: torch.Tensor, n_m: int, cells: torch.Tensor | None = None, prec: str = "fp64",
+                layout: str = "full", hbar: float = HBAR_EVFS, out: torch.Tensor | None = None):
+    """eq.(4) on the requested cells.  V: [B][nx] (1-D) or [B][ny][nx] (2-D) float64."""
+    _need_cuda(V, cells)
+    if V.dim() == 1:
+        V = V[None]
+    dim = 1 if V.dim() == 2 else 2
+    B = V.shape[0]
+    nx = V.shape[-1]
+    ny = 1 if dim == 1 else V.shape[-2]
+    V = V.contiguous()
+    assert V.dtype == torch.float64
+    n_cells = nx * ny if cells is None else int(cells.numel())
+    if cells is not None:
+        cells = cells.to(torch.int32).contiguous()
+    P = n_m // 2
+    lay = L.WK_HALF if layout == "half" else L.WK_FULL
+    p = L.PREC[prec]
+    dt = torch.float64 if p == L.WK_FP64 else torch.float32
+    if dim == 1:
+        shape = (B * n_cells, P if lay == L.WK_HALF else n_m)
+    else:
+        shape = (B * n_cells, n_m, n_m)
+    if out is None:
+        out = torch.empty(shape, dtype=dt, device=V.device)
+    m = mesh_struct(dim, nx, ny, n_m, hbar)
+    L.check(L.lib().wk_kernel_eval(ctypes.byref(m), _ptr(V), B, _ptr(cells), n_cells, p, lay,
+                                   _ptr(out), _stream()), "wk_kernel_eval")
+    return out
+
+
+def kernel_bwd(G: torch.Tensor, nx: int, n_m: int, B: int, layout: str = "full",
+               hbar: float = HBAR_EVFS, dV: torch.Tensor | None = None):
+    _need_cuda(G)
+    m = mesh_struct(1, nx, 1, n_m, hbar)
+    if dV is None:
+        dV = torch.zeros((B, nx), dtype=torch.float64, device=G.device)
+    wsz = L.lib().wk_kernel_bwd_workspace(ctypes.byref(m), B)
+    ws = torch.empty(max(int(wsz), 8), dtype=torch.uint8, device=G.device)
+    lay = L.WK_HALF if layout == "half" else L.WK_FULL
+    L.check(L.lib().wk_kernel_bwd(ctypes.byref(m), _ptr(G.contiguous()), B, lay, _ptr(dV),
+                                  _ptr(ws), int(wsz), _stream()), "wk_kernel_bwd")
+    return dV
+
+
+def gamma_tables(K: torch.Tensor, n_m: int, dt: float, dim: int = 1, layout: str = "full",
+                 hbar: float = HBAR_EVFS):
+    """Returns (gamma f64, n0 u32-as-int32, thr u32-as-int32, cdf u64-as-int64)."""
+    _need_cuda(K)
+    K = K.contiguous()
+    width = n_m if dim == 1 else n_m * n_m
+    lay = L.WK_HALF if layout == "half" else L.WK_FULL
+    row_len = n_m // 2 if lay == L.WK_HALF else width
+    n_rows = K.numel() // row_len
+    dev = K.device
+    g = torch.empty(n_rows, dtype=torch.float64, device=dev)
+    n0 = torch.empty(n_rows, dtype=torch.int32, device=dev)
+    thr = torch.empty(n_rows, dtype=torch.int32, device=dev)
+    cdf = torch.empty((n_rows, width), dtype=torch.int64, device=dev)
+    m = mesh_struct(dim, 1, 1, n_m, hbar)
+    L.check(L.lib().wk_gamma_tables(ctypes.byref(m), _ptr(K), int(K.dtype == torch.float64), lay,
+                                    n_rows, dt, _ptr(g), _ptr(n0), _ptr(thr), _ptr(cdf), _stream()),
+            "wk_gamma_tables")
+    return g, n0, thr, cdf
+
+
+# ----------------------------------------------------------------------------- particles
+def geom_struct(mesh: dict, seed: int) -> L.SpGeom:
+    return L.SpGeom(mesh["dim"], mesh["nx"], mesh.get("ny", 1), mesh["n_m"], mesh["n_k"],
+                    mesh["M_min"], int(mesh["pos_f64"]), 0, float(mesh["vdt"]), seed)
+
+
+class DeviceParticles:
+    """Struct-of-arrays particle buffer in HBM (positions in cell units)."""
+
+    def __init__(self, dim: int, capacity: int, pos_f64: bool, device="cuda"):
+        ft = torch.float64 if pos_f64 else torch.float32
+        mt = torch.int32 if dim == 1 else torch.int16
+        self.dim, self.pos_f64, self.capacity = dim, pos_f64, int(capacity)
+        self.x = torch.zeros(capacity, dtype=ft, device=device)
+        self.y = torch.zeros(capacity, dtype=ft, device=device) if dim == 2 else None
+        self.M = torch.zeros(capacity, dtype=mt, device=device)
+        self.My = torch.zeros(capacity, dtype=mt, device=device) if dim == 2 else None
+        self.s = torch.zeros(capacity, dtype=torch.int8, device=device)
+        self.d_n = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def struct(self) -> L.SpParticles:
+        return L.SpParticles(self.x.data_ptr(), self.y.data_ptr() if self.y is not None else None,
+                             self.M.data_ptr(), self.My.data_ptr() if self.My is not None else None,
+                             self.s.data_ptr(), self.capacity, self.d_n.data_ptr())
+
+    def count(self) -> int:
+        return int(self.d_n.item())
+
+    def load(self, n: int, x, M, s, y=None, My=None):
+        """Copy host arrays in (test helper for given particle states)."""
+        dev = self.x.device
+        self.x[:n] = torch.as_tensor(x, device=dev).to(self.x.dtype)
+        self.M[:n] = torch.as_tensor(M, device=dev).to(self.M.dtype)
+        self.s[:n] = torch.as_tensor(s, device=dev).to(torch.int8)
+        if self.dim == 2:
+            self.y[:n] = torch.as_tensor(y, device=dev).to(self.y.dtype)
+            self.My[:n] = torch.as_tensor(My, device=dev).to(self.My.dtype)
+        self.d_n.fill_(n)
+
+    def view(self) -> dict:
+        n = self.count()
+        d = {"x": self.x[:n].cpu().numpy(), "M": self.M[:n].cpu().numpy(), "s": self.s[:n].cpu().numpy()}
+        if self.dim == 2:
+            d["y"] = self.y[:n].cpu().numpy()
+            d["My"] = self.My[:n].cpu().numpy()
+        return d
+
+
+def sp_workspace(mesh: dict, seed: int = 0, device="cuda") -> torch.Tensor:
+    g = geom_struct(mesh, seed)
+    n = int(L.lib().sp_workspace_size(ctypes.byref(g)))
+    if n == 0:
+        L.check(L.WK_EINVAL, "sp_workspace_size")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def new_stats(device="cuda") -> torch.Tensor:
+    return torch.zeros(L.ST_COUNT, dtype=torch.int64, device=device)
+
+
+def sp_init(mesh: dict, seed: int, bin_counts: torch.Tensor, out: DeviceParticles,
+            stats: torch.Tensor, ws: torch.Tensor):
+    g = geom_struct(mesh, seed)
+    ps = out.struct()
+    L.check(L.lib().sp_init(ctypes.byref(g), _ptr(bin_counts.to(torch.int32).contiguous()),
+                            ctypes.byref(ps), _ptr(stats), _ptr(ws), ws.numel(), _stream()),
+            "sp_init")
+
+
+def sp_step(mesh: dict, seed: int, cell_slot, n0, thr, cdf, p: DeviceParticles, step: int,
+            stats: torch.Tensor, ws: torch.Tensor):
+    g = geom_struct(mesh, seed)
+    ps = p.struct()
+    L.check(L.lib().sp_step(ctypes.byref(g), _ptr(cell_slot), _ptr(n0), _ptr(thr), _ptr(cdf),
+                            ctypes.byref(ps), step, _ptr(stats), _ptr(ws), ws.numel(), _stream()),
+            "sp_step")
+
+
+def sp_annihilate(mesh: dict, seed: int, pin: DeviceParticles, pout: DeviceParticles,
+                  hist: torch.Tensor, step: int, stats: torch.Tensor, ws: torch.Tensor):
+    g = geom_struct(mesh, seed)
+    a, b = pin.struct(), pout.struct()
+    L.check(L.lib().sp_annihilate(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _ptr(hist),
+                                  step, _ptr(stats), _ptr(ws), ws.numel(), _stream()),
+            "sp_annihilate")
+
+
+def sp_density(mesh: dict, hist: torch.Tensor, N0: float, rho: torch.Tensor | None = None):
+    g = geom_struct(mesh, 0)
+    if rho is None:
+        rho = torch.empty(mesh["nx"] * mesh.get("ny", 1), dtype=torch.float64, device=hist.device)
+    L.check(L.lib().sp_density(ctypes.byref(g), _ptr(hist), float(N0), _ptr(rho), _stream()),
+            "sp_density")
+    return rho
+
+
+def n_bins(mesh: dict) -> int:
+    return mesh["nx"] * mesh.get("ny", 1) * mesh["n_k"] ** mesh["dim"]

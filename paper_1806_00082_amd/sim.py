@@ -1,0 +1,139 @@
+"""Time loop of the signed-particle method (Sec. 2.1, Sec. 3): host-side orchestration of the
+library's kernels, no computation in Python.
+
+Per step: (every `refresh_every` steps) kernel rows for newly occupied cells -> creation
+tables; sp_step (creation at rate gamma, drift, absorbing boundaries); sp_annihilate (rule 2,
+and the signed histogram of rule 1).  The particle count stays in device memory; the host
+synchronises only to size the occasional kernel-row refresh and to read statistics.
+
+Kernel sources (the paper's two steps, Sec. 4): "exact" = eq.(4) on MFMA in FP64 or a reduced
+precision; "surrogate" = the trained network of eq.(5).  Rows are evaluated only for cells
+within a margin of the occupied ones ("occupied", the paper's memory/speed point) or for
+every cell at start ("all"); both give the same trajectory bit for bit when the margin
+covers the drift between refreshes.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from . import _lib as L
+from . import learn, ops
+
+
+class Simulator:
+    def __init__(self, cfg, kernel: str = "exact", prec: str = "fp64", mode: str = "occupied",
+                 refresh_every: int = 8, cap_factor: float = 3.0, weights=None, N: int = 2,
+                 device="cuda"):
+        self.cfg = cfg
+        self.md = cfg.mesh.as_dict(cfg.dt)
+        md = self.md
+        self.dim = md["dim"]
+        self.kernel, self.prec, self.mode = kernel, prec, mode
+        self.refresh_every = max(1, int(refresh_every))
+        self.N, self.weights = N, weights
+        self.seed = cfg.seed
+        self.dev = torch.device(device)
+        self.n_m = md["n_m"]
+        self.n_cells = md["nx"] * md.get("ny", 1)
+        self.width = self.n_m if self.dim == 1 else self.n_m * self.n_m
+        self.half = self.dim == 1                       # 1-D rows are kept as half tables
+        self.row_len = self.n_m // 2 if self.half else self.width
+        V = torch.as_tensor(cfg.V, dtype=torch.float64)
+        self.V = (V[None] if V.dim() == self.dim else V).contiguous().to(self.dev)
+        # per-cell creation tables (rows handed out as cells become occupied)
+        self.cell_slot = torch.full((self.n_cells,), -1, dtype=torch.int32, device=self.dev)
+        self.gamma = torch.zeros(self.n_cells, dtype=torch.float64, device=self.dev)
+        self.n0 = torch.zeros(self.n_cells, dtype=torch.int32, device=self.dev)
+        self.thr = torch.zeros(self.n_cells, dtype=torch.int32, device=self.dev)
+        self.cdf = torch.zeros((self.n_cells, self.width), dtype=torch.int64, device=self.dev)
+        kdt = torch.float64 if (kernel == "exact" and prec == "fp64") else torch.float32
+        self.Kbuf = torch.empty((self.n_cells, self.row_len), dtype=kdt, device=self.dev)
+        self.new_cells = torch.empty(self.n_cells, dtype=torch.int32, device=self.dev)
+        self.d_count = torch.zeros(1, dtype=torch.int64, device=self.dev)
+        self.n_rows = 0
+        # particles
+        bc = torch.as_tensor(cfg.bin_counts, dtype=torch.int32)
+        n0 = int(bc.sum())
+        self.capacity = int(cap_factor * n0) + 1024
+        self.a = ops.DeviceParticles(self.dim, self.capacity, md["pos_f64"], self.dev)
+        self.b = ops.DeviceParticles(self.dim, self.capacity, md["pos_f64"], self.dev)
+        self.stats = ops.new_stats(self.dev)
+        self.ws = ops.sp_workspace(md, self.seed, self.dev)
+        self.hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=self.dev)
+        ops.sp_init(md, self.seed, bc.to(self.dev), self.a, self.stats, self.ws)
+        self.step_index = 0
+        # the initial ensemble is single-signed: this pass only builds the histogram
+        ops.sp_annihilate(md, self.seed, self.a, self.b, self.hist, 0xFFFFFFFF, self.stats, self.ws)
+        self.a, self.b = self.b, self.a
+        vmax = max(abs(md["M_min"]), abs(md["M_min"] + md["n_k"] - 1)) * abs(md["vdt"])
+        self.margin = int(math.ceil(self.refresh_every * vmax)) + 1
+        if mode == "all":
+            self._rows_for(torch.arange(self.n_cells, dtype=torch.int32, device=self.dev), self.n_cells)
+            self.cell_slot.copy_(torch.arange(self.n_cells, dtype=torch.int32, device=self.dev))
+        else:
+            self.refresh()
+
+    # ------------------------------------------------------------------ kernel rows
+    def _rows_for(self, cells: torch.Tensor, count: int):
+        """Kernel rows + creation tables for `count` cells, appended at row self.n_rows."""
+        if count == 0:
+            return
+        K = self.Kbuf[:count]
+        if self.kernel == "exact":
+            ops.kernel_eval(self.V, self.n_m, cells=cells[:count], prec=self.prec,
+                            layout="half" if self.half else "full", out=K)
+        else:
+            wV, wT, W = self.weights
+            learn.surrogate_fwd(self.V, self.n_m, self.N, wV, wT, W, cells=cells[:count],
+                                prec=self.prec if self.prec in ("fp64", "bf16") else "fp32", out=K)
+        r0 = self.n_rows
+        m = ops.mesh_struct(self.dim, 1, 1, self.n_m)
+        L.check(L.lib().wk_gamma_tables(
+            ctypes.byref(m), ops._ptr(K), int(K.dtype == torch.float64),
+            L.WK_HALF if self.half else L.WK_FULL, count, float(self.cfg.dt),
+            ctypes.c_void_p(self.gamma.data_ptr() + 8 * r0), ctypes.c_void_p(self.n0.data_ptr() + 4 * r0),
+            ctypes.c_void_p(self.thr.data_ptr() + 4 * r0),
+            ctypes.c_void_p(self.cdf.data_ptr() + 8 * self.width * r0), ops._stream()), "wk_gamma_tables")
+        self.n_rows += count
+
+    def refresh(self) -> int:
+        """Rows for the cells near occupied ones that have none yet (one host sync)."""
+        g = ops.geom_struct(self.md, self.seed)
+        L.check(L.lib().sp_cells_to_evaluate(ctypes.byref(g), ops._ptr(self.hist), self.margin,
+                                             ops._ptr(self.cell_slot), ops._ptr(self.new_cells),
+                                             ops._ptr(self.d_count), ops._ptr(self.ws),
+                                             self.ws.numel(), ops._stream()), "sp_cells_to_evaluate")
+        count = int(self.d_count.item())
+        if count:
+            self._rows_for(self.new_cells, count)
+            L.check(L.lib().sp_assign_slots(ops._ptr(self.new_cells), ops._ptr(self.d_count), count,
+                                            self.n_rows - count, ops._ptr(self.cell_slot),
+                                            ops._stream()), "sp_assign_slots")
+        return count
+
+    # ------------------------------------------------------------------ time loop
+    def step(self):
+        s = self.step_index
+        if self.mode == "occupied" and s > 0 and s % self.refresh_every == 0:
+            self.refresh()
+        ops.sp_step(self.md, self.seed, self.cell_slot, self.n0, self.thr, self.cdf, self.a, s,
+                    self.stats, self.ws)
+        ops.sp_annihilate(self.md, self.seed, self.a, self.b, self.hist, s, self.stats, self.ws)
+        self.a, self.b = self.b, self.a
+        self.step_index += 1
+
+    def run(self, steps: int):
+        for _ in range(steps):
+            self.step()
+
+    def count(self) -> int:
+        return self.a.count()
+
+    def overflowed(self) -> bool:
+        return bool(self.stats[L.ST_OVERFLOW].item())
+
+    def density(self):
+        return ops.sp_density(self.md, self.hist, float(self.cfg.N0))

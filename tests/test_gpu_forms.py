@@ -1,0 +1,220 @@
+"""GPU parity of the three added forms against the FP64 oracle:
+(1) precision: BF16/FP16 MFMA contraction with FP32 accumulation and hi/lo split correction;
+(3) differentiation: the hand-written adjoint of eq.(4) and of eq.(5);
+(4) learned: the eq.(5) network forward, backward, loss, update and training."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import HB, dev, normwise, to_np
+from paper_1806_00082_amd import inputs, learn, ops
+
+pytestmark = pytest.mark.gpu
+
+# Normwise bounds (max |err| / max |K| per potential).  Single-pass forms: one rounding of
+# each operand (u_bf16 = 2^-8, u_fp16 = 2^-11) plus FP32 sums; split forms: the operands
+# carry 16 (bf16) or 22 (fp16) bits and the dropped lo*lo term is ~u^2.
+LOWP_TOL = {"bf16": 1e-2, "fp16": 2e-3, "bf16x3": 5e-5, "fp16x3": 1e-5}
+U_IN = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11}
+# Underflow: a rounded operand is d (1 + delta) + eta with |eta| below the smallest normal
+# of the format (the matrix cores may flush subnormals): 2^-126 for bf16, 2^-14 for fp16.
+ETA_IN = {"bf16": 2.0 ** -126, "fp16": 2.0 ** -14}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("nx,n_m,B", [(300, 64, 3), (2048, 512, 2), (100, 30, 2)])
+def test_lowp_kernel_error_bounds(orc, prec, nx, n_m, B):
+    print(f"lowp {prec} nx={nx} n_m={n_m}", flush=True)
+    V = inputs.random_potentials(B, nx, 0.5, seed=nx + 7)
+    ref = orc.kernel_1d(V, n_m, HB)
+    Vd = torch.from_numpy(V).to(dev())
+    full = to_np(ops.kernel_eval(Vd, n_m, prec=prec, layout="full")).astype(np.float64)
+    half = to_np(ops.kernel_eval(Vd, n_m, prec=prec, layout="half")).astype(np.float64)
+    assert normwise(full.reshape(B, -1), ref.reshape(B, -1)) <= LOWP_TOL[prec]
+    assert normwise(half.reshape(B, -1), orc.full_to_half(ref).reshape(B, -1)) <= LOWP_TOL[prec]
+    if prec in U_IN:
+        # per-entry bound: |dK| <= (2u + u^2 + (P-1) u32) |c| sum_j |S D| (+ output rounding)
+        P = n_m // 2
+        u, u32 = U_IN[prec], 2.0 ** -24
+        c = 2.0 / (HB * n_m)
+        j = np.arange(1, P + 1)
+        m = np.arange(1, P + 1)
+        S = np.abs(np.sin(2 * np.pi * np.outer(j, m) / n_m))
+        for b in range(B):
+            Vb = V[b]
+            idx = np.arange(nx)
+            D = np.abs(Vb[np.clip(idx[:, None] + j[None, :], 0, nx - 1)] -
+                       Vb[np.clip(idx[:, None] - j[None, :], 0, nx - 1)])
+            eta = ETA_IN[prec]
+            bound = (2 * u + u * u + (P - 1) * u32) * c * (D @ S) + u32 * np.abs(orc.full_to_half(ref[b])) \
+                + 2 * c * eta * S.sum(axis=0)[None, :]
+            err = np.abs(half.reshape(B, nx, P)[b] - orc.full_to_half(ref[b]))
+            assert np.all(err <= bound * 1.0001 + 1e-300)
+
+
+def test_lowp_cell_list_and_constant(orc):
+    nx, n_m = 200, 64
+    V = inputs.random_potentials(2, nx, 0.5, seed=3)
+    cells = np.array([0, 199, 50, 50, 7], np.int32)
+    ref = orc.kernel_1d(V, n_m, HB, cells=cells)
+    got = to_np(ops.kernel_eval(torch.from_numpy(V).to(dev()), n_m, cells=torch.from_numpy(cells).to(dev()),
+                                prec="bf16x3")).astype(np.float64)
+    assert normwise(got.reshape(2, -1), ref.reshape(2, -1)) <= LOWP_TOL["bf16x3"]
+    Z = torch.full((1, 100), 0.2, dtype=torch.float64, device=dev())
+    for prec in LOWP_TOL:
+        assert torch.count_nonzero(ops.kernel_eval(Z, 32, prec=prec)).item() == 0
+
+
+def test_lowp_full_size_sampled(orc):
+    """Precision batch at full size (4096 x 2048 x 512), BF16 and BF16x3, sampled rows."""
+    c3 = inputs.C3
+    B, nx, n_m = c3["B"], c3["nx"], c3["n_m"]
+    V = inputs.random_potentials(B, nx, c3["dx"], seed=c3["seed"])
+    Vd = torch.from_numpy(V).to(dev())
+    rows = np.array([0, 1, nx - 1, 5 * nx + 17, B * nx - 1, 1234567, 7654321])
+    for prec in ("bf16", "bf16x3"):
+        K = ops.kernel_eval(Vd, n_m, prec=prec, layout="half")
+        got = to_np(K[torch.from_numpy(rows).to(dev())]).astype(np.float64)
+        del K
+        for k, r in enumerate(rows):
+            b, i = divmod(int(r), nx)
+            ref = orc.full_to_half(orc.kernel_1d(V[b], n_m, HB))[0]
+            scale = np.abs(ref).max()
+            assert np.abs(got[k] - ref[i]).max() <= LOWP_TOL[prec] * scale, (prec, b, i)
+
+
+# ----------------------------------------------------------------------------- adjoint
+@pytest.mark.parametrize("nx,n_m,B", [(90, 30, 2), (257, 64, 3), (40, 80, 1)])
+def test_kernel_adjoint_matches_oracle(orc, nx, n_m, B):
+    P = n_m // 2
+    rng = np.random.default_rng(nx)
+    G = rng.normal(size=(B, nx, P))
+    ref = orc.kernel_bwd_1d(G, n_m, HB)
+    got = to_np(ops.kernel_bwd(torch.from_numpy(G).to(dev()), nx, n_m, B, layout="half"))
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_kernel_adjoint_full_layout_dot_product():
+    """<G, K(dV)> = <K^T G, dV> with the GPU forward and backward, full table layout."""
+    nx, n_m, B = 150, 40, 2
+    g = torch.Generator(device="cpu").manual_seed(0)
+    G = torch.randn((B * nx, n_m), generator=g, dtype=torch.float64).to(dev())
+    dV = torch.randn((B, nx), generator=g, dtype=torch.float64).to(dev())
+    K = ops.kernel_eval(dV, n_m, layout="full")
+    lhs = float((G * K).sum())
+    rhs = float((ops.kernel_bwd(G, nx, n_m, B, layout="full") * dV).sum())
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_wigner_kernel_gradcheck():
+    V = torch.randn((2, 24), dtype=torch.float64, device=dev(), requires_grad=True)
+    fn = lambda v: learn.WignerKernelFn.apply(v, 8, "full")
+    assert torch.autograd.gradcheck(fn, (V,), eps=1e-6, atol=1e-8, rtol=1e-6)
+    fn = lambda v: learn.WignerKernelFn.apply(v, 12, "half")
+    assert torch.autograd.gradcheck(fn, (V,), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+# ----------------------------------------------------------------------------- surrogate
+def _weights(n_m, N, seed, analytic=False):
+    if analytic:
+        return [np.asarray(w) for w in ( np.ones(N), np.full(N, 1.0 / N), np.full(n_m // N, -2.0 / (HB * n_m)))]
+    rng = np.random.default_rng(seed)
+    return [rng.normal(1.0, 0.1, N), rng.normal(1.0 / N, 0.05, N), rng.normal(-2.0 / (HB * n_m), 0.01, n_m // N)]
+
+
+def _f32(ws):
+    return [torch.from_numpy(np.asarray(w, np.float32)).to(dev()) for w in ws]
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 8])
+@pytest.mark.parametrize("analytic", [True, False])
+def test_surrogate_fwd(orc, N, analytic):
+    nx, n_m, B = 150, 64, 2
+    V = inputs.random_potentials(B, nx, 0.5, seed=N)
+    w = _weights(n_m, N, N, analytic)
+    w32 = [np.asarray(x, np.float32).astype(np.float64) for x in w]   # the device holds floats
+    ref = orc.surrogate_fwd(V, n_m, N, *w32)
+    Vd = torch.from_numpy(V).to(dev())
+    wd = _f32(w)
+    got64 = to_np(learn.surrogate_fwd(Vd, n_m, N, *wd, prec="fp64"))
+    assert normwise(got64.reshape(B, -1), ref.reshape(B, -1)) <= 1e-12
+    got32 = to_np(learn.surrogate_fwd(Vd, n_m, N, *wd, prec="fp32")).astype(np.float64)
+    assert normwise(got32.reshape(B, -1), ref.reshape(B, -1)) <= 2e-5
+    gotbf = to_np(learn.surrogate_fwd(Vd, n_m, N, *wd, prec="bf16")).astype(np.float64)
+    assert normwise(gotbf.reshape(B, -1), ref.reshape(B, -1)) <= 3e-2
+    if analytic and N == 1:
+        exact = orc.full_to_half(orc.kernel_1d(V, n_m, HB))
+        assert normwise(got64.reshape(B, -1), exact.reshape(B, -1)) <= 1e-6   # float weights
+
+
+def test_surrogate_fwd_cells(orc):
+    nx, n_m, N = 120, 32, 2
+    V = inputs.random_potentials(3, nx, 0.5, seed=5)
+    w = _weights(n_m, N, 1)
+    w32 = [np.asarray(x, np.float32).astype(np.float64) for x in w]
+    cells = np.array([0, 119, 60, 3, 3], np.int32)
+    ref = orc.surrogate_fwd(V, n_m, N, *w32, cells=cells)
+    got = to_np(learn.surrogate_fwd(torch.from_numpy(V).to(dev()), n_m, N, *_f32(w),
+                                    cells=torch.from_numpy(cells).to(dev()), prec="fp64"))
+    assert normwise(got.reshape(3, -1), ref.reshape(3, -1)) <= 1e-12
+
+
+@pytest.mark.parametrize("N", [1, 2, 4])
+def test_surrogate_bwd_vs_oracle(orc, N):
+    """FP32 hand-written gradients against the FP64 oracle gradients."""
+    nx, n_m, B = 130, 32, 3
+    rng = np.random.default_rng(40 + N)
+    V = inputs.random_potentials(B, nx, 0.5, seed=N + 30)
+    w = _weights(n_m, N, N)
+    w32 = [np.asarray(x, np.float32).astype(np.float64) for x in w]
+    E = rng.normal(size=(B, nx, n_m // 2)).astype(np.float32)
+    dwV, dwT, dW, dV = orc.surrogate_bwd(V, n_m, N, *w32, E.astype(np.float64))
+    g = learn.surrogate_bwd(torch.from_numpy(V).to(dev()), n_m, N, *_f32(w),
+                            torch.from_numpy(E.reshape(B * nx, -1)).to(dev()), want_dV=True)
+    for got, ref in zip(g, (dwV, dwT, dW, dV)):
+        got = to_np(got).astype(np.float64).reshape(ref.shape)
+        assert np.abs(got - ref).max() <= 1e-4 * np.abs(ref).max(), (got, ref)
+
+
+def test_surrogate_autograd_matches_bwd(orc):
+    nx, n_m, N = 64, 16, 2
+    V = torch.from_numpy(inputs.random_potentials(2, nx, 0.5, seed=2)).to(dev()).requires_grad_(True)
+    wV, wT, W = [t.requires_grad_(True) for t in _f32(_weights(n_m, N, 3))]
+    Kh = learn.SurrogateFn.apply(V, wV, wT, W, n_m, N)
+    E = torch.randn_like(Kh)
+    (Kh * E).sum().backward()
+    ref = orc.surrogate_bwd(to_np(V.detach()), n_m, N, *[to_np(t.detach()).astype(np.float64) for t in (wV, wT, W)],
+                            to_np(E).astype(np.float64).reshape(2, nx, -1))
+    for got, r in zip((wV.grad, wT.grad, W.grad, V.grad), ref):
+        got = to_np(got).astype(np.float64).reshape(r.shape)
+        assert np.abs(got - r).max() <= 1e-4 * np.abs(r).max()
+
+
+def test_mse_grad_and_sgd():
+    g = torch.Generator(device="cpu").manual_seed(1)
+    Kh = torch.randn(1000, generator=g).to(torch.float32).to(dev())
+    K = torch.randn(1000, generator=g, dtype=torch.float64).to(dev())
+    E, loss = learn.mse_grad(Kh, K, 3.0)
+    d = (Kh.double() - K) * 3.0
+    assert abs(float(loss) - float((d * d).mean())) <= 1e-12 * float((d * d).mean())
+    assert torch.allclose(E.double(), 2 * d * 3.0 / 1000, rtol=1e-6, atol=0)
+    w = torch.ones(10, device=dev())
+    learn.sgd_update(w, torch.arange(10, dtype=torch.float32, device=dev()), 0.5)
+    assert torch.equal(w.cpu(), 1 - 0.5 * torch.arange(10, dtype=torch.float32))
+
+
+def test_training_beats_barycentric():
+    """Learned form: SGD from the barycentric N = 2 weights reduces the held-out kernel error
+    (the gain of the trained network over the method without training)."""
+    nx, n_m, N = 256, 64, 2
+    Vtr = torch.from_numpy(inputs.random_potentials(96, nx, 0.5, seed=0)).to(dev())
+    Vte = torch.from_numpy(inputs.random_potentials(32, nx, 0.5, seed=1)).to(dev())
+    init = learn.analytic_weights(n_m, N)
+    e0 = learn.surrogate_error(Vte, n_m, N, *init)
+    res = learn.train_surrogate(Vtr, n_m, N, epochs=40, batch=16, lr=1e-2)
+    e1 = learn.surrogate_error(Vte, n_m, N, res.wV, res.wT, res.W)
+    print(f"held-out normwise error: barycentric {e0:.4f} -> trained {e1:.4f}; losses {res.losses[0]:.3e} -> {res.losses[-1]:.3e}")
+    assert res.losses[-1] < res.losses[0]
+    assert e1 < e0

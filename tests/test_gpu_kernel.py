@@ -1,0 +1,120 @@
+"""GPU parity of the Wigner kernel (eq.(4)) and the creation tables (eq.(1)) against the
+oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import HB, as_u32, as_u64, dev, normwise, to_np
+from paper_1806_00082_amd import inputs, ops
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10      # normwise error bound for the FP64 path
+
+
+@pytest.mark.parametrize("nx,n_m,B", [(100, 30, 1), (400, 80, 2), (333, 256, 3), (70, 16, 4),
+                                      (1024, 256, 2), (130, 2, 1)])
+def test_kernel_fp64_all_cells(orc, nx, n_m, B):
+    """Several row tiles, several column tiles and ragged tails, both layouts."""
+    print(f"kernel fp64 nx={nx} n_m={n_m} B={B}", flush=True)
+    V = inputs.random_potentials(B, nx, 0.5, seed=nx + n_m)
+    ref = orc.kernel_1d(V, n_m, HB).reshape(B * nx, n_m)
+    Vd = torch.from_numpy(V).to(dev())
+    full = to_np(ops.kernel_eval(Vd, n_m, layout="full"))
+    half = to_np(ops.kernel_eval(Vd, n_m, layout="half"))
+    assert normwise(full.reshape(B, -1), ref.reshape(B, -1)) <= FP64_TOL
+    assert normwise(half.reshape(B, -1), orc.full_to_half(ref).reshape(B, -1)) <= FP64_TOL
+    P = n_m // 2
+    # exact zeros and exact oddness in the full layout
+    assert np.all(full[:, P] == 0) and np.all(full[:, 0] == 0)
+    assert np.array_equal(full[:, 1:P], -full[:, P + 1:][:, ::-1])
+
+
+def test_kernel_fp64_cell_list(orc):
+    """Occupied-cell evaluation: arbitrary order, duplicates, both mesh edges."""
+    nx, n_m, B = 257, 64, 3
+    V = inputs.random_potentials(B, nx, 0.5, seed=2)
+    cells = np.array([5, 0, 256, 128, 128, 1, 255, 77] * 9 + [3], dtype=np.int32)
+    ref = orc.kernel_1d(V, n_m, HB, cells=cells)
+    got = ops.kernel_eval(torch.from_numpy(V).to(dev()), n_m,
+                          cells=torch.from_numpy(cells).to(dev()), layout="full")
+    assert normwise(to_np(got).reshape(B, -1), ref.reshape(B, -1)) <= FP64_TOL
+
+
+def test_kernel_constant_potential_is_zero():
+    V = torch.full((2, 300), 0.37, dtype=torch.float64, device=dev())
+    for lay in ("full", "half"):
+        K = ops.kernel_eval(V, 64, layout=lay)
+        assert torch.count_nonzero(K).item() == 0
+
+
+def test_kernel_empty_inputs():
+    V = torch.zeros((0, 50), dtype=torch.float64, device=dev())
+    K = ops.kernel_eval(V, 16)
+    assert K.shape == (0, 16)
+    V = torch.zeros((2, 50), dtype=torch.float64, device=dev())
+    cells = torch.zeros(0, dtype=torch.int32, device=dev())
+    assert ops.kernel_eval(V, 16, cells=cells).shape == (0, 16)
+
+
+def test_kernel_fp64_full_size_sampled(orc):
+    """The precision-batch workload at full size (4096 potentials x 2048 cells x 512 m) in
+    the layout the benchmark times; sampled rows against the oracle."""
+    c3 = inputs.C3
+    B, nx, n_m = c3["B"], c3["nx"], c3["n_m"]
+    print("full-size kernel: generating potentials", flush=True)
+    V = inputs.random_potentials(B, nx, c3["dx"], seed=c3["seed"])
+    Vd = torch.from_numpy(V).to(dev())
+    K = ops.kernel_eval(Vd, n_m, layout="half")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    rows = np.concatenate([[0, B * nx - 1, nx - 1, nx], rng.integers(0, B * nx, 28)])
+    got = to_np(K[torch.from_numpy(rows).to(dev())])
+    for k, r in enumerate(rows):
+        b, i = divmod(int(r), nx)
+        ref = orc.full_to_half(orc.kernel_1d(V[b], n_m, HB, cells=[i]))[0, 0]
+        scale = np.abs(orc.full_to_half(orc.kernel_1d(V[b], n_m, HB, cells=[i]))).max()
+        assert np.abs(got[k] - ref).max() <= FP64_TOL * max(scale, 1e-30) + 1e-300, (b, i)
+    del K
+
+
+# ----------------------------------------------------------------------------- tables
+@pytest.mark.parametrize("layout,f64", [("full", True), ("half", True), ("full", False), ("half", False)])
+def test_gamma_tables_bit_exact(orc, layout, f64):
+    """Same kernel rows in -> identical gamma (FP64, sequential order), n0, thr and CDF."""
+    nx, n_m = 400, 80
+    V = inputs.random_potentials(2, nx, 0.5, seed=9)
+    Kf = orc.kernel_1d(V, n_m, HB).reshape(-1, n_m)
+    if not f64:
+        Kf = Kf.astype(np.float32).astype(np.float64)
+    dt = 0.7
+    ref = orc.gamma_tables(Kf, dt)
+    src = orc.full_to_half(Kf) if layout == "half" else Kf
+    Kd = torch.from_numpy(src.astype(np.float64 if f64 else np.float32)).to(dev())
+    g, n0, thr, cdf = ops.gamma_tables(Kd, n_m, dt, layout=layout)
+    assert np.array_equal(to_np(g), ref[0])
+    assert np.array_equal(as_u32(n0), ref[1])
+    assert np.array_equal(as_u32(thr), ref[2])
+    assert np.array_equal(as_u64(cdf), ref[3])
+
+
+def test_gamma_tables_large_rate(orc):
+    """gamma dt > 1 (several pairs per step) and all-zero rows."""
+    K = np.random.default_rng(3).normal(size=(50, 32)) * 3.0
+    K[7] = 0.0
+    ref = orc.gamma_tables(K, 2.5)
+    g, n0, thr, cdf = ops.gamma_tables(torch.from_numpy(K).to(dev()), 32, 2.5)
+    assert np.array_equal(to_np(g), ref[0])
+    assert np.array_equal(as_u32(n0), ref[1]) and ref[1].max() > 1
+    assert np.array_equal(as_u32(thr), ref[2])
+    assert np.array_equal(as_u64(cdf), ref[3])
+
+
+def test_gamma_tables_2d(orc):
+    n_m = 8
+    V = np.random.default_rng(4).normal(size=(6, 7)) * 0.1
+    K = orc.kernel_2d(V, n_m, HB).reshape(-1, n_m * n_m)
+    ref = orc.gamma_tables(K, 0.5)
+    g, n0, thr, cdf = ops.gamma_tables(torch.from_numpy(K).to(dev()), n_m, 0.5, dim=2)
+    assert np.array_equal(to_np(g), ref[0])
+    assert np.array_equal(as_u64(cdf), ref[3])
