@@ -9,12 +9,16 @@
 
 namespace wk {
 
-constexpr int KE_BK = 16;     // contraction depth staged per LDS tile
+constexpr int KE_BK = 16;     // contraction depth staged per LDS tile (FP64)
 constexpr int KE_THREADS = 256;
+constexpr int KE_BM = 64;     // rows per workgroup
+constexpr int KE_WIN = 64 + 2 * 512 + 8;   // LDS potential window (rows + 2P + 1), P <= 512
 
-// Row r -> (offset of its potential in V, cell index) for the BM rows of a block.
+// Row r -> (offset of its potential in V, cell index) for the BM rows of a block, and
+// whether the block's rows are consecutive cells of one potential (then they share one
+// window of the potential, staged in LDS).
 template <int BM>
-__device__ __forceinline__ void load_rows(long row0, long R, int n_cells, int nx,
+__device__ __forceinline__ bool load_rows(long row0, long R, int n_cells, int nx, int P,
                                           const int32_t* __restrict__ cells, long* rbase,
                                           int* rcell) {
     for (int rr = threadIdx.x; rr < BM; rr += blockDim.x) {
@@ -31,27 +35,65 @@ __device__ __forceinline__ void load_rows(long row0, long R, int n_cells, int nx
         rbase[rr] = base;
         rcell[rr] = cell;
     }
+    return cells == nullptr && row0 + BM <= R && row0 / n_cells == (row0 + BM - 1) / n_cells &&
+           BM + 2 * P + 1 <= KE_WIN;
 }
 
-// FP64 path: v_mfma_f64_16x16x4_f64.  Four waves in a 2 x 2 arrangement; each wave owns a
-// (16 WM) x (16 WN) output tile.  Operand layouts (16x16x4 f64): lane l holds
-// A[l % 16][l / 16], B[l / 16][l % 16], and C[l / 16 + 4 e][l % 16] for e < 4.
-template <int WM, int WN>
+// Potential window W[t] = V(c0 - P + t), t < BM + 2P + 1 (nearest-edge value outside).
+template <int BM>
+__device__ __forceinline__ void load_window(const double* __restrict__ V, long base, int c0, int nx,
+                                            int P, double* Wv) {
+    for (int t = threadIdx.x; t < BM + 2 * P + 1; t += blockDim.x)
+        Wv[t] = V[base + min(max(c0 - P + t, 0), nx - 1)];
+}
+
+// D[rr][jj] = V(cell + jj + 1) - V(cell - jj - 1) for a row of the block (0 beyond P).
+template <int BM>
+__device__ __forceinline__ double d_elem(bool contig, const double* Wv, const double* __restrict__ V,
+                                         const long* rbase, const int* rcell, int nx, int P, int rr,
+                                         int j) {
+    const int cell = rcell[rr];
+    if (cell == -2) return __builtin_nan("");
+    if (cell < 0 || j > P) return 0.0;
+    if (contig) return Wv[rr + P + j] - Wv[rr + P - j];
+    const double* Vb = V + rbase[rr];
+    return Vb[min(cell + j, nx - 1)] - Vb[max(cell - j, 0)];
+}
+
+// FP64 path: v_mfma_f64_16x16x4_f64.  WAVES_N waves split the columns, 4 / WAVES_N split the
+// rows; each wave owns a (16 WM) x (16 WN) output tile.  Operand layouts (16x16x4 f64):
+// lane l holds A[l % 16][l / 16], B[l / 16][l % 16], and C[l / 16 + 4 e][l % 16], e < 4.
+// The D tile is double-buffered in LDS and the next chunk's sine-table fragments are
+// loaded while the current chunk's products run.
+template <int WM, int WN, int WAVES_N>
 __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
     const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
     int P, int n_m, int Pk, int Pn, const double* __restrict__ S, double c, int layout,
     double* __restrict__ out) {
-    constexpr int BM = 32 * WM, BN = 32 * WN, BK = KE_BK;
-    __shared__ double Ds[BM][BK + 1];
+    constexpr int WAVES_M = 4 / WAVES_N;
+    constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N, BK = KE_BK;
+    static_assert(BM == KE_BM, "row tile");
+    __shared__ double Ds[2][BM][BK + 1];
+    __shared__ double Wv[KE_WIN];
     __shared__ long rbase[BM];
     __shared__ int rcell[BM];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / WAVES_N, wc = wave % WAVES_N;
     const long row0 = (long)blockIdx.x * BM;
     const int col0 = blockIdx.y * BN;
+    const int lr = lane & 15, lk = lane >> 4;
 
-    load_rows<BM>(row0, R, n_cells, nx, cells, rbase, rcell);
+    const bool contig = load_rows<BM>(row0, R, n_cells, nx, P, cells, rbase, rcell);
+    if (contig) load_window<BM>(V, (row0 / n_cells) * (long)nx, (int)(row0 % n_cells), nx, P, Wv);
+    __syncthreads();
+
+    auto build = [&](int k0, int buf) {
+        for (int e = threadIdx.x; e < BM * BK; e += KE_THREADS) {
+            const int rr = e / BK, kk = e - rr * BK;
+            Ds[buf][rr][kk] = d_elem<BM>(contig, Wv, V, rbase, rcell, nx, P, rr, k0 + kk + 1);
+        }
+    };
 
     f64x4 acc[WM][WN];
 #pragma unroll
@@ -59,37 +101,32 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
 #pragma unroll
         for (int b = 0; b < WN; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    const int lr = lane & 15, lk = lane >> 4;
     const double* Sw = S + (long)col0 + wc * WN * 16 + lr;
+    double bfrag[BK / 4][WN];
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks)
+#pragma unroll
+        for (int tn = 0; tn < WN; ++tn) bfrag[ks][tn] = Sw[(long)(4 * ks + lk) * Pn + tn * 16];
+    build(0, 0);
+    __syncthreads();
 
+    int buf = 0;
     for (int k0 = 0; k0 < Pk; k0 += BK) {
-        double bfrag[BK / 4][WN];
+        const bool more = k0 + BK < Pk;
+        double bnext[BK / 4][WN];
+        if (more) {
 #pragma unroll
-        for (int ks = 0; ks < BK / 4; ++ks)
+            for (int ks = 0; ks < BK / 4; ++ks)
 #pragma unroll
-            for (int tn = 0; tn < WN; ++tn)
-                bfrag[ks][tn] = Sw[(long)(k0 + 4 * ks + lk) * Pn + tn * 16];
-
-        __syncthreads();  // rows staged / previous tile consumed
-        for (int e = threadIdx.x; e < BM * BK; e += KE_THREADS) {
-            const int rr = e / BK, kk = e - rr * BK;
-            const int cell = rcell[rr];
-            const int j = k0 + kk + 1;
-            double d = cell == -2 ? __builtin_nan("") : 0.0;
-            if (cell >= 0 && j <= P) {
-                const double* Vb = V + rbase[rr];
-                const int ip = min(cell + j, nx - 1), im = max(cell - j, 0);
-                d = Vb[ip] - Vb[im];
-            }
-            Ds[rr][kk] = d;
+                for (int tn = 0; tn < WN; ++tn)
+                    bnext[ks][tn] = Sw[(long)(k0 + BK + 4 * ks + lk) * Pn + tn * 16];
+            build(k0 + BK, buf ^ 1);
         }
-        __syncthreads();
-
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             double afrag[WM];
 #pragma unroll
-            for (int tm = 0; tm < WM; ++tm) afrag[tm] = Ds[(wr * WM + tm) * 16 + lr][4 * ks + lk];
+            for (int tm = 0; tm < WM; ++tm) afrag[tm] = Ds[buf][(wr * WM + tm) * 16 + lr][4 * ks + lk];
 #pragma unroll
             for (int tm = 0; tm < WM; ++tm)
 #pragma unroll
@@ -97,6 +134,14 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
                     acc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(afrag[tm], bfrag[ks][tn],
                                                                      acc[tm][tn], 0, 0, 0);
         }
+        if (more) {
+#pragma unroll
+            for (int ks = 0; ks < BK / 4; ++ks)
+#pragma unroll
+                for (int tn = 0; tn < WN; ++tn) bfrag[ks][tn] = bnext[ks][tn];
+        }
+        __syncthreads();
+        buf ^= 1;
     }
 
 #pragma unroll
@@ -179,25 +224,55 @@ __device__ __forceinline__ void split16(double d, uint16_t* hi, uint16_t* lo) {
     }
 }
 
-template <int PREC, int WM, int WN>
+template <int PREC, int WM, int WN, int WAVES_N>
 __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
     int P, int n_m, int Pk, const uint16_t* __restrict__ St_hi, const uint16_t* __restrict__ St_lo,
     float c, int layout, float* __restrict__ out) {
     typedef LowpTraits<PREC> TR;
-    constexpr int BM = 32 * WM, BN = 32 * WN, BK = LP_BK, LD = BK + 8;
-    __shared__ __attribute__((aligned(16))) uint16_t Dh[BM][LD];
-    __shared__ __attribute__((aligned(16))) uint16_t Dl[TR::split ? BM : 1][LD];
+    constexpr int WAVES_M = 4 / WAVES_N;
+    constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N, BK = LP_BK, LD = BK + 8;
+    static_assert(BM == KE_BM, "row tile");
+    __shared__ __attribute__((aligned(16))) uint16_t Dh[2][BM][LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Dl[2][TR::split ? BM : 1][LD];
+    __shared__ double Wv[KE_WIN];
     __shared__ long rbase[BM];
     __shared__ int rcell[BM];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / WAVES_N, wc = wave % WAVES_N;
     const long row0 = (long)blockIdx.x * BM;
     const int col0 = blockIdx.y * BN;
     const int lr = lane & 15, lk = lane >> 4;
 
-    load_rows<BM>(row0, R, n_cells, nx, cells, rbase, rcell);
+    const bool contig = load_rows<BM>(row0, R, n_cells, nx, P, cells, rbase, rcell);
+    if (contig) load_window<BM>(V, (row0 / n_cells) * (long)nx, (int)(row0 % n_cells), nx, P, Wv);
+    __syncthreads();
+
+    auto build = [&](int k0, int buf) {
+        for (int e = threadIdx.x; e < BM * (BK / 8); e += KE_THREADS) {
+            const int rr = e / (BK / 8), kq = (e - rr * (BK / 8)) * 8;
+            s16x8 hv, lv;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double d = d_elem<BM>(contig, Wv, V, rbase, rcell, nx, P, rr, k0 + kq + q + 1);
+                uint16_t h, l;
+                split16<TR::half>(d, &h, &l);
+                hv[q] = (short)h;
+                lv[q] = (short)l;
+            }
+            *reinterpret_cast<s16x8*>(&Dh[buf][rr][kq]) = hv;
+            if constexpr (TR::split) *reinterpret_cast<s16x8*>(&Dl[buf][rr][kq]) = lv;
+        }
+    };
+    auto load_b = [&](int k0, s16x8* bh, s16x8* bl) {
+#pragma unroll
+        for (int tn = 0; tn < WN; ++tn) {
+            const long off = (long)(col0 + (wc * WN + tn) * 16 + lr) * Pk + k0 + 8 * lk;
+            bh[tn] = *reinterpret_cast<const s16x8*>(St_hi + off);
+            if constexpr (TR::split) bl[tn] = *reinterpret_cast<const s16x8*>(St_lo + off);
+        }
+    };
 
     f32x4 acc[WM][WN];
 #pragma unroll
@@ -205,42 +280,24 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
 #pragma unroll
         for (int b = 0; b < WN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    s16x8 bh[WN], bl[WN];
+    load_b(0, bh, bl);
+    build(0, 0);
+    __syncthreads();
+    int buf = 0;
     for (int k0 = 0; k0 < Pk; k0 += BK) {
-        s16x8 bh[WN], bl[WN];
-#pragma unroll
-        for (int tn = 0; tn < WN; ++tn) {
-            const long off = (long)(col0 + (wc * WN + tn) * 16 + lr) * Pk + k0 + 8 * lk;
-            bh[tn] = *reinterpret_cast<const s16x8*>(St_hi + off);
-            if constexpr (TR::split) bl[tn] = *reinterpret_cast<const s16x8*>(St_lo + off);
+        const bool more = k0 + BK < Pk;
+        s16x8 nh[WN], nl[WN];
+        if (more) {
+            load_b(k0 + BK, nh, nl);
+            build(k0 + BK, buf ^ 1);
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < BM * (BK / 8); e += KE_THREADS) {
-            const int rr = e / (BK / 8), kq = (e - rr * (BK / 8)) * 8;
-            const int cell = rcell[rr];
-            s16x8 hv, lv;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int j = k0 + kq + q + 1;
-                double d = cell == -2 ? __builtin_nan("") : 0.0;
-                if (cell >= 0 && j <= P) {
-                    const double* Vb = V + rbase[rr];
-                    d = Vb[min(cell + j, nx - 1)] - Vb[max(cell - j, 0)];
-                }
-                uint16_t h, l;
-                split16<TR::half>(d, &h, &l);
-                hv[q] = (short)h;
-                lv[q] = (short)l;
-            }
-            *reinterpret_cast<s16x8*>(&Dh[rr][kq]) = hv;
-            if constexpr (TR::split) *reinterpret_cast<s16x8*>(&Dl[rr][kq]) = lv;
-        }
-        __syncthreads();
 #pragma unroll
         for (int tm = 0; tm < WM; ++tm) {
             const int rr = (wr * WM + tm) * 16 + lr;
-            const s16x8 ah = *reinterpret_cast<const s16x8*>(&Dh[rr][8 * lk]);
+            const s16x8 ah = *reinterpret_cast<const s16x8*>(&Dh[buf][rr][8 * lk]);
             s16x8 al;
-            if constexpr (TR::split) al = *reinterpret_cast<const s16x8*>(&Dl[rr][8 * lk]);
+            if constexpr (TR::split) al = *reinterpret_cast<const s16x8*>(&Dl[buf][rr][8 * lk]);
 #pragma unroll
             for (int tn = 0; tn < WN; ++tn) {
                 acc[tm][tn] = mfma16<TR::half>(ah, bh[tn], acc[tm][tn]);
@@ -250,6 +307,15 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
                 }
             }
         }
+        if (more) {
+#pragma unroll
+            for (int tn = 0; tn < WN; ++tn) {
+                bh[tn] = nh[tn];
+                if constexpr (TR::split) bl[tn] = nl[tn];
+            }
+        }
+        __syncthreads();
+        buf ^= 1;
     }
 
 #pragma unroll
@@ -281,10 +347,16 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
 
 static int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
+// Tile shape by table width: waves split the columns when P is large (one column block
+// covers P <= 256, so each potential difference is formed once per row).
+enum { CFG_SMALL = 0, CFG_MID = 1, CFG_LARGE = 2 };
+static int tile_cfg(int P) { return P > 128 ? CFG_LARGE : (P > 64 ? CFG_MID : CFG_SMALL); }
+static int tile_bn(int cfg) { return cfg == CFG_LARGE ? 256 : (cfg == CFG_MID ? 128 : 64); }
+
 int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_t* cells,
                        int n_cells, int layout, double* out, hipStream_t stream) {
-    constexpr int WM = 2, WN = 2, BM = 32 * WM, BN = 32 * WN;
     const int n_m = mesh->n_m, P = n_m / 2;
+    const int cfg = tile_cfg(P), BN = tile_bn(cfg);
     const int Pk = round_up(P, KE_BK), Pn = round_up(P, BN);
     int err = WK_OK;
     const double* S = static_cast<const double*>(sine_table(n_m, 0, Pk, Pn, stream, &err));
@@ -292,17 +364,39 @@ int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_
     const long R = (long)B * n_cells;
     if (R == 0) return WK_OK;
     const double c = -2.0 / (mesh->hbar * (double)n_m);
-    dim3 grid((unsigned)((R + BM - 1) / BM), (unsigned)(Pn / BN));
-    hipLaunchKernelGGL((kernel_eval_f64<WM, WN>), grid, dim3(KE_THREADS), 0, stream, V, mesh->nx,
-                       R, n_cells, cells, P, n_m, Pk, Pn, S, c, layout, out);
+    dim3 grid((unsigned)((R + KE_BM - 1) / KE_BM), (unsigned)(Pn / BN));
+#define KE_LAUNCH_F64(WM, WN, WNV)                                                              \
+    hipLaunchKernelGGL((kernel_eval_f64<WM, WN, WNV>), grid, dim3(KE_THREADS), 0, stream, V,     \
+                       mesh->nx, R, n_cells, cells, P, n_m, Pk, Pn, S, c, layout, out)
+    if (cfg == CFG_LARGE)
+        KE_LAUNCH_F64(4, 4, 4);
+    else if (cfg == CFG_MID)
+        KE_LAUNCH_F64(2, 4, 2);
+    else
+        KE_LAUNCH_F64(1, 4, 1);
+#undef KE_LAUNCH_F64
     return check_launch("kernel_eval_f64");
 }
 
+template <int PREC>
+static void launch_lowp(int cfg, dim3 grid, hipStream_t stream, const double* V, int nx, long R,
+                        int n_cells, const int32_t* cells, int P, int n_m, int Pk,
+                        const uint16_t* hi, const uint16_t* lo, float c, int layout, float* out) {
+    if (cfg == CFG_LARGE)
+        hipLaunchKernelGGL((kernel_eval_lowp<PREC, 4, 4, 4>), grid, dim3(KE_THREADS), 0, stream, V, nx,
+                           R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+    else if (cfg == CFG_MID)
+        hipLaunchKernelGGL((kernel_eval_lowp<PREC, 2, 4, 2>), grid, dim3(KE_THREADS), 0, stream, V, nx,
+                           R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+    else
+        hipLaunchKernelGGL((kernel_eval_lowp<PREC, 1, 4, 1>), grid, dim3(KE_THREADS), 0, stream, V, nx,
+                           R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+}
 
 int kernel_eval_1d_lowp(const wk_mesh* mesh, const double* V, int B, const int32_t* cells,
                         int n_cells, int prec, int layout, float* out, hipStream_t stream) {
-    constexpr int WM = 2, WN = 2, BM = 32 * WM, BN = 32 * WN;
     const int n_m = mesh->n_m, P = n_m / 2;
+    const int cfg = tile_cfg(P), BN = tile_bn(cfg);
     const int Pk = round_up(P, LP_BK), Pn = round_up(P, BN);
     const bool half = prec == WK_FP16 || prec == WK_FP16X3;
     const bool split = prec == WK_BF16X3 || prec == WK_FP16X3;
@@ -317,28 +411,23 @@ int kernel_eval_1d_lowp(const wk_mesh* mesh, const double* V, int B, const int32
     }
     const long R = (long)B * n_cells;
     const float c = (float)(-2.0 / (mesh->hbar * (double)n_m));
-    dim3 grid((unsigned)((R + BM - 1) / BM), (unsigned)(Pn / BN));
+    dim3 grid((unsigned)((R + KE_BM - 1) / KE_BM), (unsigned)(Pn / BN));
     switch (prec) {
         case WK_BF16:
-            hipLaunchKernelGGL((kernel_eval_lowp<WK_BF16, WM, WN>), grid, dim3(KE_THREADS), 0, stream,
-                               V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            launch_lowp<WK_BF16>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
             break;
         case WK_FP16:
-            hipLaunchKernelGGL((kernel_eval_lowp<WK_FP16, WM, WN>), grid, dim3(KE_THREADS), 0, stream,
-                               V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            launch_lowp<WK_FP16>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
             break;
         case WK_BF16X3:
-            hipLaunchKernelGGL((kernel_eval_lowp<WK_BF16X3, WM, WN>), grid, dim3(KE_THREADS), 0,
-                               stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            launch_lowp<WK_BF16X3>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
             break;
         default:
-            hipLaunchKernelGGL((kernel_eval_lowp<WK_FP16X3, WM, WN>), grid, dim3(KE_THREADS), 0,
-                               stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            launch_lowp<WK_FP16X3>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
             break;
     }
     return check_launch("kernel_eval_lowp");
 }
-
 }  // namespace wk
 
 extern "C" int wk_kernel_eval(const wk_mesh* mesh, const double* V, int32_t B,
@@ -500,7 +589,7 @@ extern "C" int wk_kernel_bwd(const wk_mesh* mesh, const double* G, int32_t B, in
     if (B == 0) return WK_OK;
     WK_REQUIRE(G && dV && ws, "wk_kernel_bwd: NULL array");
     WK_REQUIRE(ws_bytes >= wk_kernel_bwd_workspace(mesh, B), "wk_kernel_bwd: workspace too small");
-    constexpr int WM = 2, WN = 2, BM = 32 * WM, BN = 32 * WN;
+    constexpr int WM = 2, WN = 2, BM = 32 * WM, BN = 32 * WN;   // 2 x 2 waves
     hipStream_t s = as_stream(stream);
     const int n_m = mesh->n_m, P = n_m / 2, nx = mesh->nx;
     const int Pk = round_up(P, KE_BK), Pn = round_up(P, BN);

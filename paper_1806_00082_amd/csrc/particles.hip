@@ -9,6 +9,8 @@
 // counts, pass 2 re-derives the per-particle counts and scans them inside the workgroup.
 // Output positions therefore depend only on the data, never on scheduling, and there
 // are no floating-point atomics anywhere (integer atomics only for histogram counts).
+#include <climits>
+
 #include "wk_internal.h"
 
 namespace wk {
@@ -385,10 +387,14 @@ __global__ __launch_bounds__(PT) void bins_scan(int mode, long long* d_n_out, lo
     __shared__ long long mixed_total;
     scan_pb(w.bpart, w.boffs, &total);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    {
+        __shared__ long long red[PT / 64];
         long long m = 0;
-        for (int k = 0; k < PB; ++k) m += w.counts[k];
-        mixed_total = m;
+        for (int k = threadIdx.x; k < PB; k += PT) m += w.counts[k];
+        m = wave_sum_ll(m);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) mixed_total = red[0] + red[1] + red[2] + red[3];
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -484,16 +490,67 @@ __global__ void fill_i32(int32_t* p, long n, int32_t v) {
         p[i] = v;
 }
 
+// Signed histogram of rule 1.  Counters are shared by all XCDs, so every global update is a
+// device-coherent atomic; the ensemble is close to bin-ordered (initial placement is
+// bin-major, survivors keep their order, fresh particles are appended bin by bin), so the
+// contiguous chunk a workgroup owns touches a narrow range of bins.  Each workgroup counts
+// into an LDS window of HW bins starting just below the smallest bin of its first tile,
+// then adds the non-zero window entries to the global histogram; particles outside the
+// window (rare) go straight to global atomics, merged per run of equal keys in a wave.
+constexpr int HW = 4096;
+
 template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void annih_hist(Geo g, const T* x, const T* y, const MT* M,
                                                  const MT* My, const int8_t* s,
                                                  const long long* d_n, int32_t* hist,
                                                  const long long* stats) {
+    __shared__ int lh[2][HW];
+    __shared__ long wmin[PT / 64];
     if (stats[WK_ST_OVERFLOW] != 0) return;
-    const long n = (long)*d_n;
-    for (long id = (long)blockIdx.x * PT + threadIdx.x; id < n; id += (long)gridDim.x * PT) {
-        const long b = bin_of<T, MT, DIM>(g, id, x, y, M, My, s);
-        if (b >= 0) atomicAdd(&hist[s[id] > 0 ? b : g.n_bins + b], 1);
+    long lo, hi;
+    chunk_of((long)*d_n, &lo, &hi);
+    const int lane = threadIdx.x & 63;
+    for (int k = threadIdx.x; k < 2 * HW; k += PT) (&lh[0][0])[k] = 0;
+    // window base from the first tile
+    long b0 = LONG_MAX;
+    if (lo + threadIdx.x < hi) {
+        const long b = bin_of<T, MT, DIM>(g, lo + threadIdx.x, x, y, M, My, s);
+        if (b >= 0) b0 = b;
+    }
+    for (int o = 32; o > 0; o >>= 1) b0 = min(b0, (long)__shfl_xor(b0, o, 64));
+    if (lane == 0) wmin[threadIdx.x >> 6] = b0;
+    __syncthreads();
+    long base = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
+    base = base == LONG_MAX ? 0 : max(0L, base - HW / 4);
+    for (long t0 = lo; t0 < hi; t0 += PT) {   // uniform trip count
+        const long id = t0 + threadIdx.x;
+        uint32_t key = 0xFFFFFFFFu;            // out-of-window key (global path)
+        if (id < hi) {
+            const long b = bin_of<T, MT, DIM>(g, id, x, y, M, My, s);
+            if (b >= 0) {
+                const int sg = s[id] > 0 ? 0 : 1;
+                if (b >= base && b < base + HW)
+                    atomicAdd(&lh[sg][b - base], 1);
+                else
+                    key = (uint32_t)(2 * b + sg);
+            }
+        }
+        const uint32_t prev = __shfl_up(key, 1, 64);
+        const bool head = lane == 0 || prev != key;
+        const unsigned long long heads = __ballot(head);
+        if (head && key != 0xFFFFFFFFu) {
+            const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1));
+            const int next = above ? lane + 1 + __builtin_ctzll(above) : 64;
+            const long b = (long)(key >> 1);
+            atomicAdd(&hist[(key & 1u) ? g.n_bins + b : b], next - lane);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < HW; k += PT) {
+        const long b = base + k;
+        if (b >= g.n_bins) break;
+        if (lh[0][k]) atomicAdd(&hist[b], lh[0][k]);
+        if (lh[1][k]) atomicAdd(&hist[g.n_bins + b], lh[1][k]);
     }
 }
 
@@ -576,17 +633,19 @@ __global__ void density_kernel(const int32_t* hist, long n_cells, long per_cell,
 
 
 // ----------------------------------------------------------------------------- occupied cells
-// occ[c] = 1 if the histogram holds any particle in cell c.
+// occ[c] = 1 if the histogram holds any particle in cell c (one wave per cell).
 __global__ void occupied_kernel(const int32_t* __restrict__ hist, long n_cells, long per_cell,
                                 long n_bins, uint8_t* __restrict__ occ) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long c = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (c >= n_cells) return;
-    uint8_t o = 0;
-    for (long k = 0; k < per_cell && !o; ++k) {
+    int o = 0;
+    for (long k = lane; k < per_cell; k += 64) {
         const long b = c * per_cell + k;
-        o = (hist[b] | hist[n_bins + b]) != 0;
+        o |= (hist[b] | hist[n_bins + b]) != 0;
     }
-    occ[c] = o;
+    const unsigned long long any = __ballot(o);
+    if (lane == 0) occ[c] = any != 0ull;
 }
 
 // Cells without a table row that lie within `margin` cells (per axis) of an occupied cell,
@@ -695,7 +754,7 @@ static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp
     const long long* d_n = reinterpret_cast<const long long*>(in->d_n);
     hipLaunchKernelGGL(fill_i32, dim3(1024), dim3(256), 0, s, hist, 2 * g.n_bins, 0);
     hipLaunchKernelGGL((annih_hist<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
-                       d_n, hist, stats);
+                       d_n, hist, stats);  // fixed grid: chunk_of() splits the ensemble
     hipLaunchKernelGGL((annih_keep_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
                        in->s, d_n, hist, stats, w);
     hipLaunchKernelGGL(annih_keep_scan, dim3(1), dim3(PT), 0, s, d_n, w);
@@ -829,7 +888,7 @@ extern "C" int sp_cells_to_evaluate(const sp_geom* gm, const int32_t* hist, int3
     const long n_cells = (long)g.nx * g.ny;
     uint8_t* occ = reinterpret_cast<uint8_t*>(carve(ws).binoff);  // n_cells <= n_bins bytes
     hipStream_t s = as_stream(stream);
-    hipLaunchKernelGGL(occupied_kernel, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(occupied_kernel, dim3((unsigned)((n_cells * 64 + 255) / 256)), dim3(256), 0, s,
                        hist, n_cells, g.n_bins / n_cells, g.n_bins, occ);
     hipLaunchKernelGGL(cells_needed_kernel, dim3(1), dim3(1024), 0, s, occ, g.dim, g.nx, g.ny, margin,
                        cell_slot, new_cells, reinterpret_cast<long long*>(d_count));
