@@ -34,8 +34,11 @@ METRIC = "Wigner kernel entries/s + particle-steps/s; BF16/surrogate vs FP64 at 
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "fp16x3": 2500.0,
                "fp32": 157.3}
-# algorithmic bytes (struct-of-arrays, FP32 positions): x 4 + M 4 + s 1
-B_PART = 9
+
+
+# HBM traffic of the dominant kernel per launch (GB), from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counter runs (profiles/), or None when not measured for the current kernel.
+TRAFFIC = {}
 
 
 def _events():
@@ -43,70 +46,69 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def run_headline(steps: int, warmup: int):
+# Algorithmic HBM bytes per launch of each particle kernel, from the running sums the
+# library keeps (S = stats): what the pass must move at minimum with 9-byte particles
+# (x 4 + M 4 + s 1, FP32 positions).
+KERNEL_BYTES = {
+    "step_apply": lambda S, L: 13 * S[L.ST_CUM_N] + 18 * S[L.ST_CUM_PAIRS],   # read 9 + write x 4; 2 children
+    "step_count": lambda S, L: 5 * S[L.ST_CUM_N],                              # read x 4 + s 1
+    "annih_hist": lambda S, L: 9 * S[L.ST_CUM_ANNIH_IN],                       # read 9
+    "annih_keep_count": lambda S, L: 9 * S[L.ST_CUM_ANNIH_IN],                 # read 9
+    "annih_keep_write": lambda S, L: 9 * S[L.ST_CUM_ANNIH_IN] + 9 * S[L.ST_CUM_KEPT],  # read 9, write kept 9
+    "bins_place": lambda S, L: 9 * S[L.ST_CUM_REGEN],                          # write 9
+}
+
+
+def run_headline(steps: int, warmup: int, traced: bool):
+    """The headline run.  traced=True replays the identical (bit-exact, same seed) run with
+    per-kernel events, used only for the per-kernel roofline; the headline value comes from
+    the untraced run."""
     import torch
     from paper_1806_00082_amd import _lib as L
-    from paper_1806_00082_amd import inputs, ops
+    from paper_1806_00082_amd import inputs
     from paper_1806_00082_amd.sim import Simulator
 
     cfg = inputs.config_c2()
     sim = Simulator(cfg, kernel="exact", prec="fp64", mode="occupied", refresh_every=8)
     for _ in range(warmup):
         sim.step()
-    dev = sim.dev
-    log_n = torch.zeros(steps, dtype=torch.int64, device=dev)          # N at step start
-    log_step = torch.zeros((steps, L.ST_COUNT), dtype=torch.int64, device=dev)
-    ev = [(_events(), _events()) for _ in range(steps)]
+    sim.stats[L.ST_CUM_STEPS:L.ST_COUNT].zero_()
+    if traced:
+        L.check(L.lib().wk_trace_enable(steps * 24 + 64), "wk_trace_enable")
     torch.cuda.synchronize()
     t0, t1 = _events()
     wall0 = time.perf_counter()
     t0.record()
-    for k in range(steps):
-        s = sim.step_index
-        log_n[k].copy_(sim.a.d_n[0])
-        if sim.mode == "occupied" and s > 0 and s % sim.refresh_every == 0:
-            sim.refresh()
-        (e0, e1), (e2, e3) = ev[k]
-        e0.record()
-        ops.sp_step(sim.md, sim.seed, sim.cell_slot, sim.n0, sim.thr, sim.cdf, sim.a, s,
-                    sim.stats, sim.ws)
-        e1.record()
-        log_step[k].copy_(sim.stats)
-        e2.record()
-        ops.sp_annihilate(sim.md, sim.seed, sim.a, sim.b, sim.hist, s, sim.stats, sim.ws)
-        e3.record()
-        sim.a, sim.b = sim.b, sim.a
-        sim.step_index += 1
+    for _ in range(steps):
+        sim.step()
     t1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = t0.elapsed_time(t1)
-    n_start = log_n.cpu().numpy()
-    st = log_step.cpu().numpy()
-    t_step = sum(a[0].elapsed_time(a[1]) for a, _ in ev)
-    t_ann = sum(b[0].elapsed_time(b[1]) for _, b in ev)
-    # algorithmic bytes: sp_step reads x, M, s and writes x (13 B) per particle and writes two
-    # 9-byte children per pair; sp_annihilate reads the ensemble twice (histogram, keep pass)
-    # and writes the survivors (27 B per particle) plus the 2 x n_bins int32 histogram.
-    bytes_step = float((n_start * 13).sum() + (st[:, L.ST_PAIRS] * 18).sum())
-    n_after = st[:, L.ST_N]
-    bytes_ann = float((n_after * 27).sum() + steps * 2 * 4 * ops.n_bins(sim.md) * 2)
-    passes = {
-        "sp_step": {"ms": t_step, "bytes": bytes_step},
-        "sp_annihilate": {"ms": t_ann, "bytes": bytes_ann},
-    }
-    dom = max(passes, key=lambda k: passes[k]["ms"])
-    ach = passes[dom]["bytes"] / (passes[dom]["ms"] * 1e-3) / 1e9
-    assert not sim.overflowed(), "particle buffer overflowed during the timed run"
-    return {
-        "cfg": cfg, "ms": ms, "wall_s": wall, "particle_steps": float(n_start.sum()),
-        "n_first": int(n_start[0]), "n_last": int(sim.count()),
-        "pairs": int(st[:, L.ST_PAIRS].sum()), "rows": sim.n_rows,
-        "passes": {k: {"ms_total": round(v["ms"], 3),
-                       "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)} for k, v in passes.items()},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None},
-    }
+    S = [int(v) for v in sim.stats.cpu().tolist()]
+    assert S[L.ST_OVERFLOW] == 0, "particle buffer overflowed during the timed run"
+    assert S[L.ST_CUM_STEPS] == steps
+    out = {"cfg": cfg, "ms": ms, "wall_s": wall, "particle_steps": float(S[L.ST_CUM_N]),
+           "pairs": S[L.ST_CUM_PAIRS], "regen": S[L.ST_CUM_REGEN], "n_last": int(sim.count()),
+           "rows": sim.n_rows, "stats": S}
+    if not traced:
+        return out
+    L.check(L.lib().wk_trace_disable(), "wk_trace_disable")
+    kernels = {}
+    for name in L.trace_names():
+        tot, cnt = L.trace_read(name)
+        kernels[name] = {"ms_total": round(tot, 3), "launches": cnt, "us_avg": round(1e3 * tot / max(cnt, 1), 2)}
+        if name in KERNEL_BYTES:
+            b = KERNEL_BYTES[name](S, L)
+            kernels[name]["alg_GB"] = round(b / 1e9, 3)
+            kernels[name]["alg_GBps"] = round(b / (tot * 1e-3) / 1e9, 1)
+    dom = max((k for k in kernels if k in KERNEL_BYTES), key=lambda k: kernels[k]["ms_total"])
+    ach = kernels[dom]["alg_GBps"]
+    out["kernels"] = kernels
+    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                       "traffic": TRAFFIC.get(dom)}
+    return out
 
 
 def run_kernel_forms():
@@ -236,7 +238,9 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    h = run_headline(args.steps, args.warmup)
+    h = run_headline(args.steps, args.warmup, traced=False)
+    tr = run_headline(args.steps, args.warmup, traced=True)
+    assert tr["stats"][11:16] == h["stats"][11:16], "traced replica diverged from the timed run"
     forms = {} if args.no_forms else {"kernel_eq4": run_kernel_forms(), "surrogate_eq5": run_surrogate_forms()}
     cpu = None if args.no_cpu else run_cpu_baseline(args.cpu_steps)
     value = h["particle_steps"] / (h["ms"] * 1e-3)
@@ -257,10 +261,11 @@ def main():
         "config": {"workload": cfg.name, "cells": cfg.mesh.nx, "dx_nm": cfg.mesh.dx,
                    "n_m": cfg.mesh.n_m, "particles_initial": int(cfg.bin_counts.sum()),
                    "dt_fs": cfg.dt, "annihilation": "every step", "kernel": "exact fp64, occupied cells"},
-        "run": {"n_first": h["n_first"], "n_last": h["n_last"], "pairs_created": h["pairs"],
+        "run": {"n_last": h["n_last"], "pairs_created": h["pairs"], "regenerated": h["regen"],
                 "kernel_rows_evaluated": h["rows"], "wall_s": round(h["wall_s"], 3),
-                "passes": h["passes"]},
-        "roofline": h["roofline"],
+                "traced_replica_ms_per_step": round(tr["ms"] / args.steps, 4),
+                "kernels": tr["kernels"]},
+        "roofline": tr["roofline"],
         "cpu_baseline": cpu,
         "forms": forms,
     }

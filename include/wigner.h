@@ -109,11 +109,28 @@ enum wk_stat {
     WK_ST_OVERFLOW = 8,   /* sticky: 1 once an overflow happened; later particle calls
                              are then no-ops until the caller clears it */
     WK_ST_OVERFLOW_STEP = 9, /* step index of that overflow */
+    /* running sums over calls (the caller zeroes them to start a measurement window) */
+    WK_ST_CUM_STEPS = 10,    /* sp_step calls that ran */
+    WK_ST_CUM_N = 11,        /* particles at the start of those steps */
+    WK_ST_CUM_PAIRS = 12,    /* pairs they created */
+    WK_ST_CUM_ANNIH_IN = 13, /* particles entering sp_annihilate */
+    WK_ST_CUM_KEPT = 14,     /* particles it kept */
+    WK_ST_CUM_REGEN = 15,    /* particles it regenerated */
     WK_ST_COUNT = 16
 };
 
 const char* wk_last_error(void);
 int wk_version(void);
+
+/* Per-kernel timing for measurement tools.  wk_trace_enable(max) creates 2*max events and
+ * from then on brackets each library kernel launch (up to max launches) with events on the
+ * launch stream; wk_trace_read(name) synchronises those events and returns the summed
+ * duration (ms) and number of launches of kernel `name`; wk_trace_names() writes the
+ * traced kernel names, one per line.  Host-side bookkeeping only; results are unchanged. */
+int wk_trace_enable(int32_t max_launches);
+int wk_trace_disable(void);
+int wk_trace_read(const char* name, double* total_ms, int64_t* count);
+int wk_trace_names(char* buf, size_t len);
 /* Number of HIP devices visible (0 without a GPU); never fails. */
 int wk_device_count(void);
 

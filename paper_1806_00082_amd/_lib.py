@@ -15,7 +15,8 @@ WK_OK, WK_EINVAL, WK_ECAPACITY, WK_EHIP = 0, -1, -2, -3
 WK_FP64, WK_BF16, WK_FP16, WK_BF16X3, WK_FP16X3 = 0, 1, 2, 3, 4
 WK_FULL, WK_HALF = 0, 1
 (ST_N, ST_PAIRS, ST_ABS_X, ST_ABS_M, ST_NEEDED, ST_KEPT, ST_REGEN, ST_MIXED,
- ST_OVERFLOW, ST_OVERFLOW_STEP) = range(10)
+ ST_OVERFLOW, ST_OVERFLOW_STEP, ST_CUM_STEPS, ST_CUM_N, ST_CUM_PAIRS, ST_CUM_ANNIH_IN,
+ ST_CUM_KEPT, ST_CUM_REGEN) = range(16)
 ST_COUNT = 16
 
 PREC = {"fp64": WK_FP64, "bf16": WK_BF16, "fp16": WK_FP16, "bf16x3": WK_BF16X3,
@@ -48,6 +49,10 @@ SIGNATURES = {
     "wk_last_error": (ctypes.c_char_p, []),
     "wk_version": (ctypes.c_int, []),
     "wk_device_count": (ctypes.c_int, []),
+    "wk_trace_enable": (ctypes.c_int, [_i32]),
+    "wk_trace_disable": (ctypes.c_int, []),
+    "wk_trace_read": (ctypes.c_int, [ctypes.c_char_p, _P, _P]),
+    "wk_trace_names": (ctypes.c_int, [ctypes.c_char_p, _sz]),
     "wk_kernel_eval": (ctypes.c_int, [_MP, _P, _i32, _P, _i32, _i32, _i32, _P, _P]),
     "wk_kernel_bwd_workspace": (_sz, [_MP, _i32]),
     "wk_kernel_bwd": (ctypes.c_int, [_MP, _P, _i32, _i32, _P, _P, _sz, _P]),
@@ -96,3 +101,17 @@ def check(rc: int, what: str) -> int:
         msg = lib().wk_last_error().decode(errors="replace")
         raise WignerError(f"{what} failed ({rc}): {msg}")
     return rc
+
+
+def trace_read(name: str):
+    """(total ms, launches) of a traced kernel since wk_trace_enable."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    check(lib().wk_trace_read(name.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "wk_trace_read")
+    return ms.value, cnt.value
+
+
+def trace_names():
+    buf = ctypes.create_string_buffer(8192)
+    check(lib().wk_trace_names(buf, len(buf)), "wk_trace_names")
+    return [n for n in buf.value.decode().split("\n") if n]

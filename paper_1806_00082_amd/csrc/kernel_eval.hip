@@ -366,7 +366,7 @@ int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_
     const double c = -2.0 / (mesh->hbar * (double)n_m);
     dim3 grid((unsigned)((R + KE_BM - 1) / KE_BM), (unsigned)(Pn / BN));
 #define KE_LAUNCH_F64(WM, WN, WNV)                                                              \
-    hipLaunchKernelGGL((kernel_eval_f64<WM, WN, WNV>), grid, dim3(KE_THREADS), 0, stream, V,     \
+    WK_LAUNCH("kernel_eval_f64", (kernel_eval_f64<WM, WN, WNV>), grid, dim3(KE_THREADS), 0, stream, V, \
                        mesh->nx, R, n_cells, cells, P, n_m, Pk, Pn, S, c, layout, out)
     if (cfg == CFG_LARGE)
         KE_LAUNCH_F64(4, 4, 4);
@@ -383,13 +383,13 @@ static void launch_lowp(int cfg, dim3 grid, hipStream_t stream, const double* V,
                         int n_cells, const int32_t* cells, int P, int n_m, int Pk,
                         const uint16_t* hi, const uint16_t* lo, float c, int layout, float* out) {
     if (cfg == CFG_LARGE)
-        hipLaunchKernelGGL((kernel_eval_lowp<PREC, 4, 4, 4>), grid, dim3(KE_THREADS), 0, stream, V, nx,
+        WK_LAUNCH("kernel_eval_lowp", (kernel_eval_lowp<PREC, 4, 4, 4>), grid, dim3(KE_THREADS), 0, stream, V, nx,
                            R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
     else if (cfg == CFG_MID)
-        hipLaunchKernelGGL((kernel_eval_lowp<PREC, 2, 4, 2>), grid, dim3(KE_THREADS), 0, stream, V, nx,
+        WK_LAUNCH("kernel_eval_lowp", (kernel_eval_lowp<PREC, 2, 4, 2>), grid, dim3(KE_THREADS), 0, stream, V, nx,
                            R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
     else
-        hipLaunchKernelGGL((kernel_eval_lowp<PREC, 1, 4, 1>), grid, dim3(KE_THREADS), 0, stream, V, nx,
+        WK_LAUNCH("kernel_eval_lowp", (kernel_eval_lowp<PREC, 1, 4, 1>), grid, dim3(KE_THREADS), 0, stream, V, nx,
                            R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
 }
 

@@ -55,9 +55,12 @@ static size_t ws_bytes_for(long n_bins) {
     return sizeof(long long) * (16 + 4 * (size_t)PB) + sizeof(int) * (size_t)(n_bins + 1);
 }
 
+constexpr int IT = 4;          // particles per thread in the streaming passes
+constexpr int TILE = PT * IT;  // particles per workgroup iteration
+
 __device__ __forceinline__ void chunk_of(long n, long* lo, long* hi) {
     long chunk = (n + PB - 1) / PB;
-    chunk = (chunk + PT - 1) / PT * PT;
+    chunk = (chunk + TILE - 1) / TILE * TILE;
     *lo = (long)blockIdx.x * chunk;
     *hi = min(n, *lo + chunk);
     if (*lo > n) *lo = n;
@@ -76,20 +79,89 @@ __device__ __forceinline__ T cell_plus_frac(int c, uint32_t u, int fb) {
 }
 
 // Histogram bin of a particle, -1 when dead or outside the grid.
-template <typename T, typename MT, int DIM>
-__device__ __forceinline__ long bin_of(const Geo& g, long id, const T* x, const T* y, const MT* M,
-                                       const MT* My, const int8_t* s) {
-    if (s[id] == 0) return -1;
-    const int cx = cell_index<T>(x[id], g.nx);
+template <typename T, int DIM>
+__device__ __forceinline__ long bin_val(const Geo& g, T x, T y, int m, int my, int8_t s) {
+    if (s == 0) return -1;
+    const int cx = cell_index<T>(x, g.nx);
     if (cx < 0) return -1;
-    const int kx = (int)M[id] - g.M_min;
+    const int kx = m - g.M_min;
     if (kx < 0 || kx >= g.n_k) return -1;
     if (DIM == 1) return (long)cx * g.n_k + kx;
-    const int cy = cell_index<T>(y[id], g.ny);
+    const int cy = cell_index<T>(y, g.ny);
     if (cy < 0) return -1;
-    const int ky = (int)My[id] - g.M_min;
+    const int ky = my - g.M_min;
     if (ky < 0 || ky >= g.n_k) return -1;
     return (((long)cy * g.nx + cx) * g.n_k + ky) * g.n_k + kx;
+}
+
+// Four consecutive particles (ids id .. id+3, id a multiple of 4) loaded with 16-byte
+// (positions, int32 momenta), 8-byte (int16 momenta) and 4-byte (signs) accesses;
+// slots at or beyond hi read as dead.
+template <typename T, int DIM>
+struct Part4 {
+    T x[IT], y[IT];
+    int m[IT], my[IT];
+    int8_t s[IT];
+};
+
+__device__ __forceinline__ void ld4(const float* p, long i, float* v) {
+    const float4 t = *reinterpret_cast<const float4*>(p + i);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ __forceinline__ void ld4(const double* p, long i, double* v) {
+    const double2 a = *reinterpret_cast<const double2*>(p + i);
+    const double2 b = *reinterpret_cast<const double2*>(p + i + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void ld4(const int32_t* p, long i, int* v) {
+    const int4 t = *reinterpret_cast<const int4*>(p + i);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ __forceinline__ void ld4(const int16_t* p, long i, int* v) {
+    const short4 t = *reinterpret_cast<const short4*>(p + i);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ __forceinline__ void ld4(const int8_t* p, long i, int8_t* v) {
+    const char4 t = *reinterpret_cast<const char4*>(p + i);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ __forceinline__ void st4(float* p, long i, const float* v) {
+    *reinterpret_cast<float4*>(p + i) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st4(double* p, long i, const double* v) {
+    *reinterpret_cast<double2*>(p + i) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + i + 2) = make_double2(v[2], v[3]);
+}
+
+template <typename T, typename MT, int DIM>
+__device__ __forceinline__ void load4(const T* x, const T* y, const MT* M, const MT* My,
+                                      const int8_t* s, long id, long hi, Part4<T, DIM>& p) {
+    if (id + IT <= hi) {
+        ld4(x, id, p.x);
+        ld4(M, id, p.m);
+        ld4(s, id, p.s);
+        if (DIM == 2) {
+            ld4(y, id, p.y);
+            ld4(My, id, p.my);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const bool v = id + k < hi;
+            p.x[k] = v ? x[id + k] : (T)0;
+            p.m[k] = v ? (int)M[id + k] : 0;
+            p.s[k] = v ? s[id + k] : (int8_t)0;
+            p.y[k] = (DIM == 2 && v) ? y[id + k] : (T)0;
+            p.my[k] = (DIM == 2 && v) ? (int)My[id + k] : 0;
+        }
+    }
+    if (DIM == 1) {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            p.y[k] = (T)0;
+            p.my[k] = 0;
+        }
+    }
 }
 
 // Pairs created by particle id this step (postulate II with the integer tables).
@@ -141,7 +213,8 @@ __device__ __forceinline__ bool inside(T x, int n) {
 template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int32_t* cell_slot,
                                                  const uint32_t* n0, const uint32_t* thr,
-                                                 const T* x, const T* y, const int8_t* s,
+                                                 const T* x, const T* y, const MT* M,
+                                                 const MT* My, const int8_t* s,
                                                  const long long* d_n, const long long* stats,
                                                  WS w) {
     __shared__ long long red[PT / 64];
@@ -149,11 +222,17 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
     if (stats[WK_ST_OVERFLOW] == 0) {
         long lo, hi;
         chunk_of(*d_n, &lo, &hi);
-        for (long id = lo + threadIdx.x; id < hi; id += PT) {
-            int slot;
-            u32x4 r;
-            cnt += pairs_of<T, DIM>(g, (uint32_t)id, step, x[id], DIM == 2 ? y[id] : (T)0, s[id],
-                                    cell_slot, n0, thr, &slot, &r);
+        for (long t0 = lo; t0 < hi; t0 += TILE) {
+            const long id = t0 + IT * threadIdx.x;
+            Part4<T, DIM> p;
+            load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
+#pragma unroll
+            for (int k = 0; k < IT; ++k) {
+                int slot;
+                u32x4 r;
+                cnt += pairs_of<T, DIM>(g, (uint32_t)(id + k), step, p.x[k], p.y[k], p.s[k],
+                                        cell_slot, n0, thr, &slot, &r);
+            }
         }
     }
     cnt = wave_sum_ll(cnt);
@@ -214,6 +293,9 @@ __global__ __launch_bounds__(PT) void step_scan(long long* d_n, long long capaci
     w.sc[SC_GO] = 1;
     stats[WK_ST_N] = needed;
     stats[WK_ST_PAIRS] = total;
+    stats[WK_ST_CUM_STEPS] += 1;
+    stats[WK_ST_CUM_N] += n;
+    stats[WK_ST_CUM_PAIRS] += total;
     stats[WK_ST_ABS_X] = 0;
     stats[WK_ST_ABS_M] = 0;
     stats[WK_ST_NEEDED] = 0;
@@ -234,86 +316,95 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
     long long run = w.offs[blockIdx.x];
     const T vdt = (T)g.vdt;
     long long abs_x = 0, abs_m = 0;
-    for (long base = lo; base < hi; base += PT) {  // uniform trip count in the workgroup
-        const long id = base + threadIdx.x;
-        const bool valid = id < hi;
-        T px = 0, py = 0;
-        int pm = 0, pmy = 0;
-        int8_t sv = 0;
-        if (valid) {
-            px = x[id];
-            if (DIM == 2) py = y[id];
-            pm = (int)M[id];
-            if (DIM == 2) pmy = (int)My[id];
-            sv = s[id];
-        }
-        int slot = -1;
-        u32x4 r;
-        const int np = valid ? pairs_of<T, DIM>(g, (uint32_t)id, step, px, py, sv, cell_slot, n0,
-                                                thr, &slot, &r)
-                             : 0;
-        int tot;
-        const int ex = block_excl_scan_256(np, &tot, lds5);
-        long o = n + 2 * (long)(run + ex);
-        for (int k = 0; k < np; ++k) {
-            uint32_t u;
-            if (k < 3) {
-                u = r.v[k + 1];
-            } else {
-                const u32x4 r2 = philox((uint32_t)id, step, (uint32_t)(1 + (k - 3) / 4), TAG_CREATE, g.seed);
-                u = r2.v[(k - 3) & 3];
-            }
-            const int t = sample_cdf(cdf + (long)slot * g.width, g.width, u);
-            const int mx = (DIM == 1 ? t : t % g.n_m) - g.P;
-            const int my = DIM == 1 ? 0 : t / g.n_m - g.P;
+    auto absorbed = [&](T nx_, T ny_, int m, int my) -> int {
+        bool outx = !inside<T>(nx_, g.nx);
+        if (DIM == 2) outx = outx || !inside<T>(ny_, g.ny);
+        bool outm = m < g.M_min || m >= g.M_min + g.n_k;
+        if (DIM == 2) outm = outm || my < g.M_min || my >= g.M_min + g.n_k;
+        return outx ? 1 : (outm ? 2 : 0);
+    };
+    for (long t0 = lo; t0 < hi; t0 += TILE) {  // uniform trip count in the workgroup
+        const long id = t0 + IT * threadIdx.x;
+        Part4<T, DIM> p;
+        load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
+        int slot[IT];
+        u32x4 r[IT];
+        int np[IT], npt = 0;
 #pragma unroll
-            for (int ch = 0; ch < 2; ++ch, ++o) {
-                const int sg = ch == 0 ? 1 : -1;
-                const int cm = pm + sg * mx, cmy = pmy + sg * my;
-                int8_t cs = (int8_t)(sg * sv);
-                const T cx = drift(px, cm, vdt);
-                T cy = 0;
-                bool outx = !inside<T>(cx, g.nx);
-                if (DIM == 2) {
-                    cy = drift(py, cmy, vdt);
-                    outx = outx || !inside<T>(cy, g.ny);
+        for (int k = 0; k < IT; ++k) {
+            np[k] = pairs_of<T, DIM>(g, (uint32_t)(id + k), step, p.x[k], p.y[k], p.s[k], cell_slot,
+                                     n0, thr, &slot[k], &r[k]);
+            npt += np[k];
+        }
+        int tot;
+        const int ex = block_excl_scan_256(npt, &tot, lds5);
+        long o = n + 2 * (long)(run + ex);
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            for (int q = 0; q < np[k]; ++q) {
+                uint32_t u;
+                if (q < 3) {
+                    u = q == 0 ? r[k].v[1] : (q == 1 ? r[k].v[2] : r[k].v[3]);
+                } else {
+                    const u32x4 r2 = philox((uint32_t)(id + k), step, (uint32_t)(1 + (q - 3) / 4),
+                                            TAG_CREATE, g.seed);
+                    const int wq = (q - 3) & 3;
+                    u = wq == 0 ? r2.v[0] : (wq == 1 ? r2.v[1] : (wq == 2 ? r2.v[2] : r2.v[3]));
                 }
-                bool outm = cm < g.M_min || cm >= g.M_min + g.n_k;
-                if (DIM == 2) outm = outm || cmy < g.M_min || cmy >= g.M_min + g.n_k;
-                if (outx) {
-                    cs = 0;
-                    ++abs_x;
-                } else if (outm) {
-                    cs = 0;
-                    ++abs_m;
+                const int t = sample_cdf(cdf + (long)slot[k] * g.width, g.width, u);
+                const int mx = (DIM == 1 ? t : t % g.n_m) - g.P;
+                const int my = DIM == 1 ? 0 : t / g.n_m - g.P;
+#pragma unroll
+                for (int ch = 0; ch < 2; ++ch, ++o) {
+                    const int sg = ch == 0 ? 1 : -1;
+                    const int cm = p.m[k] + sg * mx, cmy = p.my[k] + sg * my;
+                    const T cx = drift(p.x[k], cm, vdt);
+                    const T cy = DIM == 2 ? drift(p.y[k], cmy, vdt) : (T)0;
+                    const int a = absorbed(cx, cy, cm, cmy);
+                    abs_x += a == 1;
+                    abs_m += a == 2;
+                    x[o] = cx;
+                    M[o] = (MT)cm;
+                    if (DIM == 2) {
+                        y[o] = cy;
+                        My[o] = (MT)cmy;
+                    }
+                    s[o] = a ? (int8_t)0 : (int8_t)(sg * p.s[k]);
                 }
-                x[o] = cx;
-                M[o] = (MT)cm;
-                if (DIM == 2) {
-                    y[o] = cy;
-                    My[o] = (MT)cmy;
-                }
-                s[o] = cs;
             }
         }
-        if (valid && sv != 0) {
-            const T nxp = drift(px, pm, vdt);
-            bool outx = !inside<T>(nxp, g.nx);
-            T nyp = 0;
-            if (DIM == 2) {
-                nyp = drift(py, pmy, vdt);
-                outx = outx || !inside<T>(nyp, g.ny);
+        // parents: drift in place, absorb
+        T nxv[IT], nyv[IT];
+        bool sdirty = false;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            nxv[k] = p.x[k];
+            nyv[k] = p.y[k];
+            if (p.s[k] != 0) {
+                nxv[k] = drift(p.x[k], p.m[k], vdt);
+                if (DIM == 2) nyv[k] = drift(p.y[k], p.my[k], vdt);
+                const int a = absorbed(nxv[k], nyv[k], p.m[k], p.my[k]);
+                abs_x += a == 1;
+                abs_m += a == 2;
+                if (a) {
+                    p.s[k] = 0;
+                    sdirty = true;
+                }
             }
-            bool outm = pm < g.M_min || pm >= g.M_min + g.n_k;
-            if (DIM == 2) outm = outm || pmy < g.M_min || pmy >= g.M_min + g.n_k;
-            x[id] = nxp;
-            if (DIM == 2) y[id] = nyp;
-            if (outx) {
-                s[id] = 0;
-                ++abs_x;
-            } else if (outm) {
-                s[id] = 0;
-                ++abs_m;
+        }
+        if (id + IT <= hi) {
+            st4(x, id, nxv);
+            if (DIM == 2) st4(y, id, nyv);
+            if (sdirty)
+                *reinterpret_cast<char4*>(s + id) = make_char4(p.s[0], p.s[1], p.s[2], p.s[3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < IT; ++k) {
+                if (id + k < hi) {
+                    x[id + k] = nxv[k];
+                    if (DIM == 2) y[id + k] = nyv[k];
+                    s[id + k] = p.s[k];
+                }
             }
         }
         run += tot;
@@ -417,6 +508,9 @@ __global__ __launch_bounds__(PT) void bins_scan(int mode, long long* d_n_out, lo
         stats[WK_ST_KEPT] = base;
         stats[WK_ST_REGEN] = total;
         stats[WK_ST_MIXED] = mixed_total;
+        stats[WK_ST_CUM_ANNIH_IN] += w.sc[SC_N_OLD];
+        stats[WK_ST_CUM_KEPT] += base;
+        stats[WK_ST_CUM_REGEN] += total;
     } else {
         stats[WK_ST_NEEDED] = 0;
     }
@@ -439,9 +533,8 @@ __global__ __launch_bounds__(PT) void bins_downsweep(BinCount bc, int mode, WS w
     }
 }
 
-// Particle slot o of the bin range -> its bin (largest b with binoff[b] <= o).
-__device__ __forceinline__ long find_bin(const int* binoff, long n_bins, long o) {
-    long lo = 0, hi = n_bins;  // upper_bound in [0, n_bins)
+// Particle slot o of the bin range -> its bin: the largest b in [lo, hi) with binoff[b] <= o.
+__device__ __forceinline__ long find_bin(const int* binoff, long lo, long hi, long o) {
     while (lo < hi) {
         const long mid = (lo + hi) >> 1;
         if ((long)binoff[mid] <= o)
@@ -452,31 +545,46 @@ __device__ __forceinline__ long find_bin(const int* binoff, long n_bins, long o)
     return lo - 1;
 }
 
+// Each workgroup fills a contiguous range of output slots; the bins covering the range are
+// bracketed once per workgroup, so each slot searches only a few bins.
 template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void bins_place(Geo g, BinCount bc, int mode, uint32_t c1,
                                                  uint32_t tag, T* x, T* y, MT* M, MT* My,
                                                  int8_t* s, WS w) {
+    __shared__ long brange[2];
     if (w.sc[SC_GO] == 0) return;
     const long base = mode == 0 ? 0 : (long)w.sc[SC_KEPT];
     const long total = (long)w.sc[SC_NBIN_TOTAL];
-    for (long k = (long)blockIdx.x * PT + threadIdx.x; k < total; k += (long)gridDim.x * PT) {
+    const long chunk = (total + gridDim.x - 1) / gridDim.x;
+    const long k_lo = min(total, (long)blockIdx.x * chunk), k_hi = min(total, k_lo + chunk);
+    if (k_lo >= k_hi) return;
+    if (threadIdx.x == 0) {
+        brange[0] = find_bin(w.binoff, 0, g.n_bins, base + k_lo);
+        brange[1] = find_bin(w.binoff, 0, g.n_bins, base + k_hi - 1) + 1;
+    }
+    __syncthreads();
+    const long blo = brange[0], bhi = brange[1];
+    for (long k = k_lo + threadIdx.x; k < k_hi; k += PT) {
         const long o = base + k;
-        const long b = find_bin(w.binoff, g.n_bins, o);
+        const long b = find_bin(w.binoff, blo, bhi, o);
         const long r = o - w.binoff[b];
         int8_t sign = 1;
         if (mode == 1) sign = bc.hist[b] > bc.hist[g.n_bins + b] ? 1 : -1;
         if (DIM == 1) {
             const int cx = (int)(b / g.n_k), kx = (int)(b % g.n_k);
             const u32x4 u = philox((uint32_t)b, c1, (uint32_t)(r >> 2), tag, g.seed);
-            x[o] = cell_plus_frac<T>(cx, u.v[r & 3], g.fb);
+            const int wq = (int)(r & 3);
+            const uint32_t uw = wq == 0 ? u.v[0] : (wq == 1 ? u.v[1] : (wq == 2 ? u.v[2] : u.v[3]));
+            x[o] = cell_plus_frac<T>(cx, uw, g.fb);
             M[o] = (MT)(g.M_min + kx);
         } else {
             const int kx = (int)(b % g.n_k), ky = (int)((b / g.n_k) % g.n_k);
             const long c = b / ((long)g.n_k * g.n_k);
             const int cx = (int)(c % g.nx), cy = (int)(c / g.nx);
             const u32x4 u = philox((uint32_t)b, c1, (uint32_t)(r >> 1), tag, g.seed);
-            x[o] = cell_plus_frac<T>(cx, u.v[2 * (r & 1)], g.fb);
-            y[o] = cell_plus_frac<T>(cy, u.v[2 * (r & 1) + 1], g.fb);
+            const bool odd = (r & 1) != 0;
+            x[o] = cell_plus_frac<T>(cx, odd ? u.v[2] : u.v[0], g.fb);
+            y[o] = cell_plus_frac<T>(cy, odd ? u.v[3] : u.v[1], g.fb);
             M[o] = (MT)(g.M_min + kx);
             My[o] = (MT)(g.M_min + ky);
         }
@@ -511,38 +619,46 @@ __global__ __launch_bounds__(PT) void annih_hist(Geo g, const T* x, const T* y, 
     chunk_of((long)*d_n, &lo, &hi);
     const int lane = threadIdx.x & 63;
     for (int k = threadIdx.x; k < 2 * HW; k += PT) (&lh[0][0])[k] = 0;
-    // window base from the first tile
+    // window base: smallest bin of the first tile, less a quarter window
     long b0 = LONG_MAX;
-    if (lo + threadIdx.x < hi) {
-        const long b = bin_of<T, MT, DIM>(g, lo + threadIdx.x, x, y, M, My, s);
-        if (b >= 0) b0 = b;
+    {
+        Part4<T, DIM> p;
+        load4<T, MT, DIM>(x, y, M, My, s, lo + IT * threadIdx.x, hi, p);
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const long b = bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]);
+            if (b >= 0) b0 = min(b0, b);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) b0 = min(b0, (long)__shfl_xor(b0, o, 64));
     if (lane == 0) wmin[threadIdx.x >> 6] = b0;
     __syncthreads();
     long base = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
     base = base == LONG_MAX ? 0 : max(0L, base - HW / 4);
-    for (long t0 = lo; t0 < hi; t0 += PT) {   // uniform trip count
-        const long id = t0 + threadIdx.x;
-        uint32_t key = 0xFFFFFFFFu;            // out-of-window key (global path)
-        if (id < hi) {
-            const long b = bin_of<T, MT, DIM>(g, id, x, y, M, My, s);
+    for (long t0 = lo; t0 < hi; t0 += TILE) {
+        const long id = t0 + IT * threadIdx.x;
+        Part4<T, DIM> p;
+        load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            uint32_t key = 0xFFFFFFFFu;    // out-of-window key (global path)
+            const long b = bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]);
             if (b >= 0) {
-                const int sg = s[id] > 0 ? 0 : 1;
+                const int sg = p.s[k] > 0 ? 0 : 1;
                 if (b >= base && b < base + HW)
                     atomicAdd(&lh[sg][b - base], 1);
                 else
                     key = (uint32_t)(2 * b + sg);
             }
-        }
-        const uint32_t prev = __shfl_up(key, 1, 64);
-        const bool head = lane == 0 || prev != key;
-        const unsigned long long heads = __ballot(head);
-        if (head && key != 0xFFFFFFFFu) {
-            const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1));
-            const int next = above ? lane + 1 + __builtin_ctzll(above) : 64;
-            const long b = (long)(key >> 1);
-            atomicAdd(&hist[(key & 1u) ? g.n_bins + b : b], next - lane);
+            const uint32_t prev = __shfl_up(key, 1, 64);
+            const bool head = lane == 0 || prev != key;
+            const unsigned long long heads = __ballot(head);
+            if (head && key != 0xFFFFFFFFu) {
+                const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1));
+                const int next = above ? lane + 1 + __builtin_ctzll(above) : 64;
+                const long bb = (long)(key >> 1);
+                atomicAdd(&hist[(key & 1u) ? g.n_bins + bb : bb], next - lane);
+            }
         }
     }
     __syncthreads();
@@ -554,11 +670,8 @@ __global__ __launch_bounds__(PT) void annih_hist(Geo g, const T* x, const T* y, 
     }
 }
 
-template <typename T, typename MT, int DIM>
-__device__ __forceinline__ bool keeps(const Geo& g, long id, const T* x, const T* y, const MT* M,
-                                      const MT* My, const int8_t* s, const int32_t* hist) {
-    const long b = bin_of<T, MT, DIM>(g, id, x, y, M, My, s);
-    return b >= 0 && !(hist[b] > 0 && hist[g.n_bins + b] > 0);
+__device__ __forceinline__ bool keeps_bin(long b, const int32_t* hist, long n_bins) {
+    return b >= 0 && !(hist[b] > 0 && hist[n_bins + b] > 0);
 }
 
 template <typename T, typename MT, int DIM>
@@ -571,8 +684,15 @@ __global__ __launch_bounds__(PT) void annih_keep_count(Geo g, const T* x, const 
     if (stats[WK_ST_OVERFLOW] == 0) {
         long lo, hi;
         chunk_of(*d_n, &lo, &hi);
-        for (long id = lo + threadIdx.x; id < hi; id += PT)
-            c += keeps<T, MT, DIM>(g, id, x, y, M, My, s, hist) ? 1 : 0;
+        for (long t0 = lo; t0 < hi; t0 += TILE) {
+            const long id = t0 + IT * threadIdx.x;
+            Part4<T, DIM> p;
+            load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
+#pragma unroll
+            for (int k = 0; k < IT; ++k)
+                c += keeps_bin(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), hist,
+                               g.n_bins) ? 1 : 0;
+        }
     }
     c = wave_sum_ll(c);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
@@ -600,20 +720,31 @@ __global__ __launch_bounds__(PT) void annih_keep_write(Geo g, const T* x, const 
     long lo, hi;
     chunk_of((long)w.sc[SC_N_OLD], &lo, &hi);
     long long run = w.offs[blockIdx.x];
-    for (long base = lo; base < hi; base += PT) {
-        const long id = base + threadIdx.x;
-        const int k = (id < hi && keeps<T, MT, DIM>(g, id, x, y, M, My, s, hist)) ? 1 : 0;
+    for (long t0 = lo; t0 < hi; t0 += TILE) {
+        const long id = t0 + IT * threadIdx.x;
+        Part4<T, DIM> p;
+        load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
+        bool kp[IT];
+        int kt = 0;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            kp[k] = keeps_bin(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), hist, g.n_bins);
+            kt += kp[k];
+        }
         int tot;
-        const int ex = block_excl_scan_256(k, &tot, lds5);
-        if (k) {
-            const long o = run + ex;
-            xo[o] = x[id];
-            Mo[o] = M[id];
+        const int ex = block_excl_scan_256(kt, &tot, lds5);
+        long o = run + ex;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            if (!kp[k]) continue;
+            xo[o] = p.x[k];
+            Mo[o] = (MT)p.m[k];
             if (DIM == 2) {
-                yo[o] = y[id];
-                Myo[o] = My[id];
+                yo[o] = p.y[k];
+                Myo[o] = (MT)p.my[k];
             }
-            so[o] = s[id];
+            so[o] = p.s[k];
+            ++o;
         }
         run += tot;
     }
@@ -737,10 +868,10 @@ static void launch_step(const Geo& g, uint32_t step, const int32_t* cs, const ui
     MT* M = static_cast<MT*>(p->M);
     MT* My = static_cast<MT*>(p->My);
     long long* d_n = reinterpret_cast<long long*>(p->d_n);
-    hipLaunchKernelGGL((step_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, step, cs, n0, thr, x,
-                       y, p->s, d_n, stats, w);
-    hipLaunchKernelGGL(step_scan, dim3(1), dim3(PT), 0, s, d_n, (long long)p->capacity, stats, st, w);
-    hipLaunchKernelGGL((step_apply<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, step, cs, n0, thr,
+    WK_LAUNCH("step_count", (step_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, step, cs, n0, thr, x,
+                       y, M, My, p->s, d_n, stats, w);
+    WK_LAUNCH("step_scan", step_scan, dim3(1), dim3(PT), 0, s, d_n, (long long)p->capacity, stats, st, w);
+    WK_LAUNCH("step_apply", (step_apply<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, step, cs, n0, thr,
                        cdf, x, y, M, My, p->s, stats, w);
 }
 
@@ -752,21 +883,21 @@ static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp
     const MT* M = static_cast<const MT*>(in->M);
     const MT* My = static_cast<const MT*>(in->My);
     const long long* d_n = reinterpret_cast<const long long*>(in->d_n);
-    hipLaunchKernelGGL(fill_i32, dim3(1024), dim3(256), 0, s, hist, 2 * g.n_bins, 0);
-    hipLaunchKernelGGL((annih_hist<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
+    WK_LAUNCH("hist_clear", fill_i32, dim3(1024), dim3(256), 0, s, hist, 2 * g.n_bins, 0);
+    WK_LAUNCH("annih_hist", (annih_hist<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
                        d_n, hist, stats);  // fixed grid: chunk_of() splits the ensemble
-    hipLaunchKernelGGL((annih_keep_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
+    WK_LAUNCH("annih_keep_count", (annih_keep_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
                        in->s, d_n, hist, stats, w);
-    hipLaunchKernelGGL(annih_keep_scan, dim3(1), dim3(PT), 0, s, d_n, w);
-    hipLaunchKernelGGL((annih_keep_write<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
+    WK_LAUNCH("annih_keep_scan", annih_keep_scan, dim3(1), dim3(PT), 0, s, d_n, w);
+    WK_LAUNCH("annih_keep_write", (annih_keep_write<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
                        in->s, hist, static_cast<T*>(out->x), static_cast<T*>(out->y),
                        static_cast<MT*>(out->M), static_cast<MT*>(out->My), out->s, stats, w);
     BinCount bc{nullptr, hist, g.n_bins};
-    hipLaunchKernelGGL(bins_reduce, dim3(PB), dim3(PT), 0, s, bc, stats, w);
-    hipLaunchKernelGGL(bins_scan, dim3(1), dim3(PT), 0, s, 1,
+    WK_LAUNCH("bins_reduce", bins_reduce, dim3(PB), dim3(PT), 0, s, bc, stats, w);
+    WK_LAUNCH("bins_scan", bins_scan, dim3(1), dim3(PT), 0, s, 1,
                        reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, stats, w);
-    hipLaunchKernelGGL(bins_downsweep, dim3(PB), dim3(PT), 0, s, bc, 1, w);
-    hipLaunchKernelGGL((bins_place<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, bc, 1, step,
+    WK_LAUNCH("bins_downsweep", bins_downsweep, dim3(PB), dim3(PT), 0, s, bc, 1, w);
+    WK_LAUNCH("bins_place", (bins_place<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, bc, 1, step,
                        (uint32_t)TAG_ANNIH, static_cast<T*>(out->x), static_cast<T*>(out->y),
                        static_cast<MT*>(out->M), static_cast<MT*>(out->My), out->s, w);
 }
@@ -775,11 +906,11 @@ template <typename T, typename MT, int DIM>
 static void launch_init(const Geo& g, const int32_t* counts, sp_particles* out, long long* stats,
                         WS w, hipStream_t s) {
     BinCount bc{counts, nullptr, g.n_bins};
-    hipLaunchKernelGGL(bins_reduce, dim3(PB), dim3(PT), 0, s, bc, stats, w);
-    hipLaunchKernelGGL(bins_scan, dim3(1), dim3(PT), 0, s, 0,
+    WK_LAUNCH("bins_reduce", bins_reduce, dim3(PB), dim3(PT), 0, s, bc, stats, w);
+    WK_LAUNCH("bins_scan", bins_scan, dim3(1), dim3(PT), 0, s, 0,
                        reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, stats, w);
-    hipLaunchKernelGGL(bins_downsweep, dim3(PB), dim3(PT), 0, s, bc, 0, w);
-    hipLaunchKernelGGL((bins_place<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, bc, 0, 0xFFFFFFFFu,
+    WK_LAUNCH("bins_downsweep", bins_downsweep, dim3(PB), dim3(PT), 0, s, bc, 0, w);
+    WK_LAUNCH("bins_place", (bins_place<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, bc, 0, 0xFFFFFFFFu,
                        (uint32_t)TAG_INIT, static_cast<T*>(out->x), static_cast<T*>(out->y),
                        static_cast<MT*>(out->M), static_cast<MT*>(out->My), out->s, w);
 }

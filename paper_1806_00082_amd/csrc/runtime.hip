@@ -1,7 +1,10 @@
 // Library runtime: error reporting, version, device tables.
+#include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
+#include <vector>
 
 #include "wk_internal.h"
 #include "lowp.h"
@@ -74,6 +77,100 @@ const void* sine_table(int n_m, int kind, int Pk, int Pn, hipStream_t stream, in
     return p;
 }
 
+
+// ----------------------------------------------------------------------------- tracing
+// Optional per-kernel timing: when enabled, launches wrapped by trace_begin/trace_end are
+// bracketed by events (from a pool created at enable time) on the launch stream.
+namespace {
+struct TraceRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_trace_mu;
+bool g_trace_on = false;
+std::vector<hipEvent_t> g_pool;
+size_t g_pool_next = 0;
+std::vector<TraceRec> g_recs;
+}  // namespace
+
+int trace_begin(const char* name, hipStream_t s) {
+    if (!g_trace_on) return -1;
+    std::lock_guard<std::mutex> lock(g_trace_mu);
+    if (g_pool_next + 2 > g_pool.size()) return -1;
+    TraceRec r{name, g_pool[g_pool_next], g_pool[g_pool_next + 1]};
+    g_pool_next += 2;
+    (void)hipEventRecord(r.a, s);
+    g_recs.push_back(r);
+    return (int)g_recs.size() - 1;
+}
+
+void trace_end(int h, hipStream_t s) {
+    if (h < 0) return;
+    std::lock_guard<std::mutex> lock(g_trace_mu);
+    (void)hipEventRecord(g_recs[h].b, s);
+}
+
+}  // namespace wk
+
+extern "C" int wk_trace_enable(int32_t max_launches) {
+    using namespace wk;
+    WK_REQUIRE(max_launches > 0, "wk_trace_enable: max_launches must be positive");
+    std::lock_guard<std::mutex> lock(g_trace_mu);
+    while ((int)g_pool.size() < 2 * max_launches) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return fail(WK_EHIP, "wk_trace_enable: hipEventCreate failed");
+        g_pool.push_back(e);
+    }
+    g_pool_next = 0;
+    g_recs.clear();
+    g_trace_on = true;
+    return WK_OK;
+}
+
+extern "C" int wk_trace_disable(void) {
+    using namespace wk;
+    std::lock_guard<std::mutex> lock(g_trace_mu);
+    g_trace_on = false;
+    return WK_OK;
+}
+
+extern "C" int wk_trace_read(const char* name, double* total_ms, int64_t* count) {
+    using namespace wk;
+    WK_REQUIRE(name && total_ms && count, "wk_trace_read: NULL argument");
+    std::lock_guard<std::mutex> lock(g_trace_mu);
+    double t = 0.0;
+    int64_t c = 0;
+    for (const auto& r : g_recs) {
+        if (r.name != name) continue;
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(WK_EHIP, "wk_trace_read: event sync failed");
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+            return fail(WK_EHIP, "wk_trace_read: elapsed time failed");
+        t += ms;
+        ++c;
+    }
+    *total_ms = t;
+    *count = c;
+    return WK_OK;
+}
+
+extern "C" int wk_trace_names(char* buf, size_t len) {
+    using namespace wk;
+    WK_REQUIRE(buf && len > 0, "wk_trace_names: bad buffer");
+    std::lock_guard<std::mutex> lock(g_trace_mu);
+    std::string all;
+    std::map<std::string, int> seen;
+    for (const auto& r : g_recs)
+        if (!seen.count(r.name)) {
+            seen[r.name] = 1;
+            all += r.name + "\n";
+        }
+    std::strncpy(buf, all.c_str(), len - 1);
+    buf[len - 1] = 0;
+    return WK_OK;
+}
+
+namespace wk {
 }  // namespace wk
 
 extern "C" {

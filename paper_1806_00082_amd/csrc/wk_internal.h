@@ -31,6 +31,17 @@ int check_launch(const char* what);
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Optional per-kernel timing (wk_trace_enable): bracket a launch with events on its stream.
+int trace_begin(const char* name, hipStream_t s);
+void trace_end(int handle, hipStream_t s);
+
+#define WK_LAUNCH(NAME, KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                          \
+    do {                                                                                 \
+        const int th_ = ::wk::trace_begin(NAME, STREAM);                                 \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);             \
+        ::wk::trace_end(th_, STREAM);                                                    \
+    } while (0)
+
 // Device sine table for n_m (built on first use, per device, kept for the process).
 // Layout [Pk][Pn]: S[jj][t] = sin(2 pi (jj+1)(t+1) / n_m) for jj, t < P, zero padding.
 // kind 0: double; 1: bf16 hi; 2: bf16 lo; 3: fp16 hi; 4: fp16 lo (hi/lo of the double).
