@@ -428,6 +428,9 @@ int kernel_eval_1d_lowp(const wk_mesh* mesh, const double* V, int B, const int32
     }
     return check_launch("kernel_eval_lowp");
 }
+int kernel_eval_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
+                   double* out, hipStream_t stream);
+
 }  // namespace wk
 
 extern "C" int wk_kernel_eval(const wk_mesh* mesh, const double* V, int32_t B,
@@ -455,7 +458,10 @@ extern "C" int wk_kernel_eval(const wk_mesh* mesh, const double* V, int32_t B,
                                            static_cast<float*>(K_out), wk::as_stream(stream));
         return wk::fail(WK_EINVAL, "wk_kernel_eval: unknown precision");
     }
-    return wk::fail(WK_EINVAL, "wk_kernel_eval: 2-D not supported");
+    WK_REQUIRE(prec == WK_FP64, "wk_kernel_eval: 2-D supports WK_FP64");
+    WK_REQUIRE(layout == WK_FULL, "wk_kernel_eval: 2-D tables are full");
+    return wk::kernel_eval_2d(mesh, V, B, cells, n_cells, static_cast<double*>(K_out),
+                              wk::as_stream(stream));
 }
 
 // ----------------------------------------------------------------------------- adjoint
@@ -609,3 +615,170 @@ extern "C" int wk_kernel_bwd(const wk_mesh* mesh, const double* G, int32_t B, in
                        nx, P, th, tl, dV);
     return check_launch("wk_kernel_bwd");
 }
+
+// ----------------------------------------------------------------------------- d = 2
+// eq.(4) in two dimensions (half weight at |j_a| = P), separated with
+// sin(a_x + a_y) = sin a_x cos a_y + cos a_x sin a_y:
+//   stage 1  T[jy][n]  = sum_jx D[jy][jx] B1[jx][n],  B1 = [w sin(2 pi mx jx/n_m) | w cos(...)]
+//   stage 2  K[my][mx] = c2 sum_k A2[my][k] T'[k][mx], A2 = [w cos(2 pi my jy/n_m) | w sin(...)],
+//            T' = [T_sin ; T_cos] stacked along jy
+// with D[jy][jx] = V(i + j) - V(i - j) formed in LDS from a (2P+1)^2 window of V, and
+// c2 = -1/(hbar n_m^2).  Both stages run on v_mfma_f64_16x16x4; the trig operands depend only
+// on (n_m, lane) and are computed once per workgroup into registers.  Workgroups loop over
+// the requested cells.
+namespace wk {
+
+__device__ __forceinline__ double w_end(int j, int P) { return (j == P || j == -P) ? 0.5 : 1.0; }
+
+template <int P>
+__global__ __launch_bounds__(KE_THREADS) void kernel_eval_2d_f64(
+    const double* __restrict__ V, int nx, int ny, long R, int n_cells,
+    const int32_t* __restrict__ cells, double c2, double* __restrict__ out) {
+    constexpr int J = 2 * P + 1;                       // offsets per axis
+    constexpr int M1 = (J + 15) / 16 * 16;             // stage-1 rows (jy), padded
+    constexpr int K1 = (J + 3) / 4 * 4;                // stage-1 depth (jx), padded
+    constexpr int N1 = (4 * P + 15) / 16 * 16;         // stage-1 columns: 2P sin + 2P cos
+    constexpr int NT1 = N1 / 16, MT1 = M1 / 16;
+    constexpr int M2 = (2 * P + 15) / 16 * 16;         // stage-2 rows (my)
+    constexpr int N2 = M2;                             // stage-2 columns (mx)
+    constexpr int K2 = 2 * K1;                         // stage-2 depth: sin block + cos block
+    constexpr int NT1W = (NT1 + 3) / 4;                // stage-1 column tiles per wave
+    constexpr int T2 = (M2 / 16) * (N2 / 16);          // stage-2 tiles
+    const int n_m = 2 * P;
+
+    __shared__ double Wv[J][J + 1];
+    __shared__ double Ds[M1][K1 + 1];
+    __shared__ double Ts[K2][N2 + 1];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+
+    // trig operands in registers
+    double b1[NT1W][K1 / 4];
+#pragma unroll
+    for (int q = 0; q < NT1W; ++q) {
+        const int nt = wave + 4 * q;
+#pragma unroll
+        for (int ks = 0; ks < K1 / 4; ++ks) {
+            const int jxi = 4 * ks + lk, n = nt * 16 + lr;
+            double v = 0.0;
+            if (nt < NT1 && jxi < J && n < 4 * P) {
+                const int jx = jxi - P;
+                const int mx = (n < 2 * P ? n : n - 2 * P) - P;
+                const double w = w_end(jx, P);
+                v = n < 2 * P ? w * sin_2pi_ratio((long)mx * jx, n_m) : w * cos_2pi_ratio((long)mx * jx, n_m);
+            }
+            b1[q][ks] = v;
+        }
+    }
+    double a2[K2 / 4];
+    const int tile2 = wave;                      // stage-2 tile of this wave (if any)
+    const int tm2 = tile2 / (N2 / 16), tn2 = tile2 % (N2 / 16);
+#pragma unroll
+    for (int ks = 0; ks < K2 / 4; ++ks) {
+        const int k = 4 * ks + lk, my_i = tm2 * 16 + lr;
+        double v = 0.0;
+        if (tile2 < T2 && my_i < 2 * P) {
+            const int my = my_i - P;
+            const int jyi = k < K1 ? k : k - K1;
+            if (jyi < J) {
+                const int jy = jyi - P;
+                const double w = w_end(jy, P);
+                v = k < K1 ? w * cos_2pi_ratio((long)my * jy, n_m) : w * sin_2pi_ratio((long)my * jy, n_m);
+            }
+        }
+        a2[ks] = v;
+    }
+
+    for (long r = blockIdx.x; r < R; r += gridDim.x) {
+        const long b = r / n_cells;
+        const int ci = (int)(r - b * n_cells);
+        int cell = cells ? cells[ci] : ci;
+        const bool bad = cell < 0 || cell >= nx * ny;
+        if (bad) cell = 0;
+        const int cx = cell % nx, cy = cell / nx;
+        const double* Vb = V + b * (long)nx * ny;
+        __syncthreads();  // previous cell's LDS use is over
+        for (int e = threadIdx.x; e < J * J; e += KE_THREADS) {
+            const int ty = e / J, tx = e - ty * J;
+            const int yy = min(max(cy - P + ty, 0), ny - 1), xx = min(max(cx - P + tx, 0), nx - 1);
+            Wv[ty][tx] = Vb[(long)yy * nx + xx];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < M1 * K1; e += KE_THREADS) {
+            const int jyi = e / K1, jxi = e - jyi * K1;
+            double d = 0.0;
+            if (jyi < J && jxi < J) d = Wv[jyi][jxi] - Wv[J - 1 - jyi][J - 1 - jxi];
+            Ds[jyi][jxi] = bad ? __builtin_nan("") : d;
+        }
+        __syncthreads();
+        // stage 1 -> Ts (sin part rows 0..K1-1, cos part rows K1..2K1-1)
+#pragma unroll
+        for (int q = 0; q < NT1W; ++q) {
+            const int nt = wave + 4 * q;
+            if (nt >= NT1) continue;
+#pragma unroll
+            for (int mt = 0; mt < MT1; ++mt) {
+                f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < K1 / 4; ++ks)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Ds[mt * 16 + lr][4 * ks + lk], b1[q][ks],
+                                                             acc, 0, 0, 0);
+                const int n = nt * 16 + lr;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int jyi = mt * 16 + lk + 4 * e;
+                    if (jyi >= K1 || n >= 4 * P) continue;
+                    if (n < 2 * P)
+                        Ts[jyi][n] = acc[e];
+                    else
+                        Ts[K1 + jyi][n - 2 * P] = acc[e];
+                }
+            }
+        }
+        __syncthreads();
+        if (tile2 < T2) {
+            f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < K2 / 4; ++ks) {
+                const int k = 4 * ks + lk, mx_i = tn2 * 16 + lr;
+                const double bv = mx_i < 2 * P ? Ts[k][mx_i] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[ks], bv, acc, 0, 0, 0);
+            }
+            const int mx_i = tn2 * 16 + lr;
+            double* o = out + r * (long)n_m * n_m;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int my_i = tm2 * 16 + lk + 4 * e;
+                if (my_i < 2 * P && mx_i < 2 * P) o[my_i * n_m + mx_i] = c2 * acc[e];
+            }
+        }
+    }
+}
+
+int kernel_eval_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
+                   double* out, hipStream_t stream) {
+    const long R = (long)B * n_cells;
+    if (R == 0) return WK_OK;
+    const double c2 = -1.0 / (mesh->hbar * (double)mesh->n_m * (double)mesh->n_m);
+    const unsigned grid = (unsigned)(R < 4096 ? R : 4096);
+    switch (mesh->n_m) {
+        case 8:
+            WK_LAUNCH("kernel_eval_2d_f64", kernel_eval_2d_f64<4>, dim3(grid), dim3(KE_THREADS), 0, stream,
+                      V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            break;
+        case 16:
+            WK_LAUNCH("kernel_eval_2d_f64", kernel_eval_2d_f64<8>, dim3(grid), dim3(KE_THREADS), 0, stream,
+                      V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            break;
+        case 32:
+            WK_LAUNCH("kernel_eval_2d_f64", kernel_eval_2d_f64<16>, dim3(grid), dim3(KE_THREADS), 0, stream,
+                      V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            break;
+        default:
+            return fail(WK_EINVAL, "wk_kernel_eval: 2-D supports n_m = 8, 16 and 32");
+    }
+    return check_launch("kernel_eval_2d_f64");
+}
+
+}  // namespace wk

@@ -67,6 +67,12 @@ __device__ __forceinline__ double sin_2pi_ratio(long k, long n) {
     return sg * sinpi(2.0 * (double)t / (double)n);
 }
 
+// cos(2 pi k / n) = sin(2 pi (k + n/4) / n) for n divisible by 4, else through cospi.
+__device__ __forceinline__ double cos_2pi_ratio(long k, long n) {
+    if ((n & 3) == 0) return sin_2pi_ratio(k + n / 4, n);
+    return cospi(2.0 * (double)mod_pos(k, n) / (double)n);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, multipliers
 // 0xD2511F53 / 0xCD9E8D57, round keys bumped by 0x9E3779B9 / 0xBB67AE85.
 struct u32x4 {

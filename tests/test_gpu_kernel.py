@@ -118,3 +118,31 @@ def test_gamma_tables_2d(orc):
     g, n0, thr, cdf = ops.gamma_tables(torch.from_numpy(K).to(dev()), n_m, 0.5, dim=2)
     assert np.array_equal(to_np(g), ref[0])
     assert np.array_equal(as_u64(cdf), ref[3])
+
+
+# ----------------------------------------------------------------------------- 2-D
+@pytest.mark.parametrize("n_m,ny,nx,B", [(8, 6, 7, 2), (16, 12, 10, 1)])
+def test_kernel_2d_all_cells(orc, n_m, ny, nx, B):
+    V = np.random.default_rng(n_m).uniform(0, 0.3, (B, ny, nx))
+    ref = orc.kernel_2d(V, n_m, HB)
+    got = to_np(ops.kernel_eval(torch.from_numpy(V).to(dev()), n_m))
+    assert normwise(got.reshape(B, -1), ref.reshape(B, -1)) <= FP64_TOL
+    P = n_m // 2
+    assert np.all(got.reshape(-1, n_m, n_m)[:, P, P] == 0.0)
+
+
+def test_kernel_2d_dot_cells(orc):
+    """The 2-D workload's mesh and table width (256 x 256, 32 x 32 m) on a list of cells
+    around the dot, the mesh edges and corners."""
+    mesh = inputs.Mesh2D(nx=256, ny=256, dx=0.5, n_m=32)
+    V = inputs.gaussian_dot_2d(mesh, 0.2, 4.0, 64.0, 64.0)
+    cells = np.array([128 * 256 + 128, 120 * 256 + 131, 0, 255, 255 * 256, 256 * 256 - 1,
+                      140 * 256 + 100, 128 * 256 + 128], np.int32)
+    ref = orc.kernel_2d(V, 32, HB, cells=cells)
+    got = to_np(ops.kernel_eval(torch.from_numpy(V[None]).to(dev()), 32,
+                                cells=torch.from_numpy(cells).to(dev())))
+    assert normwise(got.reshape(1, -1), ref.reshape(1, -1)) <= FP64_TOL
+    # full domain runs and is odd in m (up to rounding)
+    K = ops.kernel_eval(torch.from_numpy(V[None]).to(dev()), 32).reshape(-1, 32, 32)
+    Kn = K[:, 1:, 1:]
+    assert float((Kn + torch.flip(Kn, dims=(1, 2))).abs().max()) <= 1e-12 * float(K.abs().max())

@@ -1,0 +1,118 @@
+"""Time-loop level checks on the GPU: the occupied-cell kernel refresh gives the same
+trajectory as evaluating every cell; the simulator equals the oracle loop; physics sanity."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import HB, assert_particles_equal, dev, host_tables_to_device, to_np
+from paper_1806_00082_amd import _lib as L
+from paper_1806_00082_amd import inputs, ops
+from paper_1806_00082_amd.sim import Simulator
+
+pytestmark = pytest.mark.gpu
+
+
+def test_occupied_mode_equals_all_cells():
+    """Kernel rows only near occupied cells (refreshed every 8 steps) reproduce, bit for bit,
+    the run with rows for every cell: the paper's 'only where needed' costs nothing in results."""
+    cfg = inputs.config_c2(N0=3e5)
+    a = Simulator(cfg, mode="occupied", refresh_every=8)
+    b = Simulator(cfg, mode="all")
+    for _ in range(60):
+        a.step()
+        b.step()
+    assert a.n_rows < b.n_rows
+    assert_particles_equal(a.a.view(), b.a.view(), "occupied vs all")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_simulator_equals_oracle_loop(orc, prec):
+    """The simulator's kernel rows -> tables -> steps equal the oracle loop fed the same rows."""
+    cfg = inputs.config_c1()
+    sim = Simulator(cfg, mode="all", prec=prec)
+    md = cfg.mesh.as_dict(cfg.dt)
+    K = ops.kernel_eval(torch.from_numpy(cfg.V[None]).to(dev()), cfg.mesh.n_m, prec=prec,
+                        cells=torch.arange(cfg.mesh.nx, dtype=torch.int32, device=dev()), layout="half")
+    Kf = orc.half_to_full(to_np(K).astype(np.float64))
+    g, n0, thr, cdf = orc.gamma_tables(Kf, cfg.dt)
+    cap = sim.capacity
+    hp = orc.sp_init(md, cfg.bin_counts, cap, seed=cfg.seed)
+    slot = np.arange(md["nx"], dtype=np.int32)
+    for s in range(8):
+        hp, _ = orc.sp_step(md, hp, (n0, thr, cdf), slot, step=s, seed=cfg.seed)
+        hp, _, _, _ = orc.sp_annihilate(md, hp, step=s, seed=cfg.seed, capacity=cap)
+        sim.step()
+    assert_particles_equal(sim.a.view(), hp.view(), f"simulator vs oracle ({prec})")
+
+
+def test_2d_simulator_equals_oracle_loop(orc):
+    mesh = inputs.Mesh2D(nx=20, ny=18, dx=0.5, n_m=16, pos_f64=False)
+    V = inputs.gaussian_dot_2d(mesh, 0.2, 1.5, 5.0, 4.5)
+    bc = inputs.packet_bin_counts_2d(mesh, 2e4, 3.0, 4.5, 1.2, inputs.k_for_energy(0.1), 0.0)
+    cfg = inputs.RunConfig("tiny2d", mesh, V, bc, int(bc.sum()), 0.5, 5, seed=4)
+    sim = Simulator(cfg, mode="all")
+    md = mesh.as_dict(cfg.dt)
+    K = to_np(ops.kernel_eval(torch.from_numpy(V[None]).to(dev()), 16,
+                              cells=torch.arange(20 * 18, dtype=torch.int32, device=dev())))
+    g, n0, thr, cdf = orc.gamma_tables(K.reshape(-1, 256), cfg.dt)
+    hp = orc.sp_init(md, bc, sim.capacity, seed=cfg.seed)
+    slot = np.arange(20 * 18, dtype=np.int32)
+    for s in range(5):
+        hp, _ = orc.sp_step(md, hp, (n0, thr, cdf), slot, step=s, seed=cfg.seed)
+        hp, _, _, st = orc.sp_annihilate(md, hp, step=s, seed=cfg.seed, capacity=sim.capacity)
+        sim.step()
+    assert_particles_equal(sim.a.view(), hp.view(), "2-D simulator vs oracle")
+
+
+def test_free_packet_moments_gpu():
+    """V = 0 on the GPU at 1e6 particles: no creation, no annihilation; the mean position moves
+    by t <v> and the variance grows as Var x0 + t^2 Var v (x0 and v independent in eq.(6))."""
+    mesh = inputs.Mesh1D(nx=400, dx=0.5, n_m=80, pos_f64=True)
+    k0 = inputs.k_for_energy(0.1)
+    bc = inputs.packet_bin_counts_1d(mesh, 1e6, 50.0, 10.0, k0)
+    cfg = inputs.RunConfig("free", mesh, np.zeros(mesh.nx), bc, int(bc.sum()), 0.5, 50)
+    sim = Simulator(cfg, mode="all")
+    v0 = sim.a.view()
+    x0, M0 = v0["x"].astype(np.float64), v0["M"].astype(np.float64)
+    steps = 50
+    sim.run(steps)
+    assert int(sim.stats[L.ST_CUM_PAIRS]) == 0
+    v = sim.a.view()
+    assert len(v["x"]) == len(x0)
+    vdt = mesh.vdt(cfg.dt)
+    assert np.array_equal(v["M"], v0["M"])
+    assert abs(v["x"].mean() - (x0.mean() + steps * vdt * M0.mean())) < 1e-9
+    var_ref = x0.var() + (steps * vdt) ** 2 * M0.var() + 2 * steps * vdt * np.cov(x0, M0, bias=True)[0, 1]
+    assert abs(v["x"].var() - var_ref) < 1e-8 * var_ref
+
+
+def test_barrier_reflection_gpu():
+    """1e6-particle packet reflected by the 0.3 eV barrier on the GPU: no bin holds both signs
+    after annihilation, the sign-weighted momentum reverses and the mean position follows the
+    Schrodinger solution (the oracle's physics check, at 10x the particles)."""
+    import schrodinger
+    mesh = inputs.Mesh1D(nx=400, dx=0.5, n_m=80, pos_f64=False)
+    V = inputs.gaussian_barrier_1d(mesh, 0.3, 2.0, 100.0)
+    k0 = inputs.k_for_energy(0.1)
+    bc = inputs.packet_bin_counts_1d(mesh, 1e6, 80.0, 5.0, k0)
+    cfg = inputs.RunConfig("reflect", mesh, V, bc, int(bc.sum()), 0.5, 400)
+    sim = Simulator(cfg, cap_factor=4.0)
+    ref = schrodinger.densities(80.0, 5.0, k0, (0.3, 2.0, 100.0), (100.0, 200.0), 400, 0.5)
+    xc = (np.arange(400) + 0.5) * 0.5
+    nb = ops.n_bins(sim.md)
+    for T, rs in zip((100.0, 200.0), ref):
+        while sim.step_index < int(T / 0.5):
+            sim.step()
+        rho = to_np(sim.density())
+        assert abs((rho * xc).sum() / rho.sum() - (rs * xc).sum() / rs.sum()) < 1.5
+    assert not sim.overflowed()
+    v = sim.a.view()
+    assert np.all(v["s"] != 0)
+    b = (np.floor(v["x"]).astype(np.int64) * sim.md["n_k"] + (v["M"] - sim.md["M_min"]))
+    pos = np.bincount(b[v["s"] > 0], minlength=nb)
+    neg = np.bincount(b[v["s"] < 0], minlength=nb)
+    assert not np.any((pos > 0) & (neg > 0))
+    s = v["s"].astype(np.float64)
+    assert (s * v["M"]).sum() / s.sum() < -0.8 * k0 / mesh.dk

@@ -1,0 +1,51 @@
+"""Physics checks of the oracle's whole time loop against the Schrodinger equation
+(no exact answer exists for the discretized method: tolerances are physics tolerances)."""
+import numpy as np
+
+import schrodinger
+from paper_1806_00082_amd import inputs
+
+HB = inputs.HBAR_EVFS
+
+
+def _run(orc, U, N0, times, x0=80.0, sigma=5.0):
+    mesh = inputs.Mesh1D(nx=400, dx=0.5, n_m=80, pos_f64=False)
+    V = inputs.gaussian_barrier_1d(mesh, U, 2.0, 100.0)
+    k0 = inputs.k_for_energy(0.1)
+    bc = inputs.packet_bin_counts_1d(mesh, N0, x0, sigma, k0)
+    md = mesh.as_dict(0.5)
+    K = orc.kernel_1d(V, mesh.n_m, HB)[0]
+    _, n0, thr, cdf = orc.gamma_tables(K, 0.5)
+    p = orc.sp_init(md, bc, 40 * int(bc.sum()), seed=0)
+    slot = np.arange(mesh.nx, dtype=np.int32)
+    out, t, st = [], 0.0, 0
+    for T in times:
+        while t < T - 1e-9:
+            p, _ = orc.sp_step(md, p, (n0, thr, cdf), slot, step=st, seed=0)
+            p, hp, hm, _ = orc.sp_annihilate(md, p, step=st, seed=0)
+            t += 0.5
+            st += 1
+        v = p.view()
+        s = v["s"].astype(np.float64)
+        rho = (hp.astype(np.float64) - hm.astype(np.float64)).reshape(mesh.nx, -1).sum(1) / bc.sum()
+        out.append((rho, float((s * v["M"]).sum() / s.sum())))
+    ref = schrodinger.densities(x0, sigma, k0, None if U == 0 else (U, 2.0, 100.0), times, mesh.nx, mesh.dx)
+    return out, ref, k0 / mesh.dk
+
+
+def test_free_packet_matches_schrodinger(orc):
+    """V = 0: the signed-particle density follows |psi|^2 of the same Gaussian state."""
+    out, ref, M0 = _run(orc, 0.0, 1e5, (100.0, 200.0))
+    for (rho, _), rs in zip(out, ref):
+        assert np.abs(rho - rs).sum() < 0.03
+
+
+def test_barrier_reflection_tracks_schrodinger(orc):
+    """0.1 eV packet on a 0.3 eV barrier: the packet is reflected (sign-weighted mean momentum
+    reverses) and its mean position follows the Schrodinger solution within 1.5 nm."""
+    times = (100.0, 150.0, 200.0)
+    out, ref, M0 = _run(orc, 0.3, 1e5, times)
+    xc = (np.arange(400) + 0.5) * 0.5
+    for (rho, _), rs in zip(out, ref):
+        assert abs((rho * xc).sum() / rho.sum() - (rs * xc).sum() / rs.sum()) < 1.5
+    assert out[-1][1] < -0.8 * M0
