@@ -148,14 +148,18 @@ class TrainResult:
 
 
 def train_surrogate(V_train: torch.Tensor, n_m: int, N: int, epochs: int, batch: int,
-                    lr: float, hbar: float = HBAR_EVFS, init=None, labels=None,
+                    lr, hbar: float = HBAR_EVFS, init=None, labels=None,
                     seed: int = 0, log=None) -> TrainResult:
     """SGD on the MSE between eq.(5) and the exact eq.(4) half tables (Sec. 3).
 
     V_train: [n_pot][nx] float64 device tensor.  labels: optional precomputed exact half
     tables [n_pot][nx][P] (float64); otherwise each batch's labels are computed on the fly
     with the FP64 kernel contraction.  Batches are drawn by a seeded permutation per epoch.
+    lr: one step size, or (lr_wV, lr_wT, lr_W) per parameter group -- the angle weights wT
+    multiply offsets up to n_m/2 and momenta up to n_m/2 inside the sine, so their gradient
+    is orders of magnitude larger than the others' and they need a much smaller step.
     """
+    lr_V, lr_T, lr_W = (lr, lr, lr) if isinstance(lr, (int, float)) else lr
     dev = V_train.device
     n_pot, nx = V_train.shape
     c = -2.0 / (hbar * n_m)
@@ -190,9 +194,9 @@ def train_surrogate(V_train: torch.Tensor, n_m: int, N: int, epochs: int, batch:
             surrogate_fwd(Vb, n_m, N, wV, wT, W, prec="fp32", hbar=hbar, out=Kh)
             mse_grad(Kh, lab, inv_scale, E=E, loss=loss, ws=mse_ws)
             dwV, dwT, dW, _ = surrogate_bwd(Vb, n_m, N, wV, wT, W, E, hbar=hbar, ws=ws)
-            sgd_update(wV, dwV, lr)
-            sgd_update(wT, dwT, lr)
-            sgd_update(W, dW, lr * c * c)
+            sgd_update(wV, dwV, lr_V)
+            sgd_update(wT, dwT, lr_T)
+            sgd_update(W, dW, lr_W * c * c)
             ep_loss += loss
             nb += 1
             res.steps += 1
@@ -213,3 +217,11 @@ def surrogate_error(V: torch.Tensor, n_m: int, N: int, wV, wT, W, hbar: float = 
     Kh = surrogate_fwd(V, n_m, N, wV, wT, W, prec=prec, hbar=hbar).reshape(B, -1).to(torch.float64)
     err = (Kh - K).abs().amax(dim=1) / K.abs().amax(dim=1).clamp_min(1e-300)
     return float(err.max().item())
+
+
+def surrogate_rms_error(V: torch.Tensor, n_m: int, N: int, wV, wT, W, hbar: float = HBAR_EVFS,
+                        prec: str = "fp32") -> float:
+    """sqrt(mean (Kh - K)^2) / sqrt(mean K^2) over the batch: the quantity SGD minimises."""
+    K = ops.kernel_eval(V, n_m, layout="half", hbar=hbar)
+    Kh = surrogate_fwd(V, n_m, N, wV, wT, W, prec=prec, hbar=hbar).to(torch.float64)
+    return float(((Kh - K) ** 2).mean().sqrt() / (K ** 2).mean().sqrt())
