@@ -36,9 +36,13 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
                "fp32": 157.3}
 
 
-# HBM traffic of the dominant kernel per launch (GB), from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE counter runs (profiles/), or None when not measured for the current kernel.
-TRAFFIC = {}
+# HBM traffic per launch (GB) over the timed steps of this benchmark, from two rocprofv3
+# counter runs (FETCH_SIZE, then WRITE_SIZE) of `bench.py --no-forms --no-cpu --no-trace
+# --copy-calibration`, scaled by what the counters read for a 1 GiB device copy (fetch x2.0,
+# write x1.0).  Taken for the kernels as they are now; an entry is dropped when its kernel
+# changes until the counters are taken again.
+TRAFFIC = {"step_apply": 0.1554, "step_count": 0.0554, "annih_hist": 0.1122,
+           "annih_keep_count": 0.1114, "annih_keep_write": 0.1696, "bins_place": 0.0428}
 
 
 def _events():
@@ -228,6 +232,10 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-trace", action="store_true",
+                    help="skip the traced replica (for counter runs under rocprofv3 --pmc)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with three plain 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -239,8 +247,10 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     h = run_headline(args.steps, args.warmup, traced=False)
-    tr = run_headline(args.steps, args.warmup, traced=True)
-    assert tr["stats"][11:16] == h["stats"][11:16], "traced replica diverged from the timed run"
+    tr = h
+    if not args.no_trace:
+        tr = run_headline(args.steps, args.warmup, traced=True)
+        assert tr["stats"][11:16] == h["stats"][11:16], "traced replica diverged from the timed run"
     forms = {} if args.no_forms else {"kernel_eq4": run_kernel_forms(), "surrogate_eq5": run_surrogate_forms()}
     cpu = None if args.no_cpu else run_cpu_baseline(args.cpu_steps)
     value = h["particle_steps"] / (h["ms"] * 1e-3)
@@ -264,12 +274,18 @@ def main():
         "run": {"n_last": h["n_last"], "pairs_created": h["pairs"], "regenerated": h["regen"],
                 "kernel_rows_evaluated": h["rows"], "wall_s": round(h["wall_s"], 3),
                 "traced_replica_ms_per_step": round(tr["ms"] / args.steps, 4),
-                "kernels": tr["kernels"]},
-        "roofline": tr["roofline"],
+                "kernels": tr.get("kernels")},
+        "roofline": tr.get("roofline"),
         "cpu_baseline": cpu,
         "forms": forms,
     }
     print(json.dumps(line))
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
