@@ -173,6 +173,17 @@ int wk_gamma_tables(const wk_mesh* mesh, const void* K, int32_t k_f64, int32_t l
                     int32_t n_rows, double dt, double* gamma, uint32_t* n0, uint32_t* thr,
                     uint64_t* cdf, void* stream);
 
+/* wk_sampling_guide -- guide table for the CDF search of sp_step (indexed search, Chen and
+ * Asau 1974; an acceleration structure only: sampling results are unchanged):
+ *   guide[r][k] = min{t : cdf[r][t] > floor(k 2^32 / guide_len)}  for k < guide_len,
+ *   guide[r][guide_len] = width - 1.
+ * A draw u then lies in bucket k = floor(u guide_len / 2^32) and its index
+ * min{t : u < cdf[r][t]} in [guide[r][k], guide[r][k+1]].
+ *   cdf   [n_rows][width] uint64 from wk_gamma_tables.
+ *   guide [n_rows][guide_len + 1] uint32 (written). */
+int wk_sampling_guide(const uint64_t* cdf, int32_t n_rows, int32_t width, int32_t guide_len,
+                      uint32_t* guide, void* stream);
+
 /* ------------------------------------------------------------------ particles
  * sp_init -- place the particles of an initial Wigner function given per-bin counts
  * (eq.(6) turned into counts by the caller): for bins in ascending order, count[b]
@@ -197,12 +208,20 @@ int sp_init(const sp_geom* g, const int32_t* bin_counts, sp_particles* out, int6
  * uses counter (id, step, 1 + (k-3)/4, 1), word (k-3) mod 4.
  *   cell_slot [nx*ny] int32: table row of each cell, or -1 for no creation there.
  *   n0, thr, cdf: from wk_gamma_tables.
+ *   guide NULL (plain binary search of the CDF row), or the rows' wk_sampling_guide table
+ *         with guide_len buckets; the particles are the same either way.
+ *   hist  NULL, or [2][n_bins] int32 that receives the signed histogram of rule 1 (H+ then
+ *         H-) of the particles after the step -- the input of the next sp_annihilate,
+ *         which then need not build it (hist_ready = 1).
  * On overflow (n + 2 * pairs > capacity) nothing is written, d_stats[WK_ST_NEEDED] gets
  * the required capacity and the sticky WK_ST_OVERFLOW flag is set; because the random
- * stream is counter-based, re-running the step with a larger buffer is bit-identical. */
+ * stream is counter-based, re-running the step with a larger buffer is bit-identical.
+ * ws: sp_workspace_size() bytes (scratch between the launches of one call; calls sharing a
+ * workspace must not overlap). */
 int sp_step(const sp_geom* g, const int32_t* cell_slot, const uint32_t* n0, const uint32_t* thr,
-            const uint64_t* cdf, sp_particles* p, int64_t step, int64_t* d_stats, void* ws,
-            size_t ws_bytes, void* stream);
+            const uint64_t* cdf, const uint32_t* guide, int32_t guide_len, sp_particles* p,
+            int32_t* hist, int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes,
+            void* stream);
 
 /* sp_annihilate -- rule 2 of Sec. 2.1 on the (cell, momentum) grid, from `in` to `out`:
  * output = the live particles of bins holding one sign only, unchanged and in input
@@ -210,10 +229,14 @@ int sp_step(const sp_geom* g, const int32_t* cell_slot, const uint32_t* n0, cons
  * |H+ - H-| particles of sign sgn(H+ - H-) with the bin's momentum and positions
  * uniform in its cell (Philox counter (bin, step, r/4, 2), word r mod 4 in 1-D;
  * (bin, step, r/2, 2), words 2(r mod 2), 2(r mod 2)+1 for x, y in 2-D).
- *   hist [2][n_bins] int32 (caller-owned, left holding H+ then H- of the input: the
- *   signed histogram of rule 1).  out->capacity must be >= in's count. */
+ *   hist [2][n_bins] int32, caller-owned: with hist_ready = 0 it is rebuilt here from
+ *   `in`; with hist_ready = 1 it must already hold the histogram of `in` (as sp_step
+ *   leaves it).  Either way it is left holding H+ then H- of the input: the signed
+ *   histogram of rule 1.  out->capacity must be >= in's count.  If the output would
+ *   exceed out->capacity nothing is written and the sticky overflow flag is set. */
 int sp_annihilate(const sp_geom* g, const sp_particles* in, sp_particles* out, int32_t* hist,
-                  int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes, void* stream);
+                  int32_t hist_ready, int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes,
+                  void* stream);
 
 /* sp_density -- rule 1 read-out: rho[c] = sum_M (H+ - H-) / N0 (double [nx*ny]) from the
  * histogram sp_annihilate left in `hist`. */

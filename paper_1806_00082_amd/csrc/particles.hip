@@ -3,12 +3,20 @@
 // (sp_init) and the rule-1 read-out (sp_density).
 //
 // Layout: struct-of-arrays in HBM, positions in cell units.  Every pass streams the
-// arrays once or twice with coalesced accesses.  Ordered outputs (appended children,
-// compacted survivors) use a fixed grid of PB workgroups, each owning one contiguous
-// chunk of particle ids: pass 1 counts per chunk, a single workgroup scans the chunk
-// counts, pass 2 re-derives the per-particle counts and scans them inside the workgroup.
-// Output positions therefore depend only on the data, never on scheduling, and there
-// are no floating-point atomics anywhere (integer atomics only for histogram counts).
+// arrays once with coalesced accesses.  Ordered outputs (appended children, compacted
+// survivors) use a fixed grid of PB workgroups, each owning one contiguous chunk of
+// particle ids: a counting pass stores one count per chunk, and every workgroup of the
+// writing pass re-totals those PB counts (from L2) to get its own offset and the capacity
+// check, then scans inside the workgroup.  Particles placed bin by bin (annihilation,
+// initial state) are split into equal ranges of output slots over the placing workgroups,
+// which find their bins through per-chunk counts.  Output positions therefore depend only
+// on the data, never on scheduling, and there are no floating-point atomics anywhere
+// (integer atomics only, for histogram counts).
+//
+// One time step is four launches: step_count (creation counts; clears the histogram),
+// step_apply (children, drift, absorption, and the signed histogram of the result),
+// annih_count (survivors per particle chunk, particles to place per bin chunk) and
+// annih_write (survivors copied in order, regenerated particles placed).
 #include <climits>
 
 #include "wk_internal.h"
@@ -22,46 +30,54 @@ struct Geo {
     int dim, nx, ny, n_m, n_k, M_min, P, fb;
     long width;       // table entries per row (n_m or n_m^2)
     long n_bins;
+    long n_chunks;    // bin chunks of BC bins
+    long gpb;         // bin chunks per bin workgroup (PB bin workgroups)
     double vdt;
     uint64_t seed;
 };
 
-// Workspace (sp_workspace_size): int64 scalars[16] | int64 counts[PB] | int64 offs[PB] |
-// int64 bpart[PB] | int64 boffs[PB] | int32 binoff[n_bins].
-enum { SC_N_OLD = 0, SC_GO = 1, SC_TOTAL = 2, SC_KEPT = 3, SC_NBIN_TOTAL = 4 };
+constexpr int BC = PT;      // bins per bin chunk
+
+// Workspace (sp_workspace_size): int64 scalars[16] | int64 counts[PB] | int64 bpart[PB] |
+// int64 bmixed[PB] | int32 csum[n_chunks] | uint8 occ[n_cells].
+enum { SC_N_OLD = 0 };
 
 struct WS {
     long long* sc;
-    long long* counts;
-    long long* offs;
-    long long* bpart;
-    long long* boffs;
-    int* binoff;
+    long long* counts;  // per particle chunk: pairs (sp_step) or survivors (sp_annihilate)
+    long long* bpart;   // per bin workgroup: particles to place
+    long long* bmixed;  // per bin workgroup: mixed bins
+    int* csum;          // per bin chunk: particles to place
+    uint8_t* occ;
 };
 
-static WS carve(void* ws) {
+static long n_chunks_for(long n_bins) { return (n_bins + BC - 1) / BC; }
+
+static WS carve(void* ws, long n_bins) {
     WS w;
     char* p = static_cast<char*>(ws);
     w.sc = reinterpret_cast<long long*>(p);
     w.counts = w.sc + 16;
-    w.offs = w.counts + PB;
-    w.bpart = w.offs + PB;
-    w.boffs = w.bpart + PB;
-    w.binoff = reinterpret_cast<int*>(w.boffs + PB);
+    w.bpart = w.counts + PB;
+    w.bmixed = w.bpart + PB;
+    w.csum = reinterpret_cast<int*>(w.bmixed + PB);
+    w.occ = reinterpret_cast<uint8_t*>(w.csum + (n_chunks_for(n_bins) + 1) / 2 * 2);
     return w;
 }
 
-static size_t ws_bytes_for(long n_bins) {
-    return sizeof(long long) * (16 + 4 * (size_t)PB) + sizeof(int) * (size_t)(n_bins + 1);
+static size_t ws_bytes_for(long n_bins, long n_cells) {
+    return sizeof(long long) * (16 + 3 * (size_t)PB) +
+           sizeof(int) * (size_t)((n_chunks_for(n_bins) + 1) / 2 * 2) + (size_t)n_cells;
 }
 
 constexpr int IT = 4;          // particles per thread in the streaming passes
 constexpr int TILE = PT * IT;  // particles per workgroup iteration
 
-__device__ __forceinline__ void chunk_of(long n, long* lo, long* hi) {
+// Particle chunk `blk` of PB: a whole number of tiles, the last ones possibly empty.
+__device__ __forceinline__ void chunk_of(long n, long blk, long* lo, long* hi) {
     long chunk = (n + PB - 1) / PB;
     chunk = (chunk + TILE - 1) / TILE * TILE;
-    *lo = (long)blockIdx.x * chunk;
+    *lo = blk * chunk;
     *hi = min(n, *lo + chunk);
     if (*lo > n) *lo = n;
 }
@@ -182,14 +198,24 @@ __device__ __forceinline__ int pairs_of(const Geo& g, uint32_t id, uint32_t step
     }
     const int sl = cell_slot[c];
     if (sl < 0) return 0;
+    const uint32_t base = n0[sl], t = thr[sl];
+    if (base == 0 && t == 0) return 0;  // no pair whatever u0 is: the draw is not needed
     *slot = sl;
     *w = philox(id, step, 0u, TAG_CREATE, g.seed);
-    return (int)n0[sl] + (w->v[0] < thr[sl] ? 1 : 0);
+    return (int)base + (w->v[0] < t ? 1 : 0);
 }
 
-__device__ __forceinline__ int sample_cdf(const uint64_t* __restrict__ T, long width, uint32_t u) {
-    // smallest t with u < T[t]; T is non-decreasing and ends at 2^32 > u
+// Smallest t with u < T[t] (T non-decreasing, ending at 2^32 > u), searched in [lo, hi]:
+// the whole row, or the bucket of u given by the row's guide table (G buckets).
+__device__ __forceinline__ int sample_cdf(const uint64_t* __restrict__ T,
+                                          const uint32_t* __restrict__ guide, int G, long width,
+                                          uint32_t u) {
     long lo = 0, hi = width - 1;
+    if (guide != nullptr) {
+        const uint32_t k = (uint32_t)(((uint64_t)u * (uint32_t)G) >> 32);
+        lo = guide[k];
+        hi = guide[k + 1];
+    }
     while (lo < hi) {
         const long mid = (lo + hi) >> 1;
         if ((uint64_t)u < T[mid])
@@ -209,113 +235,237 @@ __device__ __forceinline__ bool inside(T x, int n) {
     return x >= (T)0 && x < (T)n;
 }
 
+// ----------------------------------------------------------------------------- block utilities
+__device__ __forceinline__ long long wave_incl_scan_ll(long long v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Sum over the block of one int64 per thread (PT threads); the result is valid in every
+// thread.
+__device__ __forceinline__ long long block_sum_ll(long long v, long long* red4) {
+    v = wave_sum_ll(v);
+    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const long long t = red4[0] + red4[1] + red4[2] + red4[3];
+    __syncthreads();
+    return t;
+}
+
+// Block-wide exclusive scan of one int64 per thread (PT threads).
+__device__ __forceinline__ long long block_excl_scan_ll(long long v, long long* total,
+                                                        long long* red4) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long long inc = wave_incl_scan_ll(v);
+    if (lane == 63) red4[w] = inc;
+    __syncthreads();
+    long long base = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (k < w) base += red4[k];
+    *total = red4[0] + red4[1] + red4[2] + red4[3];
+    __syncthreads();
+    return base + inc - v;
+}
+
+// Totals of the per-chunk counts a counting pass left, recomputed by every workgroup of the
+// pass that consumes them (PB values, read from L2): the sum of all of them and the sum of
+// those below `upto`.  Uniform in the block.
+__device__ __forceinline__ void chunk_totals(const long long* v, long upto, long long* total,
+                                             long long* prefix, long long* red4) {
+    long long a = 0, p = 0;
+    for (int k = threadIdx.x; k < PB; k += PT) {
+        const long long x = v[k];
+        a += x;
+        if (k < upto) p += x;
+    }
+    *total = block_sum_ll(a, red4);
+    *prefix = block_sum_ll(p, red4);
+}
+
+// First index i in [0, n) with a[i] > key (a non-decreasing), n if none.
+template <typename V, typename K>
+__device__ __forceinline__ int upper_bound_lds(const V* a, int n, K key) {
+    int l = 0, h = n;
+    while (l < h) {
+        const int mid = (l + h) >> 1;
+        if (a[mid] > key)
+            h = mid;
+        else
+            l = mid + 1;
+    }
+    return l;
+}
+
+// ----------------------------------------------------------------------------- histogram window
+// Signed histogram of rule 1.  Counters are shared by all XCDs, so a global update is a
+// device-coherent atomic; the ensemble is close to bin-ordered (initial placement is
+// bin-major, survivors keep their order, fresh particles are appended bin by bin, children
+// follow their parents' order), so the contiguous chunk a workgroup owns touches a narrow
+// range of bins, with long runs of one bin.  Each workgroup counts into an LDS window of W
+// bins per sign starting a quarter window below the smallest bin of its first tile, one
+// atomic per run of equal (bin, sign) among the 64 lanes of a wave, then adds the non-zero
+// window entries to the global histogram; runs outside the window (rare) go straight to
+// global atomics.
+template <int W>
+struct HistWindow {
+    int* lh;  // [2][W] in LDS
+    long base;
+    int32_t* hist;
+    long n_bins;
+
+    __device__ __forceinline__ void bump(long b, int sg, int cnt) {
+        const long k = b - base;
+        if (k >= 0 && k < W)
+            atomicAdd(&lh[sg * W + k], cnt);
+        else
+            atomicAdd(&hist[sg * n_bins + b], cnt);
+    }
+
+    // one particle per lane (b < 0: none); all 64 lanes of the wave must call it together
+    __device__ __forceinline__ void add_wave(long b, int8_t sv) {
+        const int lane = threadIdx.x & 63;
+        const long long key = b < 0 ? -1LL : 2LL * b + (sv > 0 ? 0 : 1);
+        const long long prev = __shfl_up(key, 1, 64);
+        const bool head = lane == 0 || prev != key;
+        const unsigned long long heads = __ballot(head);
+        if (head && key >= 0) {
+            const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1));
+            const int next = above ? lane + 1 + __builtin_ctzll(above) : 64;
+            bump((long)(key >> 1), (int)(key & 1), next - lane);
+        }
+    }
+
+    // one particle, any lane pattern
+    __device__ __forceinline__ void add_one(long b, int8_t sv) {
+        if (b >= 0) bump(b, sv > 0 ? 0 : 1, 1);
+    }
+
+    // smallest live bin among the block's candidates -> window base (uniform in the block)
+    __device__ void init(long b_min_thread, long* wmin4) {
+        for (int k = threadIdx.x; k < 2 * W; k += PT) lh[k] = 0;
+        long b0 = b_min_thread;
+        for (int o = 32; o > 0; o >>= 1) b0 = min(b0, (long)__shfl_xor(b0, o, 64));
+        if ((threadIdx.x & 63) == 0) wmin4[threadIdx.x >> 6] = b0;
+        __syncthreads();
+        const long m = min(min(wmin4[0], wmin4[1]), min(wmin4[2], wmin4[3]));
+        base = m == LONG_MAX ? 0 : max(0L, m - W / 4);
+    }
+
+    __device__ void flush() {
+        __syncthreads();
+        for (int k = threadIdx.x; k < W; k += PT) {
+            const long b = base + k;
+            if (b >= n_bins) break;
+            if (lh[k]) atomicAdd(&hist[b], lh[k]);
+            if (lh[W + k]) atomicAdd(&hist[n_bins + b], lh[W + k]);
+        }
+    }
+};
+
 // ----------------------------------------------------------------------------- sp_step
+// Pass 1: pairs per particle chunk into counts[].  When `hist` is given it is cleared here,
+// for pass 2 to accumulate into.
 template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int32_t* cell_slot,
                                                  const uint32_t* n0, const uint32_t* thr,
                                                  const T* x, const T* y, const MT* M,
                                                  const MT* My, const int8_t* s,
-                                                 const long long* d_n, const long long* stats,
-                                                 WS w) {
+                                                 const long long* d_n, int32_t* hist,
+                                                 long long* stats, WS w) {
     __shared__ long long red[PT / 64];
+    if (stats[WK_ST_OVERFLOW] != 0) return;
+    if (hist != nullptr) {
+        const long nh = 2 * g.n_bins;
+        for (long k = (long)blockIdx.x * PT + threadIdx.x; k < nh; k += (long)PB * PT) hist[k] = 0;
+    }
+    const long n = (long)*d_n;
     long long cnt = 0;
-    if (stats[WK_ST_OVERFLOW] == 0) {
-        long lo, hi;
-        chunk_of(*d_n, &lo, &hi);
-        for (long t0 = lo; t0 < hi; t0 += TILE) {
-            const long id = t0 + IT * threadIdx.x;
-            Part4<T, DIM> p;
-            load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
+    long lo, hi;
+    chunk_of(n, blockIdx.x, &lo, &hi);
+    for (long t0 = lo; t0 < hi; t0 += TILE) {
+        const long id = t0 + IT * threadIdx.x;
+        Part4<T, DIM> p;
+        load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
 #pragma unroll
-            for (int k = 0; k < IT; ++k) {
-                int slot;
-                u32x4 r;
-                cnt += pairs_of<T, DIM>(g, (uint32_t)(id + k), step, p.x[k], p.y[k], p.s[k],
-                                        cell_slot, n0, thr, &slot, &r);
-            }
+        for (int k = 0; k < IT; ++k) {
+            int slot;
+            u32x4 r;
+            cnt += pairs_of<T, DIM>(g, (uint32_t)(id + k), step, p.x[k], p.y[k], p.s[k], cell_slot,
+                                    n0, thr, &slot, &r);
         }
     }
-    cnt = wave_sum_ll(cnt);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) w.counts[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-// Exclusive scan of PB int64 values by one workgroup of PT threads (PB / PT per thread).
-__device__ void scan_pb(const long long* in, long long* out, long long* total) {
-    __shared__ long long part[PT];
-    constexpr int per = PB / PT;
-    long long loc[per];
-    long long s = 0;
-    for (int k = 0; k < per; ++k) {
-        loc[k] = in[threadIdx.x * per + k];
-        s += loc[k];
-    }
-    part[threadIdx.x] = s;
-    __syncthreads();
+    cnt = block_sum_ll(cnt, red);
     if (threadIdx.x == 0) {
-        long long run = 0;
-        for (int k = 0; k < PT; ++k) {
-            long long v = part[k];
-            part[k] = run;
-            run += v;
+        w.counts[blockIdx.x] = cnt;
+        if (blockIdx.x == 0) {
+            w.sc[SC_N_OLD] = n;
+            stats[WK_ST_ABS_X] = 0;
+            stats[WK_ST_ABS_M] = 0;
         }
-        *total = run;
-    }
-    __syncthreads();
-    long long run = part[threadIdx.x];
-    for (int k = 0; k < per; ++k) {
-        out[threadIdx.x * per + k] = run;
-        run += loc[k];
     }
 }
 
-__global__ __launch_bounds__(PT) void step_scan(long long* d_n, long long capacity,
-                                                long long* stats, long long step, WS w) {
-    __shared__ long long total;
-    const bool sticky = stats[WK_ST_OVERFLOW] != 0;
-    scan_pb(w.counts, w.offs, &total);
-    if (threadIdx.x != 0) return;
-    if (sticky) {
-        w.sc[SC_GO] = 0;
-        return;
-    }
-    const long long n = *d_n;
-    const long long needed = n + 2 * total;
-    if (needed > capacity) {
-        stats[WK_ST_NEEDED] = needed;
-        stats[WK_ST_OVERFLOW] = 1;
-        stats[WK_ST_OVERFLOW_STEP] = step;
-        w.sc[SC_GO] = 0;
-        return;
-    }
-    w.sc[SC_N_OLD] = n;
-    w.sc[SC_GO] = 1;
-    stats[WK_ST_N] = needed;
-    stats[WK_ST_PAIRS] = total;
-    stats[WK_ST_CUM_STEPS] += 1;
-    stats[WK_ST_CUM_N] += n;
-    stats[WK_ST_CUM_PAIRS] += total;
-    stats[WK_ST_ABS_X] = 0;
-    stats[WK_ST_ABS_M] = 0;
-    stats[WK_ST_NEEDED] = 0;
-    *d_n = needed;
-}
+// Pass 2: every workgroup totals the chunk counts (capacity check, its own offset), then
+// writes the children at their ordered slots, drifts every particle, absorbs, and (HIST)
+// accumulates the signed histogram of the resulting ensemble.
+constexpr int HW_STEP = 2048;
 
-template <typename T, typename MT, int DIM>
+template <typename T, typename MT, int DIM, bool HIST>
 __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int32_t* cell_slot,
                                                  const uint32_t* n0, const uint32_t* thr,
-                                                 const uint64_t* cdf, T* x, T* y, MT* M, MT* My,
-                                                 int8_t* s, long long* stats, WS w) {
+                                                 const uint64_t* cdf, const uint32_t* guide,
+                                                 int guide_len, T* x, T* y, MT* M, MT* My,
+                                                 int8_t* s, long long* d_n, long long capacity,
+                                                 int32_t* hist, long long* stats, long long st,
+                                                 WS w) {
     __shared__ int lds5[5];
-    __shared__ long long red[2][PT / 64];
-    if (w.sc[SC_GO] == 0) return;
+    __shared__ long long red[PT / 64];
+    __shared__ long wmin[PT / 64];
+    __shared__ int lh[HIST ? 2 * HW_STEP : 1];
+    if (stats[WK_ST_OVERFLOW] != 0) return;
     const long n = (long)w.sc[SC_N_OLD];
+    long long total, run;
+    chunk_totals(w.counts, blockIdx.x, &total, &run, red);
+    const long long needed = n + 2 * total;
+    if (needed > capacity) {  // the same decision in every workgroup
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            stats[WK_ST_NEEDED] = needed;
+            stats[WK_ST_OVERFLOW] = 1;
+            stats[WK_ST_OVERFLOW_STEP] = st;
+        }
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        stats[WK_ST_N] = needed;
+        stats[WK_ST_PAIRS] = total;
+        stats[WK_ST_NEEDED] = 0;
+        stats[WK_ST_CUM_STEPS] += 1;
+        stats[WK_ST_CUM_N] += n;
+        stats[WK_ST_CUM_PAIRS] += total;
+        *d_n = needed;
+    }
     long lo, hi;
-    chunk_of(n, &lo, &hi);
-    long long run = w.offs[blockIdx.x];
+    chunk_of(n, blockIdx.x, &lo, &hi);
     const T vdt = (T)g.vdt;
     long long abs_x = 0, abs_m = 0;
+    HistWindow<HW_STEP> hw{lh, 0, hist, g.n_bins};
+    if (HIST) {
+        long b0 = LONG_MAX;
+        Part4<T, DIM> p;
+        load4<T, MT, DIM>(x, y, M, My, s, lo + IT * threadIdx.x, hi, p);
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const long b = bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]);
+            if (b >= 0) b0 = min(b0, b);
+        }
+        hw.init(b0, wmin);
+    }
     auto absorbed = [&](T nx_, T ny_, int m, int my) -> int {
         bool outx = !inside<T>(nx_, g.nx);
         if (DIM == 2) outx = outx || !inside<T>(ny_, g.ny);
@@ -351,7 +501,9 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
                     const int wq = (q - 3) & 3;
                     u = wq == 0 ? r2.v[0] : (wq == 1 ? r2.v[1] : (wq == 2 ? r2.v[2] : r2.v[3]));
                 }
-                const int t = sample_cdf(cdf + (long)slot[k] * g.width, g.width, u);
+                const int t = sample_cdf(cdf + (long)slot[k] * g.width,
+                                         guide ? guide + (long)slot[k] * (guide_len + 1) : nullptr,
+                                         guide_len, g.width, u);
                 const int mx = (DIM == 1 ? t : t % g.n_m) - g.P;
                 const int my = DIM == 1 ? 0 : t / g.n_m - g.P;
 #pragma unroll
@@ -363,13 +515,17 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
                     const int a = absorbed(cx, cy, cm, cmy);
                     abs_x += a == 1;
                     abs_m += a == 2;
-                    x[o] = cx;
-                    M[o] = (MT)cm;
-                    if (DIM == 2) {
-                        y[o] = cy;
-                        My[o] = (MT)cmy;
+                    const int8_t cs = a ? (int8_t)0 : (int8_t)(sg * p.s[k]);
+                    if (o < capacity) {  // always true after the capacity check
+                        x[o] = cx;
+                        M[o] = (MT)cm;
+                        if (DIM == 2) {
+                            y[o] = cy;
+                            My[o] = (MT)cmy;
+                        }
+                        s[o] = cs;
                     }
-                    s[o] = a ? (int8_t)0 : (int8_t)(sg * p.s[k]);
+                    if (HIST) hw.add_one(bin_val<T, DIM>(g, cx, cy, cm, cmy, cs), cs);
                 }
             }
         }
@@ -391,6 +547,7 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
                     sdirty = true;
                 }
             }
+            if (HIST) hw.add_wave(bin_val<T, DIM>(g, nxv[k], nyv[k], p.m[k], p.my[k], p.s[k]), p.s[k]);
         }
         if (id + IT <= hi) {
             st4(x, id, nxv);
@@ -409,18 +566,12 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
         }
         run += tot;
     }
-    abs_x = wave_sum_ll(abs_x);
-    abs_m = wave_sum_ll(abs_m);
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = abs_x;
-        red[1][threadIdx.x >> 6] = abs_m;
-    }
-    __syncthreads();
+    if (HIST) hw.flush();
+    abs_x = block_sum_ll(abs_x, red);
+    abs_m = block_sum_ll(abs_m, red);
     if (threadIdx.x == 0) {
-        const long long ax = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-        const long long am = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-        if (ax) atomicAdd(reinterpret_cast<unsigned long long*>(&stats[WK_ST_ABS_X]), (unsigned long long)ax);
-        if (am) atomicAdd(reinterpret_cast<unsigned long long*>(&stats[WK_ST_ABS_M]), (unsigned long long)am);
+        if (abs_x) atomicAdd(reinterpret_cast<unsigned long long*>(&stats[WK_ST_ABS_X]), (unsigned long long)abs_x);
+        if (abs_m) atomicAdd(reinterpret_cast<unsigned long long*>(&stats[WK_ST_ABS_M]), (unsigned long long)abs_m);
     }
 }
 
@@ -441,155 +592,8 @@ struct BinCount {
     }
 };
 
-__device__ __forceinline__ void bin_chunk(long n_bins, long* lo, long* hi) {
-    long chunk = (n_bins + PB - 1) / PB;
-    *lo = min(n_bins, (long)blockIdx.x * chunk);
-    *hi = min(n_bins, *lo + chunk);
-}
-
-__global__ __launch_bounds__(PT) void bins_reduce(BinCount bc, const long long* stats, WS w) {
-    __shared__ long long red[2][PT / 64];
-    long long c = 0, mixed = 0;
-    if (stats[WK_ST_OVERFLOW] == 0) {
-        long lo, hi;
-        bin_chunk(bc.n_bins, &lo, &hi);
-        for (long b = lo + threadIdx.x; b < hi; b += PT) {
-            c += bc(b);
-            mixed += bc.mixed(b) ? 1 : 0;
-        }
-    }
-    c = wave_sum_ll(c);
-    mixed = wave_sum_ll(mixed);
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = c;
-        red[1][threadIdx.x >> 6] = mixed;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        w.bpart[blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-        w.counts[blockIdx.x] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-    }
-}
-
-// mode 0 (init): out count = total; mode 1 (annihilation): out count = kept + total.
-__global__ __launch_bounds__(PT) void bins_scan(int mode, long long* d_n_out, long long capacity,
-                                                long long* stats, WS w) {
-    __shared__ long long total;
-    __shared__ long long mixed_total;
-    scan_pb(w.bpart, w.boffs, &total);
-    __syncthreads();
-    {
-        __shared__ long long red[PT / 64];
-        long long m = 0;
-        for (int k = threadIdx.x; k < PB; k += PT) m += w.counts[k];
-        m = wave_sum_ll(m);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-        __syncthreads();
-        if (threadIdx.x == 0) mixed_total = red[0] + red[1] + red[2] + red[3];
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    if (stats[WK_ST_OVERFLOW] != 0) {
-        w.sc[SC_GO] = 0;
-        return;
-    }
-    const long long base = mode == 0 ? 0 : w.sc[SC_KEPT];
-    const long long n_out = base + total;
-    if (n_out > capacity) {
-        stats[WK_ST_NEEDED] = n_out;
-        stats[WK_ST_OVERFLOW] = 1;
-        w.sc[SC_GO] = 0;
-        return;
-    }
-    w.sc[SC_GO] = 1;
-    w.sc[SC_NBIN_TOTAL] = total;
-    stats[WK_ST_N] = n_out;
-    if (mode == 1) {
-        stats[WK_ST_KEPT] = base;
-        stats[WK_ST_REGEN] = total;
-        stats[WK_ST_MIXED] = mixed_total;
-        stats[WK_ST_CUM_ANNIH_IN] += w.sc[SC_N_OLD];
-        stats[WK_ST_CUM_KEPT] += base;
-        stats[WK_ST_CUM_REGEN] += total;
-    } else {
-        stats[WK_ST_NEEDED] = 0;
-    }
-    *d_n_out = n_out;
-}
-
-__global__ __launch_bounds__(PT) void bins_downsweep(BinCount bc, int mode, WS w) {
-    __shared__ int lds5[5];
-    if (w.sc[SC_GO] == 0) return;
-    long lo, hi;
-    bin_chunk(bc.n_bins, &lo, &hi);
-    long long run = w.boffs[blockIdx.x] + (mode == 0 ? 0 : w.sc[SC_KEPT]);
-    for (long base = lo; base < hi; base += PT) {
-        const long b = base + threadIdx.x;
-        const int c = b < hi ? (int)bc(b) : 0;
-        int tot;
-        const int ex = block_excl_scan_256(c, &tot, lds5);
-        if (b < hi) w.binoff[b] = (int)(run + ex);
-        run += tot;
-    }
-}
-
-// Particle slot o of the bin range -> its bin: the largest b in [lo, hi) with binoff[b] <= o.
-__device__ __forceinline__ long find_bin(const int* binoff, long lo, long hi, long o) {
-    while (lo < hi) {
-        const long mid = (lo + hi) >> 1;
-        if ((long)binoff[mid] <= o)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo - 1;
-}
-
-// Each workgroup fills a contiguous range of output slots; the bins covering the range are
-// bracketed once per workgroup, so each slot searches only a few bins.
-template <typename T, typename MT, int DIM>
-__global__ __launch_bounds__(PT) void bins_place(Geo g, BinCount bc, int mode, uint32_t c1,
-                                                 uint32_t tag, T* x, T* y, MT* M, MT* My,
-                                                 int8_t* s, WS w) {
-    __shared__ long brange[2];
-    if (w.sc[SC_GO] == 0) return;
-    const long base = mode == 0 ? 0 : (long)w.sc[SC_KEPT];
-    const long total = (long)w.sc[SC_NBIN_TOTAL];
-    const long chunk = (total + gridDim.x - 1) / gridDim.x;
-    const long k_lo = min(total, (long)blockIdx.x * chunk), k_hi = min(total, k_lo + chunk);
-    if (k_lo >= k_hi) return;
-    if (threadIdx.x == 0) {
-        brange[0] = find_bin(w.binoff, 0, g.n_bins, base + k_lo);
-        brange[1] = find_bin(w.binoff, 0, g.n_bins, base + k_hi - 1) + 1;
-    }
-    __syncthreads();
-    const long blo = brange[0], bhi = brange[1];
-    for (long k = k_lo + threadIdx.x; k < k_hi; k += PT) {
-        const long o = base + k;
-        const long b = find_bin(w.binoff, blo, bhi, o);
-        const long r = o - w.binoff[b];
-        int8_t sign = 1;
-        if (mode == 1) sign = bc.hist[b] > bc.hist[g.n_bins + b] ? 1 : -1;
-        if (DIM == 1) {
-            const int cx = (int)(b / g.n_k), kx = (int)(b % g.n_k);
-            const u32x4 u = philox((uint32_t)b, c1, (uint32_t)(r >> 2), tag, g.seed);
-            const int wq = (int)(r & 3);
-            const uint32_t uw = wq == 0 ? u.v[0] : (wq == 1 ? u.v[1] : (wq == 2 ? u.v[2] : u.v[3]));
-            x[o] = cell_plus_frac<T>(cx, uw, g.fb);
-            M[o] = (MT)(g.M_min + kx);
-        } else {
-            const int kx = (int)(b % g.n_k), ky = (int)((b / g.n_k) % g.n_k);
-            const long c = b / ((long)g.n_k * g.n_k);
-            const int cx = (int)(c % g.nx), cy = (int)(c / g.nx);
-            const u32x4 u = philox((uint32_t)b, c1, (uint32_t)(r >> 1), tag, g.seed);
-            const bool odd = (r & 1) != 0;
-            x[o] = cell_plus_frac<T>(cx, odd ? u.v[2] : u.v[0], g.fb);
-            y[o] = cell_plus_frac<T>(cy, odd ? u.v[3] : u.v[1], g.fb);
-            M[o] = (MT)(g.M_min + kx);
-            My[o] = (MT)(g.M_min + ky);
-        }
-        s[o] = sign;
-    }
+__device__ __forceinline__ bool keeps_bin(long b, const int32_t* hist, long n_bins) {
+    return b >= 0 && !(hist[b] > 0 && hist[n_bins + b] > 0);
 }
 
 // ----------------------------------------------------------------------------- annihilation
@@ -598,13 +602,7 @@ __global__ void fill_i32(int32_t* p, long n, int32_t v) {
         p[i] = v;
 }
 
-// Signed histogram of rule 1.  Counters are shared by all XCDs, so every global update is a
-// device-coherent atomic; the ensemble is close to bin-ordered (initial placement is
-// bin-major, survivors keep their order, fresh particles are appended bin by bin), so the
-// contiguous chunk a workgroup owns touches a narrow range of bins.  Each workgroup counts
-// into an LDS window of HW bins starting just below the smallest bin of its first tile,
-// then adds the non-zero window entries to the global histogram; particles outside the
-// window (rare) go straight to global atomics, merged per run of equal keys in a wave.
+// Stand-alone histogram pass (when sp_step did not build it).
 constexpr int HW = 4096;
 
 template <typename T, typename MT, int DIM>
@@ -612,16 +610,14 @@ __global__ __launch_bounds__(PT) void annih_hist(Geo g, const T* x, const T* y, 
                                                  const MT* My, const int8_t* s,
                                                  const long long* d_n, int32_t* hist,
                                                  const long long* stats) {
-    __shared__ int lh[2][HW];
+    __shared__ int lh[2 * HW];
     __shared__ long wmin[PT / 64];
     if (stats[WK_ST_OVERFLOW] != 0) return;
     long lo, hi;
-    chunk_of((long)*d_n, &lo, &hi);
-    const int lane = threadIdx.x & 63;
-    for (int k = threadIdx.x; k < 2 * HW; k += PT) (&lh[0][0])[k] = 0;
-    // window base: smallest bin of the first tile, less a quarter window
-    long b0 = LONG_MAX;
+    chunk_of((long)*d_n, blockIdx.x, &lo, &hi);
+    HistWindow<HW> hw{lh, 0, hist, g.n_bins};
     {
+        long b0 = LONG_MAX;
         Part4<T, DIM> p;
         load4<T, MT, DIM>(x, y, M, My, s, lo + IT * threadIdx.x, hi, p);
 #pragma unroll
@@ -629,124 +625,277 @@ __global__ __launch_bounds__(PT) void annih_hist(Geo g, const T* x, const T* y, 
             const long b = bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]);
             if (b >= 0) b0 = min(b0, b);
         }
+        hw.init(b0, wmin);
     }
-    for (int o = 32; o > 0; o >>= 1) b0 = min(b0, (long)__shfl_xor(b0, o, 64));
-    if (lane == 0) wmin[threadIdx.x >> 6] = b0;
-    __syncthreads();
-    long base = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
-    base = base == LONG_MAX ? 0 : max(0L, base - HW / 4);
     for (long t0 = lo; t0 < hi; t0 += TILE) {
         const long id = t0 + IT * threadIdx.x;
         Part4<T, DIM> p;
         load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
 #pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            uint32_t key = 0xFFFFFFFFu;    // out-of-window key (global path)
-            const long b = bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]);
-            if (b >= 0) {
-                const int sg = p.s[k] > 0 ? 0 : 1;
-                if (b >= base && b < base + HW)
-                    atomicAdd(&lh[sg][b - base], 1);
-                else
-                    key = (uint32_t)(2 * b + sg);
-            }
-            const uint32_t prev = __shfl_up(key, 1, 64);
-            const bool head = lane == 0 || prev != key;
-            const unsigned long long heads = __ballot(head);
-            if (head && key != 0xFFFFFFFFu) {
-                const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1));
-                const int next = above ? lane + 1 + __builtin_ctzll(above) : 64;
-                const long bb = (long)(key >> 1);
-                atomicAdd(&hist[(key & 1u) ? g.n_bins + bb : bb], next - lane);
-            }
-        }
+        for (int k = 0; k < IT; ++k)
+            hw.add_wave(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), p.s[k]);
     }
-    __syncthreads();
-    for (int k = threadIdx.x; k < HW; k += PT) {
-        const long b = base + k;
-        if (b >= g.n_bins) break;
-        if (lh[0][k]) atomicAdd(&hist[b], lh[0][k]);
-        if (lh[1][k]) atomicAdd(&hist[g.n_bins + b], lh[1][k]);
-    }
+    hw.flush();
 }
 
-__device__ __forceinline__ bool keeps_bin(long b, const int32_t* hist, long n_bins) {
-    return b >= 0 && !(hist[b] > 0 && hist[n_bins + b] > 0);
-}
-
+// Counting pass of sp_annihilate (mode 1) and sp_init (mode 0).  Workgroups below
+// part_blocks (PB in mode 1, 0 in mode 0) count the survivors of their particle chunk into
+// counts[]; the PB workgroups after them each own g.gpb consecutive chunks of BC bins and
+// store every chunk's output count in csum[], their sum in bpart[] and their mixed bins in
+// bmixed[].
 template <typename T, typename MT, int DIM>
-__global__ __launch_bounds__(PT) void annih_keep_count(Geo g, const T* x, const T* y,
-                                                       const MT* M, const MT* My, const int8_t* s,
-                                                       const long long* d_n, const int32_t* hist,
-                                                       const long long* stats, WS w) {
+__global__ __launch_bounds__(PT) void annih_count(Geo g, int part_blocks, BinCount bc,
+                                                  const T* x, const T* y, const MT* M,
+                                                  const MT* My, const int8_t* s,
+                                                  const long long* d_n_in, const long long* stats,
+                                                  WS w) {
     __shared__ long long red[PT / 64];
-    long long c = 0;
-    if (stats[WK_ST_OVERFLOW] == 0) {
+    if (stats[WK_ST_OVERFLOW] != 0) return;
+    if ((int)blockIdx.x < part_blocks) {
+        long long a = 0;
         long lo, hi;
-        chunk_of(*d_n, &lo, &hi);
+        chunk_of(*d_n_in, blockIdx.x, &lo, &hi);
         for (long t0 = lo; t0 < hi; t0 += TILE) {
             const long id = t0 + IT * threadIdx.x;
             Part4<T, DIM> p;
             load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
 #pragma unroll
             for (int k = 0; k < IT; ++k)
-                c += keeps_bin(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), hist,
-                               g.n_bins) ? 1 : 0;
+                a += keeps_bin(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]),
+                               bc.hist, g.n_bins) ? 1 : 0;
         }
+        a = block_sum_ll(a, red);
+        if (threadIdx.x == 0) w.counts[blockIdx.x] = a;
+        return;
     }
-    c = wave_sum_ll(c);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) w.counts[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-__global__ __launch_bounds__(PT) void annih_keep_scan(const long long* d_n_in, WS w) {
-    __shared__ long long total;
-    scan_pb(w.counts, w.offs, &total);
+    const long c = (long)blockIdx.x - part_blocks;
+    const long j0 = min(g.n_chunks, c * g.gpb), j1 = min(g.n_chunks, j0 + g.gpb);
+    long long part = 0, mixed = 0;
+    for (long j = j0; j < j1; ++j) {  // uniform
+        const long b = j * BC + threadIdx.x;
+        long long v = 0;
+        if (b < g.n_bins) {
+            v = bc(b);
+            mixed += bc.mixed(b) ? 1 : 0;
+        }
+        v = block_sum_ll(v, red);
+        if (threadIdx.x == 0) w.csum[j] = (int)v;  // < 2^31 whenever the capacity check passes
+        part += v;
+    }
+    mixed = block_sum_ll(mixed, red);
     if (threadIdx.x == 0) {
-        w.sc[SC_KEPT] = total;
-        w.sc[SC_N_OLD] = *d_n_in;
+        w.bpart[c] = part;
+        w.bmixed[c] = mixed;
     }
 }
 
+// Places the particles of one bin chunk (BC bins, chunk output count cnt_ch starting at
+// output slot ch_start) that fall in the slot range [s_lo, s_hi): the chunk's bin counts and
+// Philox blocks (Q particles per block: 4 draws = 4 positions in 1-D, 2 x (x, y) in 2-D)
+// are scanned in LDS, and each thread fills the particles of one Philox block.
 template <typename T, typename MT, int DIM>
-__global__ __launch_bounds__(PT) void annih_keep_write(Geo g, const T* x, const T* y,
-                                                       const MT* M, const MT* My, const int8_t* s,
-                                                       const int32_t* hist, T* xo, T* yo, MT* Mo,
-                                                       MT* Myo, int8_t* so, const long long* stats,
-                                                       WS w) {
-    __shared__ int lds5[5];
-    if (stats[WK_ST_OVERFLOW] != 0) return;
-    long lo, hi;
-    chunk_of((long)w.sc[SC_N_OLD], &lo, &hi);
-    long long run = w.offs[blockIdx.x];
-    for (long t0 = lo; t0 < hi; t0 += TILE) {
-        const long id = t0 + IT * threadIdx.x;
-        Part4<T, DIM> p;
-        load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
-        bool kp[IT];
-        int kt = 0;
-#pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            kp[k] = keeps_bin(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), hist, g.n_bins);
-            kt += kp[k];
+__device__ void place_chunk(const Geo& g, const BinCount& bc, int mode, uint32_t c1, uint32_t tag,
+                            long ch, long ch_start, long cnt_ch, long s_lo, long s_hi,
+                            long out_base, T* xo, T* yo, MT* Mo, MT* Myo, int8_t* so,
+                            long long capacity, int* bo_ex, int* bo_in, int* q_ex, int* q_in,
+                            int* lds5) {
+    constexpr int Q = DIM == 1 ? 4 : 2;
+    const long b = ch * BC + threadIdx.x;
+    const int cnt = b < g.n_bins ? (int)bc(b) : 0;
+    const int nq = (cnt + Q - 1) / Q;
+    int tc, tq;
+    const int ex = block_excl_scan_256(cnt, &tc, lds5);
+    const int exq = block_excl_scan_256(nq, &tq, lds5);
+    bo_ex[threadIdx.x] = ex;
+    bo_in[threadIdx.x] = ex + cnt;
+    q_ex[threadIdx.x] = exq;
+    q_in[threadIdx.x] = exq + nq;
+    __syncthreads();
+    const int lo_c = (int)(max(s_lo, ch_start) - ch_start);            // slots of this chunk
+    const int hi_c = (int)(min(s_hi, ch_start + cnt_ch) - ch_start);   // to fill: [lo_c, hi_c)
+    const int ja = upper_bound_lds(bo_in, BC, lo_c);
+    const int jb = upper_bound_lds(bo_in, BC, hi_c - 1);
+    const int qa = q_ex[ja] + (lo_c - bo_ex[ja]) / Q;
+    const int qb = q_ex[jb] + (hi_c - 1 - bo_ex[jb]) / Q;
+    for (int q = qa + threadIdx.x; q <= qb; q += PT) {
+        const int j = upper_bound_lds(q_in, BC, q);
+        const int qi = q - q_ex[j];
+        const int r0 = Q * qi;
+        const int nr = min(Q, bo_in[j] - bo_ex[j] - r0);
+        const long bb = ch * BC + j;
+        const int8_t sign = mode == 1 ? (bc.hist[bb] > bc.hist[g.n_bins + bb] ? 1 : -1) : 1;
+        const u32x4 u = philox((uint32_t)bb, c1, (uint32_t)qi, tag, g.seed);
+        int cx, cy = 0, kx, ky = 0;
+        if (DIM == 1) {
+            cx = (int)(bb / g.n_k);
+            kx = (int)(bb % g.n_k);
+        } else {
+            kx = (int)(bb % g.n_k);
+            ky = (int)((bb / g.n_k) % g.n_k);
+            const long cc = bb / ((long)g.n_k * g.n_k);
+            cx = (int)(cc % g.nx);
+            cy = (int)(cc / g.nx);
         }
-        int tot;
-        const int ex = block_excl_scan_256(kt, &tot, lds5);
-        long o = run + ex;
-#pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            if (!kp[k]) continue;
-            xo[o] = p.x[k];
-            Mo[o] = (MT)p.m[k];
-            if (DIM == 2) {
-                yo[o] = p.y[k];
-                Myo[o] = (MT)p.my[k];
+        for (int e = 0; e < nr; ++e) {
+            const int rel = bo_ex[j] + r0 + e;
+            if (rel < lo_c || rel >= hi_c) continue;  // another workgroup's slot
+            const long o = out_base + ch_start + rel;
+            if (o >= capacity) break;  // never taken after the capacity check
+            if (DIM == 1) {
+                const uint32_t ue = e == 0 ? u.v[0] : (e == 1 ? u.v[1] : (e == 2 ? u.v[2] : u.v[3]));
+                xo[o] = cell_plus_frac<T>(cx, ue, g.fb);
+            } else {
+                xo[o] = cell_plus_frac<T>(cx, e ? u.v[2] : u.v[0], g.fb);
+                yo[o] = cell_plus_frac<T>(cy, e ? u.v[3] : u.v[1], g.fb);
+                Myo[o] = (MT)(g.M_min + ky);
             }
-            so[o] = p.s[k];
-            ++o;
+            Mo[o] = (MT)(g.M_min + kx);
+            so[o] = sign;
         }
-        run += tot;
+    }
+    __syncthreads();  // the LDS tables are rewritten for the next chunk
+}
+
+// Writing pass of sp_annihilate (mode 1) and sp_init (mode 0).  Every workgroup first
+// totals the counts of the counting pass (capacity check, offsets).  Workgroups below
+// part_blocks copy their chunk's survivors, in order, to their scanned offsets; the
+// place_blocks after them split the regenerated (or initial) particles into equal ranges
+// of output slots and place the particles of their range bin by bin.
+template <typename T, typename MT, int DIM>
+__global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int place_blocks,
+                                                  BinCount bc, int mode, uint32_t c1,
+                                                  uint32_t tag, const T* x, const T* y,
+                                                  const MT* M, const MT* My, const int8_t* s,
+                                                  const long long* d_n_in, T* xo, T* yo, MT* Mo,
+                                                  MT* Myo, int8_t* so, long long* d_n_out,
+                                                  long long capacity, long long* stats, WS w) {
+    __shared__ int lds5[5];
+    __shared__ long long red[PT / 64];
+    __shared__ long long bp[PB];  // inclusive prefix of bpart (placing workgroups)
+    __shared__ int cs_ex[PT], cs_in[PT];
+    __shared__ int bo_ex[BC], bo_in[BC], q_ex[BC], q_in[BC];
+    if (stats[WK_ST_OVERFLOW] != 0) return;
+    const bool part = (int)blockIdx.x < part_blocks;
+    long long kept = 0, kept_pre = 0;
+    if (part_blocks > 0) chunk_totals(w.counts, blockIdx.x, &kept, &kept_pre, red);
+    long long bin_total;
+    {
+        constexpr int per = PB / PT;
+        long long loc[per], acc = 0;
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            loc[k] = w.bpart[threadIdx.x * per + k];
+            acc += loc[k];
+        }
+        long long run = block_excl_scan_ll(acc, &bin_total, red);
+        if (!part) {
+#pragma unroll
+            for (int k = 0; k < per; ++k) {
+                run += loc[k];
+                bp[threadIdx.x * per + k] = run;
+            }
+        }
+        __syncthreads();  // bp is read across threads below
+    }
+    const long long n_out = kept + bin_total;
+    if (n_out > capacity) {  // the same decision in every workgroup
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            stats[WK_ST_NEEDED] = n_out;
+            stats[WK_ST_OVERFLOW] = 1;
+        }
+        return;
+    }
+    if (blockIdx.x == 0) {
+        long long mx = 0;
+        for (int k = threadIdx.x; k < PB; k += PT) mx += w.bmixed[k];
+        mx = block_sum_ll(mx, red);
+        if (threadIdx.x == 0) {
+            stats[WK_ST_N] = n_out;
+            if (mode == 1) {
+                const long long n_in = *d_n_in;
+                stats[WK_ST_KEPT] = kept;
+                stats[WK_ST_REGEN] = bin_total;
+                stats[WK_ST_MIXED] = mx;
+                stats[WK_ST_CUM_ANNIH_IN] += n_in;
+                stats[WK_ST_CUM_KEPT] += kept;
+                stats[WK_ST_CUM_REGEN] += bin_total;
+            } else {
+                stats[WK_ST_NEEDED] = 0;
+            }
+            *d_n_out = n_out;
+        }
+    }
+    if (part) {
+        long lo, hi;
+        chunk_of((long)*d_n_in, blockIdx.x, &lo, &hi);
+        long long run = kept_pre;
+        for (long t0 = lo; t0 < hi; t0 += TILE) {
+            const long id = t0 + IT * threadIdx.x;
+            Part4<T, DIM> p;
+            load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
+            bool kp[IT];
+            int kt = 0;
+#pragma unroll
+            for (int k = 0; k < IT; ++k) {
+                kp[k] = keeps_bin(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]),
+                                  bc.hist, g.n_bins);
+                kt += kp[k];
+            }
+            int tot;
+            const int ex = block_excl_scan_256(kt, &tot, lds5);
+            long o = run + ex;
+#pragma unroll
+            for (int k = 0; k < IT; ++k) {
+                if (!kp[k]) continue;
+                if (o < capacity) {  // always true after the capacity check
+                    xo[o] = p.x[k];
+                    Mo[o] = (MT)p.m[k];
+                    if (DIM == 2) {
+                        yo[o] = p.y[k];
+                        Myo[o] = (MT)p.my[k];
+                    }
+                    so[o] = p.s[k];
+                }
+                ++o;
+            }
+            run += tot;
+        }
+        return;
+    }
+    // placing workgroup k: output slots [s_lo, s_hi) of the bin-ordered part
+    const long k = (long)blockIdx.x - part_blocks;
+    const long per = (bin_total + place_blocks - 1) / place_blocks;
+    const long s_lo = min((long)bin_total, k * per), s_hi = min((long)bin_total, s_lo + per);
+    if (s_lo >= s_hi) return;
+    const long out_base = (long)kept;
+    for (int c = upper_bound_lds(bp, PB, (long long)s_lo); c < PB; ++c) {  // uniform
+        const long c_start = c ? (long)bp[c - 1] : 0;
+        if (c_start >= s_hi) break;
+        const long j0 = min(g.n_chunks, (long)c * g.gpb), j1 = min(g.n_chunks, j0 + g.gpb);
+        long run = c_start;
+        for (long g0 = j0; g0 < j1; g0 += PT) {  // chunk sums in groups of PT
+            const int cs = g0 + threadIdx.x < j1 ? w.csum[g0 + threadIdx.x] : 0;
+            int tot;
+            const int ex = block_excl_scan_256(cs, &tot, lds5);
+            cs_ex[threadIdx.x] = ex;
+            cs_in[threadIdx.x] = ex + cs;
+            __syncthreads();
+            if (run + tot > s_lo && run < s_hi) {
+                const int ng = (int)min((long)PT, j1 - g0);
+                for (int i = upper_bound_lds(cs_in, ng, (int)max(0L, s_lo - run)); i < ng; ++i) {
+                    const long ch_start = run + cs_ex[i];
+                    if (ch_start >= s_hi) break;
+                    const long cnt_ch = cs_in[i] - cs_ex[i];
+                    if (cnt_ch == 0) continue;
+                    place_chunk<T, MT, DIM>(g, bc, mode, c1, tag, g0 + i, ch_start, cnt_ch, s_lo,
+                                            s_hi, out_base, xo, yo, Mo, Myo, so, capacity, bo_ex,
+                                            bo_in, q_ex, q_in, lds5);
+                }
+            }
+            run += tot;
+            __syncthreads();
+            if (run >= s_hi) break;
+        }
     }
 }
 
@@ -843,6 +992,8 @@ static int make_geo(const sp_geom* gm, Geo* g) {
     g->fb = frac_bits_host(gm->nx > gm->ny ? gm->nx : gm->ny, gm->pos_f64);
     g->width = gm->dim == 1 ? gm->n_m : (long)gm->n_m * gm->n_m;
     g->n_bins = (long)gm->nx * gm->ny * gm->n_k * (gm->dim == 2 ? gm->n_k : 1);
+    g->n_chunks = n_chunks_for(g->n_bins);
+    g->gpb = (g->n_chunks + PB - 1) / PB;
     g->vdt = gm->vdt;
     g->seed = gm->seed;
     WK_REQUIRE(g->n_bins < (1L << 31), "particles: too many bins");
@@ -861,58 +1012,63 @@ static int check_particles(const sp_geom* gm, const sp_particles* p, const char*
 
 template <typename T, typename MT, int DIM>
 static void launch_step(const Geo& g, uint32_t step, const int32_t* cs, const uint32_t* n0,
-                        const uint32_t* thr, const uint64_t* cdf, sp_particles* p,
-                        long long* stats, long long st, WS w, hipStream_t s) {
+                        const uint32_t* thr, const uint64_t* cdf, const uint32_t* guide,
+                        int guide_len, sp_particles* p, int32_t* hist, long long* stats,
+                        long long st, WS w, hipStream_t s) {
     T* x = static_cast<T*>(p->x);
     T* y = static_cast<T*>(p->y);
     MT* M = static_cast<MT*>(p->M);
     MT* My = static_cast<MT*>(p->My);
     long long* d_n = reinterpret_cast<long long*>(p->d_n);
-    WK_LAUNCH("step_count", (step_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, step, cs, n0, thr, x,
-                       y, M, My, p->s, d_n, stats, w);
-    WK_LAUNCH("step_scan", step_scan, dim3(1), dim3(PT), 0, s, d_n, (long long)p->capacity, stats, st, w);
-    WK_LAUNCH("step_apply", (step_apply<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, step, cs, n0, thr,
-                       cdf, x, y, M, My, p->s, stats, w);
+    const long long cap = (long long)p->capacity;
+    WK_LAUNCH("step_count", (step_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, step, cs, n0, thr,
+              x, y, M, My, p->s, d_n, hist, stats, w);
+    if (hist)
+        WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, true>), dim3(PB), dim3(PT), 0, s, g, step, cs,
+                  n0, thr, cdf, guide, guide_len, x, y, M, My, p->s, d_n, cap, hist, stats, st, w);
+    else
+        WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, false>), dim3(PB), dim3(PT), 0, s, g, step, cs,
+                  n0, thr, cdf, guide, guide_len, x, y, M, My, p->s, d_n, cap, hist, stats, st, w);
 }
+
+constexpr int PLACE_BLOCKS = PB;  // workgroups placing regenerated / initial particles
 
 template <typename T, typename MT, int DIM>
 static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp_particles* out,
-                         int32_t* hist, long long* stats, WS w, hipStream_t s) {
+                         int32_t* hist, int hist_ready, long long* stats, WS w, hipStream_t s) {
     const T* x = static_cast<const T*>(in->x);
     const T* y = static_cast<const T*>(in->y);
     const MT* M = static_cast<const MT*>(in->M);
     const MT* My = static_cast<const MT*>(in->My);
     const long long* d_n = reinterpret_cast<const long long*>(in->d_n);
-    WK_LAUNCH("hist_clear", fill_i32, dim3(1024), dim3(256), 0, s, hist, 2 * g.n_bins, 0);
-    WK_LAUNCH("annih_hist", (annih_hist<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
-                       d_n, hist, stats);  // fixed grid: chunk_of() splits the ensemble
-    WK_LAUNCH("annih_keep_count", (annih_keep_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
-                       in->s, d_n, hist, stats, w);
-    WK_LAUNCH("annih_keep_scan", annih_keep_scan, dim3(1), dim3(PT), 0, s, d_n, w);
-    WK_LAUNCH("annih_keep_write", (annih_keep_write<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
-                       in->s, hist, static_cast<T*>(out->x), static_cast<T*>(out->y),
-                       static_cast<MT*>(out->M), static_cast<MT*>(out->My), out->s, stats, w);
-    BinCount bc{nullptr, hist, g.n_bins};
-    WK_LAUNCH("bins_reduce", bins_reduce, dim3(PB), dim3(PT), 0, s, bc, stats, w);
-    WK_LAUNCH("bins_scan", bins_scan, dim3(1), dim3(PT), 0, s, 1,
-                       reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, stats, w);
-    WK_LAUNCH("bins_downsweep", bins_downsweep, dim3(PB), dim3(PT), 0, s, bc, 1, w);
-    WK_LAUNCH("bins_place", (bins_place<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, bc, 1, step,
-                       (uint32_t)TAG_ANNIH, static_cast<T*>(out->x), static_cast<T*>(out->y),
-                       static_cast<MT*>(out->M), static_cast<MT*>(out->My), out->s, w);
+    if (!hist_ready) {
+        WK_LAUNCH("hist_clear", fill_i32, dim3(1024), dim3(256), 0, s, hist, 2 * g.n_bins, 0);
+        WK_LAUNCH("annih_hist", (annih_hist<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
+                  in->s, d_n, hist, stats);
+    }
+    const BinCount bc{nullptr, hist, g.n_bins};
+    WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(2 * PB), dim3(PT), 0, s, g, PB, bc,
+              x, y, M, My, in->s, d_n, stats, w);
+    WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(PB + PLACE_BLOCKS), dim3(PT), 0, s, g,
+              PB, PLACE_BLOCKS, bc, 1, step, (uint32_t)TAG_ANNIH, x, y, M, My, in->s, d_n,
+              static_cast<T*>(out->x), static_cast<T*>(out->y), static_cast<MT*>(out->M),
+              static_cast<MT*>(out->My), out->s, reinterpret_cast<long long*>(out->d_n),
+              (long long)out->capacity, stats, w);
 }
 
 template <typename T, typename MT, int DIM>
 static void launch_init(const Geo& g, const int32_t* counts, sp_particles* out, long long* stats,
                         WS w, hipStream_t s) {
-    BinCount bc{counts, nullptr, g.n_bins};
-    WK_LAUNCH("bins_reduce", bins_reduce, dim3(PB), dim3(PT), 0, s, bc, stats, w);
-    WK_LAUNCH("bins_scan", bins_scan, dim3(1), dim3(PT), 0, s, 0,
-                       reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, stats, w);
-    WK_LAUNCH("bins_downsweep", bins_downsweep, dim3(PB), dim3(PT), 0, s, bc, 0, w);
-    WK_LAUNCH("bins_place", (bins_place<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, bc, 0, 0xFFFFFFFFu,
-                       (uint32_t)TAG_INIT, static_cast<T*>(out->x), static_cast<T*>(out->y),
-                       static_cast<MT*>(out->M), static_cast<MT*>(out->My), out->s, w);
+    const BinCount bc{counts, nullptr, g.n_bins};
+    WK_LAUNCH("init_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, 0, bc,
+              (const T*)nullptr, (const T*)nullptr, (const MT*)nullptr, (const MT*)nullptr,
+              (const int8_t*)nullptr, (const long long*)nullptr, stats, w);
+    WK_LAUNCH("init_write", (annih_write<T, MT, DIM>), dim3(PLACE_BLOCKS), dim3(PT), 0, s, g, 0,
+              PLACE_BLOCKS, bc, 0, 0xFFFFFFFFu, (uint32_t)TAG_INIT, (const T*)nullptr,
+              (const T*)nullptr, (const MT*)nullptr, (const MT*)nullptr, (const int8_t*)nullptr,
+              (const long long*)nullptr, static_cast<T*>(out->x), static_cast<T*>(out->y),
+              static_cast<MT*>(out->M), static_cast<MT*>(out->My), out->s,
+              reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, stats, w);
 }
 
 }  // namespace wk
@@ -922,7 +1078,7 @@ using namespace wk;
 extern "C" size_t sp_workspace_size(const sp_geom* gm) {
     Geo g;
     if (make_geo(gm, &g) != WK_OK) return 0;
-    return ws_bytes_for(g.n_bins);
+    return ws_bytes_for(g.n_bins, (long)g.nx * g.ny);
 }
 
 #define WK_DISPATCH(gm, FN, ...)                                                      \
@@ -948,15 +1104,16 @@ extern "C" int sp_init(const sp_geom* gm, const int32_t* bin_counts, sp_particle
     rc = check_particles(gm, out, "sp_init");
     if (rc) return rc;
     WK_REQUIRE(bin_counts && d_stats, "sp_init: NULL array");
-    WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins), "sp_init: workspace too small");
-    WS w = carve(ws);
+    WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_init: workspace too small");
+    WS w = carve(ws, g.n_bins);
     WK_DISPATCH(gm, launch_init, g, bin_counts, out, reinterpret_cast<long long*>(d_stats), w,
                 as_stream(stream));
     return check_launch("sp_init");
 }
 
 extern "C" int sp_step(const sp_geom* gm, const int32_t* cell_slot, const uint32_t* n0,
-                       const uint32_t* thr, const uint64_t* cdf, sp_particles* p, int64_t step,
+                       const uint32_t* thr, const uint64_t* cdf, const uint32_t* guide,
+                       int32_t guide_len, sp_particles* p, int32_t* hist, int64_t step,
                        int64_t* d_stats, void* ws, size_t ws_bytes, void* stream) {
     Geo g;
     int rc = make_geo(gm, &g);
@@ -965,16 +1122,18 @@ extern "C" int sp_step(const sp_geom* gm, const int32_t* cell_slot, const uint32
     if (rc) return rc;
     WK_REQUIRE(cell_slot && n0 && thr && cdf && d_stats, "sp_step: NULL array");
     WK_REQUIRE(step >= 0 && step < (1LL << 32), "sp_step: step must fit 32 bits");
-    WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins), "sp_step: workspace too small");
-    WS w = carve(ws);
-    WK_DISPATCH(gm, launch_step, g, (uint32_t)step, cell_slot, n0, thr, cdf, p,
+    WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_step: workspace too small");
+    WS w = carve(ws, g.n_bins);
+    WK_REQUIRE(guide == nullptr || (guide_len >= 1 && guide_len <= (1 << 20)),
+               "sp_step: guide_len out of range");
+    WK_DISPATCH(gm, launch_step, g, (uint32_t)step, cell_slot, n0, thr, cdf, guide, guide_len, p, hist,
                 reinterpret_cast<long long*>(d_stats), (long long)step, w, as_stream(stream));
     return check_launch("sp_step");
 }
 
 extern "C" int sp_annihilate(const sp_geom* gm, const sp_particles* in, sp_particles* out,
-                             int32_t* hist, int64_t step, int64_t* d_stats, void* ws,
-                             size_t ws_bytes, void* stream) {
+                             int32_t* hist, int32_t hist_ready, int64_t step, int64_t* d_stats,
+                             void* ws, size_t ws_bytes, void* stream) {
     Geo g;
     int rc = make_geo(gm, &g);
     if (rc) return rc;
@@ -986,9 +1145,9 @@ extern "C" int sp_annihilate(const sp_geom* gm, const sp_particles* in, sp_parti
     WK_REQUIRE(out->capacity >= in->capacity, "sp_annihilate: out capacity below in capacity");
     WK_REQUIRE(hist && d_stats, "sp_annihilate: NULL array");
     WK_REQUIRE(step >= 0 && step < (1LL << 32), "sp_annihilate: step must fit 32 bits");
-    WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins), "sp_annihilate: workspace too small");
-    WS w = carve(ws);
-    WK_DISPATCH(gm, launch_annih, g, (uint32_t)step, in, out, hist,
+    WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_annihilate: workspace too small");
+    WS w = carve(ws, g.n_bins);
+    WK_DISPATCH(gm, launch_annih, g, (uint32_t)step, in, out, hist, (int)(hist_ready != 0),
                 reinterpret_cast<long long*>(d_stats), w, as_stream(stream));
     return check_launch("sp_annihilate");
 }
@@ -1015,9 +1174,9 @@ extern "C" int sp_cells_to_evaluate(const sp_geom* gm, const int32_t* hist, int3
     if (rc) return rc;
     WK_REQUIRE(hist && cell_slot && new_cells && d_count, "sp_cells_to_evaluate: NULL array");
     WK_REQUIRE(margin >= 0, "sp_cells_to_evaluate: negative margin");
-    WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins), "sp_cells_to_evaluate: workspace too small");
+    WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_cells_to_evaluate: workspace too small");
     const long n_cells = (long)g.nx * g.ny;
-    uint8_t* occ = reinterpret_cast<uint8_t*>(carve(ws).binoff);  // n_cells <= n_bins bytes
+    uint8_t* occ = carve(ws, g.n_bins).occ;
     hipStream_t s = as_stream(stream);
     hipLaunchKernelGGL(occupied_kernel, dim3((unsigned)((n_cells * 64 + 255) / 256)), dim3(256), 0, s,
                        hist, n_cells, g.n_bins / n_cells, g.n_bins, occ);

@@ -53,7 +53,40 @@ __global__ void gamma_tables_kernel(const KT* __restrict__ K, int layout, int wi
     }
 }
 
+// Guide table of a CDF row for indexed search (Chen and Asau, 1974): for G buckets of the
+// 32-bit uniforms, guide[k] = min{t : cdf[t] > floor(k 2^32 / G)} (k < G) and guide[G] =
+// width - 1.  A draw u falls in bucket k = floor(u G / 2^32), and min{t : u < cdf[t]} lies in
+// [guide[k], guide[k+1]], so the search visits a handful of entries instead of log2(width).
+// One thread per row, one merge pass over the row.
+__global__ void sampling_guide_kernel(const uint64_t* __restrict__ cdf, int n_rows, int width,
+                                      int G, uint32_t* __restrict__ guide) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const uint64_t* T = cdf + (long)r * width;
+    uint32_t* out = guide + (long)r * (G + 1);
+    int t = 0;
+    for (int k = 0; k < G; ++k) {
+        const uint64_t L = ((uint64_t)k << 32) / (uint64_t)G;
+        while (t < width - 1 && T[t] <= L) ++t;
+        out[k] = (uint32_t)t;
+    }
+    out[G] = (uint32_t)(width - 1);
+}
+
 }  // namespace wk
+
+extern "C" int wk_sampling_guide(const uint64_t* cdf, int32_t n_rows, int32_t width,
+                                 int32_t guide_len, uint32_t* guide, void* stream) {
+    WK_REQUIRE(n_rows >= 0, "wk_sampling_guide: negative row count");
+    WK_REQUIRE(width >= 1, "wk_sampling_guide: width must be positive");
+    WK_REQUIRE(guide_len >= 1 && guide_len <= (1 << 20), "wk_sampling_guide: guide_len out of range");
+    if (n_rows == 0) return WK_OK;
+    WK_REQUIRE(cdf && guide, "wk_sampling_guide: NULL array");
+    dim3 grid((n_rows + 127) / 128), block(128);
+    hipLaunchKernelGGL(wk::sampling_guide_kernel, grid, block, 0, wk::as_stream(stream), cdf, n_rows,
+                       width, guide_len, guide);
+    return wk::check_launch("wk_sampling_guide");
+}
 
 extern "C" int wk_gamma_tables(const wk_mesh* mesh, const void* K, int32_t k_f64, int32_t layout,
                                int32_t n_rows, double dt, double* gamma, uint32_t* n0,

@@ -84,14 +84,15 @@ __device__ __forceinline__ u32x4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t p0lo = 0xD2511F53u * c0, p0hi = __umulhi(0xD2511F53u, c0);
-        const uint32_t p1lo = 0xCD9E8D57u * c2, p1hi = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = p1hi ^ c1 ^ k0;
-        const uint32_t n2 = p0hi ^ c3 ^ k1;
+        // full 32 x 32 -> 64-bit products: one v_mad_u64_u32 each instead of mul_lo + mul_hi
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = p1lo;
+        c1 = (uint32_t)p1;
         c2 = n2;
-        c3 = p0lo;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

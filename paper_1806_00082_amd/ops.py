@@ -167,22 +167,39 @@ def sp_init(mesh: dict, seed: int, bin_counts: torch.Tensor, out: DeviceParticle
             "sp_init")
 
 
+def sampling_guide(cdf: torch.Tensor, guide_len: int, out: torch.Tensor | None = None):
+    """Guide table [rows][guide_len + 1] (int32 holding uint32) of CDF rows [rows][width]."""
+    _need_cuda(cdf)
+    rows, width = cdf.shape
+    if out is None:
+        out = torch.empty((rows, guide_len + 1), dtype=torch.int32, device=cdf.device)
+    L.check(L.lib().wk_sampling_guide(_ptr(cdf), rows, width, guide_len, _ptr(out), _stream()),
+            "wk_sampling_guide")
+    return out
+
+
 def sp_step(mesh: dict, seed: int, cell_slot, n0, thr, cdf, p: DeviceParticles, step: int,
-            stats: torch.Tensor, ws: torch.Tensor):
+            stats: torch.Tensor, ws: torch.Tensor, hist: torch.Tensor | None = None,
+            guide: torch.Tensor | None = None):
+    """hist (optional): receives the signed histogram of the ensemble after the step.
+    guide (optional): sampling_guide() of the cdf rows, [rows][G + 1]."""
     g = geom_struct(mesh, seed)
     ps = p.struct()
+    glen = 0 if guide is None else guide.shape[1] - 1
     L.check(L.lib().sp_step(ctypes.byref(g), _ptr(cell_slot), _ptr(n0), _ptr(thr), _ptr(cdf),
-                            ctypes.byref(ps), step, _ptr(stats), _ptr(ws), ws.numel(), _stream()),
-            "sp_step")
+                            _ptr(guide), glen, ctypes.byref(ps), _ptr(hist), step, _ptr(stats),
+                            _ptr(ws), ws.numel(), _stream()), "sp_step")
 
 
 def sp_annihilate(mesh: dict, seed: int, pin: DeviceParticles, pout: DeviceParticles,
-                  hist: torch.Tensor, step: int, stats: torch.Tensor, ws: torch.Tensor):
+                  hist: torch.Tensor, step: int, stats: torch.Tensor, ws: torch.Tensor,
+                  hist_ready: bool = False):
+    """hist_ready: `hist` already holds the histogram of `pin` (from sp_step)."""
     g = geom_struct(mesh, seed)
     a, b = pin.struct(), pout.struct()
     L.check(L.lib().sp_annihilate(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _ptr(hist),
-                                  step, _ptr(stats), _ptr(ws), ws.numel(), _stream()),
-            "sp_annihilate")
+                                  int(bool(hist_ready)), step, _ptr(stats), _ptr(ws), ws.numel(),
+                                  _stream()), "sp_annihilate")
 
 
 def sp_density(mesh: dict, hist: torch.Tensor, N0: float, rho: torch.Tensor | None = None):

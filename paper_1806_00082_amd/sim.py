@@ -2,9 +2,10 @@
 library's kernels, no computation in Python.
 
 Per step: (every `refresh_every` steps) kernel rows for newly occupied cells -> creation
-tables; sp_step (creation at rate gamma, drift, absorbing boundaries); sp_annihilate (rule 2,
-and the signed histogram of rule 1).  The particle count stays in device memory; the host
-synchronises only to size the occasional kernel-row refresh and to read statistics.
+tables; sp_step (creation at rate gamma, drift, absorbing boundaries, and the signed
+histogram of rule 1 of the result); sp_annihilate (rule 2 on that histogram).  The particle
+count stays in device memory; the host synchronises only to size the occasional kernel-row
+refresh and to read statistics.
 
 Kernel sources (the paper's two steps, Sec. 4): "exact" = eq.(4) on MFMA in FP64 or a reduced
 precision; "surrogate" = the trained network of eq.(5).  Rows are evaluated only for cells
@@ -26,12 +27,13 @@ from . import learn, ops
 class Simulator:
     def __init__(self, cfg, kernel: str = "exact", prec: str = "fp64", mode: str = "occupied",
                  refresh_every: int = 8, cap_factor: float = 3.0, weights=None, N: int = 2,
-                 device="cuda"):
+                 device="cuda", hist_in_step: bool = True):
         self.cfg = cfg
         self.md = cfg.mesh.as_dict(cfg.dt)
         md = self.md
         self.dim = md["dim"]
         self.kernel, self.prec, self.mode = kernel, prec, mode
+        self.hist_in_step = hist_in_step   # sp_step builds the histogram sp_annihilate uses
         self.refresh_every = max(1, int(refresh_every))
         self.N, self.weights = N, weights
         self.seed = cfg.seed
@@ -49,6 +51,8 @@ class Simulator:
         self.n0 = torch.zeros(self.n_cells, dtype=torch.int32, device=self.dev)
         self.thr = torch.zeros(self.n_cells, dtype=torch.int32, device=self.dev)
         self.cdf = torch.zeros((self.n_cells, self.width), dtype=torch.int64, device=self.dev)
+        self.glen = min(self.width, 256)                # guide buckets for the CDF search
+        self.guide = torch.zeros((self.n_cells, self.glen + 1), dtype=torch.int32, device=self.dev)
         kdt = torch.float64 if (kernel == "exact" and prec == "fp64") else torch.float32
         self.Kbuf = torch.empty((self.n_cells, self.row_len), dtype=kdt, device=self.dev)
         self.new_cells = torch.empty(self.n_cells, dtype=torch.int32, device=self.dev)
@@ -97,6 +101,7 @@ class Simulator:
             ctypes.c_void_p(self.gamma.data_ptr() + 8 * r0), ctypes.c_void_p(self.n0.data_ptr() + 4 * r0),
             ctypes.c_void_p(self.thr.data_ptr() + 4 * r0),
             ctypes.c_void_p(self.cdf.data_ptr() + 8 * self.width * r0), ops._stream()), "wk_gamma_tables")
+        ops.sampling_guide(self.cdf[r0:r0 + count], self.glen, out=self.guide[r0:r0 + count])
         self.n_rows += count
 
     def refresh(self) -> int:
@@ -120,8 +125,10 @@ class Simulator:
         if self.mode == "occupied" and s > 0 and s % self.refresh_every == 0:
             self.refresh()
         ops.sp_step(self.md, self.seed, self.cell_slot, self.n0, self.thr, self.cdf, self.a, s,
-                    self.stats, self.ws)
-        ops.sp_annihilate(self.md, self.seed, self.a, self.b, self.hist, s, self.stats, self.ws)
+                    self.stats, self.ws, hist=self.hist if self.hist_in_step else None,
+                    guide=self.guide)
+        ops.sp_annihilate(self.md, self.seed, self.a, self.b, self.hist, s, self.stats, self.ws,
+                          hist_ready=self.hist_in_step)
         self.a, self.b = self.b, self.a
         self.step_index += 1
 

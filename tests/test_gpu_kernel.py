@@ -120,6 +120,33 @@ def test_gamma_tables_2d(orc):
     assert np.array_equal(as_u64(cdf), ref[3])
 
 
+@pytest.mark.parametrize("glen", [1, 7, 80, 256])
+def test_sampling_guide_definition(orc, glen):
+    """guide[k] = min{t : cdf[t] > floor(k 2^32 / G)} (capped at width - 1), guide[G] =
+    width - 1, on rows with zero rates, one positive entry and generic rows."""
+    nx, n_m = 300, 80
+    V = inputs.random_potentials(1, nx, 0.5, seed=21)
+    K = orc.kernel_1d(V, n_m, HB).reshape(-1, n_m)
+    K[5] = 0.0
+    K[6] = 0.0
+    K[6, 17] = 1.0
+    cdf = orc.gamma_tables(K, 0.5)[3]
+    got = as_u32(ops.sampling_guide(torch.from_numpy(cdf.view(np.int64)).to(dev()), glen))
+    L = (np.arange(glen, dtype=np.uint64) << np.uint64(32)) // np.uint64(glen)
+    for r in range(cdf.shape[0]):
+        ref = np.minimum(np.searchsorted(cdf[r], L, side="right"), n_m - 1)
+        assert np.array_equal(got[r, :glen], ref), r
+        assert got[r, glen] == n_m - 1
+    # every uniform's answer lies in its bucket's range
+    u = np.random.default_rng(2).integers(0, 2 ** 32, 4096, dtype=np.uint64)
+    k = (u * np.uint64(glen)) >> np.uint64(32)
+    for r in (0, 6, 150):
+        t = np.searchsorted(cdf[r], u, side="right")
+        if cdf[r, -1] == 0:
+            continue
+        assert np.all(got[r, k] <= t) and np.all(t <= got[r, k + 1])
+
+
 # ----------------------------------------------------------------------------- 2-D
 @pytest.mark.parametrize("n_m,ny,nx,B", [(8, 6, 7, 2), (16, 12, 10, 1)])
 def test_kernel_2d_all_cells(orc, n_m, ny, nx, B):

@@ -61,9 +61,14 @@ def _run_both(orc, cfg, steps, N0_scale=1.0, check_every=1):
     hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev())
     n0, thr, cdf = host_tables_to_device((None,) + tuple(tables))
     slot_d = torch.from_numpy(slot).to(dev())
+    guide = ops.sampling_guide(cdf, min(cdf.shape[1], 256))
     for s in range(steps):
+        # odd steps: the histogram comes out of sp_step; even steps: sp_annihilate builds it.
+        # Steps 2, 3 (mod 4) search the CDF through the guide table.
+        fused = s % 2 == 1
         hp, hst = orc.sp_step(md, hp, tables, slot, step=s, seed=seed)
-        ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, s, st, ws)
+        ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, s, st, ws, hist=hist if fused else None,
+                    guide=guide if s % 4 >= 2 else None)
         gst = to_np(st)
         assert gst[L.ST_OVERFLOW] == 0
         for k in (L.ST_N, L.ST_PAIRS, L.ST_ABS_X, L.ST_ABS_M):
@@ -71,7 +76,11 @@ def _run_both(orc, cfg, steps, N0_scale=1.0, check_every=1):
         if s % check_every == 0:
             assert_particles_equal(a.view(), hp.view(), f"sp_step {s}")
         hp, hh_p, hh_m, hst = orc.sp_annihilate(md, hp, step=s, seed=seed, capacity=cap)
-        ops.sp_annihilate(md, seed, a, b, hist, s, st, ws)
+        if fused:
+            h = to_np(hist)
+            nb = ops.n_bins(md)
+            assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"step hist {s}"
+        ops.sp_annihilate(md, seed, a, b, hist, s, st, ws, hist_ready=fused)
         gst = to_np(st)
         for k in (L.ST_N, L.ST_KEPT, L.ST_REGEN, L.ST_MIXED):
             assert gst[k] == hst[k], (s, k, gst[k], hst[k])
@@ -146,8 +155,11 @@ def test_step_overflow_and_retry(orc):
     assert_particles_equal(big.view(), ref.view(), "retry")
 
 
-def test_many_pairs_per_particle(orc):
-    """gamma dt > 4: pairs beyond the first Philox block (block 1 + (k-3)/4)."""
+@pytest.mark.parametrize("glen", [None, 1, 5, 16, 64])
+def test_many_pairs_per_particle(orc, glen):
+    """gamma dt > 4: pairs beyond the first Philox block (block 1 + (k-3)/4); the CDF searched
+    in full or through guide tables of several bucket counts (including more buckets than
+    entries)."""
     md = {"dim": 1, "nx": 10, "ny": 1, "n_m": 16, "n_k": 32, "M_min": -16, "pos_f64": False,
           "vdt": 0.01}
     rng = np.random.default_rng(5)
@@ -169,7 +181,9 @@ def test_many_pairs_per_particle(orc):
     slot = np.arange(10, dtype=np.int32)
     n0, thr, cdf = host_tables_to_device(tables)
     st = ops.new_stats()
-    ops.sp_step(md, 3, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, 7, st, ops.sp_workspace(md, 3))
+    guide = None if glen is None else ops.sampling_guide(cdf, glen)
+    ops.sp_step(md, 3, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, 7, st, ops.sp_workspace(md, 3),
+                guide=guide)
     ref, rst = orc.sp_step(md, hp, tables[1:], slot, step=7, seed=3)
     assert_particles_equal(a.view(), ref.view(), "many pairs")
     assert to_np(st)[L.ST_PAIRS] == rst[orc.ST_PAIRS]
@@ -215,12 +229,19 @@ def test_2d_step_and_annihilation(orc):
     slot = np.arange(24 * 20, dtype=np.int32)
     n0, thr, cdf = host_tables_to_device(tables)
     slot_d = torch.from_numpy(slot).to(dev())
+    guide = ops.sampling_guide(cdf, 16)
     for s in range(4):
+        fused = s % 2 == 1
         hp, hst = orc.sp_step(md, hp, tables[1:], slot, step=s, seed=seed)
-        ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, s, st, ws)
+        ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, s, st, ws, hist=hist if fused else None,
+                    guide=guide if s >= 2 else None)
         assert_particles_equal(a.view(), hp.view(), f"2-D step {s}")
-        hp, _, _, hst = orc.sp_annihilate(md, hp, step=s, seed=seed, capacity=cap)
-        ops.sp_annihilate(md, seed, a, b, hist, s, st, ws)
+        hp, hh_p, hh_m, hst = orc.sp_annihilate(md, hp, step=s, seed=seed, capacity=cap)
+        if fused:
+            h = to_np(hist)
+            nb = ops.n_bins(md)
+            assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"2-D step hist {s}"
+        ops.sp_annihilate(md, seed, a, b, hist, s, st, ws, hist_ready=fused)
         assert_particles_equal(b.view(), hp.view(), f"2-D annihilate {s}")
         a, b = b, a
     assert hst[orc.ST_MIXED] > 0

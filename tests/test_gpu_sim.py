@@ -27,6 +27,30 @@ def test_occupied_mode_equals_all_cells():
     assert_particles_equal(a.a.view(), b.a.view(), "occupied vs all")
 
 
+def test_full_size_run_repeatable_both_histogram_paths():
+    """The 1e7-particle run, 40 steps, three times: twice with the histogram built inside
+    sp_step and once with sp_annihilate building it.  Every run must give the same ensemble
+    bit for bit (output order is defined by the data alone, not by scheduling)."""
+    cfg = inputs.config_c2()
+    print("full-size repeatability: 3 x 40 steps of 1e7 particles", flush=True)
+    runs = [Simulator(cfg, hist_in_step=True), Simulator(cfg, hist_in_step=True),
+            Simulator(cfg, hist_in_step=False)]
+    for sim in runs:
+        sim.run(40)
+    torch.cuda.synchronize()
+    ref = runs[0]
+    S0 = to_np(ref.stats)
+    assert S0[L.ST_OVERFLOW] == 0 and S0[L.ST_CUM_PAIRS] > 0 and S0[L.ST_CUM_REGEN] > 0
+    n = ref.count()
+    for k, sim in enumerate(runs[1:], 1):
+        S = to_np(sim.stats)
+        assert np.array_equal(S[L.ST_CUM_STEPS:L.ST_COUNT], S0[L.ST_CUM_STEPS:L.ST_COUNT]), k
+        assert sim.count() == n, k
+        for f in ("x", "M", "s"):
+            assert torch.equal(getattr(sim.a, f)[:n], getattr(ref.a, f)[:n]), (k, f)
+        assert torch.equal(sim.hist, ref.hist), k
+
+
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
 def test_simulator_equals_oracle_loop(orc, prec):
     """The simulator's kernel rows -> tables -> steps equal the oracle loop fed the same rows."""
