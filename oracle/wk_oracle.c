@@ -23,6 +23,9 @@
  *   - Annihilation (rule 2) on the (cell, momentum) grid: particles in bins
  *     holding only one sign are kept unchanged, each bin holding both signs
  *     is replaced by |net| particles of the net sign, uniform in the cell.
+ *     Storage order (a convention; the ensemble is a set): the fresh
+ *     particles in ascending bin order first, then the kept ones in input
+ *     order.
  */
 #include "wk_oracle.h"
 
@@ -496,8 +499,23 @@ int64_t oracle_sp_annihilate(int dim, int nx, int ny, int n_k, int M_min, int po
         else
             hm[b]++;
     }
-    int64_t o = 0, rc = 0;
-    /* particles of single-sign bins, unchanged and in input order */
+    int64_t o = 0, rc = 0, mixed = 0;
+    /* mixed bins, ascending: |net| fresh particles of the net sign */
+    for (long b = 0; b < n_bins && rc == 0; ++b) {
+        if (!(hp[b] > 0 && hm[b] > 0)) continue;
+        ++mixed;
+        const long net = (long)hp[b] - (long)hm[b];
+        const long cnt = net < 0 ? -net : net;
+        if (o + cnt > capacity) {
+            rc = -2;
+            break;
+        }
+        for (long r = 0; r < cnt; ++r, ++o)
+            place_in_bin(&g, seed, (uint32_t)step, TAG_ANNIH, b, r, net > 0 ? 1 : -1, o, xo, yo,
+                         Mo, Myo, so);
+    }
+    const int64_t regen = o;
+    /* then the particles of single-sign bins, unchanged and in input order */
     for (int64_t id = 0; id < n && rc == 0; ++id) {
         long b = bin_of(&g, id, x, y, M, My, s);
         if (b < 0 || (hp[b] > 0 && hm[b] > 0)) continue;
@@ -513,28 +531,12 @@ int64_t oracle_sp_annihilate(int dim, int nx, int ny, int n_k, int M_min, int po
         }
         so[o++] = s[id];
     }
-    const int64_t kept = o;
-    int64_t mixed = 0;
-    /* mixed bins, ascending: |net| fresh particles of the net sign */
-    for (long b = 0; b < n_bins && rc == 0; ++b) {
-        if (!(hp[b] > 0 && hm[b] > 0)) continue;
-        ++mixed;
-        const long net = (long)hp[b] - (long)hm[b];
-        const long cnt = net < 0 ? -net : net;
-        if (o + cnt > capacity) {
-            rc = -2;
-            break;
-        }
-        for (long r = 0; r < cnt; ++r, ++o)
-            place_in_bin(&g, seed, (uint32_t)step, TAG_ANNIH, b, r, net > 0 ? 1 : -1, o, xo, yo,
-                         Mo, Myo, so);
-    }
     if (!hist_plus) free(hp);
     if (!hist_minus) free(hm);
     if (rc) return rc;
     stats[ORACLE_ST_N] = o;
-    stats[ORACLE_ST_ANNIH_KEPT] = kept;
-    stats[ORACLE_ST_ANNIH_REGEN] = o - kept;
+    stats[ORACLE_ST_ANNIH_KEPT] = o - regen;
+    stats[ORACLE_ST_ANNIH_REGEN] = regen;
     stats[ORACLE_ST_MIXED] = mixed;
     return o;
 }

@@ -197,7 +197,8 @@ def test_sp_step_creation_statistics(orc):
 
 def test_annihilation_invariants(orc):
     """Rule 2 per (cell, momentum) bin: net sign per bin conserved, no mixed bin left,
-    single-sign particles kept unchanged and in order, fresh particles inside their cell."""
+    fresh particles inside their cell (ascending bins, first in the output), then the
+    single-sign particles unchanged and in input order."""
     rng = np.random.default_rng(2)
     mesh = _mesh1(nx=10, n_m=4)
     n = 3000
@@ -225,14 +226,16 @@ def test_annihilation_invariants(orc):
         assert not ((sg > 0).any() and (sg < 0).any())
     keep = alive & ~mixed[b_in]
     k = keep.sum()
-    assert st[orc.ST_KEPT] == k and st[orc.ST_MIXED] == mixed.sum()
-    assert np.array_equal(v["x"][:k], p.x[:n][keep])
-    assert np.array_equal(v["M"][:k], p.M[:n][keep])
-    assert np.array_equal(v["s"][:k], p.s[:n][keep])
+    r = int(np.abs(net_in[mixed]).sum())
+    assert st[orc.ST_KEPT] == k and st[orc.ST_MIXED] == mixed.sum() and q.n == r + k
+    assert np.array_equal(v["x"][r:], p.x[:n][keep])
+    assert np.array_equal(v["M"][r:], p.M[:n][keep])
+    assert np.array_equal(v["s"][r:], p.s[:n][keep])
     # histogram returned is the input's
     assert np.array_equal(hp - hm, net_in.astype(np.int64))
-    # regenerated: ascending bins, |net| each
-    regen_bins = b_out[k:]
+    # regenerated: ascending bins, |net| each, positions inside their cell
+    regen_bins = b_out[:r]
+    assert np.all(mixed[regen_bins])
     assert np.all(np.diff(regen_bins) >= 0)
     assert np.array_equal(np.bincount(regen_bins, minlength=80)[mixed], np.abs(net_in[mixed]).astype(np.int64))
 
