@@ -38,11 +38,9 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 
 # HBM traffic per launch (GB) over the timed steps of this benchmark, from two rocprofv3
 # counter runs (FETCH_SIZE, then WRITE_SIZE) of `bench.py --no-forms --no-cpu --no-trace
-# --copy-calibration`, scaled by what the counters read for a 1 GiB device copy (fetch x2.0,
-# write x1.0).  Taken for the kernels as they are now; an entry is dropped when its kernel
-# changes until the counters are taken again.
-TRAFFIC = {"step_apply": 0.1554, "step_count": 0.0554, "annih_hist": 0.1122,
-           "annih_keep_count": 0.1114, "annih_keep_write": 0.1696, "bins_place": 0.0428}
+# --copy-calibration`, scaled by what the counters read for a 1 GiB device copy.  Only for
+# kernels unchanged since the counters were taken (none at present: null in the output).
+TRAFFIC = {}
 
 
 def _events():
@@ -52,14 +50,13 @@ def _events():
 
 # Algorithmic HBM bytes per launch of each particle kernel, from the running sums the
 # library keeps (S = stats): what the pass must move at minimum with 9-byte particles
-# (x 4 + M 4 + s 1, FP32 positions).
+# (x 4 + M 4 + s 1, FP32 positions).  The histogram and the tables are L2-resident.
 KERNEL_BYTES = {
     "step_apply": lambda S, L: 13 * S[L.ST_CUM_N] + 18 * S[L.ST_CUM_PAIRS],   # read 9 + write x 4; 2 children
     "step_count": lambda S, L: 5 * S[L.ST_CUM_N],                              # read x 4 + s 1
-    "annih_hist": lambda S, L: 9 * S[L.ST_CUM_ANNIH_IN],                       # read 9
-    "annih_keep_count": lambda S, L: 9 * S[L.ST_CUM_ANNIH_IN],                 # read 9
-    "annih_keep_write": lambda S, L: 9 * S[L.ST_CUM_ANNIH_IN] + 9 * S[L.ST_CUM_KEPT],  # read 9, write kept 9
-    "bins_place": lambda S, L: 9 * S[L.ST_CUM_REGEN],                          # write 9
+    "annih_count": lambda S, L: 9 * S[L.ST_CUM_ANNIH_IN],                      # read 9
+    "annih_write": lambda S, L: (9 * S[L.ST_CUM_ANNIH_IN] + 9 * S[L.ST_CUM_KEPT]
+                                 + 9 * S[L.ST_CUM_REGEN]),                     # read 9, write kept + placed
 }
 
 

@@ -197,12 +197,13 @@ int sp_init(const sp_geom* g, const int32_t* bin_counts, sp_particles* out, int6
             void* ws, size_t ws_bytes, void* stream);
 
 /* sp_step -- one time step dt of postulate II (Sec. 2.1) with absorbing boundaries
- * (Sec. 3), in place:
+ * (Sec. 3), from `in` (n particles) to `out`:
  *   1. each particle (index id < n) in a cell with a table row creates
  *      n0 + [u0 < thr] pairs; pair k draws t_k = min{t : u < cdf[t]}, momentum offset
- *      m' = t_k - P (2-D: (t mod n_m - P, t / n_m - P)), and appends the children
- *      (x, M + m', +s), (x, M - m', -s) at n + 2 * (pairs of lower ids) + 2k, 2k + 1;
- *   2. every particle drifts: x <- fma(M, vdt, x) in the position precision;
+ *      m' = t_k - P (2-D: (t mod n_m - P, t / n_m - P)), and the children
+ *      (x, M + m', +s), (x, M - m', -s) go to out at n + 2 * (pairs of lower ids) + 2k, 2k + 1;
+ *   2. every particle drifts: x <- fma(M, vdt, x) in the position precision; the parent
+ *      goes to out at its own index id;
  *   3. particles leaving [0, nx) (x [0, ny)) or the momentum window get s = 0.
  * Philox counter (id, step, 0, 1) gives u0 and the draws of pairs 0..2; pair k >= 3
  * uses counter (id, step, 1 + (k-3)/4, 1), word (k-3) mod 4.
@@ -210,30 +211,32 @@ int sp_init(const sp_geom* g, const int32_t* bin_counts, sp_particles* out, int6
  *   n0, thr, cdf: from wk_gamma_tables.
  *   guide NULL (plain binary search of the CDF row), or the rows' wk_sampling_guide table
  *         with guide_len buckets; the particles are the same either way.
+ *   in, out  distinct buffers; *out->d_n receives n + 2 * pairs.
  *   hist  NULL, or [2][n_bins] int32 that receives the signed histogram of rule 1 (H+ then
  *         H-) of the particles after the step -- the input of the next sp_annihilate,
  *         which then need not build it (hist_ready = 1).
- * On overflow (n + 2 * pairs > capacity) nothing is written, d_stats[WK_ST_NEEDED] gets
- * the required capacity and the sticky WK_ST_OVERFLOW flag is set; because the random
- * stream is counter-based, re-running the step with a larger buffer is bit-identical.
+ * If out cannot hold n + 2 * pairs particles, d_stats[WK_ST_NEEDED] gets the required
+ * capacity, the sticky WK_ST_OVERFLOW flag is set and `out` is invalid; `in` is never
+ * written, and because the random stream is counter-based, re-running the step into a
+ * larger buffer is bit-identical.
  * ws: sp_workspace_size() bytes (scratch between the launches of one call; calls sharing a
  * workspace must not overlap). */
 int sp_step(const sp_geom* g, const int32_t* cell_slot, const uint32_t* n0, const uint32_t* thr,
-            const uint64_t* cdf, const uint32_t* guide, int32_t guide_len, sp_particles* p,
-            int32_t* hist, int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes,
-            void* stream);
+            const uint64_t* cdf, const uint32_t* guide, int32_t guide_len,
+            const sp_particles* in, sp_particles* out, int32_t* hist, int64_t step,
+            int64_t* d_stats, void* ws, size_t ws_bytes, void* stream);
 
 /* sp_annihilate -- rule 2 of Sec. 2.1 on the (cell, momentum) grid, from `in` to `out`:
- * output = the live particles of bins holding one sign only, unchanged and in input
- * order, followed by, for each bin holding both signs in ascending bin order,
- * |H+ - H-| particles of sign sgn(H+ - H-) with the bin's momentum and positions
- * uniform in its cell (Philox counter (bin, step, r/4, 2), word r mod 4 in 1-D;
- * (bin, step, r/2, 2), words 2(r mod 2), 2(r mod 2)+1 for x, y in 2-D).
+ * output = for each bin holding both signs, in ascending bin order, |H+ - H-| particles of
+ * sign sgn(H+ - H-) with the bin's momentum and positions uniform in its cell (Philox
+ * counter (bin, step, r/4, 2), word r mod 4 in 1-D; (bin, step, r/2, 2), words 2(r mod 2),
+ * 2(r mod 2)+1 for x, y in 2-D), followed by the live particles of bins holding one sign
+ * only, unchanged and in input order.
  *   hist [2][n_bins] int32, caller-owned: with hist_ready = 0 it is rebuilt here from
  *   `in`; with hist_ready = 1 it must already hold the histogram of `in` (as sp_step
  *   leaves it).  Either way it is left holding H+ then H- of the input: the signed
- *   histogram of rule 1.  out->capacity must be >= in's count.  If the output would
- *   exceed out->capacity nothing is written and the sticky overflow flag is set. */
+ *   histogram of rule 1.  If the output would exceed out->capacity, d_stats gets the
+ *   needed size, the sticky overflow flag is set and `out` is invalid (`in` is untouched). */
 int sp_annihilate(const sp_geom* g, const sp_particles* in, sp_particles* out, int32_t* hist,
                   int32_t hist_ready, int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes,
                   void* stream);

@@ -4,19 +4,20 @@
 //
 // Layout: struct-of-arrays in HBM, positions in cell units.  Every pass streams the
 // arrays once with coalesced accesses.  Ordered outputs (appended children, compacted
-// survivors) use a fixed grid of PB workgroups, each owning one contiguous chunk of
-// particle ids: a counting pass stores one count per chunk, and every workgroup of the
-// writing pass re-totals those PB counts (from L2) to get its own offset and the capacity
-// check, then scans inside the workgroup.  Particles placed bin by bin (annihilation,
-// initial state) are split into equal ranges of output slots over the placing workgroups,
-// which find their bins through per-chunk counts.  Output positions therefore depend only
-// on the data, never on scheduling, and there are no floating-point atomics anywhere
-// (integer atomics only, for histogram counts).
+// survivors) use a fixed grid of PB workgroups whose waves each own one contiguous chunk of
+// particle ids: a counting pass stores one count per wave and per workgroup, and every
+// workgroup of the writing pass re-totals the PB workgroup counts (from L2) for its own
+// offset and the capacity check; each wave then walks its chunk with wave-level scans only,
+// no workgroup barriers.  Particles placed bin by bin (annihilation, initial state) are
+// split into equal ranges of output slots over the placing workgroups, which find their
+// bins through per-chunk counts.  Output positions therefore depend only on the data, never
+// on scheduling, and there are no floating-point atomics anywhere (integer atomics only,
+// for histogram counts).
 //
 // One time step is four launches: step_count (creation counts; clears the histogram),
-// step_apply (children, drift, absorption, and the signed histogram of the result),
-// annih_count (survivors per particle chunk, particles to place per bin chunk) and
-// annih_write (survivors copied in order, regenerated particles placed).
+// step_apply (children, drifted parents, absorption, and the signed histogram of the
+// result), annih_count (survivors per wave chunk, particles to place per bin chunk) and
+// annih_write (regenerated particles placed, then the survivors copied in order).
 #include <climits>
 
 #include "wk_internal.h"
@@ -37,14 +38,15 @@ struct Geo {
 };
 
 constexpr int BC = PT;      // bins per bin chunk
+constexpr int WPB = PT / 64;  // waves per workgroup
+constexpr int NW = PB * WPB;  // wave chunks of the ordered passes
 
-// Workspace (sp_workspace_size): int64 scalars[16] | int64 counts[PB] | int64 bpart[PB] |
-// int64 bmixed[PB] | int32 csum[n_chunks] | uint8 occ[n_cells].
-enum { SC_N_OLD = 0 };
-
+// Workspace (sp_workspace_size): int64 scalars[16] | int64 bcnt[PB] | int64 wcnt[NW] |
+// int64 bpart[PB] | int64 bmixed[PB] | int32 csum[n_chunks] | uint8 occ[n_cells].
 struct WS {
     long long* sc;
-    long long* counts;  // per particle chunk: pairs (sp_step) or survivors (sp_annihilate)
+    long long* bcnt;    // per workgroup of a counting pass: its count
+    long long* wcnt;    // per wave of a counting pass: its count
     long long* bpart;   // per bin workgroup: particles to place
     long long* bmixed;  // per bin workgroup: mixed bins
     int* csum;          // per bin chunk: particles to place
@@ -57,8 +59,9 @@ static WS carve(void* ws, long n_bins) {
     WS w;
     char* p = static_cast<char*>(ws);
     w.sc = reinterpret_cast<long long*>(p);
-    w.counts = w.sc + 16;
-    w.bpart = w.counts + PB;
+    w.bcnt = w.sc + 16;
+    w.wcnt = w.bcnt + PB;
+    w.bpart = w.wcnt + NW;
     w.bmixed = w.bpart + PB;
     w.csum = reinterpret_cast<int*>(w.bmixed + PB);
     w.occ = reinterpret_cast<uint8_t*>(w.csum + (n_chunks_for(n_bins) + 1) / 2 * 2);
@@ -66,20 +69,19 @@ static WS carve(void* ws, long n_bins) {
 }
 
 static size_t ws_bytes_for(long n_bins, long n_cells) {
-    return sizeof(long long) * (16 + 3 * (size_t)PB) +
+    return sizeof(long long) * (16 + 3 * (size_t)PB + (size_t)NW) +
            sizeof(int) * (size_t)((n_chunks_for(n_bins) + 1) / 2 * 2) + (size_t)n_cells;
 }
 
-constexpr int IT = 4;          // particles per thread in the streaming passes
-constexpr int TILE = PT * IT;  // particles per workgroup iteration
+constexpr int IT = 4;          // particles per lane in the streaming passes
+constexpr int WT = 64 * IT;    // particles per wave tile
 
-// Particle chunk `blk` of PB: a whole number of tiles, the last ones possibly empty.
-__device__ __forceinline__ void chunk_of(long n, long blk, long* lo, long* hi) {
-    long chunk = (n + PB - 1) / PB;
-    chunk = (chunk + TILE - 1) / TILE * TILE;
-    *lo = blk * chunk;
-    *hi = min(n, *lo + chunk);
-    if (*lo > n) *lo = n;
+// Wave chunk `wv` of NW: a whole number of wave tiles, the last ones possibly empty.
+__device__ __forceinline__ void wave_chunk(long n, long wv, long* lo, long* hi) {
+    long cs = (n + NW - 1) / NW;
+    cs = (cs + WT - 1) / WT * WT;
+    *lo = min(n, wv * cs);
+    *hi = min(n, *lo + cs);
 }
 
 template <typename T>
@@ -149,6 +151,13 @@ __device__ __forceinline__ void st4(double* p, long i, const double* v) {
     *reinterpret_cast<double2*>(p + i + 2) = make_double2(v[2], v[3]);
 }
 
+__device__ __forceinline__ void st4(int32_t* p, long i, const int* v) {
+    *reinterpret_cast<int4*>(p + i) = make_int4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st4(int16_t* p, long i, const int* v) {
+    *reinterpret_cast<short4*>(p + i) = make_short4((short)v[0], (short)v[1], (short)v[2], (short)v[3]);
+}
+
 template <typename T, typename MT, int DIM>
 __device__ __forceinline__ void load4(const T* x, const T* y, const MT* M, const MT* My,
                                       const int8_t* s, long id, long hi, Part4<T, DIM>& p) {
@@ -180,6 +189,62 @@ __device__ __forceinline__ void load4(const T* x, const T* y, const MT* M, const
     }
 }
 
+// Stores four consecutive particles (positions xv, yv; momenta and signs from p); slots at
+// or beyond hi are left alone.
+template <typename T, typename MT, int DIM>
+__device__ __forceinline__ void store4(T* x, T* y, MT* M, MT* My, int8_t* s, long id, long hi,
+                                       const T* xv, const T* yv, const Part4<T, DIM>& p) {
+    if (id + IT <= hi) {
+        st4(x, id, xv);
+        st4(M, id, p.m);
+        *reinterpret_cast<char4*>(s + id) = make_char4(p.s[0], p.s[1], p.s[2], p.s[3]);
+        if (DIM == 2) {
+            st4(y, id, yv);
+            st4(My, id, p.my);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            if (id + k < hi) {
+                x[id + k] = xv[k];
+                M[id + k] = (MT)p.m[k];
+                s[id + k] = p.s[k];
+                if (DIM == 2) {
+                    y[id + k] = yv[k];
+                    My[id + k] = (MT)p.my[k];
+                }
+            }
+        }
+    }
+}
+
+// Pair counts of four consecutive particles kept between the two passes of sp_step in the
+// first four bytes of each particle's slot of the output positions (unused until the second
+// pass writes the particle there).
+template <typename T>
+__device__ __forceinline__ void store_np4(T* xo, long id, long hi, const int* np) {
+    if (sizeof(T) == 4 && id + IT <= hi) {
+        *reinterpret_cast<int4*>(xo + id) = make_int4(np[0], np[1], np[2], np[3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < IT; ++k)
+            if (id + k < hi) *reinterpret_cast<int*>(xo + id + k) = np[k];
+    }
+}
+template <typename T>
+__device__ __forceinline__ void load_np4(const T* xo, long id, long hi, int* np) {
+    if (sizeof(T) == 4 && id + IT <= hi) {
+        const int4 v = *reinterpret_cast<const int4*>(xo + id);
+        np[0] = v.x;
+        np[1] = v.y;
+        np[2] = v.z;
+        np[3] = v.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) np[k] = id + k < hi ? *reinterpret_cast<const int*>(xo + id + k) : 0;
+    }
+}
+
 // Pairs created by particle id this step (postulate II with the integer tables).
 template <typename T, int DIM>
 __device__ __forceinline__ int pairs_of(const Geo& g, uint32_t id, uint32_t step, T px, T py,
@@ -202,6 +267,8 @@ __device__ __forceinline__ int pairs_of(const Geo& g, uint32_t id, uint32_t step
     if (base == 0 && t == 0) return 0;  // no pair whatever u0 is: the draw is not needed
     *slot = sl;
     *w = philox(id, step, 0u, TAG_CREATE, g.seed);
+    // 2^30 pairs already exceed any capacity (< 2^31): larger counts are reported as that
+    if (base >= (1u << 30)) return 1 << 30;
     return (int)base + (w->v[0] < t ? 1 : 0);
 }
 
@@ -273,19 +340,19 @@ __device__ __forceinline__ long long block_excl_scan_ll(long long v, long long* 
     return base + inc - v;
 }
 
-// Totals of the per-chunk counts a counting pass left, recomputed by every workgroup of the
-// pass that consumes them (PB values, read from L2): the sum of all of them and the sum of
-// those below `upto`.  Uniform in the block.
-__device__ __forceinline__ void chunk_totals(const long long* v, long upto, long long* total,
-                                             long long* prefix, long long* red4) {
-    long long a = 0, p = 0;
-    for (int k = threadIdx.x; k < PB; k += PT) {
-        const long long x = v[k];
-        a += x;
-        if (k < upto) p += x;
-    }
-    *total = block_sum_ll(a, red4);
-    *prefix = block_sum_ll(p, red4);
+// Sum of v[0..PB) over the block (uniform result).
+__device__ __forceinline__ long long sum_pb(const long long* v, long long* red4) {
+    long long a = 0;
+    for (int k = threadIdx.x; k < PB; k += PT) a += v[k];
+    return block_sum_ll(a, red4);
+}
+
+// Makes the LDS writes of every lane of the wave visible to the others (the waves of a
+// workgroup run independently here, so no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // First index i in [0, n) with a[i] > key (a non-decreasing), n if none.
@@ -302,16 +369,50 @@ __device__ __forceinline__ int upper_bound_lds(const V* a, int n, K key) {
     return l;
 }
 
+// ----------------------------------------------------------------------------- chunk offsets
+// A counting pass leaves one count per workgroup (bcnt) and per wave (wcnt) of its PB
+// chunk-owning workgroups.  Each workgroup of the matching writing pass totals bcnt (PB
+// values from L2) for the capacity check; a chunk owner (blockIdx.x < PB, own = true) also
+// gets the offset of its calling wave's chunk in *wave_off (valid in every lane).
+__device__ long long chunk_offsets(const WS& w, bool own, long long* wave_off, long long* red4) {
+    long long a = 0, p = 0;
+    for (int k = threadIdx.x; k < PB; k += PT) {
+        const long long v = w.bcnt[k];
+        a += v;
+        if (own && k < (int)blockIdx.x) p += v;
+    }
+    const long long total = block_sum_ll(a, red4);
+    long long off = 0;
+    if (own) {
+        off = block_sum_ll(p, red4);
+        const int wv = threadIdx.x >> 6;
+        for (int j = 0; j < wv; ++j) off += w.wcnt[(long)blockIdx.x * WPB + j];
+    }
+    *wave_off = off;
+    return total;
+}
+
+// Stores a wave's count (lane 0) and the workgroup's sum of its waves' counts (thread 0).
+__device__ void store_counts(const WS& w, long long wave_count, long long* red4) {
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        w.wcnt[(long)blockIdx.x * WPB + wv] = wave_count;
+        red4[wv] = wave_count;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) w.bcnt[blockIdx.x] = red4[0] + red4[1] + red4[2] + red4[3];
+}
+
 // ----------------------------------------------------------------------------- histogram window
 // Signed histogram of rule 1.  Counters are shared by all XCDs, so a global update is a
 // device-coherent atomic; the ensemble is close to bin-ordered (initial placement is
-// bin-major, survivors keep their order, fresh particles are appended bin by bin, children
-// follow their parents' order), so the contiguous chunk a workgroup owns touches a narrow
-// range of bins, with long runs of one bin.  Each workgroup counts into an LDS window of W
-// bins per sign starting a quarter window below the smallest bin of its first tile, one
-// atomic per run of equal (bin, sign) among the 64 lanes of a wave, then adds the non-zero
-// window entries to the global histogram; runs outside the window (rare) go straight to
-// global atomics.
+// bin-major, survivors keep their order, fresh particles are placed bin by bin, children
+// follow their parents' order), so the particles of one workgroup touch a narrow range of
+// bins, with long runs of one bin.  Each workgroup counts into an LDS window of W bins per
+// sign starting a quarter window below the smallest bin of its first particles, one atomic
+// per run of equal (bin, sign) among the 64 lanes of a wave, then adds the non-zero window
+// entries to the global histogram; runs outside the window (rare) go straight to global
+// atomics.
 template <int W>
 struct HistWindow {
     int* lh;  // [2][W] in LDS
@@ -368,72 +469,107 @@ struct HistWindow {
     }
 };
 
+// Smallest live bin among a lane's first particles of its wave chunk (LONG_MAX if none).
+template <typename T, typename MT, int DIM>
+__device__ long first_bin(const Geo& g, const T* x, const T* y, const MT* M, const MT* My,
+                          const int8_t* s, long lo, long hi) {
+    long b0 = LONG_MAX;
+    Part4<T, DIM> p;
+    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, p);
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const long b = bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]);
+        if (b >= 0) b0 = min(b0, b);
+    }
+    return b0;
+}
+
 // ----------------------------------------------------------------------------- sp_step
-// Pass 1: pairs per particle chunk into counts[].  When `hist` is given it is cleared here,
-// for pass 2 to accumulate into.
+// Pass 1: pairs per wave chunk of `in`.  Also clears the histogram pass 2 accumulates into
+// and the absorption counters; refuses an input count the buffers cannot hold.
 template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int32_t* cell_slot,
                                                  const uint32_t* n0, const uint32_t* thr,
                                                  const T* x, const T* y, const MT* M,
                                                  const MT* My, const int8_t* s,
-                                                 const long long* d_n, int32_t* hist,
-                                                 long long* stats, WS w) {
+                                                 const long long* d_n_in, long long cap_in,
+                                                 T* xo, long long cap_out, int32_t* hist,
+                                                 long long* stats, long long st, WS w) {
     __shared__ long long red[PT / 64];
     if (stats[WK_ST_OVERFLOW] != 0) return;
+    const long n = (long)*d_n_in;
+    if (n < 0 || n > cap_in || n > cap_out) {  // refused: nothing is written
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            stats[WK_ST_NEEDED] = n > cap_in || n < 0 ? -1 : n;
+            stats[WK_ST_OVERFLOW] = 1;
+            stats[WK_ST_OVERFLOW_STEP] = st;
+        }
+        return;
+    }
     if (hist != nullptr) {
         const long nh = 2 * g.n_bins;
         for (long k = (long)blockIdx.x * PT + threadIdx.x; k < nh; k += (long)PB * PT) hist[k] = 0;
     }
-    const long n = (long)*d_n;
-    long long cnt = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        stats[WK_ST_ABS_X] = 0;
+        stats[WK_ST_ABS_M] = 0;
+    }
     long lo, hi;
-    chunk_of(n, blockIdx.x, &lo, &hi);
-    for (long t0 = lo; t0 < hi; t0 += TILE) {
-        const long id = t0 + IT * threadIdx.x;
-        Part4<T, DIM> p;
-        load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
+    wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
+    long long cnt = 0;
+    Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
+    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
+    for (long t0 = lo; t0 < hi; t0 += WT) {
+        const long id = t0 + IT * (threadIdx.x & 63);
+        Part4<T, DIM> p = nxt;
+        load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+        int np[IT];
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
             int slot;
             u32x4 r;
-            cnt += pairs_of<T, DIM>(g, (uint32_t)(id + k), step, p.x[k], p.y[k], p.s[k], cell_slot,
-                                    n0, thr, &slot, &r);
+            np[k] = pairs_of<T, DIM>(g, (uint32_t)(id + k), step, p.x[k], p.y[k], p.s[k], cell_slot,
+                                     n0, thr, &slot, &r);
+            cnt += np[k];
         }
+        store_np4<T>(xo, id, hi, np);  // for pass 2
     }
-    cnt = block_sum_ll(cnt, red);
-    if (threadIdx.x == 0) {
-        w.counts[blockIdx.x] = cnt;
-        if (blockIdx.x == 0) {
-            w.sc[SC_N_OLD] = n;
-            stats[WK_ST_ABS_X] = 0;
-            stats[WK_ST_ABS_M] = 0;
-        }
-    }
+    store_counts(w, wave_sum_ll(cnt), red);
 }
 
-// Pass 2: every workgroup totals the chunk counts (capacity check, its own offset), then
-// writes the children at their ordered slots, drifts every particle, absorbs, and (HIST)
-// accumulates the signed histogram of the resulting ensemble.
+// Pass 2, in -> out: every workgroup totals the counts (capacity check, its waves' offsets);
+// each wave then walks its chunk: the drifted and absorbed parents go to their own index and
+// (HIST) into the histogram, and every particle that creates pairs goes into a per-wave
+// queue in LDS (id, slot of its first child); the pair counts come from pass 1 (kept in the
+// output's position slots).  Between tiles, once the queue could not take another tile, and
+// at the end of the chunk, the wave drains it one particle per lane: the parent's draws are
+// redone (same Philox counters), its pairs' momentum offsets sampled from its CDF row and its
+// children written.  One chain of dependent table loads serves up to 64 creating particles,
+// and the streaming loop draws nothing.
 constexpr int HW_STEP = 2048;
+constexpr int QN = 320;  // creator queue entries per wave: up to 64 waiting + a tile of 256
 
 template <typename T, typename MT, int DIM, bool HIST>
 __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int32_t* cell_slot,
                                                  const uint32_t* n0, const uint32_t* thr,
                                                  const uint64_t* cdf, const uint32_t* guide,
-                                                 int guide_len, T* x, T* y, MT* M, MT* My,
-                                                 int8_t* s, long long* d_n, long long capacity,
-                                                 int32_t* hist, long long* stats, long long st,
-                                                 WS w) {
-    __shared__ int lds5[5];
+                                                 int guide_len, const T* x, const T* y,
+                                                 const MT* M, const MT* My, const int8_t* s,
+                                                 const long long* d_n_in, T* xo, T* yo, MT* Mo,
+                                                 MT* Myo, int8_t* so, long long* d_n_out,
+                                                 long long cap_out, int32_t* hist,
+                                                 long long* stats, long long st, WS w) {
     __shared__ long long red[PT / 64];
     __shared__ long wmin[PT / 64];
     __shared__ int lh[HIST ? 2 * HW_STEP : 1];
+    __shared__ uint32_t q_id[WPB][QN];
+    __shared__ int q_o[WPB][QN];
     if (stats[WK_ST_OVERFLOW] != 0) return;
-    const long n = (long)w.sc[SC_N_OLD];
-    long long total, run;
-    chunk_totals(w.counts, blockIdx.x, &total, &run, red);
+    const long n = (long)*d_n_in;
+    long long run;
+    const long long total = chunk_offsets(w, true, &run, red);  // grid = PB chunk owners
     const long long needed = n + 2 * total;
-    if (needed > capacity) {  // the same decision in every workgroup
+    if (needed > cap_out) {  // the same decision in every workgroup
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             stats[WK_ST_NEEDED] = needed;
             stats[WK_ST_OVERFLOW] = 1;
@@ -448,24 +584,15 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
         stats[WK_ST_CUM_STEPS] += 1;
         stats[WK_ST_CUM_N] += n;
         stats[WK_ST_CUM_PAIRS] += total;
-        *d_n = needed;
+        *d_n_out = needed;
     }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     long lo, hi;
-    chunk_of(n, blockIdx.x, &lo, &hi);
+    wave_chunk(n, (long)blockIdx.x * WPB + wv, &lo, &hi);
     const T vdt = (T)g.vdt;
     long long abs_x = 0, abs_m = 0;
     HistWindow<HW_STEP> hw{lh, 0, hist, g.n_bins};
-    if (HIST) {
-        long b0 = LONG_MAX;
-        Part4<T, DIM> p;
-        load4<T, MT, DIM>(x, y, M, My, s, lo + IT * threadIdx.x, hi, p);
-#pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            const long b = bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]);
-            if (b >= 0) b0 = min(b0, b);
-        }
-        hw.init(b0, wmin);
-    }
+    if (HIST) hw.init(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), wmin);
     auto absorbed = [&](T nx_, T ny_, int m, int my) -> int {
         bool outx = !inside<T>(nx_, g.nx);
         if (DIM == 2) outx = outx || !inside<T>(ny_, g.ny);
@@ -473,65 +600,100 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
         if (DIM == 2) outm = outm || my < g.M_min || my >= g.M_min + g.n_k;
         return outx ? 1 : (outm ? 2 : 0);
     };
-    for (long t0 = lo; t0 < hi; t0 += TILE) {  // uniform trip count in the workgroup
-        const long id = t0 + IT * threadIdx.x;
-        Part4<T, DIM> p;
-        load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
-        int slot[IT];
-        u32x4 r[IT];
-        int np[IT], npt = 0;
-#pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            np[k] = pairs_of<T, DIM>(g, (uint32_t)(id + k), step, p.x[k], p.y[k], p.s[k], cell_slot,
-                                     n0, thr, &slot[k], &r[k]);
-            npt += np[k];
-        }
-        int tot;
-        const int ex = block_excl_scan_256(npt, &tot, lds5);
-        long o = n + 2 * (long)(run + ex);
-#pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            for (int q = 0; q < np[k]; ++q) {
-                uint32_t u;
-                if (q < 3) {
-                    u = q == 0 ? r[k].v[1] : (q == 1 ? r[k].v[2] : r[k].v[3]);
-                } else {
-                    const u32x4 r2 = philox((uint32_t)(id + k), step, (uint32_t)(1 + (q - 3) / 4),
-                                            TAG_CREATE, g.seed);
-                    const int wq = (q - 3) & 3;
-                    u = wq == 0 ? r2.v[0] : (wq == 1 ? r2.v[1] : (wq == 2 ? r2.v[2] : r2.v[3]));
-                }
-                const int t = sample_cdf(cdf + (long)slot[k] * g.width,
-                                         guide ? guide + (long)slot[k] * (guide_len + 1) : nullptr,
-                                         guide_len, g.width, u);
-                const int mx = (DIM == 1 ? t : t % g.n_m) - g.P;
-                const int my = DIM == 1 ? 0 : t / g.n_m - g.P;
-#pragma unroll
-                for (int ch = 0; ch < 2; ++ch, ++o) {
-                    const int sg = ch == 0 ? 1 : -1;
-                    const int cm = p.m[k] + sg * mx, cmy = p.my[k] + sg * my;
-                    const T cx = drift(p.x[k], cm, vdt);
-                    const T cy = DIM == 2 ? drift(p.y[k], cmy, vdt) : (T)0;
-                    const int a = absorbed(cx, cy, cm, cmy);
-                    abs_x += a == 1;
-                    abs_m += a == 2;
-                    const int8_t cs = a ? (int8_t)0 : (int8_t)(sg * p.s[k]);
-                    if (o < capacity) {  // always true after the capacity check
-                        x[o] = cx;
-                        M[o] = (MT)cm;
-                        if (DIM == 2) {
-                            y[o] = cy;
-                            My[o] = (MT)cmy;
-                        }
-                        s[o] = cs;
+    int qhead = 0, qlen = 0;  // uniform in the wave
+    // children of the queued particles until at most `keep` remain, up to 64 at a time
+    auto drain = [&](int keep) {
+        wave_lds_sync();
+        while (qlen > keep) {
+            const int cnt = qlen < 64 ? qlen : 64;
+            if (lane < cnt) {
+                int e = qhead + lane;
+                if (e >= QN) e -= QN;
+                const long pid = (long)q_id[wv][e];
+                long o = (long)q_o[wv][e];
+                const T px = x[pid];
+                const T py = DIM == 2 ? y[pid] : (T)0;
+                const int pm = (int)M[pid];
+                const int pmy = DIM == 2 ? (int)My[pid] : 0;
+                const int8_t ps = s[pid];
+                int row;
+                u32x4 r;
+                const int np = pairs_of<T, DIM>(g, (uint32_t)pid, step, px, py, ps, cell_slot, n0,
+                                                thr, &row, &r);
+                const uint64_t* crow = cdf + (long)row * g.width;
+                const uint32_t* grow = guide ? guide + (long)row * (guide_len + 1) : nullptr;
+                for (int q = 0; q < np; ++q) {
+                    uint32_t u;
+                    if (q < 3) {
+                        u = q == 0 ? r.v[1] : (q == 1 ? r.v[2] : r.v[3]);
+                    } else {
+                        const u32x4 r2 = philox((uint32_t)pid, step, (uint32_t)(1 + (q - 3) / 4),
+                                                TAG_CREATE, g.seed);
+                        const int wq = (q - 3) & 3;
+                        u = wq == 0 ? r2.v[0] : (wq == 1 ? r2.v[1] : (wq == 2 ? r2.v[2] : r2.v[3]));
                     }
-                    if (HIST) hw.add_one(bin_val<T, DIM>(g, cx, cy, cm, cmy, cs), cs);
+                    const int t = sample_cdf(crow, grow, guide_len, g.width, u);
+                    const int mx = (DIM == 1 ? t : t % g.n_m) - g.P;
+                    const int my = DIM == 1 ? 0 : t / g.n_m - g.P;
+#pragma unroll
+                    for (int ch = 0; ch < 2; ++ch, ++o) {
+                        const int sg = ch == 0 ? 1 : -1;
+                        const int cm = pm + sg * mx, cmy = pmy + sg * my;
+                        const T cx = drift(px, cm, vdt);
+                        const T cy = DIM == 2 ? drift(py, cmy, vdt) : (T)0;
+                        const int a = absorbed(cx, cy, cm, cmy);
+                        abs_x += a == 1;
+                        abs_m += a == 2;
+                        const int8_t cs = a ? (int8_t)0 : (int8_t)(sg * ps);
+                        if (o < cap_out) {  // always true after the capacity check
+                            xo[o] = cx;
+                            Mo[o] = (MT)cm;
+                            if (DIM == 2) {
+                                yo[o] = cy;
+                                Myo[o] = (MT)cmy;
+                            }
+                            so[o] = cs;
+                        }
+                        if (HIST) hw.add_one(bin_val<T, DIM>(g, cx, cy, cm, cmy, cs), cs);
+                    }
                 }
             }
+            qhead += cnt;
+            if (qhead >= QN) qhead -= QN;
+            qlen -= cnt;
         }
-        // parents: drift in place, absorb
+        wave_lds_sync();  // the entries are reused by later particles
+    };
+    Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
+    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
+    for (long t0 = lo; t0 < hi; t0 += WT) {  // per wave, no workgroup barriers
+        const long id = t0 + IT * lane;
+        Part4<T, DIM> p = nxt;
+        load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+        int np[IT];
+        load_np4<T>(xo, id, hi, np);  // left by pass 1 (before the parents overwrite it below)
+        long long npt = 0;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) npt += np[k];
+        const long long inc = wave_incl_scan_ll(npt);
+        long o = n + 2 * (long)(run + inc - npt);  // this lane's first child slot
+        run += __shfl(inc, 63, 64);
+        // queue the creating particles (at most WT per tile; room was left by the last drain)
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const bool has = np[k] > 0;
+            const unsigned long long m = __ballot(has);
+            if (has) {
+                int e = qhead + qlen + __popcll(m & ((1ull << lane) - 1ull));
+                if (e >= QN) e -= QN;
+                q_id[wv][e] = (uint32_t)(id + k);
+                q_o[wv][e] = (int)o;
+            }
+            qlen += __popcll(m);
+            o += 2 * np[k];
+        }
+        // parents: drift, absorb, same index in `out` (n <= cap_out was checked)
         T nxv[IT], nyv[IT];
-        bool sdirty = false;
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
             nxv[k] = p.x[k];
@@ -542,30 +704,14 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
                 const int a = absorbed(nxv[k], nyv[k], p.m[k], p.my[k]);
                 abs_x += a == 1;
                 abs_m += a == 2;
-                if (a) {
-                    p.s[k] = 0;
-                    sdirty = true;
-                }
+                if (a) p.s[k] = 0;
             }
             if (HIST) hw.add_wave(bin_val<T, DIM>(g, nxv[k], nyv[k], p.m[k], p.my[k], p.s[k]), p.s[k]);
         }
-        if (id + IT <= hi) {
-            st4(x, id, nxv);
-            if (DIM == 2) st4(y, id, nyv);
-            if (sdirty)
-                *reinterpret_cast<char4*>(s + id) = make_char4(p.s[0], p.s[1], p.s[2], p.s[3]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < IT; ++k) {
-                if (id + k < hi) {
-                    x[id + k] = nxv[k];
-                    if (DIM == 2) y[id + k] = nyv[k];
-                    s[id + k] = p.s[k];
-                }
-            }
-        }
-        run += tot;
+        store4<T, MT, DIM>(xo, yo, Mo, Myo, so, id, hi, nxv, nyv, p);
+        if (qlen > QN - WT) drain(QN - WT);  // room for the next tile
     }
+    drain(0);
     if (HIST) hw.flush();
     abs_x = block_sum_ll(abs_x, red);
     abs_m = block_sum_ll(abs_m, red);
@@ -602,35 +748,29 @@ __global__ void fill_i32(int32_t* p, long n, int32_t v) {
         p[i] = v;
 }
 
-// Stand-alone histogram pass (when sp_step did not build it).
+// Stand-alone histogram pass (when sp_step did not build it), over the wave chunks.
 constexpr int HW = 4096;
 
 template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void annih_hist(Geo g, const T* x, const T* y, const MT* M,
                                                  const MT* My, const int8_t* s,
-                                                 const long long* d_n, int32_t* hist,
-                                                 const long long* stats) {
+                                                 const long long* d_n, long long cap_in,
+                                                 int32_t* hist, const long long* stats) {
     __shared__ int lh[2 * HW];
     __shared__ long wmin[PT / 64];
     if (stats[WK_ST_OVERFLOW] != 0) return;
+    const long n = (long)*d_n;
+    if (n < 0 || n > cap_in) return;  // refused by annih_count
     long lo, hi;
-    chunk_of((long)*d_n, blockIdx.x, &lo, &hi);
+    wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
     HistWindow<HW> hw{lh, 0, hist, g.n_bins};
-    {
-        long b0 = LONG_MAX;
-        Part4<T, DIM> p;
-        load4<T, MT, DIM>(x, y, M, My, s, lo + IT * threadIdx.x, hi, p);
-#pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            const long b = bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]);
-            if (b >= 0) b0 = min(b0, b);
-        }
-        hw.init(b0, wmin);
-    }
-    for (long t0 = lo; t0 < hi; t0 += TILE) {
-        const long id = t0 + IT * threadIdx.x;
-        Part4<T, DIM> p;
-        load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
+    hw.init(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), wmin);
+    Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
+    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
+    for (long t0 = lo; t0 < hi; t0 += WT) {
+        const long id = t0 + IT * (threadIdx.x & 63);
+        Part4<T, DIM> p = nxt;
+        load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
 #pragma unroll
         for (int k = 0; k < IT; ++k)
             hw.add_wave(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), p.s[k]);
@@ -639,34 +779,45 @@ __global__ __launch_bounds__(PT) void annih_hist(Geo g, const T* x, const T* y, 
 }
 
 // Counting pass of sp_annihilate (mode 1) and sp_init (mode 0).  Workgroups below
-// part_blocks (PB in mode 1, 0 in mode 0) count the survivors of their particle chunk into
-// counts[]; the PB workgroups after them each own g.gpb consecutive chunks of BC bins and
-// store every chunk's output count in csum[], their sum in bpart[] and their mixed bins in
+// part_blocks (PB in mode 1, 0 in mode 0) count the survivors of their waves' chunks of
+// `in`; the PB workgroups after them each own g.gpb consecutive chunks of BC bins and store
+// every chunk's output count in csum[], their sum in bpart[] and their mixed bins in
 // bmixed[].
 template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void annih_count(Geo g, int part_blocks, BinCount bc,
                                                   const T* x, const T* y, const MT* M,
                                                   const MT* My, const int8_t* s,
-                                                  const long long* d_n_in, const long long* stats,
-                                                  WS w) {
+                                                  const long long* d_n_in, long long cap_in,
+                                                  long long* stats, WS w) {
     __shared__ long long red[PT / 64];
     if (stats[WK_ST_OVERFLOW] != 0) return;
-    if ((int)blockIdx.x < part_blocks) {
-        long long a = 0;
-        long lo, hi;
-        chunk_of(*d_n_in, blockIdx.x, &lo, &hi);
-        for (long t0 = lo; t0 < hi; t0 += TILE) {
-            const long id = t0 + IT * threadIdx.x;
-            Part4<T, DIM> p;
-            load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
-#pragma unroll
-            for (int k = 0; k < IT; ++k)
-                a += keeps_bin(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]),
-                               bc.hist, g.n_bins) ? 1 : 0;
+    if (part_blocks > 0) {
+        const long n = (long)*d_n_in;
+        if (n < 0 || n > cap_in) {  // refused: nothing is written
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                stats[WK_ST_NEEDED] = -1;
+                stats[WK_ST_OVERFLOW] = 1;
+            }
+            return;
         }
-        a = block_sum_ll(a, red);
-        if (threadIdx.x == 0) w.counts[blockIdx.x] = a;
-        return;
+        if ((int)blockIdx.x < part_blocks) {
+            long lo, hi;
+            wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
+            long long a = 0;
+            Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
+            load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
+            for (long t0 = lo; t0 < hi; t0 += WT) {
+                const long id = t0 + IT * (threadIdx.x & 63);
+                Part4<T, DIM> p = nxt;
+                load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+#pragma unroll
+                for (int k = 0; k < IT; ++k)
+                    a += keeps_bin(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]),
+                                   bc.hist, g.n_bins) ? 1 : 0;
+            }
+            store_counts(w, wave_sum_ll(a), red);
+            return;
+        }
     }
     const long c = (long)blockIdx.x - part_blocks;
     const long j0 = min(g.n_chunks, c * g.gpb), j1 = min(g.n_chunks, j0 + g.gpb);
@@ -690,77 +841,58 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, int part_blocks, BinCou
 }
 
 // Places the particles of one bin chunk (BC bins, chunk output count cnt_ch starting at
-// output slot ch_start) that fall in the slot range [s_lo, s_hi): the chunk's bin counts and
-// Philox blocks (Q particles per block: 4 draws = 4 positions in 1-D, 2 x (x, y) in 2-D)
-// are scanned in LDS, and each thread fills the particles of one Philox block.
+// output slot ch_start) that fall in the slot range [s_lo, s_hi): the chunk's bin counts are
+// scanned in LDS and consecutive threads fill consecutive slots (coalesced stores), each
+// taking its position from its Philox block (4 draws = 4 positions in 1-D, 2 x (x, y) in 2-D).
 template <typename T, typename MT, int DIM>
 __device__ void place_chunk(const Geo& g, const BinCount& bc, int mode, uint32_t c1, uint32_t tag,
-                            long ch, long ch_start, long cnt_ch, long s_lo, long s_hi,
-                            long out_base, T* xo, T* yo, MT* Mo, MT* Myo, int8_t* so,
-                            long long capacity, int* bo_ex, int* bo_in, int* q_ex, int* q_in,
-                            int* lds5) {
+                            long ch, long ch_start, long cnt_ch, long s_lo, long s_hi, T* xo,
+                            T* yo, MT* Mo, MT* Myo, int8_t* so, long long capacity, int* bo_ex,
+                            int* bo_in, int* lds5) {
     constexpr int Q = DIM == 1 ? 4 : 2;
     const long b = ch * BC + threadIdx.x;
     const int cnt = b < g.n_bins ? (int)bc(b) : 0;
-    const int nq = (cnt + Q - 1) / Q;
-    int tc, tq;
+    int tc;
     const int ex = block_excl_scan_256(cnt, &tc, lds5);
-    const int exq = block_excl_scan_256(nq, &tq, lds5);
     bo_ex[threadIdx.x] = ex;
     bo_in[threadIdx.x] = ex + cnt;
-    q_ex[threadIdx.x] = exq;
-    q_in[threadIdx.x] = exq + nq;
     __syncthreads();
     const int lo_c = (int)(max(s_lo, ch_start) - ch_start);            // slots of this chunk
     const int hi_c = (int)(min(s_hi, ch_start + cnt_ch) - ch_start);   // to fill: [lo_c, hi_c)
-    const int ja = upper_bound_lds(bo_in, BC, lo_c);
-    const int jb = upper_bound_lds(bo_in, BC, hi_c - 1);
-    const int qa = q_ex[ja] + (lo_c - bo_ex[ja]) / Q;
-    const int qb = q_ex[jb] + (hi_c - 1 - bo_ex[jb]) / Q;
-    for (int q = qa + threadIdx.x; q <= qb; q += PT) {
-        const int j = upper_bound_lds(q_in, BC, q);
-        const int qi = q - q_ex[j];
-        const int r0 = Q * qi;
-        const int nr = min(Q, bo_in[j] - bo_ex[j] - r0);
+    for (int rel = lo_c + threadIdx.x; rel < hi_c; rel += PT) {
+        const int j = upper_bound_lds(bo_in, BC, rel);
+        const int r = rel - bo_ex[j];
         const long bb = ch * BC + j;
+        const long o = ch_start + rel;
+        if (o >= capacity) break;  // never taken after the capacity check
         const int8_t sign = mode == 1 ? (bc.hist[bb] > bc.hist[g.n_bins + bb] ? 1 : -1) : 1;
-        const u32x4 u = philox((uint32_t)bb, c1, (uint32_t)qi, tag, g.seed);
-        int cx, cy = 0, kx, ky = 0;
+        const u32x4 u = philox((uint32_t)bb, c1, (uint32_t)(r / Q), tag, g.seed);
+        const int e = r % Q;
         if (DIM == 1) {
-            cx = (int)(bb / g.n_k);
-            kx = (int)(bb % g.n_k);
-        } else {
-            kx = (int)(bb % g.n_k);
-            ky = (int)((bb / g.n_k) % g.n_k);
-            const long cc = bb / ((long)g.n_k * g.n_k);
-            cx = (int)(cc % g.nx);
-            cy = (int)(cc / g.nx);
-        }
-        for (int e = 0; e < nr; ++e) {
-            const int rel = bo_ex[j] + r0 + e;
-            if (rel < lo_c || rel >= hi_c) continue;  // another workgroup's slot
-            const long o = out_base + ch_start + rel;
-            if (o >= capacity) break;  // never taken after the capacity check
-            if (DIM == 1) {
-                const uint32_t ue = e == 0 ? u.v[0] : (e == 1 ? u.v[1] : (e == 2 ? u.v[2] : u.v[3]));
-                xo[o] = cell_plus_frac<T>(cx, ue, g.fb);
-            } else {
-                xo[o] = cell_plus_frac<T>(cx, e ? u.v[2] : u.v[0], g.fb);
-                yo[o] = cell_plus_frac<T>(cy, e ? u.v[3] : u.v[1], g.fb);
-                Myo[o] = (MT)(g.M_min + ky);
-            }
+            const int cx = (int)(bb / g.n_k), kx = (int)(bb % g.n_k);
+            const uint32_t ue = e == 0 ? u.v[0] : (e == 1 ? u.v[1] : (e == 2 ? u.v[2] : u.v[3]));
+            xo[o] = cell_plus_frac<T>(cx, ue, g.fb);
             Mo[o] = (MT)(g.M_min + kx);
-            so[o] = sign;
+        } else {
+            const int kx = (int)(bb % g.n_k), ky = (int)((bb / g.n_k) % g.n_k);
+            const long cc = bb / ((long)g.n_k * g.n_k);
+            const int cx = (int)(cc % g.nx), cy = (int)(cc / g.nx);
+            xo[o] = cell_plus_frac<T>(cx, e ? u.v[2] : u.v[0], g.fb);
+            yo[o] = cell_plus_frac<T>(cy, e ? u.v[3] : u.v[1], g.fb);
+            Mo[o] = (MT)(g.M_min + kx);
+            Myo[o] = (MT)(g.M_min + ky);
         }
+        so[o] = sign;
     }
     __syncthreads();  // the LDS tables are rewritten for the next chunk
 }
 
-// Writing pass of sp_annihilate (mode 1) and sp_init (mode 0).  Every workgroup first
-// totals the counts of the counting pass (capacity check, offsets).  Workgroups below
-// part_blocks copy their chunk's survivors, in order, to their scanned offsets; the
-// place_blocks after them split the regenerated (or initial) particles into equal ranges
-// of output slots and place the particles of their range bin by bin.
+// Writing pass of sp_annihilate (mode 1) and sp_init (mode 0).  Output: the particles placed
+// bin by bin (mixed bins' survivors of rule 2, or the initial state), then, in mode 1, the
+// particles of single-sign bins in input order.  Every workgroup first totals the counts of
+// the counting pass (capacity check, offsets).  Workgroups below part_blocks copy their
+// waves' survivors, in order; the place_blocks after them split the placed particles into
+// equal ranges of output slots and fill their range bin chunk by bin chunk.
 template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int place_blocks,
                                                   BinCount bc, int mode, uint32_t c1,
@@ -769,16 +901,17 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
                                                   const long long* d_n_in, T* xo, T* yo, MT* Mo,
                                                   MT* Myo, int8_t* so, long long* d_n_out,
                                                   long long capacity, long long* stats, WS w) {
+    constexpr int STAGE = WT * (2 * (int)sizeof(T) + 2 * (int)sizeof(int) + 1);  // per wave
+    constexpr int SMEM = PB * 8 > WPB * STAGE ? PB * 8 : WPB * STAGE;
     __shared__ int lds5[5];
     __shared__ long long red[PT / 64];
-    __shared__ long long bp[PB];  // inclusive prefix of bpart (placing workgroups)
+    __shared__ __align__(16) char smem[SMEM];  // placers: prefix of bpart; keepers: wave stages
     __shared__ int cs_ex[PT], cs_in[PT];
-    __shared__ int bo_ex[BC], bo_in[BC], q_ex[BC], q_in[BC];
+    __shared__ int bo_ex[BC], bo_in[BC];
+    long long* bp = reinterpret_cast<long long*>(smem);  // inclusive prefix of bpart
     if (stats[WK_ST_OVERFLOW] != 0) return;
     const bool part = (int)blockIdx.x < part_blocks;
-    long long kept = 0, kept_pre = 0;
-    if (part_blocks > 0) chunk_totals(w.counts, blockIdx.x, &kept, &kept_pre, red);
-    long long bin_total;
+    long long placed;  // particles placed bin by bin: the offset of the kept ones
     {
         constexpr int per = PB / PT;
         long long loc[per], acc = 0;
@@ -787,7 +920,7 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
             loc[k] = w.bpart[threadIdx.x * per + k];
             acc += loc[k];
         }
-        long long run = block_excl_scan_ll(acc, &bin_total, red);
+        long long run = block_excl_scan_ll(acc, &placed, red);
         if (!part) {
 #pragma unroll
             for (int k = 0; k < per; ++k) {
@@ -797,7 +930,9 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
         }
         __syncthreads();  // bp is read across threads below
     }
-    const long long n_out = kept + bin_total;
+    long long kept = 0, wave_off = 0;
+    if (part_blocks > 0) kept = chunk_offsets(w, part, &wave_off, red);
+    const long long n_out = placed + kept;
     if (n_out > capacity) {  // the same decision in every workgroup
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             stats[WK_ST_NEEDED] = n_out;
@@ -811,28 +946,36 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
         mx = block_sum_ll(mx, red);
         if (threadIdx.x == 0) {
             stats[WK_ST_N] = n_out;
+            stats[WK_ST_NEEDED] = 0;
             if (mode == 1) {
-                const long long n_in = *d_n_in;
                 stats[WK_ST_KEPT] = kept;
-                stats[WK_ST_REGEN] = bin_total;
+                stats[WK_ST_REGEN] = placed;
                 stats[WK_ST_MIXED] = mx;
-                stats[WK_ST_CUM_ANNIH_IN] += n_in;
+                stats[WK_ST_CUM_ANNIH_IN] += *d_n_in;
                 stats[WK_ST_CUM_KEPT] += kept;
-                stats[WK_ST_CUM_REGEN] += bin_total;
-            } else {
-                stats[WK_ST_NEEDED] = 0;
+                stats[WK_ST_CUM_REGEN] += placed;
             }
             *d_n_out = n_out;
         }
     }
     if (part) {
+        const int lane = threadIdx.x & 63;
+        // per-wave stage: the tile's survivors, compacted, then written out contiguously
+        char* st = smem + (threadIdx.x >> 6) * STAGE;
+        T* sx = reinterpret_cast<T*>(st);
+        T* sy = sx + WT;
+        int* sm = reinterpret_cast<int*>(sy + WT);
+        int* smy = sm + WT;
+        int8_t* ssg = reinterpret_cast<int8_t*>(smy + WT);
         long lo, hi;
-        chunk_of((long)*d_n_in, blockIdx.x, &lo, &hi);
-        long long run = kept_pre;
-        for (long t0 = lo; t0 < hi; t0 += TILE) {
-            const long id = t0 + IT * threadIdx.x;
-            Part4<T, DIM> p;
-            load4<T, MT, DIM>(x, y, M, My, s, id, hi, p);
+        wave_chunk((long)*d_n_in, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
+        long long run = placed + wave_off;
+        Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
+        load4<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
+        for (long t0 = lo; t0 < hi; t0 += WT) {  // per wave, no workgroup barriers
+            const long id = t0 + IT * lane;
+            Part4<T, DIM> p = nxt;
+            load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
             bool kp[IT];
             int kt = 0;
 #pragma unroll
@@ -841,33 +984,43 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
                                   bc.hist, g.n_bins);
                 kt += kp[k];
             }
-            int tot;
-            const int ex = block_excl_scan_256(kt, &tot, lds5);
-            long o = run + ex;
+            const int inc = wave_incl_scan(kt);
+            const int tot = __shfl(inc, 63, 64);
+            int e = inc - kt;
 #pragma unroll
             for (int k = 0; k < IT; ++k) {
                 if (!kp[k]) continue;
-                if (o < capacity) {  // always true after the capacity check
-                    xo[o] = p.x[k];
-                    Mo[o] = (MT)p.m[k];
-                    if (DIM == 2) {
-                        yo[o] = p.y[k];
-                        Myo[o] = (MT)p.my[k];
-                    }
-                    so[o] = p.s[k];
+                sx[e] = p.x[k];
+                sm[e] = p.m[k];
+                if (DIM == 2) {
+                    sy[e] = p.y[k];
+                    smy[e] = p.my[k];
                 }
-                ++o;
+                ssg[e] = p.s[k];
+                ++e;
             }
+            wave_lds_sync();
+            for (int i = lane; i < tot; i += 64) {
+                const long o = (long)run + i;
+                if (o >= capacity) break;  // never taken after the capacity check
+                xo[o] = sx[i];
+                Mo[o] = (MT)sm[i];
+                if (DIM == 2) {
+                    yo[o] = sy[i];
+                    Myo[o] = (MT)smy[i];
+                }
+                so[o] = ssg[i];
+            }
+            wave_lds_sync();  // the stage is rewritten by the next tile
             run += tot;
         }
         return;
     }
     // placing workgroup k: output slots [s_lo, s_hi) of the bin-ordered part
     const long k = (long)blockIdx.x - part_blocks;
-    const long per = (bin_total + place_blocks - 1) / place_blocks;
-    const long s_lo = min((long)bin_total, k * per), s_hi = min((long)bin_total, s_lo + per);
+    const long per = (placed + place_blocks - 1) / place_blocks;
+    const long s_lo = min((long)placed, k * per), s_hi = min((long)placed, s_lo + per);
     if (s_lo >= s_hi) return;
-    const long out_base = (long)kept;
     for (int c = upper_bound_lds(bp, PB, (long long)s_lo); c < PB; ++c) {  // uniform
         const long c_start = c ? (long)bp[c - 1] : 0;
         if (c_start >= s_hi) break;
@@ -888,8 +1041,8 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
                     const long cnt_ch = cs_in[i] - cs_ex[i];
                     if (cnt_ch == 0) continue;
                     place_chunk<T, MT, DIM>(g, bc, mode, c1, tag, g0 + i, ch_start, cnt_ch, s_lo,
-                                            s_hi, out_base, xo, yo, Mo, Myo, so, capacity, bo_ex,
-                                            bo_in, q_ex, q_in, lds5);
+                                            s_hi, xo, yo, Mo, Myo, so, capacity, bo_ex, bo_in,
+                                            lds5);
                 }
             }
             run += tot;
@@ -1013,22 +1166,29 @@ static int check_particles(const sp_geom* gm, const sp_particles* p, const char*
 template <typename T, typename MT, int DIM>
 static void launch_step(const Geo& g, uint32_t step, const int32_t* cs, const uint32_t* n0,
                         const uint32_t* thr, const uint64_t* cdf, const uint32_t* guide,
-                        int guide_len, sp_particles* p, int32_t* hist, long long* stats,
-                        long long st, WS w, hipStream_t s) {
-    T* x = static_cast<T*>(p->x);
-    T* y = static_cast<T*>(p->y);
-    MT* M = static_cast<MT*>(p->M);
-    MT* My = static_cast<MT*>(p->My);
-    long long* d_n = reinterpret_cast<long long*>(p->d_n);
-    const long long cap = (long long)p->capacity;
+                        int guide_len, const sp_particles* in, sp_particles* out, int32_t* hist,
+                        long long* stats, long long st, WS w, hipStream_t s) {
+    const long long* d_n_in = reinterpret_cast<const long long*>(in->d_n);
+    long long* d_n_out = reinterpret_cast<long long*>(out->d_n);
+    const long long cap = (long long)out->capacity;
+    const T* x = static_cast<const T*>(in->x);
+    const T* y = static_cast<const T*>(in->y);
+    const MT* M = static_cast<const MT*>(in->M);
+    const MT* My = static_cast<const MT*>(in->My);
+    T* xo = static_cast<T*>(out->x);
+    T* yo = static_cast<T*>(out->y);
+    MT* Mo = static_cast<MT*>(out->M);
+    MT* Myo = static_cast<MT*>(out->My);
     WK_LAUNCH("step_count", (step_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, step, cs, n0, thr,
-              x, y, M, My, p->s, d_n, hist, stats, w);
+              x, y, M, My, in->s, d_n_in, (long long)in->capacity, xo, cap, hist, stats, st, w);
     if (hist)
         WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, true>), dim3(PB), dim3(PT), 0, s, g, step, cs,
-                  n0, thr, cdf, guide, guide_len, x, y, M, My, p->s, d_n, cap, hist, stats, st, w);
+                  n0, thr, cdf, guide, guide_len, x, y, M, My, in->s, d_n_in, xo, yo, Mo, Myo,
+                  out->s, d_n_out, cap, hist, stats, st, w);
     else
         WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, false>), dim3(PB), dim3(PT), 0, s, g, step, cs,
-                  n0, thr, cdf, guide, guide_len, x, y, M, My, p->s, d_n, cap, hist, stats, st, w);
+                  n0, thr, cdf, guide, guide_len, x, y, M, My, in->s, d_n_in, xo, yo, Mo, Myo,
+                  out->s, d_n_out, cap, hist, stats, st, w);
 }
 
 constexpr int PLACE_BLOCKS = PB;  // workgroups placing regenerated / initial particles
@@ -1041,14 +1201,15 @@ static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp
     const MT* M = static_cast<const MT*>(in->M);
     const MT* My = static_cast<const MT*>(in->My);
     const long long* d_n = reinterpret_cast<const long long*>(in->d_n);
+    const long long cap_in = (long long)in->capacity;
     if (!hist_ready) {
         WK_LAUNCH("hist_clear", fill_i32, dim3(1024), dim3(256), 0, s, hist, 2 * g.n_bins, 0);
         WK_LAUNCH("annih_hist", (annih_hist<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
-                  in->s, d_n, hist, stats);
+                  in->s, d_n, cap_in, hist, stats);
     }
     const BinCount bc{nullptr, hist, g.n_bins};
-    WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(2 * PB), dim3(PT), 0, s, g, PB, bc,
-              x, y, M, My, in->s, d_n, stats, w);
+    WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(2 * PB), dim3(PT), 0, s, g, PB, bc, x, y,
+              M, My, in->s, d_n, cap_in, stats, w);
     WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(PB + PLACE_BLOCKS), dim3(PT), 0, s, g,
               PB, PLACE_BLOCKS, bc, 1, step, (uint32_t)TAG_ANNIH, x, y, M, My, in->s, d_n,
               static_cast<T*>(out->x), static_cast<T*>(out->y), static_cast<MT*>(out->M),
@@ -1062,7 +1223,7 @@ static void launch_init(const Geo& g, const int32_t* counts, sp_particles* out, 
     const BinCount bc{counts, nullptr, g.n_bins};
     WK_LAUNCH("init_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, 0, bc,
               (const T*)nullptr, (const T*)nullptr, (const MT*)nullptr, (const MT*)nullptr,
-              (const int8_t*)nullptr, (const long long*)nullptr, stats, w);
+              (const int8_t*)nullptr, (const long long*)nullptr, 0LL, stats, w);
     WK_LAUNCH("init_write", (annih_write<T, MT, DIM>), dim3(PLACE_BLOCKS), dim3(PT), 0, s, g, 0,
               PLACE_BLOCKS, bc, 0, 0xFFFFFFFFu, (uint32_t)TAG_INIT, (const T*)nullptr,
               (const T*)nullptr, (const MT*)nullptr, (const MT*)nullptr, (const int8_t*)nullptr,
@@ -1113,21 +1274,27 @@ extern "C" int sp_init(const sp_geom* gm, const int32_t* bin_counts, sp_particle
 
 extern "C" int sp_step(const sp_geom* gm, const int32_t* cell_slot, const uint32_t* n0,
                        const uint32_t* thr, const uint64_t* cdf, const uint32_t* guide,
-                       int32_t guide_len, sp_particles* p, int32_t* hist, int64_t step,
-                       int64_t* d_stats, void* ws, size_t ws_bytes, void* stream) {
+                       int32_t guide_len, const sp_particles* in, sp_particles* out,
+                       int32_t* hist, int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes,
+                       void* stream) {
     Geo g;
     int rc = make_geo(gm, &g);
     if (rc) return rc;
-    rc = check_particles(gm, p, "sp_step");
+    rc = check_particles(gm, in, "sp_step(in)");
     if (rc) return rc;
+    rc = check_particles(gm, out, "sp_step(out)");
+    if (rc) return rc;
+    WK_REQUIRE(in->x != out->x && in->M != out->M && in->s != out->s && in->d_n != out->d_n,
+               "sp_step: in and out must be different buffers");
     WK_REQUIRE(cell_slot && n0 && thr && cdf && d_stats, "sp_step: NULL array");
     WK_REQUIRE(step >= 0 && step < (1LL << 32), "sp_step: step must fit 32 bits");
-    WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_step: workspace too small");
-    WS w = carve(ws, g.n_bins);
     WK_REQUIRE(guide == nullptr || (guide_len >= 1 && guide_len <= (1 << 20)),
                "sp_step: guide_len out of range");
-    WK_DISPATCH(gm, launch_step, g, (uint32_t)step, cell_slot, n0, thr, cdf, guide, guide_len, p, hist,
-                reinterpret_cast<long long*>(d_stats), (long long)step, w, as_stream(stream));
+    WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_step: workspace too small");
+    WS w = carve(ws, g.n_bins);
+    WK_DISPATCH(gm, launch_step, g, (uint32_t)step, cell_slot, n0, thr, cdf, guide, guide_len, in,
+                out, hist, reinterpret_cast<long long*>(d_stats), (long long)step, w,
+                as_stream(stream));
     return check_launch("sp_step");
 }
 
@@ -1141,8 +1308,8 @@ extern "C" int sp_annihilate(const sp_geom* gm, const sp_particles* in, sp_parti
     if (rc) return rc;
     rc = check_particles(gm, out, "sp_annihilate(out)");
     if (rc) return rc;
-    WK_REQUIRE(in->x != out->x && in->s != out->s, "sp_annihilate: in and out must differ");
-    WK_REQUIRE(out->capacity >= in->capacity, "sp_annihilate: out capacity below in capacity");
+    WK_REQUIRE(in->x != out->x && in->M != out->M && in->s != out->s && in->d_n != out->d_n,
+               "sp_annihilate: in and out must be different buffers");
     WK_REQUIRE(hist && d_stats, "sp_annihilate: NULL array");
     WK_REQUIRE(step >= 0 && step < (1LL << 32), "sp_annihilate: step must fit 32 bits");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_annihilate: workspace too small");

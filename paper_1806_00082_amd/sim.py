@@ -124,12 +124,11 @@ class Simulator:
         s = self.step_index
         if self.mode == "occupied" and s > 0 and s % self.refresh_every == 0:
             self.refresh()
-        ops.sp_step(self.md, self.seed, self.cell_slot, self.n0, self.thr, self.cdf, self.a, s,
-                    self.stats, self.ws, hist=self.hist if self.hist_in_step else None,
+        ops.sp_step(self.md, self.seed, self.cell_slot, self.n0, self.thr, self.cdf, self.a,
+                    self.b, s, self.stats, self.ws, hist=self.hist if self.hist_in_step else None,
                     guide=self.guide)
-        ops.sp_annihilate(self.md, self.seed, self.a, self.b, self.hist, s, self.stats, self.ws,
+        ops.sp_annihilate(self.md, self.seed, self.b, self.a, self.hist, s, self.stats, self.ws,
                           hist_ready=self.hist_in_step)
-        self.a, self.b = self.b, self.a
         self.step_index += 1
 
     def run(self, steps: int):

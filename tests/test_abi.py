@@ -50,3 +50,26 @@ def test_host_validation_without_gpu():
     assert lib.wk_kernel_eval(ctypes.byref(m), None, 0, None, 10, 0, 0, None, None) == 0  # empty
     g = _lib.SpGeom(1, 10, 1, 8, 16, -8, 0, 0, 0.1, 0)
     assert lib.sp_workspace_size(ctypes.byref(g)) > 0
+
+
+def test_particle_calls_reject_aliased_buffers_without_gpu():
+    """sp_step and sp_annihilate write `out` while reading `in`: the same buffers twice are
+    refused on the host (the pointers are never dereferenced)."""
+    from paper_1806_00082_amd import _lib
+    lib = _lib.lib()
+    g = _lib.SpGeom(1, 10, 1, 8, 16, -8, 0, 0, 0.1, 0)
+    p = _lib.SpParticles(0x1000, None, 0x2000, None, 0x3000, 100, 0x4000)
+    q = _lib.SpParticles(0x5000, None, 0x6000, None, 0x7000, 100, 0x8000)
+    ws = int(lib.sp_workspace_size(ctypes.byref(g)))
+    f = 0x9000
+    rc = lib.sp_step(ctypes.byref(g), f, f, f, f, None, 0, ctypes.byref(p), ctypes.byref(p), None,
+                     0, f, f, ws, None)
+    assert rc == _lib.WK_EINVAL and b"different buffers" in lib.wk_last_error()
+    rc = lib.sp_annihilate(ctypes.byref(g), ctypes.byref(q), ctypes.byref(q), f, 0, 0, f, f, ws, None)
+    assert rc == _lib.WK_EINVAL and b"different buffers" in lib.wk_last_error()
+    rc = lib.sp_step(ctypes.byref(g), f, f, f, f, f, 0, ctypes.byref(p), ctypes.byref(q), None,
+                     0, f, f, ws, None)
+    assert rc == _lib.WK_EINVAL and b"guide_len" in lib.wk_last_error()
+    rc = lib.sp_step(ctypes.byref(g), f, f, f, f, None, 0, ctypes.byref(p), ctypes.byref(q), None,
+                     0, f, f, ws - 1, None)
+    assert rc == _lib.WK_EINVAL and b"workspace" in lib.wk_last_error()

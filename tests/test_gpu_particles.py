@@ -67,29 +67,28 @@ def _run_both(orc, cfg, steps, N0_scale=1.0, check_every=1):
         # Steps 2, 3 (mod 4) search the CDF through the guide table.
         fused = s % 2 == 1
         hp, hst = orc.sp_step(md, hp, tables, slot, step=s, seed=seed)
-        ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, s, st, ws, hist=hist if fused else None,
+        ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, b, s, st, ws, hist=hist if fused else None,
                     guide=guide if s % 4 >= 2 else None)
         gst = to_np(st)
         assert gst[L.ST_OVERFLOW] == 0
         for k in (L.ST_N, L.ST_PAIRS, L.ST_ABS_X, L.ST_ABS_M):
             assert gst[k] == hst[k], (s, k, gst[k], hst[k])
         if s % check_every == 0:
-            assert_particles_equal(a.view(), hp.view(), f"sp_step {s}")
+            assert_particles_equal(b.view(), hp.view(), f"sp_step {s}")
         hp, hh_p, hh_m, hst = orc.sp_annihilate(md, hp, step=s, seed=seed, capacity=cap)
         if fused:
             h = to_np(hist)
             nb = ops.n_bins(md)
             assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"step hist {s}"
-        ops.sp_annihilate(md, seed, a, b, hist, s, st, ws, hist_ready=fused)
+        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=fused)
         gst = to_np(st)
         for k in (L.ST_N, L.ST_KEPT, L.ST_REGEN, L.ST_MIXED):
             assert gst[k] == hst[k], (s, k, gst[k], hst[k])
         if s % check_every == 0:
-            assert_particles_equal(b.view(), hp.view(), f"sp_annihilate {s}")
+            assert_particles_equal(a.view(), hp.view(), f"sp_annihilate {s}")
             h = to_np(hist)
             nb = ops.n_bins(md)
             assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m)
-        a, b = b, a
     return md, hp, a, hist
 
 
@@ -119,8 +118,9 @@ def test_density_readout(orc):
 
 
 def test_step_overflow_and_retry(orc):
-    """Capacity too small: nothing written, needed size reported, sticky flag set, later
-    calls are no-ops; a retry with a larger buffer gives the oracle's result exactly."""
+    """Output too small: the input is untouched, the needed size reported, the sticky flag
+    set, later calls are no-ops; a retry into a larger buffer gives the oracle's result
+    exactly."""
     cfg = inputs.config_c1()
     md, tables, bc, _ = _setup(orc, cfg)
     seed = 0
@@ -135,20 +135,22 @@ def test_step_overflow_and_retry(orc):
     n0, thr, cdf = host_tables_to_device((None,) + tuple(tables))
     st = ops.new_stats()
     ws = ops.sp_workspace(md)
-    ops.sp_step(md, seed, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, 0, st, ws)
+    small = ops.DeviceParticles(1, n + 10, True)
+    ops.sp_step(md, seed, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, small, 0, st, ws)
     s = to_np(st)
     ref, rst = orc.sp_step(md, hp, tables, slot, step=0, seed=seed)
     assert ref is None and s[L.ST_OVERFLOW] == 1 and s[L.ST_NEEDED] == rst[orc.ST_NEEDED]
     assert s[L.ST_OVERFLOW_STEP] == 0
-    assert_particles_equal(a.view(), v, "untouched after overflow")
-    ops.sp_step(md, seed, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, 1, st, ws)
+    assert_particles_equal(a.view(), v, "input untouched after overflow")
+    small.d_n.fill_(0)
+    ops.sp_step(md, seed, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, small, 1, st, ws)
     assert_particles_equal(a.view(), v, "no-op while the sticky flag is set")
+    assert small.count() == 0
     # retry with enough room
     need = int(s[L.ST_NEEDED])
     big = ops.DeviceParticles(1, need, True)
-    big.load(hp.n, v["x"], v["M"], v["s"])
     st2 = ops.new_stats()
-    ops.sp_step(md, seed, torch.from_numpy(slot).to(dev()), n0, thr, cdf, big, 0, st2, ws)
+    ops.sp_step(md, seed, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, big, 0, st2, ws)
     hp2 = orc.Particles(1, need, True)
     hp2.x[: hp.n], hp2.M[: hp.n], hp2.s[: hp.n], hp2.n = v["x"], v["M"], v["s"], hp.n
     ref, rst = orc.sp_step(md, hp2, tables, slot, step=0, seed=seed)
@@ -182,10 +184,11 @@ def test_many_pairs_per_particle(orc, glen):
     n0, thr, cdf = host_tables_to_device(tables)
     st = ops.new_stats()
     guide = None if glen is None else ops.sampling_guide(cdf, glen)
-    ops.sp_step(md, 3, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, 7, st, ops.sp_workspace(md, 3),
-                guide=guide)
+    b = ops.DeviceParticles(1, cap, False)
+    ops.sp_step(md, 3, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, b, 7, st,
+                ops.sp_workspace(md, 3), guide=guide)
     ref, rst = orc.sp_step(md, hp, tables[1:], slot, step=7, seed=3)
-    assert_particles_equal(a.view(), ref.view(), "many pairs")
+    assert_particles_equal(b.view(), ref.view(), "many pairs")
     assert to_np(st)[L.ST_PAIRS] == rst[orc.ST_PAIRS]
 
 
@@ -205,10 +208,11 @@ def test_cell_slot_subset(orc):
     a.load(hp.n, v["x"], v["M"], v["s"])
     n0, thr, cdf = host_tables_to_device(t)
     st = ops.new_stats()
-    ops.sp_step(md, 1, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, 2, st, ops.sp_workspace(md, 1))
+    b = ops.DeviceParticles(1, cap, False)
+    ops.sp_step(md, 1, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, b, 2, st, ops.sp_workspace(md, 1))
     ref, rst = orc.sp_step(md, hp, t[1:], slot, step=2, seed=1)
     assert rst[orc.ST_PAIRS] > 0
-    assert_particles_equal(a.view(), ref.view(), "cell subset")
+    assert_particles_equal(b.view(), ref.view(), "cell subset")
 
 
 def test_2d_step_and_annihilation(orc):
@@ -233,17 +237,16 @@ def test_2d_step_and_annihilation(orc):
     for s in range(4):
         fused = s % 2 == 1
         hp, hst = orc.sp_step(md, hp, tables[1:], slot, step=s, seed=seed)
-        ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, s, st, ws, hist=hist if fused else None,
+        ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, b, s, st, ws, hist=hist if fused else None,
                     guide=guide if s >= 2 else None)
-        assert_particles_equal(a.view(), hp.view(), f"2-D step {s}")
+        assert_particles_equal(b.view(), hp.view(), f"2-D step {s}")
         hp, hh_p, hh_m, hst = orc.sp_annihilate(md, hp, step=s, seed=seed, capacity=cap)
         if fused:
             h = to_np(hist)
             nb = ops.n_bins(md)
             assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"2-D step hist {s}"
-        ops.sp_annihilate(md, seed, a, b, hist, s, st, ws, hist_ready=fused)
-        assert_particles_equal(b.view(), hp.view(), f"2-D annihilate {s}")
-        a, b = b, a
+        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=fused)
+        assert_particles_equal(a.view(), hp.view(), f"2-D annihilate {s}")
     assert hst[orc.ST_MIXED] > 0
 
 
@@ -256,7 +259,10 @@ def test_empty_ensemble(orc):
     slot = torch.arange(50, dtype=torch.int32, device=dev())
     z32 = torch.zeros(50, dtype=torch.int32, device=dev())
     cdf = torch.zeros((50, 8), dtype=torch.int64, device=dev())
-    ops.sp_step(md, 0, slot, z32, z32, cdf, a, 0, st, ws)
+    b.d_n.fill_(5)
     hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev())
-    ops.sp_annihilate(md, 0, a, b, hist, 0, st, ws)
-    assert b.count() == 0 and to_np(st)[L.ST_N] == 0
+    ops.sp_step(md, 0, slot, z32, z32, cdf, a, b, 0, st, ws, hist=hist)
+    assert b.count() == 0 and to_np(st)[L.ST_N] == 0 and to_np(st)[L.ST_CUM_STEPS] == 1
+    a.d_n.fill_(5)
+    ops.sp_annihilate(md, 0, b, a, hist, 0, st, ws, hist_ready=True)
+    assert a.count() == 0 and to_np(st)[L.ST_N] == 0 and to_np(hist).sum() == 0
