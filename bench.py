@@ -50,10 +50,11 @@ def _events():
 
 # Algorithmic HBM bytes per launch of each particle kernel, from the running sums the
 # library keeps (S = stats): what the pass must move at minimum with 9-byte particles
-# (x 4 + M 4 + s 1, FP32 positions).  The histogram and the tables are L2-resident.
+# (x 4 + M 4 + s 1, FP32 positions).  The histogram and the tables are L2-resident; the
+# pair counts the two sp_step passes hand over are not counted (an implementation choice).
 KERNEL_BYTES = {
-    "step_apply": lambda S, L: 13 * S[L.ST_CUM_N] + 18 * S[L.ST_CUM_PAIRS],   # read 9 + write x 4; 2 children
     "step_count": lambda S, L: 5 * S[L.ST_CUM_N],                              # read x 4 + s 1
+    "step_apply": lambda S, L: 18 * S[L.ST_CUM_N] + 18 * S[L.ST_CUM_PAIRS],   # read 9, write 9; 2 children
     "annih_count": lambda S, L: 9 * S[L.ST_CUM_ANNIH_IN],                      # read 9
     "annih_write": lambda S, L: (9 * S[L.ST_CUM_ANNIH_IN] + 9 * S[L.ST_CUM_KEPT]
                                  + 9 * S[L.ST_CUM_REGEN]),                     # read 9, write kept + placed

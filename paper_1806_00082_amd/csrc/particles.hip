@@ -41,14 +41,22 @@ constexpr int BC = PT;      // bins per bin chunk
 constexpr int WPB = PT / 64;  // waves per workgroup
 constexpr int NW = PB * WPB;  // wave chunks of the ordered passes
 
+constexpr int PLACE_BLOCKS = PB;  // workgroups placing regenerated / initial particles
+
 // Workspace (sp_workspace_size): int64 scalars[16] | int64 bcnt[PB] | int64 wcnt[NW] |
-// int64 bpart[PB] | int64 bmixed[PB] | int32 csum[n_chunks] | uint8 occ[n_cells].
+// int64 bpart[PB] | int64 bmixed[PB] | int64 kpre[PB] | int64 bpre[PB] |
+// int32 pstart[PLACE_BLOCKS] | int32 csum[n_chunks] | uint8 occ[n_cells].
+enum { SC_GO = 0, SC_PLACED = 1, SC_KEPT = 2 };
+
 struct WS {
     long long* sc;
     long long* bcnt;    // per workgroup of a counting pass: its count
     long long* wcnt;    // per wave of a counting pass: its count
     long long* bpart;   // per bin workgroup: particles to place
     long long* bmixed;  // per bin workgroup: mixed bins
+    long long* kpre;    // exclusive prefix of the survivor counts (bcnt) of sp_annihilate
+    long long* bpre;    // inclusive prefix of bpart
+    int* pstart;        // per placing workgroup: first bin workgroup of its slot range
     int* csum;          // per bin chunk: particles to place
     uint8_t* occ;
 };
@@ -63,14 +71,18 @@ static WS carve(void* ws, long n_bins) {
     w.wcnt = w.bcnt + PB;
     w.bpart = w.wcnt + NW;
     w.bmixed = w.bpart + PB;
-    w.csum = reinterpret_cast<int*>(w.bmixed + PB);
+    w.kpre = w.bmixed + PB;
+    w.bpre = w.kpre + PB;
+    w.pstart = reinterpret_cast<int*>(w.bpre + PB);
+    w.csum = w.pstart + PLACE_BLOCKS;
     w.occ = reinterpret_cast<uint8_t*>(w.csum + (n_chunks_for(n_bins) + 1) / 2 * 2);
     return w;
 }
 
 static size_t ws_bytes_for(long n_bins, long n_cells) {
-    return sizeof(long long) * (16 + 3 * (size_t)PB + (size_t)NW) +
-           sizeof(int) * (size_t)((n_chunks_for(n_bins) + 1) / 2 * 2) + (size_t)n_cells;
+    return sizeof(long long) * (16 + 5 * (size_t)PB + (size_t)NW) +
+           sizeof(int) * (size_t)(PLACE_BLOCKS + (n_chunks_for(n_bins) + 1) / 2 * 2) +
+           (size_t)n_cells;
 }
 
 constexpr int IT = 4;          // particles per lane in the streaming passes
@@ -645,7 +657,7 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
                         abs_x += a == 1;
                         abs_m += a == 2;
                         const int8_t cs = a ? (int8_t)0 : (int8_t)(sg * ps);
-                        if (o < cap_out) {  // always true after the capacity check
+                        if (o >= n && o < cap_out) {  // always true after the capacity check
                             xo[o] = cx;
                             Mo[o] = (MT)cm;
                             if (DIM == 2) {
@@ -887,89 +899,130 @@ __device__ void place_chunk(const Geo& g, const BinCount& bc, int mode, uint32_t
     __syncthreads();  // the LDS tables are rewritten for the next chunk
 }
 
+// Between the counting and the writing pass of sp_annihilate (mode 1) / sp_init (mode 0),
+// one workgroup: prefix of the particles to place per bin workgroup (bpre, inclusive) and of
+// the survivors per particle workgroup (kpre, exclusive), the capacity check, the counts
+// and statistics, and for every placing workgroup the bin workgroup where its equal share of
+// output slots starts.
+constexpr int ST_THREADS = 1024;
+
+__global__ __launch_bounds__(ST_THREADS) void annih_scan(int mode, int place_blocks,
+                                                         const long long* d_n_in,
+                                                         long long* d_n_out, long long capacity,
+                                                         long long* stats, WS w) {
+    __shared__ long long bp[PB];
+    __shared__ long long part[ST_THREADS];
+    __shared__ long long tot[2];
+    if (stats[WK_ST_OVERFLOW] != 0) {
+        if (threadIdx.x == 0) w.sc[SC_GO] = 0;
+        return;
+    }
+    constexpr int per = PB / ST_THREADS;
+    // exclusive / inclusive scans of PB values, per thread `per` consecutive ones
+    auto scan = [&](const long long* in, long long* out_excl, long long* out_incl, long long* total) {
+        long long loc[per], acc = 0;
+        for (int k = 0; k < per; ++k) {
+            loc[k] = in[threadIdx.x * per + k];
+            acc += loc[k];
+        }
+        part[threadIdx.x] = acc;
+        __syncthreads();
+        for (int o = 1; o < ST_THREADS; o <<= 1) {  // Hillis-Steele over the thread sums
+            const long long v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+            __syncthreads();
+            part[threadIdx.x] += v;
+            __syncthreads();
+        }
+        long long run = part[threadIdx.x] - acc;
+        for (int k = 0; k < per; ++k) {
+            if (out_excl) out_excl[threadIdx.x * per + k] = run;
+            run += loc[k];
+            if (out_incl) out_incl[threadIdx.x * per + k] = run;
+        }
+        if (threadIdx.x == ST_THREADS - 1) *total = part[ST_THREADS - 1];
+        __syncthreads();
+    };
+    scan(w.bpart, nullptr, bp, &tot[0]);
+    if (mode == 1) {
+        scan(w.bcnt, w.kpre, nullptr, &tot[1]);
+    } else if (threadIdx.x == 0) {
+        tot[1] = 0;
+    }
+    long long mx = 0;
+    for (int k = threadIdx.x; k < PB; k += ST_THREADS) {
+        w.bpre[k] = bp[k];
+        mx += w.bmixed[k];
+    }
+    mx = wave_sum_ll(mx);
+    __syncthreads();
+    const long long placed = tot[0], kept = tot[1];
+    const long per_pl = (long)((placed + place_blocks - 1) / place_blocks);
+    for (int k = threadIdx.x; k < place_blocks; k += ST_THREADS)
+        w.pstart[k] = upper_bound_lds(bp, PB, (long long)min((long)placed, (long)k * per_pl));
+    // mixed-bin total: one value per wave, summed by thread 0
+    __shared__ long long wmx[ST_THREADS / 64];
+    if ((threadIdx.x & 63) == 0) wmx[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    long long mixed = 0;
+    for (int k = 0; k < ST_THREADS / 64; ++k) mixed += wmx[k];
+    const long long n_out = placed + kept;
+    if (n_out > capacity) {
+        stats[WK_ST_NEEDED] = n_out;
+        stats[WK_ST_OVERFLOW] = 1;
+        w.sc[SC_GO] = 0;
+        return;
+    }
+    w.sc[SC_GO] = 1;
+    w.sc[SC_PLACED] = placed;
+    w.sc[SC_KEPT] = kept;
+    stats[WK_ST_N] = n_out;
+    stats[WK_ST_NEEDED] = 0;
+    if (mode == 1) {
+        const long long n_in = *d_n_in;
+        stats[WK_ST_KEPT] = kept;
+        stats[WK_ST_REGEN] = placed;
+        stats[WK_ST_MIXED] = mixed;
+        stats[WK_ST_CUM_ANNIH_IN] += n_in;
+        stats[WK_ST_CUM_KEPT] += kept;
+        stats[WK_ST_CUM_REGEN] += placed;
+    }
+    *d_n_out = n_out;
+}
+
 // Writing pass of sp_annihilate (mode 1) and sp_init (mode 0).  Output: the particles placed
 // bin by bin (mixed bins' survivors of rule 2, or the initial state), then, in mode 1, the
-// particles of single-sign bins in input order.  Every workgroup first totals the counts of
-// the counting pass (capacity check, offsets).  Workgroups below part_blocks copy their
-// waves' survivors, in order; the place_blocks after them split the placed particles into
-// equal ranges of output slots and fill their range bin chunk by bin chunk.
+// particles of single-sign bins in input order.  Workgroups below part_blocks copy their
+// waves' survivors, in order, through an LDS stage; the place_blocks after them fill equal
+// ranges of the placed particles' output slots bin chunk by bin chunk.
 template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int place_blocks,
                                                   BinCount bc, int mode, uint32_t c1,
                                                   uint32_t tag, const T* x, const T* y,
                                                   const MT* M, const MT* My, const int8_t* s,
                                                   const long long* d_n_in, T* xo, T* yo, MT* Mo,
-                                                  MT* Myo, int8_t* so, long long* d_n_out,
-                                                  long long capacity, long long* stats, WS w) {
-    constexpr int STAGE = WT * (2 * (int)sizeof(T) + 2 * (int)sizeof(int) + 1);  // per wave
-    constexpr int SMEM = PB * 8 > WPB * STAGE ? PB * 8 : WPB * STAGE;
+                                                  MT* Myo, int8_t* so, long long capacity,
+                                                  WS w) {
+    constexpr int STAGE = WT * (DIM * (int)sizeof(T) + DIM * (int)sizeof(int) + 1);  // per wave
     __shared__ int lds5[5];
-    __shared__ long long red[PT / 64];
-    __shared__ __align__(16) char smem[SMEM];  // placers: prefix of bpart; keepers: wave stages
+    __shared__ __align__(16) char smem[WPB * STAGE];  // keepers: one stage per wave
     __shared__ int cs_ex[PT], cs_in[PT];
     __shared__ int bo_ex[BC], bo_in[BC];
-    long long* bp = reinterpret_cast<long long*>(smem);  // inclusive prefix of bpart
-    if (stats[WK_ST_OVERFLOW] != 0) return;
-    const bool part = (int)blockIdx.x < part_blocks;
-    long long placed;  // particles placed bin by bin: the offset of the kept ones
-    {
-        constexpr int per = PB / PT;
-        long long loc[per], acc = 0;
-#pragma unroll
-        for (int k = 0; k < per; ++k) {
-            loc[k] = w.bpart[threadIdx.x * per + k];
-            acc += loc[k];
-        }
-        long long run = block_excl_scan_ll(acc, &placed, red);
-        if (!part) {
-#pragma unroll
-            for (int k = 0; k < per; ++k) {
-                run += loc[k];
-                bp[threadIdx.x * per + k] = run;
-            }
-        }
-        __syncthreads();  // bp is read across threads below
-    }
-    long long kept = 0, wave_off = 0;
-    if (part_blocks > 0) kept = chunk_offsets(w, part, &wave_off, red);
-    const long long n_out = placed + kept;
-    if (n_out > capacity) {  // the same decision in every workgroup
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            stats[WK_ST_NEEDED] = n_out;
-            stats[WK_ST_OVERFLOW] = 1;
-        }
-        return;
-    }
-    if (blockIdx.x == 0) {
-        long long mx = 0;
-        for (int k = threadIdx.x; k < PB; k += PT) mx += w.bmixed[k];
-        mx = block_sum_ll(mx, red);
-        if (threadIdx.x == 0) {
-            stats[WK_ST_N] = n_out;
-            stats[WK_ST_NEEDED] = 0;
-            if (mode == 1) {
-                stats[WK_ST_KEPT] = kept;
-                stats[WK_ST_REGEN] = placed;
-                stats[WK_ST_MIXED] = mx;
-                stats[WK_ST_CUM_ANNIH_IN] += *d_n_in;
-                stats[WK_ST_CUM_KEPT] += kept;
-                stats[WK_ST_CUM_REGEN] += placed;
-            }
-            *d_n_out = n_out;
-        }
-    }
-    if (part) {
-        const int lane = threadIdx.x & 63;
+    if (w.sc[SC_GO] == 0) return;
+    const long long placed = w.sc[SC_PLACED];
+    if ((int)blockIdx.x < part_blocks) {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         // per-wave stage: the tile's survivors, compacted, then written out contiguously
-        char* st = smem + (threadIdx.x >> 6) * STAGE;
+        char* st = smem + wv * STAGE;
         T* sx = reinterpret_cast<T*>(st);
-        T* sy = sx + WT;
-        int* sm = reinterpret_cast<int*>(sy + WT);
-        int* smy = sm + WT;
-        int8_t* ssg = reinterpret_cast<int8_t*>(smy + WT);
+        T* sy = sx + (DIM == 2 ? WT : 0);
+        int* sm = reinterpret_cast<int*>(sx + DIM * WT);
+        int* smy = sm + (DIM == 2 ? WT : 0);
+        int8_t* ssg = reinterpret_cast<int8_t*>(sm + DIM * WT);
         long lo, hi;
-        wave_chunk((long)*d_n_in, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
-        long long run = placed + wave_off;
+        wave_chunk((long)*d_n_in, (long)blockIdx.x * WPB + wv, &lo, &hi);
+        long long run = placed + w.kpre[blockIdx.x];
+        for (int j = 0; j < wv; ++j) run += w.wcnt[(long)blockIdx.x * WPB + j];
         Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
         load4<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
         for (long t0 = lo; t0 < hi; t0 += WT) {  // per wave, no workgroup barriers
@@ -1021,8 +1074,8 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
     const long per = (placed + place_blocks - 1) / place_blocks;
     const long s_lo = min((long)placed, k * per), s_hi = min((long)placed, s_lo + per);
     if (s_lo >= s_hi) return;
-    for (int c = upper_bound_lds(bp, PB, (long long)s_lo); c < PB; ++c) {  // uniform
-        const long c_start = c ? (long)bp[c - 1] : 0;
+    for (int c = w.pstart[k]; c < PB; ++c) {  // uniform
+        const long c_start = c ? (long)w.bpre[c - 1] : 0;
         if (c_start >= s_hi) break;
         const long j0 = min(g.n_chunks, (long)c * g.gpb), j1 = min(g.n_chunks, j0 + g.gpb);
         long run = c_start;
@@ -1191,8 +1244,6 @@ static void launch_step(const Geo& g, uint32_t step, const int32_t* cs, const ui
                   out->s, d_n_out, cap, hist, stats, st, w);
 }
 
-constexpr int PLACE_BLOCKS = PB;  // workgroups placing regenerated / initial particles
-
 template <typename T, typename MT, int DIM>
 static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp_particles* out,
                          int32_t* hist, int hist_ready, long long* stats, WS w, hipStream_t s) {
@@ -1208,13 +1259,15 @@ static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp
                   in->s, d_n, cap_in, hist, stats);
     }
     const BinCount bc{nullptr, hist, g.n_bins};
+    long long* d_n_out = reinterpret_cast<long long*>(out->d_n);
     WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(2 * PB), dim3(PT), 0, s, g, PB, bc, x, y,
               M, My, in->s, d_n, cap_in, stats, w);
+    WK_LAUNCH("annih_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 1, PLACE_BLOCKS, d_n,
+              d_n_out, (long long)out->capacity, stats, w);
     WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(PB + PLACE_BLOCKS), dim3(PT), 0, s, g,
               PB, PLACE_BLOCKS, bc, 1, step, (uint32_t)TAG_ANNIH, x, y, M, My, in->s, d_n,
               static_cast<T*>(out->x), static_cast<T*>(out->y), static_cast<MT*>(out->M),
-              static_cast<MT*>(out->My), out->s, reinterpret_cast<long long*>(out->d_n),
-              (long long)out->capacity, stats, w);
+              static_cast<MT*>(out->My), out->s, (long long)out->capacity, w);
 }
 
 template <typename T, typename MT, int DIM>
@@ -1224,12 +1277,15 @@ static void launch_init(const Geo& g, const int32_t* counts, sp_particles* out, 
     WK_LAUNCH("init_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, 0, bc,
               (const T*)nullptr, (const T*)nullptr, (const MT*)nullptr, (const MT*)nullptr,
               (const int8_t*)nullptr, (const long long*)nullptr, 0LL, stats, w);
+    WK_LAUNCH("init_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 0, PLACE_BLOCKS,
+              (const long long*)nullptr, reinterpret_cast<long long*>(out->d_n),
+              (long long)out->capacity, stats, w);
     WK_LAUNCH("init_write", (annih_write<T, MT, DIM>), dim3(PLACE_BLOCKS), dim3(PT), 0, s, g, 0,
               PLACE_BLOCKS, bc, 0, 0xFFFFFFFFu, (uint32_t)TAG_INIT, (const T*)nullptr,
               (const T*)nullptr, (const MT*)nullptr, (const MT*)nullptr, (const int8_t*)nullptr,
               (const long long*)nullptr, static_cast<T*>(out->x), static_cast<T*>(out->y),
               static_cast<MT*>(out->M), static_cast<MT*>(out->My), out->s,
-              reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, stats, w);
+              (long long)out->capacity, w);
 }
 
 }  // namespace wk
