@@ -38,9 +38,11 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 
 # HBM traffic per launch (GB) over the timed steps of this benchmark, from two rocprofv3
 # counter runs (FETCH_SIZE, then WRITE_SIZE) of `bench.py --no-forms --no-cpu --no-trace
-# --copy-calibration`, scaled by what the counters read for a 1 GiB device copy.  Only for
-# kernels unchanged since the counters were taken (none at present: null in the output).
-TRAFFIC = {}
+# --copy-calibration`, scaled by what the counters read for a 1 GiB device copy (fetch x2.0,
+# write x1.0).  Taken for the kernels as they are now; an entry is dropped when its kernel
+# changes until the counters are taken again.
+TRAFFIC = {"step_apply": 0.3024, "step_count": 0.1002, "annih_count": 0.1120,
+           "annih_write": 0.2149}
 
 
 def _events():
