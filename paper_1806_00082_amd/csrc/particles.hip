@@ -231,30 +231,40 @@ __device__ __forceinline__ void store4(T* x, T* y, MT* M, MT* My, int8_t* s, lon
 }
 
 // Pair counts of four consecutive particles kept between the two passes of sp_step in the
-// first four bytes of each particle's slot of the output positions (unused until the second
-// pass writes the particle there).
+// output buffer, which the second pass overwrites only after reading them: one byte per
+// particle in the sign array, and for a count of 255 or more (byte 255) the full count in the
+// first four bytes of the particle's position slot.
 template <typename T>
-__device__ __forceinline__ void store_np4(T* xo, long id, long hi, const int* np) {
-    if (sizeof(T) == 4 && id + IT <= hi) {
-        *reinterpret_cast<int4*>(xo + id) = make_int4(np[0], np[1], np[2], np[3]);
+__device__ __forceinline__ void store_np4(T* xo, int8_t* so, long id, long hi, const int* np) {
+    uint8_t b[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        b[k] = np[k] >= 255 ? (uint8_t)255 : (uint8_t)np[k];
+        if (np[k] >= 255 && id + k < hi) *reinterpret_cast<int*>(xo + id + k) = np[k];
+    }
+    if (id + IT <= hi) {
+        *reinterpret_cast<uchar4*>(so + id) = make_uchar4(b[0], b[1], b[2], b[3]);
     } else {
 #pragma unroll
         for (int k = 0; k < IT; ++k)
-            if (id + k < hi) *reinterpret_cast<int*>(xo + id + k) = np[k];
+            if (id + k < hi) so[id + k] = (int8_t)b[k];
     }
 }
 template <typename T>
-__device__ __forceinline__ void load_np4(const T* xo, long id, long hi, int* np) {
-    if (sizeof(T) == 4 && id + IT <= hi) {
-        const int4 v = *reinterpret_cast<const int4*>(xo + id);
+__device__ __forceinline__ void load_np4(const T* xo, const int8_t* so, long id, long hi, int* np) {
+    if (id + IT <= hi) {
+        const uchar4 v = *reinterpret_cast<const uchar4*>(so + id);
         np[0] = v.x;
         np[1] = v.y;
         np[2] = v.z;
         np[3] = v.w;
     } else {
 #pragma unroll
-        for (int k = 0; k < IT; ++k) np[k] = id + k < hi ? *reinterpret_cast<const int*>(xo + id + k) : 0;
+        for (int k = 0; k < IT; ++k) np[k] = id + k < hi ? (int)(uint8_t)so[id + k] : 0;
     }
+#pragma unroll
+    for (int k = 0; k < IT; ++k)
+        if (np[k] == 255) np[k] = *reinterpret_cast<const int*>(xo + id + k);
 }
 
 // Pairs created by particle id this step (postulate II with the integer tables).
@@ -282,6 +292,43 @@ __device__ __forceinline__ int pairs_of(const Geo& g, uint32_t id, uint32_t step
     // 2^30 pairs already exceed any capacity (< 2^31): larger counts are reported as that
     if (base >= (1u << 30)) return 1 << 30;
     return (int)base + (w->v[0] < t ? 1 : 0);
+}
+
+// Pair count only (postulate II), with (n0, thr) of the particle's cell taken from a
+// per-workgroup LDS table when the mesh is small enough (ct != nullptr), else through
+// cell_slot from global memory.  Only the first Philox word is used.
+constexpr int CT_MAX = 1024;  // cells of the LDS creation table
+
+template <typename T, int DIM>
+__device__ __forceinline__ int pairs_count(const Geo& g, uint32_t id, uint32_t step, T px, T py,
+                                           int8_t sv, const uint2* ct,
+                                           const int32_t* __restrict__ cell_slot,
+                                           const uint32_t* __restrict__ n0,
+                                           const uint32_t* __restrict__ thr) {
+    if (sv == 0) return 0;
+    const int cx = cell_index<T>(px, g.nx);
+    if (cx < 0) return 0;
+    int c = cx;
+    if (DIM == 2) {
+        const int cy = cell_index<T>(py, g.ny);
+        if (cy < 0) return 0;
+        c = cy * g.nx + cx;
+    }
+    uint32_t base, t;
+    if (ct != nullptr) {
+        const uint2 e = ct[c];
+        base = e.x;
+        t = e.y;
+    } else {
+        const int sl = cell_slot[c];
+        if (sl < 0) return 0;
+        base = n0[sl];
+        t = thr[sl];
+    }
+    if (base == 0 && t == 0) return 0;
+    const u32x4 w = philox(id, step, 0u, TAG_CREATE, g.seed);
+    if (base >= (1u << 30)) return 1 << 30;
+    return (int)base + (w.v[0] < t ? 1 : 0);
 }
 
 // Smallest t with u < T[t] (T non-decreasing, ending at 2^32 > u), searched in [lo, hi]:
@@ -505,9 +552,11 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
                                                  const T* x, const T* y, const MT* M,
                                                  const MT* My, const int8_t* s,
                                                  const long long* d_n_in, long long cap_in,
-                                                 T* xo, long long cap_out, int32_t* hist,
-                                                 long long* stats, long long st, WS w) {
+                                                 T* xo, int8_t* so, long long cap_out,
+                                                 int32_t* hist, long long* stats, long long st,
+                                                 WS w) {
     __shared__ long long red[PT / 64];
+    __shared__ uint2 ct_lds[CT_MAX];
     if (stats[WK_ST_OVERFLOW] != 0) return;
     const long n = (long)*d_n_in;
     if (n < 0 || n > cap_in || n > cap_out) {  // refused: nothing is written
@@ -526,6 +575,16 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
         stats[WK_ST_ABS_X] = 0;
         stats[WK_ST_ABS_M] = 0;
     }
+    const long n_cells = (long)g.nx * g.ny;
+    const uint2* ct = nullptr;
+    if (n_cells <= CT_MAX) {  // (n0, thr) per cell in LDS
+        for (int c = threadIdx.x; c < n_cells; c += PT) {
+            const int sl = cell_slot[c];
+            ct_lds[c] = sl < 0 ? make_uint2(0u, 0u) : make_uint2(n0[sl], thr[sl]);
+        }
+        __syncthreads();
+        ct = ct_lds;
+    }
     long lo, hi;
     wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
     long long cnt = 0;
@@ -538,13 +597,11 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
         int np[IT];
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
-            int slot;
-            u32x4 r;
-            np[k] = pairs_of<T, DIM>(g, (uint32_t)(id + k), step, p.x[k], p.y[k], p.s[k], cell_slot,
-                                     n0, thr, &slot, &r);
+            np[k] = pairs_count<T, DIM>(g, (uint32_t)(id + k), step, p.x[k], p.y[k], p.s[k], ct,
+                                        cell_slot, n0, thr);
             cnt += np[k];
         }
-        store_np4<T>(xo, id, hi, np);  // for pass 2
+        store_np4<T>(xo, so, id, hi, np);  // for pass 2
     }
     store_counts(w, wave_sum_ll(cnt), red);
 }
@@ -553,7 +610,7 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
 // each wave then walks its chunk: the drifted and absorbed parents go to their own index and
 // (HIST) into the histogram, and every particle that creates pairs goes into a per-wave
 // queue in LDS (id, slot of its first child); the pair counts come from pass 1 (kept in the
-// output's position slots).  Between tiles, once the queue could not take another tile, and
+// output buffer).  Between tiles, once the queue could not take another tile, and
 // at the end of the chunk, the wave drains it one particle per lane: the parent's draws are
 // redone (same Philox counters), its pairs' momentum offsets sampled from its CDF row and its
 // children written.  One chain of dependent table loads serves up to 64 creating particles,
@@ -683,7 +740,7 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
         Part4<T, DIM> p = nxt;
         load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
         int np[IT];
-        load_np4<T>(xo, id, hi, np);  // left by pass 1 (before the parents overwrite it below)
+        load_np4<T>(xo, so, id, hi, np);  // left by pass 1 (before the parents overwrite it below)
         long long npt = 0;
 #pragma unroll
         for (int k = 0; k < IT; ++k) npt += np[k];
@@ -750,8 +807,47 @@ struct BinCount {
     }
 };
 
-__device__ __forceinline__ bool keeps_bin(long b, const int32_t* hist, long n_bins) {
-    return b >= 0 && !(hist[b] > 0 && hist[n_bins + b] > 0);
+// The histogram bins a workgroup's particles fall in, copied to LDS (W bins per sign from a
+// quarter window below the smallest bin of its waves' first tiles); the survivor test reads
+// there and falls back to global memory outside the window.
+constexpr int KW = 2048;
+
+struct KeepWindow {
+    const int* lw;  // [2][KW] in LDS
+    long base;
+    const int32_t* hist;
+    long n_bins;
+
+    __device__ __forceinline__ bool keeps(long b) const {
+        if (b < 0) return false;
+        const long k = b - base;
+        int hp, hm;
+        if (k >= 0 && k < KW) {
+            hp = lw[k];
+            hm = lw[KW + k];
+        } else {
+            hp = hist[b];
+            hm = hist[n_bins + b];
+        }
+        return !(hp > 0 && hm > 0);
+    }
+};
+
+__device__ KeepWindow keep_window(long b_min_thread, int* lw, long* wmin4, const int32_t* hist,
+                                  long n_bins) {
+    long b0 = b_min_thread;
+    for (int o = 32; o > 0; o >>= 1) b0 = min(b0, (long)__shfl_xor(b0, o, 64));
+    if ((threadIdx.x & 63) == 0) wmin4[threadIdx.x >> 6] = b0;
+    __syncthreads();
+    const long m = min(min(wmin4[0], wmin4[1]), min(wmin4[2], wmin4[3]));
+    const long base = m == LONG_MAX ? 0 : max(0L, m - KW / 4);
+    for (int k = threadIdx.x; k < KW; k += PT) {
+        const long b = base + k;
+        lw[k] = b < n_bins ? hist[b] : 0;
+        lw[KW + k] = b < n_bins ? hist[n_bins + b] : 0;
+    }
+    __syncthreads();
+    return KeepWindow{lw, base, hist, n_bins};
 }
 
 // ----------------------------------------------------------------------------- annihilation
@@ -802,6 +898,8 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, int part_blocks, BinCou
                                                   const long long* d_n_in, long long cap_in,
                                                   long long* stats, WS w) {
     __shared__ long long red[PT / 64];
+    __shared__ int lw[2 * KW];
+    __shared__ long wmin[PT / 64];
     if (stats[WK_ST_OVERFLOW] != 0) return;
     if (part_blocks > 0) {
         const long n = (long)*d_n_in;
@@ -815,6 +913,8 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, int part_blocks, BinCou
         if ((int)blockIdx.x < part_blocks) {
             long lo, hi;
             wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
+            const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw,
+                                              wmin, bc.hist, g.n_bins);
             long long a = 0;
             Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
             load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
@@ -824,8 +924,7 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, int part_blocks, BinCou
                 load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
 #pragma unroll
                 for (int k = 0; k < IT; ++k)
-                    a += keeps_bin(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]),
-                                   bc.hist, g.n_bins) ? 1 : 0;
+                    a += kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k])) ? 1 : 0;
             }
             store_counts(w, wave_sum_ll(a), red);
             return;
@@ -1004,10 +1103,17 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
                                                   MT* Myo, int8_t* so, long long capacity,
                                                   WS w) {
     constexpr int STAGE = WT * (DIM * (int)sizeof(T) + DIM * (int)sizeof(int) + 1);  // per wave
+    constexpr int KEEP_LDS = WPB * STAGE + 2 * KW * (int)sizeof(int);
+    constexpr int PLACE_LDS = 2 * PT * (int)sizeof(int) + 2 * BC * (int)sizeof(int);
     __shared__ int lds5[5];
-    __shared__ __align__(16) char smem[WPB * STAGE];  // keepers: one stage per wave
-    __shared__ int cs_ex[PT], cs_in[PT];
-    __shared__ int bo_ex[BC], bo_in[BC];
+    __shared__ long wmin[PT / 64];
+    // keepers: one stage per wave + histogram window; placers: chunk and bin prefix tables
+    __shared__ __align__(16) char smem[KEEP_LDS > PLACE_LDS ? KEEP_LDS : PLACE_LDS];
+    int* lw = reinterpret_cast<int*>(smem + WPB * STAGE);
+    int* cs_ex = reinterpret_cast<int*>(smem);
+    int* cs_in = cs_ex + PT;
+    int* bo_ex = cs_in + PT;
+    int* bo_in = bo_ex + BC;
     if (w.sc[SC_GO] == 0) return;
     const long long placed = w.sc[SC_PLACED];
     if ((int)blockIdx.x < part_blocks) {
@@ -1021,6 +1127,8 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
         int8_t* ssg = reinterpret_cast<int8_t*>(sm + DIM * WT);
         long lo, hi;
         wave_chunk((long)*d_n_in, (long)blockIdx.x * WPB + wv, &lo, &hi);
+        const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw,
+                                          wmin, bc.hist, g.n_bins);
         long long run = placed + w.kpre[blockIdx.x];
         for (int j = 0; j < wv; ++j) run += w.wcnt[(long)blockIdx.x * WPB + j];
         Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
@@ -1033,8 +1141,7 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
             int kt = 0;
 #pragma unroll
             for (int k = 0; k < IT; ++k) {
-                kp[k] = keeps_bin(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]),
-                                  bc.hist, g.n_bins);
+                kp[k] = kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]));
                 kt += kp[k];
             }
             const int inc = wave_incl_scan(kt);
@@ -1233,7 +1340,7 @@ static void launch_step(const Geo& g, uint32_t step, const int32_t* cs, const ui
     MT* Mo = static_cast<MT*>(out->M);
     MT* Myo = static_cast<MT*>(out->My);
     WK_LAUNCH("step_count", (step_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, step, cs, n0, thr,
-              x, y, M, My, in->s, d_n_in, (long long)in->capacity, xo, cap, hist, stats, st, w);
+              x, y, M, My, in->s, d_n_in, (long long)in->capacity, xo, out->s, cap, hist, stats, st, w);
     if (hist)
         WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, true>), dim3(PB), dim3(PT), 0, s, g, step, cs,
                   n0, thr, cdf, guide, guide_len, x, y, M, My, in->s, d_n_in, xo, yo, Mo, Myo,
