@@ -233,8 +233,13 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     constexpr int WAVES_M = 4 / WAVES_N;
     constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N, BK = LP_BK, LD = BK + 8;
     static_assert(BM == KE_BM, "row tile");
-    __shared__ __attribute__((aligned(16))) uint16_t Dh[2][BM][LD];
-    __shared__ __attribute__((aligned(16))) uint16_t Dl[2][TR::split ? BM : 1][LD];
+    // operand tiles during the contraction; the same bytes stage the output afterwards
+    // (16 * WAVES_M rows x BN columns of FP32 at a time)
+    constexpr int OPS = 2 * BM * LD * 2 + 2 * (TR::split ? BM : 1) * LD * 2;
+    constexpr int STG = 16 * WAVES_M * BN * 4;
+    __shared__ __attribute__((aligned(16))) char lds_ops[OPS > STG ? OPS : STG];
+    auto Dh = reinterpret_cast<uint16_t(*)[BM][LD]>(lds_ops);
+    auto Dl = reinterpret_cast<uint16_t(*)[TR::split ? BM : 1][LD]>(lds_ops + 2 * BM * LD * 2);
     __shared__ double Wv[KE_WIN];
     __shared__ long rbase[BM];
     __shared__ int rcell[BM];
@@ -318,6 +323,39 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
         buf ^= 1;
     }
 
+    if (layout == WK_HALF) {
+        // staged through LDS so that whole rows of the half table leave in 16-byte stores
+        float* stg = reinterpret_cast<float*>(lds_ops);  // [16 * WAVES_M][BN]
+        constexpr int SR = 16 * WAVES_M;
+        const int ncol = min(BN, P - col0);
+#pragma unroll
+        for (int tm = 0; tm < WM; ++tm) {
+#pragma unroll
+            for (int tn = 0; tn < WN; ++tn)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    stg[(wr * 16 + 4 * lk + e) * BN + (wc * WN + tn) * 16 + lr] = c * acc[tm][tn][e];
+            __syncthreads();
+            // local row q of the stage is global row row0 + ((q / 16) * WM + tm) * 16 + q % 16
+            if ((P & 3) == 0) {
+                for (int f = threadIdx.x; f < SR * (BN / 4); f += KE_THREADS) {
+                    const int q = f / (BN / 4), c4 = (f - q * (BN / 4)) * 4;
+                    const long row = row0 + ((q / 16) * WM + tm) * 16 + (q & 15);
+                    if (row < R && c4 < ncol)
+                        *reinterpret_cast<float4*>(out + row * P + col0 + c4) =
+                            *reinterpret_cast<const float4*>(stg + q * BN + c4);
+                }
+            } else {
+                for (int f = threadIdx.x; f < SR * BN; f += KE_THREADS) {
+                    const int q = f / BN, cc = f - q * BN;
+                    const long row = row0 + ((q / 16) * WM + tm) * 16 + (q & 15);
+                    if (row < R && cc < ncol) out[row * P + col0 + cc] = stg[q * BN + cc];
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
 #pragma unroll
     for (int tm = 0; tm < WM; ++tm) {
 #pragma unroll
@@ -328,9 +366,7 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
                 const long row = row0 + (wr * WM + tm) * 16 + 4 * lk + e;
                 if (row >= R || t >= P) continue;
                 const float k = c * acc[tm][tn][e];
-                if (layout == WK_HALF) {
-                    out[row * P + t] = k;
-                } else {
+                {
                     float* o = out + row * (long)n_m;
                     if (t < P - 1) {
                         o[P + 1 + t] = k;

@@ -8,6 +8,7 @@
 // A is a stride-N convolution of the potential (the f_V of Sec. 3) built per row tile in
 // LDS; Bm and Pi are tiny (H x P, P) and are formed once per call by surr_prep.
 #include <map>
+#include <type_traits>
 #include <mutex>
 
 #include "lowp.h"
@@ -16,7 +17,7 @@
 namespace wk {
 
 constexpr int SU_THREADS = 256;
-constexpr int SU_BM = 32;            // rows per workgroup (FP32 / BF16 forward)
+constexpr int SU_BM = 32;            // rows per workgroup of the backward
 constexpr int SD_BM = 16;            // rows per workgroup (FP64 forward, backward tiles)
 constexpr int SB_MAXBLK = 1024;      // workgroups of the backward (each loops over row tiles)
 constexpr int SU_MAXH = 256;         // largest hidden width supported
@@ -113,97 +114,120 @@ __global__ __launch_bounds__(SU_THREADS) void surr_fwd_f64(
     }
 }
 
-// FP32 forward on v_mfma_f32_16x16x4_f32 (lane l: A[l%16][l/16], B[l/16][l%16],
-// C[4(l/16)+e][l%16]).  Four waves split the columns; each wave covers all SU_BM rows.
-__global__ __launch_bounds__(SU_THREADS) void surr_fwd_f32(
-    const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
-    int P, int N, int H, int Hk, int Pn, const float* __restrict__ wV, const float* __restrict__ Bf,
-    const float* __restrict__ Pif, float* __restrict__ out) {
-    extern __shared__ float smem_f[];
-    __shared__ int rcell[SU_BM];
-    __shared__ long rbase[SU_BM];
-    float* A = smem_f;  // [SU_BM][Hk + 1], zero padded beyond H
-    const long row0 = (long)blockIdx.x * SU_BM;
-    for (int e = threadIdx.x; e < SU_BM * (Hk + 1); e += blockDim.x) A[e] = 0.f;
-    __syncthreads();
-    conv_rows<SU_BM, float>(V, nx, row0, R, n_cells, cells, P, N, H, wV, A, Hk + 1, rcell, rbase);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    // column tiles of 16 handed to waves round-robin
-    for (int ct = wave; ct * 16 < Pn; ct += 4) {
-        f32x4 acc[SU_BM / 16];
-#pragma unroll
-        for (int tm = 0; tm < SU_BM / 16; ++tm) acc[tm] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < Hk; k0 += 4) {
-            const int g = k0 + lk;
-            const float b = g < H ? Bf[(long)g * Pn + ct * 16 + lr] : 0.f;
-#pragma unroll
-            for (int tm = 0; tm < SU_BM / 16; ++tm) {
-                const float a = A[(tm * 16 + lr) * (Hk + 1) + g];
-                acc[tm] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[tm], 0, 0, 0);
-            }
-        }
-        const int t = ct * 16 + lr;
-        if (t < P) {
-            const float pi = Pif[t];
-#pragma unroll
-            for (int tm = 0; tm < SU_BM / 16; ++tm)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const long r = row0 + tm * 16 + 4 * lk + e;
-                    if (r < R) out[r * P + t] = pi * acc[tm][e];
-                }
-        }
-    }
+// Bm transposed and zero padded to Hk (a multiple of 32), in FP32 and as BF16 bits, so that a
+// lane's MFMA B fragment is contiguous: Bt[t][g] = Bm[g][t].
+__global__ void surr_prep_t(int H, int Hk, int Pn, const float* __restrict__ Bf,
+                            float* __restrict__ Btf, uint16_t* __restrict__ Btb) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)Pn * Hk) return;
+    const int t = (int)(idx / Hk), g = (int)(idx % Hk);
+    const float v = g < H ? Bf[(long)g * Pn + t] : 0.f;
+    Btf[idx] = v;
+    Btb[idx] = bf16_bits_f(v);
 }
 
-// BF16 inference forward on v_mfma_f32_16x16x32_bf16 (operands rounded to bf16, FP32 sums).
-__global__ __launch_bounds__(SU_THREADS) void surr_fwd_bf16(
+// Forward on MFMA (FP32: v_mfma_f32_16x16x4_f32; BF16: v_mfma_f32_16x16x32_bf16 with FP32
+// sums), SF_BM rows per tile, workgroups looping over tiles.  When a tile is a run of
+// consecutive cells of one potential (all cells evaluated), the potential window it needs
+// (SF_BM + n_m values) is staged in LDS once and the stride-N convolution reads it there;
+// otherwise (cell lists, tiles across potentials) rows gather their values from global
+// memory.  A is kept in LDS in the MFMA input type.  The contraction index is permuted per
+// lane group (lane group j of a 16 x 16 x 4 step s takes g = j Hk/4 + s; of a 16 x 16 x 32
+// step s, g = j Hk/4 + 8 s + q), the same for A and B, so that a lane's fragments of
+// consecutive steps are contiguous and load as 16-byte vectors.  Four waves split the
+// column tiles; B fragments come from the transposed table.
+constexpr int SF_BM = 64;
+
+template <bool BF16>
+__global__ __launch_bounds__(SU_THREADS) void surr_fwd_mfma(
     const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
-    int P, int N, int H, int Hk, int Pn, const float* __restrict__ wV, const float* __restrict__ Bf,
+    int P, int N, int H, int Hk, int Pn, const float* __restrict__ wV,
+    const float* __restrict__ Btf, const uint16_t* __restrict__ Btb,
     const float* __restrict__ Pif, float* __restrict__ out) {
-    extern __shared__ float smem_f[];
-    __shared__ int rcell[SU_BM];
-    __shared__ long rbase[SU_BM];
-    float* A = smem_f;  // [SU_BM][Hk + 1]
-    const long row0 = (long)blockIdx.x * SU_BM;
-    for (int e = threadIdx.x; e < SU_BM * (Hk + 1); e += blockDim.x) A[e] = 0.f;
-    __syncthreads();
-    conv_rows<SU_BM, float>(V, nx, row0, R, n_cells, cells, P, N, H, wV, A, Hk + 1, rcell, rbase);
+    using AT = typename std::conditional<BF16, uint16_t, float>::type;
+    extern __shared__ double smem_sf[];
+    __shared__ int rcell[SF_BM];
+    __shared__ long rbase[SF_BM];
+    const int lda = BF16 ? Hk + 8 : Hk + 4;  // 16-byte aligned rows, bank-spread
+    AT* A = reinterpret_cast<AT*>(smem_sf);                                  // [SF_BM][lda]
+    double* Vw = smem_sf + (SF_BM * lda * (int)sizeof(AT) + 7) / 8;          // [SF_BM + 2P]
+    float* Ag = reinterpret_cast<float*>(Vw);  // gather path: FP32 rows [SF_BM][Hk + 1]
+    for (int e = threadIdx.x; e < SF_BM * lda; e += blockDim.x) A[e] = (AT)0;  // pads stay 0
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    for (int ct = wave; ct * 16 < Pn; ct += 4) {
-        f32x4 acc[SU_BM / 16];
-#pragma unroll
-        for (int tm = 0; tm < SU_BM / 16; ++tm) acc[tm] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < Hk; k0 += 32) {
-            s16x8 b;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int g = k0 + 8 * lk + q;
-                b[q] = (short)bf16_bits_f(g < H ? Bf[(long)g * Pn + ct * 16 + lr] : 0.f);
+    const int kq = Hk / 4;  // contraction indices per lane group
+    const long ntiles = (R + SF_BM - 1) / SF_BM;
+    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long row0 = tile * SF_BM;
+        const long rend = min(R, row0 + SF_BM);
+        const bool run = cells == nullptr && n_cells == nx && row0 / nx == (rend - 1) / nx;
+        __syncthreads();  // previous tile's users of A / Vw are done
+        if (run) {
+            const long b = row0 / nx;
+            const int c0 = (int)(row0 - b * nx);
+            const double* Vb = V + b * (long)nx;
+            const int nw = SF_BM + 2 * P;
+            for (int k = threadIdx.x; k < nw; k += blockDim.x)
+                Vw[k] = Vb[min(max(c0 - P + k, 0), nx - 1)];
+            __syncthreads();
+            const int nrow = (int)(rend - row0);
+            for (int e = threadIdx.x; e < SF_BM * H; e += blockDim.x) {
+                const int rr = e / H, g = e - rr * H;
+                double a = 0.0;
+                if (rr < nrow)
+                    for (int p = 0; p < N; ++p) a += (double)wV[p] * Vw[rr + N * g + p];
+                A[rr * lda + g] = BF16 ? (AT)bf16_bits_f((float)a) : (AT)(float)a;
             }
-#pragma unroll
-            for (int tm = 0; tm < SU_BM / 16; ++tm) {
-                s16x8 a;
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    a[q] = (short)bf16_bits_f(A[(tm * 16 + lr) * (Hk + 1) + k0 + 8 * lk + q]);
-                acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                                 __builtin_bit_cast(bf16x8, b),
-                                                                 acc[tm], 0, 0, 0);
+        } else {
+            conv_rows<SF_BM, float>(V, nx, row0, R, n_cells, cells, P, N, H, wV, Ag, Hk + 1, rcell,
+                                    rbase);
+            for (int e = threadIdx.x; e < SF_BM * H; e += blockDim.x) {
+                const int rr = e / H, g = e - rr * H;
+                const float a = Ag[rr * (Hk + 1) + g];
+                A[rr * lda + g] = BF16 ? (AT)bf16_bits_f(a) : (AT)a;
             }
         }
-        const int t = ct * 16 + lr;
-        if (t < P) {
-            const float pi = Pif[t];
+        __syncthreads();
+        for (int ct = wave; ct * 16 < Pn; ct += 4) {
+            f32x4 acc[SF_BM / 16];
 #pragma unroll
-            for (int tm = 0; tm < SU_BM / 16; ++tm)
+            for (int tm = 0; tm < SF_BM / 16; ++tm) acc[tm] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const long brow = (long)(ct * 16 + lr) * Hk + lk * kq;
+            if (BF16) {
+                for (int s8 = 0; s8 < kq; s8 += 8) {
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Btb + brow + s8);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const long r = row0 + tm * 16 + 4 * lk + e;
-                    if (r < R) out[r * P + t] = pi * acc[tm][e];
+                    for (int tm = 0; tm < SF_BM / 16; ++tm) {
+                        const bf16x8 av = *reinterpret_cast<const bf16x8*>(
+                            reinterpret_cast<const uint16_t*>(A) + (tm * 16 + lr) * lda + lk * kq + s8);
+                        acc[tm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[tm], 0, 0, 0);
+                    }
                 }
+            } else {
+                for (int s4 = 0; s4 < kq; s4 += 4) {
+                    const float4 bv = *reinterpret_cast<const float4*>(Btf + brow + s4);
+#pragma unroll
+                    for (int tm = 0; tm < SF_BM / 16; ++tm) {
+                        const float4 av = *reinterpret_cast<const float4*>(
+                            reinterpret_cast<const float*>(A) + (tm * 16 + lr) * lda + lk * kq + s4);
+                        acc[tm] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc[tm], 0, 0, 0);
+                        acc[tm] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc[tm], 0, 0, 0);
+                        acc[tm] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc[tm], 0, 0, 0);
+                        acc[tm] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc[tm], 0, 0, 0);
+                    }
+                }
+            }
+            const int t = ct * 16 + lr;
+            if (t < P) {
+                const float pi = Pif[t];
+#pragma unroll
+                for (int tm = 0; tm < SF_BM / 16; ++tm)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const long r = row0 + tm * 16 + 4 * lk + e;
+                        if (r < R) out[r * P + t] = pi * acc[tm][e];
+                    }
+            }
         }
     }
 }
@@ -446,29 +470,43 @@ extern "C" int wk_surrogate_fwd(const wk_mesh* mesh, int32_t N, const float* wV,
     const int P = mesh->n_m / 2, Pn = (P + 15) / 16 * 16;
     const long R = (long)B * n_cells;
     // prep tables live in a scratch area sized like the backward's prep section
-    const size_t prep = surr_ws_bytes(H, P, N, 0, false);
+    const int Hk = (H + 31) / 32 * 32;
+    const size_t prep = (surr_ws_bytes(H, P, N, 0, false) + 255) / 256 * 256;
+    const size_t tbytes = (size_t)Pn * Hk * (sizeof(float) + sizeof(uint16_t));
     int err;
-    void* scratch = fwd_scratch(prep, &err);
+    void* scratch = fwd_scratch(prep + tbytes, &err);
     if (!scratch) return err;
     SurrWS w = surr_carve(scratch, H, P, N, 0, false);
+    float* Btf = reinterpret_cast<float*>(static_cast<char*>(scratch) + prep);
+    uint16_t* Btb = reinterpret_cast<uint16_t*>(Btf + (size_t)Pn * Hk);
     const long np = (long)H * Pn > Pn ? (long)H * Pn : Pn;
     hipLaunchKernelGGL(surr_prep, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, mesh->n_m, N,
                        H, Pn, wT, W, w.Bd, w.Bf, w.Pid, w.Pif, w.u);
-    const dim3 grid((unsigned)((R + SU_BM - 1) / SU_BM));
     if (prec == WK_FP64) {
         const size_t sh = sizeof(double) * SD_BM * (H + 1);
         hipLaunchKernelGGL(surr_fwd_f64, dim3((unsigned)((R + SD_BM - 1) / SD_BM)), dim3(SU_THREADS), sh, s, V, mesh->nx, R, n_cells,
                            cells, P, N, H, Pn, wV, w.Bd, w.Pid, static_cast<double*>(K_out));
-    } else if (prec == WK_BF16) {
-        const int Hk = (H + 31) / 32 * 32;
-        const size_t sh = sizeof(float) * SU_BM * (Hk + 1);
-        hipLaunchKernelGGL(surr_fwd_bf16, grid, dim3(SU_THREADS), sh, s, V, mesh->nx, R, n_cells,
-                           cells, P, N, H, Hk, Pn, wV, w.Bf, w.Pif, static_cast<float*>(K_out));
     } else {
-        const int Hk = (H + 3) / 4 * 4;
-        const size_t sh = sizeof(float) * SU_BM * (Hk + 1);
-        hipLaunchKernelGGL(surr_fwd_f32, grid, dim3(SU_THREADS), sh, s, V, mesh->nx, R, n_cells,
-                           cells, P, N, H, Hk, Pn, wV, w.Bf, w.Pif, static_cast<float*>(K_out));
+        const long nt = (long)Pn * Hk;
+        hipLaunchKernelGGL(surr_prep_t, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, H, Hk, Pn,
+                           w.Bf, Btf, Btb);
+        const long ntiles = (R + SF_BM - 1) / SF_BM;
+        const dim3 grid((unsigned)(ntiles < 4096 ? ntiles : 4096));
+        // A [SF_BM][Hk + 8] (bf16) or [SF_BM][Hk + 4] (f32), then the potential window or,
+        // for gathered rows, an FP32 staging copy of A
+        const size_t a_bytes = prec == WK_BF16 ? sizeof(uint16_t) * SF_BM * (Hk + 8)
+                                               : sizeof(float) * SF_BM * (Hk + 4);
+        const size_t w_bytes = sizeof(double) * (SF_BM + 2 * P);
+        const size_t g_bytes = sizeof(float) * SF_BM * (Hk + 1);
+        const size_t sh = (a_bytes + 7) / 8 * 8 + (w_bytes > g_bytes ? w_bytes : g_bytes);
+        if (prec == WK_BF16)
+            hipLaunchKernelGGL(surr_fwd_mfma<true>, grid, dim3(SU_THREADS), sh, s, V, mesh->nx, R,
+                               n_cells, cells, P, N, H, Hk, Pn, wV, Btf, Btb, w.Pif,
+                               static_cast<float*>(K_out));
+        else
+            hipLaunchKernelGGL(surr_fwd_mfma<false>, grid, dim3(SU_THREADS), sh, s, V, mesh->nx, R,
+                               n_cells, cells, P, N, H, Hk, Pn, wV, Btf, Btb, w.Pif,
+                               static_cast<float*>(K_out));
     }
     return check_launch("wk_surrogate_fwd");
 }
