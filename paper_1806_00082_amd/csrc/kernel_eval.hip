@@ -110,6 +110,11 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
     build(0, 0);
     __syncthreads();
 
+    // The next chunk's D tile is built in four slices, one after each sub-step's products
+    // (the products run on the matrix cores while the slice's FP64 differences are formed),
+    // and the A fragments of a sub-step are read from LDS one sub-step ahead.
+    static_assert((BM * BK) % (KE_THREADS * (BK / 4)) == 0, "build slices");
+    constexpr int SLICE = BM * BK / (BK / 4);  // D elements per slice
     int buf = 0;
     for (int k0 = 0; k0 < Pk; k0 += BK) {
         const bool more = k0 + BK < Pk;
@@ -120,19 +125,33 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
 #pragma unroll
                 for (int tn = 0; tn < WN; ++tn)
                     bnext[ks][tn] = Sw[(long)(k0 + BK + 4 * ks + lk) * Pn + tn * 16];
-            build(k0 + BK, buf ^ 1);
         }
+        double afrag[WM], anext[WM];
+#pragma unroll
+        for (int tm = 0; tm < WM; ++tm) afrag[tm] = Ds[buf][(wr * WM + tm) * 16 + lr][lk];
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
-            double afrag[WM];
+            if (ks + 1 < BK / 4) {
 #pragma unroll
-            for (int tm = 0; tm < WM; ++tm) afrag[tm] = Ds[buf][(wr * WM + tm) * 16 + lr][4 * ks + lk];
+                for (int tm = 0; tm < WM; ++tm)
+                    anext[tm] = Ds[buf][(wr * WM + tm) * 16 + lr][4 * (ks + 1) + lk];
+            }
 #pragma unroll
             for (int tm = 0; tm < WM; ++tm)
 #pragma unroll
                 for (int tn = 0; tn < WN; ++tn)
                     acc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(afrag[tm], bfrag[ks][tn],
                                                                      acc[tm][tn], 0, 0, 0);
+            if (more) {
+                for (int e = ks * SLICE + threadIdx.x; e < (ks + 1) * SLICE; e += KE_THREADS) {
+                    const int rr = e / BK, kk = e - rr * BK;
+                    Ds[buf ^ 1][rr][kk] = d_elem<BM>(contig, Wv, V, rbase, rcell, nx, P, rr, k0 + BK + kk + 1);
+                }
+            }
+            if (ks + 1 < BK / 4) {
+#pragma unroll
+                for (int tm = 0; tm < WM; ++tm) afrag[tm] = anext[tm];
+            }
         }
         if (more) {
 #pragma unroll
