@@ -407,11 +407,14 @@ static int round_up(int a, int b) { return (a + b - 1) / b * b; }
 enum { CFG_SMALL = 0, CFG_MID = 1, CFG_LARGE = 2 };
 static int tile_cfg(int P) { return P > 128 ? CFG_LARGE : (P > 64 ? CFG_MID : CFG_SMALL); }
 static int tile_bn(int cfg) { return cfg == CFG_LARGE ? 256 : (cfg == CFG_MID ? 128 : 64); }
+// FP64 column block: the wide configuration uses 64 x 32 wave tiles (BN = 128) so that two
+// waves fit per SIMD; the differences of a row are then formed once per column block.
+static int tile_bn_f64(int cfg) { return cfg == CFG_SMALL ? 64 : 128; }
 
 int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_t* cells,
                        int n_cells, int layout, double* out, hipStream_t stream) {
     const int n_m = mesh->n_m, P = n_m / 2;
-    const int cfg = tile_cfg(P), BN = tile_bn(cfg);
+    const int cfg = tile_cfg(P), BN = tile_bn_f64(cfg);
     const int Pk = round_up(P, KE_BK), Pn = round_up(P, BN);
     int err = WK_OK;
     const double* S = static_cast<const double*>(sine_table(n_m, 0, Pk, Pn, stream, &err));
@@ -424,7 +427,7 @@ int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_
     WK_LAUNCH("kernel_eval_f64", (kernel_eval_f64<WM, WN, WNV>), grid, dim3(KE_THREADS), 0, stream, V, \
                        mesh->nx, R, n_cells, cells, P, n_m, Pk, Pn, S, c, layout, out)
     if (cfg == CFG_LARGE)
-        KE_LAUNCH_F64(4, 4, 4);
+        KE_LAUNCH_F64(4, 2, 4);
     else if (cfg == CFG_MID)
         KE_LAUNCH_F64(2, 4, 2);
     else
