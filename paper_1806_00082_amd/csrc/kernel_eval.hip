@@ -60,20 +60,28 @@ __device__ __forceinline__ double d_elem(bool contig, const double* Wv, const do
     return Vb[min(cell + j, nx - 1)] - Vb[max(cell - j, 0)];
 }
 
-// FP64 path: v_mfma_f64_16x16x4_f64.  WAVES_N waves split the columns, 4 / WAVES_N split the
-// rows; each wave owns a (16 WM) x (16 WN) output tile.  Operand layouts (16x16x4 f64):
-// lane l holds A[l % 16][l / 16], B[l / 16][l % 16], and C[l / 16 + 4 e][l % 16], e < 4.
-// The D tile is double-buffered in LDS and the next chunk's sine-table fragments are
-// loaded while the current chunk's products run.
+// FP64 path: v_mfma_f64_16x16x4_f64 on the folded sum.  With n_m = 2P the sine of eq.(4)
+// obeys sin(2 pi j (P - m) / n_m) = -(-1)^j sin(2 pi j m / n_m), so splitting the sum over j
+// into odd and even terms gives, for m = t + 1 <= H = floor(P / 2),
+//   O[row][t] = sum_k So[k][t] D[row][2k + 1],   E[row][t] = sum_k Se[k][t] D[row][2k + 2],
+//   K(m) = c (O + E),   K(P - m) = c (O - E),
+// two H x H contractions per row in place of one (P - 1) x (P - 1): half the products
+// (one radix-2 step of a fast sine transform; the tables obey the identity exactly, so the
+// results differ from the direct sum by rounding order only).
+// WAVES_N waves split the columns t, 4 / WAVES_N split the rows; each wave owns a
+// (16 WM) x (16 WN) tile of both O and E.  Operand layouts (16x16x4 f64): lane l holds
+// A[l % 16][l / 16], B[l / 16][l % 16], and C[l / 16 + 4 e][l % 16], e < 4.  The odd and even
+// D tiles are double-buffered in LDS; the next chunk's tiles are built in four slices between
+// the current chunk's sub-steps, and its sine fragments are loaded one chunk ahead.
 template <int WM, int WN, int WAVES_N>
 __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
     const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
-    int P, int n_m, int Pk, int Pn, const double* __restrict__ S, double c, int layout,
-    double* __restrict__ out) {
+    int P, int n_m, int H, int Hk, int Hn, const double* __restrict__ So,
+    const double* __restrict__ Se, double c, int layout, double* __restrict__ out) {
     constexpr int WAVES_M = 4 / WAVES_N;
     constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N, BK = KE_BK;
-    static_assert(BM == KE_BM, "row tile");
-    __shared__ double Ds[2][BM][BK + 1];
+    static_assert(BM <= KE_BM, "row tile");
+    __shared__ double Ds[2][2][BM][BK + 1];  // [buffer][0: odd j, 1: even j][row][k]
     __shared__ double Wv[KE_WIN];
     __shared__ long rbase[BM];
     __shared__ int rcell[BM];
@@ -88,76 +96,87 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
     if (contig) load_window<BM>(V, (row0 / n_cells) * (long)nx, (int)(row0 % n_cells), nx, P, Wv);
     __syncthreads();
 
-    auto build = [&](int k0, int buf) {
-        for (int e = threadIdx.x; e < BM * BK; e += KE_THREADS) {
-            const int rr = e / BK, kk = e - rr * BK;
-            Ds[buf][rr][kk] = d_elem<BM>(contig, Wv, V, rbase, rcell, nx, P, rr, k0 + kk + 1);
-        }
+    // element e of a chunk's two tiles: part e / (BM BK), then row-major [BM][BK]
+    auto put = [&](int e, int k0, int buf) {
+        const int part = e / (BM * BK), rem = e - part * (BM * BK);
+        const int rr = rem / BK, kk = rem - rr * BK;
+        Ds[buf][part][rr][kk] = d_elem<BM>(contig, Wv, V, rbase, rcell, nx, P, rr, 2 * (k0 + kk) + 1 + part);
     };
 
-    f64x4 acc[WM][WN];
+    f64x4 acc[2][WM][WN];
 #pragma unroll
-    for (int a = 0; a < WM; ++a)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int b = 0; b < WN; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int a = 0; a < WM; ++a)
+#pragma unroll
+            for (int b = 0; b < WN; ++b) acc[p][a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    const double* Sw = S + (long)col0 + wc * WN * 16 + lr;
-    double bfrag[BK / 4][WN];
+    const long cw = (long)col0 + wc * WN * 16 + lr;
+    const double* Sw[2] = {So + cw, Se + cw};
+    double bfrag[2][BK / 4][WN];
 #pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int tn = 0; tn < WN; ++tn) bfrag[ks][tn] = Sw[(long)(4 * ks + lk) * Pn + tn * 16];
-    build(0, 0);
+        for (int ks = 0; ks < BK / 4; ++ks)
+#pragma unroll
+            for (int tn = 0; tn < WN; ++tn) bfrag[p][ks][tn] = Sw[p][(long)(4 * ks + lk) * Hn + tn * 16];
+    for (int e = threadIdx.x; e < 2 * BM * BK; e += KE_THREADS) put(e, 0, 0);
     __syncthreads();
 
-    // The next chunk's D tile is built in four slices, one after each sub-step's products
-    // (the products run on the matrix cores while the slice's FP64 differences are formed),
-    // and the A fragments of a sub-step are read from LDS one sub-step ahead.
-    static_assert((BM * BK) % (KE_THREADS * (BK / 4)) == 0, "build slices");
-    constexpr int SLICE = BM * BK / (BK / 4);  // D elements per slice
+    static_assert((2 * BM * BK) % (KE_THREADS * (BK / 4)) == 0, "build slices");
+    constexpr int SLICE = 2 * BM * BK / (BK / 4);  // D elements per slice
     int buf = 0;
-    for (int k0 = 0; k0 < Pk; k0 += BK) {
-        const bool more = k0 + BK < Pk;
-        double bnext[BK / 4][WN];
+    for (int k0 = 0; k0 < Hk; k0 += BK) {
+        const bool more = k0 + BK < Hk;
+        double bnext[2][BK / 4][WN];
         if (more) {
 #pragma unroll
-            for (int ks = 0; ks < BK / 4; ++ks)
+            for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int tn = 0; tn < WN; ++tn)
-                    bnext[ks][tn] = Sw[(long)(k0 + BK + 4 * ks + lk) * Pn + tn * 16];
+                for (int ks = 0; ks < BK / 4; ++ks)
+#pragma unroll
+                    for (int tn = 0; tn < WN; ++tn)
+                        bnext[p][ks][tn] = Sw[p][(long)(k0 + BK + 4 * ks + lk) * Hn + tn * 16];
         }
-        double afrag[WM], anext[WM];
+        double afrag[2][WM], anext[2][WM];
 #pragma unroll
-        for (int tm = 0; tm < WM; ++tm) afrag[tm] = Ds[buf][(wr * WM + tm) * 16 + lr][lk];
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int tm = 0; tm < WM; ++tm) afrag[p][tm] = Ds[buf][p][(wr * WM + tm) * 16 + lr][lk];
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             if (ks + 1 < BK / 4) {
 #pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int tm = 0; tm < WM; ++tm)
+                        anext[p][tm] = Ds[buf][p][(wr * WM + tm) * 16 + lr][4 * (ks + 1) + lk];
+            }
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
                 for (int tm = 0; tm < WM; ++tm)
-                    anext[tm] = Ds[buf][(wr * WM + tm) * 16 + lr][4 * (ks + 1) + lk];
-            }
 #pragma unroll
-            for (int tm = 0; tm < WM; ++tm)
-#pragma unroll
-                for (int tn = 0; tn < WN; ++tn)
-                    acc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(afrag[tm], bfrag[ks][tn],
-                                                                     acc[tm][tn], 0, 0, 0);
-            if (more) {
-                for (int e = ks * SLICE + threadIdx.x; e < (ks + 1) * SLICE; e += KE_THREADS) {
-                    const int rr = e / BK, kk = e - rr * BK;
-                    Ds[buf ^ 1][rr][kk] = d_elem<BM>(contig, Wv, V, rbase, rcell, nx, P, rr, k0 + BK + kk + 1);
-                }
-            }
+                    for (int tn = 0; tn < WN; ++tn)
+                        acc[p][tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            afrag[p][tm], bfrag[p][ks][tn], acc[p][tm][tn], 0, 0, 0);
+            if (more)
+                for (int e = ks * SLICE + threadIdx.x; e < (ks + 1) * SLICE; e += KE_THREADS)
+                    put(e, k0 + BK, buf ^ 1);
             if (ks + 1 < BK / 4) {
 #pragma unroll
-                for (int tm = 0; tm < WM; ++tm) afrag[tm] = anext[tm];
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int tm = 0; tm < WM; ++tm) afrag[p][tm] = anext[p][tm];
             }
         }
         if (more) {
 #pragma unroll
-            for (int ks = 0; ks < BK / 4; ++ks)
+            for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int tn = 0; tn < WN; ++tn) bfrag[ks][tn] = bnext[ks][tn];
+                for (int ks = 0; ks < BK / 4; ++ks)
+#pragma unroll
+                    for (int tn = 0; tn < WN; ++tn) bfrag[p][ks][tn] = bnext[p][ks][tn];
         }
         __syncthreads();
         buf ^= 1;
@@ -167,27 +186,41 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
     for (int tm = 0; tm < WM; ++tm) {
 #pragma unroll
         for (int tn = 0; tn < WN; ++tn) {
-            const int t = col0 + (wc * WN + tn) * 16 + lr;
+            const int t = col0 + (wc * WN + tn) * 16 + lr, m = t + 1;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const long row = row0 + (wr * WM + tm) * 16 + lk + 4 * e;
-                if (row >= R || t >= P) continue;
-                const double k = c * acc[tm][tn][e];
+                if (row >= R || t >= H) continue;
+                const double o = acc[0][tm][tn][e], ev = acc[1][tm][tn][e];
+                const double kp = c * (o + ev), km = c * (o - ev);
+                const bool mirror = 2 * m < P;  // m = P / 2 (even P) is its own mirror
                 if (layout == WK_HALF) {
-                    out[row * P + t] = k;
+                    double* h = out + row * P;  // entry m - 1 holds K(m), m = 1..P
+                    h[m - 1] = kp;
+                    if (mirror) h[P - m - 1] = km;
+                    if (t == 0) h[P - 1] = 0.0;
                 } else {
-                    double* o = out + row * (long)n_m;
-                    if (t < P - 1) {
-                        o[P + 1 + t] = k;
-                        o[P - 1 - t] = -k;
-                    } else {
-                        o[0] = -k;
-                        o[P] = 0.0;
+                    double* f = out + row * (long)n_m;  // entry P + m holds K(m), m = -P..P-1
+                    f[P + m] = kp;
+                    f[P - m] = -kp;
+                    if (mirror) {
+                        f[2 * P - m] = km;
+                        f[m] = -km;
+                    }
+                    if (t == 0) {
+                        f[0] = 0.0;
+                        f[P] = 0.0;
                     }
                 }
             }
         }
     }
+}
+
+// n_m = 2: every entry of eq.(4) is sin(pi j m) = 0.
+__global__ void kernel_zero_f64(double* __restrict__ out, long n) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) out[idx] = 0.0;
 }
 
 // Reduced-precision path: v_mfma_f32_16x16x32_{bf16,f16} with FP32 accumulation.  Layouts
@@ -407,31 +440,42 @@ static int round_up(int a, int b) { return (a + b - 1) / b * b; }
 enum { CFG_SMALL = 0, CFG_MID = 1, CFG_LARGE = 2 };
 static int tile_cfg(int P) { return P > 128 ? CFG_LARGE : (P > 64 ? CFG_MID : CFG_SMALL); }
 static int tile_bn(int cfg) { return cfg == CFG_LARGE ? 256 : (cfg == CFG_MID ? 128 : 64); }
-// FP64 column block: the wide configuration uses 64 x 32 wave tiles (BN = 128) so that two
-// waves fit per SIMD; the differences of a row are then formed once per column block.
-static int tile_bn_f64(int cfg) { return cfg == CFG_SMALL ? 64 : 128; }
+
+// Folded FP64 tiles by H = floor(P / 2): 32 x 128 blocks of 32 x 32 wave tiles (both parts,
+// eight accumulators) for H > 64, 64 x 64 for H in (32, 64], 64 x 32 below; one column block
+// covers H <= 128 (P <= 257), so each difference is formed once per row.
+static int fold_cfg(int H) { return H > 64 ? CFG_LARGE : (H > 32 ? CFG_MID : CFG_SMALL); }
+static int fold_bn(int cfg) { return cfg == CFG_LARGE ? 128 : (cfg == CFG_MID ? 64 : 32); }
+static int fold_bm(int cfg) { return cfg == CFG_LARGE ? 32 : 64; }
 
 int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_t* cells,
                        int n_cells, int layout, double* out, hipStream_t stream) {
-    const int n_m = mesh->n_m, P = n_m / 2;
-    const int cfg = tile_cfg(P), BN = tile_bn_f64(cfg);
-    const int Pk = round_up(P, KE_BK), Pn = round_up(P, BN);
-    int err = WK_OK;
-    const double* S = static_cast<const double*>(sine_table(n_m, 0, Pk, Pn, stream, &err));
-    if (!S) return err;
+    const int n_m = mesh->n_m, P = n_m / 2, H = P / 2;
     const long R = (long)B * n_cells;
     if (R == 0) return WK_OK;
+    if (H == 0) {
+        const long n = R * (layout == WK_HALF ? P : n_m);
+        hipLaunchKernelGGL(kernel_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, out, n);
+        return check_launch("kernel_zero_f64");
+    }
+    const int cfg = fold_cfg(H), BN = fold_bn(cfg), BM = fold_bm(cfg);
+    const int Hk = round_up(H, KE_BK), Hn = round_up(H, BN);
+    int err = WK_OK;
+    const double* So = static_cast<const double*>(sine_table(n_m, SINE_ODD, Hk, Hn, stream, &err));
+    if (!So) return err;
+    const double* Se = static_cast<const double*>(sine_table(n_m, SINE_EVEN, Hk, Hn, stream, &err));
+    if (!Se) return err;
     const double c = -2.0 / (mesh->hbar * (double)n_m);
-    dim3 grid((unsigned)((R + KE_BM - 1) / KE_BM), (unsigned)(Pn / BN));
+    dim3 grid((unsigned)((R + BM - 1) / BM), (unsigned)(Hn / BN));
 #define KE_LAUNCH_F64(WM, WN, WNV)                                                              \
     WK_LAUNCH("kernel_eval_f64", (kernel_eval_f64<WM, WN, WNV>), grid, dim3(KE_THREADS), 0, stream, V, \
-                       mesh->nx, R, n_cells, cells, P, n_m, Pk, Pn, S, c, layout, out)
+                       mesh->nx, R, n_cells, cells, P, n_m, H, Hk, Hn, So, Se, c, layout, out)
     if (cfg == CFG_LARGE)
-        KE_LAUNCH_F64(4, 2, 4);
+        KE_LAUNCH_F64(2, 2, 4);
     else if (cfg == CFG_MID)
-        KE_LAUNCH_F64(2, 4, 2);
+        KE_LAUNCH_F64(4, 1, 4);
     else
-        KE_LAUNCH_F64(1, 4, 1);
+        KE_LAUNCH_F64(2, 1, 2);
 #undef KE_LAUNCH_F64
     return check_launch("kernel_eval_f64");
 }

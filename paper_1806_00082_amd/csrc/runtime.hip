@@ -26,15 +26,28 @@ int check_launch(const char* what) {
     return WK_OK;
 }
 
-// S[jj][t] = sin(2 pi (jj+1)(t+1)/n_m) for jj, t < P, zero elsewhere, in the requested form.
-__global__ void build_sine_table(void* out, int n_m, int Pk, int Pn, int kind) {
+// Sine tables of eq.(4), kind = format | (part << 3).  Formats: 0 FP64, 1 BF16, 2 BF16
+// remainder (v - bf16(v)), 3 FP16, 4 FP16 remainder.  Parts (a = row, b = column):
+//   0: S[a][b] = sin(2 pi (a+1)(b+1) / n_m) for a, b < P = n_m / 2;
+//   1: odd-j fold  So[a][b] = sin(2 pi (2a+1)(b+1) / n_m),   a, b < H = floor(P / 2);
+//   2: even-j fold Se[a][b] = sin(2 pi (2a+2)(b+1) / n_m),   a, b < H;
+//   3, 4: parts 1 and 2 transposed, T[a][b] = fold[b][a].
+// Entries outside those ranges are zero (padding of the tiles).
+__global__ void build_sine_table(void* out, int n_m, int rows, int cols, int kind) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)Pk * Pn) return;
-    const int P = n_m / 2;
-    const int jj = (int)(idx / Pn), t = (int)(idx % Pn);
+    if (idx >= (long)rows * cols) return;
+    const int P = n_m / 2, H = P / 2;
+    const int a = (int)(idx / cols), b = (int)(idx % cols);
+    const int fmt = kind & 7, part = kind >> 3;
     double v = 0.0;
-    if (jj < P && t < P) v = sin_2pi_ratio((long)(jj + 1) * (t + 1), n_m);
-    switch (kind) {
+    if (part == 0) {
+        if (a < P && b < P) v = sin_2pi_ratio((long)(a + 1) * (b + 1), n_m);
+    } else {
+        const int k = part <= 2 ? a : b, t = part <= 2 ? b : a;
+        const int even = (part == 2 || part == 4) ? 1 : 0;
+        if (k < H && t < H) v = sin_2pi_ratio((long)(2 * k + 1 + even) * (t + 1), n_m);
+    }
+    switch (fmt) {
         case 0: reinterpret_cast<double*>(out)[idx] = v; break;
         case 1: reinterpret_cast<uint16_t*>(out)[idx] = bf16_bits(v); break;
         case 2: reinterpret_cast<uint16_t*>(out)[idx] = bf16_bits(v - bf16_value(bf16_bits(v))); break;
@@ -44,7 +57,7 @@ __global__ void build_sine_table(void* out, int n_m, int Pk, int Pn, int kind) {
     }
 }
 
-const void* sine_table(int n_m, int kind, int Pk, int Pn, hipStream_t stream, int* err) {
+const void* sine_table(int n_m, int kind, int rows, int cols, hipStream_t stream, int* err) {
     static std::mutex mu;
     static std::map<std::tuple<int, int, int, int, int>, void*> cache;
     *err = WK_OK;
@@ -54,19 +67,19 @@ const void* sine_table(int n_m, int kind, int Pk, int Pn, hipStream_t stream, in
         return nullptr;
     }
     std::lock_guard<std::mutex> lock(mu);
-    auto key = std::make_tuple(dev, n_m, kind, Pk, Pn);
+    auto key = std::make_tuple(dev, n_m, kind, rows, cols);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
-    const size_t elem = kind == 0 ? sizeof(double) : sizeof(uint16_t);
+    const size_t elem = (kind & 7) == 0 ? sizeof(double) : sizeof(uint16_t);
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, elem * (size_t)Pk * Pn);
+    hipError_t e = hipMalloc(&p, elem * (size_t)rows * cols);
     if (e != hipSuccess) {
         *err = fail(WK_EHIP, std::string("sine table hipMalloc: ") + hipGetErrorString(e));
         return nullptr;
     }
-    const long n = (long)Pk * Pn;
+    const long n = (long)rows * cols;
     hipLaunchKernelGGL(build_sine_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
-                       p, n_m, Pk, Pn, kind);
+                       p, n_m, rows, cols, kind);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {

@@ -13,9 +13,14 @@ FP64_TOL = 1e-10      # normwise error bound for the FP64 path
 
 
 @pytest.mark.parametrize("nx,n_m,B", [(100, 30, 1), (400, 80, 2), (333, 256, 3), (70, 16, 4),
-                                      (1024, 256, 2), (130, 2, 1)])
+                                      (1024, 256, 2), (130, 2, 1), (50, 4, 3), (41, 6, 2),
+                                      (300, 134, 2), (260, 258, 1), (200, 260, 1), (257, 512, 2),
+                                      (90, 1024, 1), (70, 1100, 1)])
 def test_kernel_fp64_all_cells(orc, nx, n_m, B):
-    """Several row tiles, several column tiles and ragged tails, both layouts."""
+    """Several row tiles, several column tiles and ragged tails, both layouts.  The folded
+    sum runs on H = n_m / 4 columns: odd and even P, H on both sides of each tile-shape
+    boundary (32, 64), two column blocks (n_m = 1024), and a table too wide for the LDS
+    window of the potential (n_m = 1100, three column blocks)."""
     print(f"kernel fp64 nx={nx} n_m={n_m} B={B}", flush=True)
     V = inputs.random_potentials(B, nx, 0.5, seed=nx + n_m)
     ref = orc.kernel_1d(V, n_m, HB).reshape(B * nx, n_m)
@@ -26,13 +31,14 @@ def test_kernel_fp64_all_cells(orc, nx, n_m, B):
     assert normwise(half.reshape(B, -1), orc.full_to_half(ref).reshape(B, -1)) <= FP64_TOL
     P = n_m // 2
     # exact zeros and exact oddness in the full layout
-    assert np.all(full[:, P] == 0) and np.all(full[:, 0] == 0)
+    assert np.all(full[:, P] == 0) and np.all(full[:, 0] == 0) and np.all(half[:, P - 1] == 0)
     assert np.array_equal(full[:, 1:P], -full[:, P + 1:][:, ::-1])
 
 
-def test_kernel_fp64_cell_list(orc):
+@pytest.mark.parametrize("n_m", [64, 512])
+def test_kernel_fp64_cell_list(orc, n_m):
     """Occupied-cell evaluation: arbitrary order, duplicates, both mesh edges."""
-    nx, n_m, B = 257, 64, 3
+    nx, B = 257, 3
     V = inputs.random_potentials(B, nx, 0.5, seed=2)
     cells = np.array([5, 0, 256, 128, 128, 1, 255, 77] * 9 + [3], dtype=np.int32)
     ref = orc.kernel_1d(V, n_m, HB, cells=cells)
