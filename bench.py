@@ -244,6 +244,8 @@ def main():
                     help="skip the traced replica (for counter runs under rocprofv3 --pmc)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 1 GiB device copies (counter calibration)")
+    ap.add_argument("--forms-only", action="store_true",
+                    help="only the eq.(4) precision batch (for counter runs on the contraction)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -254,6 +256,9 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.forms_only:
+        print(json.dumps({"forms": {"kernel_eq4": run_kernel_forms()}}))
+        return
     h = run_headline(args.steps, args.warmup, traced=False)
     tr = h
     if not args.no_trace:

@@ -19,8 +19,12 @@ SOURCES = ["runtime.hip", "kernel_eval.hip", "tables.hip", "particles.hip", "sur
 HEADERS = ["wk_internal.h", "lowp.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# -amdgpu-mfma-vgpr-form: MFMA accumulators live in ordinary VGPRs (gfx950 allows VGPR C/D
+# operands); otherwise loop-carried accumulators are copied into and out of AGPRs on every
+# iteration of the contraction loops (two VALU moves per accumulator register per chunk).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include")]
 
 

@@ -96,11 +96,21 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
     if (contig) load_window<BM>(V, (row0 / n_cells) * (long)nx, (int)(row0 % n_cells), nx, P, Wv);
     __syncthreads();
 
-    // element e of a chunk's two tiles: part e / (BM BK), then row-major [BM][BK]
+    // element e of a chunk's two tiles: part e / (BM BK), then row-major [BM][BK]; rows of
+    // one window need no per-row lookups (offsets past P read the window at P, then give 0)
     auto put = [&](int e, int k0, int buf) {
         const int part = e / (BM * BK), rem = e - part * (BM * BK);
         const int rr = rem / BK, kk = rem - rr * BK;
-        Ds[buf][part][rr][kk] = d_elem<BM>(contig, Wv, V, rbase, rcell, nx, P, rr, 2 * (k0 + kk) + 1 + part);
+        const int j = 2 * (k0 + kk) + 1 + part;
+        double d;
+        if (contig) {
+            const int jc = min(j, P);
+            d = Wv[rr + P + jc] - Wv[rr + P - jc];
+            if (j > P) d = 0.0;
+        } else {
+            d = d_elem<BM>(false, Wv, V, rbase, rcell, nx, P, rr, j);
+        }
+        Ds[buf][part][rr][kk] = d;
     };
 
     f64x4 acc[2][WM][WN];
@@ -113,31 +123,37 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
 
     const long cw = (long)col0 + wc * WN * 16 + lr;
     const double* Sw[2] = {So + cw, Se + cw};
-    double bfrag[2][BK / 4][WN];
+    // sine fragments: loaded one chunk ahead into bnext only (also before the loop), and
+    // moved into bfrag at the top of each chunk, so that the loads of a chunk have a whole
+    // chunk of products to arrive and no product waits on a load issued in its own chunk
+    double bnext[2][BK / 4][WN];
+    auto load_b = [&](int k0) {
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int ks = 0; ks < BK / 4; ++ks)
+            for (int ks = 0; ks < BK / 4; ++ks)
 #pragma unroll
-            for (int tn = 0; tn < WN; ++tn) bfrag[p][ks][tn] = Sw[p][(long)(4 * ks + lk) * Hn + tn * 16];
+                for (int tn = 0; tn < WN; ++tn)
+                    bnext[p][ks][tn] = Sw[p][(long)(k0 + 4 * ks + lk) * Hn + tn * 16];
+    };
+    load_b(0);
     for (int e = threadIdx.x; e < 2 * BM * BK; e += KE_THREADS) put(e, 0, 0);
     __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0);  // the prologue's loads have landed (see the 16-bit path)
 
     static_assert((2 * BM * BK) % (KE_THREADS * (BK / 4)) == 0, "build slices");
     constexpr int SLICE = 2 * BM * BK / (BK / 4);  // D elements per slice
     int buf = 0;
     for (int k0 = 0; k0 < Hk; k0 += BK) {
         const bool more = k0 + BK < Hk;
-        double bnext[2][BK / 4][WN];
-        if (more) {
+        double bfrag[2][BK / 4][WN];
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int ks = 0; ks < BK / 4; ++ks)
+            for (int ks = 0; ks < BK / 4; ++ks)
 #pragma unroll
-                    for (int tn = 0; tn < WN; ++tn)
-                        bnext[p][ks][tn] = Sw[p][(long)(k0 + BK + 4 * ks + lk) * Hn + tn * 16];
-        }
+                for (int tn = 0; tn < WN; ++tn) bfrag[p][ks][tn] = bnext[p][ks][tn];
+        if (more) load_b(k0 + BK);
         double afrag[2][WM], anext[2][WM];
 #pragma unroll
         for (int p = 0; p < 2; ++p)
@@ -169,14 +185,6 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
 #pragma unroll
                     for (int tm = 0; tm < WM; ++tm) afrag[p][tm] = anext[p][tm];
             }
-        }
-        if (more) {
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int ks = 0; ks < BK / 4; ++ks)
-#pragma unroll
-                    for (int tn = 0; tn < WN; ++tn) bfrag[p][ks][tn] = bnext[p][ks][tn];
         }
         __syncthreads();
         buf ^= 1;
@@ -312,7 +320,15 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
             s16x8 hv, lv;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const double d = d_elem<BM>(contig, Wv, V, rbase, rcell, nx, P, rr, k0 + kq + q + 1);
+                const int j = k0 + kq + q + 1;
+                double d;
+                if (contig) {  // one window: offsets past P read it at P, then give 0
+                    const int jc = min(j, P);
+                    d = Wv[rr + P + jc] - Wv[rr + P - jc];
+                    if (j > P) d = 0.0;
+                } else {
+                    d = d_elem<BM>(false, Wv, V, rbase, rcell, nx, P, rr, j);
+                }
                 uint16_t h, l;
                 split16<TR::half>(d, &h, &l);
                 hv[q] = (short)h;
@@ -337,14 +353,24 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
 #pragma unroll
         for (int b = 0; b < WN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    s16x8 bh[WN], bl[WN];
-    load_b(0, bh, bl);
+    // sine fragments are loaded one step ahead into nh / nl only and moved into bh / bl at
+    // the top of each step (no product waits on a load issued in its own step)
+    s16x8 nh[WN], nl[WN];
+    load_b(0, nh, nl);
     build(0, 0);
     __syncthreads();
+    // every load of the prologue has landed: without this the compiler's wait counting
+    // merges them into the loop and makes each step's products wait on the next step's loads
+    __builtin_amdgcn_s_waitcnt(0);
     int buf = 0;
     for (int k0 = 0; k0 < Pk; k0 += BK) {
         const bool more = k0 + BK < Pk;
-        s16x8 nh[WN], nl[WN];
+        s16x8 bh[WN], bl[WN];
+#pragma unroll
+        for (int tn = 0; tn < WN; ++tn) {
+            bh[tn] = nh[tn];
+            if constexpr (TR::split) bl[tn] = nl[tn];
+        }
         if (more) {
             load_b(k0 + BK, nh, nl);
             build(k0 + BK, buf ^ 1);
@@ -362,13 +388,6 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
                     acc[tm][tn] = mfma16<TR::half>(ah, bl[tn], acc[tm][tn]);
                     acc[tm][tn] = mfma16<TR::half>(al, bh[tn], acc[tm][tn]);
                 }
-            }
-        }
-        if (more) {
-#pragma unroll
-            for (int tn = 0; tn < WN; ++tn) {
-                bh[tn] = nh[tn];
-                if constexpr (TR::split) bl[tn] = nl[tn];
             }
         }
         __syncthreads();
