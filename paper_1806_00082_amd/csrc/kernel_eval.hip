@@ -273,17 +273,6 @@ __device__ __forceinline__ f32x4 mfma16(const s16x8& a, const s16x8& b, f32x4 c)
                                                        __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-template <bool HALF>
-__device__ __forceinline__ void split16(double d, uint16_t* hi, uint16_t* lo) {
-    if constexpr (HALF) {
-        *hi = f16_bits(d);
-        *lo = f16_bits(d - (double)f16_value(*hi));
-    } else {
-        *hi = bf16_bits(d);
-        *lo = bf16_bits(d - (double)bf16_value(*hi));
-    }
-}
-
 template <int PREC, int WM, int WN, int WAVES_N>
 __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
@@ -296,7 +285,8 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     // operand tiles during the contraction; the same bytes stage the output afterwards
     // (16 * WAVES_M rows x BN columns of FP32 at a time)
     constexpr int OPS = 2 * BM * LD * 2 + 2 * (TR::split ? BM : 1) * LD * 2;
-    constexpr int STG = 16 * WAVES_M * BN * 4;
+    constexpr int SP = BN + 4;  // stage row stride in floats (rows 4 apart on distinct banks)
+    constexpr int STG = 16 * WAVES_M * SP * 4;
     __shared__ __attribute__((aligned(16))) char lds_ops[OPS > STG ? OPS : STG];
     auto Dh = reinterpret_cast<uint16_t(*)[BM][LD]>(lds_ops);
     auto Dl = reinterpret_cast<uint16_t(*)[TR::split ? BM : 1][LD]>(lds_ops + 2 * BM * LD * 2);
@@ -317,25 +307,37 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     auto build = [&](int k0, int buf) {
         for (int e = threadIdx.x; e < BM * (BK / 8); e += KE_THREADS) {
             const int rr = e / (BK / 8), kq = (e - rr * (BK / 8)) * 8;
-            s16x8 hv, lv;
+            const int j0 = k0 + kq + 1;
+            double d[8];
+            if (contig && j0 + 7 <= P) {
+                // one window, eight offsets in range: sixteen independent LDS reads
+                const double* up = Wv + rr + P + j0;
+                const double* dn = Wv + rr + P - j0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int j = k0 + kq + q + 1;
-                double d;
-                if (contig) {  // one window: offsets past P read it at P, then give 0
-                    const int jc = min(j, P);
-                    d = Wv[rr + P + jc] - Wv[rr + P - jc];
-                    if (j > P) d = 0.0;
-                } else {
-                    d = d_elem<BM>(false, Wv, V, rbase, rcell, nx, P, rr, j);
+                for (int q = 0; q < 8; ++q) d[q] = up[q] - dn[-q];
+            } else if (contig) {  // offsets past P read the window at P, then give 0
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int j = j0 + q, jc = min(j, P);
+                    const double v = Wv[rr + P + jc] - Wv[rr + P - jc];
+                    d[q] = j > P ? 0.0 : v;
                 }
-                uint16_t h, l;
-                split16<TR::half>(d, &h, &l);
-                hv[q] = (short)h;
-                lv[q] = (short)l;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) d[q] = d_elem<BM>(false, Wv, V, rbase, rcell, nx, P, rr, j0 + q);
             }
-            *reinterpret_cast<s16x8*>(&Dh[buf][rr][kq]) = hv;
-            if constexpr (TR::split) *reinterpret_cast<s16x8*>(&Dl[buf][rr][kq]) = lv;
+            // hi = round16(d); split forms also lo = round16(d - hi) (d - hi is exact in FP64)
+            uint32_t hv[4], lv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                hv[q] = pack16<TR::half>(d[2 * q], d[2 * q + 1]);
+                if constexpr (TR::split)
+                    lv[q] = pack16<TR::half>(d[2 * q] - value16<TR::half>(hv[q] & 0xFFFFu),
+                                             d[2 * q + 1] - value16<TR::half>(hv[q] >> 16));
+            }
+            *reinterpret_cast<uint4*>(&Dh[buf][rr][kq]) = make_uint4(hv[0], hv[1], hv[2], hv[3]);
+            if constexpr (TR::split)
+                *reinterpret_cast<uint4*>(&Dl[buf][rr][kq]) = make_uint4(lv[0], lv[1], lv[2], lv[3]);
         }
     };
     auto load_b = [&](int k0, s16x8* bh, s16x8* bl) {
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
 
     if (layout == WK_HALF) {
         // staged through LDS so that whole rows of the half table leave in 16-byte stores
-        float* stg = reinterpret_cast<float*>(lds_ops);  // [16 * WAVES_M][BN]
+        float* stg = reinterpret_cast<float*>(lds_ops);  // [16 * WAVES_M][SP]
         constexpr int SR = 16 * WAVES_M;
         const int ncol = min(BN, P - col0);
 #pragma unroll
@@ -405,7 +407,7 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
             for (int tn = 0; tn < WN; ++tn)
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    stg[(wr * 16 + 4 * lk + e) * BN + (wc * WN + tn) * 16 + lr] = c * acc[tm][tn][e];
+                    stg[(wr * 16 + 4 * lk + e) * SP + (wc * WN + tn) * 16 + lr] = c * acc[tm][tn][e];
             __syncthreads();
             // local row q of the stage is global row row0 + ((q / 16) * WM + tm) * 16 + q % 16
             if ((P & 3) == 0) {
@@ -414,13 +416,13 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
                     const long row = row0 + ((q / 16) * WM + tm) * 16 + (q & 15);
                     if (row < R && c4 < ncol)
                         *reinterpret_cast<float4*>(out + row * P + col0 + c4) =
-                            *reinterpret_cast<const float4*>(stg + q * BN + c4);
+                            *reinterpret_cast<const float4*>(stg + q * SP + c4);
                 }
             } else {
                 for (int f = threadIdx.x; f < SR * BN; f += KE_THREADS) {
                     const int q = f / BN, cc = f - q * BN;
                     const long row = row0 + ((q / 16) * WM + tm) * 16 + (q & 15);
-                    if (row < R && cc < ncol) out[row * P + col0 + cc] = stg[q * BN + cc];
+                    if (row < R && cc < ncol) out[row * P + col0 + cc] = stg[q * SP + cc];
                 }
             }
             __syncthreads();
@@ -465,7 +467,7 @@ static int tile_bn(int cfg) { return cfg == CFG_LARGE ? 256 : (cfg == CFG_MID ? 
 // covers H <= 128 (P <= 257), so each difference is formed once per row.
 static int fold_cfg(int H) { return H > 64 ? CFG_LARGE : (H > 32 ? CFG_MID : CFG_SMALL); }
 static int fold_bn(int cfg) { return cfg == CFG_LARGE ? 128 : (cfg == CFG_MID ? 64 : 32); }
-static int fold_bm(int cfg) { return cfg == CFG_LARGE ? 32 : 64; }
+static int fold_bm(int cfg) { (void)cfg; return 64; }
 
 int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_t* cells,
                        int n_cells, int layout, double* out, hipStream_t stream) {
@@ -490,7 +492,7 @@ int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_
     WK_LAUNCH("kernel_eval_f64", (kernel_eval_f64<WM, WN, WNV>), grid, dim3(KE_THREADS), 0, stream, V, \
                        mesh->nx, R, n_cells, cells, P, n_m, H, Hk, Hn, So, Se, c, layout, out)
     if (cfg == CFG_LARGE)
-        KE_LAUNCH_F64(2, 2, 4);
+        KE_LAUNCH_F64(4, 2, 4);
     else if (cfg == CFG_MID)
         KE_LAUNCH_F64(4, 1, 4);
     else
