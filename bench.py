@@ -127,12 +127,12 @@ def run_kernel_forms():
     V = torch.from_numpy(inputs.random_potentials(B, nx, c3["dx"], seed=c3["seed"])).cuda()
     entries = B * nx * n_m
     # FLOP of the direct sum of eq.(4) (the unit of "alg_TFLOPs"), and the MFMA FLOP each form
-    # issues: the FP64 path runs the odd/even fold (two H x H products per row, H = P / 2),
-    # the 16-bit paths the direct P x P product, three times for the split forms.
+    # issues: every form runs the odd/even fold (two H x H products per row, H = P / 2), three
+    # times for the split forms.
     flops = 2.0 * (P - 1) ** 2 * B * nx
     H = P // 2
-    issued = {"fp64": 4.0 * H * H, "bf16": 2.0 * P * P, "fp16": 2.0 * P * P,
-              "bf16x3": 6.0 * P * P, "fp16x3": 6.0 * P * P}
+    issued = {"fp64": 4.0 * H * H, "bf16": 4.0 * H * H, "fp16": 4.0 * H * H,
+              "bf16x3": 12.0 * H * H, "fp16x3": 12.0 * H * H}
     out = {"workload": "precision batch: 4096 potentials x 2048 cells x 512 m, half table"}
     ref = ops.kernel_eval(V, n_m, layout="half")
     refmax = ref.reshape(B, -1).abs().amax(dim=1)

@@ -231,13 +231,14 @@ __global__ void kernel_zero_f64(double* __restrict__ out, long n) {
     if (idx < n) out[idx] = 0.0;
 }
 
-// Reduced-precision path: v_mfma_f32_16x16x32_{bf16,f16} with FP32 accumulation.  Layouts
-// (16x16x32): lane l holds A[l % 16][8 (l / 16) + q], B[8 (l / 16) + q][l % 16] for q < 8,
-// and C[4 (l / 16) + e][l % 16] for e < 4.  The potential differences are formed in FP64
-// and rounded to the 16-bit format (hi); the split forms also keep lo = d - hi, and sum
-// hi*hi + hi*lo + lo*hi (the lo*lo term is below FP32 accumulation error).
-// The sine table is read transposed, St[t][jj] (it is symmetric), so each lane's eight
-// B elements are one contiguous 16-byte load.
+// Reduced-precision path: v_mfma_f32_16x16x32_{bf16,f16} with FP32 accumulation, on the same
+// odd/even fold as the FP64 path (O and E accumulated separately, K(m) = c(O+E),
+// K(P-m) = c(O-E)).  Layouts (16x16x32): lane l holds A[l % 16][8 (l / 16) + q],
+// B[8 (l / 16) + q][l % 16] for q < 8, and C[4 (l / 16) + e][l % 16] for e < 4.  The potential
+// differences are formed in FP64 and rounded to the 16-bit format (hi); the split forms also
+// keep lo = d - hi, and sum hi*hi + hi*lo + lo*hi (the lo*lo term is below FP32 accumulation
+// error).  The fold tables are read transposed, T[t][k], so each lane's eight B elements are
+// one contiguous 16-byte load.
 constexpr int LP_BK = 32;
 
 template <int PREC>
@@ -276,20 +277,21 @@ __device__ __forceinline__ f32x4 mfma16(const s16x8& a, const s16x8& b, f32x4 c)
 template <int PREC, int WM, int WN, int WAVES_N>
 __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
-    int P, int n_m, int Pk, const uint16_t* __restrict__ St_hi, const uint16_t* __restrict__ St_lo,
-    float c, int layout, float* __restrict__ out) {
+    int P, int n_m, int H, int Hk, const uint16_t* __restrict__ To_hi, const uint16_t* __restrict__ Te_hi,
+    const uint16_t* __restrict__ To_lo, const uint16_t* __restrict__ Te_lo, float c, int layout,
+    float* __restrict__ out) {
     typedef LowpTraits<PREC> TR;
     constexpr int WAVES_M = 4 / WAVES_N;
     constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N, BK = LP_BK, LD = BK + 8;
+    constexpr int NS = TR::split ? 2 : 1;  // hi (and lo) tiles
     static_assert(BM == KE_BM, "row tile");
-    // operand tiles during the contraction; the same bytes stage the output afterwards
-    // (16 * WAVES_M rows x BN columns of FP32 at a time)
-    constexpr int OPS = 2 * BM * LD * 2 + 2 * (TR::split ? BM : 1) * LD * 2;
-    constexpr int SP = BN + 4;  // stage row stride in floats (rows 4 apart on distinct banks)
+    // operand tiles [buffer][part][hi, lo][row][k] during the contraction; the same bytes stage
+    // whole output rows afterwards (16 * WAVES_M rows of up to 2 BN + 4 floats)
+    constexpr int OPS = 2 * 2 * NS * BM * LD * 2;
+    constexpr int SP = 2 * BN + 4;
     constexpr int STG = 16 * WAVES_M * SP * 4;
     __shared__ __attribute__((aligned(16))) char lds_ops[OPS > STG ? OPS : STG];
-    auto Dh = reinterpret_cast<uint16_t(*)[BM][LD]>(lds_ops);
-    auto Dl = reinterpret_cast<uint16_t(*)[TR::split ? BM : 1][LD]>(lds_ops + 2 * BM * LD * 2);
+    auto Dt = reinterpret_cast<uint16_t(*)[2][NS][BM][LD]>(lds_ops);
     __shared__ double Wv[KE_WIN];
     __shared__ long rbase[BM];
     __shared__ int rcell[BM];
@@ -304,27 +306,30 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     if (contig) load_window<BM>(V, (row0 / n_cells) * (long)nx, (int)(row0 % n_cells), nx, P, Wv);
     __syncthreads();
 
+    // group g of a step: part g / (BM BK/8), row g % BM, eight consecutive k; the 64 lanes of
+    // a wave take 64 consecutive rows (window reads on distinct banks).  Offsets j = 2k+1+part.
     auto build = [&](int k0, int buf) {
-        for (int e = threadIdx.x; e < BM * (BK / 8); e += KE_THREADS) {
-            const int rr = e / (BK / 8), kq = (e - rr * (BK / 8)) * 8;
-            const int j0 = k0 + kq + 1;
+        for (int g = threadIdx.x; g < 2 * BM * (BK / 8); g += KE_THREADS) {
+            const int part = g / (BM * (BK / 8)), rem = g - part * (BM * (BK / 8));
+            const int rr = rem % BM, kq = (rem / BM) * 8;
+            const int j0 = 2 * (k0 + kq) + 1 + part;
             double d[8];
-            if (contig && j0 + 7 <= P) {
+            if (contig && j0 + 14 <= P) {
                 // one window, eight offsets in range: sixteen independent LDS reads
                 const double* up = Wv + rr + P + j0;
                 const double* dn = Wv + rr + P - j0;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) d[q] = up[q] - dn[-q];
+                for (int q = 0; q < 8; ++q) d[q] = up[2 * q] - dn[-2 * q];
             } else if (contig) {  // offsets past P read the window at P, then give 0
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    const int j = j0 + q, jc = min(j, P);
+                    const int j = j0 + 2 * q, jc = min(j, P);
                     const double v = Wv[rr + P + jc] - Wv[rr + P - jc];
                     d[q] = j > P ? 0.0 : v;
                 }
             } else {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) d[q] = d_elem<BM>(false, Wv, V, rbase, rcell, nx, P, rr, j0 + q);
+                for (int q = 0; q < 8; ++q) d[q] = d_elem<BM>(false, Wv, V, rbase, rcell, nx, P, rr, j0 + 2 * q);
             }
             // hi = round16(d); split forms also lo = round16(d - hi) (d - hi is exact in FP64)
             uint32_t hv[4], lv[4];
@@ -335,29 +340,35 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
                     lv[q] = pack16<TR::half>(d[2 * q] - value16<TR::half>(hv[q] & 0xFFFFu),
                                              d[2 * q + 1] - value16<TR::half>(hv[q] >> 16));
             }
-            *reinterpret_cast<uint4*>(&Dh[buf][rr][kq]) = make_uint4(hv[0], hv[1], hv[2], hv[3]);
+            *reinterpret_cast<uint4*>(&Dt[buf][part][0][rr][kq]) = make_uint4(hv[0], hv[1], hv[2], hv[3]);
             if constexpr (TR::split)
-                *reinterpret_cast<uint4*>(&Dl[buf][rr][kq]) = make_uint4(lv[0], lv[1], lv[2], lv[3]);
+                *reinterpret_cast<uint4*>(&Dt[buf][part][NS - 1][rr][kq]) = make_uint4(lv[0], lv[1], lv[2], lv[3]);
         }
     };
-    auto load_b = [&](int k0, s16x8* bh, s16x8* bl) {
+    const uint16_t* Th[2] = {To_hi, Te_hi};
+    const uint16_t* Tl[2] = {To_lo, Te_lo};
+    auto load_b = [&](int k0, s16x8 (&bh)[2][WN], s16x8 (&bl)[2][WN]) {
 #pragma unroll
-        for (int tn = 0; tn < WN; ++tn) {
-            const long off = (long)(col0 + (wc * WN + tn) * 16 + lr) * Pk + k0 + 8 * lk;
-            bh[tn] = *reinterpret_cast<const s16x8*>(St_hi + off);
-            if constexpr (TR::split) bl[tn] = *reinterpret_cast<const s16x8*>(St_lo + off);
-        }
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int tn = 0; tn < WN; ++tn) {
+                const long off = (long)(col0 + (wc * WN + tn) * 16 + lr) * Hk + k0 + 8 * lk;
+                bh[p][tn] = *reinterpret_cast<const s16x8*>(Th[p] + off);
+                if constexpr (TR::split) bl[p][tn] = *reinterpret_cast<const s16x8*>(Tl[p] + off);
+            }
     };
 
-    f32x4 acc[WM][WN];
+    f32x4 acc[2][WM][WN];
 #pragma unroll
-    for (int a = 0; a < WM; ++a)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int b = 0; b < WN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int a = 0; a < WM; ++a)
+#pragma unroll
+            for (int b = 0; b < WN; ++b) acc[p][a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // sine fragments are loaded one step ahead into nh / nl only and moved into bh / bl at
     // the top of each step (no product waits on a load issued in its own step)
-    s16x8 nh[WN], nl[WN];
+    s16x8 nh[2][WN], nl[2][WN];
     load_b(0, nh, nl);
     build(0, 0);
     __syncthreads();
@@ -365,65 +376,70 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     // merges them into the loop and makes each step's products wait on the next step's loads
     __builtin_amdgcn_s_waitcnt(0);
     int buf = 0;
-    for (int k0 = 0; k0 < Pk; k0 += BK) {
-        const bool more = k0 + BK < Pk;
-        s16x8 bh[WN], bl[WN];
+    for (int k0 = 0; k0 < Hk; k0 += BK) {
+        const bool more = k0 + BK < Hk;
+        s16x8 bh[2][WN], bl[2][WN];
 #pragma unroll
-        for (int tn = 0; tn < WN; ++tn) {
-            bh[tn] = nh[tn];
-            if constexpr (TR::split) bl[tn] = nl[tn];
-        }
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int tn = 0; tn < WN; ++tn) {
+                bh[p][tn] = nh[p][tn];
+                if constexpr (TR::split) bl[p][tn] = nl[p][tn];
+            }
         if (more) {
             load_b(k0 + BK, nh, nl);
             build(k0 + BK, buf ^ 1);
         }
 #pragma unroll
-        for (int tm = 0; tm < WM; ++tm) {
-            const int rr = (wr * WM + tm) * 16 + lr;
-            const s16x8 ah = *reinterpret_cast<const s16x8*>(&Dh[buf][rr][8 * lk]);
-            s16x8 al;
-            if constexpr (TR::split) al = *reinterpret_cast<const s16x8*>(&Dl[buf][rr][8 * lk]);
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int tn = 0; tn < WN; ++tn) {
-                acc[tm][tn] = mfma16<TR::half>(ah, bh[tn], acc[tm][tn]);
-                if constexpr (TR::split) {
-                    acc[tm][tn] = mfma16<TR::half>(ah, bl[tn], acc[tm][tn]);
-                    acc[tm][tn] = mfma16<TR::half>(al, bh[tn], acc[tm][tn]);
+            for (int tm = 0; tm < WM; ++tm) {
+                const int rr = (wr * WM + tm) * 16 + lr;
+                const s16x8 ah = *reinterpret_cast<const s16x8*>(&Dt[buf][p][0][rr][8 * lk]);
+                s16x8 al;
+                if constexpr (TR::split) al = *reinterpret_cast<const s16x8*>(&Dt[buf][p][NS - 1][rr][8 * lk]);
+#pragma unroll
+                for (int tn = 0; tn < WN; ++tn) {
+                    acc[p][tm][tn] = mfma16<TR::half>(ah, bh[p][tn], acc[p][tm][tn]);
+                    if constexpr (TR::split) {
+                        acc[p][tm][tn] = mfma16<TR::half>(ah, bl[p][tn], acc[p][tm][tn]);
+                        acc[p][tm][tn] = mfma16<TR::half>(al, bh[p][tn], acc[p][tm][tn]);
+                    }
                 }
             }
-        }
         __syncthreads();
         buf ^= 1;
     }
 
-    if (layout == WK_HALF) {
-        // staged through LDS so that whole rows of the half table leave in 16-byte stores
+    if (layout == WK_HALF && gridDim.y == 1 && (P & 3) == 0 && P <= SP - 4) {
+        // one column block holds every m of its rows: whole rows of the half table are staged
+        // in LDS and leave in 16-byte stores (entry m - 1 holds K(m), m = 1..P)
         float* stg = reinterpret_cast<float*>(lds_ops);  // [16 * WAVES_M][SP]
         constexpr int SR = 16 * WAVES_M;
-        const int ncol = min(BN, P - col0);
 #pragma unroll
         for (int tm = 0; tm < WM; ++tm) {
 #pragma unroll
-            for (int tn = 0; tn < WN; ++tn)
+            for (int tn = 0; tn < WN; ++tn) {
+                const int t = (wc * WN + tn) * 16 + lr, m = t + 1;
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    stg[(wr * 16 + 4 * lk + e) * SP + (wc * WN + tn) * 16 + lr] = c * acc[tm][tn][e];
+                for (int e = 0; e < 4; ++e) {
+                    float* srow = stg + (wr * 16 + 4 * lk + e) * SP;
+                    if (t < H) {
+                        const float o = acc[0][tm][tn][e], ev = acc[1][tm][tn][e];
+                        srow[m - 1] = c * (o + ev);
+                        if (2 * m < P) srow[P - m - 1] = c * (o - ev);
+                    }
+                    if (t == 0) srow[P - 1] = 0.0f;
+                }
+            }
             __syncthreads();
             // local row q of the stage is global row row0 + ((q / 16) * WM + tm) * 16 + q % 16
-            if ((P & 3) == 0) {
-                for (int f = threadIdx.x; f < SR * (BN / 4); f += KE_THREADS) {
-                    const int q = f / (BN / 4), c4 = (f - q * (BN / 4)) * 4;
-                    const long row = row0 + ((q / 16) * WM + tm) * 16 + (q & 15);
-                    if (row < R && c4 < ncol)
-                        *reinterpret_cast<float4*>(out + row * P + col0 + c4) =
-                            *reinterpret_cast<const float4*>(stg + q * SP + c4);
-                }
-            } else {
-                for (int f = threadIdx.x; f < SR * BN; f += KE_THREADS) {
-                    const int q = f / BN, cc = f - q * BN;
-                    const long row = row0 + ((q / 16) * WM + tm) * 16 + (q & 15);
-                    if (row < R && cc < ncol) out[row * P + col0 + cc] = stg[q * SP + cc];
-                }
+            for (int f = threadIdx.x; f < SR * (P / 4); f += KE_THREADS) {
+                const int q = f / (P / 4), c4 = (f - q * (P / 4)) * 4;
+                const long row = row0 + ((q / 16) * WM + tm) * 16 + (q & 15);
+                if (row < R)
+                    *reinterpret_cast<float4*>(out + row * P + c4) =
+                        *reinterpret_cast<const float4*>(stg + q * SP + c4);
             }
             __syncthreads();
         }
@@ -433,20 +449,30 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     for (int tm = 0; tm < WM; ++tm) {
 #pragma unroll
         for (int tn = 0; tn < WN; ++tn) {
-            const int t = col0 + (wc * WN + tn) * 16 + lr;
+            const int t = col0 + (wc * WN + tn) * 16 + lr, m = t + 1;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const long row = row0 + (wr * WM + tm) * 16 + 4 * lk + e;
-                if (row >= R || t >= P) continue;
-                const float k = c * acc[tm][tn][e];
-                {
-                    float* o = out + row * (long)n_m;
-                    if (t < P - 1) {
-                        o[P + 1 + t] = k;
-                        o[P - 1 - t] = -k;
-                    } else {
-                        o[0] = -k;
-                        o[P] = 0.0f;
+                if (row >= R || t >= H) continue;
+                const float o = acc[0][tm][tn][e], ev = acc[1][tm][tn][e];
+                const float kp = c * (o + ev), km = c * (o - ev);
+                const bool mirror = 2 * m < P;
+                if (layout == WK_HALF) {
+                    float* h = out + row * P;
+                    h[m - 1] = kp;
+                    if (mirror) h[P - m - 1] = km;
+                    if (t == 0) h[P - 1] = 0.0f;
+                } else {
+                    float* f = out + row * (long)n_m;
+                    f[P + m] = kp;
+                    f[P - m] = -kp;
+                    if (mirror) {
+                        f[2 * P - m] = km;
+                        f[m] = -km;
+                    }
+                    if (t == 0) {
+                        f[0] = 0.0f;
+                        f[P] = 0.0f;
                     }
                 }
             }
@@ -454,16 +480,18 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     }
 }
 
+// n_m = 2 in reduced precision: every entry is zero.
+__global__ void kernel_zero_f32(float* __restrict__ out, long n) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) out[idx] = 0.0f;
+}
+
 static int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
-// Tile shape by table width: waves split the columns when P is large (one column block
-// covers P <= 256, so each potential difference is formed once per row).
 enum { CFG_SMALL = 0, CFG_MID = 1, CFG_LARGE = 2 };
-static int tile_cfg(int P) { return P > 128 ? CFG_LARGE : (P > 64 ? CFG_MID : CFG_SMALL); }
-static int tile_bn(int cfg) { return cfg == CFG_LARGE ? 256 : (cfg == CFG_MID ? 128 : 64); }
 
-// Folded FP64 tiles by H = floor(P / 2): 32 x 128 blocks of 32 x 32 wave tiles (both parts,
-// eight accumulators) for H > 64, 64 x 64 for H in (32, 64], 64 x 32 below; one column block
+// Folded FP64 tiles by H = floor(P / 2): 64 x 128 blocks of 64 x 32 wave tiles (both parts,
+// sixteen accumulators) for H > 64, 64 x 64 for H in (32, 64], 64 x 32 below; one column block
 // covers H <= 128 (P <= 257), so each difference is formed once per row.
 static int fold_cfg(int H) { return H > 64 ? CFG_LARGE : (H > 32 ? CFG_MID : CFG_SMALL); }
 static int fold_bn(int cfg) { return cfg == CFG_LARGE ? 128 : (cfg == CFG_MID ? 64 : 32); }
@@ -501,52 +529,65 @@ int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_
     return check_launch("kernel_eval_f64");
 }
 
+// 16-bit fold tiles by H: 64 x 128 blocks of 64 x 32 wave tiles (both parts) for H > 64,
+// 64 x 64 for H in (32, 64], 64 x 32 below.
 template <int PREC>
 static void launch_lowp(int cfg, dim3 grid, hipStream_t stream, const double* V, int nx, long R,
-                        int n_cells, const int32_t* cells, int P, int n_m, int Pk,
-                        const uint16_t* hi, const uint16_t* lo, float c, int layout, float* out) {
+                        int n_cells, const int32_t* cells, int P, int n_m, int H, int Hk,
+                        const uint16_t* const* T, float c, int layout, float* out) {
+#define KE_LAUNCH_LP(WM, WN, WNV)                                                                  \
+    WK_LAUNCH("kernel_eval_lowp", (kernel_eval_lowp<PREC, WM, WN, WNV>), grid, dim3(KE_THREADS), 0, \
+              stream, V, nx, R, n_cells, cells, P, n_m, H, Hk, T[0], T[1], T[2], T[3], c, layout, out)
     if (cfg == CFG_LARGE)
-        WK_LAUNCH("kernel_eval_lowp", (kernel_eval_lowp<PREC, 4, 4, 4>), grid, dim3(KE_THREADS), 0, stream, V, nx,
-                           R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+        KE_LAUNCH_LP(4, 2, 4);
     else if (cfg == CFG_MID)
-        WK_LAUNCH("kernel_eval_lowp", (kernel_eval_lowp<PREC, 2, 4, 2>), grid, dim3(KE_THREADS), 0, stream, V, nx,
-                           R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+        KE_LAUNCH_LP(4, 1, 4);
     else
-        WK_LAUNCH("kernel_eval_lowp", (kernel_eval_lowp<PREC, 1, 4, 1>), grid, dim3(KE_THREADS), 0, stream, V, nx,
-                           R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+        KE_LAUNCH_LP(2, 1, 2);
+#undef KE_LAUNCH_LP
 }
 
 int kernel_eval_1d_lowp(const wk_mesh* mesh, const double* V, int B, const int32_t* cells,
                         int n_cells, int prec, int layout, float* out, hipStream_t stream) {
-    const int n_m = mesh->n_m, P = n_m / 2;
-    const int cfg = tile_cfg(P), BN = tile_bn(cfg);
-    const int Pk = round_up(P, LP_BK), Pn = round_up(P, BN);
+    const int n_m = mesh->n_m, P = n_m / 2, H = P / 2;
+    const long R = (long)B * n_cells;
+    if (R == 0) return WK_OK;
+    if (H == 0) {
+        const long n = R * (layout == WK_HALF ? P : n_m);
+        hipLaunchKernelGGL(kernel_zero_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, out, n);
+        return check_launch("kernel_zero_f32");
+    }
+    const int cfg = fold_cfg(H), BN = fold_bn(cfg);
+    const int Hk = round_up(H, LP_BK), Hn = round_up(H, BN);
     const bool half = prec == WK_FP16 || prec == WK_FP16X3;
     const bool split = prec == WK_BF16X3 || prec == WK_FP16X3;
+    const int fh = half ? 3 : 1, fl = half ? 4 : 2;
+    // transposed fold tables T[t][k] (Hn rows, Hk columns): odd hi, even hi, odd lo, even lo
+    const int kinds[4] = {fh | SINE_ODD_T, fh | SINE_EVEN_T, fl | SINE_ODD_T, fl | SINE_EVEN_T};
+    const uint16_t* T[4];
     int err = WK_OK;
-    // rows t (Pn of them), columns jj (Pk): St[t][jj] = S[jj][t]
-    const uint16_t* hi = static_cast<const uint16_t*>(sine_table(n_m, half ? 3 : 1, Pn, Pk, stream, &err));
-    if (!hi) return err;
-    const uint16_t* lo = hi;
-    if (split) {
-        lo = static_cast<const uint16_t*>(sine_table(n_m, half ? 4 : 2, Pn, Pk, stream, &err));
-        if (!lo) return err;
+    for (int i = 0; i < 4; ++i) {
+        if (i >= 2 && !split) {
+            T[i] = T[i - 2];
+            continue;
+        }
+        T[i] = static_cast<const uint16_t*>(sine_table(n_m, kinds[i], Hn, Hk, stream, &err));
+        if (!T[i]) return err;
     }
-    const long R = (long)B * n_cells;
     const float c = (float)(-2.0 / (mesh->hbar * (double)n_m));
-    dim3 grid((unsigned)((R + KE_BM - 1) / KE_BM), (unsigned)(Pn / BN));
+    dim3 grid((unsigned)((R + KE_BM - 1) / KE_BM), (unsigned)(Hn / BN));
     switch (prec) {
         case WK_BF16:
-            launch_lowp<WK_BF16>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            launch_lowp<WK_BF16>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, H, Hk, T, c, layout, out);
             break;
         case WK_FP16:
-            launch_lowp<WK_FP16>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            launch_lowp<WK_FP16>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, H, Hk, T, c, layout, out);
             break;
         case WK_BF16X3:
-            launch_lowp<WK_BF16X3>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            launch_lowp<WK_BF16X3>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, H, Hk, T, c, layout, out);
             break;
         default:
-            launch_lowp<WK_FP16X3>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, Pk, hi, lo, c, layout, out);
+            launch_lowp<WK_FP16X3>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, H, Hk, T, c, layout, out);
             break;
     }
     return check_launch("kernel_eval_lowp");

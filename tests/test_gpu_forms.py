@@ -24,8 +24,12 @@ ETA_IN = {"bf16": 2.0 ** -126, "fp16": 2.0 ** -14}
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16x3", "fp16x3"])
-@pytest.mark.parametrize("nx,n_m,B", [(300, 64, 3), (2048, 512, 2), (100, 30, 2)])
+@pytest.mark.parametrize("nx,n_m,B", [(300, 64, 3), (2048, 512, 2), (100, 30, 2), (1024, 256, 2),
+                                      (300, 134, 2), (90, 1024, 1), (70, 1100, 1), (41, 6, 2)])
 def test_lowp_kernel_error_bounds(orc, prec, nx, n_m, B):
+    """Both layouts; every fold tile shape (H = n_m / 4 below 32, in (32, 64], above 64), odd
+    P, whole-row staging (one column block, P % 4 == 0) and per-entry stores (several column
+    blocks, odd P, the full layout), rows built from the LDS window and from L2 (n_m = 1100)."""
     print(f"lowp {prec} nx={nx} n_m={n_m}", flush=True)
     V = inputs.random_potentials(B, nx, 0.5, seed=nx + 7)
     ref = orc.kernel_1d(V, n_m, HB)
