@@ -232,6 +232,195 @@ __global__ __launch_bounds__(SU_THREADS) void surr_fwd_mfma(
     }
 }
 
+// Forward with the whole transposed table Bt in LDS (used when it fits): persistent
+// workgroups load Bt once, then per tile of SF_BM rows form A in LDS (as above), and each wave
+// takes 16 rows: its A fragments for the whole contraction move into registers, and it sweeps
+// the column tiles four at a time (four independent accumulators), B fragments from LDS.
+// Natural contraction order per 16x16x32 step (g = 32 s + 8 (l / 16) + q); the FP32 form
+// takes four 16x16x4 steps per 16-byte fragment (g = 16 s + 4 (l / 16) + q, step q).
+template <bool BF16, int HK>
+__global__ __launch_bounds__(SU_THREADS) void surr_fwd_lds(
+    const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
+    int P, int N, int H, int Pn, const float* __restrict__ wV,
+    const float* __restrict__ Btf, const uint16_t* __restrict__ Btb,
+    const float* __restrict__ Pif, float* __restrict__ out) {
+    using AT = typename std::conditional<BF16, uint16_t, float>::type;
+    constexpr int LD = HK + (BF16 ? 8 : 4);    // row stride (elements): 16-byte rows, spread banks
+    constexpr int NF = BF16 ? HK / 32 : HK / 16;  // 16-byte A fragments per lane
+    extern __shared__ double smem_fl[];
+    __shared__ int rcell[SF_BM];
+    __shared__ long rbase[SF_BM];
+    // column tiles padded to a multiple of four (zero rows of Bt, zero Pi): no per-tile guards
+    const int Pn4 = (Pn + 63) / 64 * 64;
+    AT* Bs = reinterpret_cast<AT*>(smem_fl);                               // [Pn4][LD]
+    AT* As = Bs + (long)Pn4 * LD;                                          // [SF_BM][LD]
+    float* Pis = reinterpret_cast<float*>(As + SF_BM * LD);                // [Pn4]
+    double* Vw = smem_fl + ((long)(Pn4 + SF_BM) * LD * (long)sizeof(AT) + 4L * Pn4 + 7) / 8;  // [SF_BM + 2P]
+    for (int e = threadIdx.x; e < Pn4 * HK; e += blockDim.x) {
+        const int t = e / HK, g = e - t * HK;
+        Bs[t * LD + g] = t < Pn ? (BF16 ? (AT)Btb[e] : (AT)Btf[e]) : (AT)0;
+    }
+    for (int t = threadIdx.x; t < Pn4; t += blockDim.x) Pis[t] = t < P ? Pif[t] : 0.f;
+    for (int e = threadIdx.x; e < SF_BM * LD; e += blockDim.x) As[e] = (AT)0;  // pads stay 0
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int nct = Pn4 / 16;
+    const long ntiles = (R + SF_BM - 1) / SF_BM;
+    // a tile whose rows are consecutive cells of one potential reads a window of it; the next
+    // tile's window is loaded into registers while this tile's products run (WPF values per
+    // thread; wider windows are loaded in place)
+    constexpr int WPF = 4;
+    const int nwin = SF_BM + 2 * P;
+    const bool pf = nwin <= WPF * SU_THREADS;
+    auto is_run = [&](long row0) {
+        const long rend = min(R, row0 + SF_BM);
+        return cells == nullptr && n_cells == nx && row0 / nx == (rend - 1) / nx;
+    };
+    double wpf[WPF];
+    auto fetch = [&](long row0) {
+        const long b = row0 / nx;
+        const int c0 = (int)(row0 - b * nx);
+        const double* Vb = V + b * (long)nx;
+#pragma unroll
+        for (int i = 0; i < WPF; ++i) {
+            const int k = threadIdx.x + i * SU_THREADS;
+            if (k < nwin) wpf[i] = Vb[min(max(c0 - P + k, 0), nx - 1)];
+        }
+    };
+    if (pf && blockIdx.x < ntiles && is_run((long)blockIdx.x * SF_BM)) fetch((long)blockIdx.x * SF_BM);
+    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long row0 = tile * SF_BM;
+        const long rend = min(R, row0 + SF_BM);
+        const int nrow = (int)(rend - row0);
+        const bool run = is_run(row0);
+        __syncthreads();  // previous tile's readers of As / Vw are done
+        if (run) {
+            if (pf) {
+#pragma unroll
+                for (int i = 0; i < WPF; ++i) {
+                    const int k = threadIdx.x + i * SU_THREADS;
+                    if (k < nwin) Vw[k] = wpf[i];
+                }
+            } else {
+                const long b = row0 / nx;
+                const int c0 = (int)(row0 - b * nx);
+                const double* Vb = V + b * (long)nx;
+                for (int k = threadIdx.x; k < nwin; k += blockDim.x) Vw[k] = Vb[min(max(c0 - P + k, 0), nx - 1)];
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < SF_BM * H; e += blockDim.x) {
+                const int rr = e / H, g = e - rr * H;
+                double a = 0.0;
+                if (rr < nrow)
+                    for (int p = 0; p < N; ++p) a += (double)wV[p] * Vw[rr + N * g + p];
+                As[rr * LD + g] = BF16 ? (AT)bf16_bits_f((float)a) : (AT)(float)a;
+            }
+        } else {
+            for (int rr = threadIdx.x; rr < SF_BM; rr += blockDim.x) {
+                const long r = row0 + rr;
+                int cell = -1;
+                long base = 0;
+                if (r < R) {
+                    const long b = r / n_cells;
+                    const int ci = (int)(r - b * n_cells);
+                    cell = cells ? cells[ci] : ci;
+                    if (cell < 0 || cell >= nx) cell = -2;  // id outside the mesh: row of NaN
+                    base = b * (long)nx;
+                }
+                rcell[rr] = cell;
+                rbase[rr] = base;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < SF_BM * H; e += blockDim.x) {
+                const int rr = e / H, g = e - rr * H;
+                const int cell = rcell[rr];
+                double a = cell == -2 ? __builtin_nan("") : 0.0;
+                if (cell >= 0) {
+                    const double* Vb = V + rbase[rr];
+                    for (int p = 0; p < N; ++p)
+                        a += (double)wV[p] * Vb[min(max(cell - P + N * g + p, 0), nx - 1)];
+                }
+                As[rr * LD + g] = BF16 ? (AT)bf16_bits_f((float)a) : (AT)(float)a;
+            }
+        }
+        __syncthreads();
+        // this wave's rows: 16 wave .. 16 wave + 15
+        s16x8 afb[BF16 ? NF : 1];
+        float4 aff[BF16 ? 1 : NF];
+        const AT* arow = As + (wave * 16 + lr) * LD;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if constexpr (BF16)
+                afb[f] = *reinterpret_cast<const s16x8*>(arow + 32 * f + 8 * lk);
+            else
+                aff[f] = *reinterpret_cast<const float4*>(arow + 16 * f + 4 * lk);
+        }
+        {
+            const long nt = tile + gridDim.x;
+            if (pf && nt < ntiles && is_run(nt * SF_BM)) fetch(nt * SF_BM);
+        }
+        for (int ct0 = 0; ct0 < nct; ct0 += 4) {
+            f32x4 acc[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                if constexpr (BF16) {
+                    s16x8 bv[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        bv[c] = *reinterpret_cast<const s16x8*>(Bs + ((ct0 + c) * 16 + lr) * LD + 32 * f + 8 * lk);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf16x8, afb[f]), __builtin_bit_cast(bf16x8, bv[c]), acc[c], 0, 0, 0);
+                } else {
+                    float4 bv[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        bv[c] = *reinterpret_cast<const float4*>(Bs + ((ct0 + c) * 16 + lr) * LD + 16 * f + 4 * lk);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(aff[f].x, bv[c].x, acc[c], 0, 0, 0);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(aff[f].y, bv[c].y, acc[c], 0, 0, 0);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(aff[f].z, bv[c].z, acc[c], 0, 0, 0);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(aff[f].w, bv[c].w, acc[c], 0, 0, 0);
+                }
+            }
+            float* orow = out + (row0 + wave * 16 + 4 * lk) * P + ct0 * 16 + lr;
+            if (nrow == SF_BM && (ct0 + 4) * 16 <= P) {
+                // whole group inside the table: no per-lane guards (stores issue back to back)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float pi = Pis[(ct0 + c) * 16 + lr];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) orow[e * P + c * 16] = pi * acc[c][e];
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int t = (ct0 + c) * 16 + lr;
+                    const float pi = Pis[t];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (t < P && wave * 16 + 4 * lk + e < nrow) orow[e * P + c * 16] = pi * acc[c][e];
+                }
+            }
+        }
+    }
+}
+
+// LDS bytes of surr_fwd_lds for a shape, or 0 when it does not fit (then surr_fwd_mfma runs).
+static size_t surr_fwd_lds_bytes(bool bf16, int Hk, int Pn, int P) {
+    if (Hk != 32 && Hk != 64 && Hk != 128 && Hk != 256) return 0;
+    const size_t es = bf16 ? 2 : 4, ld = (size_t)Hk + (bf16 ? 8 : 4);
+    const size_t pn4 = ((size_t)Pn + 63) / 64 * 64;
+    const size_t b = ((pn4 + SF_BM) * ld * es + 4 * pn4 + 7) / 8 * 8 + sizeof(double) * (SF_BM + 2 * (size_t)P);
+    return b <= 150 * 1024 ? b : 0;
+}
+
 // ----------------------------------------------------------------------------- backward
 // Per workgroup of SU_BM rows: Et = E * Pi (LDS), GA = Et Bm^T (LDS and, for dV, global),
 // block partials of GB = A^T Et (H x P) and of dwV.  A fixed-order reduction over the
@@ -491,6 +680,39 @@ extern "C" int wk_surrogate_fwd(const wk_mesh* mesh, int32_t N, const float* wV,
         hipLaunchKernelGGL(surr_prep_t, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, H, Hk, Pn,
                            w.Bf, Btf, Btb);
         const long ntiles = (R + SF_BM - 1) / SF_BM;
+        const bool bf = prec == WK_BF16;
+        // the LDS-resident form only where two workgroups fit per CU (one per CU leaves each
+        // tile's load, convolution and stores without overlap: slower than streaming Bt)
+        size_t lds = surr_fwd_lds_bytes(bf, Hk, Pn, P);
+        if (lds > 76 * 1024) lds = 0;
+        if (lds) {
+            const long per_cu = lds <= 50 * 1024 ? 3 : 2;
+            const long g = 256 * per_cu;
+            const dim3 gl((unsigned)(ntiles < g ? ntiles : g));
+#define SURR_LDS(BFV, HKV)                                                                           \
+    do {                                                                                             \
+        auto* fn = surr_fwd_lds<BFV, HKV>;                                                           \
+        if (lds > 64 * 1024 &&                                                                        \
+            hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,        \
+                                (int)lds) != hipSuccess)                                             \
+            return fail(WK_EHIP, "wk_surrogate_fwd: cannot reserve LDS");                            \
+        hipLaunchKernelGGL(fn, gl, dim3(SU_THREADS), lds, s, V, mesh->nx, R, n_cells, cells, P, N, H, \
+                           Pn, wV, Btf, Btb, w.Pif, static_cast<float*>(K_out));                    \
+    } while (0)
+            if (bf) {
+                if (Hk == 32) SURR_LDS(true, 32);
+                else if (Hk == 64) SURR_LDS(true, 64);
+                else if (Hk == 128) SURR_LDS(true, 128);
+                else SURR_LDS(true, 256);
+            } else {
+                if (Hk == 32) SURR_LDS(false, 32);
+                else if (Hk == 64) SURR_LDS(false, 64);
+                else if (Hk == 128) SURR_LDS(false, 128);
+                else SURR_LDS(false, 256);
+            }
+#undef SURR_LDS
+            return check_launch("wk_surrogate_fwd");
+        }
         const dim3 grid((unsigned)(ntiles < 4096 ? ntiles : 4096));
         // A [SF_BM][Hk + 8] (bf16) or [SF_BM][Hk + 4] (f32), then the potential window or,
         // for gathered rows, an FP32 staging copy of A

@@ -153,6 +153,25 @@ def test_surrogate_fwd(orc, N, analytic):
         assert normwise(got64.reshape(B, -1), exact.reshape(B, -1)) <= 1e-6   # float weights
 
 
+@pytest.mark.parametrize("N", [1, 2, 4, 8])
+def test_surrogate_fwd_wide(orc, N):
+    """The learned-kernel shape (256 momenta): hidden width 256 / 128 / 64 / 32; tiles inside
+    one potential (window) and across two (gathered rows), a ragged last tile.  FP32 with
+    H = 256 takes the path without the LDS-resident table."""
+    nx, n_m, B = 300, 256, 2
+    print(f"surrogate fwd n_m={n_m} N={N}", flush=True)
+    V = inputs.random_potentials(B, nx, 0.5, seed=40 + N)
+    w = _weights(n_m, N, 40 + N, False)
+    w32 = [np.asarray(x, np.float32).astype(np.float64) for x in w]
+    ref = orc.surrogate_fwd(V, n_m, N, *w32)
+    Vd = torch.from_numpy(V).to(dev())
+    wd = _f32(w)
+    got32 = to_np(learn.surrogate_fwd(Vd, n_m, N, *wd, prec="fp32")).astype(np.float64)
+    assert normwise(got32.reshape(B, -1), ref.reshape(B, -1)) <= 2e-5
+    gotbf = to_np(learn.surrogate_fwd(Vd, n_m, N, *wd, prec="bf16")).astype(np.float64)
+    assert normwise(gotbf.reshape(B, -1), ref.reshape(B, -1)) <= 3e-2
+
+
 def test_surrogate_fwd_cells(orc):
     nx, n_m, N = 120, 32, 2
     V = inputs.random_potentials(3, nx, 0.5, seed=5)
