@@ -45,7 +45,7 @@ constexpr int PLACE_BLOCKS = PB;  // workgroups placing regenerated / initial pa
 
 // Workspace (sp_workspace_size): int64 scalars[16] | int64 bcnt[PB] | int64 wcnt[NW] |
 // int64 bpart[PB] | int64 bmixed[PB] | int64 kpre[PB] | int64 bpre[PB] |
-// int32 pstart[PLACE_BLOCKS] | int32 csum[n_chunks] | uint8 occ[n_cells].
+// int32 pstart[PLACE_BLOCKS] | int32 csum[n_chunks] | uint8 occ[n_cells] | uint8 occx[n_cells].
 enum { SC_GO = 0, SC_PLACED = 1, SC_KEPT = 2 };
 
 struct WS {
@@ -82,7 +82,7 @@ static WS carve(void* ws, long n_bins) {
 static size_t ws_bytes_for(long n_bins, long n_cells) {
     return sizeof(long long) * (16 + 5 * (size_t)PB + (size_t)NW) +
            sizeof(int) * (size_t)(PLACE_BLOCKS + (n_chunks_for(n_bins) + 1) / 2 * 2) +
-           (size_t)n_cells;
+           2 * (size_t)n_cells;  // occupancy byte per cell, then its dilation along x
 }
 
 constexpr int IT = 4;          // particles per lane in the streaming passes
@@ -1241,28 +1241,43 @@ __global__ void occupied_kernel(const int32_t* __restrict__ hist, long n_cells, 
     if (lane == 0) occ[c] = any != 0ull;
 }
 
-// Cells without a table row that lie within `margin` cells (per axis) of an occupied cell,
-// compacted in ascending order by one workgroup (deterministic).
-__global__ __launch_bounds__(1024) void cells_needed_kernel(const uint8_t* __restrict__ occ,
-                                                           int dim, int nx, int ny, int margin,
-                                                           const int32_t* __restrict__ cell_slot,
+// Cells without a table row that lie within `margin` cells (per axis) of an occupied cell.
+// The box test is separable: dilate the occupancy along x, then along y (one thread per cell
+// each), then one workgroup compacts the flagged cells in ascending order (deterministic).
+__global__ void dilate_x_kernel(const uint8_t* __restrict__ occ, int nx, long n_cells, int margin,
+                                uint8_t* __restrict__ occx) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const int cx = (int)(c % nx);
+    const uint8_t* row = occ + (c - cx);
+    int o = 0;
+    for (int xx = max(cx - margin, 0); xx <= min(cx + margin, nx - 1) && !o; ++xx) o = row[xx];
+    occx[c] = o != 0;
+}
+
+__global__ void need_kernel(const uint8_t* __restrict__ occx, int dim, int nx, int ny, int margin,
+                            const int32_t* __restrict__ cell_slot, uint8_t* __restrict__ need) {
+    const long n_cells = (long)nx * ny;
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    int o = 0;
+    if (cell_slot[c] < 0) {
+        const int cx = (int)(c % nx), cy = (int)(c / nx);
+        const int y0 = dim == 2 ? max(cy - margin, 0) : 0, y1 = dim == 2 ? min(cy + margin, ny - 1) : 0;
+        for (int yy = y0; yy <= y1 && !o; ++yy) o = occx[(long)yy * nx + cx];
+    }
+    need[c] = o != 0;
+}
+
+__global__ __launch_bounds__(1024) void cells_needed_kernel(const uint8_t* __restrict__ need,
+                                                           long n_cells,
                                                            int32_t* __restrict__ new_cells,
                                                            long long* __restrict__ d_count) {
     __shared__ int wsum[16];
-    const long n_cells = (long)nx * ny;
     const long per = (n_cells + 1023) / 1024;
     const long lo = min(n_cells, (long)threadIdx.x * per), hi = min(n_cells, lo + per);
-    auto needed = [&](long c) -> int {
-        if (cell_slot[c] >= 0) return 0;
-        const int cx = (int)(c % nx), cy = (int)(c / nx);
-        const int y0 = dim == 2 ? max(cy - margin, 0) : 0, y1 = dim == 2 ? min(cy + margin, ny - 1) : 0;
-        for (int yy = y0; yy <= y1; ++yy)
-            for (int xx = max(cx - margin, 0); xx <= min(cx + margin, nx - 1); ++xx)
-                if (occ[(long)yy * nx + xx]) return 1;
-        return 0;
-    };
     int cnt = 0;
-    for (long c = lo; c < hi; ++c) cnt += needed(c);
+    for (long c = lo; c < hi; ++c) cnt += need[c];
     // block exclusive scan of cnt over 1024 threads (16 waves)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int inc = wave_incl_scan(cnt);
@@ -1275,7 +1290,7 @@ __global__ __launch_bounds__(1024) void cells_needed_kernel(const uint8_t* __res
     }
     long o = base + inc - cnt;
     for (long c = lo; c < hi; ++c)
-        if (needed(c)) new_cells[o++] = (int32_t)c;
+        if (need[c]) new_cells[o++] = (int32_t)c;
     if (threadIdx.x == 0) *d_count = total;
 }
 
@@ -1506,12 +1521,16 @@ extern "C" int sp_cells_to_evaluate(const sp_geom* gm, const int32_t* hist, int3
     WK_REQUIRE(margin >= 0, "sp_cells_to_evaluate: negative margin");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_cells_to_evaluate: workspace too small");
     const long n_cells = (long)g.nx * g.ny;
-    uint8_t* occ = carve(ws, g.n_bins).occ;
+    uint8_t* occ = carve(ws, g.n_bins).occ;  // [n_cells] occupancy, then [n_cells] x-dilation
+    uint8_t* occx = occ + n_cells;
     hipStream_t s = as_stream(stream);
+    const dim3 cg((unsigned)((n_cells + 255) / 256));
     hipLaunchKernelGGL(occupied_kernel, dim3((unsigned)((n_cells * 64 + 255) / 256)), dim3(256), 0, s,
                        hist, n_cells, g.n_bins / n_cells, g.n_bins, occ);
-    hipLaunchKernelGGL(cells_needed_kernel, dim3(1), dim3(1024), 0, s, occ, g.dim, g.nx, g.ny, margin,
-                       cell_slot, new_cells, reinterpret_cast<long long*>(d_count));
+    hipLaunchKernelGGL(dilate_x_kernel, cg, dim3(256), 0, s, occ, g.nx, n_cells, margin, occx);
+    hipLaunchKernelGGL(need_kernel, cg, dim3(256), 0, s, occx, g.dim, g.nx, g.ny, margin, cell_slot, occ);
+    hipLaunchKernelGGL(cells_needed_kernel, dim3(1), dim3(1024), 0, s, occ, n_cells, new_cells,
+                       reinterpret_cast<long long*>(d_count));
     return check_launch("sp_cells_to_evaluate");
 }
 
