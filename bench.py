@@ -168,6 +168,35 @@ def run_kernel_forms():
     return out
 
 
+def run_2d(steps=40, warmup=8):
+    """The 2-D workload: 256 x 256 cells of 0.5 nm, 32 x 32 momenta, 5e7 particles, exact FP64
+    kernel rows formed near occupied cells (refreshed every 8 steps), annihilation every step."""
+    import torch
+    from paper_1806_00082_amd import _lib as L
+    from paper_1806_00082_amd import inputs
+    from paper_1806_00082_amd.sim import Simulator
+
+    cfg = inputs.config_c5()
+    sim = Simulator(cfg)
+    sim.run(warmup)
+    torch.cuda.synchronize()
+    sim.stats[L.ST_CUM_STEPS:L.ST_COUNT].zero_()
+    e0, e1 = _events()
+    e0.record()
+    sim.run(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    S = sim.stats.cpu().tolist()
+    out = {"workload": "2-D: 256x256 cells, 32x32 m, 5e7 particles, exact fp64 rows near occupied cells",
+           "steps": steps, "ms_per_step": round(ms / steps, 4),
+           "particle_steps_per_s": S[L.ST_CUM_N] / (ms * 1e-3), "n_last": sim.count(),
+           "kernel_rows": sim.n_rows}
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_surrogate_forms():
     """eq.(5) forward (analytic barycentric weights) vs the exact kernel, 1024 cells x 256 m."""
     import torch
@@ -264,7 +293,8 @@ def main():
     if not args.no_trace:
         tr = run_headline(args.steps, args.warmup, traced=True)
         assert tr["stats"][11:16] == h["stats"][11:16], "traced replica diverged from the timed run"
-    forms = {} if args.no_forms else {"kernel_eq4": run_kernel_forms(), "surrogate_eq5": run_surrogate_forms()}
+    forms = {} if args.no_forms else {"kernel_eq4": run_kernel_forms(), "surrogate_eq5": run_surrogate_forms(),
+                                      "workload_2d": run_2d()}
     cpu = None if args.no_cpu else run_cpu_baseline(args.cpu_steps)
     value = h["particle_steps"] / (h["ms"] * 1e-3)
     cfg = h["cfg"]

@@ -1,5 +1,6 @@
 """Time-loop level checks on the GPU: the occupied-cell kernel refresh gives the same
 trajectory as evaluating every cell; the simulator equals the oracle loop; physics sanity."""
+import ctypes
 import math
 
 import numpy as np
@@ -140,3 +141,40 @@ def test_barrier_reflection_gpu():
     assert not np.any((pos > 0) & (neg > 0))
     s = v["s"].astype(np.float64)
     assert (s * v["M"]).sum() / s.sum() < -0.8 * k0 / mesh.dk
+
+
+@pytest.mark.parametrize("dim,nx,ny,margin", [(1, 300, 1, 3), (2, 37, 23, 2), (2, 64, 50, 0), (2, 20, 70, 25)])
+def test_cells_to_evaluate_box(dim, nx, ny, margin):
+    """sp_cells_to_evaluate against the box test written out: every cell without a table row
+    that has an occupied cell within `margin` cells along each axis, in ascending order."""
+    print(f"cells to evaluate dim={dim} {nx}x{ny} margin={margin}", flush=True)
+    n_m = 8
+    mesh = inputs.Mesh1D(nx, 1.0, n_m) if dim == 1 else inputs.Mesh2D(nx, ny, 0.5, n_m)
+    md = mesh.as_dict(0.5)
+    rng = np.random.default_rng(nx * 7 + margin)
+    n_cells = nx * ny
+    per_cell = ops.n_bins(md) // n_cells
+    hist = np.zeros((2, n_cells, per_cell), np.int32)
+    occ = rng.random(n_cells) < 0.03
+    for c in np.flatnonzero(occ):                        # an occupied cell holds a particle
+        hist[rng.integers(2), c, rng.integers(per_cell)] = 1 + rng.integers(3)
+    slot = np.where(rng.random(n_cells) < 0.2, rng.integers(0, 1000, n_cells), -1).astype(np.int32)
+    grid = occ.reshape(ny, nx)
+    want = []
+    for c in range(n_cells):
+        cy, cx = divmod(c, nx)
+        box = grid[max(cy - margin, 0):cy + margin + 1, max(cx - margin, 0):cx + margin + 1]
+        if slot[c] < 0 and box.any():
+            want.append(c)
+    d_hist = torch.from_numpy(hist.reshape(-1)).to(dev())
+    d_slot = torch.from_numpy(slot).to(dev())
+    new_cells = torch.full((n_cells,), -7, dtype=torch.int32, device=dev())
+    d_count = torch.zeros(1, dtype=torch.int64, device=dev())
+    ws = ops.sp_workspace(md, 0, dev())
+    g = ops.geom_struct(md, 0)
+    L.check(L.lib().sp_cells_to_evaluate(ctypes.byref(g), ops._ptr(d_hist), margin, ops._ptr(d_slot),
+                                         ops._ptr(new_cells), ops._ptr(d_count), ops._ptr(ws), ws.numel(),
+                                         ops._stream()), "sp_cells_to_evaluate")
+    count = int(d_count.item())
+    assert count == len(want)
+    assert to_np(new_cells[:count]).tolist() == want
