@@ -168,6 +168,75 @@ def run_kernel_forms():
     return out
 
 
+def run_learning(B=64, N=4, reps=5):
+    """One SGD step of the eq.(5) training loop on 64 potentials x 1024 cells x 256 m (exact
+    FP64 labels, FP32 forward, MSE gradient, backward, update), its parts, and the eq.(4)
+    adjoint on the same batch."""
+    import torch
+    from paper_1806_00082_amd import inputs, learn, ops
+
+    c4 = inputs.C4
+    nx, n_m = c4["nx"], c4["n_m"]
+    P = n_m // 2
+    dev = torch.device("cuda")
+    V = torch.from_numpy(inputs.random_potentials(B, nx, c4["dx"], seed=c4["test_seed"])).to(dev)
+    wV, wT, W = learn.analytic_weights(n_m, N, device=dev)
+    inv_scale = 1.0 / abs(-2.0 / (inputs.HBAR_EVFS * n_m))
+    Klab = torch.empty((B * nx, P), dtype=torch.float64, device=dev)
+    Kh = torch.empty((B * nx, P), dtype=torch.float32, device=dev)
+    E = torch.empty_like(Kh)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    mws = torch.empty(8 * 1024, dtype=torch.uint8, device=dev)
+    G = torch.randn((B * nx, P), dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
+    dV = torch.zeros((B, nx), dtype=torch.float64, device=dev)
+
+    def labels():
+        ops.kernel_eval(V, n_m, layout="half", out=Klab)
+
+    def fwd():
+        learn.surrogate_fwd(V, n_m, N, wV, wT, W, prec="fp32", out=Kh)
+
+    def mse():
+        learn.mse_grad(Kh, Klab, inv_scale, E=E, loss=loss, ws=mws)
+
+    grads = {}
+
+    def bwd():
+        grads["g"] = learn.surrogate_bwd(V, n_m, N, wV, wT, W, E)
+
+    def sgd():
+        dwV, dwT, dW, _ = grads["g"]
+        learn.sgd_update(wV, dwV, 0.0)
+        learn.sgd_update(wT, dwT, 0.0)
+        learn.sgd_update(W, dW, 0.0)
+
+    def adjoint():
+        ops.kernel_bwd(G, nx, n_m, B, layout="half", dV=dV)
+
+    def step():
+        labels(), fwd(), mse(), bwd(), sgd()
+
+    def timeit(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return round(e0.elapsed_time(e1) / reps, 4)
+
+    out = {"workload": f"{B} potentials x {nx} cells x {n_m} m, N={N} (H={n_m // N}), lr 0 (timing)"}
+    for name, fn in (("labels_fp64", labels), ("surrogate_fwd_fp32", fwd), ("mse_grad", mse),
+                     ("surrogate_bwd", bwd), ("sgd_update_x3", sgd), ("train_step", step),
+                     ("kernel_adjoint_fp64", adjoint)):
+        out[name + "_ms"] = timeit(fn)
+    del Klab, Kh, E, G
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_2d(steps=40, warmup=8):
     """The 2-D workload: 256 x 256 cells of 0.5 nm, 32 x 32 momenta, 5e7 particles, exact FP64
     kernel rows formed near occupied cells (refreshed every 8 steps), annihilation every step."""
@@ -294,7 +363,7 @@ def main():
         tr = run_headline(args.steps, args.warmup, traced=True)
         assert tr["stats"][11:16] == h["stats"][11:16], "traced replica diverged from the timed run"
     forms = {} if args.no_forms else {"kernel_eq4": run_kernel_forms(), "surrogate_eq5": run_surrogate_forms(),
-                                      "workload_2d": run_2d()}
+                                      "learning": run_learning(), "workload_2d": run_2d()}
     cpu = None if args.no_cpu else run_cpu_baseline(args.cpu_steps)
     value = h["particle_steps"] / (h["ms"] * 1e-3)
     cfg = h["cfg"]

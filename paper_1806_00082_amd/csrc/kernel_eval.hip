@@ -632,111 +632,179 @@ extern "C" int wk_kernel_eval(const wk_mesh* mesh, const double* V, int32_t B,
 // K is linear in V (eq.(4)), so dL/dV = (dK/dV)^T G, computed in three deterministic steps:
 //   1. fold the table gradient onto the unique momenta: G1[r][t] = dL/dK(m = t + 1)
 //      (full layout: G(m) - G(-m), and -G(-P) for m = P);
-//   2. GD[r][jj] = c * sum_t G1[r][t] S[t][jj]  (FP64 MFMA, the sine table is symmetric);
+//   2. GD[r][jj] = c * sum_t G1[r][t] S[t][jj]  (FP64 MFMA on the odd/even fold below);
 //   3. dV[b][l] += sum_j GD[l - j][j] - sum_j GD[l + j][j], plus at the two edges the sums
 //      of every term whose clamped index lands there (per-row tails, then a fixed-order sum).
 namespace wk {
 
+// Step 2 on the odd/even fold (the transpose of the forward's): pairing m with P - m,
+//   GD[r][2k]     = c sum_{m <= H} So[k][m - 1] (G1(m) + G1(P - m))     (j = 2k + 1 odd)
+//   GD[r][2k + 1] = c sum_{m <= H} Se[k][m - 1] (G1(m) - G1(P - m))     (j = 2k + 2 even)
+// (m = P / 2 taken once), two H x H products per row; the fold tables are read transposed,
+// T[m - 1][k].  For odd P the column j = P (all sines zero) is written as 0.
 template <int WM, int WN>
 __global__ __launch_bounds__(KE_THREADS) void kernel_bwd_gemm(
-    const double* __restrict__ G, long R, int P, int n_m, int layout, int Pk, int Pn,
-    const double* __restrict__ S, double c, double* __restrict__ GD) {
+    const double* __restrict__ G, long R, int P, int n_m, int layout, int H, int Hk, int Hn,
+    const double* __restrict__ To, const double* __restrict__ Te, double c, double* __restrict__ GD) {
     constexpr int BM = 32 * WM, BN = 32 * WN, BK = KE_BK;
-    __shared__ double As[BM][BK + 1];
+    __shared__ double As[2][BM][BK + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const long row0 = (long)blockIdx.x * BM;
     const int col0 = blockIdx.y * BN;
     const int lr = lane & 15, lk = lane >> 4;
-    f64x4 acc[WM][WN];
+    // dL/dK at momentum m (1 <= m <= P) of row r, from either layout
+    auto g1 = [&](long r, int m) -> double {
+        if (layout == WK_HALF) return G[r * P + (m - 1)];
+        const double* gr = G + r * (long)n_m;
+        return m < P ? gr[P + m] - gr[P - m] : -gr[0];
+    };
+    f64x4 acc[2][WM][WN];
 #pragma unroll
-    for (int a = 0; a < WM; ++a)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int b = 0; b < WN; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    const double* Sw = S + (long)col0 + wc * WN * 16 + lr;
-    for (int k0 = 0; k0 < Pk; k0 += BK) {
-        double bfrag[BK / 4][WN];
+        for (int a = 0; a < WM; ++a)
 #pragma unroll
-        for (int ks = 0; ks < BK / 4; ++ks)
+            for (int b = 0; b < WN; ++b) acc[p][a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const long cw = (long)col0 + wc * WN * 16 + lr;
+    const double* Tw[2] = {To + cw, Te + cw};
+    for (int k0 = 0; k0 < Hk; k0 += BK) {
+        double bfrag[2][BK / 4][WN];
 #pragma unroll
-            for (int tn = 0; tn < WN; ++tn) bfrag[ks][tn] = Sw[(long)(k0 + 4 * ks + lk) * Pn + tn * 16];
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int ks = 0; ks < BK / 4; ++ks)
+#pragma unroll
+                for (int tn = 0; tn < WN; ++tn) bfrag[p][ks][tn] = Tw[p][(long)(k0 + 4 * ks + lk) * Hn + tn * 16];
         __syncthreads();
         for (int e = threadIdx.x; e < BM * BK; e += KE_THREADS) {
             const int rr = e / BK, kk = e - rr * BK;
             const long r = row0 + rr;
-            const int t = k0 + kk;
-            double g = 0.0;
-            if (r < R && t < P) {
-                if (layout == WK_HALF) {
-                    g = G[r * P + t];
-                } else {
-                    const double* gr = G + r * (long)n_m;
-                    g = t < P - 1 ? gr[P + 1 + t] - gr[P - 1 - t] : -gr[0];
-                }
+            const int m = k0 + kk + 1;
+            double gp = 0.0, gm = 0.0;
+            if (r < R && m <= H) {
+                const double a = g1(r, m), b = 2 * m < P ? g1(r, P - m) : 0.0;
+                gp = a + b;
+                gm = a - b;
             }
-            As[rr][kk] = g;
+            As[0][rr][kk] = gp;
+            As[1][rr][kk] = gm;
         }
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
-            double afrag[WM];
 #pragma unroll
-            for (int tm = 0; tm < WM; ++tm) afrag[tm] = As[(wr * WM + tm) * 16 + lr][4 * ks + lk];
+            for (int p = 0; p < 2; ++p) {
+                double afrag[WM];
 #pragma unroll
-            for (int tm = 0; tm < WM; ++tm)
+                for (int tm = 0; tm < WM; ++tm) afrag[tm] = As[p][(wr * WM + tm) * 16 + lr][4 * ks + lk];
 #pragma unroll
-                for (int tn = 0; tn < WN; ++tn)
-                    acc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(afrag[tm], bfrag[ks][tn],
-                                                                     acc[tm][tn], 0, 0, 0);
+                for (int tm = 0; tm < WM; ++tm)
+#pragma unroll
+                    for (int tn = 0; tn < WN; ++tn)
+                        acc[p][tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(afrag[tm], bfrag[p][ks][tn],
+                                                                            acc[p][tm][tn], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
     for (int tm = 0; tm < WM; ++tm)
 #pragma unroll
         for (int tn = 0; tn < WN; ++tn) {
-            const int jj = col0 + (wc * WN + tn) * 16 + lr;
+            const int k = col0 + (wc * WN + tn) * 16 + lr;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const long row = row0 + (wr * WM + tm) * 16 + lk + 4 * e;
-                if (row < R && jj < P) GD[row * P + jj] = c * acc[tm][tn][e];
+                if (row >= R) continue;
+                if (k < H) {
+                    GD[row * P + 2 * k] = c * acc[0][tm][tn][e];
+                    GD[row * P + 2 * k + 1] = c * acc[1][tm][tn][e];
+                }
+                if ((P & 1) && k == 0) GD[row * P + P - 1] = 0.0;
             }
         }
 }
 
 // Per row i of potential b: sums of GD over the offsets whose clamped index is an edge.
-__global__ void kernel_bwd_tails(const double* __restrict__ GD, long R, int nx, int P,
-                                 double* __restrict__ tail_hi, double* __restrict__ tail_lo) {
-    const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    const int i = (int)(r % nx);
-    const double* g = GD + r * P;
-    double hi = 0.0, lo = 0.0;
-    for (int j = 1; j <= P; ++j) {
-        if (i + j >= nx - 1) hi += g[j - 1];   // V(i + j) clamps to (or is) cell nx - 1
-        if (i - j <= 0) lo += g[j - 1];        // V(i - j) clamps to (or is) cell 0
-    }
-    tail_hi[r] = hi;
-    tail_lo[r] = lo;
+// Only rows within P of an edge have such offsets (i >= nx - 1 - P for the upper edge, i <= P
+// for the lower); one wave per such row reads it coalesced and adds with a fixed butterfly.
+// Rows are enumerated per potential: first 0..nlo-1 (nlo = min(P, nx - 1) + 1), then the rest
+// of [nx - 1 - P, nx - 1].
+__device__ __forceinline__ void edge_rows(int nx, int P, int* nlo, int* hi0, int* ne) {
+    *nlo = min(P, nx - 1) + 1;
+    *hi0 = max(*nlo, nx - 1 - P);
+    *ne = *nlo + (nx - *hi0);
 }
 
-__global__ void kernel_bwd_gather(const double* __restrict__ GD, int B, int nx, int P,
-                                  const double* __restrict__ tail_hi,
-                                  const double* __restrict__ tail_lo, double* __restrict__ dV) {
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)B * nx) return;
-    const long b = idx / nx;
-    const int l = (int)(idx - b * nx);
+__global__ __launch_bounds__(256) void kernel_bwd_tails(const double* __restrict__ GD, int B, int nx, int P,
+                                                        double* __restrict__ tail_hi,
+                                                        double* __restrict__ tail_lo) {
+    const int lane = threadIdx.x & 63;
+    const long wid = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int nlo, hi0, ne;
+    edge_rows(nx, P, &nlo, &hi0, &ne);
+    const long b = wid / ne;
+    if (b >= B) return;
+    const int k = (int)(wid - b * ne);
+    const int i = k < nlo ? k : hi0 + (k - nlo);
+    const double* g = GD + (b * nx + i) * (long)P;
+    double hi = 0.0, lo = 0.0;
+    for (int j = 1 + lane; j <= P; j += 64) {
+        const double v = g[j - 1];
+        if (i + j >= nx - 1) hi += v;  // V(i + j) clamps to (or is) cell nx - 1
+        if (i - j <= 0) lo += v;       // V(i - j) clamps to (or is) cell 0
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        hi += __shfl_xor(hi, o, 64);
+        lo += __shfl_xor(lo, o, 64);
+    }
+    if (lane == 0) {
+        tail_hi[b * nx + i] = hi;
+        tail_lo[b * nx + i] = lo;
+    }
+}
+
+// A workgroup takes 64 consecutive outputs l of one potential and walks the rows they need;
+// its four waves take every fourth row.  At row i a wave's lanes read consecutive columns of
+// GD (ascending for the terms GD[l - j][j - 1], descending for GD[l + j][j - 1]), so each load
+// is one contiguous segment.  The four partial sums of an output are added in wave order, then
+// the edge tails (fixed order).
+__global__ __launch_bounds__(256) void kernel_bwd_gather(const double* __restrict__ GD, int B, int nx, int P,
+                                                         const double* __restrict__ tail_hi,
+                                                         const double* __restrict__ tail_lo,
+                                                         double* __restrict__ dV) {
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long wpp = (nx + 63) / 64;  // output groups per potential
+    const long b = blockIdx.x / wpp;
+    const int l0 = (int)(blockIdx.x - b * wpp) * 64, l = l0 + lane;
     const double* g = GD + b * (long)nx * P;
     double acc = 0.0;
-    if (l < nx - 1)
-        for (int j = 1; j <= P && l - j >= 0; ++j) acc += g[(long)(l - j) * P + (j - 1)];
-    if (l > 0)
-        for (int j = 1; j <= P && l + j <= nx - 1; ++j) acc -= g[(long)(l + j) * P + (j - 1)];
-    if (l == nx - 1)
-        for (int i = 0; i < nx; ++i) acc += tail_hi[b * nx + i];
-    if (l == 0)
-        for (int i = 0; i < nx; ++i) acc -= tail_lo[b * nx + i];
-    dV[idx] += acc;
+    // rows i = l - j, j = 1..P (outputs l < nx - 1)
+    const int i1 = min(l0 + 62, nx - 1);
+#pragma unroll 4
+    for (int i = max(l0 - P, 0) + wv; i <= i1; i += 4) {
+        const int j = l - i;
+        if (l < nx - 1 && j >= 1 && j <= P) acc += g[(long)i * P + (j - 1)];
+    }
+    // rows i = l + j, j = 1..P (outputs 0 < l < nx)
+    const int i2 = min(l0 + 63 + P, nx - 1);
+#pragma unroll 4
+    for (int i = l0 + 1 + wv; i <= i2; i += 4) {
+        const int j = i - l;
+        if (l > 0 && l < nx && j >= 1 && j <= P) acc -= g[(long)i * P + (j - 1)];
+    }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && l < nx) {
+        double t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        // edge tails: only the rows within P of the edge have them (see kernel_bwd_tails)
+        if (l == nx - 1)
+            for (int i = max(0, nx - 1 - P); i < nx; ++i) t += tail_hi[b * nx + i];
+        if (l == 0)
+            for (int i = 0; i <= min(P, nx - 1); ++i) t -= tail_lo[b * nx + i];
+        dV[b * (long)nx + l] += t;
+    }
 }
 
 }  // namespace wk
@@ -761,22 +829,32 @@ extern "C" int wk_kernel_bwd(const wk_mesh* mesh, const double* G, int32_t B, in
     WK_REQUIRE(ws_bytes >= wk_kernel_bwd_workspace(mesh, B), "wk_kernel_bwd: workspace too small");
     constexpr int WM = 2, WN = 2, BM = 32 * WM, BN = 32 * WN;   // 2 x 2 waves
     hipStream_t s = as_stream(stream);
-    const int n_m = mesh->n_m, P = n_m / 2, nx = mesh->nx;
-    const int Pk = round_up(P, KE_BK), Pn = round_up(P, BN);
-    int err = WK_OK;
-    const double* S = static_cast<const double*>(sine_table(n_m, 0, Pk, Pn, s, &err));
-    if (!S) return err;
+    const int n_m = mesh->n_m, P = n_m / 2, H = P / 2, nx = mesh->nx;
     const long R = (long)B * nx;
     double* GD = static_cast<double*>(ws);
     double* th = GD + R * P;
     double* tl = th + R;
     const double c = -2.0 / (mesh->hbar * (double)n_m);
-    hipLaunchKernelGGL((kernel_bwd_gemm<WM, WN>), dim3((unsigned)((R + BM - 1) / BM), Pn / BN),
-                       dim3(KE_THREADS), 0, s, G, R, P, n_m, layout, Pk, Pn, S, c, GD);
-    hipLaunchKernelGGL(kernel_bwd_tails, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, GD, R,
-                       nx, P, th, tl);
-    hipLaunchKernelGGL(kernel_bwd_gather, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, GD, B,
-                       nx, P, th, tl, dV);
+    if (H == 0) {  // n_m = 2: every sine of eq.(4) is zero
+        hipLaunchKernelGGL(kernel_zero_f64, dim3((unsigned)((R * P + 255) / 256)), dim3(256), 0, s, GD, R * P);
+    } else {
+        const int Hk = round_up(H, KE_BK), Hn = round_up(H, BN);
+        int err = WK_OK;
+        const double* To = static_cast<const double*>(sine_table(n_m, SINE_ODD_T, Hk, Hn, s, &err));
+        if (!To) return err;
+        const double* Te = static_cast<const double*>(sine_table(n_m, SINE_EVEN_T, Hk, Hn, s, &err));
+        if (!Te) return err;
+        hipLaunchKernelGGL((kernel_bwd_gemm<WM, WN>), dim3((unsigned)((R + BM - 1) / BM), Hn / BN),
+                           dim3(KE_THREADS), 0, s, G, R, P, n_m, layout, H, Hk, Hn, To, Te, c, GD);
+    }
+    {
+        const int nlo = (P < nx - 1 ? P : nx - 1) + 1, hi0 = nlo > nx - 1 - P ? nlo : nx - 1 - P;
+        const long erows = (long)B * (nlo + (nx - hi0));  // one wave each
+        hipLaunchKernelGGL(kernel_bwd_tails, dim3((unsigned)((erows + 3) / 4)), dim3(256), 0, s, GD, B,
+                           nx, P, th, tl);
+    }
+    hipLaunchKernelGGL(kernel_bwd_gather, dim3((unsigned)((long)B * ((nx + 63) / 64))), dim3(256), 0, s,
+                       GD, B, nx, P, th, tl, dV);
     return check_launch("wk_kernel_bwd");
 }
 

@@ -430,6 +430,7 @@ struct SurrWS {
     float* wVpart;    // [nblk][N]
     float* GA;        // [R][H]   (only when dV is requested)
     double* u;        // [H]
+    double* du;       // [H]
     double* Bd;       // [H][Pn]
     float* Bf;        // [H][Pn]
     double* Pid;      // [Pn]
@@ -494,43 +495,281 @@ __global__ __launch_bounds__(SU_THREADS) void surr_bwd_block(
     }
 }
 
+// The same partials on FP32 MFMA (v_mfma_f32_16x16x4_f32), for shapes whose tables fit in
+// LDS.  Persistent workgroups over tiles of SBM rows; per tile, in LDS: Et = E Pi (row-major
+// for GA, transposed for GB), A^T from the convolution, GA = Et Bm^T (Bm resident for the
+// whole workgroup).  GB += A^T Et accumulates in registers across the workgroup's tiles (16 x
+// 16 tiles of GB dealt round-robin to the four waves), dwV in LDS; both are written to the
+// workgroup's partial slots at the end, for the same fixed-order reductions as above.
+// Operand layouts (16x16x4 f32): lane l holds A[l % 16][k], B[k][l % 16] with k = l / 16, and
+// C[4 (l / 16) + e][l % 16]; four consecutive steps take k = 16 s + 4 (l / 16) + q (q < 4), the
+// same for both operands, so each lane's operands are 16-byte LDS reads.
+constexpr int SBM = 32;       // rows per tile
+constexpr int SB_MAXT = 16;   // GB accumulator tiles per wave
+
+__global__ __launch_bounds__(SU_THREADS) void surr_bwd_mfma(
+    const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
+    int P, int N, int H, int Pn, int Hp, int Pp, const float* __restrict__ wV,
+    const float* __restrict__ E, SurrWS w, int want_GA) {
+    extern __shared__ float smem_b[];
+    __shared__ int rcell[SBM];
+    __shared__ long rbase[SBM];
+    const int LP = Pp + 4, LR = SBM + 4, LH = Hp + 4;
+    float* Bms = smem_b;                      // [Hp][LP]   Bm[g][t]
+    float* EtR = Bms + Hp * LP;               // [SBM][LP]  Et[r][t]
+    float* EtT = EtR + SBM * LP;              // [Pp][LR]   Et[r][t] at [t][r]
+    float* AsT = EtT + Pp * LR;               // [Hp][LR]   A[r][g] at [g][r]
+    float* GAs = AsT + Hp * LR;               // [SBM][LH]  GA[r][g]
+    float* dwv = GAs + SBM * LH;              // [N]
+    double* Vw = reinterpret_cast<double*>(dwv + ((N + 1) / 2) * 2);   // [SBM + 2P]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    // global -> LDS fills load eight values per thread before storing any (loads in flight)
+    for (int e0 = threadIdx.x; e0 < Hp * LP; e0 += 8 * SU_THREADS) {
+        float v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = e0 + q * SU_THREADS, g = e / LP, t = e - g * LP;
+            v[q] = (e < Hp * LP && g < H && t < P) ? w.Bf[(long)g * Pn + t] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (e0 + q * SU_THREADS < Hp * LP) Bms[e0 + q * SU_THREADS] = v[q];
+    }
+    for (int p = threadIdx.x; p < N; p += blockDim.x) dwv[p] = 0.f;
+    const int ngt = (Hp / 16) * (Pp / 16);    // GB tiles
+    f32x4 gb[SB_MAXT];
+#pragma unroll
+    for (int k = 0; k < SB_MAXT; ++k) gb[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const long ntiles = (R + SBM - 1) / SBM;
+    // the next tile's E values and potential window are loaded into registers while this
+    // tile's products run (one workgroup per CU: nothing else would hide those loads)
+    constexpr int EPF = SBM * 128 / SU_THREADS;  // E values per thread (Pp <= 128)
+    constexpr int WPF = 4;                       // window values per thread
+    const int nwin = SBM + 2 * P;
+    float epf[EPF];
+    double wpf[WPF];
+    auto is_run = [&](long row0) {
+        const long rend = min(R, row0 + SBM);
+        return cells == nullptr && n_cells == nx && row0 / nx == (rend - 1) / nx;
+    };
+    auto fetch = [&](long row0) {
+#pragma unroll
+        for (int q = 0; q < EPF; ++q) {
+            const int e = threadIdx.x + q * SU_THREADS, rr = e / Pp, t = e - rr * Pp;
+            epf[q] = (e < SBM * Pp && t < P && row0 + rr < R) ? E[(row0 + rr) * P + t] : 0.f;
+        }
+        if (nwin <= WPF * SU_THREADS && is_run(row0)) {
+            const long b = row0 / nx;
+            const int c0 = (int)(row0 - b * nx);
+            const double* Vb = V + b * (long)nx;
+#pragma unroll
+            for (int i = 0; i < WPF; ++i) {
+                const int k = threadIdx.x + i * SU_THREADS;
+                if (k < nwin) wpf[i] = Vb[min(max(c0 - P + k, 0), nx - 1)];
+            }
+        }
+    };
+    if (blockIdx.x < ntiles) fetch((long)blockIdx.x * SBM);
+    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long row0 = tile * SBM;
+        const bool run = is_run(row0);
+        __syncthreads();  // the previous tile's readers are done
+        for (int rr = threadIdx.x; rr < SBM; rr += blockDim.x) {
+            const long r = row0 + rr;
+            int cell = -1;
+            long base = 0;
+            if (r < R) {
+                const long b = r / n_cells;
+                const int ci = (int)(r - b * n_cells);
+                cell = cells ? cells[ci] : ci;
+                if (cell < 0 || cell >= nx) cell = -2;
+                base = b * (long)nx;
+            }
+            rcell[rr] = cell;
+            rbase[rr] = base;
+        }
+        if (run) {
+            if (nwin <= WPF * SU_THREADS) {
+#pragma unroll
+                for (int i = 0; i < WPF; ++i) {
+                    const int k = threadIdx.x + i * SU_THREADS;
+                    if (k < nwin) Vw[k] = wpf[i];
+                }
+            } else {
+                const long b = row0 / nx;
+                const int c0 = (int)(row0 - b * nx);
+                const double* Vb = V + b * (long)nx;
+                for (int k = threadIdx.x; k < nwin; k += blockDim.x) Vw[k] = Vb[min(max(c0 - P + k, 0), nx - 1)];
+            }
+        }
+        __syncthreads();
+        // Et (both layouts) and A^T; rows outside the mesh or past R contribute nothing
+#pragma unroll
+        for (int q = 0; q < EPF; ++q) {
+            const int e = threadIdx.x + q * SU_THREADS, rr = e / Pp, t = e - rr * Pp;
+            if (e < SBM * Pp) {
+                const float v = (t < P && rcell[rr] >= 0) ? epf[q] * w.Pif[t] : 0.f;
+                EtR[rr * LP + t] = v;
+                EtT[t * LR + rr] = v;
+            }
+        }
+        for (int e = threadIdx.x; e < SBM * Hp; e += blockDim.x) {
+            const int rr = e / Hp, g = e - rr * Hp;
+            const int cell = rcell[rr];
+            double a = 0.0;
+            if (cell >= 0 && g < H) {
+                if (run) {
+                    for (int p = 0; p < N; ++p) a += (double)wV[p] * Vw[rr + N * g + p];
+                } else {
+                    const double* Vb = V + rbase[rr];
+                    for (int p = 0; p < N; ++p) a += (double)wV[p] * Vb[min(max(cell - P + N * g + p, 0), nx - 1)];
+                }
+            }
+            AsT[g * LR + rr] = (float)a;
+        }
+        __syncthreads();
+        if (tile + gridDim.x < ntiles) fetch((tile + gridDim.x) * SBM);
+        // GA = Et Bm^T: (SBM x Pp) (Pp x Hp); output tiles (row block i, column block j)
+        const int nga = (SBM / 16) * (Hp / 16);
+        for (int q = wave; q < nga; q += 4) {
+            const int i = q % (SBM / 16), j = q / (SBM / 16);
+            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+            const float* ar = EtR + (16 * i + lr) * LP + 4 * lk;
+            const float* br = Bms + (16 * j + lr) * LP + 4 * lk;
+            for (int s = 0; s < Pp; s += 16) {
+                const float4 a = *reinterpret_cast<const float4*>(ar + s);
+                const float4 b = *reinterpret_cast<const float4*>(br + s);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
+            }
+            const int g = 16 * j + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int rr = 16 * i + 4 * lk + e;
+                GAs[rr * LH + g] = acc[e];
+                if (want_GA && g < H && row0 + rr < R) w.GA[(row0 + rr) * H + g] = acc[e];
+            }
+        }
+        // GB += A^T Et: (Hp x SBM) (SBM x Pp)
+#pragma unroll
+        for (int k = 0; k < SB_MAXT; ++k) {
+            const int q = wave + 4 * k;
+            if (q >= ngt) break;
+            const int gi = q % (Hp / 16), tj = q / (Hp / 16);
+            const float* ar = AsT + (16 * gi + lr) * LR + 4 * lk;
+            const float* br = EtT + (16 * tj + lr) * LR + 4 * lk;
+#pragma unroll
+            for (int s = 0; s < SBM; s += 16) {
+                const float4 a = *reinterpret_cast<const float4*>(ar + s);
+                const float4 b = *reinterpret_cast<const float4*>(br + s);
+                gb[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, gb[k], 0, 0, 0);
+                gb[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, gb[k], 0, 0, 0);
+                gb[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, gb[k], 0, 0, 0);
+                gb[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, gb[k], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // GA complete
+        // dwV += sum over rows and groups of GA[r][g] V(clamp(i_r + o(g,p))), one wave per tap
+        for (int p = wave; p < N; p += 4) {
+            float acc = 0.f;
+            for (int e = lane; e < SBM * H; e += 64) {
+                const int rr = e / H, g = e - rr * H;
+                const int cell = rcell[rr];
+                if (cell < 0) continue;
+                const double v = run ? Vw[rr + N * g + p] : V[rbase[rr] + min(max(cell - P + N * g + p, 0), nx - 1)];
+                acc = fmaf(GAs[rr * LH + g], (float)v, acc);
+            }
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            if (lane == 0) dwv[p] += acc;
+        }
+    }
+    __syncthreads();
+    float* gbp = w.GBpart + (long)blockIdx.x * H * P;
+#pragma unroll
+    for (int k = 0; k < SB_MAXT; ++k) {
+        const int q = wave + 4 * k;
+        if (q >= ngt) break;
+        const int gi = q % (Hp / 16), tj = q / (Hp / 16);
+        const int t = 16 * tj + lr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int g = 16 * gi + 4 * lk + e;
+            if (g < H && t < P) gbp[(long)g * P + t] = gb[k][e];
+        }
+    }
+    for (int p = threadIdx.x; p < N; p += blockDim.x) w.wVpart[(long)blockIdx.x * N + p] = dwv[p];
+}
+
+// LDS bytes of surr_bwd_mfma, or 0 when the shape does not fit (then surr_bwd_block runs).
+static size_t surr_bwd_mfma_bytes(int H, int P, int N) {
+    const size_t Hp = ((size_t)H + 15) / 16 * 16, Pp = ((size_t)P + 15) / 16 * 16;
+    if ((Hp / 16) * (Pp / 16) > 4 * (size_t)SB_MAXT || Pp > 128) return 0;
+    const size_t LP = Pp + 4, LR = SBM + 4, LH = Hp + 4;
+    const size_t f = Hp * LP + SBM * LP + Pp * LR + Hp * LR + SBM * LH + ((size_t)N + 1) / 2 * 2;
+    const size_t b = 4 * f + 8 * (SBM + 2 * (size_t)P);
+    return b <= 150 * 1024 ? b : 0;
+}
+
 __global__ void zero_grads(float* a, int na, float* b, int nb, float* c, int nc) {
     for (int i = threadIdx.x; i < na; i += blockDim.x) a[i] = 0.f;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) b[i] = 0.f;
     for (int i = threadIdx.x; i < nc; i += blockDim.x) c[i] = 0.f;
 }
 
-// Fixed-order sum of the block partials; one thread per (g, t) of GB, then dW, du, dwT, dwV.
-__global__ void surr_bwd_reduce_gb(int nblk, int H, int P, SurrWS w) {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long)H * P) return;
+// Fixed-order sum of the block partials: 64 entries of GB per workgroup; wave j sums the
+// partials k = j, j + 4, ... in ascending k, and the four sums are added in wave order.
+__global__ __launch_bounds__(256) void surr_bwd_reduce_gb(int nblk, int H, int P, SurrWS w) {
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long e = (long)blockIdx.x * 64 + lane;
+    const long n = (long)H * P;
     float acc = 0.f;
-    for (int k = 0; k < nblk; ++k) acc += w.GBpart[(long)k * H * P + e];
-    w.GBpart[e] = acc;  // block 0's slot now holds the total
+    if (e < n)
+        for (int k = wv; k < nblk; k += 4) acc += w.GBpart[(long)k * n + e];
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && e < n) w.GBpart[e] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
-__global__ void surr_bwd_params(int n_m, int N, int H, int P, int Pn, int nblk,
-                                const float* __restrict__ W, SurrWS w, float* __restrict__ dwV,
-                                float* __restrict__ dwT, float* __restrict__ dW) {
-    __shared__ double du_s[SU_MAXH];
-    const int tid = threadIdx.x;
-    for (int g = tid; g < H; g += blockDim.x) {
-        const double u = w.u[g];
-        double dw = 0.0, du = 0.0;
-        for (int t = 0; t < P; ++t) {
-            const double gb = (double)w.GBpart[(long)g * P + t];
-            const double m = (double)(t + 1);
-            dw += gb * sin(u * m);
-            du += gb * (double)W[g] * m * cos(u * m);
-        }
-        dW[g] = (float)dw;
-        du_s[g] = du;
+// dW[g] = sum_t GB[g][t] sin(u_g m) and du[g] = sum_t GB[g][t] W[g] m cos(u_g m), m = t + 1:
+// one workgroup per g, FP64 terms summed in a fixed tree order.
+__global__ __launch_bounds__(256) void surr_bwd_params_g(int P, const float* __restrict__ W, SurrWS w,
+                                                         float* __restrict__ dW, double* __restrict__ du) {
+    __shared__ double red[2][4];
+    const int g = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double u = w.u[g];
+    double a = 0.0, b = 0.0;
+    for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        const double gbv = (double)w.GBpart[(long)g * P + t];
+        const double m = (double)(t + 1);
+        a += gbv * sin(u * m);
+        b += gbv * (double)W[g] * m * cos(u * m);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if (lane == 0) {
+        red[0][wv] = a;
+        red[1][wv] = b;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        dW[g] = (float)(((red[0][0] + red[0][1]) + red[0][2]) + red[0][3]);
+        du[g] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
+}
+
+// dwT[p] = sum_g du[g] (2 pi / n_m) o(g,p) and dwV[p] = sum of the workgroups' partials.
+__global__ void surr_bwd_params(int n_m, int N, int H, int nblk, const double* __restrict__ du,
+                                SurrWS w, float* __restrict__ dwV, float* __restrict__ dwT) {
     const int Pm = n_m / 2;
-    for (int p = tid; p < N; p += blockDim.x) {
+    for (int p = threadIdx.x; p < N; p += blockDim.x) {
         double acc = 0.0;
-        for (int g = 0; g < H; ++g) acc += du_s[g] * (two_pi_over(n_m) * (double)(-Pm + N * g + p));
+        for (int g = 0; g < H; ++g) acc += du[g] * (two_pi_over(n_m) * (double)(-Pm + N * g + p));
         dwT[p] = (float)acc;
         double sv = 0.0;
         for (int k = 0; k < nblk; ++k) sv += (double)w.wVpart[(long)k * N + p];
@@ -587,7 +826,7 @@ static size_t surr_ws_bytes(int H, int P, int N, long R, bool with_GA) {
     b += sizeof(float) * (size_t)nblk * H * P;
     b += sizeof(float) * (size_t)nblk * N;
     b += with_GA ? sizeof(float) * (size_t)R * H : 0;
-    b += sizeof(double) * H + sizeof(double) * (size_t)H * Pn + sizeof(float) * (size_t)H * Pn;
+    b += 2 * sizeof(double) * H + sizeof(double) * (size_t)H * Pn + sizeof(float) * (size_t)H * Pn;
     b += sizeof(double) * Pn + sizeof(float) * Pn;
     return b + 8 * 256;
 }
@@ -606,6 +845,7 @@ static SurrWS surr_carve(void* ws, int H, int P, int N, long R, bool with_GA) {
     w.wVpart = reinterpret_cast<float*>(take(sizeof(float) * (size_t)nblk * N));
     w.GA = with_GA ? reinterpret_cast<float*>(take(sizeof(float) * (size_t)R * H)) : nullptr;
     w.u = reinterpret_cast<double*>(take(sizeof(double) * H));
+    w.du = reinterpret_cast<double*>(take(sizeof(double) * H));
     w.Bd = reinterpret_cast<double*>(take(sizeof(double) * (size_t)H * Pn));
     w.Bf = reinterpret_cast<float*>(take(sizeof(float) * (size_t)H * Pn));
     w.Pid = reinterpret_cast<double*>(take(sizeof(double) * Pn));
@@ -760,15 +1000,31 @@ extern "C" int wk_surrogate_bwd(const wk_mesh* mesh, int32_t N, const float* wV,
     const long np = (long)H * Pn;
     hipLaunchKernelGGL(surr_prep, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, mesh->n_m, N,
                        H, Pn, wT, W, w.Bd, w.Bf, w.Pid, w.Pif, w.u);
-    const long nblk = surr_nblk(R);
-    if (nblk > 0) {
+    long nblk = surr_nblk(R);
+    const size_t lds = surr_bwd_mfma_bytes(H, P, N);
+    if (nblk > 0 && lds) {
+        // persistent workgroups (at most the partial slots the workspace holds)
+        const long per_cu = lds <= 76 * 1024 ? 2 : 1;
+        const long tiles = (R + SBM - 1) / SBM;
+        nblk = min(nblk, min(tiles, 256 * per_cu));
+        if (lds > 64 * 1024 &&
+            hipFuncSetAttribute((const void*)surr_bwd_mfma, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds) != hipSuccess)
+            return fail(WK_EHIP, "wk_surrogate_bwd: cannot reserve LDS");
+        const int Hp = (H + 15) / 16 * 16, Pp = (P + 15) / 16 * 16;
+        hipLaunchKernelGGL(surr_bwd_mfma, dim3((unsigned)nblk), dim3(SU_THREADS), lds, s, V, mesh->nx, R,
+                           n_cells, cells, P, N, H, Pn, Hp, Pp, wV, E, w, dV ? 1 : 0);
+    } else if (nblk > 0) {
         const size_t sh = sizeof(float) * SD_BM * (2 * (H + 1) + (P + 1));
         hipLaunchKernelGGL(surr_bwd_block, dim3((unsigned)nblk), dim3(SU_THREADS), sh, s, V,
                            mesh->nx, R, n_cells, cells, P, N, H, Pn, wV, E, w, dV ? 1 : 0);
-        hipLaunchKernelGGL(surr_bwd_reduce_gb, dim3((unsigned)(((long)H * P + 255) / 256)), dim3(256),
+    }
+    if (nblk > 0) {
+        hipLaunchKernelGGL(surr_bwd_reduce_gb, dim3((unsigned)(((long)H * P + 63) / 64)), dim3(256),
                            0, s, (int)nblk, H, P, w);
-        hipLaunchKernelGGL(surr_bwd_params, dim3(1), dim3(256), 0, s, mesh->n_m, N, H, P, Pn,
-                           (int)nblk, W, w, dwV, dwT, dW);
+        hipLaunchKernelGGL(surr_bwd_params_g, dim3((unsigned)H), dim3(256), 0, s, P, W, w, dW, w.du);
+        hipLaunchKernelGGL(surr_bwd_params, dim3(1), dim3(64), 0, s, mesh->n_m, N, H, (int)nblk, w.du,
+                           w, dwV, dwT);
     } else {
         hipLaunchKernelGGL(zero_grads, dim3(1), dim3(256), 0, s, dwV, N, dwT, N, dW, H);
     }
@@ -785,10 +1041,26 @@ __global__ void mse_partial(const float* __restrict__ Kh, const double* __restri
     __shared__ double red[4];
     const double inv_n = 1.0 / (double)n;
     double acc = 0.0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double d = ((double)Kh[i] - K[i]) * inv_scale;
-        acc += d * d;
-        E[i] = (float)(2.0 * d * inv_scale * inv_n);
+    // four elements per thread and step, their loads issued together
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long i0 = (long)blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += 4 * stride) {
+        float kh[4];
+        double k[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const long i = i0 + q * stride;
+            kh[q] = i < n ? Kh[i] : 0.f;
+            k[q] = i < n ? K[i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const long i = i0 + q * stride;
+            if (i < n) {
+                const double d = ((double)kh[q] - k[q]) * inv_scale;
+                acc += d * d;
+                E[i] = (float)(2.0 * d * inv_scale * inv_n);
+            }
+        }
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -796,11 +1068,13 @@ __global__ void mse_partial(const float* __restrict__ Kh, const double* __restri
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// One wave: lane l sums the partials l, l + 64, ..., then a fixed butterfly (deterministic).
 __global__ void mse_final(const double* __restrict__ part, int nb, long n, double* loss) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int lane = threadIdx.x;
     double s = 0.0;
-    for (int k = 0; k < nb; ++k) s += part[k];
-    loss[0] = s / (double)n;
+    for (int k = lane; k < nb; k += 64) s += part[k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) loss[0] = s / (double)(n > 0 ? n : 1);
 }
 
 __global__ void sgd_kernel(float* w, const float* g, int n, float lr) {
@@ -816,13 +1090,13 @@ extern "C" int wk_mse_grad(const float* Kh, const double* K, int64_t count, doub
     WK_REQUIRE(count == 0 || (Kh && K && E), "wk_mse_grad: NULL array");
     hipStream_t s = as_stream(stream);
     if (count == 0) {
-        hipLaunchKernelGGL(mse_final, dim3(1), dim3(1), 0, s, static_cast<double*>(ws), 0, 1, loss);
+        hipLaunchKernelGGL(mse_final, dim3(1), dim3(64), 0, s, static_cast<double*>(ws), 0, 1, loss);
         return check_launch("wk_mse_grad");
     }
     const int nb = 1024;
     hipLaunchKernelGGL(mse_partial, dim3(nb), dim3(256), 0, s, Kh, K, (long)count, inv_scale, E,
                        static_cast<double*>(ws));
-    hipLaunchKernelGGL(mse_final, dim3(1), dim3(1), 0, s, static_cast<double*>(ws), nb, (long)count, loss);
+    hipLaunchKernelGGL(mse_final, dim3(1), dim3(64), 0, s, static_cast<double*>(ws), nb, (long)count, loss);
     return check_launch("wk_mse_grad");
 }
 

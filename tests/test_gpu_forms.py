@@ -90,7 +90,7 @@ def test_lowp_full_size_sampled(orc):
 
 
 # ----------------------------------------------------------------------------- adjoint
-@pytest.mark.parametrize("nx,n_m,B", [(90, 30, 2), (257, 64, 3), (40, 80, 1)])
+@pytest.mark.parametrize("nx,n_m,B", [(90, 30, 2), (257, 64, 3), (40, 80, 1), (300, 256, 2), (40, 2, 1), (70, 6, 2)])
 def test_kernel_adjoint_matches_oracle(orc, nx, n_m, B):
     P = n_m // 2
     rng = np.random.default_rng(nx)
@@ -187,7 +187,36 @@ def test_surrogate_fwd_cells(orc):
 @pytest.mark.parametrize("N", [1, 2, 4])
 def test_surrogate_bwd_vs_oracle(orc, N):
     """FP32 hand-written gradients against the FP64 oracle gradients."""
-    nx, n_m, B = 130, 32, 3
+    _bwd_case(orc, N, 130, 32, 3)
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 8])
+def test_surrogate_bwd_wide(orc, N):
+    """The learned-kernel shape (256 momenta, H = 256 / 128 / 64 / 32): tiles inside one
+    potential and across two, a ragged last tile; H = 256 takes the path without LDS tables."""
+    print(f"surrogate bwd n_m=256 N={N}", flush=True)
+    _bwd_case(orc, N, 300, 256, 2)
+
+
+def test_surrogate_bwd_cells(orc):
+    """Gradients over a cell list (arbitrary order, duplicates, both mesh edges)."""
+    nx, n_m, N, B = 90, 64, 2, 2
+    rng = np.random.default_rng(5)
+    V = inputs.random_potentials(B, nx, 0.5, seed=6)
+    w = _weights(n_m, N, 7)
+    w32 = [np.asarray(x, np.float32).astype(np.float64) for x in w]
+    cells = np.array([0, 89, 45, 45, 3, 88] * 7 + [17], np.int32)
+    E = rng.normal(size=(B, len(cells), n_m // 2)).astype(np.float32)
+    dwV, dwT, dW, _ = orc.surrogate_bwd(V, n_m, N, *w32, E.astype(np.float64), cells=cells, want_dV=False)
+    g = learn.surrogate_bwd(torch.from_numpy(V).to(dev()), n_m, N, *_f32(w),
+                            torch.from_numpy(E.reshape(B * len(cells), -1)).to(dev()),
+                            cells=torch.from_numpy(cells).to(dev()))
+    for got, ref in zip(g[:3], (dwV, dwT, dW)):
+        got = to_np(got).astype(np.float64).reshape(ref.shape)
+        assert np.abs(got - ref).max() <= 1e-4 * np.abs(ref).max(), (got, ref)
+
+
+def _bwd_case(orc, N, nx, n_m, B):
     rng = np.random.default_rng(40 + N)
     V = inputs.random_potentials(B, nx, 0.5, seed=N + 30)
     w = _weights(n_m, N, N)
