@@ -967,6 +967,27 @@ __device__ void place_chunk(const Geo& g, const BinCount& bc, int mode, uint32_t
     const int ex = block_excl_scan_256(cnt, &tc, lds5);
     bo_ex[threadIdx.x] = ex;
     bo_in[threadIdx.x] = ex + cnt;
+    // this bin's cell, momenta and sign, once per bin (32-bit index arithmetic: n_bins < 2^31)
+    int* bin_x = bo_in + BC;      // [BC] cell x
+    int* bin_kx = bin_x + BC;     // [BC] momentum index x
+    int* bin_y = bin_kx + BC;     // [BC] cell y (2-D)
+    int* bin_ky = bin_y + BC;     // [BC] momentum index y (2-D)
+    int* bin_s = bin_ky + BC;     // [BC] sign
+    if (cnt > 0) {
+        const uint32_t b32 = (uint32_t)b, nk = (uint32_t)g.n_k;
+        if (DIM == 1) {
+            const uint32_t cx = b32 / nk;
+            bin_x[threadIdx.x] = (int)cx;
+            bin_kx[threadIdx.x] = (int)(b32 - cx * nk);
+        } else {
+            const uint32_t t = b32 / nk, cc = t / nk, cy = cc / (uint32_t)g.nx;
+            bin_kx[threadIdx.x] = (int)(b32 - t * nk);
+            bin_ky[threadIdx.x] = (int)(t - cc * nk);
+            bin_x[threadIdx.x] = (int)(cc - cy * (uint32_t)g.nx);
+            bin_y[threadIdx.x] = (int)cy;
+        }
+        bin_s[threadIdx.x] = mode == 1 ? (bc.hist[b] > bc.hist[g.n_bins + b] ? 1 : -1) : 1;
+    }
     __syncthreads();
     const int lo_c = (int)(max(s_lo, ch_start) - ch_start);            // slots of this chunk
     const int hi_c = (int)(min(s_hi, ch_start + cnt_ch) - ch_start);   // to fill: [lo_c, hi_c)
@@ -976,22 +997,18 @@ __device__ void place_chunk(const Geo& g, const BinCount& bc, int mode, uint32_t
         const long bb = ch * BC + j;
         const long o = ch_start + rel;
         if (o >= capacity) break;  // never taken after the capacity check
-        const int8_t sign = mode == 1 ? (bc.hist[bb] > bc.hist[g.n_bins + bb] ? 1 : -1) : 1;
+        const int8_t sign = (int8_t)bin_s[j];
         const u32x4 u = philox((uint32_t)bb, c1, (uint32_t)(r / Q), tag, g.seed);
         const int e = r % Q;
         if (DIM == 1) {
-            const int cx = (int)(bb / g.n_k), kx = (int)(bb % g.n_k);
             const uint32_t ue = e == 0 ? u.v[0] : (e == 1 ? u.v[1] : (e == 2 ? u.v[2] : u.v[3]));
-            xo[o] = cell_plus_frac<T>(cx, ue, g.fb);
-            Mo[o] = (MT)(g.M_min + kx);
+            xo[o] = cell_plus_frac<T>(bin_x[j], ue, g.fb);
+            Mo[o] = (MT)(g.M_min + bin_kx[j]);
         } else {
-            const int kx = (int)(bb % g.n_k), ky = (int)((bb / g.n_k) % g.n_k);
-            const long cc = bb / ((long)g.n_k * g.n_k);
-            const int cx = (int)(cc % g.nx), cy = (int)(cc / g.nx);
-            xo[o] = cell_plus_frac<T>(cx, e ? u.v[2] : u.v[0], g.fb);
-            yo[o] = cell_plus_frac<T>(cy, e ? u.v[3] : u.v[1], g.fb);
-            Mo[o] = (MT)(g.M_min + kx);
-            Myo[o] = (MT)(g.M_min + ky);
+            xo[o] = cell_plus_frac<T>(bin_x[j], e ? u.v[2] : u.v[0], g.fb);
+            yo[o] = cell_plus_frac<T>(bin_y[j], e ? u.v[3] : u.v[1], g.fb);
+            Mo[o] = (MT)(g.M_min + bin_kx[j]);
+            Myo[o] = (MT)(g.M_min + bin_ky[j]);
         }
         so[o] = sign;
     }
@@ -1104,7 +1121,7 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
                                                   WS w) {
     constexpr int STAGE = WT * (DIM * (int)sizeof(T) + DIM * (int)sizeof(int) + 1);  // per wave
     constexpr int KEEP_LDS = WPB * STAGE + 2 * KW * (int)sizeof(int);
-    constexpr int PLACE_LDS = 2 * PT * (int)sizeof(int) + 2 * BC * (int)sizeof(int);
+    constexpr int PLACE_LDS = 2 * PT * (int)sizeof(int) + 7 * BC * (int)sizeof(int);
     __shared__ int lds5[5];
     __shared__ long wmin[PT / 64];
     // keepers: one stage per wave + histogram window; placers: chunk and bin prefix tables

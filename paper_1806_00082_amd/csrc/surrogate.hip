@@ -76,19 +76,21 @@ __device__ __forceinline__ void conv_rows(const double* __restrict__ V, int nx, 
         rbase[rr] = base;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < BM * H; e += blockDim.x) {
-        const int rr = e / H, g = e - rr * H;
+    const int lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
+    for (int rr = threadIdx.x >> 6; rr < BM; rr += nwv) {  // rows to waves, groups to lanes
         const int cell = rcell[rr];
-        double a = cell == -2 ? __builtin_nan("") : 0.0;
-        if (cell >= 0) {
-            const double* Vb = V + rbase[rr];
-            a = 0.0;
-            for (int p = 0; p < N; ++p) {
-                const int l = min(max(cell - P + N * g + p, 0), nx - 1);
-                a += (double)wV[p] * Vb[l];
+        const double* Vb = V + rbase[rr];
+        for (int g = lane; g < H; g += 64) {
+            double a = cell == -2 ? __builtin_nan("") : 0.0;
+            if (cell >= 0) {
+                a = 0.0;
+                for (int p = 0; p < N; ++p) {
+                    const int l = min(max(cell - P + N * g + p, 0), nx - 1);
+                    a += (double)wV[p] * Vb[l];
+                }
             }
+            A[rr * lda + g] = (T)a;
         }
-        A[rr * lda + g] = (T)a;
     }
     __syncthreads();
 }
@@ -171,21 +173,22 @@ __global__ __launch_bounds__(SU_THREADS) void surr_fwd_mfma(
                 Vw[k] = Vb[min(max(c0 - P + k, 0), nx - 1)];
             __syncthreads();
             const int nrow = (int)(rend - row0);
-            for (int e = threadIdx.x; e < SF_BM * H; e += blockDim.x) {
-                const int rr = e / H, g = e - rr * H;
-                double a = 0.0;
-                if (rr < nrow)
-                    for (int p = 0; p < N; ++p) a += (double)wV[p] * Vw[rr + N * g + p];
-                A[rr * lda + g] = BF16 ? (AT)bf16_bits_f((float)a) : (AT)(float)a;
-            }
+            // rows to waves, groups to lanes (no index divisions)
+            for (int rr = wave; rr < SF_BM; rr += 4)
+                for (int g = lane; g < H; g += 64) {
+                    double a = 0.0;
+                    if (rr < nrow)
+                        for (int p = 0; p < N; ++p) a += (double)wV[p] * Vw[rr + N * g + p];
+                    A[rr * lda + g] = BF16 ? (AT)bf16_bits_f((float)a) : (AT)(float)a;
+                }
         } else {
             conv_rows<SF_BM, float>(V, nx, row0, R, n_cells, cells, P, N, H, wV, Ag, Hk + 1, rcell,
                                     rbase);
-            for (int e = threadIdx.x; e < SF_BM * H; e += blockDim.x) {
-                const int rr = e / H, g = e - rr * H;
-                const float a = Ag[rr * (Hk + 1) + g];
-                A[rr * lda + g] = BF16 ? (AT)bf16_bits_f(a) : (AT)a;
-            }
+            for (int rr = wave; rr < SF_BM; rr += 4)
+                for (int g = lane; g < H; g += 64) {
+                    const float a = Ag[rr * (Hk + 1) + g];
+                    A[rr * lda + g] = BF16 ? (AT)bf16_bits_f(a) : (AT)a;
+                }
         }
         __syncthreads();
         for (int ct = wave; ct * 16 < Pn; ct += 4) {
@@ -308,13 +311,14 @@ __global__ __launch_bounds__(SU_THREADS) void surr_fwd_lds(
                 for (int k = threadIdx.x; k < nwin; k += blockDim.x) Vw[k] = Vb[min(max(c0 - P + k, 0), nx - 1)];
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < SF_BM * H; e += blockDim.x) {
-                const int rr = e / H, g = e - rr * H;
-                double a = 0.0;
-                if (rr < nrow)
-                    for (int p = 0; p < N; ++p) a += (double)wV[p] * Vw[rr + N * g + p];
-                As[rr * LD + g] = BF16 ? (AT)bf16_bits_f((float)a) : (AT)(float)a;
-            }
+            // rows to waves, groups to lanes (no index divisions)
+            for (int rr = wave; rr < SF_BM; rr += 4)
+                for (int g = lane; g < H; g += 64) {
+                    double a = 0.0;
+                    if (rr < nrow)
+                        for (int p = 0; p < N; ++p) a += (double)wV[p] * Vw[rr + N * g + p];
+                    As[rr * LD + g] = BF16 ? (AT)bf16_bits_f((float)a) : (AT)(float)a;
+                }
         } else {
             for (int rr = threadIdx.x; rr < SF_BM; rr += blockDim.x) {
                 const long r = row0 + rr;
@@ -331,16 +335,16 @@ __global__ __launch_bounds__(SU_THREADS) void surr_fwd_lds(
                 rbase[rr] = base;
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < SF_BM * H; e += blockDim.x) {
-                const int rr = e / H, g = e - rr * H;
+            for (int rr = wave; rr < SF_BM; rr += 4) {
                 const int cell = rcell[rr];
-                double a = cell == -2 ? __builtin_nan("") : 0.0;
-                if (cell >= 0) {
-                    const double* Vb = V + rbase[rr];
-                    for (int p = 0; p < N; ++p)
-                        a += (double)wV[p] * Vb[min(max(cell - P + N * g + p, 0), nx - 1)];
+                const double* Vb = V + rbase[rr];
+                for (int g = lane; g < H; g += 64) {
+                    double a = cell == -2 ? __builtin_nan("") : 0.0;
+                    if (cell >= 0)
+                        for (int p = 0; p < N; ++p)
+                            a += (double)wV[p] * Vb[min(max(cell - P + N * g + p, 0), nx - 1)];
+                    As[rr * LD + g] = BF16 ? (AT)bf16_bits_f((float)a) : (AT)(float)a;
                 }
-                As[rr * LD + g] = BF16 ? (AT)bf16_bits_f((float)a) : (AT)(float)a;
             }
         }
         __syncthreads();
@@ -497,8 +501,8 @@ __global__ __launch_bounds__(SU_THREADS) void surr_bwd_block(
 
 // The same partials on FP32 MFMA (v_mfma_f32_16x16x4_f32), for shapes whose tables fit in
 // LDS.  Persistent workgroups over tiles of SBM rows; per tile, in LDS: Et = E Pi (row-major
-// for GA, transposed for GB), A^T from the convolution, GA = Et Bm^T (Bm resident for the
-// whole workgroup).  GB += A^T Et accumulates in registers across the workgroup's tiles (16 x
+// for GA, transposed for GB), A^T from the convolution, GA = Et Bm^T (Bm fragments from the
+// L2-resident table).  GB += A^T Et accumulates in registers across the workgroup's tiles (16 x
 // 16 tiles of GB dealt round-robin to the four waves), dwV in LDS; both are written to the
 // workgroup's partial slots at the end, for the same fixed-order reductions as above.
 // Operand layouts (16x16x4 f32): lane l holds A[l % 16][k], B[k][l % 16] with k = l / 16, and
@@ -506,8 +510,10 @@ __global__ __launch_bounds__(SU_THREADS) void surr_bwd_block(
 // same for both operands, so each lane's operands are 16-byte LDS reads.
 constexpr int SBM = 32;       // rows per tile
 constexpr int SB_MAXT = 16;   // GB accumulator tiles per wave
+constexpr int SB_JMAX = 2;    // GA column blocks per wave (H <= 128)
+constexpr int SB_SMAX = 8;    // 16-wide contraction groups of GA (P <= 128)
 
-__global__ __launch_bounds__(SU_THREADS) void surr_bwd_mfma(
+__global__ __launch_bounds__(SU_THREADS, 2) void surr_bwd_mfma(
     const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
     int P, int N, int H, int Pn, int Hp, int Pp, const float* __restrict__ wV,
     const float* __restrict__ E, SurrWS w, int want_GA) {
@@ -515,8 +521,7 @@ __global__ __launch_bounds__(SU_THREADS) void surr_bwd_mfma(
     __shared__ int rcell[SBM];
     __shared__ long rbase[SBM];
     const int LP = Pp + 4, LR = SBM + 4, LH = Hp + 4;
-    float* Bms = smem_b;                      // [Hp][LP]   Bm[g][t]
-    float* EtR = Bms + Hp * LP;               // [SBM][LP]  Et[r][t]
+    float* EtR = smem_b;                      // [SBM][LP]  Et[r][t]
     float* EtT = EtR + SBM * LP;              // [Pp][LR]   Et[r][t] at [t][r]
     float* AsT = EtT + Pp * LR;               // [Hp][LR]   A[r][g] at [g][r]
     float* GAs = AsT + Hp * LR;               // [SBM][LH]  GA[r][g]
@@ -524,53 +529,28 @@ __global__ __launch_bounds__(SU_THREADS) void surr_bwd_mfma(
     double* Vw = reinterpret_cast<double*>(dwv + ((N + 1) / 2) * 2);   // [SBM + 2P]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    // global -> LDS fills load eight values per thread before storing any (loads in flight)
-    for (int e0 = threadIdx.x; e0 < Hp * LP; e0 += 8 * SU_THREADS) {
-        float v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int e = e0 + q * SU_THREADS, g = e / LP, t = e - g * LP;
-            v[q] = (e < Hp * LP && g < H && t < P) ? w.Bf[(long)g * Pn + t] : 0.f;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (e0 + q * SU_THREADS < Hp * LP) Bms[e0 + q * SU_THREADS] = v[q];
-    }
     for (int p = threadIdx.x; p < N; p += blockDim.x) dwv[p] = 0.f;
+    // Bm fragments of this wave's GA column blocks (g = 16 j + l % 16, t = 16 sg + 4 (l / 16) + q),
+    // loaded once: zero past H and P
+    float4 bfr[SB_JMAX][SB_SMAX];
+#pragma unroll
+    for (int jb = 0; jb < SB_JMAX; ++jb)
+#pragma unroll
+        for (int sg = 0; sg < SB_SMAX; ++sg) {
+            const int g = 16 * (wave + 4 * jb) + lr;
+            bfr[jb][sg] = (g < H && sg < Pp / 16)
+                              ? *reinterpret_cast<const float4*>(w.Bf + (long)g * Pn + 16 * sg + 4 * lk)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
     const int ngt = (Hp / 16) * (Pp / 16);    // GB tiles
     f32x4 gb[SB_MAXT];
 #pragma unroll
     for (int k = 0; k < SB_MAXT; ++k) gb[k] = f32x4{0.f, 0.f, 0.f, 0.f};
     const long ntiles = (R + SBM - 1) / SBM;
-    // the next tile's E values and potential window are loaded into registers while this
-    // tile's products run (one workgroup per CU: nothing else would hide those loads)
-    constexpr int EPF = SBM * 128 / SU_THREADS;  // E values per thread (Pp <= 128)
-    constexpr int WPF = 4;                       // window values per thread
-    const int nwin = SBM + 2 * P;
-    float epf[EPF];
-    double wpf[WPF];
     auto is_run = [&](long row0) {
         const long rend = min(R, row0 + SBM);
         return cells == nullptr && n_cells == nx && row0 / nx == (rend - 1) / nx;
     };
-    auto fetch = [&](long row0) {
-#pragma unroll
-        for (int q = 0; q < EPF; ++q) {
-            const int e = threadIdx.x + q * SU_THREADS, rr = e / Pp, t = e - rr * Pp;
-            epf[q] = (e < SBM * Pp && t < P && row0 + rr < R) ? E[(row0 + rr) * P + t] : 0.f;
-        }
-        if (nwin <= WPF * SU_THREADS && is_run(row0)) {
-            const long b = row0 / nx;
-            const int c0 = (int)(row0 - b * nx);
-            const double* Vb = V + b * (long)nx;
-#pragma unroll
-            for (int i = 0; i < WPF; ++i) {
-                const int k = threadIdx.x + i * SU_THREADS;
-                if (k < nwin) wpf[i] = Vb[min(max(c0 - P + k, 0), nx - 1)];
-            }
-        }
-    };
-    if (blockIdx.x < ntiles) fetch((long)blockIdx.x * SBM);
     for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const long row0 = tile * SBM;
         const bool run = is_run(row0);
@@ -590,67 +570,73 @@ __global__ __launch_bounds__(SU_THREADS) void surr_bwd_mfma(
             rbase[rr] = base;
         }
         if (run) {
-            if (nwin <= WPF * SU_THREADS) {
-#pragma unroll
-                for (int i = 0; i < WPF; ++i) {
-                    const int k = threadIdx.x + i * SU_THREADS;
-                    if (k < nwin) Vw[k] = wpf[i];
-                }
-            } else {
-                const long b = row0 / nx;
-                const int c0 = (int)(row0 - b * nx);
-                const double* Vb = V + b * (long)nx;
-                for (int k = threadIdx.x; k < nwin; k += blockDim.x) Vw[k] = Vb[min(max(c0 - P + k, 0), nx - 1)];
-            }
+            const long b = row0 / nx;
+            const int c0 = (int)(row0 - b * nx);
+            const double* Vb = V + b * (long)nx;
+            for (int k = threadIdx.x; k < SBM + 2 * P; k += blockDim.x) Vw[k] = Vb[min(max(c0 - P + k, 0), nx - 1)];
         }
         __syncthreads();
-        // Et (both layouts) and A^T; rows outside the mesh or past R contribute nothing
+        // Et (both layouts) and A^T; rows outside the mesh or past R contribute nothing.  Rows
+        // go to waves, columns to lanes (no index divisions); a wave's eight rows of E are
+        // loaded before any is stored (loads in flight).
+        for (int t = lane; t < Pp; t += 64) {
+            const float pi = t < P ? w.Pif[t] : 0.f;
+            float v[SBM / 4];
 #pragma unroll
-        for (int q = 0; q < EPF; ++q) {
-            const int e = threadIdx.x + q * SU_THREADS, rr = e / Pp, t = e - rr * Pp;
-            if (e < SBM * Pp) {
-                const float v = (t < P && rcell[rr] >= 0) ? epf[q] * w.Pif[t] : 0.f;
-                EtR[rr * LP + t] = v;
-                EtT[t * LR + rr] = v;
+            for (int q = 0; q < SBM / 4; ++q) {
+                const int rr = wave + 4 * q;
+                v[q] = (t < P && rcell[rr] >= 0) ? E[(row0 + rr) * P + t] * pi : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < SBM / 4; ++q) {
+                const int rr = wave + 4 * q;
+                EtR[rr * LP + t] = v[q];
+                EtT[t * LR + rr] = v[q];
             }
         }
-        for (int e = threadIdx.x; e < SBM * Hp; e += blockDim.x) {
-            const int rr = e / Hp, g = e - rr * Hp;
+        for (int rr = wave; rr < SBM; rr += 4) {
             const int cell = rcell[rr];
-            double a = 0.0;
-            if (cell >= 0 && g < H) {
-                if (run) {
-                    for (int p = 0; p < N; ++p) a += (double)wV[p] * Vw[rr + N * g + p];
-                } else {
-                    const double* Vb = V + rbase[rr];
-                    for (int p = 0; p < N; ++p) a += (double)wV[p] * Vb[min(max(cell - P + N * g + p, 0), nx - 1)];
+            const double* Vb = V + rbase[rr];
+            for (int g = lane; g < Hp; g += 64) {
+                double a = 0.0;
+                if (cell >= 0 && g < H) {
+                    if (run) {
+                        for (int p = 0; p < N; ++p) a += (double)wV[p] * Vw[rr + N * g + p];
+                    } else {
+                        for (int p = 0; p < N; ++p) a += (double)wV[p] * Vb[min(max(cell - P + N * g + p, 0), nx - 1)];
+                    }
                 }
+                AsT[g * LR + rr] = (float)a;
             }
-            AsT[g * LR + rr] = (float)a;
         }
         __syncthreads();
-        if (tile + gridDim.x < ntiles) fetch((tile + gridDim.x) * SBM);
-        // GA = Et Bm^T: (SBM x Pp) (Pp x Hp); output tiles (row block i, column block j)
-        const int nga = (SBM / 16) * (Hp / 16);
-        for (int q = wave; q < nga; q += 4) {
-            const int i = q % (SBM / 16), j = q / (SBM / 16);
-            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-            const float* ar = EtR + (16 * i + lr) * LP + 4 * lk;
-            const float* br = Bms + (16 * j + lr) * LP + 4 * lk;
-            for (int s = 0; s < Pp; s += 16) {
-                const float4 a = *reinterpret_cast<const float4*>(ar + s);
-                const float4 b = *reinterpret_cast<const float4*>(br + s);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
-            }
-            const int g = 16 * j + lr;
+        // GA = Et Bm^T: (SBM x Pp) (Pp x Hp); wave w takes column blocks j = w, w + 4 (both
+        // row blocks), with their Bm fragments held in registers for the whole workgroup
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int rr = 16 * i + 4 * lk + e;
-                GAs[rr * LH + g] = acc[e];
-                if (want_GA && g < H && row0 + rr < R) w.GA[(row0 + rr) * H + g] = acc[e];
+        for (int jb = 0; jb < SB_JMAX; ++jb) {
+            const int j = wave + 4 * jb;
+            if (j >= Hp / 16) break;
+#pragma unroll
+            for (int i = 0; i < SBM / 16; ++i) {
+                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+                const float* ar = EtR + (16 * i + lr) * LP + 4 * lk;
+#pragma unroll
+                for (int sg = 0; sg < SB_SMAX; ++sg) {
+                    if (sg >= Pp / 16) break;
+                    const float4 a = *reinterpret_cast<const float4*>(ar + 16 * sg);
+                    const float4 b = bfr[jb][sg];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
+                }
+                const int g = 16 * j + lr;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int rr = 16 * i + 4 * lk + e;
+                    GAs[rr * LH + g] = acc[e];
+                    if (want_GA && g < H && row0 + rr < R) w.GA[(row0 + rr) * H + g] = acc[e];
+                }
             }
         }
         // GB += A^T Et: (Hp x SBM) (SBM x Pp)
@@ -672,15 +658,19 @@ __global__ __launch_bounds__(SU_THREADS) void surr_bwd_mfma(
             }
         }
         __syncthreads();  // GA complete
-        // dwV += sum over rows and groups of GA[r][g] V(clamp(i_r + o(g,p))), one wave per tap
+        // dwV += sum over rows and groups of GA[r][g] V(clamp(i_r + o(g,p))), one wave per tap;
+        // branch-free (rows outside the mesh have GA = 0; the window path always reads inside
+        // the window, the gathered path a clamped cell of the row's potential)
         for (int p = wave; p < N; p += 4) {
             float acc = 0.f;
-            for (int e = lane; e < SBM * H; e += 64) {
-                const int rr = e / H, g = e - rr * H;
-                const int cell = rcell[rr];
-                if (cell < 0) continue;
-                const double v = run ? Vw[rr + N * g + p] : V[rbase[rr] + min(max(cell - P + N * g + p, 0), nx - 1)];
-                acc = fmaf(GAs[rr * LH + g], (float)v, acc);
+            for (int rr = 0; rr < SBM; ++rr) {
+                const int cell = max(rcell[rr], 0);
+                const double* Vb = V + rbase[rr];
+                for (int g = lane; g < H; g += 64) {
+                    const float v = run ? (float)Vw[rr + N * g + p]
+                                        : (float)Vb[min(max(cell - P + N * g + p, 0), nx - 1)];
+                    acc = fmaf(GAs[rr * LH + g], v, acc);
+                }
             }
             for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
             if (lane == 0) dwv[p] += acc;
@@ -706,9 +696,9 @@ __global__ __launch_bounds__(SU_THREADS) void surr_bwd_mfma(
 // LDS bytes of surr_bwd_mfma, or 0 when the shape does not fit (then surr_bwd_block runs).
 static size_t surr_bwd_mfma_bytes(int H, int P, int N) {
     const size_t Hp = ((size_t)H + 15) / 16 * 16, Pp = ((size_t)P + 15) / 16 * 16;
-    if ((Hp / 16) * (Pp / 16) > 4 * (size_t)SB_MAXT || Pp > 128) return 0;
+    if ((Hp / 16) * (Pp / 16) > 4 * (size_t)SB_MAXT || Hp > 64 * SB_JMAX || Pp > 16 * SB_SMAX) return 0;
     const size_t LP = Pp + 4, LR = SBM + 4, LH = Hp + 4;
-    const size_t f = Hp * LP + SBM * LP + Pp * LR + Hp * LR + SBM * LH + ((size_t)N + 1) / 2 * 2;
+    const size_t f = SBM * LP + Pp * LR + Hp * LR + SBM * LH + ((size_t)N + 1) / 2 * 2;
     const size_t b = 4 * f + 8 * (SBM + 2 * (size_t)P);
     return b <= 150 * 1024 ? b : 0;
 }
@@ -719,19 +709,26 @@ __global__ void zero_grads(float* a, int na, float* b, int nb, float* c, int nc)
     for (int i = threadIdx.x; i < nc; i += blockDim.x) c[i] = 0.f;
 }
 
-// Fixed-order sum of the block partials: 64 entries of GB per workgroup; wave j sums the
-// partials k = j, j + 4, ... in ascending k, and the four sums are added in wave order.
-__global__ __launch_bounds__(256) void surr_bwd_reduce_gb(int nblk, int H, int P, SurrWS w) {
-    __shared__ float part[4][64];
+// Fixed-order sum of the block partials: 64 entries of GB per workgroup of 16 waves; wave j
+// sums the partials k = j, j + 16, ... in ascending k, and the sixteen sums are added in wave
+// order.
+constexpr int RG_WAVES = 16;
+__global__ __launch_bounds__(64 * RG_WAVES) void surr_bwd_reduce_gb(int nblk, int H, int P, SurrWS w) {
+    __shared__ float part[RG_WAVES][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const long e = (long)blockIdx.x * 64 + lane;
     const long n = (long)H * P;
     float acc = 0.f;
     if (e < n)
-        for (int k = wv; k < nblk; k += 4) acc += w.GBpart[(long)k * n + e];
+        for (int k = wv; k < nblk; k += RG_WAVES) acc += w.GBpart[(long)k * n + e];
     part[wv][lane] = acc;
     __syncthreads();
-    if (wv == 0 && e < n) w.GBpart[e] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    if (wv == 0 && e < n) {
+        float t = part[0][lane];
+#pragma unroll
+        for (int j = 1; j < RG_WAVES; ++j) t += part[j][lane];
+        w.GBpart[e] = t;
+    }
 }
 
 // dW[g] = sum_t GB[g][t] sin(u_g m) and du[g] = sum_t GB[g][t] W[g] m cos(u_g m), m = t + 1:
@@ -763,16 +760,21 @@ __global__ __launch_bounds__(256) void surr_bwd_params_g(int P, const float* __r
     }
 }
 
-// dwT[p] = sum_g du[g] (2 pi / n_m) o(g,p) and dwV[p] = sum of the workgroups' partials.
-__global__ void surr_bwd_params(int n_m, int N, int H, int nblk, const double* __restrict__ du,
-                                SurrWS w, float* __restrict__ dwV, float* __restrict__ dwT) {
-    const int Pm = n_m / 2;
-    for (int p = threadIdx.x; p < N; p += blockDim.x) {
-        double acc = 0.0;
-        for (int g = 0; g < H; ++g) acc += du[g] * (two_pi_over(n_m) * (double)(-Pm + N * g + p));
-        dwT[p] = (float)acc;
-        double sv = 0.0;
-        for (int k = 0; k < nblk; ++k) sv += (double)w.wVpart[(long)k * N + p];
+// dwT[p] = sum_g du[g] (2 pi / n_m) o(g,p) and dwV[p] = sum of the workgroups' partials: one
+// wave per tap p, lanes over g (resp. workgroups), fixed butterfly.
+__global__ __launch_bounds__(64) void surr_bwd_params(int n_m, int N, int H, int nblk,
+                                                      const double* __restrict__ du, SurrWS w,
+                                                      float* __restrict__ dwV, float* __restrict__ dwT) {
+    const int Pm = n_m / 2, p = blockIdx.x, lane = threadIdx.x;
+    double a = 0.0, sv = 0.0;
+    for (int g = lane; g < H; g += 64) a += du[g] * (two_pi_over(n_m) * (double)(-Pm + N * g + p));
+    for (int k = lane; k < nblk; k += 64) sv += (double)w.wVpart[(long)k * N + p];
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        sv += __shfl_xor(sv, o, 64);
+    }
+    if (lane == 0) {
+        dwT[p] = (float)a;
         dwV[p] = (float)sv;
     }
 }
@@ -1020,10 +1022,10 @@ extern "C" int wk_surrogate_bwd(const wk_mesh* mesh, int32_t N, const float* wV,
                            mesh->nx, R, n_cells, cells, P, N, H, Pn, wV, E, w, dV ? 1 : 0);
     }
     if (nblk > 0) {
-        hipLaunchKernelGGL(surr_bwd_reduce_gb, dim3((unsigned)(((long)H * P + 63) / 64)), dim3(256),
+        hipLaunchKernelGGL(surr_bwd_reduce_gb, dim3((unsigned)(((long)H * P + 63) / 64)), dim3(64 * RG_WAVES),
                            0, s, (int)nblk, H, P, w);
         hipLaunchKernelGGL(surr_bwd_params_g, dim3((unsigned)H), dim3(256), 0, s, P, W, w, dW, w.du);
-        hipLaunchKernelGGL(surr_bwd_params, dim3(1), dim3(64), 0, s, mesh->n_m, N, H, (int)nblk, w.du,
+        hipLaunchKernelGGL(surr_bwd_params, dim3((unsigned)N), dim3(64), 0, s, mesh->n_m, N, H, (int)nblk, w.du,
                            w, dwV, dwT);
     } else {
         hipLaunchKernelGGL(zero_grads, dim3(1), dim3(256), 0, s, dwV, N, dwT, N, dW, H);
