@@ -8,7 +8,8 @@ count stays in device memory; the host synchronises only to size the occasional 
 refresh and to read statistics.
 
 Kernel sources (the paper's two steps, Sec. 4): "exact" = eq.(4) on MFMA in FP64 or a reduced
-precision; "surrogate" = the trained network of eq.(5).  Rows are evaluated only for cells
+precision; "surrogate" = the trained network of eq.(5); "given" = rows the caller computed
+(`rows`, one per cell, every cell evaluated at start).  Rows are evaluated only for cells
 within a margin of the occupied ones ("occupied", the paper's memory/speed point) or for
 every cell at start ("all"); both give the same trajectory bit for bit when the margin
 covers the drift between refreshes.
@@ -27,7 +28,7 @@ from . import learn, ops
 class Simulator:
     def __init__(self, cfg, kernel: str = "exact", prec: str = "fp64", mode: str = "occupied",
                  refresh_every: int = 8, cap_factor: float = 3.0, weights=None, N: int = 2,
-                 device="cuda", hist_in_step: bool = True):
+                 device="cuda", hist_in_step: bool = True, rows=None):
         self.cfg = cfg
         self.md = cfg.mesh.as_dict(cfg.dt)
         md = self.md
@@ -53,8 +54,17 @@ class Simulator:
         self.cdf = torch.zeros((self.n_cells, self.width), dtype=torch.int64, device=self.dev)
         self.glen = min(self.width, 256)                # guide buckets for the CDF search
         self.guide = torch.zeros((self.n_cells, self.glen + 1), dtype=torch.int32, device=self.dev)
-        kdt = torch.float64 if (kernel == "exact" and prec == "fp64") else torch.float32
-        self.Kbuf = torch.empty((self.n_cells, self.row_len), dtype=kdt, device=self.dev)
+        if kernel == "given":
+            if mode != "all":
+                raise ValueError("given kernel rows need mode='all'")
+            if (rows is None or rows.device.type != self.dev.type or rows.dtype not in (torch.float64, torch.float32)
+                    or tuple(rows.shape) != (self.n_cells, self.row_len) or not rows.is_contiguous()):
+                raise ValueError(f"rows must be a contiguous [{self.n_cells}][{self.row_len}] float "
+                                 f"tensor on {self.dev}")
+            self.Kbuf = rows
+        else:
+            kdt = torch.float64 if (kernel == "exact" and prec == "fp64") else torch.float32
+            self.Kbuf = torch.empty((self.n_cells, self.row_len), dtype=kdt, device=self.dev)
         self.new_cells = torch.empty(self.n_cells, dtype=torch.int32, device=self.dev)
         self.d_count = torch.zeros(1, dtype=torch.int64, device=self.dev)
         self.n_rows = 0
@@ -86,7 +96,9 @@ class Simulator:
         if count == 0:
             return
         K = self.Kbuf[:count]
-        if self.kernel == "exact":
+        if self.kernel == "given":
+            pass                                        # rows already in place (all cells)
+        elif self.kernel == "exact":
             ops.kernel_eval(self.V, self.n_m, cells=cells[:count], prec=self.prec,
                             layout="half" if self.half else "full", out=K)
         else:

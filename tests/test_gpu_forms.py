@@ -235,10 +235,11 @@ def test_surrogate_autograd_matches_bwd(orc):
     V = torch.from_numpy(inputs.random_potentials(2, nx, 0.5, seed=2)).to(dev()).requires_grad_(True)
     wV, wT, W = [t.requires_grad_(True) for t in _f32(_weights(n_m, N, 3))]
     Kh = learn.SurrogateFn.apply(V, wV, wT, W, n_m, N)
-    E = torch.randn_like(Kh)
-    (Kh * E).sum().backward()
-    ref = orc.surrogate_bwd(to_np(V.detach()), n_m, N, *[to_np(t.detach()).astype(np.float64) for t in (wV, wT, W)],
-                            to_np(E).astype(np.float64).reshape(2, nx, -1))
+    En = np.random.default_rng(5).normal(size=tuple(Kh.shape)).astype(np.float32)
+    (Kh * torch.from_numpy(En).to(dev())).sum().backward()
+    ref = orc.surrogate_bwd(inputs.random_potentials(2, nx, 0.5, seed=2), n_m, N,
+                            *[w.astype(np.float32).astype(np.float64) for w in _weights(n_m, N, 3)],
+                            En.astype(np.float64).reshape(2, nx, -1))
     for got, r in zip((wV.grad, wT.grad, W.grad, V.grad), ref):
         got = to_np(got).astype(np.float64).reshape(r.shape)
         assert np.abs(got - r).max() <= 1e-4 * np.abs(r).max()

@@ -52,16 +52,21 @@ def test_full_size_run_repeatable_both_histogram_paths():
         assert torch.equal(sim.hist, ref.hist), k
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
-def test_simulator_equals_oracle_loop(orc, prec):
-    """The simulator's kernel rows -> tables -> steps equal the oracle loop fed the same rows."""
+@pytest.mark.parametrize("f64", [True, False])
+def test_simulator_equals_oracle_loop(orc, f64):
+    """Rows -> tables -> steps: the simulator given the oracle's kernel rows (FP64, or rounded to
+    FP32 as the reduced-precision forms store them) equals the oracle loop on the same rows."""
     cfg = inputs.config_c1()
-    sim = Simulator(cfg, mode="all", prec=prec)
     md = cfg.mesh.as_dict(cfg.dt)
-    K = ops.kernel_eval(torch.from_numpy(cfg.V[None]).to(dev()), cfg.mesh.n_m, prec=prec,
-                        cells=torch.arange(cfg.mesh.nx, dtype=torch.int32, device=dev()), layout="half")
-    Kf = orc.half_to_full(to_np(K).astype(np.float64))
+    Kf = orc.kernel_1d(cfg.V, cfg.mesh.n_m, HB)[0]
+    if not f64:
+        Kf = Kf.astype(np.float32).astype(np.float64)
+    rows = torch.from_numpy(np.ascontiguousarray(orc.full_to_half(Kf)).astype(
+        np.float64 if f64 else np.float32)).to(dev())
+    sim = Simulator(cfg, kernel="given", mode="all", rows=rows)
     g, n0, thr, cdf = orc.gamma_tables(Kf, cfg.dt)
+    assert np.array_equal(to_np(sim.gamma), g)
+    assert np.array_equal(to_np(sim.cdf).view(np.uint64), cdf)
     cap = sim.capacity
     hp = orc.sp_init(md, cfg.bin_counts, cap, seed=cfg.seed)
     slot = np.arange(md["nx"], dtype=np.int32)
@@ -69,7 +74,22 @@ def test_simulator_equals_oracle_loop(orc, prec):
         hp, _ = orc.sp_step(md, hp, (n0, thr, cdf), slot, step=s, seed=cfg.seed)
         hp, _, _, _ = orc.sp_annihilate(md, hp, step=s, seed=cfg.seed, capacity=cap)
         sim.step()
-    assert_particles_equal(sim.a.view(), hp.view(), f"simulator vs oracle ({prec})")
+    assert_particles_equal(sim.a.view(), hp.view(), f"simulator vs oracle ({'fp64' if f64 else 'fp32'} rows)")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("bf16x3", 5e-5)])
+def test_simulator_rows_and_rates_match_oracle(orc, prec, tol):
+    """The simulator's own kernel rows (eq.(4) on the GPU) against the oracle's, normwise, and
+    the creation rates built from them against the oracle's rates from its own rows."""
+    cfg = inputs.config_c1()
+    sim = Simulator(cfg, mode="all", prec=prec)
+    Kf = orc.kernel_1d(cfg.V, cfg.mesh.n_m, HB)[0]
+    got = to_np(sim.Kbuf).astype(np.float64)
+    ref = orc.full_to_half(Kf)
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    g = orc.gamma_tables(Kf, cfg.dt)[0]
+    # gamma sums n_m rows entries of size <= max|K|: the row error bound carries over
+    assert np.abs(to_np(sim.gamma) - g).max() <= cfg.mesh.n_m * tol * np.abs(ref).max()
 
 
 def test_2d_simulator_equals_oracle_loop(orc):
@@ -77,11 +97,13 @@ def test_2d_simulator_equals_oracle_loop(orc):
     V = inputs.gaussian_dot_2d(mesh, 0.2, 1.5, 5.0, 4.5)
     bc = inputs.packet_bin_counts_2d(mesh, 2e4, 3.0, 4.5, 1.2, inputs.k_for_energy(0.1), 0.0)
     cfg = inputs.RunConfig("tiny2d", mesh, V, bc, int(bc.sum()), 0.5, 5, seed=4)
-    sim = Simulator(cfg, mode="all")
     md = mesh.as_dict(cfg.dt)
-    K = to_np(ops.kernel_eval(torch.from_numpy(V[None]).to(dev()), 16,
-                              cells=torch.arange(20 * 18, dtype=torch.int32, device=dev())))
-    g, n0, thr, cdf = orc.gamma_tables(K.reshape(-1, 256), cfg.dt)
+    K = orc.kernel_2d(V, 16, HB).reshape(-1, 256)
+    sim = Simulator(cfg, kernel="given", mode="all", rows=torch.from_numpy(np.ascontiguousarray(K)).to(dev()))
+    got = to_np(ops.kernel_eval(torch.from_numpy(V[None]).to(dev()), 16,
+                                cells=torch.arange(20 * 18, dtype=torch.int32, device=dev())))
+    assert np.abs(got.reshape(-1, 256) - K).max() <= 1e-10 * np.abs(K).max()
+    g, n0, thr, cdf = orc.gamma_tables(K, cfg.dt)
     hp = orc.sp_init(md, bc, sim.capacity, seed=cfg.seed)
     slot = np.arange(20 * 18, dtype=np.int32)
     for s in range(5):
