@@ -42,7 +42,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # write x1.0).  Taken for the kernels as they are now; an entry is dropped when its kernel
 # changes until the counters are taken again.
 TRAFFIC = {"step_count": 0.0671, "step_apply": 0.2685, "annih_count": 0.1192,
-           "annih_scan": 0.0001, "annih_write": 0.2194}
+           "annih_scan": 0.0001}
 
 
 def _events():
@@ -296,7 +296,8 @@ def run_surrogate_forms():
     ms = timeit(lambda: ops.kernel_eval(V, n_m, prec="bf16", layout="half", out=Kb))
     res["exact_bf16"] = {"ms": round(ms, 3), "entries_per_s": entries / (ms * 1e-3)}
     kmax = K.reshape(B, -1).abs().amax(dim=1)
-    for N in (2, 4, 8):
+    # N sweep of eq.(5): N cos factors, H = n_m / N sinusoid groups (N = 1 is eq.(4) itself)
+    for N in (1, 2, 4, 8, 16):
         w = learn.analytic_weights(n_m, N)
         for prec in ("fp32", "bf16"):
             ms = timeit(lambda: learn.surrogate_fwd(V, n_m, N, *w, prec=prec, out=Kb))
