@@ -433,13 +433,22 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
                 }
             }
             __syncthreads();
-            // local row q of the stage is global row row0 + ((q / 16) * WM + tm) * 16 + q % 16
-            for (int f = threadIdx.x; f < SR * (P / 4); f += KE_THREADS) {
-                const int q = f / (P / 4), c4 = (f - q * (P / 4)) * 4;
-                const long row = row0 + ((q / 16) * WM + tm) * 16 + (q & 15);
-                if (row < R)
-                    *reinterpret_cast<float4*>(out + row * P + c4) =
-                        *reinterpret_cast<const float4*>(stg + q * SP + c4);
+            // local row q of the stage is global row row0 + ((q / 16) * WM + tm) * 16 + q % 16;
+            // rows go to waves and their 16-byte pieces to lanes (no index division), and a
+            // wave's LDS reads are all issued before its stores
+            constexpr int NWV = KE_THREADS / 64, RPW = SR / NWV;
+            static_assert(SR % NWV == 0, "stage rows per wave");
+            float4 v[RPW];
+            for (int c4 = 4 * lane; c4 < P; c4 += 256) {
+#pragma unroll
+                for (int i = 0; i < RPW; ++i)
+                    v[i] = *reinterpret_cast<const float4*>(stg + (wave + NWV * i) * SP + c4);
+#pragma unroll
+                for (int i = 0; i < RPW; ++i) {
+                    const int q = wave + NWV * i;
+                    const long row = row0 + ((q >> 4) * WM + tm) * 16 + (q & 15);
+                    if (row < R) *reinterpret_cast<float4*>(out + row * P + c4) = v[i];
+                }
             }
             __syncthreads();
         }
