@@ -41,8 +41,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # --copy-calibration`, scaled by what the counters read for a 1 GiB device copy (fetch x2.0,
 # write x1.0).  Taken for the kernels as they are now; an entry is dropped when its kernel
 # changes until the counters are taken again.
-TRAFFIC = {"step_count": 0.0671, "step_apply": 0.2687, "annih_count": 0.1194,
-           "annih_scan": 0.0001, "annih_write": 0.2187}
+TRAFFIC = {}
 
 
 def _events():
@@ -51,16 +50,18 @@ def _events():
 
 
 # Algorithmic HBM bytes per launch of each particle kernel, from the running sums the
-# library keeps (S = stats): what the pass must move at minimum with 9-byte particles
-# (x 4 + M 4 + s 1, FP32 positions).  The histogram and the tables are L2-resident; the
-# pair counts the two sp_step passes hand over are not counted (an implementation choice).
-KERNEL_BYTES = {
-    "step_count": lambda S, L: 5 * S[L.ST_CUM_N],                              # read x 4 + s 1
-    "step_apply": lambda S, L: 18 * S[L.ST_CUM_N] + 18 * S[L.ST_CUM_PAIRS],   # read 9, write 9; 2 children
-    "annih_count": lambda S, L: 9 * S[L.ST_CUM_ANNIH_IN],                      # read 9
-    "annih_write": lambda S, L: (9 * S[L.ST_CUM_ANNIH_IN] + 9 * S[L.ST_CUM_KEPT]
-                                 + 9 * S[L.ST_CUM_REGEN]),                     # read 9, write kept + placed
-}
+# library keeps (S = stats): what the pass must move at minimum with PB-byte particles (the
+# headline's: x 4 + M 2 + s 1 = 7, FP32 positions and 16-bit momenta).  The histogram and
+# the tables are L2-resident; the pair counts the two sp_step passes hand over are not
+# counted (an implementation choice).
+def kernel_bytes(PB: int):
+    return {
+        "step_count": lambda S, L: 5 * S[L.ST_CUM_N],                                # read x 4 + s 1
+        "step_apply": lambda S, L: 2 * PB * (S[L.ST_CUM_N] + S[L.ST_CUM_PAIRS]),    # read, write; 2 children
+        "annih_count": lambda S, L: PB * S[L.ST_CUM_ANNIH_IN],                       # read
+        "annih_write": lambda S, L: PB * (S[L.ST_CUM_ANNIH_IN] + S[L.ST_CUM_KEPT]
+                                          + S[L.ST_CUM_REGEN]),                      # read, write kept + placed
+    }
 
 
 def run_headline(steps: int, warmup: int, traced: bool):
@@ -98,15 +99,18 @@ def run_headline(steps: int, warmup: int, traced: bool):
     if not traced:
         return out
     L.check(L.lib().wk_trace_disable(), "wk_trace_disable")
+    pbytes = (8 if sim.md["pos_f64"] else 4) + (2 if sim.a.m16 else 4) + 1
+    out["particle_bytes"] = pbytes
+    KB = kernel_bytes(pbytes)
     kernels = {}
     for name in L.trace_names():
         tot, cnt = L.trace_read(name)
         kernels[name] = {"ms_total": round(tot, 3), "launches": cnt, "us_avg": round(1e3 * tot / max(cnt, 1), 2)}
-        if name in KERNEL_BYTES:
-            b = KERNEL_BYTES[name](S, L)
+        if name in KB:
+            b = KB[name](S, L)
             kernels[name]["alg_GB"] = round(b / 1e9, 3)
             kernels[name]["alg_GBps"] = round(b / (tot * 1e-3) / 1e9, 1)
-    dom = max((k for k in kernels if k in KERNEL_BYTES), key=lambda k: kernels[k]["ms_total"])
+    dom = max((k for k in kernels if k in KB), key=lambda k: kernels[k]["ms_total"])
     ach = kernels[dom]["alg_GBps"]
     out["kernels"] = kernels
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
@@ -379,11 +383,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32+fp32 (fp64 kernel and tables)",
+        "dtype": "int16+fp32 (fp64 kernel and tables)",
         "data": "synthetic",
         "config": {"workload": cfg.name, "cells": cfg.mesh.nx, "dx_nm": cfg.mesh.dx,
                    "n_m": cfg.mesh.n_m, "particles_initial": int(cfg.bin_counts.sum()),
-                   "dt_fs": cfg.dt, "annihilation": "every step", "kernel": "exact fp64, occupied cells"},
+                   "dt_fs": cfg.dt, "annihilation": "every step", "kernel": "exact fp64, occupied cells",
+                   "particle_layout": "x fp32, M int16, s int8 (7 B)"},
         "run": {"n_last": h["n_last"], "pairs_created": h["pairs"], "regenerated": h["regen"],
                 "kernel_rows_evaluated": h["rows"], "wall_s": round(h["wall_s"], 3),
                 "traced_replica_ms_per_step": round(tr["ms"] / args.steps, 4),

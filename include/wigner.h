@@ -30,8 +30,9 @@
  *
  * Particles (Sec. 2.1)
  *   - Struct-of-arrays.  Positions are in units of the cell width (cell = floor(x)),
- *     float or double per sp_geom.pos_f64.  1-D: M is int32; 2-D: M (x axis) and My are
- *     int16.  s is int8: +1 / -1, 0 = absorbed (dropped by the next annihilation).
+ *     float or double per sp_geom.pos_f64.  1-D: M is int32, or int16 when sp_geom.m16
+ *     is set; 2-D: M (x axis) and My are int16.  s is int8: +1 / -1, 0 = absorbed
+ *     (dropped by the next annihilation).
  *   - The particle count lives in device memory (*d_n) so a time loop needs no host
  *     synchronisation.
  *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed,
@@ -81,7 +82,9 @@ typedef struct sp_geom {
     int32_t n_k;      /* particle momentum window per axis: [M_min, M_min + n_k) */
     int32_t M_min;
     int32_t pos_f64;  /* 1: double positions, 0: float positions */
-    int32_t reserved;
+    int32_t m16;      /* 1-D: 1 = M is int16 (the window must lie in [-32768, 32767]),
+                         0 = int32; every particle buffer of a call must use that width.
+                         2-D momenta are always int16 (the field is ignored). */
     double vdt;       /* drift per step per unit momentum index, in cells */
     uint64_t seed;    /* Philox key */
 } sp_geom;

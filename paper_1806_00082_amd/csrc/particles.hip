@@ -1325,8 +1325,8 @@ static int make_geo(const sp_geom* gm, Geo* g) {
     WK_REQUIRE(gm->nx > 0 && gm->ny > 0 && (gm->dim == 2 || gm->ny == 1), "particles: bad mesh");
     WK_REQUIRE(gm->n_m >= 2 && gm->n_m % 2 == 0, "particles: n_m must be even");
     WK_REQUIRE(gm->n_k > 0, "particles: n_k must be positive");
-    WK_REQUIRE(gm->dim == 1 || (gm->M_min >= -32768 && gm->M_min + gm->n_k <= 32767),
-               "particles: 2-D momenta must fit int16");
+    WK_REQUIRE((gm->dim == 1 && !gm->m16) || (gm->M_min >= -32768 && gm->M_min + gm->n_k <= 32767),
+               "particles: 16-bit momenta (2-D, or 1-D with m16) must fit int16");
     g->dim = gm->dim;
     g->nx = gm->nx;
     g->ny = gm->ny;
@@ -1439,11 +1439,16 @@ extern "C" size_t sp_workspace_size(const sp_geom* gm) {
 
 #define WK_DISPATCH(gm, FN, ...)                                                      \
     do {                                                                             \
-        if ((gm)->dim == 1) {                                                        \
+        if ((gm)->dim == 1 && !(gm)->m16) {                                          \
             if ((gm)->pos_f64)                                                       \
                 FN<double, int32_t, 1>(__VA_ARGS__);                                 \
             else                                                                     \
                 FN<float, int32_t, 1>(__VA_ARGS__);                                  \
+        } else if ((gm)->dim == 1) {                                                 \
+            if ((gm)->pos_f64)                                                       \
+                FN<double, int16_t, 1>(__VA_ARGS__);                                 \
+            else                                                                     \
+                FN<float, int16_t, 1>(__VA_ARGS__);                                  \
         } else {                                                                     \
             if ((gm)->pos_f64)                                                       \
                 FN<double, int16_t, 2>(__VA_ARGS__);                                 \

@@ -99,17 +99,33 @@ def gamma_tables(K: torch.Tensor, n_m: int, dt: float, dim: int = 1, layout: str
 
 
 # ----------------------------------------------------------------------------- particles
-def geom_struct(mesh: dict, seed: int) -> L.SpGeom:
+def geom_struct(mesh: dict, seed: int, m16: bool = False) -> L.SpGeom:
+    """m16: 1-D particle buffers hold int16 momenta (2-D momenta are always int16)."""
     return L.SpGeom(mesh["dim"], mesh["nx"], mesh.get("ny", 1), mesh["n_m"], mesh["n_k"],
-                    mesh["M_min"], int(mesh["pos_f64"]), 0, float(mesh["vdt"]), seed)
+                    mesh["M_min"], int(mesh["pos_f64"]), int(m16), float(mesh["vdt"]), seed)
+
+
+def fits_m16(mesh: dict) -> bool:
+    """Whether the momentum window fits 16-bit storage."""
+    return mesh["M_min"] >= -32768 and mesh["M_min"] + mesh["n_k"] <= 32767
+
+
+def _m16(*parts) -> bool:
+    widths = {p.m16 for p in parts}
+    if len(widths) != 1:
+        raise ValueError("the particle buffers of one call must use the same momentum width")
+    return widths.pop()
 
 
 class DeviceParticles:
     """Struct-of-arrays particle buffer in HBM (positions in cell units)."""
 
-    def __init__(self, dim: int, capacity: int, pos_f64: bool, device="cuda"):
+    def __init__(self, dim: int, capacity: int, pos_f64: bool, device="cuda", m16: bool = False):
+        """m16: 1-D momenta stored as int16 (7-byte particles with FP32 positions instead of
+        9); the momentum window must fit 16 bits.  2-D momenta are always int16."""
         ft = torch.float64 if pos_f64 else torch.float32
-        mt = torch.int32 if dim == 1 else torch.int16
+        self.m16 = bool(m16) and dim == 1
+        mt = torch.int32 if (dim == 1 and not self.m16) else torch.int16
         self.dim, self.pos_f64, self.capacity = dim, pos_f64, int(capacity)
         self.x = torch.zeros(capacity, dtype=ft, device=device)
         self.y = torch.zeros(capacity, dtype=ft, device=device) if dim == 2 else None
@@ -160,7 +176,7 @@ def new_stats(device="cuda") -> torch.Tensor:
 
 def sp_init(mesh: dict, seed: int, bin_counts: torch.Tensor, out: DeviceParticles,
             stats: torch.Tensor, ws: torch.Tensor):
-    g = geom_struct(mesh, seed)
+    g = geom_struct(mesh, seed, _m16(out))
     ps = out.struct()
     L.check(L.lib().sp_init(ctypes.byref(g), _ptr(bin_counts.to(torch.int32).contiguous()),
                             ctypes.byref(ps), _ptr(stats), _ptr(ws), ws.numel(), _stream()),
@@ -183,7 +199,7 @@ def sp_step(mesh: dict, seed: int, cell_slot, n0, thr, cdf, pin: DeviceParticles
             hist: torch.Tensor | None = None, guide: torch.Tensor | None = None):
     """One step from pin to pout.  hist (optional): receives the signed histogram of the
     ensemble after the step.  guide (optional): sampling_guide() of the cdf rows."""
-    g = geom_struct(mesh, seed)
+    g = geom_struct(mesh, seed, _m16(pin, pout))
     a, b = pin.struct(), pout.struct()
     glen = 0 if guide is None else guide.shape[1] - 1
     L.check(L.lib().sp_step(ctypes.byref(g), _ptr(cell_slot), _ptr(n0), _ptr(thr), _ptr(cdf),
@@ -195,7 +211,7 @@ def sp_annihilate(mesh: dict, seed: int, pin: DeviceParticles, pout: DeviceParti
                   hist: torch.Tensor, step: int, stats: torch.Tensor, ws: torch.Tensor,
                   hist_ready: bool = False):
     """hist_ready: `hist` already holds the histogram of `pin` (from sp_step)."""
-    g = geom_struct(mesh, seed)
+    g = geom_struct(mesh, seed, _m16(pin, pout))
     a, b = pin.struct(), pout.struct()
     L.check(L.lib().sp_annihilate(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _ptr(hist),
                                   int(bool(hist_ready)), step, _ptr(stats), _ptr(ws), ws.numel(),

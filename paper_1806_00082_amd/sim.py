@@ -28,7 +28,7 @@ from . import learn, ops
 class Simulator:
     def __init__(self, cfg, kernel: str = "exact", prec: str = "fp64", mode: str = "occupied",
                  refresh_every: int = 8, cap_factor: float = 3.0, weights=None, N: int = 2,
-                 device="cuda", hist_in_step: bool = True, rows=None):
+                 device="cuda", hist_in_step: bool = True, rows=None, m16=None):
         self.cfg = cfg
         self.md = cfg.mesh.as_dict(cfg.dt)
         md = self.md
@@ -72,8 +72,10 @@ class Simulator:
         bc = torch.as_tensor(cfg.bin_counts, dtype=torch.int32)
         n0 = int(bc.sum())
         self.capacity = int(cap_factor * n0) + 1024
-        self.a = ops.DeviceParticles(self.dim, self.capacity, md["pos_f64"], self.dev)
-        self.b = ops.DeviceParticles(self.dim, self.capacity, md["pos_f64"], self.dev)
+        # 1-D momenta in 16 bits whenever the window allows (7-byte particles with FP32 positions)
+        m16 = m16 if m16 is not None else ops.fits_m16(md)
+        self.a = ops.DeviceParticles(self.dim, self.capacity, md["pos_f64"], self.dev, m16=m16)
+        self.b = ops.DeviceParticles(self.dim, self.capacity, md["pos_f64"], self.dev, m16=m16)
         self.stats = ops.new_stats(self.dev)
         self.ws = ops.sp_workspace(md, self.seed, self.dev)
         self.hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=self.dev)

@@ -21,20 +21,21 @@ def _setup(orc, cfg, N0_scale=1.0, cap_factor=3):
     return md, tables[1:], bc, cap
 
 
-def _gpu_init(md, bc, cap, seed):
-    p = ops.DeviceParticles(md["dim"], cap, md["pos_f64"])
+def _gpu_init(md, bc, cap, seed, m16=False):
+    p = ops.DeviceParticles(md["dim"], cap, md["pos_f64"], m16=m16)
     st = ops.new_stats()
     ws = ops.sp_workspace(md, seed)
     ops.sp_init(md, seed, torch.from_numpy(bc).to(dev()), p, st, ws)
     return p, st, ws
 
 
+@pytest.mark.parametrize("m16", [False, True])
 @pytest.mark.parametrize("cfgname", ["c1", "c2small"])
-def test_init_bit_exact(orc, cfgname):
+def test_init_bit_exact(orc, cfgname, m16):
     cfg = inputs.config_c1() if cfgname == "c1" else inputs.config_c2(N0=2e5)
     md, _, bc, cap = _setup(orc, cfg)
     hp = orc.sp_init(md, bc, cap, seed=cfg.seed)
-    p, st, ws = _gpu_init(md, bc, cap, cfg.seed)
+    p, st, ws = _gpu_init(md, bc, cap, cfg.seed, m16)
     assert p.count() == hp.n
     assert_particles_equal(p.view(), hp.view(), "sp_init")
 
@@ -50,14 +51,15 @@ def test_init_overflow_reports_needed(orc):
     assert p.count() == 0
 
 
-def _run_both(orc, cfg, steps, N0_scale=1.0, check_every=1):
-    """Run the oracle and the GPU side by side from the same start, comparing every step."""
+def _run_both(orc, cfg, steps, N0_scale=1.0, check_every=1, m16=False):
+    """Run the oracle and the GPU side by side from the same start, comparing every step
+    (m16: the GPU buffers hold 16-bit momenta)."""
     md, tables, bc, cap = _setup(orc, cfg, N0_scale)
     seed = cfg.seed
     slot = np.arange(md["nx"], dtype=np.int32)
     hp = orc.sp_init(md, bc, cap, seed=seed)
-    a, st, ws = _gpu_init(md, bc, cap, seed)
-    b = ops.DeviceParticles(1, cap, md["pos_f64"])
+    a, st, ws = _gpu_init(md, bc, cap, seed, m16)
+    b = ops.DeviceParticles(1, cap, md["pos_f64"], m16=m16)
     hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev())
     n0, thr, cdf = host_tables_to_device((None,) + tuple(tables))
     slot_d = torch.from_numpy(slot).to(dev())
@@ -92,20 +94,34 @@ def _run_both(orc, cfg, steps, N0_scale=1.0, check_every=1):
     return md, hp, a, hist
 
 
-def test_c1_loop_bit_exact(orc):
+@pytest.mark.parametrize("m16", [False, True])
+def test_c1_loop_bit_exact(orc, m16):
     """1-D FP64 workload (1e5 particles), 12 full steps, every array compared every step."""
-    _run_both(orc, inputs.config_c1(), steps=12)
+    _run_both(orc, inputs.config_c1(), steps=12, m16=m16)
 
 
-def test_c2_loop_bit_exact_small(orc):
+@pytest.mark.parametrize("m16", [False, True])
+def test_c2_loop_bit_exact_small(orc, m16):
     """1-D FP32 positions, 80 pseudo-momenta, 2e5 particles, 10 steps."""
-    _run_both(orc, inputs.config_c2(N0=2e5), steps=10)
+    _run_both(orc, inputs.config_c2(N0=2e5), steps=10, m16=m16)
 
 
-def test_c2_full_size_steps(orc):
-    """The paper-shaped workload at its full 1e7 particles for 3 steps, bit-exact."""
-    print("c2 full size: 1e7 particles", flush=True)
-    _run_both(orc, inputs.config_c2(), steps=3)
+@pytest.mark.parametrize("m16", [False, True])
+def test_c2_full_size_steps(orc, m16):
+    """The paper-shaped workload at its full 1e7 particles for 3 steps, bit-exact (the
+    benchmark's buffers hold 16-bit momenta)."""
+    print(f"c2 full size: 1e7 particles, m16={m16}", flush=True)
+    _run_both(orc, inputs.config_c2(), steps=3, m16=m16)
+
+
+def test_mixed_momentum_widths_refused():
+    md = inputs.config_c1().mesh.as_dict(1.0)
+    a = ops.DeviceParticles(1, 16, True)
+    b = ops.DeviceParticles(1, 16, True, m16=True)
+    st = ops.new_stats()
+    with pytest.raises(ValueError):
+        ops.sp_annihilate(md, 0, a, b, torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev()),
+                          0, st, ops.sp_workspace(md))
 
 
 def test_density_readout(orc):
