@@ -311,6 +311,51 @@ def run_surrogate_forms():
     return res
 
 
+def run_tables_forms(reps=5):
+    """Creation tables (eq.(1), postulate II) from eq.(4) rows: the fused pass whose kernel rows
+    stay on chip against kernel_eval + gamma_tables + sampling_guide, and the device memory the
+    two-step form needs for the rows."""
+    import torch
+    from paper_1806_00082_amd import inputs, ops
+
+    out = {}
+    cases = (("1e7-particle run, every cell: 1 x 400 cells x 80 m", 1, 400, 80, 80),
+             ("learned-kernel shape: 64 potentials x 1024 cells x 256 m", 64, 1024, 256, 256),
+             ("64 potentials x 2048 cells x 512 m", 64, 2048, 512, 256))
+    for name, B, nx, n_m, glen in cases:
+        V = torch.from_numpy(inputs.random_potentials(B, nx, 0.5, seed=5)).cuda()
+        R = B * nx
+        bufs = (torch.empty(R, dtype=torch.float64, device="cuda"), torch.empty(R, dtype=torch.int32, device="cuda"),
+                torch.empty(R, dtype=torch.int32, device="cuda"),
+                torch.empty((R, n_m), dtype=torch.int64, device="cuda"),
+                torch.empty((R, glen + 1), dtype=torch.int32, device="cuda"))
+        K = torch.empty((R, n_m // 2), dtype=torch.float64, device="cuda")
+
+        def fused():
+            ops.kernel_tables(V, n_m, 0.5, guide_len=glen, out=bufs)
+
+        def two_step():
+            ops.kernel_eval(V, n_m, layout="half", out=K)
+            g, n0, thr, cdf = ops.gamma_tables(K, n_m, 0.5, layout="half")
+            ops.sampling_guide(cdf, glen, out=bufs[4])
+
+        rec = {"rows": R, "kernel_rows_MB_two_step": round(K.numel() * 8 / 1e6, 1)}
+        for tag, fn in (("fused_ms", fused), ("two_step_ms", two_step)):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = _events()
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            rec[tag] = round(e0.elapsed_time(e1) / reps, 4)
+        out[name] = rec
+        del V, bufs, K
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_cpu_baseline(sample_steps: int):
     """The oracle (single-threaded C, one core) on the first steps of the headline run."""
     import numpy as np
@@ -351,8 +396,8 @@ def main():
                     help="only the eq.(4) precision batch (for counter runs on the contraction)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(particles, cells and kernel rows are not sharded across devices).", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -368,7 +413,8 @@ def main():
         tr = run_headline(args.steps, args.warmup, traced=True)
         assert tr["stats"][11:16] == h["stats"][11:16], "traced replica diverged from the timed run"
     forms = {} if args.no_forms else {"kernel_eq4": run_kernel_forms(), "surrogate_eq5": run_surrogate_forms(),
-                                      "learning": run_learning(), "workload_2d": run_2d()}
+                                      "learning": run_learning(), "tables": run_tables_forms(),
+                                      "workload_2d": run_2d()}
     cpu = None if args.no_cpu else run_cpu_baseline(args.cpu_steps)
     value = h["particle_steps"] / (h["ms"] * 1e-3)
     cfg = h["cfg"]

@@ -60,6 +60,141 @@ __device__ __forceinline__ double d_elem(bool contig, const double* Wv, const do
     return Vb[min(cell + j, nx - 1)] - Vb[max(cell - j, 0)];
 }
 
+// Creation tables written straight from the kernel rows (the TAB form of kernel_eval_f64).
+struct TabOut {
+    double dt;
+    double* gamma;
+    uint32_t* n0;
+    uint32_t* thr;
+    uint64_t* cdf;
+    uint32_t* guide;  // NULL: no guide table
+    int G;            // guide buckets
+};
+
+constexpr int TAB_GMAX = 256;  // guide buckets the fused epilogue supports
+
+// Creation tables of eq.(1) from a workgroup's finished rows, which never leave the chip.
+// The rows are staged 8 (x WAVES_M) at a time in LDS as full rows, entry t <-> m = t - P,
+// with the values the kernel would have written (K(m) = c (O + E), K(P - m) = c (O - E),
+// K(-m) = -K(m), K(0) = K(-P) = 0); then exactly the arithmetic of the table kernels: one
+// lane per row sums the positive part in ascending m in FP64 (the order is the definition)
+// and leaves the running sums in place, every lane converts them to the integer CDF, and
+// (optionally) each bucket of the guide table is found by binary search over the CDF row.
+// One column block must hold every m of a row (H <= BN).
+template <int WM, int WN, int WAVES_N>
+__device__ __forceinline__ void tab_epilogue(const f64x4 (&acc)[2][WM][WN], double* lds, long row0,
+                                             long R, int P, int n_m, int H, double c,
+                                             const TabOut& tb) {
+    constexpr int WAVES_M = 4 / WAVES_N;
+    constexpr int SR = 8 * WAVES_M;  // staged rows per round
+    __shared__ int last_s[SR];
+    __shared__ uint64_t Lg[TAB_GMAX];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave / WAVES_N, wc = wave % WAVES_N;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int SW = n_m + 1;  // odd row stride: the per-row lanes of the prefix hit distinct banks
+    for (int k = threadIdx.x; k < tb.G; k += KE_THREADS) Lg[k] = ((uint64_t)k << 32) / (uint64_t)tb.G;
+#pragma unroll
+    for (int tm = 0; tm < WM; ++tm) {
+#pragma unroll
+        for (int eh = 0; eh < 2; ++eh) {
+            __syncthreads();  // the previous round (or the contraction) is done with the LDS
+            // staged row q = wr * 8 + lk + 4 ee holds tile row 8 eh + lk + 4 ee of wave row wr
+#pragma unroll
+            for (int tn = 0; tn < WN; ++tn) {
+                const int t = (wc * WN + tn) * 16 + lr, m = t + 1;
+#pragma unroll
+                for (int ee = 0; ee < 2; ++ee) {
+                    double* srow = lds + (wr * 8 + lk + 4 * ee) * SW;
+                    if (t < H) {
+                        const int e = 2 * eh + ee;
+                        const double o = acc[0][tm][tn][e], ev = acc[1][tm][tn][e];
+                        const double kp = c * (o + ev), km = c * (o - ev);
+                        srow[P + m] = kp;
+                        srow[P - m] = -kp;
+                        if (2 * m < P) {
+                            srow[2 * P - m] = km;
+                            srow[m] = -km;
+                        }
+                    }
+                    if (t == 0) {
+                        srow[0] = 0.0;
+                        srow[P] = 0.0;
+                    }
+                }
+            }
+            __syncthreads();
+            auto grow = [&](int q) -> long {  // table row of staged row q
+                return row0 + ((q >> 3) * WM + tm) * 16 + 8 * eh + (q & 7);
+            };
+            if (threadIdx.x < SR) {
+                const int q = threadIdx.x;
+                double* srow = lds + q * SW;
+                double C = 0.0;
+                int last = -1;
+                for (int t = 0; t < n_m; ++t) {
+                    const double k = srow[t];
+                    if (k > 0.0) {
+                        C = C + k;
+                        last = t;
+                    }
+                    srow[t] = C;
+                }
+                last_s[q] = last;
+                const long row = grow(q);
+                if (row < R) {
+                    const double p = C * tb.dt;
+                    const double fl = floor(p);
+                    tb.gamma[row] = C;
+                    tb.n0[row] = (uint32_t)fl;
+                    tb.thr[row] = (uint32_t)floor((p - fl) * 4294967296.0);
+                }
+            }
+            __syncthreads();
+            // rows to waves, entries to lanes; each lane converts its own entries in place
+            for (int q = wave; q < SR; q += KE_THREADS / 64) {
+                const long row = grow(q);
+                double* srow = lds + q * SW;
+                const int last = last_s[q];
+                const double g = last >= 0 ? srow[last] : 0.0;
+                uint64_t* crow = tb.cdf + row * n_m;
+                for (int t = lane; t < n_m; t += 64) {
+                    uint64_t v;
+                    if (last < 0)
+                        v = 0;
+                    else if (t >= last)
+                        v = 1ull << 32;
+                    else
+                        v = (uint64_t)floor(srow[t] / g * 4294967296.0);
+                    if (row < R) crow[t] = v;
+                    reinterpret_cast<uint64_t*>(srow)[t] = v;
+                }
+            }
+            if (tb.guide == nullptr) continue;
+            __syncthreads();
+            for (int q = wave; q < SR; q += KE_THREADS / 64) {
+                const long row = grow(q);
+                if (row >= R) continue;
+                const uint64_t* T = reinterpret_cast<const uint64_t*>(lds + q * SW);
+                uint32_t* gout = tb.guide + row * (tb.G + 1);
+                for (int k = lane; k < tb.G; k += 64) {
+                    const uint64_t L = Lg[k];
+                    int lo = 0, hi = n_m - 1;  // first t with T[t] > L, at most n_m - 1
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (T[mid] > L)
+                            hi = mid;
+                        else
+                            lo = mid + 1;
+                    }
+                    gout[k] = (uint32_t)lo;
+                }
+                if (lane == 0) gout[tb.G] = (uint32_t)(n_m - 1);
+            }
+        }
+    }
+}
+
 // FP64 path: v_mfma_f64_16x16x4_f64 on the folded sum.  With n_m = 2P the sine of eq.(4)
 // obeys sin(2 pi j (P - m) / n_m) = -(-1)^j sin(2 pi j m / n_m), so splitting the sum over j
 // into odd and even terms gives, for m = t + 1 <= H = floor(P / 2),
@@ -73,11 +208,11 @@ __device__ __forceinline__ double d_elem(bool contig, const double* Wv, const do
 // A[l % 16][l / 16], B[l / 16][l % 16], and C[l / 16 + 4 e][l % 16], e < 4.  The odd and even
 // D tiles are double-buffered in LDS; the next chunk's tiles are built in four slices between
 // the current chunk's sub-steps, and its sine fragments are loaded one chunk ahead.
-template <int WM, int WN, int WAVES_N>
+template <int WM, int WN, int WAVES_N, bool TAB = false>
 __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
     const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
     int P, int n_m, int H, int Hk, int Hn, const double* __restrict__ So,
-    const double* __restrict__ Se, double c, int layout, double* __restrict__ out) {
+    const double* __restrict__ Se, double c, int layout, double* __restrict__ out, TabOut tb) {
     constexpr int WAVES_M = 4 / WAVES_N;
     constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N, BK = KE_BK;
     static_assert(BM <= KE_BM, "row tile");
@@ -190,6 +325,10 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
         buf ^= 1;
     }
 
+    if constexpr (TAB) {
+        tab_epilogue<WM, WN, WAVES_N>(acc, &Ds[0][0][0][0], row0, R, P, n_m, H, c, tb);
+        return;
+    }
 #pragma unroll
     for (int tm = 0; tm < WM; ++tm) {
 #pragma unroll
@@ -527,7 +666,7 @@ int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_
     dim3 grid((unsigned)((R + BM - 1) / BM), (unsigned)(Hn / BN));
 #define KE_LAUNCH_F64(WM, WN, WNV)                                                              \
     WK_LAUNCH("kernel_eval_f64", (kernel_eval_f64<WM, WN, WNV>), grid, dim3(KE_THREADS), 0, stream, V, \
-                       mesh->nx, R, n_cells, cells, P, n_m, H, Hk, Hn, So, Se, c, layout, out)
+                       mesh->nx, R, n_cells, cells, P, n_m, H, Hk, Hn, So, Se, c, layout, out, TabOut{})
     if (cfg == CFG_LARGE)
         KE_LAUNCH_F64(4, 2, 4);
     else if (cfg == CFG_MID)
@@ -536,6 +675,42 @@ int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_
         KE_LAUNCH_F64(2, 1, 2);
 #undef KE_LAUNCH_F64
     return check_launch("kernel_eval_f64");
+}
+
+// eq.(4) rows straight into the creation tables (the TAB form of kernel_eval_f64): one column
+// block must cover every m (H <= 128, n_m <= 514) and a round of staged rows must fit the
+// operand tiles' LDS.
+int kernel_tables_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_t* cells,
+                         int n_cells, const TabOut& tb, hipStream_t stream) {
+    const int n_m = mesh->n_m, P = n_m / 2, H = P / 2;
+    const long R = (long)B * n_cells;
+    if (R == 0) return WK_OK;
+    WK_REQUIRE(n_m >= 4 && H <= 128, "wk_kernel_tables: n_m must lie in [4, 514]");
+    WK_REQUIRE(tb.guide == nullptr || (tb.G >= 1 && tb.G <= TAB_GMAX),
+               "wk_kernel_tables: guide_len must lie in [1, 256]");
+    const int cfg = fold_cfg(H), BN = fold_bn(cfg), BM = fold_bm(cfg);
+    const int waves_m = cfg == CFG_SMALL ? 2 : 1;
+    WK_REQUIRE(8 * waves_m * (n_m + 1) <= 2 * 2 * BM * (KE_BK + 1), "wk_kernel_tables: row stage exceeds LDS");
+    const int Hk = round_up(H, KE_BK), Hn = round_up(H, BN);
+    int err = WK_OK;
+    const double* So = static_cast<const double*>(sine_table(n_m, SINE_ODD, Hk, Hn, stream, &err));
+    if (!So) return err;
+    const double* Se = static_cast<const double*>(sine_table(n_m, SINE_EVEN, Hk, Hn, stream, &err));
+    if (!Se) return err;
+    const double c = -2.0 / (mesh->hbar * (double)n_m);
+    dim3 grid((unsigned)((R + BM - 1) / BM), 1);
+#define KT_LAUNCH_F64(WM, WN, WNV)                                                                 \
+    WK_LAUNCH("kernel_tables_f64", (kernel_eval_f64<WM, WN, WNV, true>), grid, dim3(KE_THREADS), 0, \
+              stream, V, mesh->nx, R, n_cells, cells, P, n_m, H, Hk, Hn, So, Se, c, WK_HALF,       \
+              (double*)nullptr, tb)
+    if (cfg == CFG_LARGE)
+        KT_LAUNCH_F64(4, 2, 4);
+    else if (cfg == CFG_MID)
+        KT_LAUNCH_F64(4, 1, 4);
+    else
+        KT_LAUNCH_F64(2, 1, 2);
+#undef KT_LAUNCH_F64
+    return check_launch("kernel_tables_f64");
 }
 
 // 16-bit fold tiles by H: 64 x 128 blocks of 64 x 32 wave tiles (both parts) for H > 64,
@@ -635,6 +810,25 @@ extern "C" int wk_kernel_eval(const wk_mesh* mesh, const double* V, int32_t B,
     WK_REQUIRE(layout == WK_FULL, "wk_kernel_eval: 2-D tables are full");
     return wk::kernel_eval_2d(mesh, V, B, cells, n_cells, static_cast<double*>(K_out),
                               wk::as_stream(stream));
+}
+
+extern "C" int wk_kernel_tables(const wk_mesh* mesh, const double* V, int32_t B,
+                                const int32_t* cells, int32_t n_cells, double dt, double* gamma,
+                                uint32_t* n0, uint32_t* thr, uint64_t* cdf, uint32_t* guide,
+                                int32_t guide_len, void* stream) {
+    WK_REQUIRE(mesh != nullptr, "wk_kernel_tables: mesh is NULL");
+    WK_REQUIRE(mesh->dim == 1 && mesh->ny == 1, "wk_kernel_tables: 1-D meshes only");
+    WK_REQUIRE(mesh->nx > 0, "wk_kernel_tables: empty mesh");
+    WK_REQUIRE(mesh->n_m >= 2 && (mesh->n_m % 2) == 0, "wk_kernel_tables: n_m must be even and >= 2");
+    WK_REQUIRE(mesh->hbar > 0.0, "wk_kernel_tables: hbar must be positive");
+    WK_REQUIRE(B >= 0 && n_cells >= 0, "wk_kernel_tables: negative size");
+    WK_REQUIRE(dt >= 0.0, "wk_kernel_tables: dt must be >= 0");
+    if ((long)B * n_cells == 0) return WK_OK;
+    WK_REQUIRE(cells != nullptr || n_cells == mesh->nx,
+               "wk_kernel_tables: with cells == NULL, n_cells must be the number of cells");
+    WK_REQUIRE(V && gamma && n0 && thr && cdf, "wk_kernel_tables: NULL array");
+    const wk::TabOut tb{dt, gamma, n0, thr, cdf, guide, guide ? (int)guide_len : 0};
+    return wk::kernel_tables_1d_f64(mesh, V, B, cells, n_cells, tb, wk::as_stream(stream));
 }
 
 // ----------------------------------------------------------------------------- adjoint

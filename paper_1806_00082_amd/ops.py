@@ -98,6 +98,39 @@ def gamma_tables(K: torch.Tensor, n_m: int, dt: float, dim: int = 1, layout: str
     return g, n0, thr, cdf
 
 
+def kernel_tables(V: torch.Tensor, n_m: int, dt: float, cells: torch.Tensor | None = None,
+                  guide_len: int = 0, hbar: float = HBAR_EVFS, out=None):
+    """eq.(4) rows of the requested cells turned straight into the creation tables (the rows
+    stay on chip).  1-D, FP64.  Returns (gamma, n0, thr, cdf, guide or None) as gamma_tables
+    and sampling_guide would; `out` may supply those five tensors (row slices are fine)."""
+    _need_cuda(V, cells)
+    if V.dim() == 1:
+        V = V[None]
+    assert V.dim() == 2 and V.dtype == torch.float64, "1-D FP64 potentials [B][nx]"
+    V = V.contiguous()
+    B, nx = V.shape
+    n_cells = nx if cells is None else int(cells.numel())
+    if cells is not None:
+        cells = cells.to(torch.int32).contiguous()
+    R = B * n_cells
+    dev = V.device
+    if out is None:
+        out = (torch.empty(R, dtype=torch.float64, device=dev), torch.empty(R, dtype=torch.int32, device=dev),
+               torch.empty(R, dtype=torch.int32, device=dev), torch.empty((R, n_m), dtype=torch.int64, device=dev),
+               torch.empty((R, guide_len + 1), dtype=torch.int32, device=dev) if guide_len else None)
+    g, n0, thr, cdf, guide = out
+    for t, shape in ((g, (R,)), (n0, (R,)), (thr, (R,)), (cdf, (R, n_m))):
+        if tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"kernel_tables: output of shape {tuple(t.shape)}, expected {shape}")
+    if guide is not None and (tuple(guide.shape) != (R, guide_len + 1) or not guide.is_contiguous()):
+        raise ValueError("kernel_tables: guide must be a contiguous [rows][guide_len + 1] tensor")
+    m = mesh_struct(1, nx, 1, n_m, hbar)
+    L.check(L.lib().wk_kernel_tables(ctypes.byref(m), _ptr(V), B, _ptr(cells), n_cells, float(dt),
+                                     _ptr(g), _ptr(n0), _ptr(thr), _ptr(cdf), _ptr(guide),
+                                     guide_len if guide is not None else 0, _stream()), "wk_kernel_tables")
+    return g, n0, thr, cdf, guide
+
+
 # ----------------------------------------------------------------------------- particles
 def geom_struct(mesh: dict, seed: int, m16: bool = False) -> L.SpGeom:
     """m16: 1-D particle buffers hold int16 momenta (2-D momenta are always int16)."""

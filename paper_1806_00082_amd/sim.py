@@ -2,8 +2,9 @@
 library's kernels, no computation in Python.
 
 Per step: (every `refresh_every` steps) kernel rows for newly occupied cells -> creation
-tables; sp_step (creation at rate gamma, drift, absorbing boundaries, and the signed
-histogram of rule 1 of the result); sp_annihilate (rule 2 on that histogram).  The particle
+tables (one fused pass for exact FP64 rows in 1-D, the rows staying on chip); sp_step
+(creation at rate gamma, drift, absorbing boundaries, and the signed histogram of rule 1 of
+the result); sp_annihilate (rule 2 on that histogram).  The particle
 count stays in device memory; the host synchronises only to size the occasional kernel-row
 refresh and to read statistics.
 
@@ -28,7 +29,8 @@ from . import learn, ops
 class Simulator:
     def __init__(self, cfg, kernel: str = "exact", prec: str = "fp64", mode: str = "occupied",
                  refresh_every: int = 8, cap_factor: float = 3.0, weights=None, N: int = 2,
-                 device="cuda", hist_in_step: bool = True, rows=None, m16=None):
+                 device="cuda", hist_in_step: bool = True, rows=None, m16=None,
+                 fused_tables: bool = True):
         self.cfg = cfg
         self.md = cfg.mesh.as_dict(cfg.dt)
         md = self.md
@@ -54,7 +56,13 @@ class Simulator:
         self.cdf = torch.zeros((self.n_cells, self.width), dtype=torch.int64, device=self.dev)
         self.glen = min(self.width, 256)                # guide buckets for the CDF search
         self.guide = torch.zeros((self.n_cells, self.glen + 1), dtype=torch.int32, device=self.dev)
-        if kernel == "given":
+        # exact FP64 rows in 1-D go straight into the creation tables (wk_kernel_tables): the
+        # kernel rows then never exist in device memory
+        self.fused = (fused_tables and kernel == "exact" and prec == "fp64" and self.dim == 1
+                      and 4 <= self.n_m <= 514)
+        if self.fused:
+            self.Kbuf = None
+        elif kernel == "given":
             if mode != "all":
                 raise ValueError("given kernel rows need mode='all'")
             if (rows is None or rows.device.type != self.dev.type or rows.dtype not in (torch.float64, torch.float32)
@@ -97,6 +105,13 @@ class Simulator:
         """Kernel rows + creation tables for `count` cells, appended at row self.n_rows."""
         if count == 0:
             return
+        r0 = self.n_rows
+        if self.fused:
+            ops.kernel_tables(self.V, self.n_m, float(self.cfg.dt), cells=cells[:count], guide_len=self.glen,
+                              out=(self.gamma[r0:r0 + count], self.n0[r0:r0 + count], self.thr[r0:r0 + count],
+                                   self.cdf[r0:r0 + count], self.guide[r0:r0 + count]))
+            self.n_rows += count
+            return
         K = self.Kbuf[:count]
         if self.kernel == "given":
             pass                                        # rows already in place (all cells)
@@ -107,7 +122,6 @@ class Simulator:
             wV, wT, W = self.weights
             learn.surrogate_fwd(self.V, self.n_m, self.N, wV, wT, W, cells=cells[:count],
                                 prec=self.prec if self.prec in ("fp64", "bf16") else "fp32", out=K)
-        r0 = self.n_rows
         m = ops.mesh_struct(self.dim, 1, 1, self.n_m)
         L.check(L.lib().wk_gamma_tables(
             ctypes.byref(m), ops._ptr(K), int(K.dtype == torch.float64),

@@ -126,6 +126,63 @@ def test_gamma_tables_2d(orc):
     assert np.array_equal(as_u64(cdf), ref[3])
 
 
+# (nx, n_m, B, with cell list, guide_len): every tile shape of the fused form (H = P / 2 in
+# the small, middle and large ranges, odd and even P), ragged row counts, cell lists, batches
+KT_CASES = [(37, 4, 1, False, 0), (50, 6, 2, True, 3), (300, 80, 1, False, 80), (129, 130, 2, True, 130),
+            (70, 132, 1, False, 256), (200, 256, 3, True, 256), (65, 258, 1, False, 7),
+            (130, 512, 1, True, 256), (64, 514, 2, False, 1)]
+
+
+@pytest.mark.parametrize("nx,n_m,B,use_cells,glen", KT_CASES)
+def test_kernel_tables_equals_two_step(nx, n_m, B, use_cells, glen):
+    """The fused rows -> tables pass equals kernel_eval (FP64) + gamma_tables + sampling_guide
+    on the GPU, bit for bit (the same kernel values meet the same table arithmetic)."""
+    V = torch.from_numpy(inputs.random_potentials(B, nx, 0.5, seed=nx + n_m)).to(dev())
+    cells = None
+    if use_cells:
+        rng = np.random.default_rng(n_m)
+        cells = torch.from_numpy(rng.permutation(nx)[: max(1, 2 * nx // 3)].astype(np.int32)).to(dev())
+    dt = 0.9
+    g, n0, thr, cdf, guide = ops.kernel_tables(V, n_m, dt, cells=cells, guide_len=glen)
+    K = ops.kernel_eval(V, n_m, cells=cells, layout="half")
+    g2, n02, thr2, cdf2 = ops.gamma_tables(K, n_m, dt, layout="half")
+    assert torch.equal(g, g2) and torch.equal(n0, n02) and torch.equal(thr, thr2)
+    assert torch.equal(cdf, cdf2)
+    if glen:
+        assert torch.equal(guide, ops.sampling_guide(cdf2, glen))
+    else:
+        assert guide is None
+
+
+@pytest.mark.parametrize("nx,n_m", [(300, 80), (200, 256), (100, 512)])
+def test_kernel_tables_vs_oracle(orc, nx, n_m):
+    """Against the oracle's tables from the oracle's rows: gamma within the eq.(4) tolerance
+    carried through the sum, and the CDF (as a probability) within that error over gamma."""
+    V = inputs.random_potentials(2, nx, 0.5, seed=n_m)
+    dt = 0.5
+    g, n0, thr, cdf, _ = ops.kernel_tables(torch.from_numpy(V).to(dev()), n_m, dt)
+    Kf = orc.kernel_1d(V, n_m, HB).reshape(-1, n_m)
+    rg, rn0, rthr, rcdf = orc.gamma_tables(Kf, dt)
+    kmax = np.abs(Kf).max(axis=1)
+    dg = n_m * FP64_TOL * kmax                       # |gamma error| bound per row
+    got_g = to_np(g)
+    assert np.all(np.abs(got_g - rg) <= dg)
+    p_err = np.abs(as_u64(cdf).astype(np.float64) - rcdf.astype(np.float64)) / 2.0 ** 32
+    bound = np.where(rg > 0, 2 * dg / np.maximum(rg, 1e-300), 0.0)[:, None] + 2.0 ** -31
+    assert np.all(p_err <= bound)
+    # creation probabilities per step: n0 + thr 2^-32 within dt times the gamma bound
+    rate = to_np(n0).view(np.uint32) + as_u32(thr) / 2.0 ** 32
+    rrate = rn0 + rthr / 2.0 ** 32
+    assert np.all(np.abs(rate - rrate) <= dt * dg + 2.0 ** -31)
+
+
+@pytest.mark.parametrize("n_m,glen", [(2, 0), (516, 0), (80, 257)])
+def test_kernel_tables_refuses_out_of_range(n_m, glen):
+    V = torch.zeros((1, 16), dtype=torch.float64, device=dev())
+    with pytest.raises(RuntimeError):
+        ops.kernel_tables(V, n_m, 1.0, guide_len=glen)
+
+
 @pytest.mark.parametrize("glen", [1, 7, 80, 256])
 def test_sampling_guide_definition(orc, glen):
     """guide[k] = min{t : cdf[t] > floor(k 2^32 / G)} (capped at width - 1), guide[G] =

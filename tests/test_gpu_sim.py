@@ -82,7 +82,7 @@ def test_simulator_rows_and_rates_match_oracle(orc, prec, tol):
     """The simulator's own kernel rows (eq.(4) on the GPU) against the oracle's, normwise, and
     the creation rates built from them against the oracle's rates from its own rows."""
     cfg = inputs.config_c1()
-    sim = Simulator(cfg, mode="all", prec=prec)
+    sim = Simulator(cfg, mode="all", prec=prec, fused_tables=False)
     Kf = orc.kernel_1d(cfg.V, cfg.mesh.n_m, HB)[0]
     got = to_np(sim.Kbuf).astype(np.float64)
     ref = orc.full_to_half(Kf)
@@ -90,6 +90,27 @@ def test_simulator_rows_and_rates_match_oracle(orc, prec, tol):
     g = orc.gamma_tables(Kf, cfg.dt)[0]
     # gamma sums n_m rows entries of size <= max|K|: the row error bound carries over
     assert np.abs(to_np(sim.gamma) - g).max() <= cfg.mesh.n_m * tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("mode", ["all", "occupied"])
+def test_fused_tables_simulator_equals_two_step(mode):
+    """Rows straight into the creation tables (kernel rows never in device memory) give the
+    same tables and, step for step, the same particles as rows -> tables in two passes."""
+    cfg = inputs.config_c2(N0=2e5)
+    fused = Simulator(cfg, mode=mode)
+    two = Simulator(cfg, mode=mode, fused_tables=False)
+    assert fused.fused and not two.fused
+    for k in range(12):
+        fused.step()
+        two.step()
+        n = fused.count()
+        assert n == two.count(), k
+        for f in ("x", "M", "s"):
+            assert torch.equal(getattr(fused.a, f)[:n], getattr(two.a, f)[:n]), (k, f)
+    r = fused.n_rows
+    assert r == two.n_rows
+    for f in ("gamma", "n0", "thr", "cdf", "guide"):
+        assert torch.equal(getattr(fused, f)[:r], getattr(two, f)[:r]), f
 
 
 def test_2d_simulator_equals_oracle_loop(orc):
