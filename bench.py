@@ -242,16 +242,17 @@ def run_learning(B=64, N=4, reps=5):
     return out
 
 
-def run_2d(steps=40, warmup=8):
+def run_2d(steps=40, warmup=8, fused_tables=True):
     """The 2-D workload: 256 x 256 cells of 0.5 nm, 32 x 32 momenta, 5e7 particles, exact FP64
-    kernel rows formed near occupied cells (refreshed every 8 steps), annihilation every step."""
+    kernel rows formed near occupied cells (refreshed every 8 steps) straight into the creation
+    tables, annihilation every step."""
     import torch
     from paper_1806_00082_amd import _lib as L
     from paper_1806_00082_amd import inputs
     from paper_1806_00082_amd.sim import Simulator
 
     cfg = inputs.config_c5()
-    sim = Simulator(cfg)
+    sim = Simulator(cfg, fused_tables=fused_tables)
     sim.run(warmup)
     torch.cuda.synchronize()
     sim.stats[L.ST_CUM_STEPS:L.ST_COUNT].zero_()
@@ -265,7 +266,8 @@ def run_2d(steps=40, warmup=8):
     out = {"workload": "2-D: 256x256 cells, 32x32 m, 5e7 particles, exact fp64 rows near occupied cells",
            "steps": steps, "ms_per_step": round(ms / steps, 4),
            "particle_steps_per_s": S[L.ST_CUM_N] / (ms * 1e-3), "n_last": sim.count(),
-           "kernel_rows": sim.n_rows}
+           "kernel_rows": sim.n_rows,
+           "kernel_row_table_MB": 0.0 if sim.fused else round(sim.Kbuf.numel() * sim.Kbuf.element_size() / 1e6, 1)}
     del sim
     torch.cuda.empty_cache()
     return out

@@ -189,14 +189,16 @@ int wk_sampling_guide(const uint64_t* cdf, int32_t n_rows, int32_t width, int32_
 
 /* wk_kernel_tables -- eq.(4) on the requested cells and, from those rows, the creation tables
  * of eq.(1) and postulate II in one pass: the kernel rows exist only on chip, never in
- * device memory (the paper's point that the kernel need not be stored, Sec. 2.2).  1-D,
- * FP64.  The results are bit-identical to wk_kernel_eval (WK_FP64) followed by
- * wk_gamma_tables and wk_sampling_guide on the same rows.
+ * device memory (the paper's point that the kernel need not be stored, Sec. 2.2).  FP64,
+ * 1-D and 2-D.  The results are bit-identical to wk_kernel_eval (WK_FP64, any layout)
+ * followed by wk_gamma_tables and wk_sampling_guide on the same rows.
  *   V, B, cells, n_cells  as wk_kernel_eval; rows r = b * n_cells + i.
  *   dt     time step in fs (p = gamma dt).
- *   gamma  [R] double, n0/thr [R] uint32, cdf [R][n_m] uint64, as wk_gamma_tables.
+ *   gamma  [R] double, n0/thr [R] uint32, cdf [R][width] uint64 (width = n_m in 1-D,
+ *          n_m^2 in 2-D), as wk_gamma_tables.
  *   guide  NULL, or [R][guide_len + 1] uint32 as wk_sampling_guide, 1 <= guide_len <= 256.
- * Limits: 4 <= n_m <= 514 (WK_EINVAL otherwise: use the two-step form). */
+ * Limits: 1-D 4 <= n_m <= 514, 2-D n_m in {8, 16, 32} (WK_EINVAL otherwise: use the
+ * two-step form). */
 int wk_kernel_tables(const wk_mesh* mesh, const double* V, int32_t B, const int32_t* cells,
                      int32_t n_cells, double dt, double* gamma, uint32_t* n0, uint32_t* thr,
                      uint64_t* cdf, uint32_t* guide, int32_t guide_len, void* stream);

@@ -778,6 +778,8 @@ int kernel_eval_1d_lowp(const wk_mesh* mesh, const double* V, int B, const int32
 }
 int kernel_eval_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
                    double* out, hipStream_t stream);
+int kernel_tables_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
+                     const TabOut& tb, hipStream_t stream);
 
 }  // namespace wk
 
@@ -817,17 +819,19 @@ extern "C" int wk_kernel_tables(const wk_mesh* mesh, const double* V, int32_t B,
                                 uint32_t* n0, uint32_t* thr, uint64_t* cdf, uint32_t* guide,
                                 int32_t guide_len, void* stream) {
     WK_REQUIRE(mesh != nullptr, "wk_kernel_tables: mesh is NULL");
-    WK_REQUIRE(mesh->dim == 1 && mesh->ny == 1, "wk_kernel_tables: 1-D meshes only");
-    WK_REQUIRE(mesh->nx > 0, "wk_kernel_tables: empty mesh");
+    WK_REQUIRE((mesh->dim == 1 && mesh->ny == 1) || mesh->dim == 2, "wk_kernel_tables: bad mesh");
+    WK_REQUIRE(mesh->nx > 0 && mesh->ny > 0, "wk_kernel_tables: empty mesh");
     WK_REQUIRE(mesh->n_m >= 2 && (mesh->n_m % 2) == 0, "wk_kernel_tables: n_m must be even and >= 2");
     WK_REQUIRE(mesh->hbar > 0.0, "wk_kernel_tables: hbar must be positive");
     WK_REQUIRE(B >= 0 && n_cells >= 0, "wk_kernel_tables: negative size");
     WK_REQUIRE(dt >= 0.0, "wk_kernel_tables: dt must be >= 0");
     if ((long)B * n_cells == 0) return WK_OK;
-    WK_REQUIRE(cells != nullptr || n_cells == mesh->nx,
+    WK_REQUIRE(cells != nullptr || n_cells == (long)mesh->nx * mesh->ny,
                "wk_kernel_tables: with cells == NULL, n_cells must be the number of cells");
     WK_REQUIRE(V && gamma && n0 && thr && cdf, "wk_kernel_tables: NULL array");
     const wk::TabOut tb{dt, gamma, n0, thr, cdf, guide, guide ? (int)guide_len : 0};
+    if (mesh->dim == 2)
+        return wk::kernel_tables_2d(mesh, V, B, cells, n_cells, tb, wk::as_stream(stream));
     return wk::kernel_tables_1d_f64(mesh, V, B, cells, n_cells, tb, wk::as_stream(stream));
 }
 
@@ -1075,10 +1079,10 @@ namespace wk {
 
 __device__ __forceinline__ double w_end(int j, int P) { return (j == P || j == -P) ? 0.5 : 1.0; }
 
-template <int P>
+template <int P, bool TAB = false>
 __global__ __launch_bounds__(KE_THREADS) void kernel_eval_2d_f64(
     const double* __restrict__ V, int nx, int ny, long R, int n_cells,
-    const int32_t* __restrict__ cells, double c2, double* __restrict__ out) {
+    const int32_t* __restrict__ cells, double c2, double* __restrict__ out, TabOut tb) {
     constexpr int J = 2 * P + 1;                       // offsets per axis
     constexpr int M1 = (J + 15) / 16 * 16;             // stage-1 rows (jy), padded
     constexpr int K1 = (J + 3) / 4 * 4;                // stage-1 depth (jx), padded
@@ -1191,39 +1195,117 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_2d_f64(
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[ks], bv, acc, 0, 0, 0);
             }
             const int mx_i = tn2 * 16 + lr;
-            double* o = out + r * (long)n_m * n_m;
+            // TAB: the row stays on chip, in the stage-1 operand tile (free after stage 1)
+            double* o = TAB ? &Ds[0][0] : out + r * (long)n_m * n_m;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int my_i = tm2 * 16 + lk + 4 * e;
                 if (my_i < 2 * P && mx_i < 2 * P) o[my_i * n_m + mx_i] = c2 * acc[e];
             }
         }
+        if constexpr (TAB) {
+            static_assert(M1 * (K1 + 1) >= 4 * P * P, "2-D row stage");
+            __shared__ int last_s;
+            constexpr int W = 4 * P * P;  // entries per row, t = (my + P) n_m + (mx + P)
+            double* Kr = &Ds[0][0];
+            __syncthreads();
+            // the arithmetic of the table kernels: ascending positive sums by one thread (the
+            // order is the definition), then every thread converts its entries
+            if (threadIdx.x == 0) {
+                double C = 0.0;
+                int last = -1;
+                for (int t = 0; t < W; ++t) {
+                    const double k = Kr[t];
+                    if (k > 0.0) {
+                        C = C + k;
+                        last = t;
+                    }
+                    Kr[t] = C;
+                }
+                last_s = last;
+                const double p = C * tb.dt;
+                const double fl = floor(p);
+                tb.gamma[r] = C;
+                tb.n0[r] = (uint32_t)fl;
+                tb.thr[r] = (uint32_t)floor((p - fl) * 4294967296.0);
+            }
+            __syncthreads();
+            const int last = last_s;
+            const double g = last >= 0 ? Kr[last] : 0.0;
+            __syncthreads();  // every thread has read Kr[last] before entries are overwritten
+            uint64_t* crow = tb.cdf + r * W;
+            for (int t = threadIdx.x; t < W; t += KE_THREADS) {
+                uint64_t v;
+                if (last < 0)
+                    v = 0;
+                else if (t >= last)
+                    v = 1ull << 32;
+                else
+                    v = (uint64_t)floor(Kr[t] / g * 4294967296.0);
+                crow[t] = v;
+                reinterpret_cast<uint64_t*>(Kr)[t] = v;
+            }
+            if (tb.guide != nullptr) {
+                __syncthreads();
+                const uint64_t* T = reinterpret_cast<const uint64_t*>(Kr);
+                uint32_t* gout = tb.guide + r * (tb.G + 1);
+                for (int k = threadIdx.x; k < tb.G; k += KE_THREADS) {
+                    const uint64_t L = ((uint64_t)k << 32) / (uint64_t)tb.G;
+                    int lo = 0, hi = W - 1;  // first t with T[t] > L, at most W - 1
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (T[mid] > L)
+                            hi = mid;
+                        else
+                            lo = mid + 1;
+                    }
+                    gout[k] = (uint32_t)lo;
+                }
+                if (threadIdx.x == 0) gout[tb.G] = (uint32_t)(W - 1);
+            }
+        }
     }
 }
 
-int kernel_eval_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
-                   double* out, hipStream_t stream) {
+// d = 2 rows, written out (TAB = false) or turned into the creation tables on chip (TAB).
+template <bool TAB>
+static int launch_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
+                     double* out, const TabOut& tb, hipStream_t stream) {
     const long R = (long)B * n_cells;
     if (R == 0) return WK_OK;
     const double c2 = -1.0 / (mesh->hbar * (double)mesh->n_m * (double)mesh->n_m);
     const unsigned grid = (unsigned)(R < 4096 ? R : 4096);
+    const char* name = TAB ? "kernel_tables_2d_f64" : "kernel_eval_2d_f64";
     switch (mesh->n_m) {
         case 8:
-            WK_LAUNCH("kernel_eval_2d_f64", kernel_eval_2d_f64<4>, dim3(grid), dim3(KE_THREADS), 0, stream,
-                      V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            WK_LAUNCH(name, (kernel_eval_2d_f64<4, TAB>), dim3(grid), dim3(KE_THREADS), 0, stream,
+                      V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out, tb);
             break;
         case 16:
-            WK_LAUNCH("kernel_eval_2d_f64", kernel_eval_2d_f64<8>, dim3(grid), dim3(KE_THREADS), 0, stream,
-                      V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            WK_LAUNCH(name, (kernel_eval_2d_f64<8, TAB>), dim3(grid), dim3(KE_THREADS), 0, stream,
+                      V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out, tb);
             break;
         case 32:
-            WK_LAUNCH("kernel_eval_2d_f64", kernel_eval_2d_f64<16>, dim3(grid), dim3(KE_THREADS), 0, stream,
-                      V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            WK_LAUNCH(name, (kernel_eval_2d_f64<16, TAB>), dim3(grid), dim3(KE_THREADS), 0, stream,
+                      V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out, tb);
             break;
         default:
-            return fail(WK_EINVAL, "wk_kernel_eval: 2-D supports n_m = 8, 16 and 32");
+            return fail(WK_EINVAL, TAB ? "wk_kernel_tables: 2-D supports n_m = 8, 16 and 32"
+                                       : "wk_kernel_eval: 2-D supports n_m = 8, 16 and 32");
     }
-    return check_launch("kernel_eval_2d_f64");
+    return check_launch(name);
+}
+
+int kernel_eval_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
+                   double* out, hipStream_t stream) {
+    return launch_2d<false>(mesh, V, B, cells, n_cells, out, TabOut{}, stream);
+}
+
+int kernel_tables_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
+                     const TabOut& tb, hipStream_t stream) {
+    WK_REQUIRE(tb.guide == nullptr || (tb.G >= 1 && tb.G <= TAB_GMAX),
+               "wk_kernel_tables: guide_len must lie in [1, 256]");
+    return launch_2d<true>(mesh, V, B, cells, n_cells, nullptr, tb, stream);
 }
 
 }  // namespace wk

@@ -101,30 +101,34 @@ def gamma_tables(K: torch.Tensor, n_m: int, dt: float, dim: int = 1, layout: str
 def kernel_tables(V: torch.Tensor, n_m: int, dt: float, cells: torch.Tensor | None = None,
                   guide_len: int = 0, hbar: float = HBAR_EVFS, out=None):
     """eq.(4) rows of the requested cells turned straight into the creation tables (the rows
-    stay on chip).  1-D, FP64.  Returns (gamma, n0, thr, cdf, guide or None) as gamma_tables
-    and sampling_guide would; `out` may supply those five tensors (row slices are fine)."""
+    stay on chip).  FP64; V [B][nx] (1-D) or [B][ny][nx] (2-D).  Returns (gamma, n0, thr, cdf,
+    guide or None) as gamma_tables and sampling_guide would; `out` may supply those five
+    tensors (row slices are fine)."""
     _need_cuda(V, cells)
     if V.dim() == 1:
         V = V[None]
-    assert V.dim() == 2 and V.dtype == torch.float64, "1-D FP64 potentials [B][nx]"
+    assert V.dim() in (2, 3) and V.dtype == torch.float64, "FP64 potentials [B][nx] or [B][ny][nx]"
     V = V.contiguous()
-    B, nx = V.shape
-    n_cells = nx if cells is None else int(cells.numel())
+    dim = V.dim() - 1
+    B, nx = V.shape[0], V.shape[-1]
+    ny = 1 if dim == 1 else V.shape[1]
+    width = n_m if dim == 1 else n_m * n_m
+    n_cells = nx * ny if cells is None else int(cells.numel())
     if cells is not None:
         cells = cells.to(torch.int32).contiguous()
     R = B * n_cells
     dev = V.device
     if out is None:
         out = (torch.empty(R, dtype=torch.float64, device=dev), torch.empty(R, dtype=torch.int32, device=dev),
-               torch.empty(R, dtype=torch.int32, device=dev), torch.empty((R, n_m), dtype=torch.int64, device=dev),
+               torch.empty(R, dtype=torch.int32, device=dev), torch.empty((R, width), dtype=torch.int64, device=dev),
                torch.empty((R, guide_len + 1), dtype=torch.int32, device=dev) if guide_len else None)
     g, n0, thr, cdf, guide = out
-    for t, shape in ((g, (R,)), (n0, (R,)), (thr, (R,)), (cdf, (R, n_m))):
+    for t, shape in ((g, (R,)), (n0, (R,)), (thr, (R,)), (cdf, (R, width))):
         if tuple(t.shape) != shape or not t.is_contiguous():
             raise ValueError(f"kernel_tables: output of shape {tuple(t.shape)}, expected {shape}")
     if guide is not None and (tuple(guide.shape) != (R, guide_len + 1) or not guide.is_contiguous()):
         raise ValueError("kernel_tables: guide must be a contiguous [rows][guide_len + 1] tensor")
-    m = mesh_struct(1, nx, 1, n_m, hbar)
+    m = mesh_struct(dim, nx, ny, n_m, hbar)
     L.check(L.lib().wk_kernel_tables(ctypes.byref(m), _ptr(V), B, _ptr(cells), n_cells, float(dt),
                                      _ptr(g), _ptr(n0), _ptr(thr), _ptr(cdf), _ptr(guide),
                                      guide_len if guide is not None else 0, _stream()), "wk_kernel_tables")

@@ -2,7 +2,7 @@
 library's kernels, no computation in Python.
 
 Per step: (every `refresh_every` steps) kernel rows for newly occupied cells -> creation
-tables (one fused pass for exact FP64 rows in 1-D, the rows staying on chip); sp_step
+tables (one fused pass for exact FP64 rows, the rows staying on chip); sp_step
 (creation at rate gamma, drift, absorbing boundaries, and the signed histogram of rule 1 of
 the result); sp_annihilate (rule 2 on that histogram).  The particle
 count stays in device memory; the host synchronises only to size the occasional kernel-row
@@ -56,10 +56,10 @@ class Simulator:
         self.cdf = torch.zeros((self.n_cells, self.width), dtype=torch.int64, device=self.dev)
         self.glen = min(self.width, 256)                # guide buckets for the CDF search
         self.guide = torch.zeros((self.n_cells, self.glen + 1), dtype=torch.int32, device=self.dev)
-        # exact FP64 rows in 1-D go straight into the creation tables (wk_kernel_tables): the
-        # kernel rows then never exist in device memory
-        self.fused = (fused_tables and kernel == "exact" and prec == "fp64" and self.dim == 1
-                      and 4 <= self.n_m <= 514)
+        # exact FP64 rows go straight into the creation tables (wk_kernel_tables): the kernel
+        # rows then never exist in device memory
+        self.fused = (fused_tables and kernel == "exact" and prec == "fp64"
+                      and ((self.dim == 1 and 4 <= self.n_m <= 514) or (self.dim == 2 and self.n_m in (8, 16, 32))))
         if self.fused:
             self.Kbuf = None
         elif kernel == "given":

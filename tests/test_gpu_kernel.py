@@ -154,6 +154,25 @@ def test_kernel_tables_equals_two_step(nx, n_m, B, use_cells, glen):
         assert guide is None
 
 
+@pytest.mark.parametrize("nx,ny,n_m,B,use_cells,glen", [(9, 7, 8, 1, False, 0), (20, 18, 16, 2, True, 64),
+                                                       (33, 30, 32, 1, True, 256), (40, 24, 32, 2, False, 5)])
+def test_kernel_tables_2d_equals_two_step(nx, ny, n_m, B, use_cells, glen):
+    """d = 2: rows straight into the tables equal kernel_eval + gamma_tables + sampling_guide."""
+    rng = np.random.default_rng(nx * ny + n_m)
+    V = torch.from_numpy(rng.normal(size=(B, ny, nx)) * 0.1).to(dev())
+    cells = None
+    if use_cells:
+        cells = torch.from_numpy(rng.permutation(nx * ny)[: nx * ny // 2].astype(np.int32)).to(dev())
+    dt = 0.5
+    g, n0, thr, cdf, guide = ops.kernel_tables(V, n_m, dt, cells=cells, guide_len=glen)
+    K = ops.kernel_eval(V, n_m, cells=cells)
+    g2, n02, thr2, cdf2 = ops.gamma_tables(K.reshape(K.shape[0], -1), n_m, dt, dim=2)
+    assert torch.equal(g, g2) and torch.equal(n0, n02) and torch.equal(thr, thr2)
+    assert torch.equal(cdf, cdf2)
+    if glen:
+        assert torch.equal(guide, ops.sampling_guide(cdf2, glen))
+
+
 @pytest.mark.parametrize("nx,n_m", [(300, 80), (200, 256), (100, 512)])
 def test_kernel_tables_vs_oracle(orc, nx, n_m):
     """Against the oracle's tables from the oracle's rows: gamma within the eq.(4) tolerance
