@@ -74,7 +74,9 @@ struct TabOut {
 constexpr int TAB_GMAX = 256;  // guide buckets the fused epilogue supports
 
 // Creation tables of eq.(1) from a workgroup's finished rows, which never leave the chip.
-// The rows are staged 8 (x WAVES_M) at a time in LDS as full rows, entry t <-> m = t - P,
+// The rows are staged in LDS as full rows, entry t <-> m = t - P, in groups of 8 (x WAVES_M)
+// rows; the narrowest tiles (H <= 32) take as many groups per round as the operand tiles' LDS
+// holds (three of four, 48 rows, at 80 momenta), the wider ones one group per round,
 // with the values the kernel would have written (K(m) = c (O + E), K(P - m) = c (O - E),
 // K(-m) = -K(m), K(0) = K(-P) = 0); then exactly the arithmetic of the table kernels: one
 // lane per row sums the positive part in ascending m in FP64 (the order is the definition)
@@ -82,115 +84,138 @@ constexpr int TAB_GMAX = 256;  // guide buckets the fused epilogue supports
 // (optionally) each bucket of the guide table is found by binary search over the CDF row.
 // One column block must hold every m of a row (H <= BN).
 template <int WM, int WN, int WAVES_N>
-__device__ __forceinline__ void tab_epilogue(const f64x4 (&acc)[2][WM][WN], double* lds, long row0,
-                                             long R, int P, int n_m, int H, double c,
+__device__ __forceinline__ void tab_epilogue(const f64x4 (&acc)[2][WM][WN], double* lds, int lds_len,
+                                             long row0, long R, int P, int n_m, int H, double c,
                                              const TabOut& tb) {
     constexpr int WAVES_M = 4 / WAVES_N;
-    constexpr int SR = 8 * WAVES_M;  // staged rows per round
-    __shared__ int last_s[SR];
+    constexpr int SR = 8 * WAVES_M;   // rows of one (tm, eh) group: tile rows 8 eh + [0, 8) of
+    constexpr int NG = 2 * WM;        // row tile tm in each wave row; NG groups per workgroup
+    __shared__ int last_s[NG * SR];
     __shared__ uint64_t Lg[TAB_GMAX];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = wave / WAVES_N, wc = wave % WAVES_N;
     const int lr = lane & 15, lk = lane >> 4;
     const int SW = n_m + 1;  // odd row stride: the per-row lanes of the prefix hit distinct banks
     for (int k = threadIdx.x; k < tb.G; k += KE_THREADS) Lg[k] = ((uint64_t)k << 32) / (uint64_t)tb.G;
+    // group gi = 2 tm + eh into staged rows slot SR + [0, SR): staged row slot SR + wr 8 + lk + 4 ee
+    // holds tile row 8 eh + lk + 4 ee of row tile tm of wave row wr
+    auto stage = [&](const int gi, const int slot) {
+        const int tm = gi >> 1, eh = gi & 1;
 #pragma unroll
-    for (int tm = 0; tm < WM; ++tm) {
+        for (int tn = 0; tn < WN; ++tn) {
+            const int t = (wc * WN + tn) * 16 + lr, m = t + 1;
 #pragma unroll
-        for (int eh = 0; eh < 2; ++eh) {
-            __syncthreads();  // the previous round (or the contraction) is done with the LDS
-            // staged row q = wr * 8 + lk + 4 ee holds tile row 8 eh + lk + 4 ee of wave row wr
-#pragma unroll
-            for (int tn = 0; tn < WN; ++tn) {
-                const int t = (wc * WN + tn) * 16 + lr, m = t + 1;
-#pragma unroll
-                for (int ee = 0; ee < 2; ++ee) {
-                    double* srow = lds + (wr * 8 + lk + 4 * ee) * SW;
-                    if (t < H) {
-                        const int e = 2 * eh + ee;
-                        const double o = acc[0][tm][tn][e], ev = acc[1][tm][tn][e];
-                        const double kp = c * (o + ev), km = c * (o - ev);
-                        srow[P + m] = kp;
-                        srow[P - m] = -kp;
-                        if (2 * m < P) {
-                            srow[2 * P - m] = km;
-                            srow[m] = -km;
-                        }
+            for (int ee = 0; ee < 2; ++ee) {
+                double* srow = lds + (slot * SR + wr * 8 + lk + 4 * ee) * SW;
+                if (t < H) {
+                    const int e = 2 * eh + ee;
+                    const double o = acc[0][tm][tn][e], ev = acc[1][tm][tn][e];
+                    const double kp = c * (o + ev), km = c * (o - ev);
+                    srow[P + m] = kp;
+                    srow[P - m] = -kp;
+                    if (2 * m < P) {
+                        srow[2 * P - m] = km;
+                        srow[m] = -km;
                     }
-                    if (t == 0) {
-                        srow[0] = 0.0;
-                        srow[P] = 0.0;
-                    }
+                }
+                if (t == 0) {
+                    srow[0] = 0.0;
+                    srow[P] = 0.0;
                 }
             }
-            __syncthreads();
-            auto grow = [&](int q) -> long {  // table row of staged row q
-                return row0 + ((q >> 3) * WM + tm) * 16 + 8 * eh + (q & 7);
-            };
-            if (threadIdx.x < SR) {
-                const int q = threadIdx.x;
-                double* srow = lds + q * SW;
-                double C = 0.0;
-                int last = -1;
-                for (int t = 0; t < n_m; ++t) {
-                    const double k = srow[t];
-                    if (k > 0.0) {
-                        C = C + k;
-                        last = t;
-                    }
-                    srow[t] = C;
+        }
+    };
+    // tables of the nr staged rows of groups g0, g0 + 1, ...
+    auto tables = [&](const int g0, const int nr) {
+        auto grow = [&](int q) -> long {  // table row of staged row q
+            const int gi = g0 + q / SR, qq = q % SR;
+            return row0 + ((qq >> 3) * WM + (gi >> 1)) * 16 + 8 * (gi & 1) + (qq & 7);
+        };
+        for (int q = threadIdx.x; q < nr; q += KE_THREADS) {  // one thread per row
+            double* srow = lds + q * SW;
+            double C = 0.0;
+            int last = -1;
+            for (int t = 0; t < n_m; ++t) {
+                const double k = srow[t];
+                if (k > 0.0) {
+                    C = C + k;
+                    last = t;
                 }
-                last_s[q] = last;
-                const long row = grow(q);
-                if (row < R) {
-                    const double p = C * tb.dt;
-                    const double fl = floor(p);
-                    tb.gamma[row] = C;
-                    tb.n0[row] = (uint32_t)fl;
-                    tb.thr[row] = (uint32_t)floor((p - fl) * 4294967296.0);
-                }
+                srow[t] = C;
             }
-            __syncthreads();
-            // rows to waves, entries to lanes; each lane converts its own entries in place
-            for (int q = wave; q < SR; q += KE_THREADS / 64) {
-                const long row = grow(q);
-                double* srow = lds + q * SW;
-                const int last = last_s[q];
-                const double g = last >= 0 ? srow[last] : 0.0;
-                uint64_t* crow = tb.cdf + row * n_m;
-                for (int t = lane; t < n_m; t += 64) {
-                    uint64_t v;
-                    if (last < 0)
-                        v = 0;
-                    else if (t >= last)
-                        v = 1ull << 32;
+            last_s[q] = last;
+            const long row = grow(q);
+            if (row < R) {
+                const double p = C * tb.dt;
+                const double fl = floor(p);
+                tb.gamma[row] = C;
+                tb.n0[row] = (uint32_t)fl;
+                tb.thr[row] = (uint32_t)floor((p - fl) * 4294967296.0);
+            }
+        }
+        __syncthreads();
+        // rows to waves, entries to lanes; each lane converts its own entries in place
+        for (int q = wave; q < nr; q += KE_THREADS / 64) {
+            const long row = grow(q);
+            double* srow = lds + q * SW;
+            const int last = last_s[q];
+            const double g = last >= 0 ? srow[last] : 0.0;
+            uint64_t* crow = tb.cdf + row * n_m;
+            for (int t = lane; t < n_m; t += 64) {
+                uint64_t v;
+                if (last < 0)
+                    v = 0;
+                else if (t >= last)
+                    v = 1ull << 32;
+                else
+                    v = (uint64_t)floor(srow[t] / g * 4294967296.0);
+                if (row < R) crow[t] = v;
+                reinterpret_cast<uint64_t*>(srow)[t] = v;
+            }
+        }
+        if (tb.guide == nullptr) return;
+        __syncthreads();
+        for (int q = wave; q < nr; q += KE_THREADS / 64) {
+            const long row = grow(q);
+            if (row >= R) continue;
+            const uint64_t* T = reinterpret_cast<const uint64_t*>(lds + q * SW);
+            uint32_t* gout = tb.guide + row * (tb.G + 1);
+            for (int k = lane; k < tb.G; k += 64) {
+                const uint64_t L = Lg[k];
+                int lo = 0, hi = n_m - 1;  // first t with T[t] > L, at most n_m - 1
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (T[mid] > L)
+                        hi = mid;
                     else
-                        v = (uint64_t)floor(srow[t] / g * 4294967296.0);
-                    if (row < R) crow[t] = v;
-                    reinterpret_cast<uint64_t*>(srow)[t] = v;
+                        lo = mid + 1;
                 }
+                gout[k] = (uint32_t)lo;
             }
-            if (tb.guide == nullptr) continue;
+            if (lane == 0) gout[tb.G] = (uint32_t)(n_m - 1);
+        }
+    };
+    if constexpr (WAVES_N == 4) {
+        // the wider tiles (H > 32) hold one or two groups per round and are register bound:
+        // straight-line rounds keep the accumulators' indices constant (and the occupancy)
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            __syncthreads();  // the previous round (or the contraction) is done with the LDS
+            stage(gi, 0);
             __syncthreads();
-            for (int q = wave; q < SR; q += KE_THREADS / 64) {
-                const long row = grow(q);
-                if (row >= R) continue;
-                const uint64_t* T = reinterpret_cast<const uint64_t*>(lds + q * SW);
-                uint32_t* gout = tb.guide + row * (tb.G + 1);
-                for (int k = lane; k < tb.G; k += 64) {
-                    const uint64_t L = Lg[k];
-                    int lo = 0, hi = n_m - 1;  // first t with T[t] > L, at most n_m - 1
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (T[mid] > L)
-                            hi = mid;
-                        else
-                            lo = mid + 1;
-                    }
-                    gout[k] = (uint32_t)lo;
-                }
-                if (lane == 0) gout[tb.G] = (uint32_t)(n_m - 1);
-            }
+            tables(gi, SR);
+        }
+    } else {
+        // as many groups per round as the LDS holds (at least one: checked on the host)
+        const int gpr = min(NG, lds_len / (SR * SW));
+        for (int g0 = 0; g0 < NG; g0 += gpr) {  // uniform
+            const int ng = min(gpr, NG - g0);
+            __syncthreads();
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi)
+                if (gi >= g0 && gi < g0 + ng) stage(gi, gi - g0);
+            __syncthreads();
+            tables(g0, ng * SR);
         }
     }
 }
@@ -326,7 +351,8 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_f64(
     }
 
     if constexpr (TAB) {
-        tab_epilogue<WM, WN, WAVES_N>(acc, &Ds[0][0][0][0], row0, R, P, n_m, H, c, tb);
+        tab_epilogue<WM, WN, WAVES_N>(acc, &Ds[0][0][0][0], 2 * 2 * BM * (BK + 1), row0, R, P, n_m,
+                                      H, c, tb);
         return;
     }
 #pragma unroll
