@@ -195,6 +195,29 @@ def test_kernel_tables_vs_oracle(orc, nx, n_m):
     assert np.all(np.abs(rate - rrate) <= dt * dg + 2.0 ** -31)
 
 
+@pytest.mark.parametrize("dim", [1, 2])
+def test_kernel_tables_edge_cases(dim):
+    """Empty batches write nothing; cell ids outside the mesh give the same (all-zero) tables
+    as the two-step form on their NaN rows; a constant potential gives zero rates."""
+    n_m = 16
+    shape = (2, 30) if dim == 1 else (2, 6, 5)
+    V = torch.from_numpy(np.random.default_rng(3).normal(size=shape) * 0.1).to(dev())
+    empty = ops.kernel_tables(V[:0], n_m, 1.0, guide_len=8)
+    assert all(t.numel() == 0 for t in empty)
+    ncell = 30
+    cells = torch.tensor([3, -1, 7, ncell, 0], dtype=torch.int32, device=dev())
+    g, n0, thr, cdf, guide = ops.kernel_tables(V, n_m, 1.0, cells=cells, guide_len=8)
+    K = ops.kernel_eval(V, n_m, cells=cells, layout="half" if dim == 1 else "full")
+    g2, n02, thr2, cdf2 = ops.gamma_tables(K.reshape(K.shape[0], -1), n_m, 1.0, dim=dim,
+                                           layout="half" if dim == 1 else "full")
+    assert torch.equal(g, g2) and torch.equal(n0, n02) and torch.equal(thr, thr2) and torch.equal(cdf, cdf2)
+    assert torch.equal(guide, ops.sampling_guide(cdf2, 8))
+    bad = torch.tensor([1, 3, 6, 8], device=dev())  # rows of ids -1 and ncell in both batches
+    assert torch.all(g[bad] == 0) and torch.all(cdf[bad] == 0)
+    gc = ops.kernel_tables(torch.full_like(V, 0.25), n_m, 1.0)[0]
+    assert torch.all(gc == 0)
+
+
 @pytest.mark.parametrize("n_m,glen", [(2, 0), (516, 0), (80, 257)])
 def test_kernel_tables_refuses_out_of_range(n_m, glen):
     V = torch.zeros((1, 16), dtype=torch.float64, device=dev())
