@@ -472,19 +472,48 @@ __device__ void store_counts(const WS& w, long long wave_count, long long* red4)
 // per run of equal (bin, sign) among the 64 lanes of a wave, then adds the non-zero window
 // entries to the global histogram; runs outside the window (rare) go straight to global
 // atomics.
-template <int W>
+// HASH (the 2-D passes): drift along y moves a particle by nx n_k^2 bins, far outside any
+// window of consecutive bins, yet a workgroup still touches only a few hundred distinct bins.
+// The same LDS then holds a hash table of W (bin, sign) keys with their counts (linear
+// probing, keys claimed by compare-and-swap), flushed once per workgroup; a key that finds
+// no slot within HPROBE probes goes to the global histogram.  Integer sums: the histogram
+// is the same whichever way a count travels.
+template <int W, bool HASH = false>
 struct HistWindow {
-    int* lh;  // [2][W] in LDS
+    int* lh;  // [2][W] in LDS: window counts per sign, or (HASH) keys then counts
     long base;
     int32_t* hist;
     long n_bins;
 
+    static_assert(!HASH || (W & (W - 1)) == 0, "hash table size must be a power of two");
+    // probes before a key gives up on the table: once it fills, long probes cost more LDS
+    // round trips than the global atomic they avoid (4 measured best of 1, 2, 4, 8, 32)
+    static constexpr int HPROBE = 4;
+    static constexpr uint32_t EMPTY = 0xFFFFFFFFu;  // never a key: 2 b + 1 < 2^32 - 1
+
     __device__ __forceinline__ void bump(long b, int sg, int cnt) {
-        const long k = b - base;
-        if (k >= 0 && k < W)
-            atomicAdd(&lh[sg * W + k], cnt);
-        else
+        if constexpr (HASH) {
+            uint32_t* keys = reinterpret_cast<uint32_t*>(lh);
+            int* vals = lh + W;
+            const uint32_t key = (uint32_t)(2 * b + sg);
+            uint32_t h = (key * 2654435761u) & (uint32_t)(W - 1);
+#pragma unroll 1
+            for (int p = 0; p < HPROBE; ++p) {
+                const uint32_t cur = atomicCAS(&keys[h], EMPTY, key);
+                if (cur == EMPTY || cur == key) {
+                    atomicAdd(&vals[h], cnt);
+                    return;
+                }
+                h = (h + 1) & (uint32_t)(W - 1);
+            }
             atomicAdd(&hist[sg * n_bins + b], cnt);
+        } else {
+            const long k = b - base;
+            if (k >= 0 && k < W)
+                atomicAdd(&lh[sg * W + k], cnt);
+            else
+                atomicAdd(&hist[sg * n_bins + b], cnt);
+        }
     }
 
     // one particle per lane (b < 0: none); all 64 lanes of the wave must call it together
@@ -508,7 +537,7 @@ struct HistWindow {
 
     // smallest live bin among the block's candidates -> window base (uniform in the block)
     __device__ void init(long b_min_thread, long* wmin4) {
-        for (int k = threadIdx.x; k < 2 * W; k += PT) lh[k] = 0;
+        for (int k = threadIdx.x; k < 2 * W; k += PT) lh[k] = (HASH && k < W) ? (int)EMPTY : 0;
         long b0 = b_min_thread;
         for (int o = 32; o > 0; o >>= 1) b0 = min(b0, (long)__shfl_xor(b0, o, 64));
         if ((threadIdx.x & 63) == 0) wmin4[threadIdx.x >> 6] = b0;
@@ -519,6 +548,15 @@ struct HistWindow {
 
     __device__ void flush() {
         __syncthreads();
+        if constexpr (HASH) {
+            const uint32_t* keys = reinterpret_cast<const uint32_t*>(lh);
+            for (int k = threadIdx.x; k < W; k += PT) {
+                const uint32_t key = keys[k];
+                const int v = lh[W + k];
+                if (key != EMPTY && v != 0) atomicAdd(&hist[(long)(key & 1u) * n_bins + (long)(key >> 1)], v);
+            }
+            return;
+        }
         for (int k = threadIdx.x; k < W; k += PT) {
             const long b = base + k;
             if (b >= n_bins) break;
@@ -660,7 +698,7 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
     wave_chunk(n, (long)blockIdx.x * WPB + wv, &lo, &hi);
     const T vdt = (T)g.vdt;
     long long abs_x = 0, abs_m = 0;
-    HistWindow<HW_STEP> hw{lh, 0, hist, g.n_bins};
+    HistWindow<HW_STEP, DIM == 2> hw{lh, 0, hist, g.n_bins};
     if (HIST) hw.init(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), wmin);
     auto absorbed = [&](T nx_, T ny_, int m, int my) -> int {
         bool outx = !inside<T>(nx_, g.nx);
@@ -871,7 +909,7 @@ __global__ __launch_bounds__(PT) void annih_hist(Geo g, const T* x, const T* y, 
     if (n < 0 || n > cap_in) return;  // refused by annih_count
     long lo, hi;
     wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
-    HistWindow<HW> hw{lh, 0, hist, g.n_bins};
+    HistWindow<HW, DIM == 2> hw{lh, 0, hist, g.n_bins};
     hw.init(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), wmin);
     Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
     load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);

@@ -136,6 +136,35 @@ def test_fused_tables_2d_simulator_equals_two_step():
         assert torch.equal(getattr(fused, f)[:r], getattr(two, f)[:r]), f
 
 
+def test_2d_full_size_histogram_recount():
+    """The 2-D workload at full size (5e7 particles): the signed histogram a step builds (LDS
+    hash aggregation, with global atomics for the keys that overflow it) equals a host recount
+    of the particles the step wrote."""
+    cfg = inputs.config_c5()
+    sim = Simulator(cfg)
+    for _ in range(3):
+        sim.step()
+    md = sim.md
+    out = ops.DeviceParticles(2, sim.capacity, md["pos_f64"])
+    hist = torch.zeros_like(sim.hist)
+    ops.sp_step(md, sim.seed, sim.cell_slot, sim.n0, sim.thr, sim.cdf, sim.a, out, sim.step_index,
+                sim.stats, sim.ws, hist=hist, guide=sim.guide)
+    assert not sim.overflowed()
+    v = out.view()
+    live = v["s"] != 0
+    cx = np.floor(v["x"][live]).astype(np.int64)
+    cy = np.floor(v["y"][live]).astype(np.int64)
+    kx = v["M"][live].astype(np.int64) - md["M_min"]
+    ky = v["My"][live].astype(np.int64) - md["M_min"]
+    b = ((cy * md["nx"] + cx) * md["n_k"] + ky) * md["n_k"] + kx
+    nb = ops.n_bins(md)
+    pos = v["s"][live] > 0
+    h = to_np(hist)
+    assert np.array_equal(h[:nb], np.bincount(b[pos], minlength=nb))
+    assert np.array_equal(h[nb:], np.bincount(b[~pos], minlength=nb))
+    assert live.sum() > 4e7
+
+
 def test_2d_simulator_equals_oracle_loop(orc):
     mesh = inputs.Mesh2D(nx=20, ny=18, dx=0.5, n_m=16, pos_f64=False)
     V = inputs.gaussian_dot_2d(mesh, 0.2, 1.5, 5.0, 4.5)
