@@ -383,29 +383,6 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long* red4) 
     return t;
 }
 
-// Block-wide exclusive scan of one int64 per thread (PT threads).
-__device__ __forceinline__ long long block_excl_scan_ll(long long v, long long* total,
-                                                        long long* red4) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const long long inc = wave_incl_scan_ll(v);
-    if (lane == 63) red4[w] = inc;
-    __syncthreads();
-    long long base = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (k < w) base += red4[k];
-    *total = red4[0] + red4[1] + red4[2] + red4[3];
-    __syncthreads();
-    return base + inc - v;
-}
-
-// Sum of v[0..PB) over the block (uniform result).
-__device__ __forceinline__ long long sum_pb(const long long* v, long long* red4) {
-    long long a = 0;
-    for (int k = threadIdx.x; k < PB; k += PT) a += v[k];
-    return block_sum_ll(a, red4);
-}
-
 // Makes the LDS writes of every lane of the wave visible to the others (the waves of a
 // workgroup run independently here, so no workgroup barrier).
 __device__ __forceinline__ void wave_lds_sync() {
