@@ -42,10 +42,12 @@ constexpr int WPB = PT / 64;  // waves per workgroup
 constexpr int NW = PB * WPB;  // wave chunks of the ordered passes
 
 constexpr int PLACE_BLOCKS = PB;  // workgroups placing regenerated / initial particles
+constexpr int CT_MAX = 1024;       // cells of the LDS creation table (larger meshes: ctab)
 
 // Workspace (sp_workspace_size): int64 scalars[16] | int64 bcnt[PB] | int64 wcnt[NW] |
 // int64 bpart[PB] | int64 bmixed[PB] | int64 kpre[PB] | int64 bpre[PB] |
-// int32 pstart[PLACE_BLOCKS] | int32 csum[n_chunks] | uint8 occ[n_cells] | uint8 occx[n_cells].
+// int32 pstart[PLACE_BLOCKS] | int32 csum[n_chunks] | uint8 occ[n_cells] | uint8 occx[n_cells] |
+// uint2 ctab[n_cells] (8-byte aligned).
 enum { SC_GO = 0, SC_PLACED = 1, SC_KEPT = 2 };
 
 struct WS {
@@ -59,11 +61,12 @@ struct WS {
     int* pstart;        // per placing workgroup: first bin workgroup of its slot range
     int* csum;          // per bin chunk: particles to place
     uint8_t* occ;
+    uint2* ctab;        // meshes above CT_MAX cells: (n0, thr) per cell, gathered each step
 };
 
 static long n_chunks_for(long n_bins) { return (n_bins + BC - 1) / BC; }
 
-static WS carve(void* ws, long n_bins) {
+static WS carve(void* ws, long n_bins, long n_cells) {
     WS w;
     char* p = static_cast<char*>(ws);
     w.sc = reinterpret_cast<long long*>(p);
@@ -76,13 +79,16 @@ static WS carve(void* ws, long n_bins) {
     w.pstart = reinterpret_cast<int*>(w.bpre + PB);
     w.csum = w.pstart + PLACE_BLOCKS;
     w.occ = reinterpret_cast<uint8_t*>(w.csum + (n_chunks_for(n_bins) + 1) / 2 * 2);
+    const uintptr_t e = reinterpret_cast<uintptr_t>(w.occ) + 2 * (size_t)n_cells;
+    w.ctab = reinterpret_cast<uint2*>((e + 7) & ~(uintptr_t)7);
     return w;
 }
 
 static size_t ws_bytes_for(long n_bins, long n_cells) {
     return sizeof(long long) * (16 + 5 * (size_t)PB + (size_t)NW) +
            sizeof(int) * (size_t)(PLACE_BLOCKS + (n_chunks_for(n_bins) + 1) / 2 * 2) +
-           2 * (size_t)n_cells;  // occupancy byte per cell, then its dilation along x
+           2 * (size_t)n_cells +  // occupancy byte per cell, then its dilation along x
+           8 + sizeof(uint2) * (n_cells > CT_MAX ? (size_t)n_cells : 0);  // aligned ctab
 }
 
 constexpr int IT = 4;          // particles per lane in the streaming passes
@@ -297,7 +303,6 @@ __device__ __forceinline__ int pairs_of(const Geo& g, uint32_t id, uint32_t step
 // Pair count only (postulate II), with (n0, thr) of the particle's cell taken from a
 // per-workgroup LDS table when the mesh is small enough (ct != nullptr), else through
 // cell_slot from global memory.  Only the first Philox word is used.
-constexpr int CT_MAX = 1024;  // cells of the LDS creation table
 
 template <typename T, int DIM>
 __device__ __forceinline__ int pairs_count(const Geo& g, uint32_t id, uint32_t step, T px, T py,
@@ -559,6 +564,18 @@ __device__ long first_bin(const Geo& g, const T* x, const T* y, const MT* M, con
 }
 
 // ----------------------------------------------------------------------------- sp_step
+// Meshes above CT_MAX cells: (n0, thr) of every cell gathered through cell_slot into one
+// cell-indexed table, so that a particle's creation test is one load instead of two
+// dependent ones.
+__global__ void cell_table_kernel(long n_cells, const int32_t* __restrict__ cell_slot,
+                                  const uint32_t* __restrict__ n0, const uint32_t* __restrict__ thr,
+                                  uint2* __restrict__ ctab) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells) return;
+    const int sl = cell_slot[c];
+    ctab[c] = sl < 0 ? make_uint2(0u, 0u) : make_uint2(n0[sl], thr[sl]);
+}
+
 // Pass 1: pairs per wave chunk of `in`.  Also clears the histogram pass 2 accumulates into
 // and the absorption counters; refuses an input count the buffers cannot hold.
 template <typename T, typename MT, int DIM>
@@ -591,7 +608,7 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
         stats[WK_ST_ABS_M] = 0;
     }
     const long n_cells = (long)g.nx * g.ny;
-    const uint2* ct = nullptr;
+    const uint2* ct = w.ctab;  // larger meshes: the cell-indexed table of cell_table_kernel
     if (n_cells <= CT_MAX) {  // (n0, thr) per cell in LDS
         for (int c = threadIdx.x; c < n_cells; c += PT) {
             const int sl = cell_slot[c];
@@ -1386,6 +1403,10 @@ static void launch_step(const Geo& g, uint32_t step, const int32_t* cs, const ui
     T* yo = static_cast<T*>(out->y);
     MT* Mo = static_cast<MT*>(out->M);
     MT* Myo = static_cast<MT*>(out->My);
+    const long n_cells = (long)g.nx * g.ny;
+    if (n_cells > CT_MAX)
+        WK_LAUNCH("cell_table", cell_table_kernel, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, s,
+                  n_cells, cs, n0, thr, w.ctab);
     WK_LAUNCH("step_count", (step_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, step, cs, n0, thr,
               x, y, M, My, in->s, d_n_in, (long long)in->capacity, xo, out->s, cap, hist, stats, st, w);
     if (hist)
@@ -1481,7 +1502,7 @@ extern "C" int sp_init(const sp_geom* gm, const int32_t* bin_counts, sp_particle
     if (rc) return rc;
     WK_REQUIRE(bin_counts && d_stats, "sp_init: NULL array");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_init: workspace too small");
-    WS w = carve(ws, g.n_bins);
+    WS w = carve(ws, g.n_bins, (long)g.nx * g.ny);
     WK_DISPATCH(gm, launch_init, g, bin_counts, out, reinterpret_cast<long long*>(d_stats), w,
                 as_stream(stream));
     return check_launch("sp_init");
@@ -1506,7 +1527,7 @@ extern "C" int sp_step(const sp_geom* gm, const int32_t* cell_slot, const uint32
     WK_REQUIRE(guide == nullptr || (guide_len >= 1 && guide_len <= (1 << 20)),
                "sp_step: guide_len out of range");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_step: workspace too small");
-    WS w = carve(ws, g.n_bins);
+    WS w = carve(ws, g.n_bins, (long)g.nx * g.ny);
     WK_DISPATCH(gm, launch_step, g, (uint32_t)step, cell_slot, n0, thr, cdf, guide, guide_len, in,
                 out, hist, reinterpret_cast<long long*>(d_stats), (long long)step, w,
                 as_stream(stream));
@@ -1528,7 +1549,7 @@ extern "C" int sp_annihilate(const sp_geom* gm, const sp_particles* in, sp_parti
     WK_REQUIRE(hist && d_stats, "sp_annihilate: NULL array");
     WK_REQUIRE(step >= 0 && step < (1LL << 32), "sp_annihilate: step must fit 32 bits");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_annihilate: workspace too small");
-    WS w = carve(ws, g.n_bins);
+    WS w = carve(ws, g.n_bins, (long)g.nx * g.ny);
     WK_DISPATCH(gm, launch_annih, g, (uint32_t)step, in, out, hist, (int)(hist_ready != 0),
                 reinterpret_cast<long long*>(d_stats), w, as_stream(stream));
     return check_launch("sp_annihilate");
@@ -1558,7 +1579,7 @@ extern "C" int sp_cells_to_evaluate(const sp_geom* gm, const int32_t* hist, int3
     WK_REQUIRE(margin >= 0, "sp_cells_to_evaluate: negative margin");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_cells_to_evaluate: workspace too small");
     const long n_cells = (long)g.nx * g.ny;
-    uint8_t* occ = carve(ws, g.n_bins).occ;  // [n_cells] occupancy, then [n_cells] x-dilation
+    uint8_t* occ = carve(ws, g.n_bins, (long)g.nx * g.ny).occ;  // [n_cells] occupancy, then [n_cells] x-dilation
     uint8_t* occx = occ + n_cells;
     hipStream_t s = as_stream(stream);
     const dim3 cg((unsigned)((n_cells + 255) / 256));

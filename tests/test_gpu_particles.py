@@ -231,9 +231,12 @@ def test_cell_slot_subset(orc):
     assert_particles_equal(b.view(), ref.view(), "cell subset")
 
 
-def test_2d_step_and_annihilation(orc):
-    """2-D passes (int16 momenta, FP32 positions) on a small mesh, bit-exact, 4 steps."""
-    mesh = inputs.Mesh2D(nx=24, ny=20, dx=0.5, n_m=8, pos_f64=False)
+@pytest.mark.parametrize("nx,ny", [(24, 20), (40, 36)])
+def test_2d_step_and_annihilation(orc, nx, ny):
+    """2-D passes (int16 momenta, FP32 positions), bit-exact, 4 steps; the larger mesh (more
+    cells than the LDS creation table holds) takes the cell-indexed table in the workspace,
+    with some cells mapped to no table row."""
+    mesh = inputs.Mesh2D(nx=nx, ny=ny, dx=0.5, n_m=8, pos_f64=False)
     md = mesh.as_dict(0.5)
     V = inputs.gaussian_dot_2d(mesh, 0.2, 1.5, 6.0, 5.0)
     K = orc.kernel_2d(V, mesh.n_m, HB)[0].reshape(-1, 64)
@@ -246,7 +249,9 @@ def test_2d_step_and_annihilation(orc):
     assert_particles_equal(a.view(), hp.view(), "2-D init")
     b = ops.DeviceParticles(2, cap, False)
     hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev())
-    slot = np.arange(24 * 20, dtype=np.int32)
+    slot = np.arange(nx * ny, dtype=np.int32)
+    if nx * ny > 1024:
+        slot[::7] = -1
     n0, thr, cdf = host_tables_to_device(tables)
     slot_d = torch.from_numpy(slot).to(dev())
     guide = ops.sampling_guide(cdf, 16)
