@@ -965,16 +965,41 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, int part_blocks, BinCou
     const long c = (long)blockIdx.x - part_blocks;
     const long j0 = min(g.n_chunks, c * g.gpb), j1 = min(g.n_chunks, j0 + g.gpb);
     long long part = 0, mixed = 0;
-    for (long j = j0; j < j1; ++j) {  // uniform
-        const long b = j * BC + threadIdx.x;
-        long long v = 0;
-        if (b < g.n_bins) {
-            v = bc(b);
-            mixed += bc.mixed(b) ? 1 : 0;
+    // NB chunks at a time (2-D, where a bin workgroup walks 128 chunks): the loads of the NB
+    // chunks are in flight together and one barrier serves their sums
+    constexpr int NB = DIM == 2 ? 4 : 1;
+    __shared__ long long bsum[NB][PT / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (long j = j0; j < j1; j += NB) {  // uniform
+        long long v[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const long b = (j + i) * BC + threadIdx.x;
+            v[i] = 0;
+            if (j + i < j1 && b < g.n_bins) {
+                v[i] = bc(b);
+                mixed += bc.mixed(b) ? 1 : 0;
+            }
         }
-        v = block_sum_ll(v, red);
-        if (threadIdx.x == 0) w.csum[j] = (int)v;  // < 2^31 whenever the capacity check passes
-        part += v;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const long long sv = wave_sum_ll(v[i]);
+            if (lane == 0) bsum[i][wv] = sv;
+        }
+        __syncthreads();
+        if (threadIdx.x < NB && j + threadIdx.x < j1) {
+            long long t = 0;
+#pragma unroll
+            for (int k = 0; k < PT / 64; ++k) t += bsum[threadIdx.x][k];
+            w.csum[j + threadIdx.x] = (int)t;  // < 2^31 whenever the capacity check passes
+        }
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int k = 0; k < PT / 64; ++k) part += bsum[i][k];
+        }
+        __syncthreads();  // bsum is rewritten by the next chunks
     }
     mixed = block_sum_ll(mixed, red);
     if (threadIdx.x == 0) {
