@@ -1091,28 +1091,33 @@ __global__ __launch_bounds__(ST_THREADS) void annih_scan(int mode, int place_blo
         return;
     }
     constexpr int per = PB / ST_THREADS;
-    // exclusive / inclusive scans of PB values, per thread `per` consecutive ones
+    constexpr int NWS = ST_THREADS / 64;
+    // exclusive / inclusive scans of PB values, per thread `per` consecutive ones: thread sums
+    // scanned within each wave by shuffles, then across the waves' totals
     auto scan = [&](const long long* in, long long* out_excl, long long* out_incl, long long* total) {
         long long loc[per], acc = 0;
         for (int k = 0; k < per; ++k) {
             loc[k] = in[threadIdx.x * per + k];
             acc += loc[k];
         }
-        part[threadIdx.x] = acc;
+        const long long inc = wave_incl_scan_ll(acc);
+        if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = inc;
         __syncthreads();
-        for (int o = 1; o < ST_THREADS; o <<= 1) {  // Hillis-Steele over the thread sums
-            const long long v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
-            __syncthreads();
-            part[threadIdx.x] += v;
-            __syncthreads();
+        long long base = 0;
+        for (int k = 0; k < (int)(threadIdx.x >> 6); ++k) base += part[k];
+        if (threadIdx.x == ST_THREADS - 1) {
+            long long t = 0;
+            for (int k = 0; k < NWS; ++k) t += part[k];
+            part[NWS] = t;
         }
-        long long run = part[threadIdx.x] - acc;
+        __syncthreads();
+        long long run = base + inc - acc;
         for (int k = 0; k < per; ++k) {
             if (out_excl) out_excl[threadIdx.x * per + k] = run;
             run += loc[k];
             if (out_incl) out_incl[threadIdx.x * per + k] = run;
         }
-        if (threadIdx.x == ST_THREADS - 1) *total = part[ST_THREADS - 1];
+        if (threadIdx.x == 0) *total = part[NWS];
         __syncthreads();
     };
     scan(w.bpart, nullptr, bp, &tot[0]);
