@@ -73,3 +73,48 @@ def test_particle_calls_reject_aliased_buffers_without_gpu():
     rc = lib.sp_step(ctypes.byref(g), f, f, f, f, None, 0, ctypes.byref(p), ctypes.byref(q), None,
                      0, f, f, ws - 1, None)
     assert rc == _lib.WK_EINVAL and b"workspace" in lib.wk_last_error()
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the parameter structs have the sizes and field offsets the C
+    compiler gives the header's structs."""
+    import shutil
+    import subprocess
+    from paper_1806_00082_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    mirrors = {"wk_mesh": _lib.WkMesh, "sp_geom": _lib.SpGeom, "sp_particles": _lib.SpParticles}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "wigner.h"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_momentum_width_rules():
+    """16-bit 1-D momenta: chosen per buffer, refused when the buffers of a call disagree
+    (checked on the host before any library call)."""
+    import torch
+    from paper_1806_00082_amd import inputs, ops
+    md = inputs.config_c1().mesh.as_dict(1.0)
+    assert ops.fits_m16(md)
+    assert not ops.fits_m16(dict(md, M_min=-40000))
+    a = ops.DeviceParticles(1, 8, True, device="cpu")
+    b = ops.DeviceParticles(1, 8, True, device="cpu", m16=True)
+    c = ops.DeviceParticles(2, 8, False, device="cpu", m16=True)
+    assert a.M.dtype == torch.int32 and b.M.dtype == torch.int16
+    assert c.M.dtype == torch.int16 and not c.m16  # 2-D momenta are always 16-bit
+    with pytest.raises(ValueError):
+        ops.sp_annihilate(md, 0, a, b, None, 0, None, None)
+    assert ops.geom_struct(md, 0, True).m16 == 1
