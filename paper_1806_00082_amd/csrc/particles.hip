@@ -379,13 +379,34 @@ __device__ __forceinline__ long long wave_incl_scan_ll(long long v) {
 
 // Sum over the block of one int64 per thread (PT threads); the result is valid in every
 // thread.
-__device__ __forceinline__ long long block_sum_ll(long long v, long long* red4) {
+__device__ __forceinline__ long long block_sum_ll(long long v, long long* redw) {
     v = wave_sum_ll(v);
-    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
+    if ((threadIdx.x & 63) == 0) redw[threadIdx.x >> 6] = v;
     __syncthreads();
-    const long long t = red4[0] + red4[1] + red4[2] + red4[3];
+    long long t = 0;
+#pragma unroll
+    for (int k = 0; k < WPB; ++k) t += redw[k];
     __syncthreads();
     return t;
+}
+
+// Block-wide exclusive scan of one int per thread (PT threads); returns the exclusive prefix
+// and writes the block total to *total.  Uses WPB ints of LDS.
+__device__ __forceinline__ int block_excl_scan_pt(int v, int* total, int* ldsw) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int inc = wave_incl_scan(v);
+    if (lane == 63) ldsw[wv] = inc;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < WPB; ++k) {
+        const int t = ldsw[k];
+        base += k < wv ? t : 0;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
 }
 
 // Makes the LDS writes of every lane of the wave visible to the others (the waves of a
@@ -415,17 +436,17 @@ __device__ __forceinline__ int upper_bound_lds(const V* a, int n, K key) {
 // chunk-owning workgroups.  Each workgroup of the matching writing pass totals bcnt (PB
 // values from L2) for the capacity check; a chunk owner (blockIdx.x < PB, own = true) also
 // gets the offset of its calling wave's chunk in *wave_off (valid in every lane).
-__device__ long long chunk_offsets(const WS& w, bool own, long long* wave_off, long long* red4) {
+__device__ long long chunk_offsets(const WS& w, bool own, long long* wave_off, long long* redw) {
     long long a = 0, p = 0;
     for (int k = threadIdx.x; k < PB; k += PT) {
         const long long v = w.bcnt[k];
         a += v;
         if (own && k < (int)blockIdx.x) p += v;
     }
-    const long long total = block_sum_ll(a, red4);
+    const long long total = block_sum_ll(a, redw);
     long long off = 0;
     if (own) {
-        off = block_sum_ll(p, red4);
+        off = block_sum_ll(p, redw);
         const int wv = threadIdx.x >> 6;
         for (int j = 0; j < wv; ++j) off += w.wcnt[(long)blockIdx.x * WPB + j];
     }
@@ -434,14 +455,19 @@ __device__ long long chunk_offsets(const WS& w, bool own, long long* wave_off, l
 }
 
 // Stores a wave's count (lane 0) and the workgroup's sum of its waves' counts (thread 0).
-__device__ void store_counts(const WS& w, long long wave_count, long long* red4) {
+__device__ void store_counts(const WS& w, long long wave_count, long long* redw) {
     const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         w.wcnt[(long)blockIdx.x * WPB + wv] = wave_count;
-        red4[wv] = wave_count;
+        redw[wv] = wave_count;
     }
     __syncthreads();
-    if (threadIdx.x == 0) w.bcnt[blockIdx.x] = red4[0] + red4[1] + red4[2] + red4[3];
+    if (threadIdx.x == 0) {
+        long long t = 0;
+#pragma unroll
+        for (int k = 0; k < WPB; ++k) t += redw[k];
+        w.bcnt[blockIdx.x] = t;
+    }
 }
 
 // ----------------------------------------------------------------------------- histogram window
@@ -518,13 +544,15 @@ struct HistWindow {
     }
 
     // smallest live bin among the block's candidates -> window base (uniform in the block)
-    __device__ void init(long b_min_thread, long* wmin4) {
+    __device__ void init(long b_min_thread, long* wminw) {
         for (int k = threadIdx.x; k < 2 * W; k += PT) lh[k] = (HASH && k < W) ? (int)EMPTY : 0;
         long b0 = b_min_thread;
         for (int o = 32; o > 0; o >>= 1) b0 = min(b0, (long)__shfl_xor(b0, o, 64));
-        if ((threadIdx.x & 63) == 0) wmin4[threadIdx.x >> 6] = b0;
+        if ((threadIdx.x & 63) == 0) wminw[threadIdx.x >> 6] = b0;
         __syncthreads();
-        const long m = min(min(wmin4[0], wmin4[1]), min(wmin4[2], wmin4[3]));
+        long m = wminw[0];
+#pragma unroll
+        for (int k = 1; k < WPB; ++k) m = min(m, wminw[k]);
         base = m == LONG_MAX ? 0 : max(0L, m - W / 4);
     }
 
@@ -865,13 +893,15 @@ struct KeepWindow {
     }
 };
 
-__device__ KeepWindow keep_window(long b_min_thread, int* lw, long* wmin4, const int32_t* hist,
+__device__ KeepWindow keep_window(long b_min_thread, int* lw, long* wminw, const int32_t* hist,
                                   long n_bins) {
     long b0 = b_min_thread;
     for (int o = 32; o > 0; o >>= 1) b0 = min(b0, (long)__shfl_xor(b0, o, 64));
-    if ((threadIdx.x & 63) == 0) wmin4[threadIdx.x >> 6] = b0;
+    if ((threadIdx.x & 63) == 0) wminw[threadIdx.x >> 6] = b0;
     __syncthreads();
-    const long m = min(min(wmin4[0], wmin4[1]), min(wmin4[2], wmin4[3]));
+    long m = wminw[0];
+#pragma unroll
+    for (int k = 1; k < WPB; ++k) m = min(m, wminw[k]);
     const long base = m == LONG_MAX ? 0 : max(0L, m - KW / 4);
     for (int k = threadIdx.x; k < KW; k += PT) {
         const long b = base + k;
@@ -1016,12 +1046,12 @@ template <typename T, typename MT, int DIM>
 __device__ void place_chunk(const Geo& g, const BinCount& bc, int mode, uint32_t c1, uint32_t tag,
                             long ch, long ch_start, long cnt_ch, long s_lo, long s_hi, T* xo,
                             T* yo, MT* Mo, MT* Myo, int8_t* so, long long capacity, int* bo_ex,
-                            int* bo_in, int* lds5) {
+                            int* bo_in, int* ldsw) {
     constexpr int Q = DIM == 1 ? 4 : 2;
     const long b = ch * BC + threadIdx.x;
     const int cnt = b < g.n_bins ? (int)bc(b) : 0;
     int tc;
-    const int ex = block_excl_scan_256(cnt, &tc, lds5);
+    const int ex = block_excl_scan_pt(cnt, &tc, ldsw);
     bo_ex[threadIdx.x] = ex;
     bo_in[threadIdx.x] = ex + cnt;
     // this bin's cell, momenta and sign, once per bin (32-bit index arithmetic: n_bins < 2^31)
@@ -1184,7 +1214,7 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
     constexpr int STAGE = WT * (DIM * (int)sizeof(T) + DIM * (int)sizeof(int) + 1);  // per wave
     constexpr int KEEP_LDS = WPB * STAGE + 2 * KW * (int)sizeof(int);
     constexpr int PLACE_LDS = 2 * PT * (int)sizeof(int) + 7 * BC * (int)sizeof(int);
-    __shared__ int lds5[5];
+    __shared__ int ldsw[WPB];
     __shared__ long wmin[PT / 64];
     // keepers: one stage per wave + histogram window; placers: chunk and bin prefix tables
     __shared__ __align__(16) char smem[KEEP_LDS > PLACE_LDS ? KEEP_LDS : PLACE_LDS];
@@ -1268,7 +1298,7 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
         for (long g0 = j0; g0 < j1; g0 += PT) {  // chunk sums in groups of PT
             const int cs = g0 + threadIdx.x < j1 ? w.csum[g0 + threadIdx.x] : 0;
             int tot;
-            const int ex = block_excl_scan_256(cs, &tot, lds5);
+            const int ex = block_excl_scan_pt(cs, &tot, ldsw);
             cs_ex[threadIdx.x] = ex;
             cs_in[threadIdx.x] = ex + cs;
             __syncthreads();
@@ -1281,7 +1311,7 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
                     if (cnt_ch == 0) continue;
                     place_chunk<T, MT, DIM>(g, bc, mode, c1, tag, g0 + i, ch_start, cnt_ch, s_lo,
                                             s_hi, xo, yo, Mo, Myo, so, capacity, bo_ex, bo_in,
-                                            lds5);
+                                            ldsw);
                 }
             }
             run += tot;
