@@ -114,7 +114,8 @@ __device__ __forceinline__ T cell_plus_frac(int c, uint32_t u, int fb) {
     return (T)c + frac;
 }
 
-// Histogram bin of a particle, -1 when dead or outside the grid.
+// Histogram bin of a particle, -1 when dead or outside the grid.  n_bins < 2^31 (checked on
+// the host) and every partial sum below is at most the bin index: 32-bit arithmetic is exact.
 template <typename T, int DIM>
 __device__ __forceinline__ long bin_val(const Geo& g, T x, T y, int m, int my, int8_t s) {
     if (s == 0) return -1;
@@ -122,12 +123,12 @@ __device__ __forceinline__ long bin_val(const Geo& g, T x, T y, int m, int my, i
     if (cx < 0) return -1;
     const int kx = m - g.M_min;
     if (kx < 0 || kx >= g.n_k) return -1;
-    if (DIM == 1) return (long)cx * g.n_k + kx;
+    if (DIM == 1) return (long)(cx * g.n_k + kx);
     const int cy = cell_index<T>(y, g.ny);
     if (cy < 0) return -1;
     const int ky = my - g.M_min;
     if (ky < 0 || ky >= g.n_k) return -1;
-    return (((long)cy * g.nx + cx) * g.n_k + ky) * g.n_k + kx;
+    return (long)(((cy * g.nx + cx) * g.n_k + ky) * g.n_k + kx);
 }
 
 // Four consecutive particles (ids id .. id+3, id a multiple of 4) loaded with 16-byte
@@ -525,16 +526,17 @@ struct HistWindow {
     }
 
     // one particle per lane (b < 0: none); all 64 lanes of the wave must call it together
+    // (32-bit keys 2 b + sign: n_bins < 2^31, and EMPTY marks "no particle")
     __device__ __forceinline__ void add_wave(long b, int8_t sv) {
         const int lane = threadIdx.x & 63;
-        const long long key = b < 0 ? -1LL : 2LL * b + (sv > 0 ? 0 : 1);
-        const long long prev = __shfl_up(key, 1, 64);
+        const uint32_t key = b < 0 ? EMPTY : 2u * (uint32_t)b + (sv > 0 ? 0u : 1u);
+        const uint32_t prev = (uint32_t)__shfl_up((int)key, 1, 64);
         const bool head = lane == 0 || prev != key;
         const unsigned long long heads = __ballot(head);
-        if (head && key >= 0) {
+        if (head && key != EMPTY) {
             const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1));
             const int next = above ? lane + 1 + __builtin_ctzll(above) : 64;
-            bump((long)(key >> 1), (int)(key & 1), next - lane);
+            bump((long)(key >> 1), (int)(key & 1u), next - lane);
         }
     }
 
