@@ -517,8 +517,8 @@ struct HistWindow {
             }
             atomicAdd(&hist[sg * n_bins + b], cnt);
         } else {
-            const long k = b - base;
-            if (k >= 0 && k < W)
+            const int k = (int)b - (int)base;  // bins and base are below 2^31
+            if ((unsigned)k < (unsigned)W)
                 atomicAdd(&lh[sg * W + k], cnt);
             else
                 atomicAdd(&hist[sg * n_bins + b], cnt);
@@ -803,11 +803,12 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
         load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
         int np[IT];
         load_np4<T>(xo, so, id, hi, np);  // left by pass 1 (before the parents overwrite it below)
-        long long npt = 0;
+        // after the capacity check all pairs of the step number below 2^30: 32-bit sums
+        int npt = 0;
 #pragma unroll
         for (int k = 0; k < IT; ++k) npt += np[k];
-        const long long inc = wave_incl_scan_ll(npt);
-        long o = n + 2 * (long)(run + inc - npt);  // this lane's first child slot
+        const int inc = wave_incl_scan(npt);
+        long o = n + 2 * (long)(run + (inc - npt));  // this lane's first child slot
         run += __shfl(inc, 63, 64);
         // queue the creating particles (at most WT per tile; room was left by the last drain)
 #pragma unroll
@@ -882,9 +883,9 @@ struct KeepWindow {
 
     __device__ __forceinline__ bool keeps(long b) const {
         if (b < 0) return false;
-        const long k = b - base;
+        const int k = (int)b - (int)base;  // bins and base are below 2^31
         int hp, hm;
-        if (k >= 0 && k < KW) {
+        if ((unsigned)k < (unsigned)KW) {
             hp = lw[k];
             hm = lw[KW + k];
         } else {
