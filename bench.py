@@ -41,8 +41,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # --copy-calibration`, scaled by what the counters read for a 1 GiB device copy (fetch x2.0,
 # write x1.0).  Taken for the kernels as they are now; an entry is dropped when its kernel
 # changes until the counters are taken again.
-TRAFFIC = {"step_count": 0.0671, "step_apply": 0.2084, "annih_count": 0.0916,
-           "annih_scan": 0.0001, "annih_write": 0.1692}
+TRAFFIC = {"step_count": 0.0671, "step_apply": 0.2082, "annih_count": 0.0920,
+           "annih_scan": 0.0001, "annih_write": 0.1693}
 
 
 def _events():
