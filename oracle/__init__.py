@@ -19,6 +19,8 @@ Parity status (see the tests for each pin):
   surrogate_fwd .................. pinned (N=1 equals eq.(4); N=2 equals the
                                    barycentric form of Sec. 2.3)
   surrogate_bwd .................. pinned (finite differences in high precision)
+  mse_grad, sgd_step ............. pinned (finite differences of the loss, first-order
+                                   descent prediction, fixed point at zero residual)
 """
 from __future__ import annotations
 
@@ -64,7 +66,7 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).restype = i32
         L.oracle_kernel_2d.argtypes = [i32, i32, i32, f64, P, i32, P, i32, P]
         L.oracle_kernel_2d.restype = i32
-        L.oracle_kernel_bwd_1d.argtypes = [i32, i32, f64, P, i32, P]
+        L.oracle_kernel_bwd_1d.argtypes = [i32, i32, f64, P, i32, P, i32, P]
         L.oracle_kernel_bwd_1d.restype = i32
         L.oracle_gamma_tables.argtypes = [i32, P, i32, f64, P, P, P, P]
         L.oracle_gamma_tables.restype = i32
@@ -80,6 +82,10 @@ def lib() -> ctypes.CDLL:
         L.oracle_surrogate_fwd.restype = i32
         L.oracle_surrogate_bwd.argtypes = [i32, i32, i32, P, P, P, P, i32, P, i32, P, P, P, P, P]
         L.oracle_surrogate_bwd.restype = i32
+        L.oracle_mse_grad.argtypes = [P, P, i64, f64, P]
+        L.oracle_mse_grad.restype = f64
+        L.oracle_sgd_step.argtypes = [i32, i32, i32, f64, P, i32, P, f64, f64, f64, f64, P, P, P]
+        L.oracle_sgd_step.restype = f64
         _lib = L
     return _lib
 
@@ -138,13 +144,20 @@ def kernel_2d(V, n_m: int, hbar: float, cells=None) -> np.ndarray:
     return K
 
 
-def kernel_bwd_1d(G, n_m: int, hbar: float) -> np.ndarray:
-    """dV of <G, K_half(V)> for the all-cells half table (adjoint of eq.(4) in V)."""
+def kernel_bwd_1d(G, n_m: int, hbar: float, nx: int | None = None, cells=None) -> np.ndarray:
+    """dV of <G, K_half(V)> for the half table of eq.(4) on the requested cells (all cells
+    when `cells` is None): the adjoint of eq.(4) in V, which is linear in V."""
     G = _f64(G)
-    B, nx, P = G.shape
+    B, nc, P = G.shape
     assert P == n_m // 2
+    c = _cells(cells)
+    if c is None:
+        nx = nc if nx is None else nx
+        assert nx == nc
+    else:
+        assert nx is not None and len(c) == nc
     dV = np.zeros((B, nx))
-    _check(lib().oracle_kernel_bwd_1d(nx, n_m, hbar, _p(G), B, _p(dV)), "kernel_bwd_1d")
+    _check(lib().oracle_kernel_bwd_1d(nx, n_m, hbar, _p(G), B, _p(c), nc, _p(dV)), "kernel_bwd_1d")
     return dV
 
 
@@ -304,3 +317,31 @@ def surrogate_bwd(V, n_m: int, N: int, wV, wT, W, E, cells=None, want_dV: bool =
 def analytic_weights(n_m: int, N: int, hbar: float):
     """Barycentric weights of Sec. 2.3: wV = 1, wT = 1/N, W = -2/(hbar n_m)."""
     return (np.ones(N), np.full(N, 1.0 / N), np.full(n_m // N, -2.0 / (hbar * n_m)))
+
+
+# ----------------------------------------------------------------------------- training
+def mse_grad(Kh, K, inv_scale: float):
+    """MSE of Sec. 3 on targets scaled by inv_scale: (loss, dloss/dKh)."""
+    Kh, K = _f64(Kh), _f64(K)
+    E = np.empty_like(Kh)
+    loss = lib().oracle_mse_grad(_p(Kh), _p(K), Kh.size, float(inv_scale), _p(E))
+    return loss, E
+
+
+def sgd_step(V, K, n_m: int, N: int, hbar: float, weights, lr, inv_scale: float | None = None):
+    """One SGD step of Sec. 3 on a batch (all cells) with labels K [B][nx][P]; returns
+    (loss before the step, (wV, wT, W) after it).  lr: one value or (lr_V, lr_T, lr_W), W
+    stepped in units of c = -2/(hbar n_m)."""
+    V = _f64(np.atleast_2d(V))
+    B, nx = V.shape
+    K = _f64(K)
+    assert K.shape == (B, nx, n_m // 2)
+    lr_V, lr_T, lr_W = (lr, lr, lr) if np.isscalar(lr) else lr
+    if inv_scale is None:
+        inv_scale = hbar * n_m / 2.0
+    wV, wT, W = (_f64(w).copy() for w in weights)
+    loss = lib().oracle_sgd_step(nx, n_m, N, hbar, _p(V), B, _p(K), float(inv_scale), float(lr_V),
+                                 float(lr_T), float(lr_W), _p(wV), _p(wT), _p(W))
+    if loss < 0:
+        raise ValueError("oracle sgd_step failed")
+    return loss, (wV, wT, W)

@@ -204,14 +204,18 @@ int oracle_kernel_2d(int nx, int ny, int n_m, double hbar, const double* V, int 
 
 /* Adjoint of the 1-D map V -> half table K[b][i][t] (m = t+1), all cells:
  * K = c sum_j sin(2 pi j m/n_m) (V[cl(i+j)] - V[cl(i-j)]) is linear in V. */
-int oracle_kernel_bwd_1d(int nx, int n_m, double hbar, const double* G, int B, double* dV) {
-    if (nx <= 0 || n_m <= 0 || (n_m & 1) || B < 0 || hbar <= 0) return -1;
+int oracle_kernel_bwd_1d(int nx, int n_m, double hbar, const double* G, int B,
+                         const int32_t* cells, int n_cells, double* dV) {
+    if (nx <= 0 || n_m <= 0 || (n_m & 1) || B < 0 || n_cells < 0 || hbar <= 0) return -1;
+    if (!cells && n_cells != nx) return -1;
     const int P = n_m / 2;
     const double c = -2.0 / (hbar * (double)n_m);
     for (int b = 0; b < B; ++b) {
         double* dVb = dV + (long)b * nx;
-        for (long i = 0; i < nx; ++i) {
-            const double* g = G + ((long)b * nx + i) * P;
+        for (long r = 0; r < n_cells; ++r) {
+            const long i = cells ? cells[r] : r;
+            if (i < 0 || i >= nx) return -1;
+            const double* g = G + ((long)b * n_cells + r) * P;
             for (long j = 1; j <= P; ++j) {
                 double gd = 0.0;
                 for (long t = 0; t < P; ++t) gd += g[t] * sin_frac(j * (t + 1), n_m);
@@ -632,4 +636,57 @@ int oracle_surrogate_bwd(int nx, int n_m, int N, const double* wV, const double*
         }
     }
     return 0;
+}
+
+/* ---------------------------------------------------------------- training (Sec. 3) */
+/* Mean squared error of the network against labels, on targets scaled by inv_scale:
+ *   loss = sum ((Kh - K) inv_scale)^2 / count,  E = dloss/dKh = 2 (Kh - K) inv_scale^2 / count. */
+double oracle_mse_grad(const double* Kh, const double* K, int64_t count, double inv_scale,
+                       double* E) {
+    double loss = 0.0;
+    const double s2 = inv_scale * inv_scale;
+    for (int64_t k = 0; k < count; ++k) {
+        const double d = Kh[k] - K[k];
+        loss += d * d * s2;
+        if (E) E[k] = 2.0 * d * s2 / (double)count;
+    }
+    return loss / (double)count;
+}
+
+/* One step of stochastic gradient descent on that loss over a batch of B potentials (all
+ * cells), with the labels K [B][nx][P] given: forward of eq.(5), loss and its gradient, the
+ * backward, then w <- w - lr g per group, with W stepped in units of c = -2/(hbar n_m), i.e.
+ * W <- W - lr_W c^2 dL/dW.  Returns the loss before the step (negative on bad arguments). */
+double oracle_sgd_step(int nx, int n_m, int N, double hbar, const double* V, int B,
+                       const double* K, double inv_scale, double lr_V, double lr_T, double lr_W,
+                       double* wV, double* wT, double* W) {
+    if (nx <= 0 || n_m <= 0 || (n_m & 1) || N <= 0 || n_m % N || B <= 0 || hbar <= 0) return -1.0;
+    const int P = n_m / 2, H = n_m / N;
+    const int64_t count = (int64_t)B * nx * P;
+    double* Kh = (double*)malloc(sizeof(double) * (size_t)count);
+    double* E = (double*)malloc(sizeof(double) * (size_t)count);
+    double* gV = (double*)malloc(sizeof(double) * (size_t)N);
+    double* gT = (double*)malloc(sizeof(double) * (size_t)N);
+    double* gW = (double*)malloc(sizeof(double) * (size_t)H);
+    double loss = -1.0;
+    if (Kh && E && gV && gT && gW &&
+        oracle_surrogate_fwd(nx, n_m, N, wV, wT, W, V, B, NULL, nx, Kh) == 0) {
+        loss = oracle_mse_grad(Kh, K, count, inv_scale, E);
+        if (oracle_surrogate_bwd(nx, n_m, N, wV, wT, W, V, B, NULL, nx, E, gV, gT, gW, NULL) == 0) {
+            const double c = -2.0 / (hbar * (double)n_m);
+            for (int p = 0; p < N; ++p) {
+                wV[p] -= lr_V * gV[p];
+                wT[p] -= lr_T * gT[p];
+            }
+            for (int g = 0; g < H; ++g) W[g] -= lr_W * c * c * gW[g];
+        } else {
+            loss = -1.0;
+        }
+    }
+    free(Kh);
+    free(E);
+    free(gV);
+    free(gT);
+    free(gW);
+    return loss;
 }

@@ -39,8 +39,10 @@ int oracle_kernel_1d_literal(int nx, int n_m, double hbar, const double* V, int 
  * cells are flat ids iy*nx+ix; output [B][n_cells][n_m][n_m] (ty, tx). */
 int oracle_kernel_2d(int nx, int ny, int n_m, double hbar, const double* V, int B,
                      const int32_t* cells, int n_cells, double* K);
-/* Adjoint of V -> half table (1-D, all cells): dV[b][l] += sum G * dK/dV[l]. */
-int oracle_kernel_bwd_1d(int nx, int n_m, double hbar, const double* G, int B, double* dV);
+/* Adjoint of V -> half table (1-D) on the requested cells (NULL = all, n_cells = nx):
+ * G [B][n_cells][P]; dV[b][l] += sum_{r,t} G[b][r][t] dK(cells[r], t + 1)/dV[b][l]. */
+int oracle_kernel_bwd_1d(int nx, int n_m, double hbar, const double* G, int B,
+                         const int32_t* cells, int n_cells, double* dV);
 
 /* eq.(1) on the grid and the integer sampling tables (width = entries per row). */
 int oracle_gamma_tables(int width, const double* K, int n_rows, double dt,
@@ -78,6 +80,17 @@ int oracle_surrogate_bwd(int nx, int n_m, int N, const double* wV, const double*
                          const double* W, const double* V, int B, const int32_t* cells,
                          int n_cells, const double* E, double* dwV, double* dwT, double* dW,
                          double* dV);
+
+/* Training of Sec. 3.  MSE on targets scaled by inv_scale; returns the loss and writes
+ * E = dloss/dKh (E may be NULL). */
+double oracle_mse_grad(const double* Kh, const double* K, int64_t count, double inv_scale,
+                       double* E);
+/* One SGD step on a batch of B potentials (all cells) with labels K [B][nx][P]: updates wV,
+ * wT (step lr_V, lr_T) and W (step lr_W in units of c = -2/(hbar n_m)) in place; returns the
+ * loss before the step. */
+double oracle_sgd_step(int nx, int n_m, int N, double hbar, const double* V, int B,
+                       const double* K, double inv_scale, double lr_V, double lr_T, double lr_W,
+                       double* wV, double* wT, double* W);
 
 #ifdef __cplusplus
 }

@@ -268,3 +268,39 @@ def test_kernel_adjoint_dot_product(orc):
     lhs = np.sum(G * Kh)
     rhs = np.sum(orc.kernel_bwd_1d(G, n_m, HB) * dV)
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_kernel_adjoint_cells_dot_product(orc):
+    """The same identity on a cell list with repeats and both edges: rows of the forward on
+    `cells` against the adjoint on `cells` (the forward is pinned independently above)."""
+    rng = np.random.default_rng(12)
+    n_m, nx, B = 20, 37, 3
+    P = n_m // 2
+    cells = np.array([0, 5, 5, 36, 18, 1, 35, 20, 9], dtype=np.int32)
+    G = rng.normal(size=(B, len(cells), P))
+    dV = rng.normal(size=(B, nx))
+    Kh = orc.full_to_half(orc.kernel_1d(dV, n_m, HB, cells=cells))
+    lhs = np.sum(G * Kh)
+    rhs = np.sum(orc.kernel_bwd_1d(G, n_m, HB, nx=nx, cells=cells) * dV)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # the all-cells list in order is the all-cells adjoint
+    Ga = rng.normal(size=(B, nx, P))
+    a = orc.kernel_bwd_1d(Ga, n_m, HB)
+    b = orc.kernel_bwd_1d(Ga, n_m, HB, nx=nx, cells=np.arange(nx, dtype=np.int32))
+    assert np.array_equal(a, b)
+
+
+def test_kernel_adjoint_cells_finite_difference(orc):
+    """K is linear in V, so one finite difference per coordinate is exact up to rounding:
+    dL/dV[l] = L(e_l) for L(V) = <G, K(V)> on the cell list."""
+    rng = np.random.default_rng(13)
+    n_m, nx = 12, 15
+    P = n_m // 2
+    cells = np.array([2, 14, 7, 0, 7], dtype=np.int32)
+    G = rng.normal(size=(1, len(cells), P))
+    grad = orc.kernel_bwd_1d(G, n_m, HB, nx=nx, cells=cells)[0]
+    for l in range(nx):
+        e = np.zeros(nx)
+        e[l] = 1.0
+        fd = np.sum(G * orc.full_to_half(orc.kernel_1d(e, n_m, HB, cells=cells)))
+        assert abs(fd - grad[l]) <= 1e-13 * max(1.0, abs(fd)) / HB
