@@ -192,6 +192,7 @@ def run_learning(B=64, N=4, reps=5):
     E = torch.empty_like(Kh)
     loss = torch.empty(1, dtype=torch.float64, device=dev)
     mws = torch.empty(8 * 1024, dtype=torch.uint8, device=dev)
+    fws = learn.surrogate_fwd_workspace(n_m, N, dev)
     G = torch.randn((B * nx, P), dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
     dV = torch.zeros((B, nx), dtype=torch.float64, device=dev)
 
@@ -199,7 +200,7 @@ def run_learning(B=64, N=4, reps=5):
         ops.kernel_eval(V, n_m, layout="half", out=Klab)
 
     def fwd():
-        learn.surrogate_fwd(V, n_m, N, wV, wT, W, prec="fp32", out=Kh)
+        learn.surrogate_fwd(V, n_m, N, wV, wT, W, prec="fp32", out=Kh, ws=fws)
 
     def mse():
         learn.mse_grad(Kh, Klab, inv_scale, E=E, loss=loss, ws=mws)
@@ -306,8 +307,9 @@ def run_surrogate_forms():
     # N sweep of eq.(5): N cos factors, H = n_m / N sinusoid groups (N = 1 is eq.(4) itself)
     for N in (1, 2, 4, 8, 16):
         w = learn.analytic_weights(n_m, N)
+        fws = learn.surrogate_fwd_workspace(n_m, N, "cuda")
         for prec in ("fp32", "bf16"):
-            ms = timeit(lambda: learn.surrogate_fwd(V, n_m, N, *w, prec=prec, out=Kb))
+            ms = timeit(lambda: learn.surrogate_fwd(V, n_m, N, *w, prec=prec, out=Kb, ws=fws))
             err = float(((Kb.double() - K).reshape(B, -1).abs().amax(dim=1) / kmax).max())
             res[f"N{N}_H{n_m // N}_{prec}"] = {"ms": round(ms, 3), "entries_per_s": entries / (ms * 1e-3),
                                               "normwise_err_vs_exact": err}

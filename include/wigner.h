@@ -11,9 +11,12 @@
  *   - Return value: WK_OK (0) or a negative code.  Arguments are validated on the host
  *     before anything is enqueued; on WK_EINVAL nothing is enqueued.  wk_last_error()
  *     returns a thread-local description of the last failure.
- *   - The library keeps, per device, read-only sine tables it builds on first use of a
- *     given n_m (device memory held until the process ends).  Apart from that first use
- *     no call allocates memory: scratch space is the caller's workspace argument.
+ *   - Set-up: wk_prepare(mesh) builds, per device and n_m, the read-only sine tables the
+ *     1-D contractions read (device memory held until the process ends); it allocates and
+ *     synchronises its stream, and must be called once per device and n_m before
+ *     wk_kernel_eval, wk_kernel_tables or wk_kernel_bwd use that n_m in 1-D (they fail with
+ *     WK_EINVAL otherwise).  No other call allocates memory or synchronises: scratch
+ *     space is the caller's workspace argument.
  *   - Results are deterministic: identical inputs give bit-identical outputs.
  *
  * Mesh and tables (Sec. 2.2 of the paper)
@@ -54,7 +57,7 @@ extern "C" {
 #define WK_ECAPACITY (-2)  /* particle buffer too small (see WK_ST_NEEDED) */
 #define WK_EHIP (-3)       /* HIP runtime error (message in wk_last_error) */
 
-#define WK_VERSION 1
+#define WK_VERSION 2
 
 /* Arithmetic of the kernel contraction. */
 enum wk_prec {
@@ -62,7 +65,8 @@ enum wk_prec {
     WK_BF16 = 1,    /* BF16 operands, FP32 accumulate, FP32 output */
     WK_FP16 = 2,    /* FP16 operands, FP32 accumulate, FP32 output */
     WK_BF16X3 = 3,  /* hi/lo BF16 split, three products, FP32 accumulate and output */
-    WK_FP16X3 = 4   /* hi/lo FP16 split, three products, FP32 accumulate and output */
+    WK_FP16X3 = 4,  /* hi/lo FP16 split, three products, FP32 accumulate and output */
+    WK_FP32 = 5     /* FP32 operands and arithmetic (wk_kernel_bwd, wk_surrogate_fwd) */
 };
 
 enum wk_layout { WK_FULL = 0, WK_HALF = 1 };
@@ -138,7 +142,14 @@ int wk_trace_names(char* buf, size_t len);
 int wk_device_count(void);
 
 /* ------------------------------------------------------------------ Wigner kernel
- * wk_kernel_eval -- eq.(4) of Sec. 2.2 (the "N = 1" analytic network of Sec. 2.2):
+ * wk_prepare -- set-up for a mesh's n_m on the current device: builds the sine tables of
+ * eq.(4) (S[j][m] = sin(2 pi j m / n_m) in the folded, transposed and 16-bit / FP32 forms
+ * the 1-D contractions read).  Allocates device memory (kept until the process ends) and
+ * synchronises `stream`; a repeated call for the same device and n_m does nothing.  Not
+ * needed in 2-D.  Calls on several threads are serialised. */
+int wk_prepare(const wk_mesh* mesh, void* stream);
+
+/* wk_kernel_eval -- eq.(4) of Sec. 2.2 (the "N = 1" analytic network of Sec. 2.2):
  *   K(i, m) = -2/(hbar n_m) sum_{j=1..P} sin(2 pi j m / n_m) [V(i+j) - V(i-j)]
  * in 1-D, and its d = 2 form (weights 1/2 at |j_a| = P) in 2-D, evaluated only on the
  * requested cells (the point of the method: no table over the whole phase space).
@@ -153,13 +164,20 @@ int wk_device_count(void);
 int wk_kernel_eval(const wk_mesh* mesh, const double* V, int32_t B, const int32_t* cells,
                    int32_t n_cells, int32_t prec, int32_t layout, void* K_out, void* stream);
 
-/* wk_kernel_bwd -- adjoint of wk_kernel_eval (1-D, all cells, WK_FP64) with respect to V:
- *   dV[b][l] += sum_{i,t} G[b][i][t] dK[b][i][t] / dV[b][l]
- * (K is linear in V, eq.(4)).  G has the layout given by `layout`, double.  dV is
- * accumulated into (not overwritten).  ws: workspace of wk_kernel_bwd_workspace() bytes. */
-size_t wk_kernel_bwd_workspace(const wk_mesh* mesh, int32_t B);
-int wk_kernel_bwd(const wk_mesh* mesh, const double* G, int32_t B, int32_t layout, double* dV,
-                  void* ws, size_t ws_bytes, void* stream);
+/* wk_kernel_bwd -- adjoint of wk_kernel_eval (1-D) with respect to V, on the same rows:
+ *   dV[b][l] += sum_{r,t} G[row][t] dK[row][t] / dV[b][l],   row = b * n_cells + r,
+ * where K is eq.(4) on cell cells[r] (or r when cells is NULL; then n_cells = nx).  K is
+ * linear in V, so this is the exact derivative for any V.
+ *   G      [B * n_cells][n_m] (WK_FULL) or [B * n_cells][P] (WK_HALF): double for WK_FP64,
+ *          float for WK_FP32 (the product then runs on FP32 MFMA, sums in FP32).
+ *   cells  int32 ids in any order, repeats allowed; ids outside [0, nx) contribute nothing.
+ *   dV     [B][nx] double, accumulated into (not overwritten).
+ *   ws     workspace of wk_kernel_bwd_workspace(mesh, B, n_cells, prec) bytes.
+ * Deterministic: fixed-order sums, no floating-point atomics. */
+size_t wk_kernel_bwd_workspace(const wk_mesh* mesh, int32_t B, int32_t n_cells, int32_t prec);
+int wk_kernel_bwd(const wk_mesh* mesh, const void* G, int32_t B, const int32_t* cells,
+                  int32_t n_cells, int32_t prec, int32_t layout, double* dV, void* ws,
+                  size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ creation tables
  * wk_gamma_tables -- eq.(1) on the grid and the integer sampling tables of postulate II:
@@ -288,11 +306,15 @@ int sp_assign_slots(const int32_t* new_cells, const int64_t* d_count, int32_t ma
  * With wV = 1, wT = 1/N, W = -2/(hbar n_m): N = 1 is eq.(4) exactly, N = 2 the
  * barycentric form of Sec. 2.3.
  *   N power of two dividing n_m; wV, wT [N] and W [n_m/N] float (device).
- *   prec WK_FP64 (double out, reference arithmetic), WK_BF16 (bf16 products,
- *   FP32 accumulate) or any other value for FP32 (training); K_out [B*n_cells][P]. */
+ *   prec WK_FP64 (double out, reference arithmetic), WK_FP32 (FP32 MFMA; training) or
+ *   WK_BF16 (bf16 products, FP32 accumulate); K_out [B*n_cells][P].
+ *   ws   workspace of wk_surrogate_fwd_workspace(mesh, N) bytes (the per-call tables
+ *        W[g] sin(u_g m) and the cos prefactor); calls sharing a workspace must not overlap. */
+size_t wk_surrogate_fwd_workspace(const wk_mesh* mesh, int32_t N);
 int wk_surrogate_fwd(const wk_mesh* mesh, int32_t N, const float* wV, const float* wT,
                      const float* W, const double* V, int32_t B, const int32_t* cells,
-                     int32_t n_cells, int32_t prec, void* K_out, void* stream);
+                     int32_t n_cells, int32_t prec, void* K_out, void* ws, size_t ws_bytes,
+                     void* stream);
 
 /* wk_surrogate_bwd -- gradients of L = sum E * Kh with respect to wV, wT, W (written,
  * float) and V (accumulated into dV [B][nx] double, may be NULL); E [B*n_cells][P] float.

@@ -12,7 +12,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwigner.so")
 
 WK_OK, WK_EINVAL, WK_ECAPACITY, WK_EHIP = 0, -1, -2, -3
-WK_FP64, WK_BF16, WK_FP16, WK_BF16X3, WK_FP16X3 = 0, 1, 2, 3, 4
+WK_FP64, WK_BF16, WK_FP16, WK_BF16X3, WK_FP16X3, WK_FP32 = 0, 1, 2, 3, 4, 5
 WK_FULL, WK_HALF = 0, 1
 (ST_N, ST_PAIRS, ST_ABS_X, ST_ABS_M, ST_NEEDED, ST_KEPT, ST_REGEN, ST_MIXED,
  ST_OVERFLOW, ST_OVERFLOW_STEP, ST_CUM_STEPS, ST_CUM_N, ST_CUM_PAIRS, ST_CUM_ANNIH_IN,
@@ -54,8 +54,9 @@ SIGNATURES = {
     "wk_trace_read": (ctypes.c_int, [ctypes.c_char_p, _P, _P]),
     "wk_trace_names": (ctypes.c_int, [ctypes.c_char_p, _sz]),
     "wk_kernel_eval": (ctypes.c_int, [_MP, _P, _i32, _P, _i32, _i32, _i32, _P, _P]),
-    "wk_kernel_bwd_workspace": (_sz, [_MP, _i32]),
-    "wk_kernel_bwd": (ctypes.c_int, [_MP, _P, _i32, _i32, _P, _P, _sz, _P]),
+    "wk_prepare": (ctypes.c_int, [_MP, _P]),
+    "wk_kernel_bwd_workspace": (_sz, [_MP, _i32, _i32, _i32]),
+    "wk_kernel_bwd": (ctypes.c_int, [_MP, _P, _i32, _P, _i32, _i32, _i32, _P, _P, _sz, _P]),
     "wk_gamma_tables": (ctypes.c_int, [_MP, _P, _i32, _i32, _i32, _f64, _P, _P, _P, _P, _P]),
     "sp_workspace_size": (_sz, [_GP]),
     "sp_init": (ctypes.c_int, [_GP, _P, _PP, _P, _P, _sz, _P]),
@@ -66,7 +67,8 @@ SIGNATURES = {
     "sp_density": (ctypes.c_int, [_GP, _P, _f64, _P, _P]),
     "sp_cells_to_evaluate": (ctypes.c_int, [_GP, _P, _i32, _P, _P, _P, _P, _sz, _P]),
     "sp_assign_slots": (ctypes.c_int, [_P, _P, _i32, _i32, _P, _P]),
-    "wk_surrogate_fwd": (ctypes.c_int, [_MP, _i32, _P, _P, _P, _P, _i32, _P, _i32, _i32, _P, _P]),
+    "wk_surrogate_fwd_workspace": (_sz, [_MP, _i32]),
+    "wk_surrogate_fwd": (ctypes.c_int, [_MP, _i32, _P, _P, _P, _P, _i32, _P, _i32, _i32, _P, _P, _sz, _P]),
     "wk_surrogate_workspace": (_sz, [_MP, _i32, _i32, _i32]),
     "wk_surrogate_bwd": (ctypes.c_int, [_MP, _i32, _P, _P, _P, _P, _i32, _P, _i32, _P, _P, _P, _P,
                                         _P, _P, _sz, _P]),

@@ -684,9 +684,9 @@ int kernel_eval_1d_f64(const wk_mesh* mesh, const double* V, int B, const int32_
     const int cfg = fold_cfg(H), BN = fold_bn(cfg), BM = fold_bm(cfg);
     const int Hk = round_up(H, KE_BK), Hn = round_up(H, BN);
     int err = WK_OK;
-    const double* So = static_cast<const double*>(sine_table(n_m, SINE_ODD, Hk, Hn, stream, &err));
+    const double* So = static_cast<const double*>(sine_table(n_m, SINE_ODD, Hk, Hn, &err));
     if (!So) return err;
-    const double* Se = static_cast<const double*>(sine_table(n_m, SINE_EVEN, Hk, Hn, stream, &err));
+    const double* Se = static_cast<const double*>(sine_table(n_m, SINE_EVEN, Hk, Hn, &err));
     if (!Se) return err;
     const double c = -2.0 / (mesh->hbar * (double)n_m);
     dim3 grid((unsigned)((R + BM - 1) / BM), (unsigned)(Hn / BN));
@@ -719,9 +719,9 @@ int kernel_tables_1d_f64(const wk_mesh* mesh, const double* V, int B, const int3
     WK_REQUIRE(8 * waves_m * (n_m + 1) <= 2 * 2 * BM * (KE_BK + 1), "wk_kernel_tables: row stage exceeds LDS");
     const int Hk = round_up(H, KE_BK), Hn = round_up(H, BN);
     int err = WK_OK;
-    const double* So = static_cast<const double*>(sine_table(n_m, SINE_ODD, Hk, Hn, stream, &err));
+    const double* So = static_cast<const double*>(sine_table(n_m, SINE_ODD, Hk, Hn, &err));
     if (!So) return err;
-    const double* Se = static_cast<const double*>(sine_table(n_m, SINE_EVEN, Hk, Hn, stream, &err));
+    const double* Se = static_cast<const double*>(sine_table(n_m, SINE_EVEN, Hk, Hn, &err));
     if (!Se) return err;
     const double c = -2.0 / (mesh->hbar * (double)n_m);
     dim3 grid((unsigned)((R + BM - 1) / BM), 1);
@@ -781,7 +781,7 @@ int kernel_eval_1d_lowp(const wk_mesh* mesh, const double* V, int B, const int32
             T[i] = T[i - 2];
             continue;
         }
-        T[i] = static_cast<const uint16_t*>(sine_table(n_m, kinds[i], Hn, Hk, stream, &err));
+        T[i] = static_cast<const uint16_t*>(sine_table(n_m, kinds[i], Hn, Hk, &err));
         if (!T[i]) return err;
     }
     const float c = (float)(-2.0 / (mesh->hbar * (double)n_m));
@@ -865,44 +865,66 @@ extern "C" int wk_kernel_tables(const wk_mesh* mesh, const double* V, int32_t B,
 // K is linear in V (eq.(4)), so dL/dV = (dK/dV)^T G, computed in three deterministic steps:
 //   1. fold the table gradient onto the unique momenta: G1[r][t] = dL/dK(m = t + 1)
 //      (full layout: G(m) - G(-m), and -G(-P) for m = P);
-//   2. GD[r][jj] = c * sum_t G1[r][t] S[t][jj]  (FP64 MFMA on the odd/even fold below);
-//   3. dV[b][l] += sum_j GD[l - j][j] - sum_j GD[l + j][j], plus at the two edges the sums
-//      of every term whose clamped index lands there (per-row tails, then a fixed-order sum).
+//   2. GD[r][jj] = c * sum_t G1[r][t] S[t][jj]  (MFMA on the odd/even fold below);
+//   3. dV[b][l] += sum_r (GD[r][l - i_r] - GD[r][i_r - l]) over the rows r of potential b with
+//      cell i_r (terms with offsets in [1, P] only), plus at the two edges the sums of every
+//      term whose clamped index lands there (per-row tails, then a fixed-order sum).
+// T = double (FP64 MFMA) or float (FP32 MFMA); dV is double either way.
 namespace wk {
+
+template <typename T> struct BwdMfma;
+template <> struct BwdMfma<double> {
+    typedef f64x4 acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // output element e of a lane sits at row lane / 16 + 4 e of the 16 x 16 tile
+    static __device__ __forceinline__ int row(int lk, int e) { return lk + 4 * e; }
+};
+template <> struct BwdMfma<float> {
+    typedef f32x4 acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // output element e of a lane sits at row 4 (lane / 16) + e of the 16 x 16 tile
+    static __device__ __forceinline__ int row(int lk, int e) { return 4 * lk + e; }
+};
 
 // Step 2 on the odd/even fold (the transpose of the forward's): pairing m with P - m,
 //   GD[r][2k]     = c sum_{m <= H} So[k][m - 1] (G1(m) + G1(P - m))     (j = 2k + 1 odd)
 //   GD[r][2k + 1] = c sum_{m <= H} Se[k][m - 1] (G1(m) - G1(P - m))     (j = 2k + 2 even)
 // (m = P / 2 taken once), two H x H products per row; the fold tables are read transposed,
 // T[m - 1][k].  For odd P the column j = P (all sines zero) is written as 0.
-template <int WM, int WN>
+template <typename T, int WM, int WN>
 __global__ __launch_bounds__(KE_THREADS) void kernel_bwd_gemm(
-    const double* __restrict__ G, long R, int P, int n_m, int layout, int H, int Hk, int Hn,
-    const double* __restrict__ To, const double* __restrict__ Te, double c, double* __restrict__ GD) {
+    const T* __restrict__ G, long R, int P, int n_m, int layout, int H, int Hk, int Hn,
+    const T* __restrict__ To, const T* __restrict__ Te, T c, T* __restrict__ GD) {
+    typedef BwdMfma<T> MF;
+    typedef typename MF::acc_t acc_t;
     constexpr int BM = 32 * WM, BN = 32 * WN, BK = KE_BK;
-    __shared__ double As[2][BM][BK + 1];
+    __shared__ T As[2][BM][BK + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const long row0 = (long)blockIdx.x * BM;
     const int col0 = blockIdx.y * BN;
     const int lr = lane & 15, lk = lane >> 4;
     // dL/dK at momentum m (1 <= m <= P) of row r, from either layout
-    auto g1 = [&](long r, int m) -> double {
+    auto g1 = [&](long r, int m) -> T {
         if (layout == WK_HALF) return G[r * P + (m - 1)];
-        const double* gr = G + r * (long)n_m;
+        const T* gr = G + r * (long)n_m;
         return m < P ? gr[P + m] - gr[P - m] : -gr[0];
     };
-    f64x4 acc[2][WM][WN];
+    acc_t acc[2][WM][WN];
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int a = 0; a < WM; ++a)
 #pragma unroll
-            for (int b = 0; b < WN; ++b) acc[p][a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+            for (int b = 0; b < WN; ++b) acc[p][a][b] = acc_t{0, 0, 0, 0};
     const long cw = (long)col0 + wc * WN * 16 + lr;
-    const double* Tw[2] = {To + cw, Te + cw};
+    const T* Tw[2] = {To + cw, Te + cw};
     for (int k0 = 0; k0 < Hk; k0 += BK) {
-        double bfrag[2][BK / 4][WN];
+        T bfrag[2][BK / 4][WN];
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -914,9 +936,9 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_bwd_gemm(
             const int rr = e / BK, kk = e - rr * BK;
             const long r = row0 + rr;
             const int m = k0 + kk + 1;
-            double gp = 0.0, gm = 0.0;
+            T gp = 0, gm = 0;
             if (r < R && m <= H) {
-                const double a = g1(r, m), b = 2 * m < P ? g1(r, P - m) : 0.0;
+                const T a = g1(r, m), b = 2 * m < P ? g1(r, P - m) : T(0);
                 gp = a + b;
                 gm = a - b;
             }
@@ -928,15 +950,14 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_bwd_gemm(
         for (int ks = 0; ks < BK / 4; ++ks) {
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                double afrag[WM];
+                T afrag[WM];
 #pragma unroll
                 for (int tm = 0; tm < WM; ++tm) afrag[tm] = As[p][(wr * WM + tm) * 16 + lr][4 * ks + lk];
 #pragma unroll
                 for (int tm = 0; tm < WM; ++tm)
 #pragma unroll
                     for (int tn = 0; tn < WN; ++tn)
-                        acc[p][tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(afrag[tm], bfrag[p][ks][tn],
-                                                                            acc[p][tm][tn], 0, 0, 0);
+                        acc[p][tm][tn] = MF::mma(afrag[tm], bfrag[p][ks][tn], acc[p][tm][tn]);
             }
         }
     }
@@ -947,43 +968,68 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_bwd_gemm(
             const int k = col0 + (wc * WN + tn) * 16 + lr;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const long row = row0 + (wr * WM + tm) * 16 + lk + 4 * e;
+                const long row = row0 + (wr * WM + tm) * 16 + MF::row(lk, e);
                 if (row >= R) continue;
                 if (k < H) {
                     GD[row * P + 2 * k] = c * acc[0][tm][tn][e];
                     GD[row * P + 2 * k + 1] = c * acc[1][tm][tn][e];
                 }
-                if ((P & 1) && k == 0) GD[row * P + P - 1] = 0.0;
+                if ((P & 1) && k == 0) GD[row * P + P - 1] = T(0);
             }
         }
 }
 
-// Per row i of potential b: sums of GD over the offsets whose clamped index is an edge.
-// Only rows within P of an edge have such offsets (i >= nx - 1 - P for the upper edge, i <= P
-// for the lower); one wave per such row reads it coalesced and adds with a fixed butterfly.
-// Rows are enumerated per potential: first 0..nlo-1 (nlo = min(P, nx - 1) + 1), then the rest
-// of [nx - 1 - P, nx - 1].
+template <typename T>
+__global__ void kernel_bwd_zero(T* __restrict__ out, long n) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) out[idx] = T(0);
+}
+
+// Per row r (cell i): sums of GD over the offsets whose clamped index is an edge.  Only rows
+// within P of an edge have such offsets (i >= nx - 1 - P for the upper edge, i <= P for the
+// lower).  One wave per row reads it coalesced and adds with a fixed butterfly.
+// All cells (cells == NULL): the rows are enumerated per potential, first 0..nlo-1
+// (nlo = min(P, nx - 1) + 1), then the rest of [nx - 1 - P, nx - 1], and the tails are stored
+// by cell.  Cell lists: one wave per row of the list; rows away from the edges (and ids outside
+// the mesh) store zero tails.
 __device__ __forceinline__ void edge_rows(int nx, int P, int* nlo, int* hi0, int* ne) {
     *nlo = min(P, nx - 1) + 1;
     *hi0 = max(*nlo, nx - 1 - P);
     *ne = *nlo + (nx - *hi0);
 }
 
-__global__ __launch_bounds__(256) void kernel_bwd_tails(const double* __restrict__ GD, int B, int nx, int P,
-                                                        double* __restrict__ tail_hi,
-                                                        double* __restrict__ tail_lo) {
+template <typename T>
+__global__ __launch_bounds__(256) void kernel_bwd_tails(const T* __restrict__ GD, int B, int nx, int P,
+                                                        const int32_t* __restrict__ cells, int n_cells,
+                                                        T* __restrict__ tail_hi, T* __restrict__ tail_lo) {
     const int lane = threadIdx.x & 63;
     const long wid = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    int nlo, hi0, ne;
-    edge_rows(nx, P, &nlo, &hi0, &ne);
-    const long b = wid / ne;
-    if (b >= B) return;
-    const int k = (int)(wid - b * ne);
-    const int i = k < nlo ? k : hi0 + (k - nlo);
-    const double* g = GD + (b * nx + i) * (long)P;
-    double hi = 0.0, lo = 0.0;
+    long row;
+    int i;
+    if (cells == nullptr) {
+        int nlo, hi0, ne;
+        edge_rows(nx, P, &nlo, &hi0, &ne);
+        const long b = wid / ne;
+        if (b >= B) return;
+        const int k = (int)(wid - b * ne);
+        i = k < nlo ? k : hi0 + (k - nlo);
+        row = b * nx + i;
+    } else {
+        if (wid >= (long)B * n_cells) return;
+        row = wid;
+        i = cells[wid % n_cells];
+        if (i < 0 || i >= nx || (i > P && i < nx - 1 - P)) {
+            if (lane == 0) {
+                tail_hi[row] = T(0);
+                tail_lo[row] = T(0);
+            }
+            return;
+        }
+    }
+    const T* g = GD + row * (long)P;
+    T hi = 0, lo = 0;
     for (int j = 1 + lane; j <= P; j += 64) {
-        const double v = g[j - 1];
+        const T v = g[j - 1];
         if (i + j >= nx - 1) hi += v;  // V(i + j) clamps to (or is) cell nx - 1
         if (i - j <= 0) lo += v;       // V(i - j) clamps to (or is) cell 0
     }
@@ -992,27 +1038,28 @@ __global__ __launch_bounds__(256) void kernel_bwd_tails(const double* __restrict
         lo += __shfl_xor(lo, o, 64);
     }
     if (lane == 0) {
-        tail_hi[b * nx + i] = hi;
-        tail_lo[b * nx + i] = lo;
+        tail_hi[row] = hi;
+        tail_lo[row] = lo;
     }
 }
 
-// A workgroup takes 64 consecutive outputs l of one potential and walks the rows they need;
-// its four waves take every fourth row.  At row i a wave's lanes read consecutive columns of
-// GD (ascending for the terms GD[l - j][j - 1], descending for GD[l + j][j - 1]), so each load
-// is one contiguous segment.  The four partial sums of an output are added in wave order, then
-// the edge tails (fixed order).
-__global__ __launch_bounds__(256) void kernel_bwd_gather(const double* __restrict__ GD, int B, int nx, int P,
-                                                         const double* __restrict__ tail_hi,
-                                                         const double* __restrict__ tail_lo,
+// All cells: a workgroup takes 64 consecutive outputs l of one potential and walks the rows
+// they need; its four waves take every fourth row.  At row i a wave's lanes read consecutive
+// columns of GD (ascending for the terms GD[l - j][j - 1], descending for GD[l + j][j - 1]),
+// so each load is one contiguous segment.  The four partial sums of an output are added in
+// wave order, then the edge tails (fixed order).
+template <typename T>
+__global__ __launch_bounds__(256) void kernel_bwd_gather(const T* __restrict__ GD, int B, int nx, int P,
+                                                         const T* __restrict__ tail_hi,
+                                                         const T* __restrict__ tail_lo,
                                                          double* __restrict__ dV) {
-    __shared__ double part[4][64];
+    __shared__ T part[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const long wpp = (nx + 63) / 64;  // output groups per potential
     const long b = blockIdx.x / wpp;
     const int l0 = (int)(blockIdx.x - b * wpp) * 64, l = l0 + lane;
-    const double* g = GD + b * (long)nx * P;
-    double acc = 0.0;
+    const T* g = GD + b * (long)nx * P;
+    T acc = 0;
     // rows i = l - j, j = 1..P (outputs l < nx - 1)
     const int i1 = min(l0 + 62, nx - 1);
 #pragma unroll 4
@@ -1030,65 +1077,166 @@ __global__ __launch_bounds__(256) void kernel_bwd_gather(const double* __restric
     part[wv][lane] = acc;
     __syncthreads();
     if (wv == 0 && l < nx) {
-        double t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        T t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
         // edge tails: only the rows within P of the edge have them (see kernel_bwd_tails)
         if (l == nx - 1)
             for (int i = max(0, nx - 1 - P); i < nx; ++i) t += tail_hi[b * nx + i];
         if (l == 0)
             for (int i = 0; i <= min(P, nx - 1); ++i) t -= tail_lo[b * nx + i];
-        dV[b * (long)nx + l] += t;
+        dV[b * (long)nx + l] += (double)t;
     }
+}
+
+// Cell lists: a workgroup takes 64 consecutive outputs l of one potential; its four waves take
+// every fourth row of the potential's list (the cell id is wave-uniform).  Row r with cell i
+// adds GD[r][l - i - 1] for l - i in [1, P] (l < nx - 1) and subtracts GD[r][i - l - 1] for
+// i - l in [1, P] (l > 0): each a contiguous segment of the row across the lanes.  Rows whose
+// window misses the group are skipped; ids outside the mesh contribute nothing.  Partial
+// sums are added in wave order, then the tails of the rows in list order.
+template <typename T>
+__global__ __launch_bounds__(256) void kernel_bwd_gather_cells(
+    const T* __restrict__ GD, int B, int nx, int P, const int32_t* __restrict__ cells, int n_cells,
+    const T* __restrict__ tail_hi, const T* __restrict__ tail_lo, double* __restrict__ dV) {
+    __shared__ T part[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long wpp = (nx + 63) / 64;
+    const long b = blockIdx.x / wpp;
+    const int l0 = (int)(blockIdx.x - b * wpp) * 64, l = l0 + lane;
+    const T* g = GD + b * (long)n_cells * P;
+    T acc = 0;
+    for (int r = wv; r < n_cells; r += 4) {
+        const int i = cells[r];
+        if (i < 0 || i >= nx || i + P < l0 || i - P > l0 + 63) continue;
+        const T* gr = g + (long)r * P;
+        const int jp = l - i, jm = i - l;
+        if (l < nx - 1 && jp >= 1 && jp <= P) acc += gr[jp - 1];
+        if (l > 0 && l < nx && jm >= 1 && jm <= P) acc -= gr[jm - 1];
+    }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && l < nx) {
+        T t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        const long r0 = b * (long)n_cells;
+        if (l == nx - 1)
+            for (int r = 0; r < n_cells; ++r) t += tail_hi[r0 + r];
+        if (l == 0)
+            for (int r = 0; r < n_cells; ++r) t -= tail_lo[r0 + r];
+        dV[b * (long)nx + l] += (double)t;
+    }
+}
+
+// Tile of the adjoint product: 2 x 2 waves of 32 x 32 (BN = 64 columns per block).
+constexpr int BWD_WM = 2, BWD_WN = 2, BWD_BM = 32 * BWD_WM, BWD_BN = 32 * BWD_WN;
+
+template <typename T>
+static int kernel_bwd_run(const wk_mesh* mesh, const T* G, int B, const int32_t* cells, int n_cells,
+                          int layout, double* dV, void* ws, hipStream_t s) {
+    const int n_m = mesh->n_m, P = n_m / 2, H = P / 2, nx = mesh->nx;
+    const long R = (long)B * n_cells;
+    T* GD = static_cast<T*>(ws);
+    T* th = GD + R * P;
+    T* tl = th + R;
+    const T c = (T)(-2.0 / (mesh->hbar * (double)n_m));
+    const char* name = sizeof(T) == 8 ? "kernel_bwd_f64" : "kernel_bwd_f32";
+    if (H == 0) {  // n_m = 2: every sine of eq.(4) is zero
+        hipLaunchKernelGGL(kernel_bwd_zero<T>, dim3((unsigned)((R * P + 255) / 256)), dim3(256), 0, s, GD, R * P);
+    } else {
+        const int Hk = round_up(H, KE_BK), Hn = round_up(H, BWD_BN);
+        const int fmt = sizeof(T) == 8 ? SINE_F64 : SINE_F32;
+        int err = WK_OK;
+        const T* To = static_cast<const T*>(sine_table(n_m, fmt | SINE_ODD_T, Hk, Hn, &err));
+        if (!To) return err;
+        const T* Te = static_cast<const T*>(sine_table(n_m, fmt | SINE_EVEN_T, Hk, Hn, &err));
+        if (!Te) return err;
+        WK_LAUNCH(name, (kernel_bwd_gemm<T, BWD_WM, BWD_WN>),
+                  dim3((unsigned)((R + BWD_BM - 1) / BWD_BM), Hn / BWD_BN), dim3(KE_THREADS), 0, s, G, R, P,
+                  n_m, layout, H, Hk, Hn, To, Te, c, GD);
+    }
+    const long groups = (long)B * ((nx + 63) / 64);
+    if (cells == nullptr) {
+        const int nlo = (P < nx - 1 ? P : nx - 1) + 1, hi0 = nlo > nx - 1 - P ? nlo : nx - 1 - P;
+        const long erows = (long)B * (nlo + (nx - hi0));  // one wave each
+        hipLaunchKernelGGL(kernel_bwd_tails<T>, dim3((unsigned)((erows + 3) / 4)), dim3(256), 0, s, GD, B, nx,
+                           P, nullptr, n_cells, th, tl);
+        hipLaunchKernelGGL(kernel_bwd_gather<T>, dim3((unsigned)groups), dim3(256), 0, s, GD, B, nx, P, th, tl, dV);
+    } else {
+        hipLaunchKernelGGL(kernel_bwd_tails<T>, dim3((unsigned)((R + 3) / 4)), dim3(256), 0, s, GD, B, nx, P,
+                           cells, n_cells, th, tl);
+        hipLaunchKernelGGL(kernel_bwd_gather_cells<T>, dim3((unsigned)groups), dim3(256), 0, s, GD, B, nx, P,
+                           cells, n_cells, th, tl, dV);
+    }
+    return check_launch("wk_kernel_bwd");
 }
 
 }  // namespace wk
 
-extern "C" size_t wk_kernel_bwd_workspace(const wk_mesh* mesh, int32_t B) {
-    if (!mesh || mesh->n_m < 2 || B < 0 || mesh->nx <= 0) return 0;
-    const size_t R = (size_t)B * mesh->nx;
-    return sizeof(double) * (R * (size_t)(mesh->n_m / 2) + 2 * R) + 256;
+extern "C" size_t wk_kernel_bwd_workspace(const wk_mesh* mesh, int32_t B, int32_t n_cells, int32_t prec) {
+    if (!mesh || mesh->n_m < 2 || B < 0 || n_cells < 0 || mesh->nx <= 0) return 0;
+    if (prec != WK_FP64 && prec != WK_FP32) return 0;
+    const size_t R = (size_t)B * n_cells, el = prec == WK_FP64 ? sizeof(double) : sizeof(float);
+    return el * (R * (size_t)(mesh->n_m / 2) + 2 * R) + 256;
 }
 
-extern "C" int wk_kernel_bwd(const wk_mesh* mesh, const double* G, int32_t B, int32_t layout,
-                             double* dV, void* ws, size_t ws_bytes, void* stream) {
+extern "C" int wk_kernel_bwd(const wk_mesh* mesh, const void* G, int32_t B, const int32_t* cells,
+                             int32_t n_cells, int32_t prec, int32_t layout, double* dV, void* ws,
+                             size_t ws_bytes, void* stream) {
     using namespace wk;
     WK_REQUIRE(mesh != nullptr, "wk_kernel_bwd: mesh is NULL");
     WK_REQUIRE(mesh->dim == 1 && mesh->ny == 1 && mesh->nx > 0, "wk_kernel_bwd: 1-D meshes only");
     WK_REQUIRE(mesh->n_m >= 2 && mesh->n_m % 2 == 0, "wk_kernel_bwd: n_m must be even");
     WK_REQUIRE(mesh->hbar > 0.0, "wk_kernel_bwd: hbar must be positive");
     WK_REQUIRE(layout == WK_FULL || layout == WK_HALF, "wk_kernel_bwd: bad layout");
-    WK_REQUIRE(B >= 0, "wk_kernel_bwd: negative batch");
-    if (B == 0) return WK_OK;
+    WK_REQUIRE(prec == WK_FP64 || prec == WK_FP32, "wk_kernel_bwd: prec must be WK_FP64 or WK_FP32");
+    WK_REQUIRE(B >= 0 && n_cells >= 0, "wk_kernel_bwd: negative size");
+    WK_REQUIRE(cells != nullptr || n_cells == mesh->nx,
+               "wk_kernel_bwd: with cells == NULL, n_cells must be nx");
+    if ((long)B * n_cells == 0) return WK_OK;
     WK_REQUIRE(G && dV && ws, "wk_kernel_bwd: NULL array");
-    WK_REQUIRE(ws_bytes >= wk_kernel_bwd_workspace(mesh, B), "wk_kernel_bwd: workspace too small");
-    constexpr int WM = 2, WN = 2, BM = 32 * WM, BN = 32 * WN;   // 2 x 2 waves
+    WK_REQUIRE(ws_bytes >= wk_kernel_bwd_workspace(mesh, B, n_cells, prec), "wk_kernel_bwd: workspace too small");
     hipStream_t s = as_stream(stream);
-    const int n_m = mesh->n_m, P = n_m / 2, H = P / 2, nx = mesh->nx;
-    const long R = (long)B * nx;
-    double* GD = static_cast<double*>(ws);
-    double* th = GD + R * P;
-    double* tl = th + R;
-    const double c = -2.0 / (mesh->hbar * (double)n_m);
-    if (H == 0) {  // n_m = 2: every sine of eq.(4) is zero
-        hipLaunchKernelGGL(kernel_zero_f64, dim3((unsigned)((R * P + 255) / 256)), dim3(256), 0, s, GD, R * P);
-    } else {
-        const int Hk = round_up(H, KE_BK), Hn = round_up(H, BN);
-        int err = WK_OK;
-        const double* To = static_cast<const double*>(sine_table(n_m, SINE_ODD_T, Hk, Hn, s, &err));
-        if (!To) return err;
-        const double* Te = static_cast<const double*>(sine_table(n_m, SINE_EVEN_T, Hk, Hn, s, &err));
-        if (!Te) return err;
-        hipLaunchKernelGGL((kernel_bwd_gemm<WM, WN>), dim3((unsigned)((R + BM - 1) / BM), Hn / BN),
-                           dim3(KE_THREADS), 0, s, G, R, P, n_m, layout, H, Hk, Hn, To, Te, c, GD);
+    if (prec == WK_FP64)
+        return kernel_bwd_run<double>(mesh, static_cast<const double*>(G), B, cells, n_cells, layout, dV, ws, s);
+    return kernel_bwd_run<float>(mesh, static_cast<const float*>(G), B, cells, n_cells, layout, dV, ws, s);
+}
+
+// ----------------------------------------------------------------------------- set-up
+// The sine tables every 1-D contraction of this file reads for a given n_m (forward FP64 and
+// fused tables, the 16-bit forms, the FP64 and FP32 adjoints), in the shapes they look up.
+namespace wk {
+static int prepare_1d(int n_m, hipStream_t s) {
+    const int P = n_m / 2, H = P / 2;
+    if (H == 0) return WK_OK;
+    int rc;
+    {   // forward FP64 and the fused tables
+        const int Hk = round_up(H, KE_BK), Hn = round_up(H, fold_bn(fold_cfg(H)));
+        if ((rc = sine_table_build(n_m, SINE_ODD, Hk, Hn, s))) return rc;
+        if ((rc = sine_table_build(n_m, SINE_EVEN, Hk, Hn, s))) return rc;
     }
-    {
-        const int nlo = (P < nx - 1 ? P : nx - 1) + 1, hi0 = nlo > nx - 1 - P ? nlo : nx - 1 - P;
-        const long erows = (long)B * (nlo + (nx - hi0));  // one wave each
-        hipLaunchKernelGGL(kernel_bwd_tails, dim3((unsigned)((erows + 3) / 4)), dim3(256), 0, s, GD, B,
-                           nx, P, th, tl);
+    {   // 16-bit forms: transposed hi / lo fold tables
+        const int Hk = round_up(H, LP_BK), Hn = round_up(H, fold_bn(fold_cfg(H)));
+        for (int fmt = 1; fmt <= 4; ++fmt) {
+            if ((rc = sine_table_build(n_m, fmt | SINE_ODD_T, Hn, Hk, s))) return rc;
+            if ((rc = sine_table_build(n_m, fmt | SINE_EVEN_T, Hn, Hk, s))) return rc;
+        }
     }
-    hipLaunchKernelGGL(kernel_bwd_gather, dim3((unsigned)((long)B * ((nx + 63) / 64))), dim3(256), 0, s,
-                       GD, B, nx, P, th, tl, dV);
-    return check_launch("wk_kernel_bwd");
+    {   // adjoints
+        const int Hk = round_up(H, KE_BK), Hn = round_up(H, BWD_BN);
+        for (int fmt : {SINE_F64, SINE_F32}) {
+            if ((rc = sine_table_build(n_m, fmt | SINE_ODD_T, Hk, Hn, s))) return rc;
+            if ((rc = sine_table_build(n_m, fmt | SINE_EVEN_T, Hk, Hn, s))) return rc;
+        }
+    }
+    return WK_OK;
+}
+}  // namespace wk
+
+extern "C" int wk_prepare(const wk_mesh* mesh, void* stream) {
+    using namespace wk;
+    WK_REQUIRE(mesh != nullptr, "wk_prepare: mesh is NULL");
+    WK_REQUIRE(mesh->n_m >= 2 && mesh->n_m % 2 == 0, "wk_prepare: n_m must be even and >= 2");
+    if (mesh->dim == 2) return WK_OK;  // the 2-D contraction forms its trig operands in registers
+    WK_REQUIRE(mesh->dim == 1, "wk_prepare: dim must be 1 or 2");
+    return prepare_1d(mesh->n_m, as_stream(stream));
 }
 
 // ----------------------------------------------------------------------------- d = 2

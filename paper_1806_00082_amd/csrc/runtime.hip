@@ -27,7 +27,7 @@ int check_launch(const char* what) {
 }
 
 // Sine tables of eq.(4), kind = format | (part << 3).  Formats: 0 FP64, 1 BF16, 2 BF16
-// remainder (v - bf16(v)), 3 FP16, 4 FP16 remainder.  Parts (a = row, b = column):
+// remainder (v - bf16(v)), 3 FP16, 4 FP16 remainder, 5 FP32.  Parts (a = row, b = column):
 //   0: S[a][b] = sin(2 pi (a+1)(b+1) / n_m) for a, b < P = n_m / 2;
 //   1: odd-j fold  So[a][b] = sin(2 pi (2a+1)(b+1) / n_m),   a, b < H = floor(P / 2);
 //   2: even-j fold Se[a][b] = sin(2 pi (2a+2)(b+1) / n_m),   a, b < H;
@@ -53,41 +53,56 @@ __global__ void build_sine_table(void* out, int n_m, int rows, int cols, int kin
         case 2: reinterpret_cast<uint16_t*>(out)[idx] = bf16_bits(v - bf16_value(bf16_bits(v))); break;
         case 3: reinterpret_cast<uint16_t*>(out)[idx] = f16_bits(v); break;
         case 4: reinterpret_cast<uint16_t*>(out)[idx] = f16_bits(v - f16_value(f16_bits(v))); break;
+        case 5: reinterpret_cast<float*>(out)[idx] = (float)v; break;
         default: break;
     }
 }
 
-const void* sine_table(int n_m, int kind, int rows, int cols, hipStream_t stream, int* err) {
-    static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, int>, void*> cache;
-    *err = WK_OK;
+namespace {
+std::mutex g_sine_mu;
+std::map<std::tuple<int, int, int, int, int>, void*> g_sine;
+
+size_t sine_elem(int kind) {
+    const int fmt = kind & 7;
+    return fmt == 0 ? sizeof(double) : (fmt == 5 ? sizeof(float) : sizeof(uint16_t));
+}
+}  // namespace
+
+int sine_table_build(int n_m, int kind, int rows, int cols, hipStream_t stream) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
-        *err = fail(WK_EHIP, "hipGetDevice failed");
-        return nullptr;
-    }
-    std::lock_guard<std::mutex> lock(mu);
+    if (hipGetDevice(&dev) != hipSuccess) return fail(WK_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lock(g_sine_mu);
     auto key = std::make_tuple(dev, n_m, kind, rows, cols);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    const size_t elem = (kind & 7) == 0 ? sizeof(double) : sizeof(uint16_t);
+    if (g_sine.count(key)) return WK_OK;
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, elem * (size_t)rows * cols);
-    if (e != hipSuccess) {
-        *err = fail(WK_EHIP, std::string("sine table hipMalloc: ") + hipGetErrorString(e));
-        return nullptr;
-    }
+    hipError_t e = hipMalloc(&p, sine_elem(kind) * (size_t)rows * cols);
+    if (e != hipSuccess) return fail(WK_EHIP, std::string("wk_prepare: hipMalloc: ") + hipGetErrorString(e));
     const long n = (long)rows * cols;
     hipLaunchKernelGGL(build_sine_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
                        p, n_m, rows, cols, kind);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
-        *err = fail(WK_EHIP, std::string("sine table build: ") + hipGetErrorString(e));
+        (void)hipFree(p);
+        return fail(WK_EHIP, std::string("wk_prepare: sine table build: ") + hipGetErrorString(e));
+    }
+    g_sine[key] = p;
+    return WK_OK;
+}
+
+const void* sine_table(int n_m, int kind, int rows, int cols, int* err) {
+    *err = WK_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *err = fail(WK_EHIP, "hipGetDevice failed");
         return nullptr;
     }
-    cache[key] = p;
-    return p;
+    std::lock_guard<std::mutex> lock(g_sine_mu);
+    auto it = g_sine.find(std::make_tuple(dev, n_m, kind, rows, cols));
+    if (it != g_sine.end()) return it->second;
+    *err = fail(WK_EINVAL, "sine tables for n_m = " + std::to_string(n_m) +
+                               " are not prepared on this device: call wk_prepare first");
+    return nullptr;
 }
 
 

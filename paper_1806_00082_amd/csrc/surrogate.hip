@@ -7,9 +7,8 @@
 //   Pi(t)    = prod_{s < log2 N} cos(2^s pi m / n_m)
 // A is a stride-N convolution of the potential (the f_V of Sec. 3) built per row tile in
 // LDS; Bm and Pi are tiny (H x P, P) and are formed once per call by surr_prep.
-#include <map>
+#include <string>
 #include <type_traits>
-#include <mutex>
 
 #include "lowp.h"
 #include "wk_internal.h"
@@ -855,58 +854,47 @@ static SurrWS surr_carve(void* ws, int H, int P, int N, long R, bool with_GA) {
     return w;
 }
 
-// Scratch for the forward's Bm/Pi tables: a per-device buffer grown on demand (prep data of
-// a few hundred KB at most).
-static void* fwd_scratch(size_t bytes, int* err) {
-    static std::mutex mu;
-    static std::map<int, std::pair<void*, size_t>> bufs;
-    int dev = 0;
-    *err = WK_OK;
-    if (hipGetDevice(&dev) != hipSuccess) {
-        *err = fail(WK_EHIP, "hipGetDevice failed");
-        return nullptr;
-    }
-    std::lock_guard<std::mutex> lock(mu);
-    auto& e = bufs[dev];
-    if (e.second < bytes) {
-        if (e.first) (void)hipFree(e.first);
-        e.first = nullptr;
-        if (hipMalloc(&e.first, bytes) != hipSuccess) {
-            e.second = 0;
-            *err = fail(WK_EHIP, "surrogate scratch hipMalloc failed");
-            return nullptr;
-        }
-        e.second = bytes;
-    }
-    return e.first;
+// Scratch of the forward: the Bm / Pi tables of the prep kernel (the backward's prep section)
+// followed by the transposed FP32 and BF16 copies of Bm.
+static size_t surr_fwd_ws_bytes(int H, int P, int N) {
+    const int Pn = (P + 15) / 16 * 16, Hk = (H + 31) / 32 * 32;
+    const size_t prep = (surr_ws_bytes(H, P, N, 0, false) + 255) / 256 * 256;
+    return prep + (size_t)Pn * Hk * (sizeof(float) + sizeof(uint16_t));
 }
 
-}  // namespace wk
-
-using namespace wk;
-
-extern "C" int wk_surrogate_fwd(const wk_mesh* mesh, int32_t N, const float* wV, const float* wT,
-                                const float* W, const double* V, int32_t B,
-                                const int32_t* cells, int32_t n_cells, int32_t prec, void* K_out,
-                                void* stream) {
-    int H;
-    int rc = surr_check(mesh, N, &H);
+// Validation shared by the forward entry points; *H receives n_m / N.
+int surr_fwd_check(const wk_mesh* mesh, int N, const float* wV, const float* wT, const float* W,
+                   const double* V, int B, const int32_t* cells, int n_cells, int prec, void* K_out,
+                   int* H) {
+    int rc = surr_check(mesh, N, H);
     if (rc) return rc;
     WK_REQUIRE(B >= 0 && n_cells >= 0, "wk_surrogate_fwd: negative size");
+    WK_REQUIRE(prec == WK_FP64 || prec == WK_FP32 || prec == WK_BF16,
+               "wk_surrogate_fwd: prec must be WK_FP64, WK_FP32 or WK_BF16");
     if ((long)B * n_cells == 0) return WK_OK;
     WK_REQUIRE(cells != nullptr || n_cells == mesh->nx,
                "wk_surrogate_fwd: with cells == NULL, n_cells must be nx");
     WK_REQUIRE(wV && wT && W && V && K_out, "wk_surrogate_fwd: NULL array");
-    hipStream_t s = as_stream(stream);
+    return WK_OK;
+}
+
+size_t surr_fwd_scratch_bytes(const wk_mesh* mesh, int N) {
+    int H;
+    if (surr_check(mesh, N, &H) != WK_OK) return 0;
+    return surr_fwd_ws_bytes(H, mesh->n_m / 2, N);
+}
+
+// The forward on validated arguments with `scratch` (surr_fwd_scratch_bytes bytes) as the
+// prep tables' memory.
+int surr_fwd_run(const wk_mesh* mesh, int N, int H, const float* wV, const float* wT, const float* W,
+                 const double* V, int B, const int32_t* cells, int n_cells, int prec, void* K_out,
+                 void* scratch, hipStream_t s) {
+    if ((long)B * n_cells == 0) return WK_OK;
     const int P = mesh->n_m / 2, Pn = (P + 15) / 16 * 16;
     const long R = (long)B * n_cells;
-    // prep tables live in a scratch area sized like the backward's prep section
+    // prep tables, then the transposed copies of Bm
     const int Hk = (H + 31) / 32 * 32;
     const size_t prep = (surr_ws_bytes(H, P, N, 0, false) + 255) / 256 * 256;
-    const size_t tbytes = (size_t)Pn * Hk * (sizeof(float) + sizeof(uint16_t));
-    int err;
-    void* scratch = fwd_scratch(prep + tbytes, &err);
-    if (!scratch) return err;
     SurrWS w = surr_carve(scratch, H, P, N, 0, false);
     float* Btf = reinterpret_cast<float*>(static_cast<char*>(scratch) + prep);
     uint16_t* Btb = reinterpret_cast<uint16_t*>(Btf + (size_t)Pn * Hk);
@@ -973,6 +961,25 @@ extern "C" int wk_surrogate_fwd(const wk_mesh* mesh, int32_t N, const float* wV,
                                static_cast<float*>(K_out));
     }
     return check_launch("wk_surrogate_fwd");
+}
+}  // namespace wk
+
+using namespace wk;
+
+extern "C" size_t wk_surrogate_fwd_workspace(const wk_mesh* mesh, int32_t N) {
+    return surr_fwd_scratch_bytes(mesh, N);
+}
+
+extern "C" int wk_surrogate_fwd(const wk_mesh* mesh, int32_t N, const float* wV, const float* wT,
+                                const float* W, const double* V, int32_t B,
+                                const int32_t* cells, int32_t n_cells, int32_t prec, void* K_out,
+                                void* ws, size_t ws_bytes, void* stream) {
+    int H;
+    int rc = surr_fwd_check(mesh, N, wV, wT, W, V, B, cells, n_cells, prec, K_out, &H);
+    if (rc) return rc;
+    if ((long)B * n_cells == 0) return WK_OK;
+    WK_REQUIRE(ws && ws_bytes >= surr_fwd_scratch_bytes(mesh, N), "wk_surrogate_fwd: workspace too small");
+    return surr_fwd_run(mesh, N, H, wV, wT, W, V, B, cells, n_cells, prec, K_out, ws, as_stream(stream));
 }
 
 extern "C" size_t wk_surrogate_workspace(const wk_mesh* mesh, int32_t N, int32_t B, int32_t n_cells) {
@@ -1109,3 +1116,4 @@ extern "C" int wk_sgd_update(float* w, const float* grad, int32_t n, float lr, v
     hipLaunchKernelGGL(sgd_kernel, dim3((n + 255) / 256), dim3(256), 0, as_stream(stream), w, grad, n, lr);
     return check_launch("wk_sgd_update");
 }
+

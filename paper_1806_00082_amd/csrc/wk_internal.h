@@ -42,14 +42,18 @@ void trace_end(int handle, hipStream_t s);
         ::wk::trace_end(th_, STREAM);                                                    \
     } while (0)
 
-// Device sine table for n_m (built on first use, per device, kept for the process), a
-// [rows][cols] array with zero padding.  kind = format | (part << 3); format 0: double,
-// 1: bf16 hi, 2: bf16 lo, 3: fp16 hi, 4: fp16 lo (hi/lo of the double); part 0: the plain
-// table S[jj][t] = sin(2 pi (jj+1)(t+1) / n_m), jj, t < P; parts 1 / 2: the odd-j / even-j
-// fold So[k][t] = sin(2 pi (2k+1)(t+1) / n_m), Se[k][t] = sin(2 pi (2k+2)(t+1) / n_m),
+// Device sine tables for n_m, [rows][cols] arrays with zero padding, one per device, kind and
+// shape.  kind = format | (part << 3); format 0: double, 1: bf16 hi, 2: bf16 lo, 3: fp16 hi,
+// 4: fp16 lo (hi/lo of the double), 5: float; part 0: the plain table
+// S[jj][t] = sin(2 pi (jj+1)(t+1) / n_m), jj, t < P; parts 1 / 2: the odd-j / even-j fold
+// So[k][t] = sin(2 pi (2k+1)(t+1) / n_m), Se[k][t] = sin(2 pi (2k+2)(t+1) / n_m),
 // k, t < floor(P / 2); parts 3 / 4: those two transposed.
+// sine_table_build allocates, fills and synchronises (set-up only: wk_prepare);
+// sine_table only looks a built table up and fails with WK_EINVAL when it is absent.
 enum { SINE_PLAIN = 0, SINE_ODD = 1 << 3, SINE_EVEN = 2 << 3, SINE_ODD_T = 3 << 3, SINE_EVEN_T = 4 << 3 };
-const void* sine_table(int n_m, int kind, int rows, int cols, hipStream_t stream, int* err);
+enum { SINE_F64 = 0, SINE_F32 = 5 };
+int sine_table_build(int n_m, int kind, int rows, int cols, hipStream_t stream);
+const void* sine_table(int n_m, int kind, int rows, int cols, int* err);
 
 // ----------------------------------------------------------------------------- device utils
 __device__ __forceinline__ long mod_pos(long a, long n) {

@@ -34,23 +34,37 @@ def analytic_weights(n_m: int, N: int, hbar: float = HBAR_EVFS, device="cuda"):
 
 
 # ----------------------------------------------------------------------------- raw calls
+def surrogate_fwd_workspace(n_m: int, N: int, device, hbar: float = HBAR_EVFS) -> torch.Tensor:
+    """Scratch buffer for surrogate_fwd (the per-call W sin(u m) and prefactor tables)."""
+    m = ops.mesh_struct(1, 1, 1, n_m, hbar)
+    n = int(L.lib().wk_surrogate_fwd_workspace(ctypes.byref(m), N))
+    if n == 0:
+        L.check(L.WK_EINVAL, "wk_surrogate_fwd_workspace")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
 def surrogate_fwd(V, n_m: int, N: int, wV, wT, W, cells=None, prec: str = "fp32",
-                  hbar: float = HBAR_EVFS, out=None):
-    """Half table [B * n_cells][P] of eq.(5); float32 (fp32, bf16) or float64 (fp64)."""
+                  hbar: float = HBAR_EVFS, out=None, ws=None):
+    """Half table [B * n_cells][P] of eq.(5); float32 (fp32, bf16) or float64 (fp64).
+    ws: surrogate_fwd_workspace() buffer (allocated here when None); calls sharing one must
+    not overlap."""
     if V.dim() == 1:
         V = V[None]
     B, nx = V.shape
     n_cells = nx if cells is None else int(cells.numel())
     P = n_m // 2
-    p = {"fp64": L.WK_FP64, "bf16": L.WK_BF16}.get(prec, L.WK_FP16X3 + 1)
+    p = {"fp64": L.WK_FP64, "bf16": L.WK_BF16, "fp32": L.WK_FP32}[prec]
     dt = torch.float64 if prec == "fp64" else torch.float32
     if out is None:
         out = torch.empty((B * n_cells, P), dtype=dt, device=V.device)
+    if ws is None:
+        ws = surrogate_fwd_workspace(n_m, N, V.device, hbar)
     m = ops.mesh_struct(1, nx, 1, n_m, hbar)
     c = None if cells is None else cells.to(torch.int32).contiguous()
     L.check(L.lib().wk_surrogate_fwd(ctypes.byref(m), N, ops._ptr(wV), ops._ptr(wT), ops._ptr(W),
                                      ops._ptr(V.contiguous()), B, ops._ptr(c), n_cells, p,
-                                     ops._ptr(out), ops._stream()), "wk_surrogate_fwd")
+                                     ops._ptr(out), ops._ptr(ws), ws.numel(), ops._stream()),
+            "wk_surrogate_fwd")
     return out
 
 
@@ -147,9 +161,63 @@ class TrainResult:
     seconds: float = 0.0
 
 
+class SGDState:
+    """Device buffers of one training step (Sec. 3) for batches of `batch` potentials of nx
+    cells: label, forward and gradient tables, the loss, and the three calls' workspaces."""
+
+    def __init__(self, n_m: int, N: int, batch: int, nx: int, device, hbar: float = HBAR_EVFS):
+        P = n_m // 2
+        self.n_m, self.N, self.batch, self.nx, self.hbar = n_m, N, batch, nx, hbar
+        self.c = -2.0 / (hbar * n_m)
+        self.inv_scale = 1.0 / abs(self.c)
+        self.Kh = torch.empty((batch * nx, P), dtype=torch.float32, device=device)
+        self.Klab = torch.empty((batch * nx, P), dtype=torch.float64, device=device)
+        self.E = torch.empty_like(self.Kh)
+        self.loss = torch.empty(1, dtype=torch.float64, device=device)
+        self.mse_ws = torch.empty(8 * 1024, dtype=torch.uint8, device=device)
+        self.fwd_ws = surrogate_fwd_workspace(n_m, N, device, hbar)
+        m = ops.mesh_struct(1, nx, 1, n_m, hbar)
+        self.bwd_ws = torch.empty(int(L.lib().wk_surrogate_workspace(ctypes.byref(m), N, batch, nx)),
+                                  dtype=torch.uint8, device=device)
+
+    def step(self, Vb, weights, lr, labels=None):
+        """One SGD step on the batch Vb [batch][nx] (all cells), in place on `weights`:
+        exact eq.(4) half tables as labels (FP64, unless `labels` [batch * nx][P] is given),
+        eq.(5) forward in FP32, MSE on targets scaled by 1 / |c|, backward, then
+        w -= lr * g per group with W stepped in units of c (lr_W c^2).  The loss before the
+        step is left in self.loss (device)."""
+        lr_V, lr_T, lr_W = (lr, lr, lr) if isinstance(lr, (int, float)) else lr
+        wV, wT, W = weights
+        if labels is None:
+            ops.kernel_eval(Vb, self.n_m, layout="half", hbar=self.hbar, out=self.Klab)
+            labels = self.Klab
+        surrogate_fwd(Vb, self.n_m, self.N, wV, wT, W, prec="fp32", hbar=self.hbar, out=self.Kh,
+                      ws=self.fwd_ws)
+        mse_grad(self.Kh, labels, self.inv_scale, E=self.E, loss=self.loss, ws=self.mse_ws)
+        dwV, dwT, dW, _ = surrogate_bwd(Vb, self.n_m, self.N, wV, wT, W, self.E, hbar=self.hbar,
+                                        ws=self.bwd_ws)
+        sgd_update(wV, dwV, lr_V)
+        sgd_update(wT, dwT, lr_T)
+        sgd_update(W, dW, lr_W * self.c * self.c)
+        return self.loss
+
+
+def sgd_steps(V: torch.Tensor, batches, n_m: int, N: int, lr, init, hbar: float = HBAR_EVFS):
+    """SGD steps on the given batches (lists of potential indices into V [n_pot][nx]) from
+    the weights `init`; returns (wV, wT, W) and the loss before each step (host floats)."""
+    w = [t.clone() for t in init]
+    nx = V.shape[1]
+    st = SGDState(n_m, N, len(batches[0]), nx, V.device, hbar)
+    losses = []
+    for idx in batches:
+        Vb = V.index_select(0, torch.as_tensor(idx, dtype=torch.long, device=V.device)).contiguous()
+        losses.append(float(st.step(Vb, w, lr).item()))
+    return w, losses
+
+
 def train_surrogate(V_train: torch.Tensor, n_m: int, N: int, epochs: int, batch: int,
                     lr, hbar: float = HBAR_EVFS, init=None, labels=None,
-                    seed: int = 0, log=None) -> TrainResult:
+                    seed: int = 0, log=None, epoch_end=None) -> TrainResult:
     """SGD on the MSE between eq.(5) and the exact eq.(4) half tables (Sec. 3).
 
     V_train: [n_pot][nx] float64 device tensor.  labels: optional precomputed exact half
@@ -158,25 +226,16 @@ def train_surrogate(V_train: torch.Tensor, n_m: int, N: int, epochs: int, batch:
     lr: one step size, or (lr_wV, lr_wT, lr_W) per parameter group -- the angle weights wT
     multiply offsets up to n_m/2 and momenta up to n_m/2 inside the sine, so their gradient
     is orders of magnitude larger than the others' and they need a much smaller step.
+    epoch_end(ep, weights): optional callback after each epoch (e.g. held-out error).
     """
-    lr_V, lr_T, lr_W = (lr, lr, lr) if isinstance(lr, (int, float)) else lr
     dev = V_train.device
     n_pot, nx = V_train.shape
-    c = -2.0 / (hbar * n_m)
-    inv_scale = 1.0 / abs(c)
-    wV, wT, W = [t.clone() for t in (init or analytic_weights(n_m, N, hbar, dev))]
+    w = [t.clone() for t in (init or analytic_weights(n_m, N, hbar, dev))]
+    st = SGDState(n_m, N, batch, nx, dev, hbar)
     P = n_m // 2
-    Kh = torch.empty((batch * nx, P), dtype=torch.float32, device=dev)
-    Klab = torch.empty((batch * nx, P), dtype=torch.float64, device=dev)
-    E = torch.empty_like(Kh)
-    loss = torch.empty(1, dtype=torch.float64, device=dev)
-    mse_ws = torch.empty(8 * 1024, dtype=torch.uint8, device=dev)
-    m = ops.mesh_struct(1, nx, 1, n_m, hbar)
-    ws = torch.empty(int(L.lib().wk_surrogate_workspace(ctypes.byref(m), N, batch, nx)),
-                     dtype=torch.uint8, device=dev)
     gen = torch.Generator(device="cpu")
     gen.manual_seed(seed)
-    res = TrainResult(wV, wT, W)
+    res = TrainResult(*w)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     for ep in range(epochs):
@@ -186,23 +245,15 @@ def train_surrogate(V_train: torch.Tensor, n_m: int, N: int, epochs: int, batch:
         for k in range(0, n_pot - batch + 1, batch):
             idx = perm[k:k + batch].to(dev)
             Vb = V_train.index_select(0, idx)
-            if labels is None:
-                ops.kernel_eval(Vb, n_m, layout="half", hbar=hbar, out=Klab)
-                lab = Klab
-            else:
-                lab = labels.index_select(0, idx).reshape(batch * nx, P)
-            surrogate_fwd(Vb, n_m, N, wV, wT, W, prec="fp32", hbar=hbar, out=Kh)
-            mse_grad(Kh, lab, inv_scale, E=E, loss=loss, ws=mse_ws)
-            dwV, dwT, dW, _ = surrogate_bwd(Vb, n_m, N, wV, wT, W, E, hbar=hbar, ws=ws)
-            sgd_update(wV, dwV, lr_V)
-            sgd_update(wT, dwT, lr_T)
-            sgd_update(W, dW, lr_W * c * c)
-            ep_loss += loss
+            lab = None if labels is None else labels.index_select(0, idx).reshape(batch * nx, P)
+            ep_loss += st.step(Vb, w, lr, labels=lab)
             nb += 1
             res.steps += 1
         res.losses.append(float((ep_loss / max(nb, 1)).item()))
         if log:
             log(f"epoch {ep}: loss {res.losses[-1]:.6e}")
+        if epoch_end:
+            epoch_end(ep, w)
     ev1.record()
     torch.cuda.synchronize()
     res.seconds = ev0.elapsed_time(ev1) / 1e3

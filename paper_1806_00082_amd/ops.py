@@ -31,6 +31,24 @@ def mesh_struct(dim: int, nx: int, ny: int, n_m: int, hbar: float = HBAR_EVFS) -
     return L.WkMesh(dim, nx, ny, n_m, hbar)
 
 
+# ----------------------------------------------------------------------------- set-up
+_prepared = set()
+
+
+def prepare(n_m: int, device=None, hbar: float = HBAR_EVFS):
+    """wk_prepare for n_m on `device` (default: the current one), once per process: builds the
+    library's sine tables for the 1-D contractions (allocates and synchronises)."""
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+    dev = torch.cuda.current_device() if dev is None else dev
+    key = (dev, int(n_m))
+    if key in _prepared:
+        return
+    m = mesh_struct(1, 1, 1, n_m, hbar)
+    with torch.cuda.device(dev):
+        L.check(L.lib().wk_prepare(ctypes.byref(m), _stream()), "wk_prepare")
+    _prepared.add(key)
+
+
 # ----------------------------------------------------------------------------- kernel
 def kernel_eval(V: torch.Tensor, n_m: int, cells: torch.Tensor | None = None, prec: str = "fp64",
                 layout: str = "full", hbar: float = HBAR_EVFS, out: torch.Tensor | None = None):
@@ -57,6 +75,8 @@ def kernel_eval(V: torch.Tensor, n_m: int, cells: torch.Tensor | None = None, pr
         shape = (B * n_cells, n_m, n_m)
     if out is None:
         out = torch.empty(shape, dtype=dt, device=V.device)
+    if dim == 1:
+        prepare(n_m, V.device)
     m = mesh_struct(dim, nx, ny, n_m, hbar)
     L.check(L.lib().wk_kernel_eval(ctypes.byref(m), _ptr(V), B, _ptr(cells), n_cells, p, lay,
                                    _ptr(out), _stream()), "wk_kernel_eval")
@@ -64,16 +84,24 @@ def kernel_eval(V: torch.Tensor, n_m: int, cells: torch.Tensor | None = None, pr
 
 
 def kernel_bwd(G: torch.Tensor, nx: int, n_m: int, B: int, layout: str = "full",
-               hbar: float = HBAR_EVFS, dV: torch.Tensor | None = None):
-    _need_cuda(G)
+               hbar: float = HBAR_EVFS, dV: torch.Tensor | None = None,
+               cells: torch.Tensor | None = None):
+    """Adjoint of eq.(4) in V on the rows of kernel_eval (all cells, or `cells`): G is float64
+    (FP64 product) or float32 (FP32 product); dV [B][nx] float64 is accumulated into."""
+    _need_cuda(G, cells)
+    prec = {torch.float64: L.WK_FP64, torch.float32: L.WK_FP32}[G.dtype]
+    n_cells = nx if cells is None else int(cells.numel())
+    if cells is not None:
+        cells = cells.to(torch.int32).contiguous()
     m = mesh_struct(1, nx, 1, n_m, hbar)
+    prepare(n_m, G.device)
     if dV is None:
         dV = torch.zeros((B, nx), dtype=torch.float64, device=G.device)
-    wsz = L.lib().wk_kernel_bwd_workspace(ctypes.byref(m), B)
+    wsz = L.lib().wk_kernel_bwd_workspace(ctypes.byref(m), B, n_cells, prec)
     ws = torch.empty(max(int(wsz), 8), dtype=torch.uint8, device=G.device)
     lay = L.WK_HALF if layout == "half" else L.WK_FULL
-    L.check(L.lib().wk_kernel_bwd(ctypes.byref(m), _ptr(G.contiguous()), B, lay, _ptr(dV),
-                                  _ptr(ws), int(wsz), _stream()), "wk_kernel_bwd")
+    L.check(L.lib().wk_kernel_bwd(ctypes.byref(m), _ptr(G.contiguous()), B, _ptr(cells), n_cells, prec,
+                                  lay, _ptr(dV), _ptr(ws), int(wsz), _stream()), "wk_kernel_bwd")
     return dV
 
 
@@ -128,6 +156,8 @@ def kernel_tables(V: torch.Tensor, n_m: int, dt: float, cells: torch.Tensor | No
             raise ValueError(f"kernel_tables: output of shape {tuple(t.shape)}, expected {shape}")
     if guide is not None and (tuple(guide.shape) != (R, guide_len + 1) or not guide.is_contiguous()):
         raise ValueError("kernel_tables: guide must be a contiguous [rows][guide_len + 1] tensor")
+    if dim == 1:
+        prepare(n_m, V.device)
     m = mesh_struct(dim, nx, ny, n_m, hbar)
     L.check(L.lib().wk_kernel_tables(ctypes.byref(m), _ptr(V), B, _ptr(cells), n_cells, float(dt),
                                      _ptr(g), _ptr(n0), _ptr(thr), _ptr(cdf), _ptr(guide),

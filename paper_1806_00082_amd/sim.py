@@ -73,6 +73,8 @@ class Simulator:
         else:
             kdt = torch.float64 if (kernel == "exact" and prec == "fp64") else torch.float32
             self.Kbuf = torch.empty((self.n_cells, self.row_len), dtype=kdt, device=self.dev)
+        self.surr_ws = (learn.surrogate_fwd_workspace(self.n_m, N, self.dev)
+                        if kernel == "surrogate" else None)
         self.new_cells = torch.empty(self.n_cells, dtype=torch.int32, device=self.dev)
         self.d_count = torch.zeros(1, dtype=torch.int64, device=self.dev)
         self.n_rows = 0
@@ -121,7 +123,8 @@ class Simulator:
         else:
             wV, wT, W = self.weights
             learn.surrogate_fwd(self.V, self.n_m, self.N, wV, wT, W, cells=cells[:count],
-                                prec=self.prec if self.prec in ("fp64", "bf16") else "fp32", out=K)
+                                prec=self.prec if self.prec in ("fp64", "bf16") else "fp32", out=K,
+                                ws=self.surr_ws)
         m = ops.mesh_struct(self.dim, 1, 1, self.n_m)
         L.check(L.lib().wk_gamma_tables(
             ctypes.byref(m), ops._ptr(K), int(K.dtype == torch.float64),

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     lib = _lib.lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.wk_version() == 1
+    assert lib.wk_version() == 2
 
 
 def test_python_binding_names_match_header():
@@ -50,6 +50,36 @@ def test_host_validation_without_gpu():
     assert lib.wk_kernel_eval(ctypes.byref(m), None, 0, None, 10, 0, 0, None, None) == 0  # empty
     g = _lib.SpGeom(1, 10, 1, 8, 16, -8, 0, 0, 0.1, 0)
     assert lib.sp_workspace_size(ctypes.byref(g)) > 0
+
+
+def test_workspace_contracts_without_gpu():
+    """Workspace queries and checks of the calls whose scratch is the caller's (host only)."""
+    from paper_1806_00082_amd import _lib
+    lib = _lib.lib()
+    m = _lib.WkMesh(1, 64, 1, 32, 0.65)
+    n = lib.wk_surrogate_fwd_workspace(ctypes.byref(m), 4)
+    assert n > 0
+    assert lib.wk_surrogate_fwd_workspace(ctypes.byref(m), 3) == 0      # N must be a power of two
+    fake = ctypes.c_void_p(16)                                           # never dereferenced
+    rc = lib.wk_surrogate_fwd(ctypes.byref(m), 4, fake, fake, fake, fake, 1, None, 64, _lib.WK_FP32,
+                              fake, fake, n - 1, None)
+    assert rc == _lib.WK_EINVAL and b"workspace" in lib.wk_last_error()
+    rc = lib.wk_surrogate_fwd(ctypes.byref(m), 4, fake, fake, fake, fake, 1, None, 64, _lib.WK_FP16,
+                              fake, fake, n, None)
+    assert rc == _lib.WK_EINVAL and b"prec" in lib.wk_last_error()
+    # the adjoint: FP64 and FP32 workspaces, cell lists, bad precision
+    w64 = lib.wk_kernel_bwd_workspace(ctypes.byref(m), 2, 10, _lib.WK_FP64)
+    w32 = lib.wk_kernel_bwd_workspace(ctypes.byref(m), 2, 10, _lib.WK_FP32)
+    assert w64 > w32 > 0 and lib.wk_kernel_bwd_workspace(ctypes.byref(m), 2, 10, _lib.WK_BF16) == 0
+    rc = lib.wk_kernel_bwd(ctypes.byref(m), fake, 2, None, 10, _lib.WK_FP64, _lib.WK_HALF, fake, fake,
+                           w64, None)
+    assert rc == _lib.WK_EINVAL and b"n_cells must be nx" in lib.wk_last_error()
+    rc = lib.wk_kernel_bwd(ctypes.byref(m), fake, 2, fake, 10, _lib.WK_FP64, _lib.WK_HALF, fake, fake,
+                           w64 - 1, None)
+    assert rc == _lib.WK_EINVAL and b"workspace" in lib.wk_last_error()
+    # set-up validates before touching a device
+    bad = _lib.WkMesh(1, 64, 1, 31, 0.65)
+    assert lib.wk_prepare(ctypes.byref(bad), None) == _lib.WK_EINVAL
 
 
 def test_particle_calls_reject_aliased_buffers_without_gpu():

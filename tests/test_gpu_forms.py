@@ -245,14 +245,16 @@ def test_surrogate_autograd_matches_bwd(orc):
         assert np.abs(got - r).max() <= 1e-4 * np.abs(r).max()
 
 
-def test_mse_grad_and_sgd():
+def test_mse_grad_and_sgd(orc):
+    """Loss and dloss/dKh against the oracle's MSE of Sec. 3 (FP32 network outputs, FP64
+    labels); the update is w - lr g elementwise."""
     g = torch.Generator(device="cpu").manual_seed(1)
     Kh = torch.randn(1000, generator=g).to(torch.float32).to(dev())
     K = torch.randn(1000, generator=g, dtype=torch.float64).to(dev())
     E, loss = learn.mse_grad(Kh, K, 3.0)
-    d = (Kh.double() - K) * 3.0
-    assert abs(float(loss) - float((d * d).mean())) <= 1e-12 * float((d * d).mean())
-    assert torch.allclose(E.double(), 2 * d * 3.0 / 1000, rtol=1e-6, atol=0)
+    ref_loss, ref_E = orc.mse_grad(to_np(Kh).astype(np.float64), to_np(K), 3.0)
+    assert abs(float(loss) - ref_loss) <= 1e-12 * ref_loss
+    assert np.allclose(to_np(E).astype(np.float64), ref_E, rtol=1e-6, atol=0)
     w = torch.ones(10, device=dev())
     learn.sgd_update(w, torch.arange(10, dtype=torch.float32, device=dev()), 0.5)
     assert torch.equal(w.cpu(), 1 - 0.5 * torch.arange(10, dtype=torch.float32))
