@@ -316,6 +316,21 @@ int wk_surrogate_fwd(const wk_mesh* mesh, int32_t N, const float* wV, const floa
                      int32_t n_cells, int32_t prec, void* K_out, void* ws, size_t ws_bytes,
                      void* stream);
 
+/* wk_surrogate_fwd_static -- wk_surrogate_fwd without a workspace argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * wk_surrogate_fwd; its scratch is a library-owned device array of
+ * wk_surrogate_fwd_static_max() bytes (4 MiB; every device the library runs on holds one
+ * until the process ends), enough for every supported shape with n_m <= 1024.  Shapes whose scratch
+ * (wk_surrogate_fwd_workspace) exceeds it fail with WK_EINVAL.  The call allocates
+ * nothing; its first call on a device resolves that device's array address once.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (two streams, two
+ * threads) race and must be serialised by the caller. */
+size_t wk_surrogate_fwd_static_max(void);
+int wk_surrogate_fwd_static(const wk_mesh* mesh, int32_t N, const float* wV, const float* wT,
+                            const float* W, const double* V, int32_t B, const int32_t* cells,
+                            int32_t n_cells, int32_t prec, void* K_out, void* stream);
+
 /* wk_surrogate_bwd -- gradients of L = sum E * Kh with respect to wV, wT, W (written,
  * float) and V (accumulated into dV [B][nx] double, may be NULL); E [B*n_cells][P] float.
  * Deterministic two-level reductions.  ws: wk_surrogate_workspace() bytes. */

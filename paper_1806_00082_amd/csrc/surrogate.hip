@@ -7,6 +7,8 @@
 //   Pi(t)    = prod_{s < log2 N} cos(2^s pi m / n_m)
 // A is a stride-N convolution of the potential (the f_V of Sec. 3) built per row tile in
 // LDS; Bm and Pi are tiny (H x P, P) and are formed once per call by surr_prep.
+#include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -1117,3 +1119,56 @@ extern "C" int wk_sgd_update(float* w, const float* grad, int32_t n, float lr, v
     return check_launch("wk_sgd_update");
 }
 
+// ----------------------------------------------------------------------------- no-alloc forward
+// Scratch of wk_surrogate_fwd_static: one file-scope device array per GPU.  In host code the
+// array's name is a host-side stand-in, not a device address; the kernels only ever receive
+// the address hipGetSymbolAddress returns for the current device, resolved once per device on
+// the entry point's first call there.  Every call on a device shares that device's copy.
+namespace wk {
+constexpr size_t SURR_STATIC_BYTES = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[SURR_STATIC_BYTES];
+
+static void* static_scratch(int* err) {
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    int dev = 0;
+    *err = WK_OK;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *err = fail(WK_EHIP, "wk_surrogate_fwd_static: hipGetDevice failed");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) return it->second;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+        *err = fail(WK_EHIP, std::string("wk_surrogate_fwd_static: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        return nullptr;
+    }
+    addr[dev] = p;
+    return p;
+}
+}  // namespace wk
+
+extern "C" size_t wk_surrogate_fwd_static_max(void) { return wk::SURR_STATIC_BYTES; }
+
+extern "C" int wk_surrogate_fwd_static(const wk_mesh* mesh, int32_t N, const float* wV, const float* wT,
+                                       const float* W, const double* V, int32_t B,
+                                       const int32_t* cells, int32_t n_cells, int32_t prec,
+                                       void* K_out, void* stream) {
+    int H;
+    int rc = surr_fwd_check(mesh, N, wV, wT, W, V, B, cells, n_cells, prec, K_out, &H);
+    if (rc) return rc;
+    if ((long)B * n_cells == 0) return WK_OK;
+    const size_t need = surr_fwd_scratch_bytes(mesh, N);
+    if (need > SURR_STATIC_BYTES)
+        return fail(WK_EINVAL, "wk_surrogate_fwd_static: n_m = " + std::to_string(mesh->n_m) + ", N = " +
+                                   std::to_string(N) + " needs " + std::to_string(need) +
+                                   " bytes of scratch, above the static " +
+                                   std::to_string(SURR_STATIC_BYTES) + " (use wk_surrogate_fwd)");
+    int err;
+    void* ptr = static_scratch(&err);
+    if (!ptr) return err;
+    return surr_fwd_run(mesh, N, H, wV, wT, W, V, B, cells, n_cells, prec, K_out, ptr, as_stream(stream));
+}
