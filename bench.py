@@ -2,20 +2,22 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-forms] [--no-cpu]
 
-Headline workload: the 1-D paper-shaped run (400 cells of 0.5 nm, L_C = 40 nm -> 80
-pseudo-momenta, Gaussian barrier 0.3 eV sigma 2 nm at 100 nm, Gaussian packet at 50 nm
-sigma 10 nm with 0.1 eV, 1e7 signed particles in FP32, dt = 0.5 fs, annihilation every
-step).  One step = kernel rows for newly occupied cells (every 8 steps) + creation tables +
-sp_step (creation at rate gamma, drift, absorbing boundaries) + sp_annihilate.  W warm-up
-steps, then exactly K timed steps (default W + K = the run's 400 steps).
+Headline workload: the 2-D run (256 x 256 cells of 0.5 nm, L_C = 16 nm -> 32 x 32
+pseudo-momenta, Gaussian dot 0.2 eV sigma 4 nm at (64, 64) nm, Gaussian packet sigma 8 nm at
+(32, 64) nm with 0.1 eV along +x, 5e7 signed particles in FP32, dt = 0.5 fs, annihilation
+every step), the largest workload that fits one GPU.  One step = kernel rows for newly
+occupied cells (every 8 steps, straight into the creation tables) + sp_step (creation at
+rate gamma, drift, absorbing boundaries, signed histogram) + sp_annihilate.  W warm-up
+steps, then exactly K timed steps (default W + K = the run's 200 steps).
 
 value = particle-steps/s = sum over timed steps of the particle count at the start of the
 step, divided by the time between the events bracketing the K steps (inputs resident in HBM).
 
-Also reported (same JSON line): kernel entries/s of eq.(4) on the precision batch (4096
-potentials x 2048 cells x 512 m) in FP64 and the BF16/FP16 (+split) forms with their
-normwise error against the FP64 path, and the learned eq.(5) forward on 1024-cell, 256-m
-potentials; the CPU oracle timed on a bounded sample of the headline run.
+Also reported (same JSON line): the 1-D paper-shaped run (400 cells, 1e7 particles) as a
+secondary line; kernel entries/s of eq.(4) on the precision batch (4096 potentials x 2048
+cells x 512 m) in FP64 and the BF16/FP16 (+split) forms with their normwise error against
+the FP64 path; the learned eq.(5) forward, its training on 1e5 random potentials
+(1024 cells x 256 m) and the run it drives; the CPU oracle timed on bounded samples.
 """
 from __future__ import annotations
 
@@ -36,13 +38,13 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
                "fp32": 157.3}
 
 
-# HBM traffic per launch (GB) over the timed steps of this benchmark, from two rocprofv3
-# counter runs (FETCH_SIZE, then WRITE_SIZE) of `bench.py --no-forms --no-cpu --no-trace
-# --copy-calibration`, scaled by what the counters read for a 1 GiB device copy (fetch x2.0,
-# write x1.0).  Taken for the kernels as they are now; an entry is dropped when its kernel
-# changes until the counters are taken again.
-TRAFFIC = {"step_count": 0.0671, "step_apply": 0.2082, "annih_count": 0.0920,
-           "annih_scan": 0.0001, "annih_write": 0.1693}
+# HBM traffic per launch (GB) of the particle kernels of each workload over its timed steps,
+# from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE) of `bench.py --no-forms
+# --no-cpu --no-trace --copy-calibration` (2-D: the headline; 1-D: with --headline-1d), scaled
+# by what the counters read for a 1 GiB device copy (fetch x2.0, write x1.0).  Taken for the
+# kernels as they are now; an entry is dropped when its kernel changes until the counters are
+# taken again.
+TRAFFIC = {"1d": {}, "2d": {}}
 
 
 def _events():
@@ -51,30 +53,32 @@ def _events():
 
 
 # Algorithmic HBM bytes per launch of each particle kernel, from the running sums the
-# library keeps (S = stats): what the pass must move at minimum with PB-byte particles (the
-# headline's: x 4 + M 2 + s 1 = 7, FP32 positions and 16-bit momenta).  The histogram and
-# the tables are L2-resident; the pair counts the two sp_step passes hand over are not
-# counted (an implementation choice).
-def kernel_bytes(PB: int):
+# library keeps (S = stats): what the pass must move at minimum with PB-byte particles
+# (1-D: x 4 + M 2 + s 1 = 7; 2-D: x 4 + y 4 + M 2 + My 2 + s 1 = 13) and, where the pass
+# clears or walks the signed histogram (2-D: 2 x 4 B x 67M bins, beyond every cache), that
+# histogram.  The 1-D histogram and all tables are L2-resident and not counted; neither are
+# the pair counts the two sp_step passes hand over (an implementation choice).
+def kernel_bytes(PB: int, dim: int, hist_bytes: int):
+    pos = 4 * dim + 1            # what the counting pass reads: positions and sign
+    H = hist_bytes if dim == 2 else 0
     return {
-        "step_count": lambda S, L: 5 * S[L.ST_CUM_N],                                # read x 4 + s 1
-        "step_apply": lambda S, L: 2 * PB * (S[L.ST_CUM_N] + S[L.ST_CUM_PAIRS]),    # read, write; 2 children
-        "annih_count": lambda S, L: PB * S[L.ST_CUM_ANNIH_IN],                       # read
+        "step_count": lambda S, L: pos * S[L.ST_CUM_N] + H * S[L.ST_CUM_STEPS],      # + histogram clear
+        "step_apply": lambda S, L: 2 * PB * (S[L.ST_CUM_N] + S[L.ST_CUM_PAIRS]),     # read, write; 2 children
+        "annih_count": lambda S, L: PB * S[L.ST_CUM_ANNIH_IN] + H * S[L.ST_CUM_STEPS],  # + histogram walk
         "annih_write": lambda S, L: PB * (S[L.ST_CUM_ANNIH_IN] + S[L.ST_CUM_KEPT]
                                           + S[L.ST_CUM_REGEN]),                      # read, write kept + placed
     }
 
 
-def run_headline(steps: int, warmup: int, traced: bool):
-    """The headline run.  traced=True replays the identical (bit-exact, same seed) run with
-    per-kernel events, used only for the per-kernel roofline; the headline value comes from
+def run_particles(cfg, steps: int, warmup: int, traced: bool):
+    """A time-loop workload.  traced=True replays the identical (bit-exact, same seed) run with
+    per-kernel events, used only for the per-kernel roofline; the reported value comes from
     the untraced run."""
     import torch
     from paper_1806_00082_amd import _lib as L
-    from paper_1806_00082_amd import inputs
+    from paper_1806_00082_amd import ops
     from paper_1806_00082_amd.sim import Simulator
 
-    cfg = inputs.config_c2()
     sim = Simulator(cfg, kernel="exact", prec="fp64", mode="occupied", refresh_every=8)
     for _ in range(warmup):
         sim.step()
@@ -94,29 +98,41 @@ def run_headline(steps: int, warmup: int, traced: bool):
     S = [int(v) for v in sim.stats.cpu().tolist()]
     assert S[L.ST_OVERFLOW] == 0, "particle buffer overflowed during the timed run"
     assert S[L.ST_CUM_STEPS] == steps
+    dim = sim.dim
     out = {"cfg": cfg, "ms": ms, "wall_s": wall, "particle_steps": float(S[L.ST_CUM_N]),
            "pairs": S[L.ST_CUM_PAIRS], "regen": S[L.ST_CUM_REGEN], "n_last": int(sim.count()),
            "rows": sim.n_rows, "stats": S}
+    pbytes = (8 if sim.md["pos_f64"] else 4) * dim + (2 if (dim == 2 or sim.a.m16) else 4) * dim + 1
+    out["particle_bytes"] = pbytes
+    hist_bytes = 2 * 4 * ops.n_bins(sim.md)
+    del sim
+    torch.cuda.empty_cache()
     if not traced:
         return out
     L.check(L.lib().wk_trace_disable(), "wk_trace_disable")
-    pbytes = (8 if sim.md["pos_f64"] else 4) + (2 if sim.a.m16 else 4) + 1
-    out["particle_bytes"] = pbytes
-    KB = kernel_bytes(pbytes)
+    KB = kernel_bytes(pbytes, dim, hist_bytes)
     kernels = {}
     for name in L.trace_names():
         tot, cnt = L.trace_read(name)
         kernels[name] = {"ms_total": round(tot, 3), "launches": cnt, "us_avg": round(1e3 * tot / max(cnt, 1), 2)}
         if name in KB:
             b = KB[name](S, L)
-            kernels[name]["alg_GB"] = round(b / 1e9, 3)
+            kernels[name]["alg_GB_per_launch"] = round(b / max(cnt, 1) / 1e9, 4)
             kernels[name]["alg_GBps"] = round(b / (tot * 1e-3) / 1e9, 1)
     dom = max((k for k in kernels if k in KB), key=lambda k: kernels[k]["ms_total"])
     ach = kernels[dom]["alg_GBps"]
+    traffic = TRAFFIC["2d" if dim == 2 else "1d"].get(dom)
     out["kernels"] = kernels
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                       "traffic": TRAFFIC.get(dom)}
+                       "traffic": traffic,
+                       "alg_GB_per_launch": kernels[dom]["alg_GB_per_launch"],
+                       "us_per_launch": kernels[dom]["us_avg"]}
+    # the whole step against the sum of its kernels' algorithmic bytes
+    tot_b = sum(KB[k](S, L) for k in KB)
+    out["step_roofline"] = {"alg_GB_per_step": round(tot_b / steps / 1e9, 4),
+                            "achieved_GBps": round(tot_b / (ms * 1e-3) / 1e9, 1),
+                            "frac": round(tot_b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     return out
 
 
@@ -243,34 +259,101 @@ def run_learning(B=64, N=4, reps=5):
     return out
 
 
-def run_2d(steps=40, warmup=8, fused_tables=True):
-    """The 2-D workload: 256 x 256 cells of 0.5 nm, 32 x 32 momenta, 5e7 particles, exact FP64
-    kernel rows formed near occupied cells (refreshed every 8 steps) straight into the creation
-    tables, annihilation every step."""
+def run_learning_c4(n_train=100000, n_test=1000, sweep_epochs=3, train_epochs=6, batch=64,
+                    driven_particles=1e7, driven_steps=400):
+    """The learned form at its workload (Sec. 3): eq.(5) trained by SGD on the MSE against
+    exact eq.(4) labels (computed per batch in FP64) for n_train random Gaussian-bell
+    potentials of 1024 cells x 256 m, scored on n_test held-out ones, for H = 128, 64, 32
+    (N = 2, 4, 8).  (a) One learning rate for every weight group, the paper's three values,
+    from weights perturbed off the barycentric ones (the Fig. 3 analogue: mean batch loss per
+    epoch).  (b) Per-group steps below each group's stability limit, from the barycentric
+    weights: what training gains on held-out data.  (c) The trained N = 2 network drives the
+    1e7-particle barrier run on the same mesh next to the exact kernel and the untrained one."""
+    import numpy as np
     import torch
-    from paper_1806_00082_amd import _lib as L
-    from paper_1806_00082_amd import inputs
+    from paper_1806_00082_amd import inputs, learn
     from paper_1806_00082_amd.sim import Simulator
 
-    cfg = inputs.config_c5()
-    sim = Simulator(cfg, fused_tables=fused_tables)
-    sim.run(warmup)
-    torch.cuda.synchronize()
-    sim.stats[L.ST_CUM_STEPS:L.ST_COUNT].zero_()
-    e0, e1 = _events()
-    e0.record()
-    sim.run(steps)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    S = sim.stats.cpu().tolist()
-    out = {"workload": "2-D: 256x256 cells, 32x32 m, 5e7 particles, exact fp64 rows near occupied cells",
-           "steps": steps, "ms_per_step": round(ms / steps, 4),
-           "particle_steps_per_s": S[L.ST_CUM_N] / (ms * 1e-3), "n_last": sim.count(),
-           "kernel_rows": sim.n_rows,
-           "kernel_row_table_MB": 0.0 if sim.fused else round(sim.Kbuf.numel() * sim.Kbuf.element_size() / 1e6, 1)}
-    del sim
+    c4 = inputs.C4
+    nx, n_m, dx = c4["nx"], c4["n_m"], c4["dx"]
+    dev = torch.device("cuda")
+    t0 = time.perf_counter()
+    Vtr = torch.from_numpy(inputs.random_potentials(n_train, nx, dx, seed=c4["seed"])).to(dev)
+    Vte = torch.from_numpy(inputs.random_potentials(n_test, nx, dx, seed=c4["test_seed"])).to(dev)
+    out = {"workload": f"{n_train} training / {n_test} held-out potentials x {nx} cells x {n_m} m, "
+                       f"batch {batch}, labels eq.(4) FP64 per batch, forward/backward FP32",
+           "data_gen_s": round(time.perf_counter() - t0, 1)}
+    g = torch.Generator().manual_seed(0)
+    per_group_lr = (2.0, 5e-4, 30.0)
+    trained = {}
+    for N in (2, 4, 8):
+        H = n_m // N
+        wb = learn.analytic_weights(n_m, N, device=dev)
+        rec = {"barycentric": {"held_out_rel_rms": learn.surrogate_rms_error(Vte, n_m, N, *wb),
+                               "held_out_normwise": learn.surrogate_error(Vte, n_m, N, *wb)}}
+        pert = (wb[0] * (1 + 0.3 * torch.randn(N, generator=g)).to(dev),
+                wb[1] * (1 + 0.01 * torch.randn(N, generator=g)).to(dev),
+                wb[2] * (0.8 + 0.2 * torch.rand(H, generator=g)).to(dev))
+        rec["perturbed_start_rel_rms"] = learn.surrogate_rms_error(Vte, n_m, N, *pert)
+        sweep = {}
+        for lr in (1e-3, 1e-4, 1e-5):
+            r = learn.train_surrogate(Vtr, n_m, N, epochs=sweep_epochs, batch=batch, lr=lr, init=pert, seed=1)
+            fin = [float(w.abs().max()) for w in (r.wV, r.wT, r.W)]
+            sweep[f"{lr:g}"] = {"epoch_loss": [round(x, 6) for x in r.losses],
+                                "held_out_rel_rms": (learn.surrogate_rms_error(Vte, n_m, N, r.wV, r.wT, r.W)
+                                                     if all(np.isfinite(fin)) else float("nan")),
+                                "steps_per_s": round(r.steps / r.seconds, 1)}
+        rec["lr_sweep_single_lr"] = sweep
+        r = learn.train_surrogate(Vtr, n_m, N, epochs=train_epochs, batch=batch, lr=per_group_lr, init=wb, seed=2)
+        rms = learn.surrogate_rms_error(Vte, n_m, N, r.wV, r.wT, r.W)
+        rec["trained"] = {"lr_per_group": per_group_lr, "epochs": train_epochs,
+                          "epoch_loss": [round(x, 6) for x in r.losses],
+                          "held_out_rel_rms": rms,
+                          "held_out_normwise": learn.surrogate_error(Vte, n_m, N, r.wV, r.wT, r.W),
+                          "mse_gain_vs_barycentric": 1.0 - (rms / rec["barycentric"]["held_out_rel_rms"]) ** 2,
+                          "seconds": round(r.seconds, 2), "steps": r.steps,
+                          "weights": {"wV": r.wV.tolist(), "wT": r.wT.tolist(),
+                                      "W_over_c_mean": float((r.W / wb[2]).mean()),
+                                      "W_over_c_min": float((r.W / wb[2]).min()),
+                                      "W_over_c_max": float((r.W / wb[2]).max())}}
+        trained[N] = (r.wV, r.wT, r.W)
+        out[f"N{N}_H{H}"] = rec
+    del Vtr, Vte
     torch.cuda.empty_cache()
+    if driven_steps:
+        cfg = inputs.config_c4_run(N0=driven_particles, steps=driven_steps)
+        runs = {}
+        for tag, kind, N, w in (("exact_fp64", "exact", 1, None),
+                                ("surrogate_N2_trained", "surrogate", 2, trained[2]),
+                                ("surrogate_N2_barycentric", "surrogate", 2, learn.analytic_weights(n_m, 2))):
+            sim = Simulator(cfg, kernel=kind, N=N, weights=w, prec="fp64" if kind == "exact" else "fp32",
+                            cap_factor=3.0)
+            torch.cuda.synchronize()
+            e0, e1 = _events()
+            e0.record()
+            sim.run(driven_steps)
+            e1.record()
+            torch.cuda.synchronize()
+            assert not sim.overflowed()
+            gam = sim.gamma[:sim.n_rows].cpu().numpy()
+            slot = sim.cell_slot.cpu().numpy()
+            runs[tag] = {"ms_per_step": round(e0.elapsed_time(e1) / driven_steps, 4), "n_last": sim.count(),
+                         "rho": sim.density().cpu().numpy(),
+                         "gamma": np.where(slot >= 0, gam[np.maximum(slot, 0)], 0.0)}
+            del sim
+            torch.cuda.empty_cache()
+        xc = (np.arange(cfg.mesh.nx) + 0.5) * cfg.mesh.dx
+        ref = runs["exact_fp64"]
+        drv = {"workload": f"1-D barrier run on {cfg.mesh.nx} cells x {n_m} m, {driven_particles:.0e} particles, "
+                           f"{driven_steps} x {cfg.dt} fs"}
+        for tag, r in runs.items():
+            both = (ref["gamma"] > 0) & (r["gamma"] > 0)
+            drv[tag] = {"ms_per_step": r["ms_per_step"], "n_last": r["n_last"],
+                        "mean_x_nm": float((r["rho"] * xc).sum() / r["rho"].sum()),
+                        "rho_L1_vs_exact": float(np.abs(r["rho"] - ref["rho"]).sum()),
+                        "gamma_max_rel_diff_vs_exact": float(np.abs(r["gamma"][both] - ref["gamma"][both]).max()
+                                                             / ref["gamma"].max())}
+        out["driven_run"] = drv
     return out
 
 
@@ -361,68 +444,183 @@ def run_tables_forms(reps=5):
     return out
 
 
-def run_cpu_baseline(sample_steps: int):
-    """The oracle (single-threaded C, one core) on the first steps of the headline run."""
+def _oracle_rows_2d(args):
+    """Worker: oracle eq.(4) rows (direct d = 2 sum) for a chunk of cells."""
+    import oracle as orc
+    V, n_m, hbar, cells = args
+    return orc.kernel_2d(V, n_m, hbar, cells=cells)[0]
+
+
+def run_cpu_particles(sample_steps: int):
+    """The oracle (single-threaded C, one core) on the first steps of the headline run: its
+    sp_step and sp_annihilate over all 5e7 particles.  The oracle's kernel rows and creation
+    tables for the cells the particles can reach in those steps are built first, untimed, by
+    a pool of oracle processes."""
+    import multiprocessing as mp
+
     import numpy as np
     import oracle as orc
     from paper_1806_00082_amd import inputs
 
-    cfg = inputs.config_c2()
+    cfg = inputs.config_c5()
     md = cfg.mesh.as_dict(cfg.dt)
-    K = orc.kernel_1d(cfg.V, cfg.mesh.n_m, inputs.HBAR_EVFS)[0]
+    nx, ny, n_m = md["nx"], md["ny"], md["n_m"]
+    occ = cfg.bin_counts.reshape(ny, nx, -1).sum(-1) > 0
+    pad = int(np.ceil(sample_steps * abs(md["vdt"]) * max(abs(md["M_min"]), md["M_min"] + md["n_k"]))) + 1
+    reach = np.zeros_like(occ)
+    for dy in range(-pad, pad + 1):
+        for dx in range(-pad, pad + 1):
+            reach |= np.roll(np.roll(occ, dy, 0), dx, 1)
+    cells = np.flatnonzero(reach).astype(np.int32)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    chunks = np.array_split(cells, workers * 4)
+    with mp.get_context("spawn").Pool(workers) as pool:
+        rows = pool.map(_oracle_rows_2d, [(cfg.V, n_m, inputs.HBAR_EVFS, c) for c in chunks])
+    K = np.concatenate(rows).reshape(len(cells), n_m * n_m)
     _, n0, thr, cdf = orc.gamma_tables(K, cfg.dt)
-    p = orc.sp_init(md, cfg.bin_counts, 3 * int(cfg.bin_counts.sum()), seed=cfg.seed)
-    slot = np.arange(md["nx"], dtype=np.int32)
+    slot = np.full(nx * ny, -1, np.int32)
+    slot[cells] = np.arange(len(cells), dtype=np.int32)
+    t_tables = time.perf_counter() - t0
+    n_init = int(cfg.bin_counts.sum())
+    p = orc.sp_init(md, cfg.bin_counts, int(1.3 * n_init), seed=cfg.seed)
     ps = 0
     t0 = time.perf_counter()
     for s in range(sample_steps):
         ps += p.n
         p, _ = orc.sp_step(md, p, (n0, thr, cdf), slot, step=s, seed=cfg.seed)
-        p, _, _, _ = orc.sp_annihilate(md, p, step=s, seed=cfg.seed)
+        p, _, _, _ = orc.sp_annihilate(md, p, step=s, seed=cfg.seed, capacity=p.capacity)
     dt = time.perf_counter() - t0
     return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_steps} steps of the 1e7-particle run (sp_step + sp_annihilate), "
-                      f"{dt:.1f} s on one host core"}
+            "sample": f"first {sample_steps} steps of the 2-D 5e7-particle run (sp_step + sp_annihilate, "
+                      f"{ps:.3g} particle-steps in {dt:.1f} s on one host core; the oracle's kernel rows and "
+                      f"creation tables for the {len(cells)} reachable cells built beforehand, untimed, in "
+                      f"{t_tables:.1f} s by {workers} oracle processes)"}
+
+
+def run_cpu_kernel(n_pot: int):
+    """The oracle's eq.(4) (single-threaded C, one core) on the first potentials of the
+    precision batch (2048 cells x 512 m each)."""
+    import oracle as orc
+    from paper_1806_00082_amd import inputs
+
+    c3 = inputs.C3
+    V = inputs.random_potentials(n_pot, c3["nx"], c3["dx"], seed=c3["seed"])
+    t0 = time.perf_counter()
+    orc.kernel_1d(V, c3["n_m"], inputs.HBAR_EVFS)
+    dt = time.perf_counter() - t0
+    entries = n_pot * c3["nx"] * c3["n_m"]
+    return {"value": entries / dt, "unit": "kernel entries/s", "cores": 1, "kind": "oracle",
+            "sample": f"eq.(4) full tables of the first {n_pot} potentials of the precision batch "
+                      f"({entries} entries in {dt:.1f} s on one host core)"}
+
+
+def host_info():
+    info = {"cpu_count": os.cpu_count()}
+    try:
+        info["affinity_cores"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return info
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=390)
+    ap.add_argument("--steps", type=int, default=190)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-potentials", type=int, default=2)
+    ap.add_argument("--headline-1d", action="store_true",
+                    help="time the 1-D 1e7-particle run as the headline (for its counter runs)")
     ap.add_argument("--no-trace", action="store_true",
                     help="skip the traced replica (for counter runs under rocprofv3 --pmc)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 1 GiB device copies (counter calibration)")
     ap.add_argument("--forms-only", action="store_true",
                     help="only the eq.(4) precision batch (for counter runs on the contraction)")
+    ap.add_argument("--learning-only", action="store_true",
+                    help="only the training study of eq.(5) (with --train-epochs, --sweep-epochs)")
+    ap.add_argument("--train-epochs", type=int, default=6)
+    ap.add_argument("--sweep-epochs", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(particles, cells and kernel rows are not sharded across devices).", file=sys.stderr)
         sys.exit(2)
     import torch
+    if torch.cuda.device_count() < 1:          # counts devices without initialising HIP
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    # the CPU oracle legs run first, before anything touches the GPU
+    cpu = cpu_kernel = None
+    if not (args.no_cpu or args.forms_only or args.learning_only or args.headline_1d):
+        print("cpu baseline: oracle particle passes", file=sys.stderr, flush=True)
+        cpu = run_cpu_particles(args.cpu_steps)
+        print("cpu baseline: oracle eq.(4)", file=sys.stderr, flush=True)
+        cpu_kernel = run_cpu_kernel(args.cpu_potentials)
+        cpu["host"] = cpu_kernel["host"] = host_info()
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    from paper_1806_00082_amd import inputs
     if args.forms_only:
         print(json.dumps({"forms": {"kernel_eq4": run_kernel_forms()}}))
         return
-    h = run_headline(args.steps, args.warmup, traced=False)
+    if args.learning_only:
+        print(json.dumps({"forms": {"learning_c4": run_learning_c4(sweep_epochs=args.sweep_epochs,
+                                                                   train_epochs=args.train_epochs)}}))
+        return
+    cfg = inputs.config_c2() if args.headline_1d else inputs.config_c5()
+    print(f"headline: {cfg.name}, {args.warmup} + {args.steps} steps", file=sys.stderr, flush=True)
+    h = run_particles(cfg, args.steps, args.warmup, traced=False)
     tr = h
     if not args.no_trace:
-        tr = run_headline(args.steps, args.warmup, traced=True)
+        tr = run_particles(cfg, args.steps, args.warmup, traced=True)
         assert tr["stats"][11:16] == h["stats"][11:16], "traced replica diverged from the timed run"
-    forms = {} if args.no_forms else {"kernel_eq4": run_kernel_forms(), "surrogate_eq5": run_surrogate_forms(),
-                                      "learning": run_learning(), "tables": run_tables_forms(),
-                                      "workload_2d": run_2d()}
-    cpu = None if args.no_cpu else run_cpu_baseline(args.cpu_steps)
+    forms = {}
+    if not args.no_forms and not args.headline_1d:
+        print("secondary: 1-D 1e7-particle run", file=sys.stderr, flush=True)
+        c2 = inputs.config_c2()
+        s1 = run_particles(c2, 390, 10, traced=False)
+        s1t = run_particles(c2, 390, 10, traced=True)
+        assert s1t["stats"][11:16] == s1["stats"][11:16], "traced replica diverged from the timed run"
+        forms["workload_1d"] = {
+            "workload": f"{c2.name}: 1-D, 400 cells x 80 m, 1e7 particles, 390 timed steps",
+            "ms_per_step": round(s1["ms"] / 390, 4),
+            "particle_steps_per_s": s1["particle_steps"] / (s1["ms"] * 1e-3),
+            "note": "double-buffered 7-byte particles (2 x 70 MB) fit the 256 MB MALL: its HBM fraction "
+                    "is a cache-assisted figure, the headline's 2-D run is not",
+            "roofline": s1t["roofline"], "step_roofline": s1t["step_roofline"], "kernels": s1t["kernels"]}
+        for name, fn in (("kernel_eq4", run_kernel_forms), ("surrogate_eq5", run_surrogate_forms),
+                         ("learning", run_learning), ("tables", run_tables_forms),
+                         ("learning_c4", lambda: run_learning_c4(sweep_epochs=args.sweep_epochs,
+                                                                 train_epochs=args.train_epochs))):
+            print(f"forms: {name}", file=sys.stderr, flush=True)
+            forms[name] = fn()
+        if cpu_kernel is not None:
+            k = forms["kernel_eq4"]["fp64"]
+            forms["kernel_eq4"]["cpu_baseline"] = cpu_kernel
+            forms["kernel_eq4"]["fp64"]["vs_cpu_oracle"] = round(k["entries_per_s"] / cpu_kernel["value"], 1)
     value = h["particle_steps"] / (h["ms"] * 1e-3)
-    cfg = h["cfg"]
+    dim = cfg.mesh.dim
+    config = {"workload": cfg.name, "dim": dim, "dx_nm": cfg.mesh.dx, "n_m": cfg.mesh.n_m,
+              "particles_initial": int(cfg.bin_counts.sum()), "dt_fs": cfg.dt,
+              "annihilation": "every step", "kernel": "exact fp64 rows near occupied cells, fused into the "
+                                                     "creation tables",
+              "particle_layout": ("x, y fp32, Mx, My int16, s int8 (13 B)" if dim == 2
+                                  else "x fp32, M int16, s int8 (7 B)")}
+    config["cells"] = (f"{cfg.mesh.nx}x{cfg.mesh.ny}" if dim == 2 else cfg.mesh.nx)
     line = {
         "metric": METRIC,
         "value": value,
@@ -436,14 +634,11 @@ def main():
         "vs_baseline": None,
         "dtype": "int16+fp32 (fp64 kernel and tables)",
         "data": "synthetic",
-        "config": {"workload": cfg.name, "cells": cfg.mesh.nx, "dx_nm": cfg.mesh.dx,
-                   "n_m": cfg.mesh.n_m, "particles_initial": int(cfg.bin_counts.sum()),
-                   "dt_fs": cfg.dt, "annihilation": "every step", "kernel": "exact fp64, occupied cells",
-                   "particle_layout": "x fp32, M int16, s int8 (7 B)"},
+        "config": config,
         "run": {"n_last": h["n_last"], "pairs_created": h["pairs"], "regenerated": h["regen"],
                 "kernel_rows_evaluated": h["rows"], "wall_s": round(h["wall_s"], 3),
                 "traced_replica_ms_per_step": round(tr["ms"] / args.steps, 4),
-                "kernels": tr.get("kernels")},
+                "kernels": tr.get("kernels"), "step_roofline": tr.get("step_roofline")},
         "roofline": tr.get("roofline"),
         "cpu_baseline": cpu,
         "forms": forms,
