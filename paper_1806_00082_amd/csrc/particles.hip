@@ -44,11 +44,15 @@ constexpr int NW = PB * WPB;  // wave chunks of the ordered passes
 constexpr int PLACE_BLOCKS = PB;  // workgroups placing regenerated / initial particles
 constexpr int CT_MAX = 1024;       // cells of the LDS creation table (larger meshes: ctab)
 
+constexpr int PLACE_WAVES = PLACE_BLOCKS * WPB;
+// Placement work items: each bin chunk's particles to place, in pieces of at most PIECE slots.
+constexpr int PIECE = 2048;
+
 // Workspace (sp_workspace_size): int64 scalars[16] | int64 bcnt[PB] | int64 wcnt[NW] |
-// int64 bpart[PB] | int64 bmixed[PB] | int64 kpre[PB] | int64 bpre[PB] |
-// int32 pstart[PLACE_BLOCKS] | int32 csum[n_chunks] | uint8 occ[n_cells] | uint8 occx[n_cells] |
-// uint2 ctab[n_cells] (8-byte aligned).
-enum { SC_GO = 0, SC_PLACED = 1, SC_KEPT = 2 };
+// int64 bpart[PB] | int64 bmixed[PB] | int64 kpre[PB] | int64 bpre[PB] | int64 bitem[PB] |
+// int64 ipre[PB] | int32 wstart[PLACE_WAVES] | int32 csum[n_chunks] | uint8 occ[n_cells] |
+// uint8 occx[n_cells] | uint2 ctab[n_cells] (8-byte aligned).
+enum { SC_GO = 0, SC_PLACED = 1, SC_KEPT = 2, SC_ITEMS = 3 };
 
 struct WS {
     long long* sc;
@@ -58,7 +62,9 @@ struct WS {
     long long* bmixed;  // per bin workgroup: mixed bins
     long long* kpre;    // exclusive prefix of the survivor counts (bcnt) of sp_annihilate
     long long* bpre;    // inclusive prefix of bpart
-    int* pstart;        // per placing workgroup: first bin workgroup of its slot range
+    long long* bitem;   // per bin workgroup: placement work items (pieces of its chunks)
+    long long* ipre;    // inclusive prefix of bitem
+    int* wstart;        // per placing wave: bin workgroup holding its first work item
     int* csum;          // per bin chunk: particles to place
     uint8_t* occ;
     uint2* ctab;        // meshes above CT_MAX cells: (n0, thr) per cell, gathered each step
@@ -76,8 +82,10 @@ static WS carve(void* ws, long n_bins, long n_cells) {
     w.bmixed = w.bpart + PB;
     w.kpre = w.bmixed + PB;
     w.bpre = w.kpre + PB;
-    w.pstart = reinterpret_cast<int*>(w.bpre + PB);
-    w.csum = w.pstart + PLACE_BLOCKS;
+    w.bitem = w.bpre + PB;
+    w.ipre = w.bitem + PB;
+    w.wstart = reinterpret_cast<int*>(w.ipre + PB);
+    w.csum = w.wstart + PLACE_WAVES;
     w.occ = reinterpret_cast<uint8_t*>(w.csum + (n_chunks_for(n_bins) + 1) / 2 * 2);
     const uintptr_t e = reinterpret_cast<uintptr_t>(w.occ) + 2 * (size_t)n_cells;
     w.ctab = reinterpret_cast<uint2*>((e + 7) & ~(uintptr_t)7);
@@ -85,8 +93,8 @@ static WS carve(void* ws, long n_bins, long n_cells) {
 }
 
 static size_t ws_bytes_for(long n_bins, long n_cells) {
-    return sizeof(long long) * (16 + 5 * (size_t)PB + (size_t)NW) +
-           sizeof(int) * (size_t)(PLACE_BLOCKS + (n_chunks_for(n_bins) + 1) / 2 * 2) +
+    return sizeof(long long) * (16 + 7 * (size_t)PB + (size_t)NW) +
+           sizeof(int) * (size_t)(PLACE_WAVES + (n_chunks_for(n_bins) + 1) / 2 * 2) +
            2 * (size_t)n_cells +  // occupancy byte per cell, then its dilation along x
            8 + sizeof(uint2) * (n_cells > CT_MAX ? (size_t)n_cells : 0);  // aligned ctab
 }
@@ -997,7 +1005,7 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, int part_blocks, BinCou
     }
     const long c = (long)blockIdx.x - part_blocks;
     const long j0 = min(g.n_chunks, c * g.gpb), j1 = min(g.n_chunks, j0 + g.gpb);
-    long long part = 0, mixed = 0;
+    long long part = 0, mixed = 0, items = 0;
     // NB chunks at a time (2-D, where a bin workgroup walks 128 chunks): the loads of the NB
     // chunks are in flight together and one barrier serves their sums
     constexpr int NB = DIM == 2 ? 4 : 1;
@@ -1025,6 +1033,7 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, int part_blocks, BinCou
 #pragma unroll
             for (int k = 0; k < PT / 64; ++k) t += bsum[threadIdx.x][k];
             w.csum[j + threadIdx.x] = (int)t;  // < 2^31 whenever the capacity check passes
+            items += (t + PIECE - 1) / PIECE;
         }
         if (threadIdx.x == 0) {
 #pragma unroll
@@ -1035,74 +1044,105 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, int part_blocks, BinCou
         __syncthreads();  // bsum is rewritten by the next chunks
     }
     mixed = block_sum_ll(mixed, red);
+    items = block_sum_ll(items, red);
     if (threadIdx.x == 0) {
         w.bpart[c] = part;
         w.bmixed[c] = mixed;
+        w.bitem[c] = items;
     }
 }
 
-// Places the particles of one bin chunk (BC bins, chunk output count cnt_ch starting at
-// output slot ch_start) that fall in the slot range [s_lo, s_hi): the chunk's bin counts are
-// scanned in LDS and consecutive threads fill consecutive slots (coalesced stores), each
-// taking its position from its Philox block (4 draws = 4 positions in 1-D, 2 x (x, y) in 2-D).
+// One wave places the particles of one bin chunk (BC bins, chunk output count cnt_ch starting
+// at output slot ch_start) that fall in the slot range [s_lo, s_hi).  Lane j reads bins
+// 4j .. 4j+3 of the chunk; a wave scan of their counts gives every bin's first slot, which the
+// lanes keep in the wave's LDS table with the bin's cell, momenta and sign; then consecutive
+// lanes fill consecutive slots (coalesced stores), each taking its position from its Philox
+// block (4 draws = 4 positions in 1-D, 2 x (x, y) in 2-D).  No workgroup barrier: the waves
+// of a placing workgroup work on different chunks.  build = false: the table already holds
+// this chunk (consecutive pieces of one chunk).
+constexpr int PW_LDS = 6 * BC;  // ints per wave: inclusive offsets, x, kx, y, ky, sign
 template <typename T, typename MT, int DIM>
-__device__ void place_chunk(const Geo& g, const BinCount& bc, int mode, uint32_t c1, uint32_t tag,
-                            long ch, long ch_start, long cnt_ch, long s_lo, long s_hi, T* xo,
-                            T* yo, MT* Mo, MT* Myo, int8_t* so, long long capacity, int* bo_ex,
-                            int* bo_in, int* ldsw) {
+__device__ void place_chunk_wave(const Geo& g, const BinCount& bc, int mode, uint32_t c1, uint32_t tag,
+                                 long ch, long ch_start, long cnt_ch, long s_lo, long s_hi, T* xo,
+                                 T* yo, MT* Mo, MT* Myo, int8_t* so, long long capacity, int* wl,
+                                 bool build) {
     constexpr int Q = DIM == 1 ? 4 : 2;
-    const long b = ch * BC + threadIdx.x;
-    const int cnt = b < g.n_bins ? (int)bc(b) : 0;
-    int tc;
-    const int ex = block_excl_scan_pt(cnt, &tc, ldsw);
-    bo_ex[threadIdx.x] = ex;
-    bo_in[threadIdx.x] = ex + cnt;
-    // this bin's cell, momenta and sign, once per bin (32-bit index arithmetic: n_bins < 2^31)
-    int* bin_x = bo_in + BC;      // [BC] cell x
-    int* bin_kx = bin_x + BC;     // [BC] momentum index x
-    int* bin_y = bin_kx + BC;     // [BC] cell y (2-D)
-    int* bin_ky = bin_y + BC;     // [BC] momentum index y (2-D)
-    int* bin_s = bin_ky + BC;     // [BC] sign
-    if (cnt > 0) {
-        const uint32_t b32 = (uint32_t)b, nk = (uint32_t)g.n_k;
-        if (DIM == 1) {
-            const uint32_t cx = b32 / nk;
-            bin_x[threadIdx.x] = (int)cx;
-            bin_kx[threadIdx.x] = (int)(b32 - cx * nk);
-        } else {
-            const uint32_t t = b32 / nk, cc = t / nk, cy = cc / (uint32_t)g.nx;
-            bin_kx[threadIdx.x] = (int)(b32 - t * nk);
-            bin_ky[threadIdx.x] = (int)(t - cc * nk);
-            bin_x[threadIdx.x] = (int)(cc - cy * (uint32_t)g.nx);
-            bin_y[threadIdx.x] = (int)cy;
+    const int lane = threadIdx.x & 63;
+    int* bo_in = wl;            // [BC] inclusive slot offsets
+    int* m_x = wl + BC;         // [BC] cell x
+    int* m_kx = wl + 2 * BC;    // [BC] momentum index x
+    int* m_y = wl + 3 * BC;     // [BC] cell y (2-D)
+    int* m_ky = wl + 4 * BC;    // [BC] momentum index y (2-D)
+    int* m_s = wl + 5 * BC;     // [BC] sign
+    if (build) {  // else the table holds this chunk already (the previous piece's)
+        const long b0 = ch * BC + 4 * lane;
+        int cnt[4], sg[4], tot4 = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const long b = b0 + k;
+            cnt[k] = 0;
+            sg[k] = 1;
+            if (b < g.n_bins) {
+                if (bc.counts) {
+                    const int c = bc.counts[b];
+                    cnt[k] = c > 0 ? c : 0;
+                } else {
+                    const int hp = bc.hist[b], hm = bc.hist[bc.n_bins + b];
+                    if (hp > 0 && hm > 0) cnt[k] = hp > hm ? hp - hm : hm - hp;
+                    sg[k] = hp > hm ? 1 : -1;
+                }
+            }
+            tot4 += cnt[k];
         }
-        bin_s[threadIdx.x] = mode == 1 ? (bc.hist[b] > bc.hist[g.n_bins + b] ? 1 : -1) : 1;
+        int run = wave_incl_scan(tot4) - tot4;
+        wave_lds_sync();  // the previous chunk's fill has read the table
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            run += cnt[k];
+            const int j = 4 * lane + k;
+            bo_in[j] = run;
+            if (cnt[k] > 0) {
+                // this bin's cell and momenta (32-bit index arithmetic: n_bins < 2^31)
+                const uint32_t b32 = (uint32_t)(b0 + k), nk = (uint32_t)g.n_k;
+                if (DIM == 1) {
+                    const uint32_t cx = b32 / nk;
+                    m_x[j] = (int)cx;
+                    m_kx[j] = (int)(b32 - cx * nk);
+                } else {
+                    const uint32_t t = b32 / nk, cc = t / nk, cy = cc / (uint32_t)g.nx;
+                    m_kx[j] = (int)(b32 - t * nk);
+                    m_ky[j] = (int)(t - cc * nk);
+                    m_x[j] = (int)(cc - cy * (uint32_t)g.nx);
+                    m_y[j] = (int)cy;
+                }
+                m_s[j] = mode == 1 ? sg[k] : 1;
+            }
+        }
+        wave_lds_sync();
     }
-    __syncthreads();
     const int lo_c = (int)(max(s_lo, ch_start) - ch_start);            // slots of this chunk
     const int hi_c = (int)(min(s_hi, ch_start + cnt_ch) - ch_start);   // to fill: [lo_c, hi_c)
-    for (int rel = lo_c + threadIdx.x; rel < hi_c; rel += PT) {
+    for (int rel = lo_c + lane; rel < hi_c; rel += 64) {
         const int j = upper_bound_lds(bo_in, BC, rel);
-        const int r = rel - bo_ex[j];
+        const int r = rel - (j ? bo_in[j - 1] : 0);
         const long bb = ch * BC + j;
         const long o = ch_start + rel;
         if (o >= capacity) break;  // never taken after the capacity check
-        const int8_t sign = (int8_t)bin_s[j];
+        const int8_t sign = (int8_t)m_s[j];
         const u32x4 u = philox((uint32_t)bb, c1, (uint32_t)(r / Q), tag, g.seed);
         const int e = r % Q;
         if (DIM == 1) {
             const uint32_t ue = e == 0 ? u.v[0] : (e == 1 ? u.v[1] : (e == 2 ? u.v[2] : u.v[3]));
-            xo[o] = cell_plus_frac<T>(bin_x[j], ue, g.fb);
-            Mo[o] = (MT)(g.M_min + bin_kx[j]);
+            xo[o] = cell_plus_frac<T>(m_x[j], ue, g.fb);
+            Mo[o] = (MT)(g.M_min + m_kx[j]);
         } else {
-            xo[o] = cell_plus_frac<T>(bin_x[j], e ? u.v[2] : u.v[0], g.fb);
-            yo[o] = cell_plus_frac<T>(bin_y[j], e ? u.v[3] : u.v[1], g.fb);
-            Mo[o] = (MT)(g.M_min + bin_kx[j]);
-            Myo[o] = (MT)(g.M_min + bin_ky[j]);
+            xo[o] = cell_plus_frac<T>(m_x[j], e ? u.v[2] : u.v[0], g.fb);
+            yo[o] = cell_plus_frac<T>(m_y[j], e ? u.v[3] : u.v[1], g.fb);
+            Mo[o] = (MT)(g.M_min + m_kx[j]);
+            Myo[o] = (MT)(g.M_min + m_ky[j]);
         }
         so[o] = sign;
     }
-    __syncthreads();  // the LDS tables are rewritten for the next chunk
 }
 
 // Between the counting and the writing pass of sp_annihilate (mode 1) / sp_init (mode 0),
@@ -1167,9 +1207,15 @@ __global__ __launch_bounds__(ST_THREADS) void annih_scan(int mode, int place_blo
     mx = wave_sum_ll(mx);
     __syncthreads();
     const long long placed = tot[0], kept = tot[1];
-    const long per_pl = (long)((placed + place_blocks - 1) / place_blocks);
-    for (int k = threadIdx.x; k < place_blocks; k += ST_THREADS)
-        w.pstart[k] = upper_bound_lds(bp, PB, (long long)min((long)placed, (long)k * per_pl));
+    // placement work items: prefix per bin workgroup, then every placing wave's first one
+    __syncthreads();  // bp (the placed-particle prefix) has been copied out above
+    __shared__ long long n_items;
+    scan(w.bitem, nullptr, bp, &n_items);
+    for (int k = threadIdx.x; k < PB; k += ST_THREADS) w.ipre[k] = bp[k];
+    const long long nw = (long long)place_blocks * WPB;
+    const long long per_it = (n_items + nw - 1) / nw;
+    for (int v = threadIdx.x; v < nw; v += ST_THREADS)
+        w.wstart[v] = upper_bound_lds(bp, PB, (long long)min(n_items, (long long)v * per_it));
     // mixed-bin total: one value per wave, summed by thread 0
     __shared__ long long wmx[ST_THREADS / 64];
     if ((threadIdx.x & 63) == 0) wmx[threadIdx.x >> 6] = mx;
@@ -1187,6 +1233,7 @@ __global__ __launch_bounds__(ST_THREADS) void annih_scan(int mode, int place_blo
     w.sc[SC_GO] = 1;
     w.sc[SC_PLACED] = placed;
     w.sc[SC_KEPT] = kept;
+    w.sc[SC_ITEMS] = n_items;
     stats[WK_ST_N] = n_out;
     stats[WK_ST_NEEDED] = 0;
     if (mode == 1) {
@@ -1216,16 +1263,12 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
                                                   WS w) {
     constexpr int STAGE = WT * (DIM * (int)sizeof(T) + DIM * (int)sizeof(int) + 1);  // per wave
     constexpr int KEEP_LDS = WPB * STAGE + 2 * KW * (int)sizeof(int);
-    constexpr int PLACE_LDS = 2 * PT * (int)sizeof(int) + 7 * BC * (int)sizeof(int);
+    constexpr int PLACE_LDS = WPB * PW_LDS * (int)sizeof(int);
     __shared__ int ldsw[WPB];
     __shared__ long wmin[PT / 64];
     // keepers: one stage per wave + histogram window; placers: chunk and bin prefix tables
     __shared__ __align__(16) char smem[KEEP_LDS > PLACE_LDS ? KEEP_LDS : PLACE_LDS];
     int* lw = reinterpret_cast<int*>(smem + WPB * STAGE);
-    int* cs_ex = reinterpret_cast<int*>(smem);
-    int* cs_in = cs_ex + PT;
-    int* bo_ex = cs_in + PT;
-    int* bo_in = bo_ex + BC;
     if (w.sc[SC_GO] == 0) return;
     const long long placed = w.sc[SC_PLACED];
     if ((int)blockIdx.x < part_blocks) {
@@ -1288,39 +1331,58 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
         }
         return;
     }
-    // placing workgroup k: output slots [s_lo, s_hi) of the bin-ordered part
-    const long k = (long)blockIdx.x - part_blocks;
-    const long per = (placed + place_blocks - 1) / place_blocks;
-    const long s_lo = min((long)placed, k * per), s_hi = min((long)placed, s_lo + per);
-    if (s_lo >= s_hi) return;
-    for (int c = w.pstart[k]; c < PB; ++c) {  // uniform
-        const long c_start = c ? (long)w.bpre[c - 1] : 0;
-        if (c_start >= s_hi) break;
+    // placing wave v: work items [it, it_hi) of the ones dealt out evenly by annih_scan, an
+    // item being one piece of at most PIECE slots of one bin chunk.  The wave walks the bin
+    // workgroups from its first item's on, 64 chunks at a time (wave scans of their counts and
+    // item counts), and places each of its items on its own.
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long v = ((long)blockIdx.x - part_blocks) * WPB + wv;
+    const long long n_items = w.sc[SC_ITEMS];
+    const long long npw = (long long)place_blocks * WPB;
+    const long long per = (n_items + npw - 1) / npw;
+    long long it = min(n_items, (long long)v * per);
+    const long long it_hi = min(n_items, it + per);
+    if (it >= it_hi) return;
+    int* wl = reinterpret_cast<int*>(smem) + wv * PW_LDS;
+    long last_ch = -1;
+    for (int c = w.wstart[v]; c < PB && it < it_hi;) {  // uniform per wave
+        long long ib = c ? w.ipre[c - 1] : 0, sb = c ? w.bpre[c - 1] : 0;
         const long j0 = min(g.n_chunks, (long)c * g.gpb), j1 = min(g.n_chunks, j0 + g.gpb);
-        long run = c_start;
-        for (long g0 = j0; g0 < j1; g0 += PT) {  // chunk sums in groups of PT
-            const int cs = g0 + threadIdx.x < j1 ? w.csum[g0 + threadIdx.x] : 0;
-            int tot;
-            const int ex = block_excl_scan_pt(cs, &tot, ldsw);
-            cs_ex[threadIdx.x] = ex;
-            cs_in[threadIdx.x] = ex + cs;
-            __syncthreads();
-            if (run + tot > s_lo && run < s_hi) {
-                const int ng = (int)min((long)PT, j1 - g0);
-                for (int i = upper_bound_lds(cs_in, ng, (int)max(0L, s_lo - run)); i < ng; ++i) {
-                    const long ch_start = run + cs_ex[i];
-                    if (ch_start >= s_hi) break;
-                    const long cnt_ch = cs_in[i] - cs_ex[i];
-                    if (cnt_ch == 0) continue;
-                    place_chunk<T, MT, DIM>(g, bc, mode, c1, tag, g0 + i, ch_start, cnt_ch, s_lo,
-                                            s_hi, xo, yo, Mo, Myo, so, capacity, bo_ex, bo_in,
-                                            ldsw);
-                }
+        for (long g0 = j0; g0 < j1 && it < it_hi; g0 += 64) {
+            const long j = g0 + lane;
+            const long long cnt = j < j1 ? (long long)w.csum[j] : 0;
+            const long long itm = (cnt + PIECE - 1) / PIECE;
+            const long long s_inc = wave_incl_scan_ll(cnt), i_inc = wave_incl_scan_ll(itm);
+            const long long i_tot = __shfl(i_inc, 63, 64), s_tot = __shfl(s_inc, 63, 64);
+            while (it < it_hi && it < ib + i_tot) {
+                const long long rel = it - ib;
+                const int l = __builtin_ctzll(__ballot(i_inc > rel));  // the chunk holding item `it`
+                const long long i_ex = __shfl(i_inc - itm, l, 64);
+                const long long s_ex = __shfl(s_inc - cnt, l, 64);
+                const long long cn = __shfl(cnt, l, 64);
+                const long ch = g0 + l;
+                const long ch_start = (long)(sb + s_ex);
+                const long p_lo = ch_start + (long)(rel - i_ex) * PIECE;
+                const long p_hi = min(ch_start + (long)cn, p_lo + PIECE);
+                place_chunk_wave<T, MT, DIM>(g, bc, mode, c1, tag, ch, ch_start, (long)cn, p_lo, p_hi, xo,
+                                             yo, Mo, Myo, so, capacity, wl, ch != last_ch);
+                last_ch = ch;
+                ++it;
             }
-            run += tot;
-            __syncthreads();
-            if (run >= s_hi) break;
+            ib += i_tot;
+            sb += s_tot;
         }
+        // the next bin workgroup holding item `it` (skipping empty ones): first c' > c with
+        // ipre[c'] > it
+        int lo = c + 1, hi = PB;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (w.ipre[mid] > it)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        c = lo;
     }
 }
 
