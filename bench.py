@@ -56,7 +56,7 @@ def _events():
 # library keeps (S = stats): what the pass must move at minimum with PB-byte particles
 # (1-D: x 4 + M 2 + s 1 = 7; 2-D: x 4 + y 4 + M 2 + My 2 + s 1 = 13) and, where the pass
 # clears or walks the signed histogram (2-D: 2 x 4 B x 67M bins, beyond every cache), that
-# histogram.  The 1-D histogram and all tables are L2-resident and not counted; neither are
+# histogram (the 1-bit mixed-bin map annih_bins writes, 1/64 of it, is not counted).  The 1-D histogram and all tables are L2-resident and not counted; neither are
 # the pair counts the two sp_step passes hand over (an implementation choice).
 def kernel_bytes(PB: int, dim: int, hist_bytes: int):
     pos = 4 * dim + 1            # what the counting pass reads: positions and sign
@@ -64,7 +64,8 @@ def kernel_bytes(PB: int, dim: int, hist_bytes: int):
     return {
         "step_count": lambda S, L: pos * S[L.ST_CUM_N] + H * S[L.ST_CUM_STEPS],      # + histogram clear
         "step_apply": lambda S, L: 2 * PB * (S[L.ST_CUM_N] + S[L.ST_CUM_PAIRS]),     # read, write; 2 children
-        "annih_count": lambda S, L: PB * S[L.ST_CUM_ANNIH_IN] + H * S[L.ST_CUM_STEPS],  # + histogram walk
+        "annih_bins": lambda S, L: H * S[L.ST_CUM_STEPS],                             # histogram walk
+        "annih_count": lambda S, L: PB * S[L.ST_CUM_ANNIH_IN],                       # read
         "annih_write": lambda S, L: PB * (S[L.ST_CUM_ANNIH_IN] + S[L.ST_CUM_KEPT]
                                           + S[L.ST_CUM_REGEN]),                      # read, write kept + placed
     }

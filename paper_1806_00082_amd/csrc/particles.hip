@@ -51,7 +51,8 @@ constexpr int PIECE = 2048;
 // Workspace (sp_workspace_size): int64 scalars[16] | int64 bcnt[PB] | int64 wcnt[NW] |
 // int64 bpart[PB] | int64 bmixed[PB] | int64 kpre[PB] | int64 bpre[PB] | int64 bitem[PB] |
 // int64 ipre[PB] | int32 wstart[PLACE_WAVES] | int32 csum[n_chunks] | uint8 occ[n_cells] |
-// uint8 occx[n_cells] | uint2 ctab[n_cells] (8-byte aligned).
+// uint8 occx[n_cells] | uint2 ctab[n_cells] (8-byte aligned) | uint32 mixbits[8 n_chunks]
+// (16-byte aligned).
 enum { SC_GO = 0, SC_PLACED = 1, SC_KEPT = 2, SC_ITEMS = 3 };
 
 struct WS {
@@ -68,6 +69,7 @@ struct WS {
     int* csum;          // per bin chunk: particles to place
     uint8_t* occ;
     uint2* ctab;        // meshes above CT_MAX cells: (n0, thr) per cell, gathered each step
+    uint32_t* mixbits;  // one bit per bin: set when the bin holds both signs (annih_bins)
 };
 
 static long n_chunks_for(long n_bins) { return (n_bins + BC - 1) / BC; }
@@ -89,6 +91,8 @@ static WS carve(void* ws, long n_bins, long n_cells) {
     w.occ = reinterpret_cast<uint8_t*>(w.csum + (n_chunks_for(n_bins) + 1) / 2 * 2);
     const uintptr_t e = reinterpret_cast<uintptr_t>(w.occ) + 2 * (size_t)n_cells;
     w.ctab = reinterpret_cast<uint2*>((e + 7) & ~(uintptr_t)7);
+    const uintptr_t f = reinterpret_cast<uintptr_t>(w.ctab) + sizeof(uint2) * (n_cells > CT_MAX ? (size_t)n_cells : 0);
+    w.mixbits = reinterpret_cast<uint32_t*>((f + 15) & ~(uintptr_t)15);
     return w;
 }
 
@@ -96,7 +100,8 @@ static size_t ws_bytes_for(long n_bins, long n_cells) {
     return sizeof(long long) * (16 + 7 * (size_t)PB + (size_t)NW) +
            sizeof(int) * (size_t)(PLACE_WAVES + (n_chunks_for(n_bins) + 1) / 2 * 2) +
            2 * (size_t)n_cells +  // occupancy byte per cell, then its dilation along x
-           8 + sizeof(uint2) * (n_cells > CT_MAX ? (size_t)n_cells : 0);  // aligned ctab
+           8 + sizeof(uint2) * (n_cells > CT_MAX ? (size_t)n_cells : 0) +  // aligned ctab
+           16 + sizeof(uint32_t) * 8 * (size_t)n_chunks_for(n_bins);       // aligned mixbits
 }
 
 constexpr int IT = 4;          // particles per lane in the streaming passes
@@ -878,34 +883,27 @@ struct BinCount {
     }
 };
 
-// The histogram bins a workgroup's particles fall in, copied to LDS (W bins per sign from a
-// quarter window below the smallest bin of its waves' first tiles); the survivor test reads
-// there and falls back to global memory outside the window.
-constexpr int KW = 2048;
+// The mixed-bin bits of the bins a workgroup's particles fall in, copied to LDS (KWW words of
+// 32 bins from a quarter window below the smallest bin of its waves' first tiles); the
+// survivor test reads there and falls back to the global bitmap outside the window.
+constexpr int KWW = 2048;
 
 struct KeepWindow {
-    const int* lw;  // [2][KW] in LDS
-    long base;
-    const int32_t* hist;
-    long n_bins;
+    const uint32_t* lw;  // [KWW] in LDS
+    long base;           // first word of the window
+    const uint32_t* bits;
 
     __device__ __forceinline__ bool keeps(long b) const {
         if (b < 0) return false;
-        const int k = (int)b - (int)base;  // bins and base are below 2^31
-        int hp, hm;
-        if ((unsigned)k < (unsigned)KW) {
-            hp = lw[k];
-            hm = lw[KW + k];
-        } else {
-            hp = hist[b];
-            hm = hist[n_bins + b];
-        }
-        return !(hp > 0 && hm > 0);
+        const long wd = b >> 5;
+        const int k = (int)(wd - base);  // words are below 2^26
+        const uint32_t word = (unsigned)k < (unsigned)KWW ? lw[k] : bits[wd];
+        return ((word >> (b & 31)) & 1u) == 0u;
     }
 };
 
-__device__ KeepWindow keep_window(long b_min_thread, int* lw, long* wminw, const int32_t* hist,
-                                  long n_bins) {
+__device__ KeepWindow keep_window(long b_min_thread, uint32_t* lw, long* wminw, const uint32_t* bits,
+                                  long n_words) {
     long b0 = b_min_thread;
     for (int o = 32; o > 0; o >>= 1) b0 = min(b0, (long)__shfl_xor(b0, o, 64));
     if ((threadIdx.x & 63) == 0) wminw[threadIdx.x >> 6] = b0;
@@ -913,14 +911,13 @@ __device__ KeepWindow keep_window(long b_min_thread, int* lw, long* wminw, const
     long m = wminw[0];
 #pragma unroll
     for (int k = 1; k < WPB; ++k) m = min(m, wminw[k]);
-    const long base = m == LONG_MAX ? 0 : max(0L, m - KW / 4);
-    for (int k = threadIdx.x; k < KW; k += PT) {
-        const long b = base + k;
-        lw[k] = b < n_bins ? hist[b] : 0;
-        lw[KW + k] = b < n_bins ? hist[n_bins + b] : 0;
+    const long base = m == LONG_MAX ? 0 : max(0L, (m >> 5) - KWW / 4);
+    for (int k = threadIdx.x; k < KWW; k += PT) {
+        const long wd = base + k;
+        lw[k] = wd < n_words ? bits[wd] : 0u;
     }
     __syncthreads();
-    return KeepWindow{lw, base, hist, n_bins};
+    return KeepWindow{lw, base, bits};
 }
 
 // ----------------------------------------------------------------------------- annihilation
@@ -959,90 +956,95 @@ __global__ __launch_bounds__(PT) void annih_hist(Geo g, const T* x, const T* y, 
     hw.flush();
 }
 
-// Counting pass of sp_annihilate (mode 1) and sp_init (mode 0).  Workgroups below
-// part_blocks (PB in mode 1, 0 in mode 0) count the survivors of their waves' chunks of
-// `in`; the PB workgroups after them each own g.gpb consecutive chunks of BC bins and store
-// every chunk's output count in csum[], their sum in bpart[] and their mixed bins in
-// bmixed[].
+// Counting pass of sp_annihilate over the particles: each wave counts the survivors (particles
+// of bins holding one sign) of its chunk of `in`, reading the mixed-bin bits annih_bins left.
 template <typename T, typename MT, int DIM>
-__global__ __launch_bounds__(PT) void annih_count(Geo g, int part_blocks, BinCount bc,
-                                                  const T* x, const T* y, const MT* M,
+__global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y, const MT* M,
                                                   const MT* My, const int8_t* s,
                                                   const long long* d_n_in, long long cap_in,
                                                   long long* stats, WS w) {
     __shared__ long long red[PT / 64];
-    __shared__ int lw[2 * KW];
+    __shared__ uint32_t lw[KWW];
     __shared__ long wmin[PT / 64];
     if (stats[WK_ST_OVERFLOW] != 0) return;
-    if (part_blocks > 0) {
-        const long n = (long)*d_n_in;
-        if (n < 0 || n > cap_in) {  // refused: nothing is written
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                stats[WK_ST_NEEDED] = -1;
-                stats[WK_ST_OVERFLOW] = 1;
-            }
-            return;
+    const long n = (long)*d_n_in;
+    if (n < 0 || n > cap_in) {  // refused: nothing is written
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            stats[WK_ST_NEEDED] = -1;
+            stats[WK_ST_OVERFLOW] = 1;
         }
-        if ((int)blockIdx.x < part_blocks) {
-            long lo, hi;
-            wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
-            const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw,
-                                              wmin, bc.hist, g.n_bins);
-            long long a = 0;
-            Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
-            load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
-            for (long t0 = lo; t0 < hi; t0 += WT) {
-                const long id = t0 + IT * (threadIdx.x & 63);
-                Part4<T, DIM> p = nxt;
-                load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
-#pragma unroll
-                for (int k = 0; k < IT; ++k)
-                    a += kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k])) ? 1 : 0;
-            }
-            store_counts(w, wave_sum_ll(a), red);
-            return;
-        }
+        return;
     }
-    const long c = (long)blockIdx.x - part_blocks;
-    const long j0 = min(g.n_chunks, c * g.gpb), j1 = min(g.n_chunks, j0 + g.gpb);
-    long long part = 0, mixed = 0, items = 0;
-    // NB chunks at a time (2-D, where a bin workgroup walks 128 chunks): the loads of the NB
-    // chunks are in flight together and one barrier serves their sums
-    constexpr int NB = DIM == 2 ? 4 : 1;
-    __shared__ long long bsum[NB][PT / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (long j = j0; j < j1; j += NB) {  // uniform
-        long long v[NB];
+    long lo, hi;
+    wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
+    const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin,
+                                      w.mixbits, 8 * g.n_chunks);
+    long long a = 0;
+    Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
+    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
+    for (long t0 = lo; t0 < hi; t0 += WT) {
+        const long id = t0 + IT * (threadIdx.x & 63);
+        Part4<T, DIM> p = nxt;
+        load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const long b = (j + i) * BC + threadIdx.x;
-            v[i] = 0;
-            if (j + i < j1 && b < g.n_bins) {
-                v[i] = bc(b);
-                mixed += bc.mixed(b) ? 1 : 0;
+        for (int k = 0; k < IT; ++k)
+            a += kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k])) ? 1 : 0;
+    }
+    store_counts(w, wave_sum_ll(a), red);
+}
+
+// Counting pass over the bins of sp_annihilate (histogram) and sp_init (per-bin counts): bin
+// workgroup c owns g.gpb consecutive chunks of BC bins and its waves take every WPB-th chunk.
+// Per chunk (lane l holds bins 4l .. 4l+3): the particles to place (csum), their placement
+// work items, and, from the histogram, one bit per bin that holds both signs (mixbits, eight
+// words per chunk).  Per bin workgroup: the particles to place (bpart), its mixed bins
+// (bmixed) and work items (bitem).
+__global__ __launch_bounds__(PT) void annih_bins(Geo g, BinCount bc, const long long* stats, WS w) {
+    __shared__ long long red[PT / 64];
+    if (stats[WK_ST_OVERFLOW] != 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long c = blockIdx.x;
+    const long j0 = min(g.n_chunks, c * g.gpb), j1 = min(g.n_chunks, j0 + g.gpb);
+    const bool vec = bc.counts == nullptr && (bc.n_bins & 3) == 0;  // 16-byte aligned rows
+    long long part = 0, mixed = 0, items = 0;
+    for (long j = j0 + wv; j < j1; j += WPB) {  // per wave, no workgroup barriers
+        const long b0 = j * BC + 4 * lane;
+        int cnt[4];
+        uint32_t mb = 0;
+        if (vec && b0 + 3 < bc.n_bins) {
+            const int4 hp = *reinterpret_cast<const int4*>(bc.hist + b0);
+            const int4 hm = *reinterpret_cast<const int4*>(bc.hist + bc.n_bins + b0);
+            const int a[4] = {hp.x, hp.y, hp.z, hp.w}, m[4] = {hm.x, hm.y, hm.z, hm.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool mx = a[k] > 0 && m[k] > 0;
+                cnt[k] = mx ? (a[k] > m[k] ? a[k] - m[k] : m[k] - a[k]) : 0;
+                mb |= mx ? 1u << k : 0u;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const long b = b0 + k;
+                cnt[k] = b < g.n_bins ? (int)bc(b) : 0;
+                mb |= (b < g.n_bins && bc.mixed(b)) ? 1u << k : 0u;
             }
         }
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const long long sv = wave_sum_ll(v[i]);
-            if (lane == 0) bsum[i][wv] = sv;
-        }
-        __syncthreads();
-        if (threadIdx.x < NB && j + threadIdx.x < j1) {
-            long long t = 0;
-#pragma unroll
-            for (int k = 0; k < PT / 64; ++k) t += bsum[threadIdx.x][k];
-            w.csum[j + threadIdx.x] = (int)t;  // < 2^31 whenever the capacity check passes
+        const long long t = wave_sum_ll((long long)cnt[0] + cnt[1] + cnt[2] + cnt[3]);
+        mixed += __popc(mb);
+        if (lane == 0) {
+            w.csum[j] = (int)t;  // < 2^31 whenever the capacity check passes
+            part += t;
             items += (t + PIECE - 1) / PIECE;
         }
-        if (threadIdx.x == 0) {
+        if (bc.counts == nullptr) {
+            // word q of the chunk (bins 32q .. 32q+31) collects the 4-bit groups of lanes 8q .. 8q+7
+            uint32_t word = 0;
 #pragma unroll
-            for (int i = 0; i < NB; ++i)
-#pragma unroll
-                for (int k = 0; k < PT / 64; ++k) part += bsum[i][k];
+            for (int i = 0; i < 8; ++i) word |= (uint32_t)__shfl((int)mb, 8 * (lane & 7) + i, 64) << (4 * i);
+            if (lane < 8) w.mixbits[j * 8 + lane] = word;
         }
-        __syncthreads();  // bsum is rewritten by the next chunks
     }
+    part = block_sum_ll(part, red);
     mixed = block_sum_ll(mixed, red);
     items = block_sum_ll(items, red);
     if (threadIdx.x == 0) {
@@ -1262,13 +1264,13 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
                                                   MT* Myo, int8_t* so, long long capacity,
                                                   WS w) {
     constexpr int STAGE = WT * (DIM * (int)sizeof(T) + DIM * (int)sizeof(int) + 1);  // per wave
-    constexpr int KEEP_LDS = WPB * STAGE + 2 * KW * (int)sizeof(int);
+    constexpr int KEEP_LDS = WPB * STAGE + KWW * (int)sizeof(uint32_t);
     constexpr int PLACE_LDS = WPB * PW_LDS * (int)sizeof(int);
     __shared__ int ldsw[WPB];
     __shared__ long wmin[PT / 64];
     // keepers: one stage per wave + histogram window; placers: chunk and bin prefix tables
     __shared__ __align__(16) char smem[KEEP_LDS > PLACE_LDS ? KEEP_LDS : PLACE_LDS];
-    int* lw = reinterpret_cast<int*>(smem + WPB * STAGE);
+    uint32_t* lw = reinterpret_cast<uint32_t*>(smem + WPB * STAGE);
     if (w.sc[SC_GO] == 0) return;
     const long long placed = w.sc[SC_PLACED];
     if ((int)blockIdx.x < part_blocks) {
@@ -1283,7 +1285,7 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
         long lo, hi;
         wave_chunk((long)*d_n_in, (long)blockIdx.x * WPB + wv, &lo, &hi);
         const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw,
-                                          wmin, bc.hist, g.n_bins);
+                                          wmin, w.mixbits, 8 * g.n_chunks);
         long long run = placed + w.kpre[blockIdx.x];
         for (int j = 0; j < wv; ++j) run += w.wcnt[(long)blockIdx.x * WPB + j];
         Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
@@ -1560,8 +1562,9 @@ static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp
     }
     const BinCount bc{nullptr, hist, g.n_bins};
     long long* d_n_out = reinterpret_cast<long long*>(out->d_n);
-    WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(2 * PB), dim3(PT), 0, s, g, PB, bc, x, y,
-              M, My, in->s, d_n, cap_in, stats, w);
+    WK_LAUNCH("annih_bins", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, stats, w);
+    WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
+              d_n, cap_in, stats, w);
     WK_LAUNCH("annih_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 1, PLACE_BLOCKS, d_n,
               d_n_out, (long long)out->capacity, stats, w);
     WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(PB + PLACE_BLOCKS), dim3(PT), 0, s, g,
@@ -1574,9 +1577,7 @@ template <typename T, typename MT, int DIM>
 static void launch_init(const Geo& g, const int32_t* counts, sp_particles* out, long long* stats,
                         WS w, hipStream_t s) {
     const BinCount bc{counts, nullptr, g.n_bins};
-    WK_LAUNCH("init_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, 0, bc,
-              (const T*)nullptr, (const T*)nullptr, (const MT*)nullptr, (const MT*)nullptr,
-              (const int8_t*)nullptr, (const long long*)nullptr, 0LL, stats, w);
+    WK_LAUNCH("init_count", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, stats, w);
     WK_LAUNCH("init_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 0, PLACE_BLOCKS,
               (const long long*)nullptr, reinterpret_cast<long long*>(out->d_n),
               (long long)out->capacity, stats, w);
