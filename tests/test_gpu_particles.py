@@ -287,3 +287,122 @@ def test_empty_ensemble(orc):
     a.d_n.fill_(5)
     ops.sp_annihilate(md, 0, b, a, hist, 0, st, ws, hist_ready=True)
     assert a.count() == 0 and to_np(st)[L.ST_N] == 0 and to_np(hist).sum() == 0
+
+
+def _c5_tables(orc, cfg, occupied, steps):
+    import oracle_rows
+    md = cfg.mesh.as_dict(cfg.dt)
+    pad = int(np.ceil(steps * abs(md["vdt"]) * max(abs(md["M_min"]), md["M_min"] + md["n_k"]))) + 1
+    cells = oracle_rows.reachable_cells(occupied, pad)
+    K = oracle_rows.kernel_2d_rows(cfg.V, md["n_m"], HB, cells)
+    _, n0, thr, cdf = orc.gamma_tables(K, cfg.dt)
+    slot = np.full(md["nx"] * md["ny"], -1, np.int32)
+    slot[cells] = np.arange(len(cells), dtype=np.int32)
+    return md, (n0, thr, cdf), slot
+
+
+def _max_keys_per_workgroup(hp_view, md, n_wg=2048, waves=4):
+    """Largest number of distinct (bin, sign) keys among the particles of one workgroup of the
+    step's ordered passes (its waves' contiguous chunks), from the oracle's arrays."""
+    n = len(hp_view["s"])
+    nw = n_wg * waves
+    cs = -(-n // nw)
+    cs = -(-cs // 256) * 256
+    nk, nx = md["n_k"], md["nx"]
+    x = hp_view["x"].astype(np.int64)
+    y = hp_view["y"].astype(np.int64)
+    b = (((y * nx + x) * nk + (hp_view["My"].astype(np.int64) - md["M_min"])) * nk
+         + (hp_view["M"].astype(np.int64) - md["M_min"]))
+    key = 2 * b + (hp_view["s"] > 0)
+    best = 0
+    for wg in range(0, n_wg, 97):  # a sample of the workgroups
+        lo, hi = wg * waves * cs, min(n, (wg + 1) * waves * cs)
+        if lo < hi:
+            best = max(best, len(np.unique(key[lo:hi][hp_view["s"][lo:hi] != 0])))
+    return best
+
+
+def _c5_compare(orc, md, tables, slot, hp, seed, steps, first_step, label):
+    cap = hp.capacity
+    a = ops.DeviceParticles(2, cap, False)
+    v = hp.view()
+    a.load(hp.n, v["x"], v["M"], v["s"], y=v["y"], My=v["My"])
+    b = ops.DeviceParticles(2, cap, False)
+    st = ops.new_stats()
+    ws = ops.sp_workspace(md, seed)
+    hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev())
+    n0, thr, cdf = host_tables_to_device((None,) + tuple(tables))
+    slot_d = torch.from_numpy(slot).to(dev())
+    guide = ops.sampling_guide(cdf, 256)
+    nb = ops.n_bins(md)
+    max_keys = 0
+    for s in range(first_step, first_step + steps):
+        fused = s % 2 == 1
+        print(f"{label}: step {s} ({hp.n} particles, histogram from sp_step: {fused})", flush=True)
+        hp, hst = orc.sp_step(md, hp, tables, slot, step=s, seed=seed)
+        ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, b, s, st, ws, hist=hist if fused else None,
+                    guide=guide if s % 2 == 0 else None)
+        gst = to_np(st)
+        assert gst[L.ST_OVERFLOW] == 0
+        for k in (L.ST_N, L.ST_PAIRS, L.ST_ABS_X, L.ST_ABS_M):
+            assert gst[k] == hst[k], (label, s, k, gst[k], hst[k])
+        hv = hp.view()
+        assert_particles_equal(b.view(), hv, f"{label} sp_step {s}")
+        keys = _max_keys_per_workgroup(hv, md)
+        hp, hh_p, hh_m, hst = orc.sp_annihilate(md, hp, step=s, seed=seed, capacity=cap)
+        if fused:
+            h = to_np(hist)
+            assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"{label} step hist {s}"
+        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=fused)
+        gst = to_np(st)
+        for k in (L.ST_N, L.ST_KEPT, L.ST_REGEN, L.ST_MIXED):
+            assert gst[k] == hst[k], (label, s, k, gst[k], hst[k])
+        assert_particles_equal(a.view(), hp.view(), f"{label} sp_annihilate {s}")
+        h = to_np(hist)
+        assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"{label} hist {s}"
+        print(f"{label}: step {s} bit-exact; pairs {gst[L.ST_PAIRS]}, "
+              f"regenerated {gst[L.ST_REGEN]}, mixed bins {gst[L.ST_MIXED]}, "
+              f"max (bin, sign) keys per workgroup {keys}", flush=True)
+        max_keys = max(max_keys, keys)
+    # some step's histogram had a workgroup with more (bin, sign) keys than the 2048 of its LDS
+    # hash table: those went to the global atomics (the overflow path)
+    assert max_keys > 2048
+    return hp
+
+
+def test_c5_full_size_steps(orc):
+    """The 2-D workload at its full size (256 x 256 cells, 32 x 32 momenta, 5e7 particles):
+    two steps from the initial state, bit-exact, every array, both histogram paths (built by
+    sp_annihilate, then by sp_step), the 67M-bin histogram compared whole.  The oracle's kernel
+    rows are its direct d = 2 sum on every cell the particles can reach."""
+    cfg = inputs.config_c5()
+    md = cfg.mesh.as_dict(cfg.dt)
+    occ = cfg.bin_counts.reshape(md["ny"], md["nx"], -1).sum(-1) > 0
+    md, tables, slot = _c5_tables(orc, cfg, occ, steps=2)
+    n = int(cfg.bin_counts.sum())
+    hp = orc.sp_init(md, cfg.bin_counts, int(1.3 * n), seed=cfg.seed)
+    _c5_compare(orc, md, tables, slot, hp, cfg.seed, steps=2, first_step=0, label="c5 init")
+
+
+def test_c5_full_size_mixed_ensemble(orc):
+    """The same mesh with the heavy annihilation of the late run: two overlapping packets of
+    opposite sign (5e7 particles each, the second 4 nm further along x), so that most occupied
+    bins hold both signs and tens of millions of particles are regenerated per step; two
+    steps, bit-exact."""
+    cfg = inputs.config_c5()
+    md = cfg.mesh.as_dict(cfg.dt)
+    k0 = cfg.meta["k0"]
+    bc2 = inputs.packet_bin_counts_2d(cfg.mesh, 5e7, 36.0, 64.0, 8.0, k0, 0.0)
+    occ = (cfg.bin_counts + bc2).reshape(md["ny"], md["nx"], -1).sum(-1) > 0
+    md, tables, slot = _c5_tables(orc, cfg, occ, steps=2)
+    n1, n2 = int(cfg.bin_counts.sum()), int(bc2.sum())
+    cap = int(1.3 * (n1 + n2))
+    hp = orc.sp_init(md, cfg.bin_counts, cap, seed=cfg.seed)
+    hm = orc.sp_init(md, bc2, n2, seed=cfg.seed + 1)
+    for f in ("x", "y", "M", "My"):
+        getattr(hp, f)[n1:n1 + n2] = getattr(hm, f)[:n2]
+    hp.s[n1:n1 + n2] = -1
+    hp.n = n1 + n2
+    del hm
+    out = _c5_compare(orc, md, tables, slot, hp, cfg.seed, steps=2, first_step=4, label="c5 mixed")
+    assert out.n < n1 + n2  # annihilation removed particles
