@@ -16,6 +16,8 @@ Parity status (see the tests for each pin):
   gamma_tables ................... pinned (positive-part sum, sampling law)
   philox4x32_10 .................. pinned (published known-answer vectors)
   sp_init / sp_step / sp_annihilate pinned (hand-traced cases, invariants, free drift)
+  sp_annihilate_pairs ............ pinned (explicit pair matching by brute force,
+                                   net sign per bin, survivors an exact subsequence)
   surrogate_fwd .................. pinned (N=1 equals eq.(4); N=2 equals the
                                    barycentric form of Sec. 2.3)
   surrogate_bwd .................. pinned (finite differences in high precision)
@@ -78,6 +80,9 @@ def lib() -> ctypes.CDLL:
         L.oracle_sp_annihilate.argtypes = [i32, i32, i32, i32, i32, i32, u64, i64, i64,
                                            P, P, P, P, P, P, P, P, P, P, i64, P, P, P]
         L.oracle_sp_annihilate.restype = i64
+        L.oracle_sp_annihilate_pairs.argtypes = [i32, i32, i32, i32, i32, i32, i64,
+                                                 P, P, P, P, P, P, P, P, P, P, i64, P, P, P]
+        L.oracle_sp_annihilate_pairs.restype = i64
         L.oracle_surrogate_fwd.argtypes = [i32, i32, i32, P, P, P, P, i32, P, i32, P]
         L.oracle_surrogate_fwd.restype = i32
         L.oracle_surrogate_bwd.argtypes = [i32, i32, i32, P, P, P, P, i32, P, i32, P, P, P, P, P]
@@ -271,6 +276,24 @@ def sp_annihilate(mesh: dict, p: Particles, step: int, seed: int, capacity=None)
                                    int(p.pos_f64), seed, step, p.n, x, y, M, My, s,
                                    xo, yo, Mo, Myo, so, q.capacity, _p(hp), _p(hm), _p(stats))
     q.n = _check(n, "sp_annihilate")
+    return q, hp, hm, stats
+
+
+def sp_annihilate_pairs(mesh: dict, p: Particles, capacity=None):
+    """Rule 2 as literal pair removal (k-th positive meets k-th negative of a bin, input
+    order); returns (kept particles, H+, H-, stats)."""
+    dim = p.dim
+    q = Particles(dim, capacity or max(p.capacity, 1), p.pos_f64)
+    n_bins = mesh["nx"] * mesh.get("ny", 1) * mesh["n_k"] ** dim
+    hp = np.zeros(n_bins, np.int32)
+    hm = np.zeros(n_bins, np.int32)
+    stats = np.zeros(8, np.int64)
+    x, y, M, My, s = p.ptrs()
+    xo, yo, Mo, Myo, so = q.ptrs()
+    n = lib().oracle_sp_annihilate_pairs(dim, mesh["nx"], mesh.get("ny", 1), mesh["n_k"], mesh["M_min"],
+                                         int(p.pos_f64), p.n, x, y, M, My, s, xo, yo, Mo, Myo, so,
+                                         q.capacity, _p(hp), _p(hm), _p(stats))
+    q.n = _check(n, "sp_annihilate_pairs")
     return q, hp, hm, stats
 
 

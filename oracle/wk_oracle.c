@@ -690,3 +690,68 @@ double oracle_sgd_step(int nx, int n_m, int N, double hbar, const double* V, int
     free(gW);
     return loss;
 }
+
+/* ---------------------------------------------------------------- rule 2, pair removal */
+/* Rule 2 of Sec. 2.1 read literally: particles of opposite sign in the same (cell, momentum)
+ * bin annihilate in pairs.  Within a bin the k-th positive particle in input order meets
+ * the k-th negative one, k < min(H+, H-); those pairs are removed and every other live
+ * particle is kept unchanged (its exact position), in input order.  Returns the number kept,
+ * or -2 if capacity is too small; the histogram (H+, H-) of the input is left in
+ * hist_plus / hist_minus when they are given. */
+int64_t oracle_sp_annihilate_pairs(int dim, int nx, int ny, int n_k, int M_min, int pos_f64,
+                                   int64_t n, const void* x, const void* y, const void* M,
+                                   const void* My, const int8_t* s, void* xo, void* yo,
+                                   void* Mo, void* Myo, int8_t* so, int64_t capacity,
+                                   int32_t* hist_plus, int32_t* hist_minus, int64_t* stats) {
+    if ((dim != 1 && dim != 2) || nx <= 0 || n_k <= 0 || n < 0) return -1;
+    if (dim == 1) ny = 1;
+    pgeom g = {dim, nx, ny, n_k, M_min, pos_f64};
+    const long n_bins = (long)nx * ny * n_k * (dim == 2 ? n_k : 1);
+    int32_t* hp = hist_plus ? hist_plus : (int32_t*)malloc(sizeof(int32_t) * n_bins);
+    int32_t* hm = hist_minus ? hist_minus : (int32_t*)malloc(sizeof(int32_t) * n_bins);
+    int32_t* seen_p = (int32_t*)calloc((size_t)n_bins, sizeof(int32_t));
+    int32_t* seen_m = (int32_t*)calloc((size_t)n_bins, sizeof(int32_t));
+    memset(hp, 0, sizeof(int32_t) * n_bins);
+    memset(hm, 0, sizeof(int32_t) * n_bins);
+    for (int k = 0; k < 8; ++k) stats[k] = 0;
+    for (int64_t id = 0; id < n; ++id) {
+        const long b = bin_of(&g, id, x, y, M, My, s);
+        if (b < 0) continue;
+        if (s[id] > 0)
+            hp[b]++;
+        else
+            hm[b]++;
+    }
+    int64_t mixed = 0;
+    for (long b = 0; b < n_bins; ++b)
+        if (hp[b] > 0 && hm[b] > 0) ++mixed;
+    int64_t o = 0, rc = 0;
+    for (int64_t id = 0; id < n; ++id) {
+        const long b = bin_of(&g, id, x, y, M, My, s);
+        if (b < 0) continue;
+        const int32_t pairs = hp[b] < hm[b] ? hp[b] : hm[b];
+        const int32_t rank = s[id] > 0 ? seen_p[b]++ : seen_m[b]++;
+        if (rank < pairs) continue; /* annihilated with its partner of the other sign */
+        if (o >= capacity) {
+            rc = -2;
+            break;
+        }
+        set_pos(xo, pos_f64, o, get_pos(x, pos_f64, id));
+        set_mom(Mo, dim, o, get_mom(M, dim, id));
+        if (dim == 2) {
+            set_pos(yo, pos_f64, o, get_pos(y, pos_f64, id));
+            set_mom(Myo, dim, o, get_mom(My, dim, id));
+        }
+        so[o++] = s[id];
+    }
+    free(seen_p);
+    free(seen_m);
+    if (!hist_plus) free(hp);
+    if (!hist_minus) free(hm);
+    if (rc) return rc;
+    stats[ORACLE_ST_N] = o;
+    stats[ORACLE_ST_ANNIH_KEPT] = o;
+    stats[ORACLE_ST_ANNIH_REGEN] = 0;
+    stats[ORACLE_ST_MIXED] = mixed;
+    return o;
+}

@@ -71,6 +71,15 @@ int64_t oracle_sp_annihilate(int dim, int nx, int ny, int n_k, int M_min, int po
                              int8_t* so, int64_t capacity, int32_t* hist_plus,
                              int32_t* hist_minus, int64_t* stats);
 
+/* Rule 2 as pair removal: in each bin the k-th positive and k-th negative particle (input
+ * order) annihilate for k < min(H+, H-); the other live particles are kept unchanged, in
+ * input order (no regeneration, exact positions). */
+int64_t oracle_sp_annihilate_pairs(int dim, int nx, int ny, int n_k, int M_min, int pos_f64,
+                                   int64_t n, const void* x, const void* y, const void* M,
+                                   const void* My, const int8_t* s, void* xo, void* yo,
+                                   void* Mo, void* Myo, int8_t* so, int64_t capacity,
+                                   int32_t* hist_plus, int32_t* hist_minus, int64_t* stats);
+
 /* eq.(5) with N-term groups; half table m = 1..P.  wV, wT: [N]; W: [n_m/N]. */
 int oracle_surrogate_fwd(int nx, int n_m, int N, const double* wV, const double* wT,
                          const double* W, const double* V, int B, const int32_t* cells,

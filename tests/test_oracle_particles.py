@@ -284,3 +284,89 @@ def test_free_drift_sheared_gaussian(orc):
     keep = e > 5
     chi = ((obs[keep] - e[keep]) ** 2 / e[keep]).sum()
     assert sst.chi2.sf(chi, keep.sum() - 1) > 1e-3
+
+
+# ----------------------------------------------------------------------------- pair removal
+def _mixed_state(orc, md, n, seed, span_cells=6):
+    """A small signed ensemble crowded into a few cells and momenta (many mixed bins)."""
+    rng = np.random.default_rng(seed)
+    p = orc.Particles(md["dim"], n, md["pos_f64"])
+    p.x[:n] = rng.uniform(0, span_cells, n).astype(p.x.dtype)
+    p.M[:n] = rng.integers(md["M_min"], md["M_min"] + 3, n)
+    if md["dim"] == 2:
+        p.y[:n] = rng.uniform(0, 2, n).astype(p.y.dtype)
+        p.My[:n] = rng.integers(md["M_min"], md["M_min"] + 2, n)
+    p.s[:n] = rng.choice([-1, 1, 1, 0], n)
+    p.n = n
+    return p
+
+
+def _bins(md, v):
+    nk = md["n_k"]
+    cx = np.floor(v["x"]).astype(np.int64)
+    b = cx * nk + (v["M"].astype(np.int64) - md["M_min"])
+    if md["dim"] == 2:
+        cy = np.floor(v["y"]).astype(np.int64)
+        b = ((cy * md["nx"] + cx) * nk + (v["My"].astype(np.int64) - md["M_min"])) * nk + \
+            (v["M"].astype(np.int64) - md["M_min"])
+    return b
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_pair_removal_matches_fifo_matching(orc, dim):
+    """Brute force by a different procedure: walk the particles in input order keeping, per bin,
+    a queue of unmatched particles of each sign; a particle meeting a non-empty queue of the
+    other sign annihilates with its oldest member.  The survivors, in input order, must be
+    exactly the oracle's output."""
+    if dim == 1:
+        md = {"dim": 1, "nx": 8, "ny": 1, "n_m": 8, "n_k": 16, "M_min": -8, "pos_f64": True}
+    else:
+        md = {"dim": 2, "nx": 8, "ny": 3, "n_m": 8, "n_k": 8, "M_min": -4, "pos_f64": False}
+    for seed in range(4):
+        p = _mixed_state(orc, md, 300, seed)
+        v = p.view()
+        b = _bins(md, v)
+        queues, removed = {}, set()
+        for i in range(p.n):
+            if v["s"][i] == 0:
+                continue
+            q = queues.setdefault(int(b[i]), {1: [], -1: []})
+            other = q[-int(v["s"][i])]
+            if other:
+                removed.add(other.pop(0))
+                removed.add(i)
+            else:
+                q[int(v["s"][i])].append(i)
+        keep = [i for i in range(p.n) if v["s"][i] != 0 and i not in removed]
+        out, hp, hm, st = orc.sp_annihilate_pairs(md, p)
+        o = out.view()
+        assert out.n == len(keep) and st[orc.ST_N] == len(keep) and st[orc.ST_REGEN] == 0
+        for f in v:
+            assert np.array_equal(o[f], v[f][keep]), (seed, f)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_pair_removal_invariants_and_regeneration_histogram(orc, dim):
+    """Net sign per bin conserved, no mixed bin left, survivors unchanged; and the output
+    histogram equals that of the regenerating reading of rule 2 (both leave |H+ - H-|
+    particles of the net sign in a mixed bin and single-sign bins untouched)."""
+    if dim == 1:
+        md = {"dim": 1, "nx": 30, "ny": 1, "n_m": 8, "n_k": 16, "M_min": -8, "pos_f64": False, "vdt": 0.1}
+    else:
+        md = {"dim": 2, "nx": 10, "ny": 4, "n_m": 8, "n_k": 8, "M_min": -4, "pos_f64": False, "vdt": 0.1}
+    p = _mixed_state(orc, md, 5000, 11, span_cells=10)
+    out, hp, hm, st = orc.sp_annihilate_pairs(md, p)
+    assert st[orc.ST_MIXED] > 0
+    o = out.view()
+    n_bins = len(hp)
+    ob = _bins(md, o)
+    op = np.bincount(ob[o["s"] > 0], minlength=n_bins)
+    om = np.bincount(ob[o["s"] < 0], minlength=n_bins)
+    assert np.array_equal(op - om, hp.astype(np.int64) - hm)
+    assert not np.any((op > 0) & (om > 0))
+    reg, rp, rm, rst = orc.sp_annihilate(md, p, step=3, seed=5)
+    rv = reg.view()
+    rb = _bins(md, rv)
+    assert np.array_equal(np.bincount(rb[rv["s"] > 0], minlength=n_bins), op)
+    assert np.array_equal(np.bincount(rb[rv["s"] < 0], minlength=n_bins), om)
+    assert np.array_equal(rp, hp) and np.array_equal(rm, hm) and rst[orc.ST_MIXED] == st[orc.ST_MIXED]
