@@ -278,6 +278,23 @@ int sp_annihilate(const sp_geom* g, const sp_particles* in, sp_particles* out, i
                   int32_t hist_ready, int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes,
                   void* stream);
 
+/* sp_annihilate_pairs -- rule 2 of Sec. 2.1 read literally, as pair removal: in each
+ * (cell, momentum) bin the k-th positive and the k-th negative particle in input order
+ * annihilate, for k < min(H+, H-); every other live particle of `in` is kept unchanged (its
+ * exact position and momentum), in input order.  No random numbers; net sign per bin is
+ * conserved and no bin holds both signs afterwards.  The output histogram equals that of
+ * sp_annihilate (which regenerates |H+ - H-| particles of a mixed bin instead).
+ *   hist, hist_ready, ws, d_stats as sp_annihilate (WK_ST_REGEN = 0; WK_ST_KEPT = output
+ *   count); out->capacity >= the input count always suffices.
+ *   scratch  caller buffer of sp_pairs_scratch_size(g, in->capacity) bytes (the list of the
+ *            particles of mixed bins and its radix-sort buffers, ~17 B per particle slot).
+ * Requires 2 * n_bins < 2^32 (WK_EINVAL otherwise).  Calls sharing a workspace or scratch
+ * must not overlap. */
+size_t sp_pairs_scratch_size(const sp_geom* g, int64_t n_max);
+int sp_annihilate_pairs(const sp_geom* g, const sp_particles* in, sp_particles* out, int32_t* hist,
+                        int32_t hist_ready, int64_t* d_stats, void* ws, size_t ws_bytes,
+                        void* scratch, size_t scratch_bytes, void* stream);
+
 /* sp_density -- rule 1 read-out: rho[c] = sum_M (H+ - H-) / N0 (double [nx*ny]) from the
  * histogram sp_annihilate left in `hist`. */
 int sp_density(const sp_geom* g, const int32_t* hist, double N0, double* rho, void* stream);

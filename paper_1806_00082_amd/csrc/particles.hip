@@ -892,18 +892,30 @@ struct KeepWindow {
     const uint32_t* lw;  // [KWW] in LDS
     long base;           // first word of the window
     const uint32_t* bits;
+    const uint8_t* flags;  // pair removal: per input particle, 1 = not annihilated (else NULL)
 
-    __device__ __forceinline__ bool keeps(long b) const {
+    // Particle `id` in bin b survives rule 2: its bin holds one sign, or (pair removal) it
+    // has no partner of the other sign.
+    __device__ __forceinline__ bool keeps(long b, long id) const {
         if (b < 0) return false;
         const long wd = b >> 5;
         const int k = (int)(wd - base);  // words are below 2^26
         const uint32_t word = (unsigned)k < (unsigned)KWW ? lw[k] : bits[wd];
-        return ((word >> (b & 31)) & 1u) == 0u;
+        if (((word >> (b & 31)) & 1u) == 0u) return true;
+        return flags != nullptr && flags[id] != 0;
+    }
+    // the bin holds both signs
+    __device__ __forceinline__ bool mixed(long b) const {
+        if (b < 0) return false;
+        const long wd = b >> 5;
+        const int k = (int)(wd - base);
+        const uint32_t word = (unsigned)k < (unsigned)KWW ? lw[k] : bits[wd];
+        return ((word >> (b & 31)) & 1u) != 0u;
     }
 };
 
 __device__ KeepWindow keep_window(long b_min_thread, uint32_t* lw, long* wminw, const uint32_t* bits,
-                                  long n_words) {
+                                  long n_words, const uint8_t* flags) {
     long b0 = b_min_thread;
     for (int o = 32; o > 0; o >>= 1) b0 = min(b0, (long)__shfl_xor(b0, o, 64));
     if ((threadIdx.x & 63) == 0) wminw[threadIdx.x >> 6] = b0;
@@ -917,7 +929,7 @@ __device__ KeepWindow keep_window(long b_min_thread, uint32_t* lw, long* wminw, 
         lw[k] = wd < n_words ? bits[wd] : 0u;
     }
     __syncthreads();
-    return KeepWindow{lw, base, bits};
+    return KeepWindow{lw, base, bits, flags};
 }
 
 // ----------------------------------------------------------------------------- annihilation
@@ -962,7 +974,7 @@ template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y, const MT* M,
                                                   const MT* My, const int8_t* s,
                                                   const long long* d_n_in, long long cap_in,
-                                                  long long* stats, WS w) {
+                                                  const uint8_t* flags, long long* stats, WS w) {
     __shared__ long long red[PT / 64];
     __shared__ uint32_t lw[KWW];
     __shared__ long wmin[PT / 64];
@@ -978,7 +990,7 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
     long lo, hi;
     wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
     const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin,
-                                      w.mixbits, 8 * g.n_chunks);
+                                      w.mixbits, 8 * g.n_chunks, flags);
     long long a = 0;
     Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
     load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
@@ -988,7 +1000,7 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
         load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
 #pragma unroll
         for (int k = 0; k < IT; ++k)
-            a += kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k])) ? 1 : 0;
+            a += kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), id + k) ? 1 : 0;
     }
     store_counts(w, wave_sum_ll(a), red);
 }
@@ -998,8 +1010,9 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
 // Per chunk (lane l holds bins 4l .. 4l+3): the particles to place (csum), their placement
 // work items, and, from the histogram, one bit per bin that holds both signs (mixbits, eight
 // words per chunk).  Per bin workgroup: the particles to place (bpart), its mixed bins
-// (bmixed) and work items (bitem).
-__global__ __launch_bounds__(PT) void annih_bins(Geo g, BinCount bc, const long long* stats, WS w) {
+// (bmixed) and work items (bitem).  place = 0 (pair removal): nothing is placed.
+__global__ __launch_bounds__(PT) void annih_bins(Geo g, BinCount bc, int place, const long long* stats,
+                                                 WS w) {
     __shared__ long long red[PT / 64];
     if (stats[WK_ST_OVERFLOW] != 0) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1029,7 +1042,7 @@ __global__ __launch_bounds__(PT) void annih_bins(Geo g, BinCount bc, const long 
                 mb |= (b < g.n_bins && bc.mixed(b)) ? 1u << k : 0u;
             }
         }
-        const long long t = wave_sum_ll((long long)cnt[0] + cnt[1] + cnt[2] + cnt[3]);
+        const long long t = place ? wave_sum_ll((long long)cnt[0] + cnt[1] + cnt[2] + cnt[3]) : 0;
         mixed += __popc(mb);
         if (lane == 0) {
             w.csum[j] = (int)t;  // < 2^31 whenever the capacity check passes
@@ -1262,7 +1275,7 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
                                                   const MT* M, const MT* My, const int8_t* s,
                                                   const long long* d_n_in, T* xo, T* yo, MT* Mo,
                                                   MT* Myo, int8_t* so, long long capacity,
-                                                  WS w) {
+                                                  const uint8_t* flags, WS w) {
     constexpr int STAGE = WT * (DIM * (int)sizeof(T) + DIM * (int)sizeof(int) + 1);  // per wave
     constexpr int KEEP_LDS = WPB * STAGE + KWW * (int)sizeof(uint32_t);
     constexpr int PLACE_LDS = WPB * PW_LDS * (int)sizeof(int);
@@ -1285,7 +1298,7 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
         long lo, hi;
         wave_chunk((long)*d_n_in, (long)blockIdx.x * WPB + wv, &lo, &hi);
         const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw,
-                                          wmin, w.mixbits, 8 * g.n_chunks);
+                                          wmin, w.mixbits, 8 * g.n_chunks, flags);
         long long run = placed + w.kpre[blockIdx.x];
         for (int j = 0; j < wv; ++j) run += w.wcnt[(long)blockIdx.x * WPB + j];
         Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
@@ -1298,7 +1311,7 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
             int kt = 0;
 #pragma unroll
             for (int k = 0; k < IT; ++k) {
-                kp[k] = kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]));
+                kp[k] = kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), id + k);
                 kt += kp[k];
             }
             const int inc = wave_incl_scan(kt);
@@ -1386,6 +1399,326 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
         }
         c = lo;
     }
+}
+
+// ----------------------------------------------------------------------------- pair removal
+// Rule 2 read literally (sp_annihilate_pairs): in each bin the k-th positive and the k-th
+// negative particle (input order) annihilate, k < min(H+, H-).  The particles of mixed bins
+// are listed in input order as (key = 2 bin + [s > 0], index), the list is sorted by key
+// with a stable LSD radix sort (so each (bin, sign) segment keeps input order), a
+// particle's rank is its distance from the start of its segment, and it survives iff its
+// rank is at least min(H+, H-).  The survivors of all bins are then compacted in input
+// order by the passes of sp_annihilate (nothing is placed).
+constexpr int RB = PB;  // workgroups of the radix passes, each owning a contiguous range
+
+// Caller scratch of sp_annihilate_pairs: int64 sc[16] | int64 woff[NW] | uint32 cnt[256 RB] |
+// uint32 off[256 RB] | uint32 keys[2][n_max] | uint32 vals[2][n_max] | uint8 flags[n_max].
+struct PairScratch {
+    long long* sc;     // sc[0]: number of listed particles
+    long long* woff;   // per wave of the listing pass: first list slot
+    uint32_t* cnt;     // radix digit counts [digit][block]
+    uint32_t* off;     // their exclusive prefix (digit-major)
+    uint32_t* keys[2];
+    uint32_t* vals[2];
+    uint8_t* flags;
+};
+
+static size_t pair_scratch_bytes(long n_max) {
+    return sizeof(long long) * (16 + (size_t)NW) + 2 * sizeof(uint32_t) * 256 * (size_t)RB +
+           4 * sizeof(uint32_t) * (size_t)n_max + (size_t)n_max + 64;
+}
+
+static PairScratch pair_carve(void* p, long n_max) {
+    PairScratch q;
+    q.sc = static_cast<long long*>(p);
+    q.woff = q.sc + 16;
+    q.cnt = reinterpret_cast<uint32_t*>(q.woff + NW);
+    q.off = q.cnt + 256 * RB;
+    q.keys[0] = q.off + 256 * RB;
+    q.keys[1] = q.keys[0] + n_max;
+    q.vals[0] = q.keys[1] + n_max;
+    q.vals[1] = q.vals[0] + n_max;
+    q.flags = reinterpret_cast<uint8_t*>(q.vals[1] + n_max);
+    return q;
+}
+
+// Listing, pass 1: per wave, the particles of its chunk whose bin holds both signs.
+template <typename T, typename MT, int DIM>
+__global__ __launch_bounds__(PT) void pair_count(Geo g, const T* x, const T* y, const MT* M,
+                                                 const MT* My, const int8_t* s,
+                                                 const long long* d_n_in, long long cap_in,
+                                                 long long* stats, WS w) {
+    __shared__ long long red[PT / 64];
+    __shared__ uint32_t lw[KWW];
+    __shared__ long wmin[PT / 64];
+    if (stats[WK_ST_OVERFLOW] != 0) return;
+    const long n = (long)*d_n_in;
+    if (n < 0 || n > cap_in) {  // refused: the later passes see the sticky flag and do nothing
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            stats[WK_ST_NEEDED] = -1;
+            stats[WK_ST_OVERFLOW] = 1;
+        }
+        return;
+    }
+    long lo, hi;
+    wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
+    const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin,
+                                      w.mixbits, 8 * g.n_chunks, nullptr);
+    long long a = 0;
+    Part4<T, DIM> nxt;
+    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
+    for (long t0 = lo; t0 < hi; t0 += WT) {
+        const long id = t0 + IT * (threadIdx.x & 63);
+        Part4<T, DIM> p = nxt;
+        load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+#pragma unroll
+        for (int k = 0; k < IT; ++k)
+            a += kw.mixed(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k])) ? 1 : 0;
+    }
+    store_counts(w, wave_sum_ll(a), red);
+}
+
+// Exclusive prefix of the listing pass's NW wave counts (one workgroup); sc[0] = the total.
+__global__ __launch_bounds__(ST_THREADS) void pair_scan(const long long* stats, WS w, PairScratch q) {
+    __shared__ long long part[ST_THREADS / 64 + 1];
+    if (stats[WK_ST_OVERFLOW] != 0) {
+        if (threadIdx.x == 0) q.sc[0] = 0;
+        return;
+    }
+    constexpr int per = NW / ST_THREADS;
+    long long loc[per], acc = 0;
+    for (int k = 0; k < per; ++k) {
+        loc[k] = w.wcnt[threadIdx.x * per + k];
+        acc += loc[k];
+    }
+    const long long inc = wave_incl_scan_ll(acc);
+    if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = inc;
+    __syncthreads();
+    long long run = inc - acc;
+    for (int k = 0; k < (int)(threadIdx.x >> 6); ++k) run += part[k];
+    for (int k = 0; k < per; ++k) {
+        q.woff[threadIdx.x * per + k] = run;
+        run += loc[k];
+    }
+    if (threadIdx.x == ST_THREADS - 1) q.sc[0] = run;
+}
+
+// Listing, pass 2: each wave writes its listed particles, in input order, from its offset.
+template <typename T, typename MT, int DIM>
+__global__ __launch_bounds__(PT) void pair_write(Geo g, const T* x, const T* y, const MT* M,
+                                                 const MT* My, const int8_t* s,
+                                                 const long long* d_n_in, long long cap_in,
+                                                 const long long* stats, WS w, PairScratch q) {
+    __shared__ uint32_t lw[KWW];
+    __shared__ long wmin[PT / 64];
+    if (stats[WK_ST_OVERFLOW] != 0) return;
+    const long n = (long)*d_n_in;
+    if (n < 0 || n > cap_in) return;
+    const int lane = threadIdx.x & 63;
+    long lo, hi;
+    wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
+    const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin,
+                                      w.mixbits, 8 * g.n_chunks, nullptr);
+    long long run = q.woff[(long)blockIdx.x * WPB + (threadIdx.x >> 6)];
+    Part4<T, DIM> nxt;
+    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
+    for (long t0 = lo; t0 < hi; t0 += WT) {
+        const long id = t0 + IT * lane;
+        Part4<T, DIM> p = nxt;
+        load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+        long b[IT];
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            b[k] = bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]);
+            if (!kw.mixed(b[k])) b[k] = -1;
+            c += b[k] >= 0;
+        }
+        const int inc = wave_incl_scan(c);
+        long long o = run + inc - c;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            if (b[k] < 0) continue;
+            q.keys[0][o] = (uint32_t)(2 * b[k] + (p.s[k] > 0 ? 1 : 0));
+            q.vals[0][o] = (uint32_t)(id + k);
+            ++o;
+        }
+        run += __shfl(inc, 63, 64);
+    }
+}
+
+// The contiguous list range of radix block r: whole tiles of PT elements.
+__device__ __forceinline__ void radix_range(long m, long r, long* lo, long* hi) {
+    long c = (m + RB - 1) / RB;
+    c = (c + PT - 1) / PT * PT;
+    *lo = min(m, r * c);
+    *hi = min(m, *lo + c);
+}
+
+// Radix pass, 1: digit counts of each block's range (LDS counters).
+__global__ __launch_bounds__(PT) void radix_hist(const uint32_t* __restrict__ keys, int shift, PairScratch q) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    long lo, hi;
+    radix_range(q.sc[0], blockIdx.x, &lo, &hi);
+    for (long e = lo + threadIdx.x; e < hi; e += PT) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+    __syncthreads();
+    q.cnt[(long)threadIdx.x * RB + blockIdx.x] = h[threadIdx.x];
+}
+
+// Radix pass, 2: exclusive prefix of the 256 x RB counts, digit-major (one workgroup).
+__global__ __launch_bounds__(ST_THREADS) void radix_scan(PairScratch q) {
+    __shared__ long long part[ST_THREADS / 64 + 1];
+    constexpr int per = 256 * RB / ST_THREADS;
+    long long acc = 0;
+    const uint32_t* c = q.cnt + (long)threadIdx.x * per;
+    for (int k = 0; k < per; ++k) acc += c[k];
+    const long long inc = wave_incl_scan_ll(acc);
+    if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = inc;
+    __syncthreads();
+    long long run = inc - acc;
+    for (int k = 0; k < (int)(threadIdx.x >> 6); ++k) run += part[k];
+    uint32_t* o = q.off + (long)threadIdx.x * per;
+    for (int k = 0; k < per; ++k) {
+        o[k] = (uint32_t)run;
+        run += c[k];
+    }
+}
+
+// Radix pass, 3: stable scatter.  Block r walks its range in tiles of PT elements, one per
+// thread in order; an element's slot is its digit's running offset + the tile's earlier
+// elements of the same digit (the lanes of its wave with that digit, found with eight
+// ballots, plus the counts of the earlier waves).
+__global__ __launch_bounds__(PT) void radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                    int shift, PairScratch q) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t cw[WPB][256];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    run[threadIdx.x] = q.off[(long)threadIdx.x * RB + blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < WPB; ++k) cw[k][threadIdx.x] = 0;
+    __syncthreads();
+    long lo, hi;
+    radix_range(q.sc[0], blockIdx.x, &lo, &hi);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (long t0 = lo; t0 < hi; t0 += PT) {  // uniform
+        const long e = t0 + threadIdx.x;
+        const bool valid = e < hi;
+        const uint32_t key = valid ? kin[e] : 0u;
+        const uint32_t val = valid ? vin[e] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const unsigned long long m = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? m : ~m;
+        }
+        const int lower = __popcll(peers & below);
+        if (valid && lower == 0) cw[wv][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + (uint32_t)lower;
+            for (int k = 0; k < wv; ++k) pos += cw[k][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t t = 0;
+#pragma unroll
+        for (int k = 0; k < WPB; ++k) {
+            t += cw[k][threadIdx.x];
+            cw[k][threadIdx.x] = 0;
+        }
+        run[threadIdx.x] += t;
+        __syncthreads();
+    }
+}
+
+// Ranks and flags: position p of the sorted list holds key k; its rank is p minus the first
+// position of k (a running maximum of the segment heads, started from a binary search at the
+// wave's first position); flags[index] = rank >= min(H+, H-) of its bin.
+__global__ __launch_bounds__(PT) void pair_flags(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                                 const int32_t* __restrict__ hist, long n_bins, PairScratch q) {
+    const int lane = threadIdx.x & 63;
+    const long m = q.sc[0];
+    long lo, hi;
+    wave_chunk(m, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
+    if (lo >= hi) return;
+    long start;  // first position of the key at lo
+    {
+        const uint32_t k0 = keys[lo];
+        long a = 0, b = lo;
+        while (a < b) {
+            const long mid = (a + b) >> 1;
+            if (keys[mid] < k0)
+                a = mid + 1;
+            else
+                b = mid;
+        }
+        start = a;
+    }
+    for (long t0 = lo; t0 < hi; t0 += 64) {
+        const long p = t0 + lane;
+        const bool valid = p < hi;
+        const uint32_t k = valid ? keys[p] : 0u;
+        const bool head = valid && (p == 0 || keys[p - 1] != k);
+        long hs = head ? p : -1;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const long t = __shfl_up(hs, o, 64);
+            if (lane >= o) hs = max(hs, t);
+        }
+        const long st = max(start, hs);
+        if (valid) {
+            const long bin = (long)(k >> 1);
+            const int hp = hist[bin], hm = hist[n_bins + bin];
+            const long pairs = hp < hm ? hp : hm;
+            q.flags[vals[p]] = (p - st) >= pairs ? 1 : 0;
+        }
+        start = __shfl(st, 63, 64);
+    }
+}
+
+template <typename T, typename MT, int DIM>
+static void launch_pairs(const Geo& g, const sp_particles* in, sp_particles* out, int32_t* hist,
+                         int hist_ready, long long* stats, WS w, PairScratch q, int passes, hipStream_t s) {
+    const T* x = static_cast<const T*>(in->x);
+    const T* y = static_cast<const T*>(in->y);
+    const MT* M = static_cast<const MT*>(in->M);
+    const MT* My = static_cast<const MT*>(in->My);
+    const long long* d_n = reinterpret_cast<const long long*>(in->d_n);
+    const long long cap_in = (long long)in->capacity;
+    if (!hist_ready) {
+        WK_LAUNCH("hist_clear", fill_i32, dim3(1024), dim3(256), 0, s, hist, 2 * g.n_bins, 0);
+        WK_LAUNCH("annih_hist", (annih_hist<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
+                  in->s, d_n, cap_in, hist, stats);
+    }
+    const BinCount bc{nullptr, hist, g.n_bins};
+    WK_LAUNCH("annih_bins", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, 0, stats, w);
+    WK_LAUNCH("pair_count", (pair_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
+              d_n, cap_in, stats, w);
+    WK_LAUNCH("pair_scan", pair_scan, dim3(1), dim3(ST_THREADS), 0, s, stats, w, q);
+    WK_LAUNCH("pair_write", (pair_write<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
+              d_n, cap_in, stats, w, q);
+    for (int k = 0; k < passes; ++k) {
+        const int src = k & 1;
+        WK_LAUNCH("radix_hist", radix_hist, dim3(RB), dim3(PT), 0, s, q.keys[src], 8 * k, q);
+        WK_LAUNCH("radix_scan", radix_scan, dim3(1), dim3(ST_THREADS), 0, s, q);
+        WK_LAUNCH("radix_scatter", radix_scatter, dim3(RB), dim3(PT), 0, s, q.keys[src], q.vals[src],
+                  q.keys[src ^ 1], q.vals[src ^ 1], 8 * k, q);
+    }
+    WK_LAUNCH("pair_flags", pair_flags, dim3(PB), dim3(PT), 0, s, q.keys[passes & 1], q.vals[passes & 1], hist,
+              g.n_bins, q);
+    WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
+              d_n, cap_in, (const uint8_t*)q.flags, stats, w);
+    WK_LAUNCH("annih_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 1, PLACE_BLOCKS, d_n,
+              reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, stats, w);
+    WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(PB + PLACE_BLOCKS), dim3(PT), 0, s, g,
+              PB, PLACE_BLOCKS, bc, 1, 0u, (uint32_t)TAG_ANNIH, x, y, M, My, in->s, d_n,
+              static_cast<T*>(out->x), static_cast<T*>(out->y), static_cast<MT*>(out->M),
+              static_cast<MT*>(out->My), out->s, (long long)out->capacity, (const uint8_t*)q.flags, w);
 }
 
 __global__ void density_kernel(const int32_t* hist, long n_cells, long per_cell, long n_bins,
@@ -1562,22 +1895,22 @@ static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp
     }
     const BinCount bc{nullptr, hist, g.n_bins};
     long long* d_n_out = reinterpret_cast<long long*>(out->d_n);
-    WK_LAUNCH("annih_bins", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, stats, w);
+    WK_LAUNCH("annih_bins", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, 1, stats, w);
     WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
-              d_n, cap_in, stats, w);
+              d_n, cap_in, (const uint8_t*)nullptr, stats, w);
     WK_LAUNCH("annih_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 1, PLACE_BLOCKS, d_n,
               d_n_out, (long long)out->capacity, stats, w);
     WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(PB + PLACE_BLOCKS), dim3(PT), 0, s, g,
               PB, PLACE_BLOCKS, bc, 1, step, (uint32_t)TAG_ANNIH, x, y, M, My, in->s, d_n,
               static_cast<T*>(out->x), static_cast<T*>(out->y), static_cast<MT*>(out->M),
-              static_cast<MT*>(out->My), out->s, (long long)out->capacity, w);
+              static_cast<MT*>(out->My), out->s, (long long)out->capacity, (const uint8_t*)nullptr, w);
 }
 
 template <typename T, typename MT, int DIM>
 static void launch_init(const Geo& g, const int32_t* counts, sp_particles* out, long long* stats,
                         WS w, hipStream_t s) {
     const BinCount bc{counts, nullptr, g.n_bins};
-    WK_LAUNCH("init_count", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, stats, w);
+    WK_LAUNCH("init_count", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, 1, stats, w);
     WK_LAUNCH("init_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 0, PLACE_BLOCKS,
               (const long long*)nullptr, reinterpret_cast<long long*>(out->d_n),
               (long long)out->capacity, stats, w);
@@ -1586,7 +1919,7 @@ static void launch_init(const Geo& g, const int32_t* counts, sp_particles* out, 
               (const T*)nullptr, (const MT*)nullptr, (const MT*)nullptr, (const int8_t*)nullptr,
               (const long long*)nullptr, static_cast<T*>(out->x), static_cast<T*>(out->y),
               static_cast<MT*>(out->M), static_cast<MT*>(out->My), out->s,
-              (long long)out->capacity, w);
+              (long long)out->capacity, (const uint8_t*)nullptr, w);
 }
 
 }  // namespace wk
@@ -1679,6 +2012,39 @@ extern "C" int sp_annihilate(const sp_geom* gm, const sp_particles* in, sp_parti
     WK_DISPATCH(gm, launch_annih, g, (uint32_t)step, in, out, hist, (int)(hist_ready != 0),
                 reinterpret_cast<long long*>(d_stats), w, as_stream(stream));
     return check_launch("sp_annihilate");
+}
+
+extern "C" size_t sp_pairs_scratch_size(const sp_geom* gm, int64_t n_max) {
+    if (!gm || n_max < 0 || n_max >= (1LL << 31)) return 0;
+    return pair_scratch_bytes((long)n_max);
+}
+
+extern "C" int sp_annihilate_pairs(const sp_geom* gm, const sp_particles* in, sp_particles* out,
+                                   int32_t* hist, int32_t hist_ready, int64_t* d_stats, void* ws,
+                                   size_t ws_bytes, void* scratch, size_t scratch_bytes, void* stream) {
+    Geo g;
+    int rc = make_geo(gm, &g);
+    if (rc) return rc;
+    rc = check_particles(gm, in, "sp_annihilate_pairs(in)");
+    if (rc) return rc;
+    rc = check_particles(gm, out, "sp_annihilate_pairs(out)");
+    if (rc) return rc;
+    WK_REQUIRE(in->x != out->x && in->M != out->M && in->s != out->s && in->d_n != out->d_n,
+               "sp_annihilate_pairs: in and out must be different buffers");
+    WK_REQUIRE(hist && d_stats, "sp_annihilate_pairs: NULL array");
+    WK_REQUIRE(2 * g.n_bins < (1L << 32), "sp_annihilate_pairs: too many bins for 32-bit keys");
+    WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny),
+               "sp_annihilate_pairs: workspace too small");
+    WK_REQUIRE(scratch && scratch_bytes >= pair_scratch_bytes((long)in->capacity),
+               "sp_annihilate_pairs: scratch smaller than sp_pairs_scratch_size(g, in->capacity)");
+    int bits = 0;
+    while ((1L << bits) < 2 * g.n_bins) ++bits;
+    const int passes = (bits + 7) / 8;
+    WS w = carve(ws, g.n_bins, (long)g.nx * g.ny);
+    const PairScratch q = pair_carve(scratch, (long)in->capacity);
+    WK_DISPATCH(gm, launch_pairs, g, in, out, hist, (int)(hist_ready != 0),
+                reinterpret_cast<long long*>(d_stats), w, q, passes, as_stream(stream));
+    return check_launch("sp_annihilate_pairs");
 }
 
 extern "C" int sp_density(const sp_geom* gm, const int32_t* hist, double N0, double* rho,

@@ -285,6 +285,26 @@ def sp_annihilate(mesh: dict, seed: int, pin: DeviceParticles, pout: DeviceParti
                                   _stream()), "sp_annihilate")
 
 
+def sp_pairs_scratch(mesh: dict, capacity: int, device="cuda") -> torch.Tensor:
+    """Scratch buffer of sp_annihilate_pairs for input buffers of `capacity` particles."""
+    g = geom_struct(mesh, 0)
+    n = int(L.lib().sp_pairs_scratch_size(ctypes.byref(g), int(capacity)))
+    if n == 0:
+        L.check(L.WK_EINVAL, "sp_pairs_scratch_size")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def sp_annihilate_pairs(mesh: dict, pin: DeviceParticles, pout: DeviceParticles, hist: torch.Tensor,
+                        stats: torch.Tensor, ws: torch.Tensor, scratch: torch.Tensor,
+                        hist_ready: bool = False):
+    """Rule 2 as literal pair removal (survivors keep their exact positions)."""
+    g = geom_struct(mesh, 0, _m16(pin, pout))
+    a, b = pin.struct(), pout.struct()
+    L.check(L.lib().sp_annihilate_pairs(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _ptr(hist),
+                                        int(bool(hist_ready)), _ptr(stats), _ptr(ws), ws.numel(),
+                                        _ptr(scratch), scratch.numel(), _stream()), "sp_annihilate_pairs")
+
+
 def sp_density(mesh: dict, hist: torch.Tensor, N0: float, rho: torch.Tensor | None = None):
     g = geom_struct(mesh, 0)
     if rho is None:

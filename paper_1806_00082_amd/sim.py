@@ -8,6 +8,10 @@ the result); sp_annihilate (rule 2 on that histogram).  The particle
 count stays in device memory; the host synchronises only to size the occasional kernel-row
 refresh and to read statistics.
 
+Annihilation (rule 2): "regenerate" replaces the particles of each bin holding both signs by
+|H+ - H-| fresh particles of the net sign; "pairs" removes opposite-sign pairs and keeps the
+other particles exactly where they are.
+
 Kernel sources (the paper's two steps, Sec. 4): "exact" = eq.(4) on MFMA in FP64 or a reduced
 precision; "surrogate" = the trained network of eq.(5); "given" = rows the caller computed
 (`rows`, one per cell, every cell evaluated at start).  Rows are evaluated only for cells
@@ -30,12 +34,15 @@ class Simulator:
     def __init__(self, cfg, kernel: str = "exact", prec: str = "fp64", mode: str = "occupied",
                  refresh_every: int = 8, cap_factor: float = 3.0, weights=None, N: int = 2,
                  device="cuda", hist_in_step: bool = True, rows=None, m16=None,
-                 fused_tables: bool = True):
+                 fused_tables: bool = True, annihilation: str = "regenerate"):
         self.cfg = cfg
         self.md = cfg.mesh.as_dict(cfg.dt)
         md = self.md
         self.dim = md["dim"]
         self.kernel, self.prec, self.mode = kernel, prec, mode
+        if annihilation not in ("regenerate", "pairs"):
+            raise ValueError("annihilation must be 'regenerate' or 'pairs'")
+        self.annihilation = annihilation
         self.hist_in_step = hist_in_step   # sp_step builds the histogram sp_annihilate uses
         self.refresh_every = max(1, int(refresh_every))
         self.N, self.weights = N, weights
@@ -89,6 +96,8 @@ class Simulator:
         self.stats = ops.new_stats(self.dev)
         self.ws = ops.sp_workspace(md, self.seed, self.dev)
         self.hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=self.dev)
+        self.pair_scratch = (ops.sp_pairs_scratch(md, self.capacity, self.dev)
+                             if annihilation == "pairs" else None)
         ops.sp_init(md, self.seed, bc.to(self.dev), self.a, self.stats, self.ws)
         self.step_index = 0
         # the initial ensemble is single-signed: this pass only builds the histogram
@@ -158,8 +167,12 @@ class Simulator:
         ops.sp_step(self.md, self.seed, self.cell_slot, self.n0, self.thr, self.cdf, self.a,
                     self.b, s, self.stats, self.ws, hist=self.hist if self.hist_in_step else None,
                     guide=self.guide)
-        ops.sp_annihilate(self.md, self.seed, self.b, self.a, self.hist, s, self.stats, self.ws,
-                          hist_ready=self.hist_in_step)
+        if self.annihilation == "pairs":
+            ops.sp_annihilate_pairs(self.md, self.b, self.a, self.hist, self.stats, self.ws,
+                                    self.pair_scratch, hist_ready=self.hist_in_step)
+        else:
+            ops.sp_annihilate(self.md, self.seed, self.b, self.a, self.hist, s, self.stats, self.ws,
+                              hist_ready=self.hist_in_step)
         self.step_index += 1
 
     def run(self, steps: int):

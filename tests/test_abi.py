@@ -77,6 +77,10 @@ def test_workspace_contracts_without_gpu():
     rc = lib.wk_kernel_bwd(ctypes.byref(m), fake, 2, fake, 10, _lib.WK_FP64, _lib.WK_HALF, fake, fake,
                            w64 - 1, None)
     assert rc == _lib.WK_EINVAL and b"workspace" in lib.wk_last_error()
+    # pair removal: scratch sized by the input capacity
+    g = _lib.SpGeom(1, 10, 1, 8, 16, -8, 0, 0, 0.1, 0)
+    assert lib.sp_pairs_scratch_size(ctypes.byref(g), 1000) > lib.sp_pairs_scratch_size(ctypes.byref(g), 10) > 0
+    assert lib.sp_pairs_scratch_size(ctypes.byref(g), -1) == 0
     # set-up validates before touching a device
     bad = _lib.WkMesh(1, 64, 1, 31, 0.65)
     assert lib.wk_prepare(ctypes.byref(bad), None) == _lib.WK_EINVAL

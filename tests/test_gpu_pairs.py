@@ -1,0 +1,139 @@
+"""Rule 2 as literal pair removal (sp_annihilate_pairs) on the GPU against the oracle:
+bit-exact survivors (positions, momenta, signs, order), histogram and statistics."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import HB, assert_particles_equal, dev, host_tables_to_device, to_np
+from paper_1806_00082_amd import _lib as L
+from paper_1806_00082_amd import inputs, ops
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed(orc, md, n, seed, span=6, cap=None):
+    rng = np.random.default_rng(seed)
+    p = orc.Particles(md["dim"], cap or n, md["pos_f64"])
+    p.x[:n] = rng.uniform(0, span, n).astype(p.x.dtype)
+    p.M[:n] = rng.integers(md["M_min"], md["M_min"] + 3, n)
+    if md["dim"] == 2:
+        p.y[:n] = rng.uniform(0, 2, n).astype(p.y.dtype)
+        p.My[:n] = rng.integers(md["M_min"], md["M_min"] + 2, n)
+    p.s[:n] = rng.choice([-1, 1, 1, 0], n)
+    p.n = n
+    return p
+
+
+def _gpu(md, hp, cap, m16=False):
+    v = hp.view()
+    a = ops.DeviceParticles(md["dim"], cap, md["pos_f64"], m16=m16)
+    a.load(hp.n, v["x"], v["M"], v["s"], y=v.get("y"), My=v.get("My"))
+    return a
+
+
+def _check_once(orc, md, hp, cap, hist_ready, m16=False):
+    a = _gpu(md, hp, cap, m16)
+    b = ops.DeviceParticles(md["dim"], cap, md["pos_f64"], m16=m16)
+    st = ops.new_stats()
+    ws = ops.sp_workspace(md)
+    nb = ops.n_bins(md)
+    hist = torch.zeros(2 * nb, dtype=torch.int32, device=dev())
+    ref, hp_, hm_, rst = orc.sp_annihilate_pairs(md, hp, capacity=cap)
+    if hist_ready:
+        hist[:nb] = torch.from_numpy(hp_).to(dev())
+        hist[nb:] = torch.from_numpy(hm_).to(dev())
+    ops.sp_annihilate_pairs(md, a, b, hist, st, ws, ops.sp_pairs_scratch(md, cap), hist_ready=hist_ready)
+    assert_particles_equal(b.view(), ref.view(), "pair removal")
+    h = to_np(hist)
+    assert np.array_equal(h[:nb], hp_) and np.array_equal(h[nb:], hm_)
+    g = to_np(st)
+    for k, r in ((L.ST_N, orc.ST_N), (L.ST_KEPT, orc.ST_KEPT), (L.ST_REGEN, orc.ST_REGEN),
+                 (L.ST_MIXED, orc.ST_MIXED)):
+        assert g[k] == rst[r], (k, g[k], rst[r])
+    return rst
+
+
+@pytest.mark.parametrize("hist_ready", [False, True])
+@pytest.mark.parametrize("case", ["1d_f64", "1d_f32_m16", "2d"])
+def test_pair_removal_small(orc, case, hist_ready):
+    if case == "2d":
+        md = {"dim": 2, "nx": 8, "ny": 3, "n_m": 8, "n_k": 8, "M_min": -4, "pos_f64": False, "vdt": 0.1}
+    else:
+        md = {"dim": 1, "nx": 8, "ny": 1, "n_m": 8, "n_k": 16, "M_min": -8,
+              "pos_f64": case == "1d_f64", "vdt": 0.1}
+    for seed, n in ((0, 300), (1, 5000), (2, 70000)):
+        hp = _mixed(orc, md, n, seed)
+        rst = _check_once(orc, md, hp, n + 16, hist_ready, m16=case == "1d_f32_m16")
+        assert rst[orc.ST_MIXED] > 0
+
+
+def test_pair_removal_edges(orc):
+    md = {"dim": 1, "nx": 8, "ny": 1, "n_m": 8, "n_k": 16, "M_min": -8, "pos_f64": False, "vdt": 0.1}
+    # empty input
+    hp = _mixed(orc, md, 0, 0, cap=8)
+    _check_once(orc, md, hp, 8, False)
+    # one sign only: nothing annihilates, the list is empty
+    hp = _mixed(orc, md, 3000, 3)
+    hp.s[: hp.n] = np.abs(hp.s[: hp.n])
+    rst = _check_once(orc, md, hp, 3000, False)
+    assert rst[orc.ST_MIXED] == 0 and rst[orc.ST_N] == int((hp.s[:3000] != 0).sum())
+    # every particle paired off: equal numbers of each sign in one bin
+    hp = _mixed(orc, md, 2000, 4)
+    hp.x[:2000] = 2.5
+    hp.M[:2000] = -3
+    hp.s[:2000] = np.tile([1, -1], 1000)
+    rst = _check_once(orc, md, hp, 2000, False)
+    assert rst[orc.ST_N] == 0
+
+
+@pytest.mark.parametrize("cfgname", ["c1", "c2small"])
+def test_pair_removal_time_loop(orc, cfgname):
+    """Steps of postulate II followed by pair removal, on both sides, bit-exact every step."""
+    cfg = inputs.config_c1() if cfgname == "c1" else inputs.config_c2(N0=2e5)
+    md = cfg.mesh.as_dict(cfg.dt)
+    K = orc.kernel_1d(cfg.V, md["n_m"], HB)[0]
+    tables = orc.gamma_tables(K, cfg.dt)[1:]
+    bc = cfg.bin_counts
+    cap = 3 * int(bc.sum()) + 64
+    seed = cfg.seed
+    slot = np.arange(md["nx"], dtype=np.int32)
+    hp = orc.sp_init(md, bc, cap, seed=seed)
+    a = ops.DeviceParticles(1, cap, md["pos_f64"])
+    st = ops.new_stats()
+    ws = ops.sp_workspace(md, seed)
+    ops.sp_init(md, seed, torch.from_numpy(bc).to(dev()), a, st, ws)
+    b = ops.DeviceParticles(1, cap, md["pos_f64"])
+    hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev())
+    scratch = ops.sp_pairs_scratch(md, cap)
+    n0, thr, cdf = host_tables_to_device((None,) + tuple(tables))
+    slot_d = torch.from_numpy(slot).to(dev())
+    for s in range(8):
+        fused = s % 2 == 1
+        hp, _ = orc.sp_step(md, hp, tables, slot, step=s, seed=seed)
+        ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, b, s, st, ws, hist=hist if fused else None)
+        assert_particles_equal(b.view(), hp.view(), f"step {s}")
+        hp, hh_p, hh_m, hst = orc.sp_annihilate_pairs(md, hp, capacity=cap)
+        ops.sp_annihilate_pairs(md, b, a, hist, st, ws, scratch, hist_ready=fused)
+        assert_particles_equal(a.view(), hp.view(), f"pair removal {s}")
+        g = to_np(st)
+        assert g[L.ST_N] == hst[orc.ST_N] and g[L.ST_MIXED] == hst[orc.ST_MIXED]
+
+
+def test_pair_removal_full_size_2d(orc):
+    """The 2-D mesh at full size with two overlapping opposite-sign packets (1e8 particles, tens
+    of millions of them in mixed bins, 27-bit sort keys in four radix passes): bit-exact."""
+    cfg = inputs.config_c5()
+    md = cfg.mesh.as_dict(cfg.dt)
+    bc2 = inputs.packet_bin_counts_2d(cfg.mesh, 5e7, 36.0, 64.0, 8.0, cfg.meta["k0"], 0.0)
+    n1, n2 = int(cfg.bin_counts.sum()), int(bc2.sum())
+    hp = orc.sp_init(md, cfg.bin_counts, n1 + n2, seed=cfg.seed)
+    hm = orc.sp_init(md, bc2, n2, seed=cfg.seed + 1)
+    for f in ("x", "y", "M", "My"):
+        getattr(hp, f)[n1:n1 + n2] = getattr(hm, f)[:n2]
+    hp.s[n1:n1 + n2] = -1
+    hp.n = n1 + n2
+    del hm
+    print(f"pair removal, 2-D full size: {hp.n} particles", flush=True)
+    rst = _check_once(orc, md, hp, n1 + n2, False)
+    print(f"kept {rst[orc.ST_N]} of {n1 + n2}, mixed bins {rst[orc.ST_MIXED]}", flush=True)
+    assert rst[orc.ST_N] < n1 + n2
