@@ -71,7 +71,7 @@ def kernel_bytes(PB: int, dim: int, hist_bytes: int):
     }
 
 
-def run_particles(cfg, steps: int, warmup: int, traced: bool):
+def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str = "regenerate"):
     """A time-loop workload.  traced=True replays the identical (bit-exact, same seed) run with
     per-kernel events, used only for the per-kernel roofline; the reported value comes from
     the untraced run."""
@@ -80,7 +80,8 @@ def run_particles(cfg, steps: int, warmup: int, traced: bool):
     from paper_1806_00082_amd import ops
     from paper_1806_00082_amd.sim import Simulator
 
-    sim = Simulator(cfg, kernel="exact", prec="fp64", mode="occupied", refresh_every=8)
+    sim = Simulator(cfg, kernel="exact", prec="fp64", mode="occupied", refresh_every=8,
+                    annihilation=annihilation)
     for _ in range(warmup):
         sim.step()
     sim.stats[L.ST_CUM_STEPS:L.ST_COUNT].zero_()
@@ -358,6 +359,33 @@ def run_learning_c4(n_train=100000, n_test=1000, sweep_epochs=3, train_epochs=6,
     return out
 
 
+def run_annihilation_modes():
+    """Rule 2 read two ways on both time-loop workloads: regeneration of mixed bins (the
+    headline) and literal pair removal (survivors keep their positions; a stable radix sort
+    of the mixed bins' particles).  The trajectories differ (different readings), so each
+    mode is timed on its own run: ms per step and particle-steps/s untraced, and its
+    annihilation kernels from a traced replica."""
+    from paper_1806_00082_amd import inputs
+
+    out = {}
+    for tag, cfg, steps, warm in (("workload_2d", inputs.config_c5(), 190, 10),
+                                  ("workload_1d", inputs.config_c2(), 390, 10)):
+        rec = {}
+        for mode in ("regenerate", "pairs"):
+            u = run_particles(cfg, steps, warm, traced=False, annihilation=mode)
+            r = run_particles(cfg, steps, warm, traced=True, annihilation=mode)
+            k = r["kernels"]
+            annih = {n: v["us_avg"] for n, v in k.items()
+                     if n.startswith(("annih", "pair", "radix", "hist_"))}
+            rec[mode] = {"ms_per_step": round(u["ms"] / steps, 4),
+                         "particle_steps_per_s": u["particle_steps"] / (u["ms"] * 1e-3),
+                         "n_last": u["n_last"], "annihilation_kernels_us": annih,
+                         "annihilation_us_per_step": round(sum(v["ms_total"] for n, v in k.items()
+                                                               if n in annih) * 1e3 / steps, 1)}
+        out[tag] = rec
+    return out
+
+
 def run_surrogate_forms():
     """eq.(5) forward (analytic barycentric weights) vs the exact kernel, 1024 cells x 256 m."""
     import torch
@@ -551,6 +579,8 @@ def main():
                     help="only the eq.(4) precision batch (for counter runs on the contraction)")
     ap.add_argument("--learning-only", action="store_true",
                     help="only the training study of eq.(5) (with --train-epochs, --sweep-epochs)")
+    ap.add_argument("--annihilation-only", action="store_true",
+                    help="only the comparison of the two readings of rule 2")
     ap.add_argument("--train-epochs", type=int, default=6)
     ap.add_argument("--sweep-epochs", type=int, default=3)
     args = ap.parse_args()
@@ -564,7 +594,8 @@ def main():
         sys.exit(1)
     # the CPU oracle legs run first, before anything touches the GPU
     cpu = cpu_kernel = None
-    if not (args.no_cpu or args.forms_only or args.learning_only or args.headline_1d):
+    if not (args.no_cpu or args.forms_only or args.learning_only or args.headline_1d
+            or args.annihilation_only):
         print("cpu baseline: oracle particle passes", file=sys.stderr, flush=True)
         cpu = run_cpu_particles(args.cpu_steps)
         print("cpu baseline: oracle eq.(4)", file=sys.stderr, flush=True)
@@ -577,6 +608,9 @@ def main():
     from paper_1806_00082_amd import inputs
     if args.forms_only:
         print(json.dumps({"forms": {"kernel_eq4": run_kernel_forms()}}))
+        return
+    if args.annihilation_only:
+        print(json.dumps({"forms": {"annihilation_modes": run_annihilation_modes()}}))
         return
     if args.learning_only:
         print(json.dumps({"forms": {"learning_c4": run_learning_c4(sweep_epochs=args.sweep_epochs,
@@ -603,7 +637,8 @@ def main():
             "note": "double-buffered 7-byte particles (2 x 70 MB) fit the 256 MB MALL: its HBM fraction "
                     "is a cache-assisted figure, the headline's 2-D run is not",
             "roofline": s1t["roofline"], "step_roofline": s1t["step_roofline"], "kernels": s1t["kernels"]}
-        for name, fn in (("kernel_eq4", run_kernel_forms), ("surrogate_eq5", run_surrogate_forms),
+        for name, fn in (("annihilation_modes", run_annihilation_modes),
+                         ("kernel_eq4", run_kernel_forms), ("surrogate_eq5", run_surrogate_forms),
                          ("learning", run_learning), ("tables", run_tables_forms),
                          ("learning_c4", lambda: run_learning_c4(sweep_epochs=args.sweep_epochs,
                                                                  train_epochs=args.train_epochs))):

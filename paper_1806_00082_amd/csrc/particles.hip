@@ -1412,19 +1412,22 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
 constexpr int RB = PB;  // workgroups of the radix passes, each owning a contiguous range
 
 // Caller scratch of sp_annihilate_pairs: int64 sc[16] | int64 woff[NW] | uint32 cnt[256 RB] |
-// uint32 off[256 RB] | uint32 keys[2][n_max] | uint32 vals[2][n_max] | uint8 flags[n_max].
+// uint32 off[256 RB] | uint32 dtot[256] | uint32 dbase[256] | uint32 keys[2][n_max] |
+// uint32 vals[2][n_max] | uint8 flags[n_max].
 struct PairScratch {
     long long* sc;     // sc[0]: number of listed particles
     long long* woff;   // per wave of the listing pass: first list slot
     uint32_t* cnt;     // radix digit counts [digit][block]
-    uint32_t* off;     // their exclusive prefix (digit-major)
+    uint32_t* off;     // their exclusive prefix within each digit
+    uint32_t* dtot;    // per digit: its count over all blocks
+    uint32_t* dbase;   // exclusive prefix of dtot
     uint32_t* keys[2];
     uint32_t* vals[2];
     uint8_t* flags;
 };
 
 static size_t pair_scratch_bytes(long n_max) {
-    return sizeof(long long) * (16 + (size_t)NW) + 2 * sizeof(uint32_t) * 256 * (size_t)RB +
+    return sizeof(long long) * (16 + (size_t)NW) + 2 * sizeof(uint32_t) * 256 * ((size_t)RB + 1) +
            4 * sizeof(uint32_t) * (size_t)n_max + (size_t)n_max + 64;
 }
 
@@ -1434,7 +1437,9 @@ static PairScratch pair_carve(void* p, long n_max) {
     q.woff = q.sc + 16;
     q.cnt = reinterpret_cast<uint32_t*>(q.woff + NW);
     q.off = q.cnt + 256 * RB;
-    q.keys[0] = q.off + 256 * RB;
+    q.dtot = q.off + 256 * RB;
+    q.dbase = q.dtot + 256;
+    q.keys[0] = q.dbase + 256;
     q.keys[1] = q.keys[0] + n_max;
     q.vals[0] = q.keys[1] + n_max;
     q.vals[1] = q.vals[0] + n_max;
@@ -1567,23 +1572,33 @@ __global__ __launch_bounds__(PT) void radix_hist(const uint32_t* __restrict__ ke
     q.cnt[(long)threadIdx.x * RB + blockIdx.x] = h[threadIdx.x];
 }
 
-// Radix pass, 2: exclusive prefix of the 256 x RB counts, digit-major (one workgroup).
-__global__ __launch_bounds__(ST_THREADS) void radix_scan(PairScratch q) {
-    __shared__ long long part[ST_THREADS / 64 + 1];
-    constexpr int per = 256 * RB / ST_THREADS;
-    long long acc = 0;
-    const uint32_t* c = q.cnt + (long)threadIdx.x * per;
-    for (int k = 0; k < per; ++k) acc += c[k];
-    const long long inc = wave_incl_scan_ll(acc);
-    if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = inc;
-    __syncthreads();
-    long long run = inc - acc;
-    for (int k = 0; k < (int)(threadIdx.x >> 6); ++k) run += part[k];
-    uint32_t* o = q.off + (long)threadIdx.x * per;
+// Radix pass, 2a: per digit (one workgroup each), the exclusive prefix of its RB block counts
+// and its total.
+__global__ __launch_bounds__(PT) void radix_scan_digits(PairScratch q) {
+    __shared__ int ldsw[WPB];
+    constexpr int per = RB / PT;
+    const long base = (long)blockIdx.x * RB + (long)threadIdx.x * per;
+    uint32_t loc[per], acc = 0;
+#pragma unroll
     for (int k = 0; k < per; ++k) {
-        o[k] = (uint32_t)run;
-        run += c[k];
+        loc[k] = q.cnt[base + k];
+        acc += loc[k];
     }
+    int tot;
+    uint32_t run = (uint32_t)block_excl_scan_pt((int)acc, &tot, ldsw);  // counts < 2^31
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        q.off[base + k] = run;
+        run += loc[k];
+    }
+    if (threadIdx.x == 0) q.dtot[blockIdx.x] = (uint32_t)tot;
+}
+
+// Radix pass, 2b: exclusive prefix of the 256 digit totals (one workgroup).
+__global__ __launch_bounds__(PT) void radix_scan_totals(PairScratch q) {
+    __shared__ int ldsw[WPB];
+    int tot;
+    q.dbase[threadIdx.x] = (uint32_t)block_excl_scan_pt((int)q.dtot[threadIdx.x], &tot, ldsw);
 }
 
 // Radix pass, 3: stable scatter.  Block r walks its range in tiles of PT elements, one per
@@ -1596,7 +1611,7 @@ __global__ __launch_bounds__(PT) void radix_scatter(const uint32_t* __restrict__
     __shared__ uint32_t run[256];
     __shared__ uint32_t cw[WPB][256];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    run[threadIdx.x] = q.off[(long)threadIdx.x * RB + blockIdx.x];
+    run[threadIdx.x] = q.dbase[threadIdx.x] + q.off[(long)threadIdx.x * RB + blockIdx.x];
 #pragma unroll
     for (int k = 0; k < WPB; ++k) cw[k][threadIdx.x] = 0;
     __syncthreads();
@@ -1705,7 +1720,8 @@ static void launch_pairs(const Geo& g, const sp_particles* in, sp_particles* out
     for (int k = 0; k < passes; ++k) {
         const int src = k & 1;
         WK_LAUNCH("radix_hist", radix_hist, dim3(RB), dim3(PT), 0, s, q.keys[src], 8 * k, q);
-        WK_LAUNCH("radix_scan", radix_scan, dim3(1), dim3(ST_THREADS), 0, s, q);
+        WK_LAUNCH("radix_scan", radix_scan_digits, dim3(256), dim3(PT), 0, s, q);
+        WK_LAUNCH("radix_totals", radix_scan_totals, dim3(1), dim3(PT), 0, s, q);
         WK_LAUNCH("radix_scatter", radix_scatter, dim3(RB), dim3(PT), 0, s, q.keys[src], q.vals[src],
                   q.keys[src ^ 1], q.vals[src ^ 1], 8 * k, q);
     }

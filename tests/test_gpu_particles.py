@@ -406,3 +406,50 @@ def test_c5_full_size_mixed_ensemble(orc):
     del hm
     out = _c5_compare(orc, md, tables, slot, hp, cfg.seed, steps=2, first_step=4, label="c5 mixed")
     assert out.n < n1 + n2  # annihilation removed particles
+
+
+@pytest.mark.parametrize("pos_f64", [False, True])
+@pytest.mark.parametrize("glen", [None, 16])
+def test_hundreds_of_pairs_per_particle(orc, pos_f64, glen):
+    """gamma dt >= 300 in a few cells: a particle creates 300+ pairs, so its pair count no
+    longer fits the one-byte hand-over between the two sp_step passes and takes the wide
+    form; mixed with cells of ordinary rates, float and double positions, guide on and off."""
+    md = {"dim": 1, "nx": 12, "ny": 1, "n_m": 16, "n_k": 32, "M_min": -16, "pos_f64": pos_f64,
+          "vdt": 0.01}
+    rng = np.random.default_rng(17)
+    K = np.abs(rng.normal(size=(12, 16))) * 0.05
+    K[:, 8] = 0
+    K[:, 1:8] = -K[:, 9:16][:, ::-1]
+    K[3] *= 1400.0                    # gamma dt ~ 300 .. 320 in cells 3 and 8
+    K[8] *= 1500.0
+    tables = orc.gamma_tables(K, 1.0)
+    assert tables[1][3] >= 255 and tables[1][8] >= 255 and tables[1][0] < 4
+    n = 700
+    x = rng.uniform(0, 12, n)
+    x[:40] = 3.5 + rng.uniform(-0.4, 0.4, 40)       # some particles in the fast cells
+    x[40:70] = 8.5 + rng.uniform(-0.4, 0.4, 30)
+    perm = rng.permutation(n)
+    x = x[perm]
+    M = rng.integers(-4, 4, n)
+    s = rng.choice([-1, 1], n).astype(np.int8)
+    cells = np.floor(x).astype(np.int64)
+    cap = n + 2 * int((tables[1][cells].astype(np.int64) + 1).sum()) + 64   # every possible pair
+    hp = orc.Particles(1, cap, pos_f64)
+    hp.x[:n] = x.astype(hp.x.dtype)
+    hp.M[:n] = M
+    hp.s[:n] = s
+    hp.n = n
+    v = hp.view()
+    a = ops.DeviceParticles(1, cap, pos_f64)
+    a.load(n, v["x"], v["M"], v["s"])
+    slot = np.arange(12, dtype=np.int32)
+    n0, thr, cdf = host_tables_to_device(tables)
+    st = ops.new_stats()
+    guide = None if glen is None else ops.sampling_guide(cdf, glen)
+    b = ops.DeviceParticles(1, cap, pos_f64)
+    ops.sp_step(md, 9, torch.from_numpy(slot).to(dev()), n0, thr, cdf, a, b, 2, st,
+                ops.sp_workspace(md, 9), guide=guide)
+    ref, rst = orc.sp_step(md, hp, tables[1:], slot, step=2, seed=9)
+    assert rst[orc.ST_NEEDED] == 0 and rst[orc.ST_PAIRS] > 70 * 255
+    assert_particles_equal(b.view(), ref.view(), "hundreds of pairs")
+    assert to_np(st)[L.ST_PAIRS] == rst[orc.ST_PAIRS]
