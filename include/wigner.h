@@ -156,7 +156,7 @@ int wk_prepare(const wk_mesh* mesh, void* stream);
  *   V       [B][nx] (1-D) or [B][ny][nx] (2-D), double.
  *   cells   [n_cells] int32 cell ids (2-D: iy * nx + ix), or NULL for all cells
  *           (then n_cells must be nx * ny).  An id outside the mesh gives a row of NaN.
- *   prec    enum wk_prec; 2-D supports WK_FP64 only, with n_m in {8, 16, 32}.
+ *   prec    enum wk_prec (WK_FP64 .. WK_FP16X3); 2-D supports n_m in {8, 16, 32}.
  *   layout  WK_FULL or WK_HALF (1-D only).
  *   K_out   [B * n_cells][n_m] (full), [B * n_cells][P] (half) or
  *           [B * n_cells][n_m][n_m] (2-D); double for WK_FP64, float otherwise.

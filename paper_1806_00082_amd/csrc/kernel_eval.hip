@@ -804,6 +804,8 @@ int kernel_eval_1d_lowp(const wk_mesh* mesh, const double* V, int B, const int32
 }
 int kernel_eval_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
                    double* out, hipStream_t stream);
+int kernel_eval_2d_16(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
+                      int prec, float* out, hipStream_t stream);
 int kernel_tables_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
                      const TabOut& tb, hipStream_t stream);
 
@@ -834,10 +836,13 @@ extern "C" int wk_kernel_eval(const wk_mesh* mesh, const double* V, int32_t B,
                                            static_cast<float*>(K_out), wk::as_stream(stream));
         return wk::fail(WK_EINVAL, "wk_kernel_eval: unknown precision");
     }
-    WK_REQUIRE(prec == WK_FP64, "wk_kernel_eval: 2-D supports WK_FP64");
     WK_REQUIRE(layout == WK_FULL, "wk_kernel_eval: 2-D tables are full");
-    return wk::kernel_eval_2d(mesh, V, B, cells, n_cells, static_cast<double*>(K_out),
-                              wk::as_stream(stream));
+    if (prec == WK_FP64)
+        return wk::kernel_eval_2d(mesh, V, B, cells, n_cells, static_cast<double*>(K_out),
+                                  wk::as_stream(stream));
+    WK_REQUIRE(prec >= WK_BF16 && prec <= WK_FP16X3, "wk_kernel_eval: unknown precision");
+    return wk::kernel_eval_2d_16(mesh, V, B, cells, n_cells, prec, static_cast<float*>(K_out),
+                                 wk::as_stream(stream));
 }
 
 extern "C" int wk_kernel_tables(const wk_mesh* mesh, const double* V, int32_t B,
@@ -1438,6 +1443,212 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_2d_f64(
                 if (threadIdx.x == 0) gout[tb.G] = (uint32_t)(W - 1);
             }
         }
+    }
+}
+
+// d = 2 in 16-bit operands with FP32 sums (BF16 / FP16, and their hi/lo split forms): the same
+// two stages on v_mfma_f32_16x16x32_{bf16,f16}.  Stage 1 contracts over jx: T[jy][n] =
+// sum_jx D[jy][jx] B1[jx][n] (n < 2P: w sin, else w cos), D rounded from FP64 to 16 bits in
+// LDS (hi, and for the split forms lo = round16(D - hi)); its FP32 result is rounded again
+// (hi / lo) into a transposed tile Tt[mx][part * M1 + jy] (part 0: the sine columns, 1: the
+// cosines), which stage 2 contracts over (part, jy) against A2[my][(part, jy)] = w cos / w sin.
+// Split forms add the hi x lo and lo x hi products in both stages.  The trig operands depend on
+// (n_m, lane) only and live in registers; workgroups loop over the requested cells.
+template <int P, int PREC>
+__global__ __launch_bounds__(KE_THREADS) void kernel_eval_2d_lowp(
+    const double* __restrict__ V, int nx, int ny, long R, int n_cells,
+    const int32_t* __restrict__ cells, float c2, float* __restrict__ out) {
+    typedef LowpTraits<PREC> TR;
+    constexpr bool HALF = TR::half, SPLIT = TR::split;
+    constexpr int NS = SPLIT ? 2 : 1;
+    constexpr int J = 2 * P + 1;
+    constexpr int M1 = (J + 15) / 16 * 16, K1 = (J + 31) / 32 * 32, N1 = 4 * P;
+    constexpr int MT1 = M1 / 16, KS1 = K1 / 32, NT1 = N1 / 16, NT1W = (NT1 + 3) / 4;
+    constexpr int K2 = 2 * M1, KS2 = K2 / 32;
+    constexpr int M2 = (2 * P + 15) / 16 * 16, N2 = M2, T2 = (M2 / 16) * (N2 / 16);
+    constexpr int LD1 = K1 + 8, LD2 = K2 + 8;  // 16-bit row strides (16-byte aligned rows)
+    static_assert(N1 % 16 == 0 && K2 % 32 == 0, "2-D tile shapes");
+    static_assert(T2 <= 4, "one stage-2 tile per wave");
+    const int n_m = 2 * P;
+
+    __shared__ double Wv[J][J + 1];
+    __shared__ __attribute__((aligned(16))) uint16_t Ds[NS][M1][LD1];
+    __shared__ __attribute__((aligned(16))) uint16_t Tt[NS][N2][LD2];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    // hi / lo 16-bit bits of a double (lo: the rounding remainder, exact in FP64)
+    auto split16 = [&](double v, uint16_t* hi, uint16_t* lo) {
+        const uint32_t h = pack16<HALF>(v, 0.0) & 0xFFFFu;
+        *hi = (uint16_t)h;
+        if constexpr (SPLIT) *lo = (uint16_t)(pack16<HALF>(v - value16<HALF>(h), 0.0) & 0xFFFFu);
+    };
+    // stage-1 B operand: lane holds B1[jx = 32 ks + 8 lk + i][n = 16 nt + lr], i < 8
+    s16x8 b1[NT1W][KS1][NS];
+#pragma unroll
+    for (int q = 0; q < NT1W; ++q) {
+        const int nt = wave + 4 * q;
+#pragma unroll
+        for (int ks = 0; ks < KS1; ++ks) {
+            uint16_t h[8], l[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int jxi = 32 * ks + 8 * lk + i, n = nt * 16 + lr;
+                double v = 0.0;
+                if (nt < NT1 && jxi < J) {
+                    const int jx = jxi - P, mx = (n < 2 * P ? n : n - 2 * P) - P;
+                    const double w = w_end(jx, P);
+                    v = n < 2 * P ? w * sin_2pi_ratio((long)mx * jx, n_m) : w * cos_2pi_ratio((long)mx * jx, n_m);
+                }
+                split16(v, &h[i], &l[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                b1[q][ks][0][i] = (short)h[i];
+                if constexpr (SPLIT) b1[q][ks][NS - 1][i] = (short)l[i];
+            }
+        }
+    }
+    // stage-2 A operand: lane holds A2[my = 16 tm2 + lr][k = 32 ks + 8 lk + i], k = part M1 + jy
+    const int tm2 = wave / (N2 / 16), tn2 = wave % (N2 / 16);
+    s16x8 a2[KS2][NS];
+#pragma unroll
+    for (int ks = 0; ks < KS2; ++ks) {
+        uint16_t h[8], l[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = 32 * ks + 8 * lk + i, my_i = tm2 * 16 + lr;
+            const int part = k / M1, jyi = k - part * M1;
+            double v = 0.0;
+            if (wave < T2 && my_i < 2 * P && jyi < J) {
+                const int my = my_i - P, jy = jyi - P;
+                const double w = w_end(jy, P);
+                v = part == 0 ? w * cos_2pi_ratio((long)my * jy, n_m) : w * sin_2pi_ratio((long)my * jy, n_m);
+            }
+            split16(v, &h[i], &l[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            a2[ks][0][i] = (short)h[i];
+            if constexpr (SPLIT) a2[ks][NS - 1][i] = (short)l[i];
+        }
+    }
+    // padding of the transposed tile (columns mx >= 2P) stays zero
+    for (int e = threadIdx.x; e < NS * N2 * LD2; e += KE_THREADS) (&Tt[0][0][0])[e] = 0;
+
+    for (long r = blockIdx.x; r < R; r += gridDim.x) {
+        const long b = r / n_cells;
+        const int ci = (int)(r - b * n_cells);
+        int cell = cells ? cells[ci] : ci;
+        const bool bad = cell < 0 || cell >= nx * ny;
+        if (bad) cell = 0;
+        const int cx = cell % nx, cy = cell / nx;
+        const double* Vb = V + b * (long)nx * ny;
+        __syncthreads();  // previous cell's LDS use is over
+        for (int e = threadIdx.x; e < J * J; e += KE_THREADS) {
+            const int ty = e / J, tx = e - ty * J;
+            const int yy = min(max(cy - P + ty, 0), ny - 1), xx = min(max(cx - P + tx, 0), nx - 1);
+            Wv[ty][tx] = Vb[(long)yy * nx + xx];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < M1 * K1; e += KE_THREADS) {
+            const int jyi = e / K1, jxi = e - jyi * K1;
+            double d = 0.0;
+            if (jyi < J && jxi < J) d = Wv[jyi][jxi] - Wv[J - 1 - jyi][J - 1 - jxi];
+            if (bad) d = __builtin_nan("");
+            uint16_t h, l = 0;
+            split16(d, &h, &l);
+            Ds[0][jyi][jxi] = h;
+            if constexpr (SPLIT) Ds[NS - 1][jyi][jxi] = l;
+        }
+        __syncthreads();
+        // stage 1 -> Tt (rounded to 16 bits, transposed)
+#pragma unroll
+        for (int q = 0; q < NT1W; ++q) {
+            const int nt = wave + 4 * q;
+            if (nt >= NT1) continue;
+#pragma unroll
+            for (int mt = 0; mt < MT1; ++mt) {
+                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < KS1; ++ks) {
+                    const s16x8 ah = *reinterpret_cast<const s16x8*>(&Ds[0][mt * 16 + lr][32 * ks + 8 * lk]);
+                    acc = mfma16<HALF>(ah, b1[q][ks][0], acc);
+                    if constexpr (SPLIT) {
+                        const s16x8 al = *reinterpret_cast<const s16x8*>(&Ds[NS - 1][mt * 16 + lr][32 * ks + 8 * lk]);
+                        acc = mfma16<HALF>(ah, b1[q][ks][NS - 1], acc);
+                        acc = mfma16<HALF>(al, b1[q][ks][0], acc);
+                    }
+                }
+                const int n = nt * 16 + lr, part = n < 2 * P ? 0 : 1, mx = n - part * 2 * P;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int jy = mt * 16 + 4 * lk + e;
+                    uint16_t h, l = 0;
+                    split16((double)acc[e], &h, &l);
+                    Tt[0][mx][part * M1 + jy] = h;
+                    if constexpr (SPLIT) Tt[NS - 1][mx][part * M1 + jy] = l;
+                }
+            }
+        }
+        __syncthreads();
+        if (wave < T2) {
+            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KS2; ++ks) {
+                const s16x8 bh = *reinterpret_cast<const s16x8*>(&Tt[0][tn2 * 16 + lr][32 * ks + 8 * lk]);
+                acc = mfma16<HALF>(a2[ks][0], bh, acc);
+                if constexpr (SPLIT) {
+                    const s16x8 bl = *reinterpret_cast<const s16x8*>(&Tt[NS - 1][tn2 * 16 + lr][32 * ks + 8 * lk]);
+                    acc = mfma16<HALF>(a2[ks][0], bl, acc);
+                    acc = mfma16<HALF>(a2[ks][NS - 1], bh, acc);
+                }
+            }
+            const int mx_i = tn2 * 16 + lr;
+            float* o = out + r * (long)n_m * n_m;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int my_i = tm2 * 16 + 4 * lk + e;
+                if (my_i < 2 * P && mx_i < 2 * P) o[my_i * n_m + mx_i] = c2 * acc[e];
+            }
+        }
+    }
+}
+
+template <int PREC>
+static int launch_2d_lowp(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
+                          float* out, hipStream_t stream) {
+    const long R = (long)B * n_cells;
+    if (R == 0) return WK_OK;
+    const float c2 = (float)(-1.0 / (mesh->hbar * (double)mesh->n_m * (double)mesh->n_m));
+    const unsigned grid = (unsigned)(R < 4096 ? R : 4096);
+    switch (mesh->n_m) {
+        case 8:
+            WK_LAUNCH("kernel_eval_2d_lowp", (kernel_eval_2d_lowp<4, PREC>), dim3(grid), dim3(KE_THREADS), 0,
+                      stream, V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            break;
+        case 16:
+            WK_LAUNCH("kernel_eval_2d_lowp", (kernel_eval_2d_lowp<8, PREC>), dim3(grid), dim3(KE_THREADS), 0,
+                      stream, V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            break;
+        case 32:
+            WK_LAUNCH("kernel_eval_2d_lowp", (kernel_eval_2d_lowp<16, PREC>), dim3(grid), dim3(KE_THREADS), 0,
+                      stream, V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            break;
+        default:
+            return fail(WK_EINVAL, "wk_kernel_eval: 2-D supports n_m = 8, 16 and 32");
+    }
+    return check_launch("kernel_eval_2d_lowp");
+}
+
+int kernel_eval_2d_16(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
+                      int prec, float* out, hipStream_t stream) {
+    switch (prec) {
+        case WK_BF16: return launch_2d_lowp<WK_BF16>(mesh, V, B, cells, n_cells, out, stream);
+        case WK_FP16: return launch_2d_lowp<WK_FP16>(mesh, V, B, cells, n_cells, out, stream);
+        case WK_BF16X3: return launch_2d_lowp<WK_BF16X3>(mesh, V, B, cells, n_cells, out, stream);
+        case WK_FP16X3: return launch_2d_lowp<WK_FP16X3>(mesh, V, B, cells, n_cells, out, stream);
+        default: return fail(WK_EINVAL, "wk_kernel_eval: unknown precision");
     }
 }
 

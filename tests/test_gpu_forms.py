@@ -303,3 +303,67 @@ def test_surrogate_driven_run_vs_exact():
     xc = (np.arange(cfg.mesh.nx) + 0.5) * cfg.mesh.dx
     assert abs((rs * xc).sum() / rs.sum() - (rx * xc).sum() / rx.sum()) < 8.0
     assert np.abs(rs - rx).sum() < 0.35
+
+
+# ----------------------------------------------------------------------------- 2-D, 16-bit
+# Rounding units of the two 16-bit formats; a split (hi, lo) operand carries the value to
+# within about u^2.
+U16 = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11, "bf16x3": 2.0 ** -8, "fp16x3": 2.0 ** -11}
+LOWP2D_TOL = {"bf16": 2e-2, "fp16": 3e-3, "bf16x3": 1e-4, "fp16x3": 2e-5}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("nx,ny,n_m", [(20, 18, 8), (24, 21, 16), (256, 256, 32)])
+def test_2d_lowp_kernel_error_bounds(orc, prec, nx, ny, n_m):
+    """The d = 2 kernel with 16-bit operands against the oracle's direct FP64 sum.  Per entry:
+    each product of the two stages has |trig| <= 1 and weights <= 1, so every partial sum is
+    at most sum_j |D_j| over the window (twice, sine and cosine parts), and the error is at most
+    2 |c2| sum_j |D_j| (e + (K1 + K2) u32) with e = 6u for one pass (D, trig and the stage-1
+    result rounded, two products) and 6u^2 + 2 u32 for the split forms, plus the underflow of
+    the rounded operands below the format's smallest normal.  Normwise: the stated
+    tolerances.  Sampled cells on the 2-D workload's mesh (with the dot), all cells on the small
+    meshes, both mesh edges included."""
+    mesh = inputs.Mesh2D(nx=nx, ny=ny, dx=0.5, n_m=n_m, pos_f64=False)
+    if nx == 256:
+        V = inputs.gaussian_dot_2d(mesh, 0.2, 4.0, 64.0, 64.0)[None]
+        rng = np.random.default_rng(3)
+        cy, cx = rng.integers(100, 156, 40), rng.integers(100, 156, 40)   # near the dot
+        cells = np.concatenate([cy * nx + cx, [0, nx - 1, nx * ny - 1, (ny // 2) * nx + nx // 2 - 9],
+                                rng.integers(0, nx * ny, 20)]).astype(np.int32)
+    else:
+        V = np.stack([inputs.gaussian_dot_2d(mesh, 0.3, 1.5, 4.0 + 2 * b, 5.0) for b in range(2)])
+        cells = None
+    ref = orc.kernel_2d(V, n_m, HB, cells=cells)
+    got = to_np(ops.kernel_eval(torch.from_numpy(V).to(dev()), n_m, cells=None if cells is None else
+                                torch.from_numpy(cells).to(dev()), prec=prec)).astype(np.float64)
+    B = V.shape[0]
+    ref = ref.reshape(B, -1, n_m, n_m)
+    got = got.reshape(ref.shape)
+    err = normwise(got, ref)
+    # per-entry bound from the window's absolute differences
+    P = n_m // 2
+    u, u32 = U16[prec], 2.0 ** -24
+    e = (6 * u * u + 2 * u32) if prec.endswith("x3") else 6 * u
+    J = 2 * P + 1
+    K1, K2 = -(-J // 32) * 32, 2 * (-(-J // 16) * 16)
+    c2 = 1.0 / (HB * n_m * n_m)
+    # underflow: a rounded operand is v (1 + delta) + eta, |eta| below the format's smallest
+    # normal; D is rounded (hi and lo) in J^2 entries used by both trig parts, the stage-1
+    # result (hi and lo) in K2 entries
+    eta = ETA_IN["bf16" if prec.startswith("bf16") else "fp16"]
+    under = c2 * eta * (4 * J * J + 2 * K2)
+    worst = 0.0
+    ids = np.arange(nx * ny) if cells is None else cells
+    for b in range(B):
+        for r, cid in enumerate(ids):
+            iy, ix = divmod(int(cid), nx)
+            yy = np.clip(iy + np.arange(-P, P + 1), 0, ny - 1)
+            xx = np.clip(ix + np.arange(-P, P + 1), 0, nx - 1)
+            yym = np.clip(iy - np.arange(-P, P + 1), 0, ny - 1)
+            xxm = np.clip(ix - np.arange(-P, P + 1), 0, nx - 1)
+            D = V[b][np.ix_(yy, xx)] - V[b][np.ix_(yym, xxm)]
+            bound = 2 * c2 * np.abs(D).sum() * (e + (K1 + K2) * u32) + under + 1e-300
+            worst = max(worst, np.abs(got[b, r] - ref[b, r]).max() / bound)
+    print(f"2-D {prec} n_m={n_m}: normwise {err:.3e}, worst error / per-entry bound {worst:.3f}")
+    assert worst <= 1.0
+    assert err <= LOWP2D_TOL[prec]
