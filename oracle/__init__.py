@@ -21,6 +21,8 @@ Parity status (see the tests for each pin):
   surrogate_fwd .................. pinned (N=1 equals eq.(4); N=2 equals the
                                    barycentric form of Sec. 2.3)
   surrogate_bwd .................. pinned (finite differences in high precision)
+  surrogate_fwd_2d ............... pinned (N = 1 equals the d = 2 kernel; a potential of x
+                                   alone gives the 1-D network on the my = 0 row, 0 elsewhere)
   mse_grad, sgd_step ............. pinned (finite differences of the loss, first-order
                                    descent prediction, fixed point at zero residual)
 """
@@ -87,6 +89,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_surrogate_fwd.restype = i32
         L.oracle_surrogate_bwd.argtypes = [i32, i32, i32, P, P, P, P, i32, P, i32, P, P, P, P, P]
         L.oracle_surrogate_bwd.restype = i32
+        L.oracle_surrogate_fwd_2d.argtypes = [i32, i32, i32, i32, P, P, P, P, P, i32, P, i32, P]
+        L.oracle_surrogate_fwd_2d.restype = i32
         L.oracle_mse_grad.argtypes = [P, P, i64, f64, P]
         L.oracle_mse_grad.restype = f64
         L.oracle_sgd_step.argtypes = [i32, i32, i32, f64, P, i32, P, f64, f64, f64, f64, P, P, P]
@@ -335,6 +339,27 @@ def surrogate_bwd(V, n_m: int, N: int, wV, wT, W, E, cells=None, want_dV: bool =
     _check(lib().oracle_surrogate_bwd(nx, n_m, N, _p(wV), _p(wT), _p(W), _p(V), B, _p(c), nc,
                                       _p(E), _p(dwV), _p(dwT), _p(dW), _p(dV)), "surrogate_bwd")
     return dwV, dwT, dW, dV
+
+
+def surrogate_fwd_2d(V, n_m: int, N: int, wV, wTx, wTy, W, cells=None) -> np.ndarray:
+    """eq.(5) in d = 2: full table [B][n_cells][n_m(y)][n_m(x)]."""
+    V = _f64(V)
+    if V.ndim == 2:
+        V = V[None]
+    B, ny, nx = V.shape
+    c = _cells(cells)
+    nc = nx * ny if c is None else len(c)
+    wV, wTx, wTy, W = _f64(wV), _f64(wTx), _f64(wTy), _f64(W)
+    Kh = np.empty((B, nc, n_m, n_m))
+    _check(lib().oracle_surrogate_fwd_2d(nx, ny, n_m, N, _p(wV), _p(wTx), _p(wTy), _p(W), _p(V), B, _p(c), nc,
+                                         _p(Kh)), "surrogate_fwd_2d")
+    return Kh
+
+
+def analytic_weights_2d(n_m: int, N: int, hbar: float):
+    """wV = 1 (N x N), wTx = wTy = 1/N, W = -2/(hbar n_m^2) ((n_m/N)^2 groups)."""
+    H = n_m // N
+    return (np.ones(N * N), np.full(N, 1.0 / N), np.full(N, 1.0 / N), np.full(H * H, -2.0 / (hbar * n_m * n_m)))
 
 
 def analytic_weights(n_m: int, N: int, hbar: float):

@@ -755,3 +755,68 @@ int64_t oracle_sp_annihilate_pairs(int dim, int nx, int ny, int n_k, int M_min, 
     stats[ORACLE_ST_MIXED] = mixed;
     return o;
 }
+
+/* ---------------------------------------------------------------- surrogate, d = 2 */
+/* eq.(5) carried to d = 2 (the d-dimensional statement of Sec. 2.1): the offsets o of a cell's
+ * window on the periodic grid, o_a in [-P, P) per axis, are grouped N x N, g = (gx, gy),
+ * o(g, p) = (-P + N gx + px, -P + N gy + py);
+ *   Kh(i; mx, my) = prod_s cos(2^s pi mx / n_m) prod_s cos(2^s pi my / n_m)
+ *                   * sum_g W[gy H + gx] (sum_p wV[py N + px] Vt(i, o(g, p)))
+ *                     * sin(ux(gx) mx + uy(gy) my),
+ *   ux(gx) = (2 pi / n_m) sum_px wTx[px] (-P + N gx + px), uy likewise with wTy,
+ * where Vt(i, o) = V(i + o) except at an end point o_a = -P of the periodic grid, where it is
+ * the mean of V at i_a - P and i_a + P (both ends, per axis): the trapezoid half weights of
+ * the d = 2 kernel.  With wV = 1, wT = 1/N, W = -2/(hbar n_m^2), N = 1 is that kernel
+ * exactly.  Full table [B][n_cells][n_m][n_m] (ty, tx), (mx, my) = (tx - P, ty - P). */
+static double vt2(const double* Vb, int nx, int ny, long ix, long iy, long ox, long oy, int P) {
+    const int ex = ox == -P, ey = oy == -P;
+    double s = 0.0;
+    int k = 0;
+    for (int a = 0; a <= ex; ++a)
+        for (int b = 0; b <= ey; ++b) {
+            const long dx = a ? P : ox, dy = b ? P : oy;
+            s += v2(Vb, nx, ny, ix + dx, iy + dy);
+            ++k;
+        }
+    return s / (double)k;
+}
+
+int oracle_surrogate_fwd_2d(int nx, int ny, int n_m, int N, const double* wV, const double* wTx,
+                            const double* wTy, const double* W, const double* V, int B,
+                            const int32_t* cells, int n_cells, double* Kh) {
+    const int L = log2_exact(N);
+    if (nx <= 0 || ny <= 0 || n_m <= 0 || (n_m & 1) || N <= 0 || L < 0 || n_m % N || B < 0) return -1;
+    const int P = n_m / 2, H = n_m / N;
+    const long ncell = (long)nx * ny;
+    for (int b = 0; b < B; ++b) {
+        const double* Vb = V + (long)b * ncell;
+        for (int r = 0; r < n_cells; ++r) {
+            const long cid = cells ? cells[r] : r;
+            if (cid < 0 || cid >= ncell) return -1;
+            const long ix = cid % nx, iy = cid / nx;
+            double* row = Kh + ((long)b * n_cells + r) * (long)n_m * n_m;
+            for (int ty = 0; ty < n_m; ++ty) {
+                for (int tx = 0; tx < n_m; ++tx) {
+                    const long mx = tx - P, my = ty - P;
+                    double acc = 0.0;
+                    for (int gy = 0; gy < H; ++gy) {
+                        for (int gx = 0; gx < H; ++gx) {
+                            double fV = 0.0, ux = 0.0, uy = 0.0;
+                            for (int py = 0; py < N; ++py)
+                                for (int px = 0; px < N; ++px)
+                                    fV += wV[py * N + px] * vt2(Vb, nx, ny, ix, iy, -P + (long)N * gx + px,
+                                                                -P + (long)N * gy + py, P);
+                            for (int p = 0; p < N; ++p) {
+                                ux += wTx[p] * (TWO_PI * (double)(-P + N * gx + p) / (double)n_m);
+                                uy += wTy[p] * (TWO_PI * (double)(-P + N * gy + p) / (double)n_m);
+                            }
+                            acc += W[gy * H + gx] * fV * sin(ux * (double)mx + uy * (double)my);
+                        }
+                    }
+                    row[(long)ty * n_m + tx] = cos_prefactor(L, mx, n_m) * cos_prefactor(L, my, n_m) * acc;
+                }
+            }
+        }
+    }
+    return 0;
+}

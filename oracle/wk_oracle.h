@@ -90,6 +90,14 @@ int oracle_surrogate_bwd(int nx, int n_m, int N, const double* wV, const double*
                          int n_cells, const double* E, double* dwV, double* dwT, double* dW,
                          double* dV);
 
+/* eq.(5) in d = 2: offsets grouped N x N, angle weights per axis (wTx, wTy [N]), wV [N*N],
+ * W [(n_m/N)^2]; the window value at an end point -P of the periodic grid is the mean of the
+ * two end values (N = 1 with analytic weights is the d = 2 kernel).  Full table
+ * [B][n_cells][n_m][n_m]. */
+int oracle_surrogate_fwd_2d(int nx, int ny, int n_m, int N, const double* wV, const double* wTx,
+                            const double* wTy, const double* W, const double* V, int B,
+                            const int32_t* cells, int n_cells, double* Kh);
+
 /* Training of Sec. 3.  MSE on targets scaled by inv_scale; returns the loss and writes
  * E = dloss/dKh (E may be NULL). */
 double oracle_mse_grad(const double* Kh, const double* K, int64_t count, double inv_scale,

@@ -119,3 +119,57 @@ def test_barycentric_weights_near_least_squares_optimum(orc):
     rms = lambda w: np.sqrt(np.mean((Fte @ w - Kte) ** 2) / np.mean(Kte ** 2))
     assert rms(Wopt) > 0.99 * rms(W)
     assert rms(W) < 0.15
+
+
+# ----------------------------------------------------------------------------- d = 2
+def _v2(seed, nx, ny):
+    rng = np.random.default_rng(seed)
+    x = (np.arange(nx) + 0.5) * 0.5
+    y = (np.arange(ny) + 0.5) * 0.5
+    V = np.zeros((ny, nx))
+    for _ in range(3):
+        cx, cy, h, s = rng.uniform(0, nx * 0.5), rng.uniform(0, ny * 0.5), rng.uniform(0, 0.4), rng.uniform(1, 3)
+        V += h * np.exp(-((x[None] - cx) ** 2 + (y[:, None] - cy) ** 2) / (2 * s * s))
+    return V
+
+
+@pytest.mark.parametrize("n_m", [4, 8, 16])
+def test_surrogate_2d_n1_is_the_2d_kernel(orc, n_m):
+    """With N = 1 and the analytic weights the d = 2 network is the d = 2 kernel of eq.(4)
+    (pinned independently by brute force and by its reduction to 1-D), on every cell of a mesh
+    smaller than the window (both edge clampings and the end-point means in play)."""
+    nx, ny = 13, 9
+    V = _v2(1, nx, ny)
+    ref = orc.kernel_2d(V, n_m, HB)
+    got = orc.surrogate_fwd_2d(V, n_m, 1, *orc.analytic_weights_2d(n_m, 1, HB))
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_surrogate_2d_reduces_to_1d_for_a_potential_of_x(orc, N):
+    """V(x, y) = V1(x): the my = 0 row is the 1-D network of eq.(5) (pinned against eq.(4) and
+    the barycentric form) evaluated with the end-point mean in the window, and every other row
+    vanishes (the sum over gy of the phases cancels or the cos prefactor is 0)."""
+    n_m, nx, ny = 16, 30, 7
+    P = n_m // 2
+    rng = np.random.default_rng(N)
+    V1 = rng.uniform(0, 0.3, nx)
+    V = np.tile(V1, (ny, 1))
+    wV1, wT1, W1 = rng.normal(1, 0.1, N), rng.normal(1.0 / N, 0.02, N), rng.normal(-2 / (HB * n_m), 1e-3, n_m // N)
+    H = n_m // N
+    # 2-D weights that reduce to the 1-D ones: wV(px, py) = wV1(px) / N, W(gx, gy) = W1(gx) / H
+    wV2 = np.tile(wV1 / N, N)
+    W2 = np.tile(W1 / H, H)
+    cells = np.array([P, 15, nx - 1 - P, 2 * nx + 11, 5 * nx + 19], dtype=np.int32)  # interior in x
+    got = orc.surrogate_fwd_2d(V, n_m, N, wV2, wT1, np.full(N, 1.0 / N), W2, cells=cells)[0]
+    for r, cid in enumerate(cells):
+        ix = int(cid) % nx
+        # the 1-D window of this cell with the end point -P holding the mean of both ends
+        Vc = V1.copy()
+        Vc[ix - P] = 0.5 * (V1[ix - P] + V1[ix + P])
+        full1 = orc.half_to_full(orc.surrogate_fwd(Vc[None], n_m, N, wV1, wT1, W1,
+                                                   cells=np.array([ix], np.int32))[0])[0]
+        row0 = got[r, P]          # my = 0
+        assert np.abs(row0 - full1).max() <= 1e-12 * np.abs(full1).max()
+        others = np.delete(got[r], P, axis=0)
+        assert np.abs(others).max() <= 1e-12 * np.abs(full1).max()
