@@ -348,6 +348,21 @@ int wk_surrogate_fwd_static(const wk_mesh* mesh, int32_t N, const float* wV, con
                             const float* W, const double* V, int32_t B, const int32_t* cells,
                             int32_t n_cells, int32_t prec, void* K_out, void* stream);
 
+/* wk_surrogate_fwd_2d -- eq.(5) in d = 2 (FP64, forward only): the window of a cell on the
+ * periodic grid (offsets o_a in [-P, P) per axis; at the end point -P the mean of the two
+ * end values, where the d = 2 kernel of wk_kernel_eval has its half weights), grouped N x N:
+ *   Kh(i; mx, my) = prod_s cos(2^s pi mx / n_m) prod_s cos(2^s pi my / n_m)
+ *                   * sum_g W[gy H + gx] (sum_p wV[py N + px] Vt(i + o(g, p)))
+ *                     * sin(ux(gx) mx + uy(gy) my),
+ *   o(g, p) = (-P + N gx + px, -P + N gy + py), ux(gx) = (2 pi / n_m) sum_p wTx[p] (-P + N gx + p)
+ *   (uy likewise with wTy), H = n_m / N.
+ * With wV = 1, wT = 1/N, W = -2/(hbar n_m^2), N = 1 is the d = 2 kernel exactly.
+ *   n_m in {8, 16, 32}; N in {1, 2, 4, 8}, N < n_m; wV [N*N], wTx, wTy [N], W [H*H] float.
+ *   K_out [B * n_cells][n_m][n_m] double, (mx, my) = (tx - P, ty - P). */
+int wk_surrogate_fwd_2d(const wk_mesh* mesh, int32_t N, const float* wV, const float* wTx,
+                        const float* wTy, const float* W, const double* V, int32_t B,
+                        const int32_t* cells, int32_t n_cells, double* K_out, void* stream);
+
 /* wk_surrogate_bwd -- gradients of L = sum E * Kh with respect to wV, wT, W (written,
  * float) and V (accumulated into dV [B][nx] double, may be NULL); E [B*n_cells][P] float.
  * Deterministic two-level reductions.  ws: wk_surrogate_workspace() bytes. */

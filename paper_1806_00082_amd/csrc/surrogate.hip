@@ -1119,6 +1119,202 @@ extern "C" int wk_sgd_update(float* w, const float* grad, int32_t n, float lr, v
     return check_launch("wk_sgd_update");
 }
 
+// ----------------------------------------------------------------------------- d = 2 forward
+// eq.(5) in d = 2: the window of a cell on the periodic grid (o_a in [-P, P), the end point -P
+// holding the mean of the two end values, where the d = 2 kernel has its half weights) grouped
+// N x N; G[gy][gx] = W[g] sum_p wV[p] Vt(o(g, p)) is contracted like the d = 2 kernel, with
+// sin(ux mx + uy my) = sin(ux mx) cos(uy my) + cos(ux mx) sin(uy my):
+//   stage 1  T[gy][n] = sum_gx G[gy][gx] Bx[gx][n],  Bx = [sin(ux mx) | cos(ux mx)]
+//   stage 2  Kh[my][mx] = Pi(mx) Pi(my) sum_k A2[my][k] T'[k][mx],  A2 = [cos(uy my) | sin(uy my)],
+// both on v_mfma_f64_16x16x4; the trig operands depend on the weights and the lane only and are
+// formed once per workgroup; workgroups loop over the requested cells.
+namespace wk {
+__device__ __forceinline__ double prefactor2(int L, int m, int n_m) {
+    double pr = 1.0;
+    for (int s = 0; s < L; ++s) pr *= cospi((double)(1 << s) * (double)m / (double)n_m);
+    return pr;
+}
+
+template <int P, int N>
+__global__ __launch_bounds__(256) void surr_fwd_2d_f64(
+    const double* __restrict__ V, int nx, int ny, long R, int n_cells, const int32_t* __restrict__ cells,
+    const float* __restrict__ wV, const float* __restrict__ wTx, const float* __restrict__ wTy,
+    const float* __restrict__ W, double* __restrict__ out) {
+    constexpr int n_m = 2 * P, H = n_m / N, J = 2 * P + 1;
+    constexpr int M1 = (H + 15) / 16 * 16, K1 = (H + 3) / 4 * 4, N1 = 2 * n_m;
+    constexpr int NT1 = N1 / 16, MT1 = M1 / 16, NT1W = (NT1 + 3) / 4;
+    constexpr int M2 = (n_m + 15) / 16 * 16, N2 = M2, K2 = 2 * K1, T2 = (M2 / 16) * (N2 / 16);
+    static_assert(T2 <= 4, "one stage-2 tile per wave");
+    int L = 0;
+    while ((1 << L) < N) ++L;
+
+    __shared__ double Wv[J][J + 1];
+    __shared__ double Gs[M1][K1 + 1];
+    __shared__ double Ts[K2][N2 + 1];
+    __shared__ double ux[H], uy[H];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int g = threadIdx.x; g < H; g += 256) {
+        double a = 0.0, b = 0.0;
+        for (int p = 0; p < N; ++p) {
+            a += (double)wTx[p] * (two_pi * (double)(-P + N * g + p) / (double)n_m);
+            b += (double)wTy[p] * (two_pi * (double)(-P + N * g + p) / (double)n_m);
+        }
+        ux[g] = a;
+        uy[g] = b;
+    }
+    for (int e = threadIdx.x; e < K2 * (N2 + 1); e += 256) (&Ts[0][0])[e] = 0.0;
+    __syncthreads();
+    double b1[NT1W][K1 / 4];
+#pragma unroll
+    for (int q = 0; q < NT1W; ++q) {
+        const int nt = wave + 4 * q;
+#pragma unroll
+        for (int ks = 0; ks < K1 / 4; ++ks) {
+            const int gx = 4 * ks + lk, n = nt * 16 + lr;
+            double v = 0.0;
+            if (nt < NT1 && gx < H) {
+                const int mx = (n < n_m ? n : n - n_m) - P;
+                v = n < n_m ? sin(ux[gx] * (double)mx) : cos(ux[gx] * (double)mx);
+            }
+            b1[q][ks] = v;
+        }
+    }
+    const int tm2 = wave / (N2 / 16), tn2 = wave % (N2 / 16);
+    double a2[K2 / 4];
+#pragma unroll
+    for (int ks = 0; ks < K2 / 4; ++ks) {
+        const int k = 4 * ks + lk, my_i = tm2 * 16 + lr;
+        double v = 0.0;
+        if (wave < T2 && my_i < n_m) {
+            const int my = my_i - P, gy = k < K1 ? k : k - K1;
+            if (gy < H) v = k < K1 ? cos(uy[gy] * (double)my) : sin(uy[gy] * (double)my);
+        }
+        a2[ks] = v;
+    }
+    for (long r = blockIdx.x; r < R; r += gridDim.x) {
+        const long b = r / n_cells;
+        const int ci = (int)(r - b * n_cells);
+        int cell = cells ? cells[ci] : ci;
+        const bool bad = cell < 0 || cell >= nx * ny;
+        if (bad) cell = 0;
+        const int cx = cell % nx, cy = cell / nx;
+        const double* Vb = V + b * (long)nx * ny;
+        __syncthreads();  // previous cell's LDS use is over
+        for (int e = threadIdx.x; e < J * J; e += 256) {
+            const int ty = e / J, tx = e - ty * J;
+            const int yy = min(max(cy - P + ty, 0), ny - 1), xx = min(max(cx - P + tx, 0), nx - 1);
+            Wv[ty][tx] = Vb[(long)yy * nx + xx];
+        }
+        __syncthreads();
+        // G = W * (grouped, weighted window); window index o + P, the end point -P (index 0)
+        // holds the mean with index 2P along that axis
+        for (int e = threadIdx.x; e < M1 * K1; e += 256) {
+            const int gy = e / K1, gx = e - gy * K1;
+            double gv = 0.0;
+            if (gy < H && gx < H) {
+                double acc = 0.0;
+                for (int py = 0; py < N; ++py) {
+                    const int oy = N * gy + py;
+                    for (int px = 0; px < N; ++px) {
+                        const int ox = N * gx + px;
+                        double v;
+                        if (ox == 0 && oy == 0)
+                            v = 0.25 * (((Wv[0][0] + Wv[0][2 * P]) + Wv[2 * P][0]) + Wv[2 * P][2 * P]);
+                        else if (ox == 0)
+                            v = 0.5 * (Wv[oy][0] + Wv[oy][2 * P]);
+                        else if (oy == 0)
+                            v = 0.5 * (Wv[0][ox] + Wv[2 * P][ox]);
+                        else
+                            v = Wv[oy][ox];
+                        acc += (double)wV[py * N + px] * v;
+                    }
+                }
+                gv = (double)W[gy * H + gx] * acc;
+            }
+            Gs[gy][gx] = bad ? __builtin_nan("") : gv;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NT1W; ++q) {
+            const int nt = wave + 4 * q;
+            if (nt >= NT1) continue;
+#pragma unroll
+            for (int mt = 0; mt < MT1; ++mt) {
+                f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < K1 / 4; ++ks)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Gs[mt * 16 + lr][4 * ks + lk], b1[q][ks], acc, 0, 0, 0);
+                const int n = nt * 16 + lr;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int gy = mt * 16 + lk + 4 * e;
+                    if (gy >= K1) continue;
+                    if (n < n_m)
+                        Ts[gy][n] = acc[e];
+                    else
+                        Ts[K1 + gy][n - n_m] = acc[e];
+                }
+            }
+        }
+        __syncthreads();
+        if (wave < T2) {
+            f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+            const int mx_i = tn2 * 16 + lr;
+#pragma unroll
+            for (int ks = 0; ks < K2 / 4; ++ks)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[ks], Ts[4 * ks + lk][mx_i], acc, 0, 0, 0);
+            double* o = out + r * (long)n_m * n_m;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int my_i = tm2 * 16 + lk + 4 * e;
+                if (my_i < n_m && mx_i < n_m)
+                    o[my_i * n_m + mx_i] = prefactor2(L, mx_i - P, n_m) * prefactor2(L, my_i - P, n_m) * acc[e];
+            }
+        }
+    }
+}
+}  // namespace wk
+
+extern "C" int wk_surrogate_fwd_2d(const wk_mesh* mesh, int32_t N, const float* wV, const float* wTx,
+                                   const float* wTy, const float* W, const double* V, int32_t B,
+                                   const int32_t* cells, int32_t n_cells, double* K_out, void* stream) {
+    WK_REQUIRE(mesh && mesh->dim == 2 && mesh->nx > 0 && mesh->ny > 0, "wk_surrogate_fwd_2d: 2-D mesh needed");
+    WK_REQUIRE(mesh->n_m == 8 || mesh->n_m == 16 || mesh->n_m == 32,
+               "wk_surrogate_fwd_2d: n_m must be 8, 16 or 32");
+    WK_REQUIRE(N >= 1 && (N & (N - 1)) == 0 && N <= 8 && N < mesh->n_m,
+               "wk_surrogate_fwd_2d: N must be 1, 2, 4 or 8 and below n_m");
+    WK_REQUIRE(B >= 0 && n_cells >= 0, "wk_surrogate_fwd_2d: negative size");
+    if ((long)B * n_cells == 0) return WK_OK;
+    WK_REQUIRE(cells != nullptr || n_cells == mesh->nx * mesh->ny,
+               "wk_surrogate_fwd_2d: with cells == NULL, n_cells must be the number of cells");
+    WK_REQUIRE(wV && wTx && wTy && W && V && K_out, "wk_surrogate_fwd_2d: NULL array");
+    const long R = (long)B * n_cells;
+    const unsigned grid = (unsigned)(R < 4096 ? R : 4096);
+    hipStream_t s = as_stream(stream);
+#define S2D(PP, NN)                                                                                       \
+    WK_LAUNCH("surr_fwd_2d_f64", (surr_fwd_2d_f64<PP, NN>), dim3(grid), dim3(256), 0, s, V, mesh->nx,    \
+              mesh->ny, R, n_cells, cells, wV, wTx, wTy, W, K_out)
+#define S2D_N(PP)            \
+    switch (N) {             \
+        case 1: S2D(PP, 1); break; \
+        case 2: S2D(PP, 2); break; \
+        case 4: S2D(PP, 4); break; \
+        default: S2D(PP, 8); break; \
+    }
+    if (mesh->n_m == 8) {
+        S2D_N(4)
+    } else if (mesh->n_m == 16) {
+        S2D_N(8)
+    } else {
+        S2D_N(16)
+    }
+#undef S2D_N
+#undef S2D
+    return check_launch("wk_surrogate_fwd_2d");
+}
+
 // ----------------------------------------------------------------------------- no-alloc forward
 // Scratch of wk_surrogate_fwd_static: one file-scope device array per GPU.  In host code the
 // array's name is a host-side stand-in, not a device address; the kernels only ever receive

@@ -68,6 +68,31 @@ def surrogate_fwd(V, n_m: int, N: int, wV, wT, W, cells=None, prec: str = "fp32"
     return out
 
 
+def analytic_weights_2d(n_m: int, N: int, hbar: float = HBAR_EVFS, device="cuda"):
+    """wV = 1 (N x N), wTx = wTy = 1/N, W = -2/(hbar n_m^2): the d = 2 kernel for N = 1."""
+    H = n_m // N
+    return (torch.ones(N * N, dtype=torch.float32, device=device),
+            torch.full((N,), 1.0 / N, dtype=torch.float32, device=device),
+            torch.full((N,), 1.0 / N, dtype=torch.float32, device=device),
+            torch.full((H * H,), -2.0 / (hbar * n_m * n_m), dtype=torch.float32, device=device))
+
+
+def surrogate_fwd_2d(V, n_m: int, N: int, wV, wTx, wTy, W, cells=None, hbar: float = HBAR_EVFS, out=None):
+    """eq.(5) in d = 2 (FP64): full tables [B * n_cells][n_m][n_m] of V [B][ny][nx]."""
+    if V.dim() == 2:
+        V = V[None]
+    B, ny, nx = V.shape
+    n_cells = nx * ny if cells is None else int(cells.numel())
+    if out is None:
+        out = torch.empty((B * n_cells, n_m, n_m), dtype=torch.float64, device=V.device)
+    m = ops.mesh_struct(2, nx, ny, n_m, hbar)
+    c = None if cells is None else cells.to(torch.int32).contiguous()
+    L.check(L.lib().wk_surrogate_fwd_2d(ctypes.byref(m), N, ops._ptr(wV), ops._ptr(wTx), ops._ptr(wTy),
+                                        ops._ptr(W), ops._ptr(V.contiguous()), B, ops._ptr(c), n_cells,
+                                        ops._ptr(out), ops._stream()), "wk_surrogate_fwd_2d")
+    return out
+
+
 def surrogate_bwd(V, n_m: int, N: int, wV, wT, W, E, cells=None, want_dV: bool = False,
                   hbar: float = HBAR_EVFS, ws=None):
     if V.dim() == 1:

@@ -13,7 +13,8 @@ Annihilation (rule 2): "regenerate" replaces the particles of each bin holding b
 other particles exactly where they are.
 
 Kernel sources (the paper's two steps, Sec. 4): "exact" = eq.(4) on MFMA in FP64 or a reduced
-precision; "surrogate" = the trained network of eq.(5); "given" = rows the caller computed
+precision; "surrogate" = the trained network of eq.(5) (in 2-D its d = 2 form, FP64, weights
+(wV, wTx, wTy, W)); "given" = rows the caller computed
 (`rows`, one per cell, every cell evaluated at start).  Rows are evaluated only for cells
 within a margin of the occupied ones ("occupied", the paper's memory/speed point) or for
 every cell at start ("all"); both give the same trajectory bit for bit when the margin
@@ -78,10 +79,11 @@ class Simulator:
                                  f"tensor on {self.dev}")
             self.Kbuf = rows
         else:
-            kdt = torch.float64 if (kernel == "exact" and prec == "fp64") else torch.float32
+            kdt = (torch.float64 if ((kernel == "exact" and prec == "fp64") or (kernel == "surrogate" and self.dim == 2))
+                   else torch.float32)
             self.Kbuf = torch.empty((self.n_cells, self.row_len), dtype=kdt, device=self.dev)
         self.surr_ws = (learn.surrogate_fwd_workspace(self.n_m, N, self.dev)
-                        if kernel == "surrogate" else None)
+                        if kernel == "surrogate" and self.dim == 1 else None)
         self.new_cells = torch.empty(self.n_cells, dtype=torch.int32, device=self.dev)
         self.d_count = torch.zeros(1, dtype=torch.int64, device=self.dev)
         self.n_rows = 0
@@ -129,6 +131,9 @@ class Simulator:
         elif self.kernel == "exact":
             ops.kernel_eval(self.V, self.n_m, cells=cells[:count], prec=self.prec,
                             layout="half" if self.half else "full", out=K)
+        elif self.dim == 2:
+            learn.surrogate_fwd_2d(self.V, self.n_m, self.N, *self.weights, cells=cells[:count],
+                                   out=K.view(count, self.n_m, self.n_m))
         else:
             wV, wT, W = self.weights
             learn.surrogate_fwd(self.V, self.n_m, self.N, wV, wT, W, cells=cells[:count],

@@ -367,3 +367,41 @@ def test_2d_lowp_kernel_error_bounds(orc, prec, nx, ny, n_m):
     print(f"2-D {prec} n_m={n_m}: normwise {err:.3e}, worst error / per-entry bound {worst:.3f}")
     assert worst <= 1.0
     assert err <= LOWP2D_TOL[prec]
+
+
+# ----------------------------------------------------------------------------- 2-D eq.(5)
+@pytest.mark.parametrize("N", [1, 2, 4, 8])
+@pytest.mark.parametrize("nx,ny,n_m", [(13, 9, 8), (20, 17, 16), (256, 256, 32)])
+def test_surrogate_2d_vs_oracle(orc, N, nx, ny, n_m):
+    """eq.(5) in d = 2 (FP64) against the oracle: analytic weights and perturbed ones, every cell
+    of the small meshes (windows clamped at both edges) and sampled cells of the 2-D workload's
+    mesh; N = 1 with analytic weights is also the d = 2 kernel of the GPU."""
+    if N >= n_m:
+        pytest.skip("N must be below n_m")
+    mesh = inputs.Mesh2D(nx=nx, ny=ny, dx=0.5, n_m=n_m, pos_f64=False)
+    V = inputs.gaussian_dot_2d(mesh, 0.2, 2.0 if nx < 100 else 4.0, nx * 0.2, ny * 0.3)[None]
+    if nx == 256:
+        rng = np.random.default_rng(N)
+        cells = np.concatenate([[0, nx - 1, nx * ny - 1], rng.integers(0, nx * ny, 40),
+                                (rng.integers(90, 110, 20) * nx + rng.integers(40, 60, 20))]).astype(np.int32)
+    else:
+        cells = None
+    H = n_m // N
+    rng = np.random.default_rng(7 + N)
+    for analytic in (True, False):
+        w = orc.analytic_weights_2d(n_m, N, HB)
+        if not analytic:
+            w = (w[0] * rng.normal(1, 0.1, N * N), w[1] + rng.normal(0, 0.01, N), w[2] + rng.normal(0, 0.01, N),
+                 w[3] * rng.normal(1, 0.1, H * H))
+        w32 = [np.asarray(x, np.float32) for x in w]
+        ref = orc.surrogate_fwd_2d(V, n_m, N, *[x.astype(np.float64) for x in w32], cells=cells)
+        got = to_np(learn.surrogate_fwd_2d(torch.from_numpy(V).to(dev()), n_m, N,
+                                           *[torch.from_numpy(x).to(dev()) for x in w32],
+                                           cells=None if cells is None else torch.from_numpy(cells).to(dev())))
+        err = normwise(got.reshape(1, -1), ref.reshape(1, -1))
+        assert err <= 1e-12, (N, analytic, err)
+        if N == 1 and analytic:
+            kk = to_np(ops.kernel_eval(torch.from_numpy(V).to(dev()), n_m,
+                                       cells=None if cells is None else torch.from_numpy(cells).to(dev())))
+            # W = c2 held in FP32: relative rounding at most 2^-24
+            assert normwise(got.reshape(1, -1), kk.reshape(1, -1)) <= 2.0 ** -23
