@@ -386,6 +386,79 @@ def run_annihilation_modes():
     return out
 
 
+def run_forms_2d(steps=60, warmup=10):
+    """The 2-D workload's kernel in every form, side by side: eq.(4) in FP64, BF16, FP16 and
+    the split forms, and eq.(5) in d = 2 (FP64, barycentric weights, N = 2 and 4), on every cell
+    of its 256 x 256 mesh (kernel entries/s, normwise error against FP64); then the time loop
+    driven by the exact FP64 rows (fused tables), the BF16 x3 and BF16 rows and the N = 2
+    network: ms per step and the density's L1 distance from the FP64-driven run."""
+    import numpy as np
+    import torch
+    from paper_1806_00082_amd import inputs, learn, ops
+    from paper_1806_00082_amd.sim import Simulator
+
+    cfg = inputs.config_c5()
+    n_m = cfg.mesh.n_m
+    V = torch.from_numpy(cfg.V[None]).cuda()
+    R = cfg.mesh.nx * cfg.mesh.ny
+    entries = R * n_m * n_m
+
+    def timeit(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"kernel": {"workload": f"2-D kernel on all {R} cells of the 256 x 256 mesh, {n_m} x {n_m} m"}}
+    ref = ops.kernel_eval(V, n_m)
+    kmax = float(ref.abs().max())
+    for prec in ("fp64", "bf16", "fp16", "bf16x3", "fp16x3"):
+        buf = ref if prec == "fp64" else torch.empty(ref.shape, dtype=torch.float32, device="cuda")
+        ms = timeit(lambda: ops.kernel_eval(V, n_m, prec=prec, out=buf))
+        rec = {"ms": round(ms, 4), "entries_per_s": entries / (ms * 1e-3)}
+        if prec != "fp64":
+            rec["normwise_err_vs_fp64"] = float((buf.double() - ref).abs().max()) / kmax
+        out["kernel"][prec] = rec
+        del buf
+    for N in (2, 4):
+        w = learn.analytic_weights_2d(n_m, N)
+        buf = torch.empty(ref.shape, dtype=torch.float64, device="cuda")
+        ms = timeit(lambda: learn.surrogate_fwd_2d(V, n_m, N, *w, out=buf))
+        out["kernel"][f"surrogate_N{N}_fp64"] = {"ms": round(ms, 4), "entries_per_s": entries / (ms * 1e-3),
+                                                 "normwise_err_vs_exact": float((buf - ref).abs().max()) / kmax}
+        del buf
+    del ref
+    torch.cuda.empty_cache()
+    runs = {}
+    for tag, kw in (("exact_fp64", dict(kernel="exact", prec="fp64")),
+                    ("exact_bf16x3", dict(kernel="exact", prec="bf16x3")),
+                    ("exact_bf16", dict(kernel="exact", prec="bf16")),
+                    ("surrogate_N2_fp64", dict(kernel="surrogate", N=2, weights=learn.analytic_weights_2d(n_m, 2)))):
+        sim = Simulator(cfg, **kw)
+        sim.run(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        sim.run(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        assert not sim.overflowed()
+        runs[tag] = {"ms_per_step": round(e0.elapsed_time(e1) / steps, 4), "n_last": sim.count(),
+                     "rho": sim.density().cpu().numpy()}
+        del sim
+        torch.cuda.empty_cache()
+    out["time_loop"] = {"workload": f"2-D run, {warmup} + {steps} steps, 5e7 particles at start"}
+    for tag, r in runs.items():
+        out["time_loop"][tag] = {"ms_per_step": r["ms_per_step"], "n_last": r["n_last"],
+                                 "rho_L1_vs_fp64": float(np.abs(r["rho"] - runs["exact_fp64"]["rho"]).sum())}
+    return out
+
+
 def run_surrogate_forms():
     """eq.(5) forward (analytic barycentric weights) vs the exact kernel, 1024 cells x 256 m."""
     import torch
@@ -579,6 +652,8 @@ def main():
                     help="only the eq.(4) precision batch (for counter runs on the contraction)")
     ap.add_argument("--learning-only", action="store_true",
                     help="only the training study of eq.(5) (with --train-epochs, --sweep-epochs)")
+    ap.add_argument("--forms-2d-only", action="store_true",
+                    help="only the 2-D kernel forms and the runs they drive")
     ap.add_argument("--annihilation-only", action="store_true",
                     help="only the comparison of the two readings of rule 2")
     ap.add_argument("--train-epochs", type=int, default=6)
@@ -595,7 +670,7 @@ def main():
     # the CPU oracle legs run first, before anything touches the GPU
     cpu = cpu_kernel = None
     if not (args.no_cpu or args.forms_only or args.learning_only or args.headline_1d
-            or args.annihilation_only):
+            or args.annihilation_only or args.forms_2d_only):
         print("cpu baseline: oracle particle passes", file=sys.stderr, flush=True)
         cpu = run_cpu_particles(args.cpu_steps)
         print("cpu baseline: oracle eq.(4)", file=sys.stderr, flush=True)
@@ -608,6 +683,9 @@ def main():
     from paper_1806_00082_amd import inputs
     if args.forms_only:
         print(json.dumps({"forms": {"kernel_eq4": run_kernel_forms()}}))
+        return
+    if args.forms_2d_only:
+        print(json.dumps({"forms": {"forms_2d": run_forms_2d()}}))
         return
     if args.annihilation_only:
         print(json.dumps({"forms": {"annihilation_modes": run_annihilation_modes()}}))
@@ -637,7 +715,7 @@ def main():
             "note": "double-buffered 7-byte particles (2 x 70 MB) fit the 256 MB MALL: its HBM fraction "
                     "is a cache-assisted figure, the headline's 2-D run is not",
             "roofline": s1t["roofline"], "step_roofline": s1t["step_roofline"], "kernels": s1t["kernels"]}
-        for name, fn in (("annihilation_modes", run_annihilation_modes),
+        for name, fn in (("forms_2d", run_forms_2d), ("annihilation_modes", run_annihilation_modes),
                          ("kernel_eq4", run_kernel_forms), ("surrogate_eq5", run_surrogate_forms),
                          ("learning", run_learning), ("tables", run_tables_forms),
                          ("learning_c4", lambda: run_learning_c4(sweep_epochs=args.sweep_epochs,
