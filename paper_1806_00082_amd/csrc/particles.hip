@@ -4,7 +4,8 @@
 //
 // Layout: struct-of-arrays in HBM, positions in cell units.  Every pass streams the
 // arrays once with coalesced accesses.  Ordered outputs (appended children, compacted
-// survivors) use a fixed grid of PB workgroups whose waves each own one contiguous chunk of
+// survivors) use a fixed grid of PB workgroups (SB_MAX for sp_step on large buffers) whose
+// waves each own one contiguous chunk of
 // particle ids: a counting pass stores one count per wave and per workgroup, and every
 // workgroup of the writing pass re-totals the PB workgroup counts (from L2) for its own
 // offset and the capacity check; each wave then walks its chunk with wave-level scans only,
@@ -40,6 +41,13 @@ struct Geo {
 constexpr int BC = PT;      // bins per bin chunk
 constexpr int WPB = PT / 64;  // waves per workgroup
 constexpr int NW = PB * WPB;  // wave chunks of the ordered passes
+// sp_step on large buffers: twice the chunk owners.  Per-chunk work varies (creation and
+// scattered children concentrate where gamma is large) and the launch takes several
+// residency rounds, so shorter chunks shorten the last round; on small ensembles the
+// per-workgroup prologue costs more than that saves.  The host knows the buffer capacity,
+// not the particle count (that stays on the device), so capacity sets the scale.
+constexpr int SB_MAX = 2 * PB;
+constexpr long long SB_LARGE = 1LL << 26;  // output capacity from which sp_step uses SB_MAX
 
 constexpr int PLACE_BLOCKS = PB;  // workgroups placing regenerated / initial particles
 constexpr int CT_MAX = 1024;       // cells of the LDS creation table (larger meshes: ctab)
@@ -48,7 +56,7 @@ constexpr int PLACE_WAVES = PLACE_BLOCKS * WPB;
 // Placement work items: each bin chunk's particles to place, in pieces of at most PIECE slots.
 constexpr int PIECE = 2048;
 
-// Workspace (sp_workspace_size): int64 scalars[16] | int64 bcnt[PB] | int64 wcnt[NW] |
+// Workspace (sp_workspace_size): int64 scalars[16] | int64 bcnt[SB_MAX] | int64 wcnt[SB_MAX WPB] |
 // int64 bpart[PB] | int64 bmixed[PB] | int64 kpre[PB] | int64 bpre[PB] | int64 bitem[PB] |
 // int64 ipre[PB] | int32 wstart[PLACE_WAVES] | int32 csum[n_chunks] | uint8 occ[n_cells] |
 // uint8 occx[n_cells] | uint2 ctab[n_cells] (8-byte aligned) | uint32 mixbits[8 n_chunks]
@@ -79,8 +87,8 @@ static WS carve(void* ws, long n_bins, long n_cells) {
     char* p = static_cast<char*>(ws);
     w.sc = reinterpret_cast<long long*>(p);
     w.bcnt = w.sc + 16;
-    w.wcnt = w.bcnt + PB;
-    w.bpart = w.wcnt + NW;
+    w.wcnt = w.bcnt + SB_MAX;
+    w.bpart = w.wcnt + (size_t)SB_MAX * WPB;
     w.bmixed = w.bpart + PB;
     w.kpre = w.bmixed + PB;
     w.bpre = w.kpre + PB;
@@ -97,7 +105,7 @@ static WS carve(void* ws, long n_bins, long n_cells) {
 }
 
 static size_t ws_bytes_for(long n_bins, long n_cells) {
-    return sizeof(long long) * (16 + 7 * (size_t)PB + (size_t)NW) +
+    return sizeof(long long) * (16 + (size_t)SB_MAX * (1 + WPB) + 6 * (size_t)PB) +
            sizeof(int) * (size_t)(PLACE_WAVES + (n_chunks_for(n_bins) + 1) / 2 * 2) +
            2 * (size_t)n_cells +  // occupancy byte per cell, then its dilation along x
            8 + sizeof(uint2) * (n_cells > CT_MAX ? (size_t)n_cells : 0) +  // aligned ctab
@@ -107,9 +115,9 @@ static size_t ws_bytes_for(long n_bins, long n_cells) {
 constexpr int IT = 4;          // particles per lane in the streaming passes
 constexpr int WT = 64 * IT;    // particles per wave tile
 
-// Wave chunk `wv` of NW: a whole number of wave tiles, the last ones possibly empty.
-__device__ __forceinline__ void wave_chunk(long n, long wv, long* lo, long* hi) {
-    long cs = (n + NW - 1) / NW;
+// Wave chunk `wv` of nw: a whole number of wave tiles, the last ones possibly empty.
+__device__ __forceinline__ void wave_chunk(long n, long wv, long* lo, long* hi, long nw = NW) {
+    long cs = (n + nw - 1) / nw;
     cs = (cs + WT - 1) / WT * WT;
     *lo = min(n, wv * cs);
     *hi = min(n, *lo + cs);
@@ -450,9 +458,10 @@ __device__ __forceinline__ int upper_bound_lds(const V* a, int n, K key) {
 // chunk-owning workgroups.  Each workgroup of the matching writing pass totals bcnt (PB
 // values from L2) for the capacity check; a chunk owner (blockIdx.x < PB, own = true) also
 // gets the offset of its calling wave's chunk in *wave_off (valid in every lane).
-__device__ long long chunk_offsets(const WS& w, bool own, long long* wave_off, long long* redw) {
+__device__ long long chunk_offsets(const WS& w, bool own, long long* wave_off, long long* redw,
+                                   int nb = PB) {
     long long a = 0, p = 0;
-    for (int k = threadIdx.x; k < PB; k += PT) {
+    for (int k = threadIdx.x; k < nb; k += PT) {
         const long long v = w.bcnt[k];
         a += v;
         if (own && k < (int)blockIdx.x) p += v;
@@ -513,15 +522,23 @@ struct HistWindow {
     static constexpr int HPROBE = 4;
     static constexpr uint32_t EMPTY = 0xFFFFFFFFu;  // never a key: 2 b + 1 < 2^32 - 1
 
+    static constexpr int LOG2W = __builtin_ctz(W);
+
     __device__ __forceinline__ void bump(long b, int sg, int cnt) {
         if constexpr (HASH) {
             uint32_t* keys = reinterpret_cast<uint32_t*>(lh);
             int* vals = lh + W;
             const uint32_t key = (uint32_t)(2 * b + sg);
-            uint32_t h = (key * 2654435761u) & (uint32_t)(W - 1);
+            // Fibonacci hashing: the top bits of key * 2^32/phi depend on every bit of the key
+            // (its low bits would depend only on the key's low bits: sign and momentum, so the
+            // same momentum in different cells would always collide)
+            uint32_t h = (key * 2654435761u) >> (32 - LOG2W);
 #pragma unroll 1
             for (int p = 0; p < HPROBE; ++p) {
-                const uint32_t cur = atomicCAS(&keys[h], EMPTY, key);
+                // a slot's key never changes once claimed: a plain read settles hits and
+                // foreign keys, and only an empty slot needs the compare-and-swap
+                uint32_t cur = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
+                if (cur == EMPTY) cur = atomicCAS(&keys[h], EMPTY, key);
                 if (cur == EMPTY || cur == key) {
                     atomicAdd(&vals[h], cnt);
                     return;
@@ -644,7 +661,7 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
     }
     if (hist != nullptr) {
         const long nh = 2 * g.n_bins;
-        for (long k = (long)blockIdx.x * PT + threadIdx.x; k < nh; k += (long)PB * PT) hist[k] = 0;
+        for (long k = (long)blockIdx.x * PT + threadIdx.x; k < nh; k += (long)gridDim.x * PT) hist[k] = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         stats[WK_ST_ABS_X] = 0;
@@ -661,7 +678,7 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
         ct = ct_lds;
     }
     long lo, hi;
-    wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
+    wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi, (long)gridDim.x * WPB);
     long long cnt = 0;
     Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
     load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
@@ -711,7 +728,7 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
     if (stats[WK_ST_OVERFLOW] != 0) return;
     const long n = (long)*d_n_in;
     long long run;
-    const long long total = chunk_offsets(w, true, &run, red);  // grid = PB chunk owners
+    const long long total = chunk_offsets(w, true, &run, red, (int)gridDim.x);  // grid = step_count's
     const long long needed = n + 2 * total;
     if (needed > cap_out) {  // the same decision in every workgroup
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -732,7 +749,7 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     long lo, hi;
-    wave_chunk(n, (long)blockIdx.x * WPB + wv, &lo, &hi);
+    wave_chunk(n, (long)blockIdx.x * WPB + wv, &lo, &hi, (long)gridDim.x * WPB);
     const T vdt = (T)g.vdt;
     long long abs_x = 0, abs_m = 0;
     HistWindow<HW_STEP, DIM == 2> hw{lh, 0, hist, g.n_bins};
@@ -1883,14 +1900,15 @@ static void launch_step(const Geo& g, uint32_t step, const int32_t* cs, const ui
     if (n_cells > CT_MAX)
         WK_LAUNCH("cell_table", cell_table_kernel, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, s,
                   n_cells, cs, n0, thr, w.ctab);
-    WK_LAUNCH("step_count", (step_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, step, cs, n0, thr,
+    const unsigned sb = cap >= SB_LARGE ? SB_MAX : PB;  // chunk owners of both passes
+    WK_LAUNCH("step_count", (step_count<T, MT, DIM>), dim3(sb), dim3(PT), 0, s, g, step, cs, n0, thr,
               x, y, M, My, in->s, d_n_in, (long long)in->capacity, xo, out->s, cap, hist, stats, st, w);
     if (hist)
-        WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, true>), dim3(PB), dim3(PT), 0, s, g, step, cs,
+        WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, true>), dim3(sb), dim3(PT), 0, s, g, step, cs,
                   n0, thr, cdf, guide, guide_len, x, y, M, My, in->s, d_n_in, xo, yo, Mo, Myo,
                   out->s, d_n_out, cap, hist, stats, st, w);
     else
-        WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, false>), dim3(PB), dim3(PT), 0, s, g, step, cs,
+        WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, false>), dim3(sb), dim3(PT), 0, s, g, step, cs,
                   n0, thr, cdf, guide, guide_len, x, y, M, My, in->s, d_n_in, xo, yo, Mo, Myo,
                   out->s, d_n_out, cap, hist, stats, st, w);
 }

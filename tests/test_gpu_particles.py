@@ -408,6 +408,83 @@ def test_c5_full_size_mixed_ensemble(orc):
     assert out.n < n1 + n2  # annihilation removed particles
 
 
+def _max_keys_per_chunk_owner(v, md, n_wg, waves=4):
+    """Largest number of distinct (bin, sign) keys among the particles of one chunk-owning
+    workgroup (its waves' contiguous chunks of whole 256-particle tiles), over every workgroup."""
+    n = len(v["s"])
+    cs = -(-n // (n_wg * waves))
+    cs = -(-cs // 256) * 256
+    nk, nx = md["n_k"], md["nx"]
+    b = (((v["y"].astype(np.int64) * nx + v["x"].astype(np.int64)) * nk
+          + (v["My"].astype(np.int64) - md["M_min"])) * nk + (v["M"].astype(np.int64) - md["M_min"]))
+    key = np.where(v["s"] != 0, 2 * b + (v["s"] > 0), -1)
+    best = 0
+    for wg in range(n_wg):
+        part = key[wg * waves * cs:(wg + 1) * waves * cs]
+        if len(part):
+            u = np.unique(part)
+            best = max(best, len(u) - int(u[0] < 0))
+    return best
+
+
+@pytest.mark.parametrize("large", [False, True])
+def test_histogram_hash_overflow_scattered(orc, large):
+    """Both LDS hash histograms overflow for certain: 2-D particles at random cells and momenta
+    (no bin order), so that some chunk-owning workgroup holds more distinct (bin, sign) keys
+    than its table has slots (2048 in sp_step's second pass, 4096 in sp_annihilate's own
+    histogram pass) and the keys that find no slot go to the device atomics.  Two steps with
+    zero creation tables (drift, absorption, histogram, annihilation), bit-exact against the
+    oracle, the histogram built first by sp_step and then by sp_annihilate.  large: an output
+    capacity of 2^26 or more, where sp_step splits the ensemble into twice the chunks."""
+    mesh = inputs.Mesh2D(nx=128, ny=128, dx=0.5, n_m=32, pos_f64=False)
+    md = mesh.as_dict(0.5)
+    n = 24_000_000 if large else 12_000_000
+    cap = (1 << 26) if large else n + 4096
+    step_owners = 4096 if large else 2048
+    rng = np.random.default_rng(29 + large)
+    hp = orc.Particles(2, cap, False)
+    hp.x[:n] = rng.random(n, dtype=np.float32) * np.float32(md["nx"])
+    hp.y[:n] = rng.random(n, dtype=np.float32) * np.float32(md["ny"])
+    hp.M[:n] = rng.integers(md["M_min"], md["M_min"] + md["n_k"], n)
+    hp.My[:n] = rng.integers(md["M_min"], md["M_min"] + md["n_k"], n)
+    hp.s[:n] = rng.choice(np.array([-1, 1], np.int8), n)
+    hp.n = n
+    n_cells = md["nx"] * md["ny"]
+    slot = np.arange(n_cells, dtype=np.int32)
+    z = np.zeros(n_cells, np.uint32)
+    cdf = np.zeros((n_cells, md["n_m"] ** 2), np.uint64)
+    tables = (z, z, cdf)
+    a = ops.DeviceParticles(2, cap, False)
+    v = hp.view()
+    a.load(n, v["x"], v["M"], v["s"], y=v["y"], My=v["My"])
+    b = ops.DeviceParticles(2, cap, False)
+    st = ops.new_stats()
+    ws = ops.sp_workspace(md, 5)
+    nb = ops.n_bins(md)
+    hist = torch.zeros(2 * nb, dtype=torch.int32, device=dev())
+    n0, thr, cdf_d = host_tables_to_device((None,) + tables)
+    slot_d = torch.from_numpy(slot).to(dev())
+    for s, fused, owners, slots in ((0, True, step_owners, 2048), (1, False, 2048, 4096)):
+        print(f"scattered histogram: step {s}, {hp.n} particles, capacity {cap}, "
+              f"histogram from sp_step: {fused}", flush=True)
+        hp, hst = orc.sp_step(md, hp, tables, slot, step=s, seed=5)
+        ops.sp_step(md, 5, slot_d, n0, thr, cdf_d, a, b, s, st, ws, hist=hist if fused else None)
+        hv = hp.view()
+        assert_particles_equal(b.view(), hv, f"scattered sp_step {s}")
+        keys = _max_keys_per_chunk_owner(hv, md, owners)
+        assert keys > slots, (s, keys, slots)  # some workgroup's table must overflow
+        hp, hh_p, hh_m, hst = orc.sp_annihilate(md, hp, step=s, seed=5, capacity=cap)
+        ops.sp_annihilate(md, 5, b, a, hist, s, st, ws, hist_ready=fused)
+        h = to_np(hist)
+        assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"scattered hist {s}"
+        gst = to_np(st)
+        for k in (L.ST_N, L.ST_KEPT, L.ST_REGEN, L.ST_MIXED):
+            assert gst[k] == hst[k], (s, k, gst[k], hst[k])
+        assert_particles_equal(a.view(), hp.view(), f"scattered sp_annihilate {s}")
+        print(f"scattered histogram: step {s} bit-exact; most keys per workgroup {keys} "
+              f"({owners} chunk owners, {slots} table slots)", flush=True)
+
+
 @pytest.mark.parametrize("pos_f64", [False, True])
 @pytest.mark.parametrize("glen", [None, 16])
 def test_hundreds_of_pairs_per_particle(orc, pos_f64, glen):
