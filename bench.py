@@ -44,7 +44,10 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # by what the counters read for a 1 GiB device copy (fetch x2.0, write x1.0).  Taken for the
 # kernels as they are now; an entry is dropped when its kernel changes until the counters are
 # taken again.
-TRAFFIC = {"1d": {}, "2d": {}}
+TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1557, "annih_bins": 0.0008,
+                  "annih_count": 0.0732, "annih_write": 0.1451},
+           "2d": {"step_count": 1.1881, "step_apply": 2.5155, "annih_bins": 0.5481,
+                  "annih_count": 0.9619, "annih_write": 1.9386}}
 
 
 def _events():
@@ -121,6 +124,9 @@ def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str 
             b = KB[name](S, L)
             kernels[name]["alg_GB_per_launch"] = round(b / max(cnt, 1) / 1e9, 4)
             kernels[name]["alg_GBps"] = round(b / (tot * 1e-3) / 1e9, 1)
+            t = TRAFFIC["2d" if dim == 2 else "1d"].get(name)
+            if t is not None:
+                kernels[name]["traffic_GB_per_launch"] = t
     dom = max((k for k in kernels if k in KB), key=lambda k: kernels[k]["ms_total"])
     ach = kernels[dom]["alg_GBps"]
     traffic = TRAFFIC["2d" if dim == 2 else "1d"].get(dom)
