@@ -525,27 +525,30 @@ def run_tables_forms(reps=5):
                 torch.empty(R, dtype=torch.int32, device="cuda"),
                 torch.empty((R, n_m), dtype=torch.int64, device="cuda"),
                 torch.empty((R, glen + 1), dtype=torch.int32, device="cuda"))
-        K = torch.empty((R, n_m // 2), dtype=torch.float64, device="cuda")
+        rec = {"rows": R, "kernel_rows_MB_two_step": round(R * (n_m // 2) * 8 / 1e6, 1)}
+        for prec in ("fp64", "bf16", "bf16x3"):
+            K = torch.empty((R, n_m // 2), dtype=torch.float64 if prec == "fp64" else torch.float32,
+                            device="cuda")
 
-        def fused():
-            ops.kernel_tables(V, n_m, 0.5, guide_len=glen, out=bufs)
+            def fused():
+                ops.kernel_tables(V, n_m, 0.5, guide_len=glen, out=bufs, prec=prec)
 
-        def two_step():
-            ops.kernel_eval(V, n_m, layout="half", out=K)
-            g, n0, thr, cdf = ops.gamma_tables(K, n_m, 0.5, layout="half")
-            ops.sampling_guide(cdf, glen, out=bufs[4])
+            def two_step():
+                ops.kernel_eval(V, n_m, layout="half", out=K, prec=prec)
+                g, n0, thr, cdf = ops.gamma_tables(K, n_m, 0.5, layout="half")
+                ops.sampling_guide(cdf, glen, out=bufs[4])
 
-        rec = {"rows": R, "kernel_rows_MB_two_step": round(K.numel() * 8 / 1e6, 1)}
-        for tag, fn in (("fused_ms", fused), ("two_step_ms", two_step)):
-            fn()
-            torch.cuda.synchronize()
-            e0, e1 = _events()
-            e0.record()
-            for _ in range(reps):
+            r = rec if prec == "fp64" else rec.setdefault(prec, {})
+            for tag, fn in (("fused_ms", fused), ("two_step_ms", two_step)):
                 fn()
-            e1.record()
-            torch.cuda.synchronize()
-            rec[tag] = round(e0.elapsed_time(e1) / reps, 4)
+                torch.cuda.synchronize()
+                e0, e1 = _events()
+                e0.record()
+                for _ in range(reps):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                r[tag] = round(e0.elapsed_time(e1) / reps, 4)
         out[name] = rec
         del V, bufs, K
         torch.cuda.empty_cache()

@@ -73,16 +73,88 @@ struct TabOut {
 
 constexpr int TAB_GMAX = 256;  // guide buckets the fused epilogue supports
 
+// Creation tables of nr rows staged in LDS (row q at lds + q SW holds the full row, entry t
+// <-> m = t - P; grow(q) is its table row): exactly the arithmetic of the table kernels.  One
+// lane per row sums the positive part in ascending m in FP64 (the order is the definition)
+// and leaves the running sums in place, every lane converts them to the integer CDF, and
+// (optionally) each bucket of the guide table is found by binary search over the CDF row.
+// Lg holds the guide's bucket limits floor(k 2^32 / G); last_s one int per staged row.
+template <typename GrowFn>
+__device__ __forceinline__ void tab_rows(double* lds, int SW, int nr, GrowFn grow, int* last_s,
+                                         const uint64_t* Lg, long R, int n_m, const TabOut& tb) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = threadIdx.x; q < nr; q += KE_THREADS) {  // one thread per row
+        double* srow = lds + q * SW;
+        double C = 0.0;
+        int last = -1;
+        for (int t = 0; t < n_m; ++t) {
+            const double k = srow[t];
+            if (k > 0.0) {
+                C = C + k;
+                last = t;
+            }
+            srow[t] = C;
+        }
+        last_s[q] = last;
+        const long row = grow(q);
+        if (row < R) {
+            const double p = C * tb.dt;
+            const double fl = floor(p);
+            tb.gamma[row] = C;
+            tb.n0[row] = (uint32_t)fl;
+            tb.thr[row] = (uint32_t)floor((p - fl) * 4294967296.0);
+        }
+    }
+    __syncthreads();
+    // rows to waves, entries to lanes; each lane converts its own entries in place
+    for (int q = wave; q < nr; q += KE_THREADS / 64) {
+        const long row = grow(q);
+        double* srow = lds + q * SW;
+        const int last = last_s[q];
+        const double g = last >= 0 ? srow[last] : 0.0;
+        uint64_t* crow = tb.cdf + row * n_m;
+        for (int t = lane; t < n_m; t += 64) {
+            uint64_t v;
+            if (last < 0)
+                v = 0;
+            else if (t >= last)
+                v = 1ull << 32;
+            else
+                v = (uint64_t)floor(srow[t] / g * 4294967296.0);
+            if (row < R) crow[t] = v;
+            reinterpret_cast<uint64_t*>(srow)[t] = v;
+        }
+    }
+    if (tb.guide == nullptr) return;
+    __syncthreads();
+    for (int q = wave; q < nr; q += KE_THREADS / 64) {
+        const long row = grow(q);
+        if (row >= R) continue;
+        const uint64_t* T = reinterpret_cast<const uint64_t*>(lds + q * SW);
+        uint32_t* gout = tb.guide + row * (tb.G + 1);
+        for (int k = lane; k < tb.G; k += 64) {
+            const uint64_t L = Lg[k];
+            int lo = 0, hi = n_m - 1;  // first t with T[t] > L, at most n_m - 1
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (T[mid] > L)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            gout[k] = (uint32_t)lo;
+        }
+        if (lane == 0) gout[tb.G] = (uint32_t)(n_m - 1);
+    }
+}
+
 // Creation tables of eq.(1) from a workgroup's finished rows, which never leave the chip.
 // The rows are staged in LDS as full rows, entry t <-> m = t - P, in groups of 8 (x WAVES_M)
 // rows; the narrowest tiles (H <= 32) take as many groups per round as the operand tiles' LDS
 // holds (three of four, 48 rows, at 80 momenta), the wider ones one group per round,
 // with the values the kernel would have written (K(m) = c (O + E), K(P - m) = c (O - E),
-// K(-m) = -K(m), K(0) = K(-P) = 0); then exactly the arithmetic of the table kernels: one
-// lane per row sums the positive part in ascending m in FP64 (the order is the definition)
-// and leaves the running sums in place, every lane converts them to the integer CDF, and
-// (optionally) each bucket of the guide table is found by binary search over the CDF row.
-// One column block must hold every m of a row (H <= BN).
+// K(-m) = -K(m), K(0) = K(-P) = 0); then tab_rows.  One column block must hold every m of a
+// row (H <= BN).
 template <int WM, int WN, int WAVES_N>
 __device__ __forceinline__ void tab_epilogue(const f64x4 (&acc)[2][WM][WN], double* lds, int lds_len,
                                              long row0, long R, int P, int n_m, int H, double c,
@@ -131,69 +203,7 @@ __device__ __forceinline__ void tab_epilogue(const f64x4 (&acc)[2][WM][WN], doub
             const int gi = g0 + q / SR, qq = q % SR;
             return row0 + ((qq >> 3) * WM + (gi >> 1)) * 16 + 8 * (gi & 1) + (qq & 7);
         };
-        for (int q = threadIdx.x; q < nr; q += KE_THREADS) {  // one thread per row
-            double* srow = lds + q * SW;
-            double C = 0.0;
-            int last = -1;
-            for (int t = 0; t < n_m; ++t) {
-                const double k = srow[t];
-                if (k > 0.0) {
-                    C = C + k;
-                    last = t;
-                }
-                srow[t] = C;
-            }
-            last_s[q] = last;
-            const long row = grow(q);
-            if (row < R) {
-                const double p = C * tb.dt;
-                const double fl = floor(p);
-                tb.gamma[row] = C;
-                tb.n0[row] = (uint32_t)fl;
-                tb.thr[row] = (uint32_t)floor((p - fl) * 4294967296.0);
-            }
-        }
-        __syncthreads();
-        // rows to waves, entries to lanes; each lane converts its own entries in place
-        for (int q = wave; q < nr; q += KE_THREADS / 64) {
-            const long row = grow(q);
-            double* srow = lds + q * SW;
-            const int last = last_s[q];
-            const double g = last >= 0 ? srow[last] : 0.0;
-            uint64_t* crow = tb.cdf + row * n_m;
-            for (int t = lane; t < n_m; t += 64) {
-                uint64_t v;
-                if (last < 0)
-                    v = 0;
-                else if (t >= last)
-                    v = 1ull << 32;
-                else
-                    v = (uint64_t)floor(srow[t] / g * 4294967296.0);
-                if (row < R) crow[t] = v;
-                reinterpret_cast<uint64_t*>(srow)[t] = v;
-            }
-        }
-        if (tb.guide == nullptr) return;
-        __syncthreads();
-        for (int q = wave; q < nr; q += KE_THREADS / 64) {
-            const long row = grow(q);
-            if (row >= R) continue;
-            const uint64_t* T = reinterpret_cast<const uint64_t*>(lds + q * SW);
-            uint32_t* gout = tb.guide + row * (tb.G + 1);
-            for (int k = lane; k < tb.G; k += 64) {
-                const uint64_t L = Lg[k];
-                int lo = 0, hi = n_m - 1;  // first t with T[t] > L, at most n_m - 1
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (T[mid] > L)
-                        hi = mid;
-                    else
-                        lo = mid + 1;
-                }
-                gout[k] = (uint32_t)lo;
-            }
-            if (lane == 0) gout[tb.G] = (uint32_t)(n_m - 1);
-        }
+        tab_rows(lds, SW, nr, grow, last_s, Lg, R, n_m, tb);
     };
     if constexpr (WAVES_N == 4) {
         // the wider tiles (H > 32) hold one or two groups per round and are register bound:
@@ -439,12 +449,68 @@ __device__ __forceinline__ f32x4 mfma16(const s16x8& a, const s16x8& b, f32x4 c)
                                                        __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-template <int PREC, int WM, int WN, int WAVES_N>
+// Creation tables from the 16-bit kernel's finished rows (the TAB form of kernel_eval_lowp),
+// equal bit for bit to the table kernels run on the FP32 rows the kernel would have written:
+// each entry is staged as that FP32 value (c (O + E), c (O - E) in FP32), widened to FP64.
+// Accumulator layout of v_mfma_f32_16x16x32: lane l holds C[4 (l / 16) + e][l % 16], e < 4.
+// Group gi = 2 tm + eh stages the tile rows 4 lk + 2 eh + ee (ee < 2) of row tile tm of every
+// wave row: staged row wr 8 + 2 lk + ee.  One round per group (the LDS holds 8 WAVES_M rows
+// of up to 4 BN + 3 entries); one column block holds every m of a row (H <= BN).
+template <int WM, int WN, int WAVES_N>
+__device__ __forceinline__ void tab_epilogue_lowp(const f32x4 (&acc)[2][WM][WN], double* lds, long row0,
+                                                  long R, int P, int n_m, int H, float c,
+                                                  const TabOut& tb) {
+    constexpr int WAVES_M = 4 / WAVES_N;
+    constexpr int SR = 8 * WAVES_M;
+    constexpr int NG = 2 * WM;
+    __shared__ int last_s[SR];
+    __shared__ uint64_t Lg[TAB_GMAX];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave / WAVES_N, wc = wave % WAVES_N;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int SW = n_m + 1;
+    for (int k = threadIdx.x; k < tb.G; k += KE_THREADS) Lg[k] = ((uint64_t)k << 32) / (uint64_t)tb.G;
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+        const int tm = gi >> 1, eh = gi & 1;
+        __syncthreads();  // the previous round (or the contraction) is done with the LDS
+#pragma unroll
+        for (int tn = 0; tn < WN; ++tn) {
+            const int t = (wc * WN + tn) * 16 + lr, m = t + 1;
+#pragma unroll
+            for (int ee = 0; ee < 2; ++ee) {
+                double* srow = lds + (wr * 8 + 2 * lk + ee) * SW;
+                if (t < H) {
+                    const int e = 2 * eh + ee;
+                    const float o = acc[0][tm][tn][e], ev = acc[1][tm][tn][e];
+                    const double kp = (double)(c * (o + ev)), km = (double)(c * (o - ev));
+                    srow[P + m] = kp;
+                    srow[P - m] = -kp;
+                    if (2 * m < P) {
+                        srow[2 * P - m] = km;
+                        srow[m] = -km;
+                    }
+                }
+                if (t == 0) {
+                    srow[0] = 0.0;
+                    srow[P] = 0.0;
+                }
+            }
+        }
+        __syncthreads();
+        auto grow = [&](int q) -> long {  // q = wr 8 + 2 lk + ee -> tile row 4 lk + 2 eh + ee
+            return row0 + ((q >> 3) * WM + tm) * 16 + 4 * ((q & 7) >> 1) + 2 * eh + (q & 1);
+        };
+        tab_rows(lds, SW, SR, grow, last_s, Lg, R, n_m, tb);
+    }
+}
+
+template <int PREC, int WM, int WN, int WAVES_N, bool TAB = false>
 __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     const double* __restrict__ V, int nx, long R, int n_cells, const int32_t* __restrict__ cells,
     int P, int n_m, int H, int Hk, const uint16_t* __restrict__ To_hi, const uint16_t* __restrict__ Te_hi,
     const uint16_t* __restrict__ To_lo, const uint16_t* __restrict__ Te_lo, float c, int layout,
-    float* __restrict__ out) {
+    float* __restrict__ out, TabOut tb) {
     typedef LowpTraits<PREC> TR;
     constexpr int WAVES_M = 4 / WAVES_N;
     constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N, BK = LP_BK, LD = BK + 8;
@@ -455,7 +521,10 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
     constexpr int OPS = 2 * 2 * NS * BM * LD * 2;
     constexpr int SP = 2 * BN + 4;
     constexpr int STG = 16 * WAVES_M * SP * 4;
-    __shared__ __attribute__((aligned(16))) char lds_ops[OPS > STG ? OPS : STG];
+    // TAB: rounds of 8 WAVES_M full FP64 rows of up to n_m + 1 = 4 BN + 3 entries (H <= BN)
+    constexpr int TBS = TAB ? 8 * WAVES_M * (4 * BN + 3) * 8 : 0;
+    constexpr int LDS1 = OPS > STG ? OPS : STG;
+    __shared__ __attribute__((aligned(16))) char lds_ops[LDS1 > TBS ? LDS1 : TBS];
     auto Dt = reinterpret_cast<uint16_t(*)[2][NS][BM][LD]>(lds_ops);
     __shared__ double Wv[KE_WIN];
     __shared__ long rbase[BM];
@@ -576,6 +645,10 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_lowp(
         buf ^= 1;
     }
 
+    if constexpr (TAB) {
+        tab_epilogue_lowp<WM, WN, WAVES_N>(acc, reinterpret_cast<double*>(lds_ops), row0, R, P, n_m, H, c, tb);
+        return;
+    }
     if (layout == WK_HALF && gridDim.y == 1 && (P & 3) == 0 && P <= SP - 4) {
         // one column block holds every m of its rows: whole rows of the half table are staged
         // in LDS and leave in 16-byte stores (entry m - 1 holds K(m), m = 1..P)
@@ -747,7 +820,8 @@ static void launch_lowp(int cfg, dim3 grid, hipStream_t stream, const double* V,
                         const uint16_t* const* T, float c, int layout, float* out) {
 #define KE_LAUNCH_LP(WM, WN, WNV)                                                                  \
     WK_LAUNCH("kernel_eval_lowp", (kernel_eval_lowp<PREC, WM, WN, WNV>), grid, dim3(KE_THREADS), 0, \
-              stream, V, nx, R, n_cells, cells, P, n_m, H, Hk, T[0], T[1], T[2], T[3], c, layout, out)
+              stream, V, nx, R, n_cells, cells, P, n_m, H, Hk, T[0], T[1], T[2], T[3], c, layout, out, \
+              TabOut{})
     if (cfg == CFG_LARGE)
         KE_LAUNCH_LP(4, 2, 4);
     else if (cfg == CFG_MID)
@@ -802,6 +876,69 @@ int kernel_eval_1d_lowp(const wk_mesh* mesh, const double* V, int B, const int32
     }
     return check_launch("kernel_eval_lowp");
 }
+// The 16-bit forms' rows straight into the creation tables (the TAB form of kernel_eval_lowp):
+// the same tables as kernel_eval_1d_lowp's FP32 half rows given to the table kernels.  One
+// column block must cover every m (H <= 128, n_m <= 514).
+template <int PREC>
+static void launch_lowp_tab(int cfg, dim3 grid, hipStream_t stream, const double* V, int nx, long R,
+                            int n_cells, const int32_t* cells, int P, int n_m, int H, int Hk,
+                            const uint16_t* const* T, float c, const TabOut& tb) {
+#define KT_LAUNCH_LP(WM, WN, WNV)                                                                  \
+    WK_LAUNCH("kernel_tables_lowp", (kernel_eval_lowp<PREC, WM, WN, WNV, true>), grid, dim3(KE_THREADS), \
+              0, stream, V, nx, R, n_cells, cells, P, n_m, H, Hk, T[0], T[1], T[2], T[3], c, WK_HALF,   \
+              (float*)nullptr, tb)
+    if (cfg == CFG_LARGE)
+        KT_LAUNCH_LP(4, 2, 4);
+    else if (cfg == CFG_MID)
+        KT_LAUNCH_LP(4, 1, 4);
+    else
+        KT_LAUNCH_LP(2, 1, 2);
+#undef KT_LAUNCH_LP
+}
+
+int kernel_tables_1d_lowp(const wk_mesh* mesh, const double* V, int B, const int32_t* cells,
+                          int n_cells, int prec, const TabOut& tb, hipStream_t stream) {
+    const int n_m = mesh->n_m, P = n_m / 2, H = P / 2;
+    const long R = (long)B * n_cells;
+    if (R == 0) return WK_OK;
+    WK_REQUIRE(n_m >= 4 && H <= 128, "wk_kernel_tables: n_m must lie in [4, 514]");
+    WK_REQUIRE(tb.guide == nullptr || (tb.G >= 1 && tb.G <= TAB_GMAX),
+               "wk_kernel_tables: guide_len must lie in [1, 256]");
+    const int cfg = fold_cfg(H), BN = fold_bn(cfg);
+    const int Hk = round_up(H, LP_BK), Hn = round_up(H, BN);
+    const bool half = prec == WK_FP16 || prec == WK_FP16X3;
+    const bool split = prec == WK_BF16X3 || prec == WK_FP16X3;
+    const int fh = half ? 3 : 1, fl = half ? 4 : 2;
+    const int kinds[4] = {fh | SINE_ODD_T, fh | SINE_EVEN_T, fl | SINE_ODD_T, fl | SINE_EVEN_T};
+    const uint16_t* T[4];
+    int err = WK_OK;
+    for (int i = 0; i < 4; ++i) {
+        if (i >= 2 && !split) {
+            T[i] = T[i - 2];
+            continue;
+        }
+        T[i] = static_cast<const uint16_t*>(sine_table(n_m, kinds[i], Hn, Hk, &err));
+        if (!T[i]) return err;
+    }
+    const float c = (float)(-2.0 / (mesh->hbar * (double)n_m));
+    dim3 grid((unsigned)((R + KE_BM - 1) / KE_BM), 1);
+    switch (prec) {
+        case WK_BF16:
+            launch_lowp_tab<WK_BF16>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, H, Hk, T, c, tb);
+            break;
+        case WK_FP16:
+            launch_lowp_tab<WK_FP16>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, H, Hk, T, c, tb);
+            break;
+        case WK_BF16X3:
+            launch_lowp_tab<WK_BF16X3>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, H, Hk, T, c, tb);
+            break;
+        default:
+            launch_lowp_tab<WK_FP16X3>(cfg, grid, stream, V, mesh->nx, R, n_cells, cells, P, n_m, H, Hk, T, c, tb);
+            break;
+    }
+    return check_launch("kernel_tables_lowp");
+}
+
 int kernel_eval_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
                    double* out, hipStream_t stream);
 int kernel_eval_2d_16(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
@@ -846,9 +983,9 @@ extern "C" int wk_kernel_eval(const wk_mesh* mesh, const double* V, int32_t B,
 }
 
 extern "C" int wk_kernel_tables(const wk_mesh* mesh, const double* V, int32_t B,
-                                const int32_t* cells, int32_t n_cells, double dt, double* gamma,
-                                uint32_t* n0, uint32_t* thr, uint64_t* cdf, uint32_t* guide,
-                                int32_t guide_len, void* stream) {
+                                const int32_t* cells, int32_t n_cells, int32_t prec, double dt,
+                                double* gamma, uint32_t* n0, uint32_t* thr, uint64_t* cdf,
+                                uint32_t* guide, int32_t guide_len, void* stream) {
     WK_REQUIRE(mesh != nullptr, "wk_kernel_tables: mesh is NULL");
     WK_REQUIRE((mesh->dim == 1 && mesh->ny == 1) || mesh->dim == 2, "wk_kernel_tables: bad mesh");
     WK_REQUIRE(mesh->nx > 0 && mesh->ny > 0, "wk_kernel_tables: empty mesh");
@@ -861,9 +998,13 @@ extern "C" int wk_kernel_tables(const wk_mesh* mesh, const double* V, int32_t B,
                "wk_kernel_tables: with cells == NULL, n_cells must be the number of cells");
     WK_REQUIRE(V && gamma && n0 && thr && cdf, "wk_kernel_tables: NULL array");
     const wk::TabOut tb{dt, gamma, n0, thr, cdf, guide, guide ? (int)guide_len : 0};
-    if (mesh->dim == 2)
+    if (mesh->dim == 2) {
+        WK_REQUIRE(prec == WK_FP64, "wk_kernel_tables: 2-D tables are built from FP64 rows only");
         return wk::kernel_tables_2d(mesh, V, B, cells, n_cells, tb, wk::as_stream(stream));
-    return wk::kernel_tables_1d_f64(mesh, V, B, cells, n_cells, tb, wk::as_stream(stream));
+    }
+    if (prec == WK_FP64) return wk::kernel_tables_1d_f64(mesh, V, B, cells, n_cells, tb, wk::as_stream(stream));
+    WK_REQUIRE(prec >= WK_BF16 && prec <= WK_FP16X3, "wk_kernel_tables: unknown precision");
+    return wk::kernel_tables_1d_lowp(mesh, V, B, cells, n_cells, prec, tb, wk::as_stream(stream));
 }
 
 // ----------------------------------------------------------------------------- adjoint

@@ -127,11 +127,12 @@ def gamma_tables(K: torch.Tensor, n_m: int, dt: float, dim: int = 1, layout: str
 
 
 def kernel_tables(V: torch.Tensor, n_m: int, dt: float, cells: torch.Tensor | None = None,
-                  guide_len: int = 0, hbar: float = HBAR_EVFS, out=None):
+                  guide_len: int = 0, hbar: float = HBAR_EVFS, out=None, prec: str = "fp64"):
     """eq.(4) rows of the requested cells turned straight into the creation tables (the rows
-    stay on chip).  FP64; V [B][nx] (1-D) or [B][ny][nx] (2-D).  Returns (gamma, n0, thr, cdf,
-    guide or None) as gamma_tables and sampling_guide would; `out` may supply those five
-    tensors (row slices are fine)."""
+    stay on chip).  V [B][nx] (1-D) or [B][ny][nx] (2-D); prec "fp64" (1-D and 2-D) or, in
+    1-D, a 16-bit form ("bf16", "fp16", "bf16x3", "fp16x3": the tables of its FP32 rows).
+    Returns (gamma, n0, thr, cdf, guide or None) as gamma_tables and sampling_guide would;
+    `out` may supply those five tensors (row slices are fine)."""
     _need_cuda(V, cells)
     if V.dim() == 1:
         V = V[None]
@@ -159,7 +160,7 @@ def kernel_tables(V: torch.Tensor, n_m: int, dt: float, cells: torch.Tensor | No
     if dim == 1:
         prepare(n_m, V.device)
     m = mesh_struct(dim, nx, ny, n_m, hbar)
-    L.check(L.lib().wk_kernel_tables(ctypes.byref(m), _ptr(V), B, _ptr(cells), n_cells, float(dt),
+    L.check(L.lib().wk_kernel_tables(ctypes.byref(m), _ptr(V), B, _ptr(cells), n_cells, L.PREC[prec], float(dt),
                                      _ptr(g), _ptr(n0), _ptr(thr), _ptr(cdf), _ptr(guide),
                                      guide_len if guide is not None else 0, _stream()), "wk_kernel_tables")
     return g, n0, thr, cdf, guide

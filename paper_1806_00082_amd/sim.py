@@ -64,10 +64,11 @@ class Simulator:
         self.cdf = torch.zeros((self.n_cells, self.width), dtype=torch.int64, device=self.dev)
         self.glen = min(self.width, 256)                # guide buckets for the CDF search
         self.guide = torch.zeros((self.n_cells, self.glen + 1), dtype=torch.int32, device=self.dev)
-        # exact FP64 rows go straight into the creation tables (wk_kernel_tables): the kernel
-        # rows then never exist in device memory
-        self.fused = (fused_tables and kernel == "exact" and prec == "fp64"
-                      and ((self.dim == 1 and 4 <= self.n_m <= 514) or (self.dim == 2 and self.n_m in (8, 16, 32))))
+        # exact rows go straight into the creation tables (wk_kernel_tables): the kernel rows
+        # then never exist in device memory (FP64 in 1-D and 2-D, the 16-bit forms in 1-D)
+        self.fused = (fused_tables and kernel == "exact"
+                      and ((self.dim == 1 and 4 <= self.n_m <= 514)
+                           or (self.dim == 2 and prec == "fp64" and self.n_m in (8, 16, 32))))
         if self.fused:
             self.Kbuf = None
         elif kernel == "given":
@@ -121,6 +122,7 @@ class Simulator:
         r0 = self.n_rows
         if self.fused:
             ops.kernel_tables(self.V, self.n_m, float(self.cfg.dt), cells=cells[:count], guide_len=self.glen,
+                              prec=self.prec,
                               out=(self.gamma[r0:r0 + count], self.n0[r0:r0 + count], self.thr[r0:r0 + count],
                                    self.cdf[r0:r0 + count], self.guide[r0:r0 + count]))
             self.n_rows += count

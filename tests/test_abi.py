@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     lib = _lib.lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.wk_version() == 2
+    assert lib.wk_version() == 3
 
 
 def test_python_binding_names_match_header():

@@ -154,6 +154,70 @@ def test_kernel_tables_equals_two_step(nx, n_m, B, use_cells, glen):
         assert guide is None
 
 
+LOWP_FORMS = ["bf16", "fp16", "bf16x3", "fp16x3"]
+
+
+@pytest.mark.parametrize("prec", LOWP_FORMS)
+@pytest.mark.parametrize("nx,n_m,B,use_cells,glen", KT_CASES)
+def test_kernel_tables_lowp_equals_two_step(nx, n_m, B, use_cells, glen, prec):
+    """The 16-bit forms' rows straight into the tables equal kernel_eval in that form (FP32
+    half rows) + gamma_tables + sampling_guide, bit for bit, over every tile shape."""
+    V = torch.from_numpy(inputs.random_potentials(B, nx, 0.5, seed=nx + n_m)).to(dev())
+    cells = None
+    if use_cells:
+        rng = np.random.default_rng(n_m)
+        cells = torch.from_numpy(rng.permutation(nx)[: max(1, 2 * nx // 3)].astype(np.int32)).to(dev())
+    dt = 0.9
+    g, n0, thr, cdf, guide = ops.kernel_tables(V, n_m, dt, cells=cells, guide_len=glen, prec=prec)
+    K = ops.kernel_eval(V, n_m, cells=cells, layout="half", prec=prec)
+    assert K.dtype == torch.float32
+    g2, n02, thr2, cdf2 = ops.gamma_tables(K, n_m, dt, layout="half")
+    assert torch.equal(g, g2) and torch.equal(n0, n02) and torch.equal(thr, thr2)
+    assert torch.equal(cdf, cdf2)
+    if glen:
+        assert torch.equal(guide, ops.sampling_guide(cdf2, glen))
+    else:
+        assert guide is None
+
+
+@pytest.mark.parametrize("prec", LOWP_FORMS)
+@pytest.mark.parametrize("nx,n_m", [(300, 80), (100, 512)])
+def test_kernel_tables_lowp_vs_oracle(orc, nx, n_m, prec):
+    """The 16-bit forms' tables against the oracle's tables from its FP64 rows: gamma within the
+    form's normwise kernel tolerance carried through the sum (n_m entries), and the creation
+    probability per step within dt times that."""
+    tol = {"bf16": 1e-2, "fp16": 2e-3, "bf16x3": 5e-5, "fp16x3": 1e-5}[prec]
+    V = inputs.random_potentials(2, nx, 0.5, seed=n_m + 1)
+    dt = 0.5
+    g, n0, thr, cdf, _ = ops.kernel_tables(torch.from_numpy(V).to(dev()), n_m, dt, prec=prec)
+    Kf = orc.kernel_1d(V, n_m, HB).reshape(2, -1, n_m)
+    kmax = np.repeat(np.abs(Kf).reshape(2, -1).max(axis=1), Kf.shape[1])  # normwise: per potential
+    rg, rn0, rthr, rcdf = orc.gamma_tables(Kf.reshape(-1, n_m), dt)
+    dg = n_m * tol * kmax
+    assert np.all(np.abs(to_np(g) - rg) <= dg)
+    rate = to_np(n0).view(np.uint32) + as_u32(thr) / 2.0 ** 32
+    rrate = rn0 + rthr / 2.0 ** 32
+    assert np.all(np.abs(rate - rrate) <= dt * dg + 2.0 ** -31)
+
+
+def test_kernel_tables_lowp_edges():
+    """16-bit fused tables: out-of-mesh cell ids give the two-step form's all-zero tables, an
+    empty batch writes nothing, and 2-D refuses the 16-bit forms."""
+    n_m = 16
+    V = torch.from_numpy(np.random.default_rng(5).normal(size=(2, 30)) * 0.1).to(dev())
+    cells = torch.tensor([3, -1, 7, 30, 0], dtype=torch.int32, device=dev())
+    for prec in LOWP_FORMS:
+        g, n0, thr, cdf, guide = ops.kernel_tables(V, n_m, 1.0, cells=cells, guide_len=8, prec=prec)
+        K = ops.kernel_eval(V, n_m, cells=cells, layout="half", prec=prec)
+        g2, n02, thr2, cdf2 = ops.gamma_tables(K, n_m, 1.0, layout="half")
+        assert torch.equal(g, g2) and torch.equal(n0, n02) and torch.equal(thr, thr2) and torch.equal(cdf, cdf2)
+        assert torch.equal(guide, ops.sampling_guide(cdf2, 8))
+        assert all(t.numel() == 0 for t in ops.kernel_tables(V[:0], n_m, 1.0, guide_len=8, prec=prec))
+    V2 = torch.zeros((1, 6, 5), dtype=torch.float64, device=dev())
+    with pytest.raises(RuntimeError):
+        ops.kernel_tables(V2, n_m, 1.0, prec="bf16")
+
+
 @pytest.mark.parametrize("nx,ny,n_m,B,use_cells,glen", [(9, 7, 8, 1, False, 0), (20, 18, 16, 2, True, 64),
                                                        (33, 30, 32, 1, True, 256), (40, 24, 32, 2, False, 5)])
 def test_kernel_tables_2d_equals_two_step(nx, ny, n_m, B, use_cells, glen):

@@ -92,13 +92,15 @@ def test_simulator_rows_and_rates_match_oracle(orc, prec, tol):
     assert np.abs(to_np(sim.gamma) - g).max() <= cfg.mesh.n_m * tol * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("mode", ["all", "occupied"])
-def test_fused_tables_simulator_equals_two_step(mode):
+@pytest.mark.parametrize("mode,prec", [("all", "fp64"), ("occupied", "fp64"), ("occupied", "bf16"),
+                                       ("all", "bf16x3"), ("occupied", "fp16x3")])
+def test_fused_tables_simulator_equals_two_step(mode, prec):
     """Rows straight into the creation tables (kernel rows never in device memory) give the
-    same tables and, step for step, the same particles as rows -> tables in two passes."""
+    same tables and, step for step, the same particles as rows -> tables in two passes, for
+    the FP64 kernel and the 16-bit forms."""
     cfg = inputs.config_c2(N0=2e5)
-    fused = Simulator(cfg, mode=mode)
-    two = Simulator(cfg, mode=mode, fused_tables=False)
+    fused = Simulator(cfg, mode=mode, prec=prec)
+    two = Simulator(cfg, mode=mode, prec=prec, fused_tables=False)
     assert fused.fused and not two.fused
     for k in range(12):
         fused.step()
