@@ -440,6 +440,28 @@ def run_forms_2d(steps=60, warmup=10):
         del buf
     del ref
     torch.cuda.empty_cache()
+    # creation tables of every cell: rows straight into the tables against rows -> tables
+    W = n_m * n_m
+    tabs = (torch.empty(R, dtype=torch.float64, device="cuda"), torch.empty(R, dtype=torch.int32, device="cuda"),
+            torch.empty(R, dtype=torch.int32, device="cuda"), torch.empty((R, W), dtype=torch.int64, device="cuda"),
+            torch.empty((R, 257), dtype=torch.int32, device="cuda"))
+    out["tables"] = {"workload": f"creation tables (eq.(1)) of all {R} cells, guide of 256 buckets"}
+    for prec in ("fp64", "bf16", "bf16x3"):
+        K = torch.empty((R, W), dtype=torch.float64 if prec == "fp64" else torch.float32, device="cuda")
+
+        def two_step():
+            ops.kernel_eval(V, n_m, prec=prec, out=K)
+            g, n0, thr, cdf = ops.gamma_tables(K, n_m, cfg.dt, dim=2)
+            ops.sampling_guide(cdf, 256, out=tabs[4])
+
+        out["tables"][prec] = {
+            "fused_ms": round(timeit(lambda: ops.kernel_tables(V, n_m, cfg.dt, guide_len=256, out=tabs, prec=prec)), 4),
+            "two_step_ms": round(timeit(two_step), 4),
+            "kernel_rows_MB_two_step": round(K.numel() * K.element_size() / 1e6, 1)}
+        del K
+        torch.cuda.empty_cache()
+    del tabs
+    torch.cuda.empty_cache()
     runs = {}
     for tag, kw in (("exact_fp64", dict(kernel="exact", prec="fp64")),
                     ("exact_bf16x3", dict(kernel="exact", prec="bf16x3")),

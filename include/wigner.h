@@ -211,14 +211,14 @@ int wk_sampling_guide(const uint64_t* cdf, int32_t n_rows, int32_t width, int32_
  * The results are bit-identical to wk_kernel_eval in the same precision (any layout)
  * followed by wk_gamma_tables and wk_sampling_guide on the rows it would have written.
  *   V, B, cells, n_cells  as wk_kernel_eval; rows r = b * n_cells + i.
- *   prec   WK_FP64 (1-D and 2-D), or in 1-D one of WK_BF16, WK_FP16, WK_BF16X3, WK_FP16X3
- *          (the 16-bit contractions of wk_kernel_eval, whose FP32 rows feed the tables).
+ *   prec   WK_FP64, or one of WK_BF16, WK_FP16, WK_BF16X3, WK_FP16X3 (the 16-bit
+ *          contractions of wk_kernel_eval, whose FP32 rows feed the tables), 1-D and 2-D.
  *   dt     time step in fs (p = gamma dt).
  *   gamma  [R] double, n0/thr [R] uint32, cdf [R][width] uint64 (width = n_m in 1-D,
  *          n_m^2 in 2-D), as wk_gamma_tables.
  *   guide  NULL, or [R][guide_len + 1] uint32 as wk_sampling_guide, 1 <= guide_len <= 256.
- * Limits: 1-D 4 <= n_m <= 514, 2-D n_m in {8, 16, 32} and FP64 (WK_EINVAL otherwise: use
- * the two-step form). */
+ * Limits: 1-D 4 <= n_m <= 514, 2-D n_m in {8, 16, 32} (WK_EINVAL otherwise: use the
+ * two-step form). */
 int wk_kernel_tables(const wk_mesh* mesh, const double* V, int32_t B, const int32_t* cells,
                      int32_t n_cells, int32_t prec, double dt, double* gamma, uint32_t* n0,
                      uint32_t* thr, uint64_t* cdf, uint32_t* guide, int32_t guide_len,

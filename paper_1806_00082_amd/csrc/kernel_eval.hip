@@ -945,6 +945,8 @@ int kernel_eval_2d_16(const wk_mesh* mesh, const double* V, int B, const int32_t
                       int prec, float* out, hipStream_t stream);
 int kernel_tables_2d(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
                      const TabOut& tb, hipStream_t stream);
+int kernel_tables_2d_16(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
+                        int prec, const TabOut& tb, hipStream_t stream);
 
 }  // namespace wk
 
@@ -999,8 +1001,9 @@ extern "C" int wk_kernel_tables(const wk_mesh* mesh, const double* V, int32_t B,
     WK_REQUIRE(V && gamma && n0 && thr && cdf, "wk_kernel_tables: NULL array");
     const wk::TabOut tb{dt, gamma, n0, thr, cdf, guide, guide ? (int)guide_len : 0};
     if (mesh->dim == 2) {
-        WK_REQUIRE(prec == WK_FP64, "wk_kernel_tables: 2-D tables are built from FP64 rows only");
-        return wk::kernel_tables_2d(mesh, V, B, cells, n_cells, tb, wk::as_stream(stream));
+        if (prec == WK_FP64) return wk::kernel_tables_2d(mesh, V, B, cells, n_cells, tb, wk::as_stream(stream));
+        WK_REQUIRE(prec >= WK_BF16 && prec <= WK_FP16X3, "wk_kernel_tables: unknown precision");
+        return wk::kernel_tables_2d_16(mesh, V, B, cells, n_cells, prec, tb, wk::as_stream(stream));
     }
     if (prec == WK_FP64) return wk::kernel_tables_1d_f64(mesh, V, B, cells, n_cells, tb, wk::as_stream(stream));
     WK_REQUIRE(prec >= WK_BF16 && prec <= WK_FP16X3, "wk_kernel_tables: unknown precision");
@@ -1399,6 +1402,66 @@ namespace wk {
 
 __device__ __forceinline__ double w_end(int j, int P) { return (j == P || j == -P) ? 0.5 : 1.0; }
 
+// Creation tables of one 2-D row (W entries, t = (my + P) n_m + (mx + P)) staged in LDS at Kr
+// by the whole workgroup: the arithmetic of the table kernels.  Ascending positive sums by one
+// thread (the order is the definition), then every thread converts its entries; the guide by
+// binary search.  Every thread of the workgroup calls it; the row must be in place.
+__device__ __forceinline__ void tab_row_block(double* Kr, int W, long r, const TabOut& tb, int* last_s) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double C = 0.0;
+        int last = -1;
+        for (int t = 0; t < W; ++t) {
+            const double k = Kr[t];
+            if (k > 0.0) {
+                C = C + k;
+                last = t;
+            }
+            Kr[t] = C;
+        }
+        *last_s = last;
+        const double p = C * tb.dt;
+        const double fl = floor(p);
+        tb.gamma[r] = C;
+        tb.n0[r] = (uint32_t)fl;
+        tb.thr[r] = (uint32_t)floor((p - fl) * 4294967296.0);
+    }
+    __syncthreads();
+    const int last = *last_s;
+    const double g = last >= 0 ? Kr[last] : 0.0;
+    __syncthreads();  // every thread has read Kr[last] before entries are overwritten
+    uint64_t* crow = tb.cdf + r * W;
+    for (int t = threadIdx.x; t < W; t += KE_THREADS) {
+        uint64_t v;
+        if (last < 0)
+            v = 0;
+        else if (t >= last)
+            v = 1ull << 32;
+        else
+            v = (uint64_t)floor(Kr[t] / g * 4294967296.0);
+        crow[t] = v;
+        reinterpret_cast<uint64_t*>(Kr)[t] = v;
+    }
+    if (tb.guide != nullptr) {
+        __syncthreads();
+        const uint64_t* T = reinterpret_cast<const uint64_t*>(Kr);
+        uint32_t* gout = tb.guide + r * (tb.G + 1);
+        for (int k = threadIdx.x; k < tb.G; k += KE_THREADS) {
+            const uint64_t L = ((uint64_t)k << 32) / (uint64_t)tb.G;
+            int lo = 0, hi = W - 1;  // first t with T[t] > L, at most W - 1
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (T[mid] > L)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            gout[k] = (uint32_t)lo;
+        }
+        if (threadIdx.x == 0) gout[tb.G] = (uint32_t)(W - 1);
+    }
+}
+
 template <int P, bool TAB = false>
 __global__ __launch_bounds__(KE_THREADS) void kernel_eval_2d_f64(
     const double* __restrict__ V, int nx, int ny, long R, int n_cells,
@@ -1526,63 +1589,7 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_2d_f64(
         if constexpr (TAB) {
             static_assert(M1 * (K1 + 1) >= 4 * P * P, "2-D row stage");
             __shared__ int last_s;
-            constexpr int W = 4 * P * P;  // entries per row, t = (my + P) n_m + (mx + P)
-            double* Kr = &Ds[0][0];
-            __syncthreads();
-            // the arithmetic of the table kernels: ascending positive sums by one thread (the
-            // order is the definition), then every thread converts its entries
-            if (threadIdx.x == 0) {
-                double C = 0.0;
-                int last = -1;
-                for (int t = 0; t < W; ++t) {
-                    const double k = Kr[t];
-                    if (k > 0.0) {
-                        C = C + k;
-                        last = t;
-                    }
-                    Kr[t] = C;
-                }
-                last_s = last;
-                const double p = C * tb.dt;
-                const double fl = floor(p);
-                tb.gamma[r] = C;
-                tb.n0[r] = (uint32_t)fl;
-                tb.thr[r] = (uint32_t)floor((p - fl) * 4294967296.0);
-            }
-            __syncthreads();
-            const int last = last_s;
-            const double g = last >= 0 ? Kr[last] : 0.0;
-            __syncthreads();  // every thread has read Kr[last] before entries are overwritten
-            uint64_t* crow = tb.cdf + r * W;
-            for (int t = threadIdx.x; t < W; t += KE_THREADS) {
-                uint64_t v;
-                if (last < 0)
-                    v = 0;
-                else if (t >= last)
-                    v = 1ull << 32;
-                else
-                    v = (uint64_t)floor(Kr[t] / g * 4294967296.0);
-                crow[t] = v;
-                reinterpret_cast<uint64_t*>(Kr)[t] = v;
-            }
-            if (tb.guide != nullptr) {
-                __syncthreads();
-                const uint64_t* T = reinterpret_cast<const uint64_t*>(Kr);
-                uint32_t* gout = tb.guide + r * (tb.G + 1);
-                for (int k = threadIdx.x; k < tb.G; k += KE_THREADS) {
-                    const uint64_t L = ((uint64_t)k << 32) / (uint64_t)tb.G;
-                    int lo = 0, hi = W - 1;  // first t with T[t] > L, at most W - 1
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (T[mid] > L)
-                            hi = mid;
-                        else
-                            lo = mid + 1;
-                    }
-                    gout[k] = (uint32_t)lo;
-                }
-                if (threadIdx.x == 0) gout[tb.G] = (uint32_t)(W - 1);
-            }
+            tab_row_block(&Ds[0][0], 4 * P * P, r, tb, &last_s);
         }
     }
 }
@@ -1595,10 +1602,10 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_2d_f64(
 // cosines), which stage 2 contracts over (part, jy) against A2[my][(part, jy)] = w cos / w sin.
 // Split forms add the hi x lo and lo x hi products in both stages.  The trig operands depend on
 // (n_m, lane) only and live in registers; workgroups loop over the requested cells.
-template <int P, int PREC>
+template <int P, int PREC, bool TAB = false>
 __global__ __launch_bounds__(KE_THREADS) void kernel_eval_2d_lowp(
     const double* __restrict__ V, int nx, int ny, long R, int n_cells,
-    const int32_t* __restrict__ cells, float c2, float* __restrict__ out) {
+    const int32_t* __restrict__ cells, float c2, float* __restrict__ out, TabOut tb) {
     typedef LowpTraits<PREC> TR;
     constexpr bool HALF = TR::half, SPLIT = TR::split;
     constexpr int NS = SPLIT ? 2 : 1;
@@ -1746,50 +1753,83 @@ __global__ __launch_bounds__(KE_THREADS) void kernel_eval_2d_lowp(
                 }
             }
             const int mx_i = tn2 * 16 + lr;
-            float* o = out + r * (long)n_m * n_m;
+            if constexpr (TAB) {
+                // the row stays on chip as the FP32 values the kernel would store, widened to
+                // FP64, in the window tile (free once the differences are formed)
+                double* Kr = &Wv[0][0];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int my_i = tm2 * 16 + 4 * lk + e;
-                if (my_i < 2 * P && mx_i < 2 * P) o[my_i * n_m + mx_i] = c2 * acc[e];
+                for (int e = 0; e < 4; ++e) {
+                    const int my_i = tm2 * 16 + 4 * lk + e;
+                    if (my_i < 2 * P && mx_i < 2 * P) Kr[my_i * n_m + mx_i] = (double)(c2 * acc[e]);
+                }
+            } else {
+                float* o = out + r * (long)n_m * n_m;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int my_i = tm2 * 16 + 4 * lk + e;
+                    if (my_i < 2 * P && mx_i < 2 * P) o[my_i * n_m + mx_i] = c2 * acc[e];
+                }
             }
+        }
+        if constexpr (TAB) {
+            static_assert(J * (J + 1) >= 4 * P * P, "2-D row stage");
+            __shared__ int last_s;
+            tab_row_block(&Wv[0][0], 4 * P * P, r, tb, &last_s);
         }
     }
 }
 
-template <int PREC>
+template <int PREC, bool TAB = false>
 static int launch_2d_lowp(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
-                          float* out, hipStream_t stream) {
+                          float* out, const TabOut& tb, hipStream_t stream) {
     const long R = (long)B * n_cells;
     if (R == 0) return WK_OK;
     const float c2 = (float)(-1.0 / (mesh->hbar * (double)mesh->n_m * (double)mesh->n_m));
     const unsigned grid = (unsigned)(R < 4096 ? R : 4096);
+    const char* name = TAB ? "kernel_tables_2d_lowp" : "kernel_eval_2d_lowp";
     switch (mesh->n_m) {
         case 8:
-            WK_LAUNCH("kernel_eval_2d_lowp", (kernel_eval_2d_lowp<4, PREC>), dim3(grid), dim3(KE_THREADS), 0,
-                      stream, V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            WK_LAUNCH(name, (kernel_eval_2d_lowp<4, PREC, TAB>), dim3(grid), dim3(KE_THREADS), 0,
+                      stream, V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out, tb);
             break;
         case 16:
-            WK_LAUNCH("kernel_eval_2d_lowp", (kernel_eval_2d_lowp<8, PREC>), dim3(grid), dim3(KE_THREADS), 0,
-                      stream, V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            WK_LAUNCH(name, (kernel_eval_2d_lowp<8, PREC, TAB>), dim3(grid), dim3(KE_THREADS), 0,
+                      stream, V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out, tb);
             break;
         case 32:
-            WK_LAUNCH("kernel_eval_2d_lowp", (kernel_eval_2d_lowp<16, PREC>), dim3(grid), dim3(KE_THREADS), 0,
-                      stream, V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out);
+            WK_LAUNCH(name, (kernel_eval_2d_lowp<16, PREC, TAB>), dim3(grid), dim3(KE_THREADS), 0,
+                      stream, V, mesh->nx, mesh->ny, R, n_cells, cells, c2, out, tb);
             break;
         default:
-            return fail(WK_EINVAL, "wk_kernel_eval: 2-D supports n_m = 8, 16 and 32");
+            return fail(WK_EINVAL, TAB ? "wk_kernel_tables: 2-D supports n_m = 8, 16 and 32"
+                                       : "wk_kernel_eval: 2-D supports n_m = 8, 16 and 32");
     }
-    return check_launch("kernel_eval_2d_lowp");
+    return check_launch(name);
 }
 
 int kernel_eval_2d_16(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
                       int prec, float* out, hipStream_t stream) {
     switch (prec) {
-        case WK_BF16: return launch_2d_lowp<WK_BF16>(mesh, V, B, cells, n_cells, out, stream);
-        case WK_FP16: return launch_2d_lowp<WK_FP16>(mesh, V, B, cells, n_cells, out, stream);
-        case WK_BF16X3: return launch_2d_lowp<WK_BF16X3>(mesh, V, B, cells, n_cells, out, stream);
-        case WK_FP16X3: return launch_2d_lowp<WK_FP16X3>(mesh, V, B, cells, n_cells, out, stream);
+        case WK_BF16: return launch_2d_lowp<WK_BF16>(mesh, V, B, cells, n_cells, out, TabOut{}, stream);
+        case WK_FP16: return launch_2d_lowp<WK_FP16>(mesh, V, B, cells, n_cells, out, TabOut{}, stream);
+        case WK_BF16X3: return launch_2d_lowp<WK_BF16X3>(mesh, V, B, cells, n_cells, out, TabOut{}, stream);
+        case WK_FP16X3: return launch_2d_lowp<WK_FP16X3>(mesh, V, B, cells, n_cells, out, TabOut{}, stream);
         default: return fail(WK_EINVAL, "wk_kernel_eval: unknown precision");
+    }
+}
+
+// The 2-D 16-bit forms' rows straight into the creation tables (the tables of the FP32 rows
+// kernel_eval_2d_16 would write).
+int kernel_tables_2d_16(const wk_mesh* mesh, const double* V, int B, const int32_t* cells, int n_cells,
+                        int prec, const TabOut& tb, hipStream_t stream) {
+    WK_REQUIRE(tb.guide == nullptr || (tb.G >= 1 && tb.G <= TAB_GMAX),
+               "wk_kernel_tables: guide_len must lie in [1, 256]");
+    switch (prec) {
+        case WK_BF16: return launch_2d_lowp<WK_BF16, true>(mesh, V, B, cells, n_cells, nullptr, tb, stream);
+        case WK_FP16: return launch_2d_lowp<WK_FP16, true>(mesh, V, B, cells, n_cells, nullptr, tb, stream);
+        case WK_BF16X3: return launch_2d_lowp<WK_BF16X3, true>(mesh, V, B, cells, n_cells, nullptr, tb, stream);
+        case WK_FP16X3: return launch_2d_lowp<WK_FP16X3, true>(mesh, V, B, cells, n_cells, nullptr, tb, stream);
+        default: return fail(WK_EINVAL, "wk_kernel_tables: unknown precision");
     }
 }
 

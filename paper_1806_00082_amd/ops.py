@@ -129,8 +129,8 @@ def gamma_tables(K: torch.Tensor, n_m: int, dt: float, dim: int = 1, layout: str
 def kernel_tables(V: torch.Tensor, n_m: int, dt: float, cells: torch.Tensor | None = None,
                   guide_len: int = 0, hbar: float = HBAR_EVFS, out=None, prec: str = "fp64"):
     """eq.(4) rows of the requested cells turned straight into the creation tables (the rows
-    stay on chip).  V [B][nx] (1-D) or [B][ny][nx] (2-D); prec "fp64" (1-D and 2-D) or, in
-    1-D, a 16-bit form ("bf16", "fp16", "bf16x3", "fp16x3": the tables of its FP32 rows).
+    stay on chip).  V [B][nx] (1-D) or [B][ny][nx] (2-D); prec "fp64" or a 16-bit form
+    ("bf16", "fp16", "bf16x3", "fp16x3": the tables of its FP32 rows).
     Returns (gamma, n0, thr, cdf, guide or None) as gamma_tables and sampling_guide would;
     `out` may supply those five tensors (row slices are fine)."""
     _need_cuda(V, cells)

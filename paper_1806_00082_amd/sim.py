@@ -65,10 +65,9 @@ class Simulator:
         self.glen = min(self.width, 256)                # guide buckets for the CDF search
         self.guide = torch.zeros((self.n_cells, self.glen + 1), dtype=torch.int32, device=self.dev)
         # exact rows go straight into the creation tables (wk_kernel_tables): the kernel rows
-        # then never exist in device memory (FP64 in 1-D and 2-D, the 16-bit forms in 1-D)
+        # then never exist in device memory
         self.fused = (fused_tables and kernel == "exact"
-                      and ((self.dim == 1 and 4 <= self.n_m <= 514)
-                           or (self.dim == 2 and prec == "fp64" and self.n_m in (8, 16, 32))))
+                      and ((self.dim == 1 and 4 <= self.n_m <= 514) or (self.dim == 2 and self.n_m in (8, 16, 32))))
         if self.fused:
             self.Kbuf = None
         elif kernel == "given":

@@ -1,10 +1,13 @@
 """GPU parity of the Wigner kernel (eq.(4)) and the creation tables (eq.(1)) against the
 oracle, through the C ABI."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
 
 from gpu_helpers import HB, as_u32, as_u64, dev, normwise, to_np
+from paper_1806_00082_amd import _lib as L
 from paper_1806_00082_amd import inputs, ops
 
 pytestmark = pytest.mark.gpu
@@ -201,8 +204,8 @@ def test_kernel_tables_lowp_vs_oracle(orc, nx, n_m, prec):
 
 
 def test_kernel_tables_lowp_edges():
-    """16-bit fused tables: out-of-mesh cell ids give the two-step form's all-zero tables, an
-    empty batch writes nothing, and 2-D refuses the 16-bit forms."""
+    """16-bit fused tables: out-of-mesh cell ids give the two-step form's all-zero tables (1-D
+    and 2-D), an empty batch writes nothing, and an unknown precision is refused."""
     n_m = 16
     V = torch.from_numpy(np.random.default_rng(5).normal(size=(2, 30)) * 0.1).to(dev())
     cells = torch.tensor([3, -1, 7, 30, 0], dtype=torch.int32, device=dev())
@@ -213,23 +216,36 @@ def test_kernel_tables_lowp_edges():
         assert torch.equal(g, g2) and torch.equal(n0, n02) and torch.equal(thr, thr2) and torch.equal(cdf, cdf2)
         assert torch.equal(guide, ops.sampling_guide(cdf2, 8))
         assert all(t.numel() == 0 for t in ops.kernel_tables(V[:0], n_m, 1.0, guide_len=8, prec=prec))
-    V2 = torch.zeros((1, 6, 5), dtype=torch.float64, device=dev())
-    with pytest.raises(RuntimeError):
-        ops.kernel_tables(V2, n_m, 1.0, prec="bf16")
+    V2 = torch.from_numpy(np.random.default_rng(6).normal(size=(1, 6, 5)) * 0.1).to(dev())
+    cells2 = torch.tensor([4, -3, 29, 30], dtype=torch.int32, device=dev())
+    for prec in LOWP_FORMS:
+        g, n0, thr, cdf, guide = ops.kernel_tables(V2, 8, 1.0, cells=cells2, guide_len=8, prec=prec)
+        K = ops.kernel_eval(V2, 8, cells=cells2, prec=prec)
+        g2, n02, thr2, cdf2 = ops.gamma_tables(K.reshape(K.shape[0], -1), 8, 1.0, dim=2)
+        assert torch.equal(g, g2) and torch.equal(cdf, cdf2) and torch.equal(guide, ops.sampling_guide(cdf2, 8))
+        assert torch.all(g[[1, 3]] == 0)
+    m = ops.mesh_struct(1, 30, 1, n_m)
+    out = [torch.empty(2 * 30, dtype=t, device=dev()) for t in (torch.float64, torch.int32, torch.int32)]
+    cdf = torch.empty((60, n_m), dtype=torch.int64, device=dev())
+    rc = L.lib().wk_kernel_tables(ctypes.byref(m), ops._ptr(V), 2, None, 30, 42, 1.0, ops._ptr(out[0]),
+                                  ops._ptr(out[1]), ops._ptr(out[2]), ops._ptr(cdf), None, 0, ops._stream())
+    assert rc == L.WK_EINVAL
 
 
+@pytest.mark.parametrize("prec", ["fp64"] + LOWP_FORMS)
 @pytest.mark.parametrize("nx,ny,n_m,B,use_cells,glen", [(9, 7, 8, 1, False, 0), (20, 18, 16, 2, True, 64),
                                                        (33, 30, 32, 1, True, 256), (40, 24, 32, 2, False, 5)])
-def test_kernel_tables_2d_equals_two_step(nx, ny, n_m, B, use_cells, glen):
-    """d = 2: rows straight into the tables equal kernel_eval + gamma_tables + sampling_guide."""
+def test_kernel_tables_2d_equals_two_step(nx, ny, n_m, B, use_cells, glen, prec):
+    """d = 2: rows straight into the tables equal kernel_eval in the same precision (FP64, or
+    the 16-bit forms' FP32 rows) + gamma_tables + sampling_guide, bit for bit."""
     rng = np.random.default_rng(nx * ny + n_m)
     V = torch.from_numpy(rng.normal(size=(B, ny, nx)) * 0.1).to(dev())
     cells = None
     if use_cells:
         cells = torch.from_numpy(rng.permutation(nx * ny)[: nx * ny // 2].astype(np.int32)).to(dev())
     dt = 0.5
-    g, n0, thr, cdf, guide = ops.kernel_tables(V, n_m, dt, cells=cells, guide_len=glen)
-    K = ops.kernel_eval(V, n_m, cells=cells)
+    g, n0, thr, cdf, guide = ops.kernel_tables(V, n_m, dt, cells=cells, guide_len=glen, prec=prec)
+    K = ops.kernel_eval(V, n_m, cells=cells, prec=prec)
     g2, n02, thr2, cdf2 = ops.gamma_tables(K.reshape(K.shape[0], -1), n_m, dt, dim=2)
     assert torch.equal(g, g2) and torch.equal(n0, n02) and torch.equal(thr, thr2)
     assert torch.equal(cdf, cdf2)

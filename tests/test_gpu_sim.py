@@ -115,15 +115,16 @@ def test_fused_tables_simulator_equals_two_step(mode, prec):
         assert torch.equal(getattr(fused, f)[:r], getattr(two, f)[:r]), f
 
 
-def test_fused_tables_2d_simulator_equals_two_step():
+@pytest.mark.parametrize("prec", ["fp64", "bf16", "fp16x3"])
+def test_fused_tables_2d_simulator_equals_two_step(prec):
     """d = 2, rows near occupied cells: the fused rows -> tables pass gives the same tables and
-    trajectory as the two-step form."""
+    trajectory as the two-step form (FP64 and 16-bit kernels)."""
     mesh = inputs.Mesh2D(nx=40, ny=36, dx=0.5, n_m=16, pos_f64=False)
     V = inputs.gaussian_dot_2d(mesh, 0.2, 1.5, 10.0, 9.0)
     bc = inputs.packet_bin_counts_2d(mesh, 5e4, 6.0, 9.0, 1.2, inputs.k_for_energy(0.1), 0.0)
     cfg = inputs.RunConfig("small2d", mesh, V, bc, int(bc.sum()), 0.5, 10, seed=5)
-    fused = Simulator(cfg)
-    two = Simulator(cfg, fused_tables=False)
+    fused = Simulator(cfg, prec=prec)
+    two = Simulator(cfg, prec=prec, fused_tables=False)
     assert fused.fused and not two.fused
     for k in range(10):
         fused.step()
