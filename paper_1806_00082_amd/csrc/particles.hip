@@ -1296,7 +1296,6 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
     constexpr int STAGE = WT * (DIM * (int)sizeof(T) + DIM * (int)sizeof(int) + 1);  // per wave
     constexpr int KEEP_LDS = WPB * STAGE + KWW * (int)sizeof(uint32_t);
     constexpr int PLACE_LDS = WPB * PW_LDS * (int)sizeof(int);
-    __shared__ int ldsw[WPB];
     __shared__ long wmin[PT / 64];
     // keepers: one stage per wave + histogram window; placers: chunk and bin prefix tables
     __shared__ __align__(16) char smem[KEEP_LDS > PLACE_LDS ? KEEP_LDS : PLACE_LDS];
