@@ -50,6 +50,14 @@ def test_host_validation_without_gpu():
     assert lib.wk_kernel_eval(ctypes.byref(m), None, 0, None, 10, 0, 0, None, None) == 0  # empty
     g = _lib.SpGeom(1, 10, 1, 8, 16, -8, 0, 0, 0.1, 0)
     assert lib.sp_workspace_size(ctypes.byref(g)) > 0
+    # wk_kernel_tables checks its precision on the host (the pointers are never touched)
+    fake = ctypes.c_void_p(4096)
+    for dim, ny in ((1, 1), (2, 6)):
+        m = _lib.WkMesh(dim, 10, ny, 8, 0.65)
+        rc = lib.wk_kernel_tables(ctypes.byref(m), fake, 1, None, 10 * ny, 42, 0.5, fake, fake, fake, fake,
+                                  None, 0, None)
+        assert rc == _lib.WK_EINVAL
+        assert b"precision" in lib.wk_last_error()
 
 
 def test_workspace_contracts_without_gpu():
