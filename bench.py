@@ -460,7 +460,20 @@ def run_forms_2d(steps=60, warmup=10):
             "kernel_rows_MB_two_step": round(K.numel() * K.element_size() / 1e6, 1)}
         del K
         torch.cuda.empty_cache()
-    del tabs
+    w2 = learn.analytic_weights_2d(n_m, 2)
+    K = torch.empty((R, W), dtype=torch.float64, device="cuda")
+
+    def two_step_surr():
+        learn.surrogate_fwd_2d(V, n_m, 2, *w2, out=K.view(R, n_m, n_m))
+        g, n0, thr, cdf = ops.gamma_tables(K, n_m, cfg.dt, dim=2)
+        ops.sampling_guide(cdf, 256, out=tabs[4])
+
+    out["tables"]["surrogate_N2_fp64"] = {
+        "fused_ms": round(timeit(lambda: learn.surrogate_tables_2d(V, n_m, 2, *w2, cfg.dt, guide_len=256,
+                                                                   out=tabs)), 4),
+        "two_step_ms": round(timeit(two_step_surr), 4),
+        "kernel_rows_MB_two_step": round(K.numel() * 8 / 1e6, 1)}
+    del tabs, K
     torch.cuda.empty_cache()
     runs = {}
     for tag, kw in (("exact_fp64", dict(kernel="exact", prec="fp64")),

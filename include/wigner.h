@@ -366,6 +366,18 @@ int wk_surrogate_fwd_2d(const wk_mesh* mesh, int32_t N, const float* wV, const f
                         const float* wTy, const float* W, const double* V, int32_t B,
                         const int32_t* cells, int32_t n_cells, double* K_out, void* stream);
 
+/* wk_surrogate_tables_2d -- wk_surrogate_fwd_2d's rows turned straight into the creation tables
+ * of eq.(1) and postulate II, the rows never in device memory (the learned kernel in the time
+ * loop, Sec. 2.2 and Sec. 4).  Bit-identical to wk_surrogate_fwd_2d followed by
+ * wk_gamma_tables (FP64 rows, 2-D) and wk_sampling_guide.
+ *   mesh, N, wV, wTx, wTy, W, V, B, cells, n_cells  as wk_surrogate_fwd_2d.
+ *   dt, gamma, n0, thr, cdf, guide, guide_len       as wk_kernel_tables (width n_m^2). */
+int wk_surrogate_tables_2d(const wk_mesh* mesh, int32_t N, const float* wV, const float* wTx,
+                           const float* wTy, const float* W, const double* V, int32_t B,
+                           const int32_t* cells, int32_t n_cells, double dt, double* gamma,
+                           uint32_t* n0, uint32_t* thr, uint64_t* cdf, uint32_t* guide,
+                           int32_t guide_len, void* stream);
+
 /* wk_surrogate_bwd -- gradients of L = sum E * Kh with respect to wV, wT, W (written,
  * float) and V (accumulated into dV [B][nx] double, may be NULL); E [B*n_cells][P] float.
  * Deterministic two-level reductions.  ws: wk_surrogate_workspace() bytes. */

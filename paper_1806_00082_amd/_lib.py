@@ -74,6 +74,8 @@ SIGNATURES = {
     "wk_surrogate_fwd_static_max": (_sz, []),
     "wk_surrogate_fwd_static": (ctypes.c_int, [_MP, _i32, _P, _P, _P, _P, _i32, _P, _i32, _i32, _P, _P]),
     "wk_surrogate_fwd_2d": (ctypes.c_int, [_MP, _i32, _P, _P, _P, _P, _P, _i32, _P, _i32, _P, _P]),
+    "wk_surrogate_tables_2d": (ctypes.c_int, [_MP, _i32, _P, _P, _P, _P, _P, _i32, _P, _i32, _f64, _P, _P,
+                                              _P, _P, _P, _i32, _P]),
     "wk_surrogate_workspace": (_sz, [_MP, _i32, _i32, _i32]),
     "wk_surrogate_bwd": (ctypes.c_int, [_MP, _i32, _P, _P, _P, _P, _i32, _P, _i32, _P, _P, _P, _P,
                                         _P, _P, _sz, _P]),

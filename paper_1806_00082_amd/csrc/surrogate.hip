@@ -1135,11 +1135,11 @@ __device__ __forceinline__ double prefactor2(int L, int m, int n_m) {
     return pr;
 }
 
-template <int P, int N>
+template <int P, int N, bool TAB = false>
 __global__ __launch_bounds__(256) void surr_fwd_2d_f64(
     const double* __restrict__ V, int nx, int ny, long R, int n_cells, const int32_t* __restrict__ cells,
     const float* __restrict__ wV, const float* __restrict__ wTx, const float* __restrict__ wTy,
-    const float* __restrict__ W, double* __restrict__ out) {
+    const float* __restrict__ W, double* __restrict__ out, TabOut tb) {
     constexpr int n_m = 2 * P, H = n_m / N, J = 2 * P + 1;
     constexpr int M1 = (H + 15) / 16 * 16, K1 = (H + 3) / 4 * 4, N1 = 2 * n_m;
     constexpr int NT1 = N1 / 16, MT1 = M1 / 16, NT1W = (NT1 + 3) / 4;
@@ -1265,7 +1265,8 @@ __global__ __launch_bounds__(256) void surr_fwd_2d_f64(
 #pragma unroll
             for (int ks = 0; ks < K2 / 4; ++ks)
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[ks], Ts[4 * ks + lk][mx_i], acc, 0, 0, 0);
-            double* o = out + r * (long)n_m * n_m;
+            // TAB: the row stays on chip, in the window tile (free once the groups are formed)
+            double* o = TAB ? &Wv[0][0] : out + r * (long)n_m * n_m;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int my_i = tm2 * 16 + lk + 4 * e;
@@ -1273,29 +1274,41 @@ __global__ __launch_bounds__(256) void surr_fwd_2d_f64(
                     o[my_i * n_m + mx_i] = prefactor2(L, mx_i - P, n_m) * prefactor2(L, my_i - P, n_m) * acc[e];
             }
         }
+        if constexpr (TAB) {
+            static_assert(J * (J + 1) >= n_m * n_m, "2-D row stage");
+            __shared__ int last_s;
+            tab_row_block(&Wv[0][0], n_m * n_m, r, tb, &last_s);
+        }
     }
 }
 }  // namespace wk
 
-extern "C" int wk_surrogate_fwd_2d(const wk_mesh* mesh, int32_t N, const float* wV, const float* wTx,
-                                   const float* wTy, const float* W, const double* V, int32_t B,
-                                   const int32_t* cells, int32_t n_cells, double* K_out, void* stream) {
-    WK_REQUIRE(mesh && mesh->dim == 2 && mesh->nx > 0 && mesh->ny > 0, "wk_surrogate_fwd_2d: 2-D mesh needed");
-    WK_REQUIRE(mesh->n_m == 8 || mesh->n_m == 16 || mesh->n_m == 32,
-               "wk_surrogate_fwd_2d: n_m must be 8, 16 or 32");
-    WK_REQUIRE(N >= 1 && (N & (N - 1)) == 0 && N <= 8 && N < mesh->n_m,
-               "wk_surrogate_fwd_2d: N must be 1, 2, 4 or 8 and below n_m");
-    WK_REQUIRE(B >= 0 && n_cells >= 0, "wk_surrogate_fwd_2d: negative size");
+namespace wk {
+static int surr_2d_check(const wk_mesh* mesh, int N, int B, int n_cells, const int32_t* cells, const char* who) {
+    if (!(mesh && mesh->dim == 2 && mesh->nx > 0 && mesh->ny > 0)) return fail(WK_EINVAL, std::string(who) + ": 2-D mesh needed");
+    if (!(mesh->n_m == 8 || mesh->n_m == 16 || mesh->n_m == 32))
+        return fail(WK_EINVAL, std::string(who) + ": n_m must be 8, 16 or 32");
+    if (!(N >= 1 && (N & (N - 1)) == 0 && N <= 8 && N < mesh->n_m))
+        return fail(WK_EINVAL, std::string(who) + ": N must be 1, 2, 4 or 8 and below n_m");
+    if (B < 0 || n_cells < 0) return fail(WK_EINVAL, std::string(who) + ": negative size");
     if ((long)B * n_cells == 0) return WK_OK;
-    WK_REQUIRE(cells != nullptr || n_cells == mesh->nx * mesh->ny,
-               "wk_surrogate_fwd_2d: with cells == NULL, n_cells must be the number of cells");
-    WK_REQUIRE(wV && wTx && wTy && W && V && K_out, "wk_surrogate_fwd_2d: NULL array");
+    if (!(cells != nullptr || n_cells == mesh->nx * mesh->ny))
+        return fail(WK_EINVAL, std::string(who) + ": with cells == NULL, n_cells must be the number of cells");
+    return WK_OK;
+}
+
+// eq.(5) in d = 2 on R = B n_cells rows: written out (TAB = false) or turned into the
+// creation tables on chip (TAB).
+template <bool TAB>
+static int surr_2d_launch(const wk_mesh* mesh, int N, const float* wV, const float* wTx, const float* wTy,
+                          const float* W, const double* V, int B, const int32_t* cells, int n_cells,
+                          double* K_out, const TabOut& tb, hipStream_t s) {
     const long R = (long)B * n_cells;
     const unsigned grid = (unsigned)(R < 4096 ? R : 4096);
-    hipStream_t s = as_stream(stream);
+    const char* name = TAB ? "surr_tables_2d_f64" : "surr_fwd_2d_f64";
 #define S2D(PP, NN)                                                                                       \
-    WK_LAUNCH("surr_fwd_2d_f64", (surr_fwd_2d_f64<PP, NN>), dim3(grid), dim3(256), 0, s, V, mesh->nx,    \
-              mesh->ny, R, n_cells, cells, wV, wTx, wTy, W, K_out)
+    WK_LAUNCH(name, (surr_fwd_2d_f64<PP, NN, TAB>), dim3(grid), dim3(256), 0, s, V, mesh->nx,             \
+              mesh->ny, R, n_cells, cells, wV, wTx, wTy, W, K_out, tb)
 #define S2D_N(PP)            \
     switch (N) {             \
         case 1: S2D(PP, 1); break; \
@@ -1312,7 +1325,34 @@ extern "C" int wk_surrogate_fwd_2d(const wk_mesh* mesh, int32_t N, const float* 
     }
 #undef S2D_N
 #undef S2D
-    return check_launch("wk_surrogate_fwd_2d");
+    return check_launch(name);
+}
+}  // namespace wk
+
+extern "C" int wk_surrogate_fwd_2d(const wk_mesh* mesh, int32_t N, const float* wV, const float* wTx,
+                                   const float* wTy, const float* W, const double* V, int32_t B,
+                                   const int32_t* cells, int32_t n_cells, double* K_out, void* stream) {
+    const int rc = wk::surr_2d_check(mesh, N, B, n_cells, cells, "wk_surrogate_fwd_2d");
+    if (rc != WK_OK || (long)B * n_cells == 0) return rc;
+    WK_REQUIRE(wV && wTx && wTy && W && V && K_out, "wk_surrogate_fwd_2d: NULL array");
+    return wk::surr_2d_launch<false>(mesh, N, wV, wTx, wTy, W, V, B, cells, n_cells, K_out, wk::TabOut{},
+                                     wk::as_stream(stream));
+}
+
+extern "C" int wk_surrogate_tables_2d(const wk_mesh* mesh, int32_t N, const float* wV, const float* wTx,
+                                      const float* wTy, const float* W, const double* V, int32_t B,
+                                      const int32_t* cells, int32_t n_cells, double dt, double* gamma,
+                                      uint32_t* n0, uint32_t* thr, uint64_t* cdf, uint32_t* guide,
+                                      int32_t guide_len, void* stream) {
+    const int rc = wk::surr_2d_check(mesh, N, B, n_cells, cells, "wk_surrogate_tables_2d");
+    if (rc != WK_OK || (long)B * n_cells == 0) return rc;
+    WK_REQUIRE(dt >= 0.0, "wk_surrogate_tables_2d: dt must be >= 0");
+    WK_REQUIRE(wV && wTx && wTy && W && V && gamma && n0 && thr && cdf, "wk_surrogate_tables_2d: NULL array");
+    WK_REQUIRE(guide == nullptr || (guide_len >= 1 && guide_len <= wk::TAB_GMAX),
+               "wk_surrogate_tables_2d: guide_len must lie in [1, 256]");
+    const wk::TabOut tb{dt, gamma, n0, thr, cdf, guide, guide ? (int)guide_len : 0};
+    return wk::surr_2d_launch<true>(mesh, N, wV, wTx, wTy, W, V, B, cells, n_cells, nullptr, tb,
+                                    wk::as_stream(stream));
 }
 
 // ----------------------------------------------------------------------------- no-alloc forward

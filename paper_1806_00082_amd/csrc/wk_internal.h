@@ -157,4 +157,78 @@ __device__ __forceinline__ int block_excl_scan_256(int v, int* total, int* lds5)
     return base + inc - v;
 }
 
+// ----------------------------------------------------------------------------- fused tables
+// Creation tables written straight from the kernel rows (the TAB forms of the kernel passes).
+struct TabOut {
+    double dt;
+    double* gamma;
+    uint32_t* n0;
+    uint32_t* thr;
+    uint64_t* cdf;
+    uint32_t* guide;  // NULL: no guide table
+    int G;            // guide buckets
+};
+
+constexpr int TAB_GMAX = 256;  // guide buckets the fused epilogue supports
+
+// Creation tables of one 2-D row (W entries, t = (my + P) n_m + (mx + P)) staged in LDS at Kr
+// by the whole workgroup: the arithmetic of the table kernels.  Ascending positive sums by one
+// thread (the order is the definition), then every thread converts its entries; the guide by
+// binary search.  Every thread of the workgroup calls it; the row must be in place.
+__device__ __forceinline__ void tab_row_block(double* Kr, int W, long r, const TabOut& tb, int* last_s) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double C = 0.0;
+        int last = -1;
+        for (int t = 0; t < W; ++t) {
+            const double k = Kr[t];
+            if (k > 0.0) {
+                C = C + k;
+                last = t;
+            }
+            Kr[t] = C;
+        }
+        *last_s = last;
+        const double p = C * tb.dt;
+        const double fl = floor(p);
+        tb.gamma[r] = C;
+        tb.n0[r] = (uint32_t)fl;
+        tb.thr[r] = (uint32_t)floor((p - fl) * 4294967296.0);
+    }
+    __syncthreads();
+    const int last = *last_s;
+    const double g = last >= 0 ? Kr[last] : 0.0;
+    __syncthreads();  // every thread has read Kr[last] before entries are overwritten
+    uint64_t* crow = tb.cdf + r * W;
+    for (int t = threadIdx.x; t < W; t += blockDim.x) {
+        uint64_t v;
+        if (last < 0)
+            v = 0;
+        else if (t >= last)
+            v = 1ull << 32;
+        else
+            v = (uint64_t)floor(Kr[t] / g * 4294967296.0);
+        crow[t] = v;
+        reinterpret_cast<uint64_t*>(Kr)[t] = v;
+    }
+    if (tb.guide != nullptr) {
+        __syncthreads();
+        const uint64_t* T = reinterpret_cast<const uint64_t*>(Kr);
+        uint32_t* gout = tb.guide + r * (tb.G + 1);
+        for (int k = threadIdx.x; k < tb.G; k += blockDim.x) {
+            const uint64_t L = ((uint64_t)k << 32) / (uint64_t)tb.G;
+            int lo = 0, hi = W - 1;  // first t with T[t] > L, at most W - 1
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (T[mid] > L)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            gout[k] = (uint32_t)lo;
+        }
+        if (threadIdx.x == 0) gout[tb.G] = (uint32_t)(W - 1);
+    }
+}
+
 }  // namespace wk

@@ -93,6 +93,36 @@ def surrogate_fwd_2d(V, n_m: int, N: int, wV, wTx, wTy, W, cells=None, hbar: flo
     return out
 
 
+def surrogate_tables_2d(V, n_m: int, N: int, wV, wTx, wTy, W, dt: float, cells=None, guide_len: int = 0,
+                        hbar: float = HBAR_EVFS, out=None):
+    """eq.(5) in d = 2 turned straight into the creation tables (the rows stay on chip).
+    Returns (gamma, n0, thr, cdf, guide or None) as ops.kernel_tables; `out` may supply them."""
+    if V.dim() == 2:
+        V = V[None]
+    B, ny, nx = V.shape
+    n_cells = nx * ny if cells is None else int(cells.numel())
+    R, width = B * n_cells, n_m * n_m
+    dev = V.device
+    if out is None:
+        out = (torch.empty(R, dtype=torch.float64, device=dev), torch.empty(R, dtype=torch.int32, device=dev),
+               torch.empty(R, dtype=torch.int32, device=dev), torch.empty((R, width), dtype=torch.int64, device=dev),
+               torch.empty((R, guide_len + 1), dtype=torch.int32, device=dev) if guide_len else None)
+    g, n0, thr, cdf, guide = out
+    for t, shape in ((g, (R,)), (n0, (R,)), (thr, (R,)), (cdf, (R, width))):
+        if tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"surrogate_tables_2d: output of shape {tuple(t.shape)}, expected {shape}")
+    if guide is not None and (tuple(guide.shape) != (R, guide_len + 1) or not guide.is_contiguous()):
+        raise ValueError("surrogate_tables_2d: guide must be a contiguous [rows][guide_len + 1] tensor")
+    m = ops.mesh_struct(2, nx, ny, n_m, hbar)
+    c = None if cells is None else cells.to(torch.int32).contiguous()
+    L.check(L.lib().wk_surrogate_tables_2d(ctypes.byref(m), N, ops._ptr(wV), ops._ptr(wTx), ops._ptr(wTy),
+                                           ops._ptr(W), ops._ptr(V.contiguous()), B, ops._ptr(c), n_cells,
+                                           float(dt), ops._ptr(g), ops._ptr(n0), ops._ptr(thr), ops._ptr(cdf),
+                                           ops._ptr(guide), guide_len if guide is not None else 0,
+                                           ops._stream()), "wk_surrogate_tables_2d")
+    return g, n0, thr, cdf, guide
+
+
 def surrogate_bwd(V, n_m: int, N: int, wV, wT, W, E, cells=None, want_dV: bool = False,
                   hbar: float = HBAR_EVFS, ws=None):
     if V.dim() == 1:

@@ -66,8 +66,9 @@ class Simulator:
         self.guide = torch.zeros((self.n_cells, self.glen + 1), dtype=torch.int32, device=self.dev)
         # exact rows go straight into the creation tables (wk_kernel_tables): the kernel rows
         # then never exist in device memory
-        self.fused = (fused_tables and kernel == "exact"
-                      and ((self.dim == 1 and 4 <= self.n_m <= 514) or (self.dim == 2 and self.n_m in (8, 16, 32))))
+        self.fused = fused_tables and (
+            (kernel == "exact" and ((self.dim == 1 and 4 <= self.n_m <= 514) or (self.dim == 2 and self.n_m in (8, 16, 32))))
+            or (kernel == "surrogate" and self.dim == 2))
         if self.fused:
             self.Kbuf = None
         elif kernel == "given":
@@ -120,10 +121,14 @@ class Simulator:
             return
         r0 = self.n_rows
         if self.fused:
-            ops.kernel_tables(self.V, self.n_m, float(self.cfg.dt), cells=cells[:count], guide_len=self.glen,
-                              prec=self.prec,
-                              out=(self.gamma[r0:r0 + count], self.n0[r0:r0 + count], self.thr[r0:r0 + count],
-                                   self.cdf[r0:r0 + count], self.guide[r0:r0 + count]))
+            tabs = (self.gamma[r0:r0 + count], self.n0[r0:r0 + count], self.thr[r0:r0 + count],
+                    self.cdf[r0:r0 + count], self.guide[r0:r0 + count])
+            if self.kernel == "surrogate":
+                learn.surrogate_tables_2d(self.V, self.n_m, self.N, *self.weights, float(self.cfg.dt),
+                                          cells=cells[:count], guide_len=self.glen, out=tabs)
+            else:
+                ops.kernel_tables(self.V, self.n_m, float(self.cfg.dt), cells=cells[:count], guide_len=self.glen,
+                                  prec=self.prec, out=tabs)
             self.n_rows += count
             return
         K = self.Kbuf[:count]

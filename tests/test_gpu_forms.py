@@ -405,3 +405,61 @@ def test_surrogate_2d_vs_oracle(orc, N, nx, ny, n_m):
                                        cells=None if cells is None else torch.from_numpy(cells).to(dev())))
             # W = c2 held in FP32: relative rounding at most 2^-24
             assert normwise(got.reshape(1, -1), kk.reshape(1, -1)) <= 2.0 ** -23
+
+
+@pytest.mark.parametrize("N", [1, 2, 4])
+@pytest.mark.parametrize("nx,ny,n_m,use_cells,glen", [(13, 9, 8, False, 0), (20, 17, 16, True, 64),
+                                                      (40, 33, 32, True, 256), (37, 30, 32, False, 7)])
+def test_surrogate_tables_2d_equals_two_step(N, nx, ny, n_m, use_cells, glen):
+    """eq.(5) in d = 2 straight into the creation tables equals surrogate_fwd_2d followed by
+    gamma_tables and sampling_guide on the GPU, bit for bit (out-of-mesh ids included), with
+    perturbed weights."""
+    mesh = inputs.Mesh2D(nx=nx, ny=ny, dx=0.5, n_m=n_m, pos_f64=False)
+    V = torch.from_numpy(inputs.gaussian_dot_2d(mesh, 0.25, 1.5, nx * 0.3, ny * 0.4)[None]).to(dev())
+    rng = np.random.default_rng(N + nx)
+    H = n_m // N
+    wV, wTx, wTy, W = learn.analytic_weights_2d(n_m, N)
+    w = [wV * torch.from_numpy(rng.normal(1, 0.1, N * N).astype(np.float32)).to(dev()),
+         wTx + torch.from_numpy(rng.normal(0, 0.01, N).astype(np.float32)).to(dev()),
+         wTy + torch.from_numpy(rng.normal(0, 0.01, N).astype(np.float32)).to(dev()),
+         W * torch.from_numpy(rng.normal(1, 0.1, H * H).astype(np.float32)).to(dev())]
+    cells = None
+    if use_cells:
+        ids = np.concatenate([rng.permutation(nx * ny)[: nx * ny // 2], [-1, nx * ny]]).astype(np.int32)
+        cells = torch.from_numpy(ids).to(dev())
+    dt = 0.5
+    g, n0, thr, cdf, guide = learn.surrogate_tables_2d(V, n_m, N, *w, dt, cells=cells, guide_len=glen)
+    K = learn.surrogate_fwd_2d(V, n_m, N, *w, cells=cells)
+    g2, n02, thr2, cdf2 = ops.gamma_tables(K.reshape(K.shape[0], -1), n_m, dt, dim=2)
+    assert torch.equal(g, g2) and torch.equal(n0, n02) and torch.equal(thr, thr2)
+    assert torch.equal(cdf, cdf2)
+    if glen:
+        assert torch.equal(guide, ops.sampling_guide(cdf2, glen))
+    else:
+        assert guide is None
+    assert float(g.max()) > 0
+
+
+def test_surrogate_2d_simulator_fused_equals_two_step():
+    """The 2-D time loop driven by eq.(5) (N = 2, barycentric weights): creation tables straight
+    from the network's rows give the same tables and trajectory as rows -> tables."""
+    from paper_1806_00082_amd.sim import Simulator
+    mesh = inputs.Mesh2D(nx=40, ny=36, dx=0.5, n_m=16, pos_f64=False)
+    V = inputs.gaussian_dot_2d(mesh, 0.2, 1.5, 10.0, 9.0)
+    bc = inputs.packet_bin_counts_2d(mesh, 5e4, 6.0, 9.0, 1.2, inputs.k_for_energy(0.1), 0.0)
+    cfg = inputs.RunConfig("small2d", mesh, V, bc, int(bc.sum()), 0.5, 10, seed=5)
+    w = learn.analytic_weights_2d(16, 2)
+    fused = Simulator(cfg, kernel="surrogate", N=2, weights=w)
+    two = Simulator(cfg, kernel="surrogate", N=2, weights=w, fused_tables=False)
+    assert fused.fused and not two.fused and fused.Kbuf is None
+    for k in range(10):
+        fused.step()
+        two.step()
+        n = fused.count()
+        assert n == two.count(), k
+        for f in ("x", "y", "M", "My", "s"):
+            assert torch.equal(getattr(fused.a, f)[:n], getattr(two.a, f)[:n]), (k, f)
+    r = fused.n_rows
+    assert r == two.n_rows and r > 0
+    for f in ("gamma", "n0", "thr", "cdf", "guide"):
+        assert torch.equal(getattr(fused, f)[:r], getattr(two, f)[:r]), f
