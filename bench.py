@@ -46,8 +46,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # taken again.
 TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1557, "annih_bins": 0.0008,
                   "annih_count": 0.0732, "annih_write": 0.1451},
-           "2d": {"step_count": 1.1881, "step_apply": 2.5155, "annih_bins": 0.5481,
-                  "annih_count": 0.9619, "annih_write": 1.9386}}
+           "2d": {"step_count": 1.1881, "step_apply": 2.5154, "annih_bins": 0.5481,
+                  "annih_count": 0.9619, "annih_write": 1.9389}}
 
 
 def _events():
