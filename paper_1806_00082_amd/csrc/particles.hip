@@ -1426,9 +1426,13 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
 // rank is at least min(H+, H-).  The survivors of all bins are then compacted in input
 // order by the passes of sp_annihilate (nothing is placed).
 constexpr int RB = PB;  // workgroups of the radix passes, each owning a contiguous range
+constexpr int RBITS = 9;             // digit width of the radix passes
+constexpr int RD = 1 << RBITS;       // digits per pass
+constexpr int DPT = RD / PT;         // digits per thread in the per-digit loops
+static_assert(RD % PT == 0, "digits per thread");
 
-// Caller scratch of sp_annihilate_pairs: int64 sc[16] | int64 woff[NW] | uint32 cnt[256 RB] |
-// uint32 off[256 RB] | uint32 dtot[256] | uint32 dbase[256] | uint32 keys[2][n_max] |
+// Caller scratch of sp_annihilate_pairs: int64 sc[16] | int64 woff[NW] | uint32 cnt[RD RB] |
+// uint32 off[RD RB] | uint32 dtot[RD] | uint32 dbase[RD] | uint32 keys[2][n_max] |
 // uint32 vals[2][n_max] | uint8 flags[n_max].
 struct PairScratch {
     long long* sc;     // sc[0]: number of listed particles
@@ -1443,7 +1447,7 @@ struct PairScratch {
 };
 
 static size_t pair_scratch_bytes(long n_max) {
-    return sizeof(long long) * (16 + (size_t)NW) + 2 * sizeof(uint32_t) * 256 * ((size_t)RB + 1) +
+    return sizeof(long long) * (16 + (size_t)NW) + 2 * sizeof(uint32_t) * RD * ((size_t)RB + 1) +
            4 * sizeof(uint32_t) * (size_t)n_max + (size_t)n_max + 64;
 }
 
@@ -1452,10 +1456,10 @@ static PairScratch pair_carve(void* p, long n_max) {
     q.sc = static_cast<long long*>(p);
     q.woff = q.sc + 16;
     q.cnt = reinterpret_cast<uint32_t*>(q.woff + NW);
-    q.off = q.cnt + 256 * RB;
-    q.dtot = q.off + 256 * RB;
-    q.dbase = q.dtot + 256;
-    q.keys[0] = q.dbase + 256;
+    q.off = q.cnt + RD * RB;
+    q.dtot = q.off + RD * RB;
+    q.dbase = q.dtot + RD;
+    q.keys[0] = q.dbase + RD;
     q.keys[1] = q.keys[0] + n_max;
     q.vals[0] = q.keys[1] + n_max;
     q.vals[1] = q.vals[0] + n_max;
@@ -1547,6 +1551,14 @@ __global__ __launch_bounds__(PT) void pair_write(Geo g, const T* x, const T* y, 
         const long id = t0 + IT * lane;
         Part4<T, DIM> p = nxt;
         load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+        // every keep flag starts at 0 (coalesced here); pair_flags sets those of the kept ones
+        if (id + IT <= hi) {
+            *reinterpret_cast<uchar4*>(q.flags + id) = make_uchar4(0, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int k = 0; k < IT; ++k)
+                if (id + k < hi) q.flags[id + k] = 0;
+        }
         long b[IT];
         int c = 0;
 #pragma unroll
@@ -1578,14 +1590,31 @@ __device__ __forceinline__ void radix_range(long m, long r, long* lo, long* hi) 
 
 // Radix pass, 1: digit counts of each block's range (LDS counters).
 __global__ __launch_bounds__(PT) void radix_hist(const uint32_t* __restrict__ keys, int shift, PairScratch q) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    __shared__ uint32_t h[RD];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) h[threadIdx.x + j * PT] = 0;
     __syncthreads();
     long lo, hi;
     radix_range(q.sc[0], blockIdx.x, &lo, &hi);
-    for (long e = lo + threadIdx.x; e < hi; e += PT) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    // one LDS update per distinct digit of a wave's 64 elements (a pass over few distinct
+    // digits, like the top bits of the bin, would otherwise serialise on a few counters)
+    for (long b0 = lo; b0 < hi; b0 += PT) {  // uniform
+        const long e = b0 + threadIdx.x;
+        const bool valid = e < hi;
+        const uint32_t d = valid ? (keys[e] >> shift) & (uint32_t)(RD - 1) : 0u;
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < RBITS; ++bit) {
+            const unsigned long long m = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? m : ~m;
+        }
+        if (valid && (peers & below) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
     __syncthreads();
-    q.cnt[(long)threadIdx.x * RB + blockIdx.x] = h[threadIdx.x];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) q.cnt[(long)(threadIdx.x + j * PT) * RB + blockIdx.x] = h[threadIdx.x + j * PT];
 }
 
 // Radix pass, 2a: per digit (one workgroup each), the exclusive prefix of its RB block counts
@@ -1610,66 +1639,144 @@ __global__ __launch_bounds__(PT) void radix_scan_digits(PairScratch q) {
     if (threadIdx.x == 0) q.dtot[blockIdx.x] = (uint32_t)tot;
 }
 
-// Radix pass, 2b: exclusive prefix of the 256 digit totals (one workgroup).
+// Radix pass, 2b: exclusive prefix of the RD digit totals (one workgroup; DPT consecutive
+// digits per thread).
 __global__ __launch_bounds__(PT) void radix_scan_totals(PairScratch q) {
     __shared__ int ldsw[WPB];
+    uint32_t v[DPT], acc = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        v[j] = q.dtot[threadIdx.x * DPT + j];
+        acc += v[j];
+    }
     int tot;
-    q.dbase[threadIdx.x] = (uint32_t)block_excl_scan_pt((int)q.dtot[threadIdx.x], &tot, ldsw);
+    uint32_t run = (uint32_t)block_excl_scan_pt((int)acc, &tot, ldsw);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        q.dbase[threadIdx.x * DPT + j] = run;
+        run += v[j];
+    }
 }
 
-// Radix pass, 3: stable scatter.  Block r walks its range in tiles of PT elements, one per
-// thread in order; an element's slot is its digit's running offset + the tile's earlier
-// elements of the same digit (the lanes of its wave with that digit, found with eight
-// ballots, plus the counts of the earlier waves).
+// Radix pass, 3: stable scatter.  Block r walks its range in batches of RS_TILES tiles of PT
+// elements (element b0 + k PT + thread of tile k).  An element's rank among the batch's
+// elements of its digit is the tiles before it (running per-digit counts) plus the earlier
+// elements of its own tile (the lanes of its wave with that digit, found with RBITS ballots,
+// and the counts of the earlier waves).  The batch is then staged in LDS sorted by digit and
+// written out in that order, so that consecutive threads fill consecutive slots of each
+// digit's run (about RS_TILES elements per digit) instead of one scattered slot each.
+constexpr int RS_TILES = 16;
+
 __global__ __launch_bounds__(PT) void radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                     int shift, PairScratch q) {
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t cw[WPB][256];
+    constexpr int NB = RS_TILES * PT;
+    constexpr uint32_t DM = RD - 1;
+    __shared__ uint32_t run[RD];      // next output slot of each digit
+    __shared__ uint32_t bcnt[RD];     // the batch's running count of each digit
+    __shared__ uint32_t boff[RD];     // exclusive prefix of the batch counts
+    __shared__ uint32_t cw[WPB][RD];  // per wave: its count of each digit in the current tile
+    __shared__ int ldsw[WPB];
+    __shared__ uint32_t sk[NB], sv[NB];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    run[threadIdx.x] = q.dbase[threadIdx.x] + q.off[(long)threadIdx.x * RB + blockIdx.x];
 #pragma unroll
-    for (int k = 0; k < WPB; ++k) cw[k][threadIdx.x] = 0;
-    __syncthreads();
+    for (int j = 0; j < DPT; ++j) {
+        const int dd = threadIdx.x + j * PT;
+        run[dd] = q.dbase[dd] + q.off[(long)dd * RB + blockIdx.x];
+#pragma unroll
+        for (int k = 0; k < WPB; ++k) cw[k][dd] = 0;
+    }
     long lo, hi;
     radix_range(q.sc[0], blockIdx.x, &lo, &hi);
     const unsigned long long below = (1ull << lane) - 1ull;
-    for (long t0 = lo; t0 < hi; t0 += PT) {  // uniform
-        const long e = t0 + threadIdx.x;
-        const bool valid = e < hi;
-        const uint32_t key = valid ? kin[e] : 0u;
-        const uint32_t val = valid ? vin[e] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
-        unsigned long long peers = __ballot(valid);
+    for (long b0 = lo; b0 < hi; b0 += NB) {  // uniform
 #pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const unsigned long long m = __ballot((d >> bit) & 1u);
-            peers &= ((d >> bit) & 1u) ? m : ~m;
-        }
-        const int lower = __popcll(peers & below);
-        if (valid && lower == 0) cw[wv][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[d] + (uint32_t)lower;
-            for (int k = 0; k < wv; ++k) pos += cw[k][d];
-            kout[pos] = key;
-            vout[pos] = val;
+        for (int j = 0; j < DPT; ++j) bcnt[threadIdx.x + j * PT] = 0;
+        uint32_t key[RS_TILES], val[RS_TILES], rk[RS_TILES];
+#pragma unroll
+        for (int k = 0; k < RS_TILES; ++k) {
+            const long e = b0 + (long)k * PT + threadIdx.x;
+            key[k] = e < hi ? kin[e] : 0u;
+            val[k] = e < hi ? vin[e] : 0u;
         }
         __syncthreads();
-        uint32_t t = 0;
 #pragma unroll
-        for (int k = 0; k < WPB; ++k) {
-            t += cw[k][threadIdx.x];
-            cw[k][threadIdx.x] = 0;
+        for (int k = 0; k < RS_TILES; ++k) {
+            const bool valid = b0 + (long)k * PT + threadIdx.x < hi;
+            const uint32_t d = (key[k] >> shift) & DM;
+            unsigned long long peers = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < RBITS; ++bit) {
+                const unsigned long long m = __ballot((d >> bit) & 1u);
+                peers &= ((d >> bit) & 1u) ? m : ~m;
+            }
+            const int lower = __popcll(peers & below);
+            if (valid && lower == 0) cw[wv][d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            rk[k] = 0;
+            if (valid) {
+                uint32_t r = bcnt[d] + (uint32_t)lower;
+                for (int w = 0; w < wv; ++w) r += cw[w][d];
+                rk[k] = r;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < DPT; ++j) {
+                const int dd = threadIdx.x + j * PT;
+                uint32_t t = 0;
+#pragma unroll
+                for (int w = 0; w < WPB; ++w) {
+                    t += cw[w][dd];
+                    cw[w][dd] = 0;
+                }
+                bcnt[dd] += t;
+            }
+            __syncthreads();
         }
-        run[threadIdx.x] += t;
+        {  // exclusive prefix of the batch counts, DPT consecutive digits per thread
+            uint32_t v[DPT], acc = 0;
+#pragma unroll
+            for (int j = 0; j < DPT; ++j) {
+                v[j] = bcnt[threadIdx.x * DPT + j];
+                acc += v[j];
+            }
+            int tot;
+            uint32_t r = (uint32_t)block_excl_scan_pt((int)acc, &tot, ldsw);
+#pragma unroll
+            for (int j = 0; j < DPT; ++j) {
+                boff[threadIdx.x * DPT + j] = r;
+                r += v[j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RS_TILES; ++k) {
+            if (b0 + (long)k * PT + threadIdx.x < hi) {
+                const uint32_t pl = boff[(key[k] >> shift) & DM] + rk[k];
+                sk[pl] = key[k];
+                sv[pl] = val[k];
+            }
+        }
+        __syncthreads();
+        const int nb = (int)min((long)NB, hi - b0);
+        for (int i = threadIdx.x; i < nb; i += PT) {
+            const uint32_t kk = sk[i], d = (kk >> shift) & DM;
+            const uint32_t pos = run[d] + (uint32_t)i - boff[d];
+            kout[pos] = kk;
+            vout[pos] = sv[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) run[threadIdx.x + j * PT] += bcnt[threadIdx.x + j * PT];
         __syncthreads();
     }
 }
 
 // Ranks and flags: position p of the sorted list holds key k; its rank is p minus the first
 // position of k (a running maximum of the segment heads, started from a binary search at the
-// wave's first position); flags[index] = rank >= min(H+, H-) of its bin.
+// wave's first position); a particle is kept when rank >= min(H+, H-) of its bin.  Only the
+// kept ones are written (flags[index] = 1): pair_write has set every flag to 0, and far fewer
+// particles survive a mixed bin than are listed, so most scattered byte writes are saved.
 __global__ __launch_bounds__(PT) void pair_flags(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                  const int32_t* __restrict__ hist, long n_bins, PairScratch q) {
     const int lane = threadIdx.x & 63;
@@ -1706,7 +1813,7 @@ __global__ __launch_bounds__(PT) void pair_flags(const uint32_t* __restrict__ ke
             const long bin = (long)(k >> 1);
             const int hp = hist[bin], hm = hist[n_bins + bin];
             const long pairs = hp < hm ? hp : hm;
-            q.flags[vals[p]] = (p - st) >= pairs ? 1 : 0;
+            if (p - st >= pairs) q.flags[vals[p]] = 1;
         }
         start = __shfl(st, 63, 64);
     }
@@ -1735,11 +1842,11 @@ static void launch_pairs(const Geo& g, const sp_particles* in, sp_particles* out
               d_n, cap_in, stats, w, q);
     for (int k = 0; k < passes; ++k) {
         const int src = k & 1;
-        WK_LAUNCH("radix_hist", radix_hist, dim3(RB), dim3(PT), 0, s, q.keys[src], 8 * k, q);
-        WK_LAUNCH("radix_scan", radix_scan_digits, dim3(256), dim3(PT), 0, s, q);
+        WK_LAUNCH("radix_hist", radix_hist, dim3(RB), dim3(PT), 0, s, q.keys[src], RBITS * k, q);
+        WK_LAUNCH("radix_scan", radix_scan_digits, dim3(RD), dim3(PT), 0, s, q);
         WK_LAUNCH("radix_totals", radix_scan_totals, dim3(1), dim3(PT), 0, s, q);
         WK_LAUNCH("radix_scatter", radix_scatter, dim3(RB), dim3(PT), 0, s, q.keys[src], q.vals[src],
-                  q.keys[src ^ 1], q.vals[src ^ 1], 8 * k, q);
+                  q.keys[src ^ 1], q.vals[src ^ 1], RBITS * k, q);
     }
     WK_LAUNCH("pair_flags", pair_flags, dim3(PB), dim3(PT), 0, s, q.keys[passes & 1], q.vals[passes & 1], hist,
               g.n_bins, q);
@@ -2072,7 +2179,7 @@ extern "C" int sp_annihilate_pairs(const sp_geom* gm, const sp_particles* in, sp
                "sp_annihilate_pairs: scratch smaller than sp_pairs_scratch_size(g, in->capacity)");
     int bits = 0;
     while ((1L << bits) < 2 * g.n_bins) ++bits;
-    const int passes = (bits + 7) / 8;
+    const int passes = (bits + RBITS - 1) / RBITS;
     WS w = carve(ws, g.n_bins, (long)g.nx * g.ny);
     const PairScratch q = pair_carve(scratch, (long)in->capacity);
     WK_DISPATCH(gm, launch_pairs, g, in, out, hist, (int)(hist_ready != 0),
