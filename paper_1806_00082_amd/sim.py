@@ -19,11 +19,16 @@ precision; "surrogate" = the trained network of eq.(5) (in 2-D its d = 2 form, F
 within a margin of the occupied ones ("occupied", the paper's memory/speed point) or for
 every cell at start ("all"); both give the same trajectory bit for bit when the margin
 covers the drift between refreshes.
+
+`run(steps, log=f)` writes one JSON line of statistics per step; `save` / `restore` write and
+read the state carried between steps, and a restored run continues bit for bit.
 """
 from __future__ import annotations
 
 import ctypes
+import json
 import math
+import time
 
 import torch
 
@@ -186,9 +191,16 @@ class Simulator:
                               hist_ready=self.hist_in_step)
         self.step_index += 1
 
-    def run(self, steps: int):
+    def run(self, steps: int, log=None):
+        """`steps` time steps; with `log` (a writable text file) one JSON line of
+        `metrics()` per step, at one host synchronisation per step."""
+        t0 = time.perf_counter()
         for _ in range(steps):
             self.step()
+            if log is not None:
+                rec = self.metrics()
+                rec["wall_s"] = round(time.perf_counter() - t0, 6)
+                log.write(json.dumps(rec) + "\n")
 
     def count(self) -> int:
         return self.a.count()
@@ -198,3 +210,73 @@ class Simulator:
 
     def density(self):
         return ops.sp_density(self.md, self.hist, float(self.cfg.N0))
+
+    # ------------------------------------------------------------------ metrics, checkpoints
+    def metrics(self) -> dict:
+        """The statistics of the step just taken (one host synchronisation)."""
+        S = self.stats.cpu().tolist()
+        return {"step": self.step_index - 1, "particles": S[L.ST_N], "pairs": S[L.ST_PAIRS],
+                "absorbed_x": S[L.ST_ABS_X], "absorbed_m": S[L.ST_ABS_M], "kept": S[L.ST_KEPT],
+                "regenerated": S[L.ST_REGEN], "mixed_bins": S[L.ST_MIXED], "rows": self.n_rows,
+                "overflow": bool(S[L.ST_OVERFLOW])}
+
+    def _identity(self) -> dict:
+        """What a checkpoint must agree on with the simulator it is restored into."""
+        return {"mesh": self.md, "seed": int(self.seed), "kernel": self.kernel, "prec": self.prec,
+                "mode": self.mode, "refresh_every": self.refresh_every, "N": int(self.N),
+                "annihilation": self.annihilation, "hist_in_step": bool(self.hist_in_step),
+                "fused": bool(self.fused), "glen": self.glen, "m16": bool(self.a.m16)}
+
+    def checkpoint(self) -> dict:
+        """The state the time loop carries from one step to the next, copied to host memory:
+        the ensemble, the signed histogram, the running statistics, the step index and the
+        creation tables of the cells evaluated so far.  Pair creation draws from a
+        counter-based generator keyed by (seed, step, particle index) and every pass is
+        order-defined, so a simulator restored from this state continues bit for bit as the
+        uninterrupted run does."""
+        n, r = self.count(), self.n_rows
+        host = lambda t: t.detach().to("cpu").clone()
+        st = {"identity": json.dumps(self._identity(), sort_keys=True),
+              "step_index": torch.tensor(self.step_index, dtype=torch.int64),
+              "n_rows": torch.tensor(r, dtype=torch.int64), "V": host(self.V),
+              "hist": host(self.hist), "stats": host(self.stats), "cell_slot": host(self.cell_slot),
+              "gamma": host(self.gamma[:r]), "n0": host(self.n0[:r]), "thr": host(self.thr[:r]),
+              "cdf": host(self.cdf[:r]), "guide": host(self.guide[:r])}
+        for f in ("x", "y", "M", "My", "s"):
+            t = getattr(self.a, f)
+            if t is not None:
+                st["p_" + f] = host(t[:n])
+        for i, w in enumerate(self.weights or ()):
+            st[f"w{i}"] = host(torch.as_tensor(w))
+        return st
+
+    def save(self, path):
+        torch.save(self.checkpoint(), path)
+
+    def restore(self, state):
+        """Loads a checkpoint (a dict from `checkpoint()` or a file from `save()`) into this
+        simulator, which must have been built with the same configuration, potential and
+        weights (refused otherwise).  Files are read without unpickling code."""
+        if not isinstance(state, dict):
+            state = torch.load(state, map_location="cpu", weights_only=True)
+        if state["identity"] != json.dumps(self._identity(), sort_keys=True):
+            raise ValueError("checkpoint was written by a simulator of another configuration")
+        if not torch.equal(state["V"], self.V.cpu()):
+            raise ValueError("checkpoint was written for another potential")
+        for i, w in enumerate(self.weights or ()):
+            if not torch.equal(state[f"w{i}"], torch.as_tensor(w).cpu()):
+                raise ValueError("checkpoint was written with other kernel weights")
+        n, r = state["p_x"].numel(), int(state["n_rows"])
+        if n > self.a.capacity:
+            raise ValueError(f"checkpoint holds {n} particles, the buffers {self.a.capacity}")
+        for f in ("x", "y", "M", "My", "s"):
+            t = getattr(self.a, f)
+            if t is not None:
+                t[:n].copy_(state["p_" + f])
+        self.a.d_n.fill_(n)
+        for name in ("hist", "stats", "cell_slot"):
+            getattr(self, name).copy_(state[name])
+        for name in ("gamma", "n0", "thr", "cdf", "guide"):
+            getattr(self, name)[:r].copy_(state[name])
+        self.n_rows = r
+        self.step_index = int(state["step_index"])
