@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 
 METRIC = "Wigner kernel entries/s + particle-steps/s; BF16/surrogate vs FP64 at stated err"
 HBM_PEAK_GBS = 8000.0
+MTYPE = {1: "int8", 2: "int16", 4: "int32"}   # momentum storage by bytes per index
 PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "fp16x3": 2500.0,
                "fp32": 157.3}
 
@@ -44,10 +45,10 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # by what the counters read for a 1 GiB device copy (fetch x2.0, write x1.0).  Taken for the
 # kernels as they are now; an entry is dropped when its kernel changes until the counters are
 # taken again.
-TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1557, "annih_bins": 0.0008,
-                  "annih_count": 0.0732, "annih_write": 0.1451},
-           "2d": {"step_count": 1.1881, "step_apply": 2.5154, "annih_bins": 0.5481,
-                  "annih_count": 0.9619, "annih_write": 1.9389}}
+TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1348, "annih_bins": 0.0008,
+                  "annih_count": 0.0618, "annih_write": 0.1245},
+           "2d": {"step_count": 1.1881, "step_apply": 2.1781, "annih_bins": 0.548,
+                  "annih_count": 0.8137, "annih_write": 1.6508}}
 
 
 def _events():
@@ -57,7 +58,8 @@ def _events():
 
 # Algorithmic HBM bytes per launch of each particle kernel, from the running sums the
 # library keeps (S = stats): what the pass must move at minimum with PB-byte particles
-# (1-D: x 4 + M 2 + s 1 = 7; 2-D: x 4 + y 4 + M 2 + My 2 + s 1 = 13) and, where the pass
+# (FP32 positions, 8-bit momenta: 1-D x 4 + M 1 + s 1 = 6; 2-D x 4 + y 4 + M 1 + My 1 + s 1
+# = 11) and, where the pass
 # clears or walks the signed histogram (2-D: 2 x 4 B x 67M bins, beyond every cache), that
 # histogram (the 1-bit mixed-bin map annih_bins writes, 1/64 of it, is not counted).  The 1-D histogram and all tables are L2-resident and not counted; neither are
 # the pair counts the two sp_step passes hand over (an implementation choice).
@@ -74,17 +76,18 @@ def kernel_bytes(PB: int, dim: int, hist_bytes: int):
     }
 
 
-def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str = "regenerate"):
+def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str = "regenerate",
+                  m_bytes=None):
     """A time-loop workload.  traced=True replays the identical (bit-exact, same seed) run with
     per-kernel events, used only for the per-kernel roofline; the reported value comes from
-    the untraced run."""
+    the untraced run.  m_bytes: momentum storage (default: the narrowest that fits)."""
     import torch
     from paper_1806_00082_amd import _lib as L
     from paper_1806_00082_amd import ops
     from paper_1806_00082_amd.sim import Simulator
 
     sim = Simulator(cfg, kernel="exact", prec="fp64", mode="occupied", refresh_every=8,
-                    annihilation=annihilation)
+                    annihilation=annihilation, m_bytes=m_bytes)
     for _ in range(warmup):
         sim.step()
     sim.stats[L.ST_CUM_STEPS:L.ST_COUNT].zero_()
@@ -107,8 +110,9 @@ def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str 
     out = {"cfg": cfg, "ms": ms, "wall_s": wall, "particle_steps": float(S[L.ST_CUM_N]),
            "pairs": S[L.ST_CUM_PAIRS], "regen": S[L.ST_CUM_REGEN], "n_last": int(sim.count()),
            "rows": sim.n_rows, "stats": S}
-    pbytes = (8 if sim.md["pos_f64"] else 4) * dim + (2 if (dim == 2 or sim.a.m16) else 4) * dim + 1
+    pbytes = (8 if sim.md["pos_f64"] else 4) * dim + sim.a.m_bytes * dim + 1
     out["particle_bytes"] = pbytes
+    out["m_bytes"] = sim.a.m_bytes
     hist_bytes = 2 * 4 * ops.n_bins(sim.md)
     del sim
     torch.cuda.empty_cache()
@@ -683,6 +687,8 @@ def main():
     ap.add_argument("--steps", type=int, default=190)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--m-bytes", type=int, default=None, choices=(1, 2, 4),
+                    help="momentum storage of the headline run (default: the narrowest that fits)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--cpu-potentials", type=int, default=2)
@@ -740,10 +746,10 @@ def main():
         return
     cfg = inputs.config_c2() if args.headline_1d else inputs.config_c5()
     print(f"headline: {cfg.name}, {args.warmup} + {args.steps} steps", file=sys.stderr, flush=True)
-    h = run_particles(cfg, args.steps, args.warmup, traced=False)
+    h = run_particles(cfg, args.steps, args.warmup, traced=False, m_bytes=args.m_bytes)
     tr = h
     if not args.no_trace:
-        tr = run_particles(cfg, args.steps, args.warmup, traced=True)
+        tr = run_particles(cfg, args.steps, args.warmup, traced=True, m_bytes=args.m_bytes)
         assert tr["stats"][11:16] == h["stats"][11:16], "traced replica diverged from the timed run"
     forms = {}
     if not args.no_forms and not args.headline_1d:
@@ -756,7 +762,8 @@ def main():
             "workload": f"{c2.name}: 1-D, 400 cells x 80 m, 1e7 particles, 390 timed steps",
             "ms_per_step": round(s1["ms"] / 390, 4),
             "particle_steps_per_s": s1["particle_steps"] / (s1["ms"] * 1e-3),
-            "note": "double-buffered 7-byte particles (2 x 70 MB) fit the 256 MB MALL: its HBM fraction "
+            "note": f"double-buffered {s1['particle_bytes']}-byte particles (2 x "
+                    f"{round(s1['particle_bytes'] * 1e7 / 1e6)} MB) fit the 256 MB MALL: its HBM fraction "
                     "is a cache-assisted figure, the headline's 2-D run is not",
             "roofline": s1t["roofline"], "step_roofline": s1t["step_roofline"], "kernels": s1t["kernels"]}
         for name, fn in (("forms_2d", run_forms_2d), ("annihilation_modes", run_annihilation_modes),
@@ -776,8 +783,9 @@ def main():
               "particles_initial": int(cfg.bin_counts.sum()), "dt_fs": cfg.dt,
               "annihilation": "every step", "kernel": "exact fp64 rows near occupied cells, fused into the "
                                                      "creation tables",
-              "particle_layout": ("x, y fp32, Mx, My int16, s int8 (13 B)" if dim == 2
-                                  else "x fp32, M int16, s int8 (7 B)")}
+              "particle_layout": (f"x, y fp32, Mx, My {MTYPE[h['m_bytes']]}, s int8 ({h['particle_bytes']} B)"
+                                  if dim == 2 else
+                                  f"x fp32, M {MTYPE[h['m_bytes']]}, s int8 ({h['particle_bytes']} B)")}
     config["cells"] = (f"{cfg.mesh.nx}x{cfg.mesh.ny}" if dim == 2 else cfg.mesh.nx)
     line = {
         "metric": METRIC,
@@ -790,7 +798,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int16+fp32 (fp64 kernel and tables)",
+        "dtype": f"{MTYPE[h['m_bytes']]}+fp32 (fp64 kernel and tables)",
         "data": "synthetic",
         "config": config,
         "run": {"n_last": h["n_last"], "pairs_created": h["pairs"], "regenerated": h["regen"],

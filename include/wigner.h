@@ -33,9 +33,9 @@
  *
  * Particles (Sec. 2.1)
  *   - Struct-of-arrays.  Positions are in units of the cell width (cell = floor(x)),
- *     float or double per sp_geom.pos_f64.  1-D: M is int32, or int16 when sp_geom.m16
- *     is set; 2-D: M (x axis) and My are int16.  s is int8: +1 / -1, 0 = absorbed
- *     (dropped by the next annihilation).
+ *     float or double per sp_geom.pos_f64.  Momentum indices (1-D: M; 2-D: M on the x
+ *     axis and My) are int32, int16 or int8 per sp_geom.m_bytes.  s is int8: +1 / -1,
+ *     0 = absorbed (dropped by the next annihilation).
  *   - The particle count lives in device memory (*d_n) so a time loop needs no host
  *     synchronisation.
  *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed,
@@ -57,7 +57,7 @@ extern "C" {
 #define WK_ECAPACITY (-2)  /* particle buffer too small (see WK_ST_NEEDED) */
 #define WK_EHIP (-3)       /* HIP runtime error (message in wk_last_error) */
 
-#define WK_VERSION 3
+#define WK_VERSION 4
 
 /* Arithmetic of the kernel contraction. */
 enum wk_prec {
@@ -86,9 +86,12 @@ typedef struct sp_geom {
     int32_t n_k;      /* particle momentum window per axis: [M_min, M_min + n_k) */
     int32_t M_min;
     int32_t pos_f64;  /* 1: double positions, 0: float positions */
-    int32_t m16;      /* 1-D: 1 = M is int16 (the window must lie in [-32768, 32767]),
-                         0 = int32; every particle buffer of a call must use that width.
-                         2-D momenta are always int16 (the field is ignored). */
+    int32_t m_bytes;  /* bytes per stored momentum index: 4 = int32 (1-D only), 2 = int16,
+                         1 = int8; 0 = the default (4 in 1-D, 2 in 2-D).  Every particle
+                         buffer of a call uses that width.  The window widened by the
+                         largest pair offset, [M_min - n_m/2, M_min + n_k - 1 + n_m/2],
+                         must fit the type (children outside the window are stored, dead,
+                         with their momenta); else WK_EINVAL. */
     double vdt;       /* drift per step per unit momentum index, in cells */
     uint64_t seed;    /* Philox key */
 } sp_geom;
@@ -96,8 +99,8 @@ typedef struct sp_geom {
 typedef struct sp_particles {
     void* x;          /* [capacity] float or double */
     void* y;          /* [capacity] (2-D only, else NULL) */
-    void* M;          /* [capacity] int32 (1-D) or int16 (2-D) */
-    void* My;         /* [capacity] int16 (2-D only, else NULL) */
+    void* M;          /* [capacity] momentum index (x axis), width per sp_geom.m_bytes */
+    void* My;         /* [capacity] y-axis momentum index (2-D only, else NULL), same width */
     int8_t* s;        /* [capacity] */
     int64_t capacity; /* host value: number of slots */
     int64_t* d_n;     /* device int64: current number of particles */

@@ -31,7 +31,7 @@ class WkMesh(ctypes.Structure):
 class SpGeom(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("n_m", ctypes.c_int32), ("n_k", ctypes.c_int32), ("M_min", ctypes.c_int32),
-                ("pos_f64", ctypes.c_int32), ("m16", ctypes.c_int32),
+                ("pos_f64", ctypes.c_int32), ("m_bytes", ctypes.c_int32),
                 ("vdt", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 

@@ -153,7 +153,7 @@ __device__ __forceinline__ long bin_val(const Geo& g, T x, T y, int m, int my, i
 }
 
 // Four consecutive particles (ids id .. id+3, id a multiple of 4) loaded with 16-byte
-// (positions, int32 momenta), 8-byte (int16 momenta) and 4-byte (signs) accesses;
+// (positions, int32 momenta), 8-byte (int16 momenta) and 4-byte (int8 momenta, signs) accesses;
 // slots at or beyond hi read as dead.
 template <typename T, int DIM>
 struct Part4 {
@@ -179,6 +179,10 @@ __device__ __forceinline__ void ld4(const int16_t* p, long i, int* v) {
     const short4 t = *reinterpret_cast<const short4*>(p + i);
     v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
 }
+__device__ __forceinline__ void ld4(const int8_t* p, long i, int* v) {
+    const char4 t = *reinterpret_cast<const char4*>(p + i);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
 __device__ __forceinline__ void ld4(const int8_t* p, long i, int8_t* v) {
     const char4 t = *reinterpret_cast<const char4*>(p + i);
     v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
@@ -196,6 +200,10 @@ __device__ __forceinline__ void st4(int32_t* p, long i, const int* v) {
 }
 __device__ __forceinline__ void st4(int16_t* p, long i, const int* v) {
     *reinterpret_cast<short4*>(p + i) = make_short4((short)v[0], (short)v[1], (short)v[2], (short)v[3]);
+}
+__device__ __forceinline__ void st4(int8_t* p, long i, const int* v) {
+    *reinterpret_cast<char4*>(p + i) = make_char4((signed char)v[0], (signed char)v[1], (signed char)v[2],
+                                                  (signed char)v[3]);
 }
 
 template <typename T, typename MT, int DIM>
@@ -1035,7 +1043,8 @@ __global__ __launch_bounds__(PT) void annih_bins(Geo g, BinCount bc, int place, 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const long c = blockIdx.x;
     const long j0 = min(g.n_chunks, c * g.gpb), j1 = min(g.n_chunks, j0 + g.gpb);
-    const bool vec = bc.counts == nullptr && (bc.n_bins & 3) == 0;  // 16-byte aligned rows
+    const bool vec = bc.counts == nullptr && (bc.n_bins & 3) == 0 &&  // 16-byte aligned rows
+                     (reinterpret_cast<uintptr_t>(bc.hist) & 15) == 0;
     long long part = 0, mixed = 0, items = 0;
     for (long j = j0 + wv; j < j1; j += WPB) {  // per wave, no workgroup barriers
         const long b0 = j * BC + 4 * lane;
@@ -1950,14 +1959,28 @@ __global__ void assign_slots_kernel(const int32_t* __restrict__ new_cells,
 }
 
 // ----------------------------------------------------------------------------- host side
+// Bytes per stored momentum index (sp_geom.m_bytes, 0 = the default for the dimension).
+static int m_bytes_of(const sp_geom* gm) {
+    return gm->m_bytes ? gm->m_bytes : (gm->dim == 1 ? 4 : 2);
+}
+
 static int make_geo(const sp_geom* gm, Geo* g) {
     WK_REQUIRE(gm != nullptr, "particles: geometry is NULL");
     WK_REQUIRE(gm->dim == 1 || gm->dim == 2, "particles: dim must be 1 or 2");
     WK_REQUIRE(gm->nx > 0 && gm->ny > 0 && (gm->dim == 2 || gm->ny == 1), "particles: bad mesh");
     WK_REQUIRE(gm->n_m >= 2 && gm->n_m % 2 == 0, "particles: n_m must be even");
     WK_REQUIRE(gm->n_k > 0, "particles: n_k must be positive");
-    WK_REQUIRE((gm->dim == 1 && !gm->m16) || (gm->M_min >= -32768 && gm->M_min + gm->n_k <= 32767),
-               "particles: 16-bit momenta (2-D, or 1-D with m16) must fit int16");
+    const int mb = m_bytes_of(gm);
+    WK_REQUIRE(mb == 1 || mb == 2 || (mb == 4 && gm->dim == 1),
+               "particles: m_bytes must be 0, 1, 2 or (1-D) 4");
+    {
+        // stored momenta: the window and the children's offsets of up to n_m/2 either way
+        const long lo = (long)gm->M_min - gm->n_m / 2, hi = (long)gm->M_min + gm->n_k - 1 + gm->n_m / 2;
+        const long tmin = mb == 1 ? -128 : (mb == 2 ? -32768 : INT_MIN);
+        const long tmax = mb == 1 ? 127 : (mb == 2 ? 32767 : INT_MAX);
+        WK_REQUIRE(lo >= tmin && hi <= tmax, "particles: the momentum window (widened by n_m/2) "
+                                             "does not fit the momentum type (m_bytes)");
+    }
     g->dim = gm->dim;
     g->nx = gm->nx;
     g->ny = gm->ny;
@@ -2072,23 +2095,30 @@ extern "C" size_t sp_workspace_size(const sp_geom* gm) {
     return ws_bytes_for(g.n_bins, (long)g.nx * g.ny);
 }
 
+#define WK_DISPATCH_POS(gm, FN, MT, D, ...)                                          \
+    do {                                                                             \
+        if ((gm)->pos_f64)                                                           \
+            FN<double, MT, D>(__VA_ARGS__);                                          \
+        else                                                                         \
+            FN<float, MT, D>(__VA_ARGS__);                                           \
+    } while (0)
+
+// make_geo has accepted gm (dimension and momentum width are consistent)
 #define WK_DISPATCH(gm, FN, ...)                                                      \
     do {                                                                             \
-        if ((gm)->dim == 1 && !(gm)->m16) {                                          \
-            if ((gm)->pos_f64)                                                       \
-                FN<double, int32_t, 1>(__VA_ARGS__);                                 \
+        const int mb_ = m_bytes_of(gm);                                              \
+        if ((gm)->dim == 1) {                                                        \
+            if (mb_ == 4)                                                            \
+                WK_DISPATCH_POS(gm, FN, int32_t, 1, __VA_ARGS__);                    \
+            else if (mb_ == 2)                                                       \
+                WK_DISPATCH_POS(gm, FN, int16_t, 1, __VA_ARGS__);                    \
             else                                                                     \
-                FN<float, int32_t, 1>(__VA_ARGS__);                                  \
-        } else if ((gm)->dim == 1) {                                                 \
-            if ((gm)->pos_f64)                                                       \
-                FN<double, int16_t, 1>(__VA_ARGS__);                                 \
-            else                                                                     \
-                FN<float, int16_t, 1>(__VA_ARGS__);                                  \
+                WK_DISPATCH_POS(gm, FN, int8_t, 1, __VA_ARGS__);                     \
         } else {                                                                     \
-            if ((gm)->pos_f64)                                                       \
-                FN<double, int16_t, 2>(__VA_ARGS__);                                 \
+            if (mb_ == 2)                                                            \
+                WK_DISPATCH_POS(gm, FN, int16_t, 2, __VA_ARGS__);                    \
             else                                                                     \
-                FN<float, int16_t, 2>(__VA_ARGS__);                                  \
+                WK_DISPATCH_POS(gm, FN, int8_t, 2, __VA_ARGS__);                     \
         }                                                                            \
     } while (0)
 

@@ -167,19 +167,38 @@ def kernel_tables(V: torch.Tensor, n_m: int, dt: float, cells: torch.Tensor | No
 
 
 # ----------------------------------------------------------------------------- particles
-def geom_struct(mesh: dict, seed: int, m16: bool = False) -> L.SpGeom:
-    """m16: 1-D particle buffers hold int16 momenta (2-D momenta are always int16)."""
+def geom_struct(mesh: dict, seed: int, m_bytes: int = 0) -> L.SpGeom:
+    """m_bytes: bytes per stored momentum index (0 = the library default: 4 in 1-D, 2 in 2-D)."""
     return L.SpGeom(mesh["dim"], mesh["nx"], mesh.get("ny", 1), mesh["n_m"], mesh["n_k"],
-                    mesh["M_min"], int(mesh["pos_f64"]), int(m16), float(mesh["vdt"]), seed)
+                    mesh["M_min"], int(mesh["pos_f64"]), int(m_bytes), float(mesh["vdt"]), seed)
+
+
+_M_RANGE = {1: (-128, 127), 2: (-32768, 32767), 4: (-2 ** 31, 2 ** 31 - 1)}
+
+
+def fits_m_bytes(mesh: dict, m_bytes: int) -> bool:
+    """Whether momenta of m_bytes bytes hold the window widened by the largest pair offset
+    (children outside the window are stored, dead, with their momenta)."""
+    lo = mesh["M_min"] - mesh["n_m"] // 2
+    hi = mesh["M_min"] + mesh["n_k"] - 1 + mesh["n_m"] // 2
+    tmin, tmax = _M_RANGE[m_bytes]
+    return tmin <= lo and hi <= tmax and (m_bytes != 4 or mesh["dim"] == 1)
 
 
 def fits_m16(mesh: dict) -> bool:
-    """Whether the momentum window fits 16-bit storage."""
-    return mesh["M_min"] >= -32768 and mesh["M_min"] + mesh["n_k"] <= 32767
+    return fits_m_bytes(mesh, 2)
 
 
-def _m16(*parts) -> bool:
-    widths = {p.m16 for p in parts}
+def narrowest_m_bytes(mesh: dict) -> int:
+    """The narrowest momentum storage the mesh's window fits (fewer bytes streamed per pass)."""
+    for mb in (1, 2, 4):
+        if fits_m_bytes(mesh, mb):
+            return mb
+    raise ValueError("momentum window does not fit int32")
+
+
+def _m_bytes(*parts) -> int:
+    widths = {p.m_bytes for p in parts}
     if len(widths) != 1:
         raise ValueError("the particle buffers of one call must use the same momentum width")
     return widths.pop()
@@ -188,12 +207,18 @@ def _m16(*parts) -> bool:
 class DeviceParticles:
     """Struct-of-arrays particle buffer in HBM (positions in cell units)."""
 
-    def __init__(self, dim: int, capacity: int, pos_f64: bool, device="cuda", m16: bool = False):
-        """m16: 1-D momenta stored as int16 (7-byte particles with FP32 positions instead of
-        9); the momentum window must fit 16 bits.  2-D momenta are always int16."""
+    def __init__(self, dim: int, capacity: int, pos_f64: bool, device="cuda", m16: bool = False,
+                 m_bytes: int | None = None):
+        """m_bytes: bytes per momentum index, 4 (1-D only), 2 or 1 (default: 4 in 1-D, 2 in
+        2-D; m16 = True selects 2); the library refuses a width the mesh's window does not
+        fit.  With FP32 positions a 1-D particle takes 9, 7 or 6 bytes, a 2-D one 13 or 11."""
         ft = torch.float64 if pos_f64 else torch.float32
-        self.m16 = bool(m16) and dim == 1
-        mt = torch.int32 if (dim == 1 and not self.m16) else torch.int16
+        if m_bytes is None:
+            m_bytes = 2 if (m16 or dim == 2) else 4
+        if m_bytes not in (1, 2, 4) or (m_bytes == 4 and dim != 1):
+            raise ValueError("m_bytes must be 1, 2 or (1-D) 4")
+        self.m_bytes = int(m_bytes)
+        mt = {1: torch.int8, 2: torch.int16, 4: torch.int32}[self.m_bytes]
         self.dim, self.pos_f64, self.capacity = dim, pos_f64, int(capacity)
         self.x = torch.zeros(capacity, dtype=ft, device=device)
         self.y = torch.zeros(capacity, dtype=ft, device=device) if dim == 2 else None
@@ -244,7 +269,7 @@ def new_stats(device="cuda") -> torch.Tensor:
 
 def sp_init(mesh: dict, seed: int, bin_counts: torch.Tensor, out: DeviceParticles,
             stats: torch.Tensor, ws: torch.Tensor):
-    g = geom_struct(mesh, seed, _m16(out))
+    g = geom_struct(mesh, seed, _m_bytes(out))
     ps = out.struct()
     L.check(L.lib().sp_init(ctypes.byref(g), _ptr(bin_counts.to(torch.int32).contiguous()),
                             ctypes.byref(ps), _ptr(stats), _ptr(ws), ws.numel(), _stream()),
@@ -267,7 +292,7 @@ def sp_step(mesh: dict, seed: int, cell_slot, n0, thr, cdf, pin: DeviceParticles
             hist: torch.Tensor | None = None, guide: torch.Tensor | None = None):
     """One step from pin to pout.  hist (optional): receives the signed histogram of the
     ensemble after the step.  guide (optional): sampling_guide() of the cdf rows."""
-    g = geom_struct(mesh, seed, _m16(pin, pout))
+    g = geom_struct(mesh, seed, _m_bytes(pin, pout))
     a, b = pin.struct(), pout.struct()
     glen = 0 if guide is None else guide.shape[1] - 1
     L.check(L.lib().sp_step(ctypes.byref(g), _ptr(cell_slot), _ptr(n0), _ptr(thr), _ptr(cdf),
@@ -279,7 +304,7 @@ def sp_annihilate(mesh: dict, seed: int, pin: DeviceParticles, pout: DeviceParti
                   hist: torch.Tensor, step: int, stats: torch.Tensor, ws: torch.Tensor,
                   hist_ready: bool = False):
     """hist_ready: `hist` already holds the histogram of `pin` (from sp_step)."""
-    g = geom_struct(mesh, seed, _m16(pin, pout))
+    g = geom_struct(mesh, seed, _m_bytes(pin, pout))
     a, b = pin.struct(), pout.struct()
     L.check(L.lib().sp_annihilate(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _ptr(hist),
                                   int(bool(hist_ready)), step, _ptr(stats), _ptr(ws), ws.numel(),
@@ -299,7 +324,7 @@ def sp_annihilate_pairs(mesh: dict, pin: DeviceParticles, pout: DeviceParticles,
                         stats: torch.Tensor, ws: torch.Tensor, scratch: torch.Tensor,
                         hist_ready: bool = False):
     """Rule 2 as literal pair removal (survivors keep their exact positions)."""
-    g = geom_struct(mesh, 0, _m16(pin, pout))
+    g = geom_struct(mesh, 0, _m_bytes(pin, pout))
     a, b = pin.struct(), pout.struct()
     L.check(L.lib().sp_annihilate_pairs(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _ptr(hist),
                                         int(bool(hist_ready)), _ptr(stats), _ptr(ws), ws.numel(),

@@ -39,7 +39,7 @@ from . import learn, ops
 class Simulator:
     def __init__(self, cfg, kernel: str = "exact", prec: str = "fp64", mode: str = "occupied",
                  refresh_every: int = 8, cap_factor: float = 3.0, weights=None, N: int = 2,
-                 device="cuda", hist_in_step: bool = True, rows=None, m16=None,
+                 device="cuda", hist_in_step: bool = True, rows=None, m_bytes=None,
                  fused_tables: bool = True, annihilation: str = "regenerate"):
         self.cfg = cfg
         self.md = cfg.mesh.as_dict(cfg.dt)
@@ -97,10 +97,11 @@ class Simulator:
         bc = torch.as_tensor(cfg.bin_counts, dtype=torch.int32)
         n0 = int(bc.sum())
         self.capacity = int(cap_factor * n0) + 1024
-        # 1-D momenta in 16 bits whenever the window allows (7-byte particles with FP32 positions)
-        m16 = m16 if m16 is not None else ops.fits_m16(md)
-        self.a = ops.DeviceParticles(self.dim, self.capacity, md["pos_f64"], self.dev, m16=m16)
-        self.b = ops.DeviceParticles(self.dim, self.capacity, md["pos_f64"], self.dev, m16=m16)
+        # momenta in the narrowest integer type the window allows (int8 for the workloads here:
+        # 6-byte 1-D and 11-byte 2-D particles with FP32 positions)
+        m_bytes = m_bytes if m_bytes is not None else ops.narrowest_m_bytes(md)
+        self.a = ops.DeviceParticles(self.dim, self.capacity, md["pos_f64"], self.dev, m_bytes=m_bytes)
+        self.b = ops.DeviceParticles(self.dim, self.capacity, md["pos_f64"], self.dev, m_bytes=m_bytes)
         self.stats = ops.new_stats(self.dev)
         self.ws = ops.sp_workspace(md, self.seed, self.dev)
         self.hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=self.dev)
@@ -225,7 +226,7 @@ class Simulator:
         return {"mesh": self.md, "seed": int(self.seed), "kernel": self.kernel, "prec": self.prec,
                 "mode": self.mode, "refresh_every": self.refresh_every, "N": int(self.N),
                 "annihilation": self.annihilation, "hist_in_step": bool(self.hist_in_step),
-                "fused": bool(self.fused), "glen": self.glen, "m16": bool(self.a.m16)}
+                "fused": bool(self.fused), "glen": self.glen, "m_bytes": self.a.m_bytes}
 
     def checkpoint(self) -> dict:
         """The state the time loop carries from one step to the next, copied to host memory:

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     lib = _lib.lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.wk_version() == 3
+    assert lib.wk_version() == 4
 
 
 def test_python_binding_names_match_header():
@@ -145,18 +145,53 @@ def test_struct_layouts_match_header(tmp_path):
 
 
 def test_momentum_width_rules():
-    """16-bit 1-D momenta: chosen per buffer, refused when the buffers of a call disagree
-    (checked on the host before any library call)."""
+    """Momentum storage width: chosen per buffer (int32, int16 or int8), the narrowest that
+    holds the window widened by the largest pair offset; refused when the buffers of a call
+    disagree (checked on the host before any library call)."""
     import torch
     from paper_1806_00082_amd import inputs, ops
-    md = inputs.config_c1().mesh.as_dict(1.0)
-    assert ops.fits_m16(md)
+    md = inputs.config_c1().mesh.as_dict(1.0)          # M in [-30, 30), n_m = 30
+    assert ops.fits_m16(md) and ops.fits_m_bytes(md, 1) and ops.narrowest_m_bytes(md) == 1
     assert not ops.fits_m16(dict(md, M_min=-40000))
+    assert ops.narrowest_m_bytes(dict(md, M_min=-113)) == 1    # -113 - 15 = -128
+    assert ops.narrowest_m_bytes(dict(md, M_min=-114)) == 2
+    assert ops.narrowest_m_bytes(dict(md, M_min=-32768 + 15)) == 2
+    assert ops.narrowest_m_bytes(dict(md, M_min=-32768 + 14)) == 4
+    md2 = inputs.config_c5().mesh.as_dict(0.5)        # 2-D: M in [-32, 32), n_m = 32
+    assert ops.narrowest_m_bytes(md2) == 1
+    assert not ops.fits_m_bytes(md2, 4)                # 2-D momenta are at most 16 bits
     a = ops.DeviceParticles(1, 8, True, device="cpu")
     b = ops.DeviceParticles(1, 8, True, device="cpu", m16=True)
-    c = ops.DeviceParticles(2, 8, False, device="cpu", m16=True)
+    c = ops.DeviceParticles(2, 8, False, device="cpu")
+    d = ops.DeviceParticles(2, 8, False, device="cpu", m_bytes=1)
+    e = ops.DeviceParticles(1, 8, False, device="cpu", m_bytes=1)
     assert a.M.dtype == torch.int32 and b.M.dtype == torch.int16
-    assert c.M.dtype == torch.int16 and not c.m16  # 2-D momenta are always 16-bit
+    assert c.M.dtype == torch.int16 and c.My.dtype == torch.int16 and c.m_bytes == 2
+    assert d.M.dtype == torch.int8 and d.My.dtype == torch.int8 and e.M.dtype == torch.int8
+    with pytest.raises(ValueError):
+        ops.DeviceParticles(2, 8, False, device="cpu", m_bytes=4)
+    with pytest.raises(ValueError):
+        ops.DeviceParticles(1, 8, False, device="cpu", m_bytes=3)
     with pytest.raises(ValueError):
         ops.sp_annihilate(md, 0, a, b, None, 0, None, None)
-    assert ops.geom_struct(md, 0, True).m16 == 1
+    with pytest.raises(ValueError):
+        ops.sp_annihilate(md, 0, b, e, None, 0, None, None)
+    assert ops.geom_struct(md, 0, 2).m_bytes == 2
+
+
+def test_momentum_width_checked_by_the_library():
+    """sp_workspace_size validates the geometry (0 = refused) without touching a device: the
+    momentum type must hold the window widened by n_m / 2, and 2-D momenta are not int32."""
+    from paper_1806_00082_amd import _lib
+    lib = _lib.lib()
+
+    def ok(dim, n_m, n_k, M_min, mb):
+        g = _lib.SpGeom(dim, 10, 1 if dim == 1 else 10, n_m, n_k, M_min, 0, mb, 0.1, 0)
+        return lib.sp_workspace_size(ctypes.byref(g)) > 0
+
+    assert ok(1, 30, 60, -30, 1) and ok(1, 30, 60, -30, 2) and ok(1, 30, 60, -30, 4) and ok(1, 30, 60, -30, 0)
+    assert ok(1, 30, 60, -113, 1) and not ok(1, 30, 60, -114, 1)        # low end: -113 - 15 = -128
+    assert ok(1, 30, 226, -113, 1) and not ok(1, 30, 227, -113, 1)      # high end: -113 + 225 + 15 = 127
+    assert ok(2, 32, 64, -32, 1) and ok(2, 32, 64, -32, 2) and ok(2, 32, 64, -32, 0)
+    assert not ok(2, 32, 64, -32, 4) and not ok(1, 30, 60, -30, 3) and not ok(2, 32, 64, -32, -1)
+    assert not ok(2, 32, 64, -32768, 2) and ok(2, 32, 64, -32768 + 16, 2)

@@ -24,16 +24,16 @@ def _mixed(orc, md, n, seed, span=6, cap=None):
     return p
 
 
-def _gpu(md, hp, cap, m16=False):
+def _gpu(md, hp, cap, m_bytes=None):
     v = hp.view()
-    a = ops.DeviceParticles(md["dim"], cap, md["pos_f64"], m16=m16)
+    a = ops.DeviceParticles(md["dim"], cap, md["pos_f64"], m_bytes=m_bytes)
     a.load(hp.n, v["x"], v["M"], v["s"], y=v.get("y"), My=v.get("My"))
     return a
 
 
-def _check_once(orc, md, hp, cap, hist_ready, m16=False):
-    a = _gpu(md, hp, cap, m16)
-    b = ops.DeviceParticles(md["dim"], cap, md["pos_f64"], m16=m16)
+def _check_once(orc, md, hp, cap, hist_ready, m_bytes=None):
+    a = _gpu(md, hp, cap, m_bytes)
+    b = ops.DeviceParticles(md["dim"], cap, md["pos_f64"], m_bytes=m_bytes)
     st = ops.new_stats()
     ws = ops.sp_workspace(md)
     nb = ops.n_bins(md)
@@ -54,16 +54,17 @@ def _check_once(orc, md, hp, cap, hist_ready, m16=False):
 
 
 @pytest.mark.parametrize("hist_ready", [False, True])
-@pytest.mark.parametrize("case", ["1d_f64", "1d_f32_m16", "2d"])
+@pytest.mark.parametrize("case", ["1d_f64", "1d_f32_m16", "1d_f32_m8", "2d", "2d_m8"])
 def test_pair_removal_small(orc, case, hist_ready):
-    if case == "2d":
+    if case.startswith("2d"):
         md = {"dim": 2, "nx": 8, "ny": 3, "n_m": 8, "n_k": 8, "M_min": -4, "pos_f64": False, "vdt": 0.1}
     else:
         md = {"dim": 1, "nx": 8, "ny": 1, "n_m": 8, "n_k": 16, "M_min": -8,
               "pos_f64": case == "1d_f64", "vdt": 0.1}
     for seed, n in ((0, 300), (1, 5000), (2, 70000)):
         hp = _mixed(orc, md, n, seed)
-        rst = _check_once(orc, md, hp, n + 16, hist_ready, m16=case == "1d_f32_m16")
+        mb = {"1d_f32_m16": 2, "1d_f32_m8": 1, "2d_m8": 1}.get(case)
+        rst = _check_once(orc, md, hp, n + 16, hist_ready, m_bytes=mb)
         assert rst[orc.ST_MIXED] > 0
 
 

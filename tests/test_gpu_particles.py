@@ -21,21 +21,21 @@ def _setup(orc, cfg, N0_scale=1.0, cap_factor=3):
     return md, tables[1:], bc, cap
 
 
-def _gpu_init(md, bc, cap, seed, m16=False):
-    p = ops.DeviceParticles(md["dim"], cap, md["pos_f64"], m16=m16)
+def _gpu_init(md, bc, cap, seed, m_bytes=None):
+    p = ops.DeviceParticles(md["dim"], cap, md["pos_f64"], m_bytes=m_bytes)
     st = ops.new_stats()
     ws = ops.sp_workspace(md, seed)
     ops.sp_init(md, seed, torch.from_numpy(bc).to(dev()), p, st, ws)
     return p, st, ws
 
 
-@pytest.mark.parametrize("m16", [False, True])
+@pytest.mark.parametrize("m_bytes", [4, 2, 1])
 @pytest.mark.parametrize("cfgname", ["c1", "c2small"])
-def test_init_bit_exact(orc, cfgname, m16):
+def test_init_bit_exact(orc, cfgname, m_bytes):
     cfg = inputs.config_c1() if cfgname == "c1" else inputs.config_c2(N0=2e5)
     md, _, bc, cap = _setup(orc, cfg)
     hp = orc.sp_init(md, bc, cap, seed=cfg.seed)
-    p, st, ws = _gpu_init(md, bc, cap, cfg.seed, m16)
+    p, st, ws = _gpu_init(md, bc, cap, cfg.seed, m_bytes)
     assert p.count() == hp.n
     assert_particles_equal(p.view(), hp.view(), "sp_init")
 
@@ -51,16 +51,26 @@ def test_init_overflow_reports_needed(orc):
     assert p.count() == 0
 
 
-def _run_both(orc, cfg, steps, N0_scale=1.0, check_every=1, m16=False):
+def _odd_word_hist(n):
+    """A zeroed int32 histogram that starts 4 bytes into an 8-byte word (the flush pairs
+    counters by their address in the caller's array)."""
+    h = torch.zeros(n + 1, dtype=torch.int32, device=dev())[1:]
+    assert h.data_ptr() % 8 == 4
+    return h
+
+
+def _run_both(orc, cfg, steps, N0_scale=1.0, check_every=1, m_bytes=None, odd_hist=False):
     """Run the oracle and the GPU side by side from the same start, comparing every step
-    (m16: the GPU buffers hold 16-bit momenta)."""
+    (m_bytes: bytes per momentum in the GPU buffers; odd_hist: the histogram array starts at
+    an odd 4-byte word)."""
     md, tables, bc, cap = _setup(orc, cfg, N0_scale)
     seed = cfg.seed
     slot = np.arange(md["nx"], dtype=np.int32)
     hp = orc.sp_init(md, bc, cap, seed=seed)
-    a, st, ws = _gpu_init(md, bc, cap, seed, m16)
-    b = ops.DeviceParticles(1, cap, md["pos_f64"], m16=m16)
-    hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev())
+    a, st, ws = _gpu_init(md, bc, cap, seed, m_bytes)
+    b = ops.DeviceParticles(1, cap, md["pos_f64"], m_bytes=m_bytes)
+    hist = (_odd_word_hist(2 * ops.n_bins(md)) if odd_hist
+            else torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev()))
     n0, thr, cdf = host_tables_to_device((None,) + tuple(tables))
     slot_d = torch.from_numpy(slot).to(dev())
     guide = ops.sampling_guide(cdf, min(cdf.shape[1], 256))
@@ -94,34 +104,36 @@ def _run_both(orc, cfg, steps, N0_scale=1.0, check_every=1, m16=False):
     return md, hp, a, hist
 
 
-@pytest.mark.parametrize("m16", [False, True])
-def test_c1_loop_bit_exact(orc, m16):
-    """1-D FP64 workload (1e5 particles), 12 full steps, every array compared every step."""
-    _run_both(orc, inputs.config_c1(), steps=12, m16=m16)
+@pytest.mark.parametrize("m_bytes,odd_hist", [(4, False), (2, False), (1, False), (4, True), (1, True)])
+def test_c1_loop_bit_exact(orc, m_bytes, odd_hist):
+    """1-D FP64 workload (1e5 particles), 12 full steps, every array compared every step;
+    also with the histogram starting at an odd 4-byte word."""
+    _run_both(orc, inputs.config_c1(), steps=12, m_bytes=m_bytes, odd_hist=odd_hist)
 
 
-@pytest.mark.parametrize("m16", [False, True])
-def test_c2_loop_bit_exact_small(orc, m16):
+@pytest.mark.parametrize("m_bytes", [4, 2, 1])
+def test_c2_loop_bit_exact_small(orc, m_bytes):
     """1-D FP32 positions, 80 pseudo-momenta, 2e5 particles, 10 steps."""
-    _run_both(orc, inputs.config_c2(N0=2e5), steps=10, m16=m16)
+    _run_both(orc, inputs.config_c2(N0=2e5), steps=10, m_bytes=m_bytes)
 
 
-@pytest.mark.parametrize("m16", [False, True])
-def test_c2_full_size_steps(orc, m16):
+@pytest.mark.parametrize("m_bytes", [4, 1])
+def test_c2_full_size_steps(orc, m_bytes):
     """The paper-shaped workload at its full 1e7 particles for 3 steps, bit-exact (the
     benchmark's buffers hold 16-bit momenta)."""
-    print(f"c2 full size: 1e7 particles, m16={m16}", flush=True)
-    _run_both(orc, inputs.config_c2(), steps=3, m16=m16)
+    print(f"c2 full size: 1e7 particles, m_bytes={m_bytes}", flush=True)
+    _run_both(orc, inputs.config_c2(), steps=3, m_bytes=m_bytes)
 
 
 def test_mixed_momentum_widths_refused():
     md = inputs.config_c1().mesh.as_dict(1.0)
-    a = ops.DeviceParticles(1, 16, True)
-    b = ops.DeviceParticles(1, 16, True, m16=True)
     st = ops.new_stats()
-    with pytest.raises(ValueError):
-        ops.sp_annihilate(md, 0, a, b, torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev()),
-                          0, st, ops.sp_workspace(md))
+    for wa, wb in ((4, 2), (2, 1), (4, 1)):
+        a = ops.DeviceParticles(1, 16, True, m_bytes=wa)
+        b = ops.DeviceParticles(1, 16, True, m_bytes=wb)
+        with pytest.raises(ValueError):
+            ops.sp_annihilate(md, 0, a, b, torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev()),
+                              0, st, ops.sp_workspace(md))
 
 
 def test_density_readout(orc):
@@ -231,11 +243,13 @@ def test_cell_slot_subset(orc):
     assert_particles_equal(b.view(), ref.view(), "cell subset")
 
 
-@pytest.mark.parametrize("nx,ny", [(24, 20), (40, 36)])
-def test_2d_step_and_annihilation(orc, nx, ny):
+@pytest.mark.parametrize("nx,ny,odd_hist,m_bytes", [(24, 20, False, 2), (40, 36, False, 2), (24, 20, True, 2),
+                                                     (24, 20, False, 1), (40, 36, False, 1)])
+def test_2d_step_and_annihilation(orc, nx, ny, odd_hist, m_bytes):
     """2-D passes (int16 momenta, FP32 positions), bit-exact, 4 steps; the larger mesh (more
     cells than the LDS creation table holds) takes the cell-indexed table in the workspace,
-    with some cells mapped to no table row."""
+    with some cells mapped to no table row; odd_hist: the histogram array starts at an odd
+    4-byte word; m_bytes: 16- or 8-bit momenta."""
     mesh = inputs.Mesh2D(nx=nx, ny=ny, dx=0.5, n_m=8, pos_f64=False)
     md = mesh.as_dict(0.5)
     V = inputs.gaussian_dot_2d(mesh, 0.2, 1.5, 6.0, 5.0)
@@ -245,10 +259,11 @@ def test_2d_step_and_annihilation(orc, nx, ny):
     cap = 4 * int(bc.sum())
     seed = 11
     hp = orc.sp_init(md, bc, cap, seed=seed)
-    a, st, ws = _gpu_init(md, bc, cap, seed)
+    a, st, ws = _gpu_init(md, bc, cap, seed, m_bytes)
     assert_particles_equal(a.view(), hp.view(), "2-D init")
-    b = ops.DeviceParticles(2, cap, False)
-    hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev())
+    b = ops.DeviceParticles(2, cap, False, m_bytes=m_bytes)
+    hist = (_odd_word_hist(2 * ops.n_bins(md)) if odd_hist
+            else torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev()))
     slot = np.arange(nx * ny, dtype=np.int32)
     if nx * ny > 1024:
         slot[::7] = -1
@@ -322,12 +337,12 @@ def _max_keys_per_workgroup(hp_view, md, n_wg=2048, waves=4):
     return best
 
 
-def _c5_compare(orc, md, tables, slot, hp, seed, steps, first_step, label):
+def _c5_compare(orc, md, tables, slot, hp, seed, steps, first_step, label, m_bytes=2):
     cap = hp.capacity
-    a = ops.DeviceParticles(2, cap, False)
+    a = ops.DeviceParticles(2, cap, False, m_bytes=m_bytes)
     v = hp.view()
     a.load(hp.n, v["x"], v["M"], v["s"], y=v["y"], My=v["My"])
-    b = ops.DeviceParticles(2, cap, False)
+    b = ops.DeviceParticles(2, cap, False, m_bytes=m_bytes)
     st = ops.new_stats()
     ws = ops.sp_workspace(md, seed)
     hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev())
@@ -370,18 +385,21 @@ def _c5_compare(orc, md, tables, slot, hp, seed, steps, first_step, label):
     return hp
 
 
-def test_c5_full_size_steps(orc):
+@pytest.mark.parametrize("m_bytes", [2, 1])
+def test_c5_full_size_steps(orc, m_bytes):
     """The 2-D workload at its full size (256 x 256 cells, 32 x 32 momenta, 5e7 particles):
     two steps from the initial state, bit-exact, every array, both histogram paths (built by
-    sp_annihilate, then by sp_step), the 67M-bin histogram compared whole.  The oracle's kernel
-    rows are its direct d = 2 sum on every cell the particles can reach."""
+    sp_annihilate, then by sp_step), the 67M-bin histogram compared whole, with 16- and 8-bit
+    momenta.  The oracle's kernel rows are its direct d = 2 sum on every cell the particles
+    can reach."""
     cfg = inputs.config_c5()
     md = cfg.mesh.as_dict(cfg.dt)
     occ = cfg.bin_counts.reshape(md["ny"], md["nx"], -1).sum(-1) > 0
     md, tables, slot = _c5_tables(orc, cfg, occ, steps=2)
     n = int(cfg.bin_counts.sum())
     hp = orc.sp_init(md, cfg.bin_counts, int(1.3 * n), seed=cfg.seed)
-    _c5_compare(orc, md, tables, slot, hp, cfg.seed, steps=2, first_step=0, label="c5 init")
+    _c5_compare(orc, md, tables, slot, hp, cfg.seed, steps=2, first_step=0, label=f"c5 init m{8 * m_bytes}",
+                m_bytes=m_bytes)
 
 
 def test_c5_full_size_mixed_ensemble(orc):
@@ -404,7 +422,8 @@ def test_c5_full_size_mixed_ensemble(orc):
     hp.s[n1:n1 + n2] = -1
     hp.n = n1 + n2
     del hm
-    out = _c5_compare(orc, md, tables, slot, hp, cfg.seed, steps=2, first_step=4, label="c5 mixed")
+    out = _c5_compare(orc, md, tables, slot, hp, cfg.seed, steps=2, first_step=4, label="c5 mixed",
+                      m_bytes=1)
     assert out.n < n1 + n2  # annihilation removed particles
 
 

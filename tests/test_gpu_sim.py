@@ -148,7 +148,7 @@ def test_2d_full_size_histogram_recount():
     for _ in range(3):
         sim.step()
     md = sim.md
-    out = ops.DeviceParticles(2, sim.capacity, md["pos_f64"])
+    out = ops.DeviceParticles(2, sim.capacity, md["pos_f64"], m_bytes=sim.a.m_bytes)
     hist = torch.zeros_like(sim.hist)
     ops.sp_step(md, sim.seed, sim.cell_slot, sim.n0, sim.thr, sim.cdf, sim.a, out, sim.step_index,
                 sim.stats, sim.ws, hist=hist, guide=sim.guide)
@@ -233,12 +233,13 @@ def test_barrier_reflection_gpu():
     assert not sim.overflowed()
     v = sim.a.view()
     assert np.all(v["s"] != 0)
-    b = (np.floor(v["x"]).astype(np.int64) * sim.md["n_k"] + (v["M"] - sim.md["M_min"]))
+    M = v["M"].astype(np.int64)                  # stored in the narrowest type (int8 here)
+    b = (np.floor(v["x"]).astype(np.int64) * sim.md["n_k"] + (M - sim.md["M_min"]))
     pos = np.bincount(b[v["s"] > 0], minlength=nb)
     neg = np.bincount(b[v["s"] < 0], minlength=nb)
     assert not np.any((pos > 0) & (neg > 0))
     s = v["s"].astype(np.float64)
-    assert (s * v["M"]).sum() / s.sum() < -0.8 * k0 / mesh.dk
+    assert (s * M).sum() / s.sum() < -0.8 * k0 / mesh.dk
 
 
 @pytest.mark.parametrize("dim,nx,ny,margin", [(1, 300, 1, 3), (2, 37, 23, 2), (2, 64, 50, 0), (2, 20, 70, 25)])
