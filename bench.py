@@ -45,10 +45,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # by what the counters read for a 1 GiB device copy (fetch x2.0, write x1.0).  Taken for the
 # kernels as they are now; an entry is dropped when its kernel changes until the counters are
 # taken again.
-TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1348, "annih_bins": 0.0008,
-                  "annih_count": 0.0618, "annih_write": 0.1245},
-           "2d": {"step_count": 1.1881, "step_apply": 2.1781, "annih_bins": 0.548,
-                  "annih_count": 0.8137, "annih_write": 1.6508}}
+TRAFFIC = {"1d": {}, "2d": {}}
 
 
 def _events():
@@ -63,13 +60,16 @@ def _events():
 # clears or walks the signed histogram (2-D: 2 x 4 B x 67M bins, beyond every cache), that
 # histogram (the 1-bit mixed-bin map annih_bins writes, 1/64 of it, is not counted).  The 1-D histogram and all tables are L2-resident and not counted; neither are
 # the pair counts the two sp_step passes hand over (an implementation choice).
-def kernel_bytes(PB: int, dim: int, hist_bytes: int):
+def kernel_bytes(PB: int, dim: int, hist_bytes: int, walked_bytes=None):
+    """walked_bytes: histogram bytes the bin pass had to read over the run (2-D: the blocks
+    of bins that held counts, which the step marks; None = the whole histogram each step)."""
     pos = 4 * dim + 1            # what the counting pass reads: positions and sign
     H = hist_bytes if dim == 2 else 0
+    walk = (lambda S, L: H * S[L.ST_CUM_STEPS]) if walked_bytes is None else (lambda S, L: walked_bytes)
     return {
         "step_count": lambda S, L: pos * S[L.ST_CUM_N] + H * S[L.ST_CUM_STEPS],      # + histogram clear
         "step_apply": lambda S, L: 2 * PB * (S[L.ST_CUM_N] + S[L.ST_CUM_PAIRS]),     # read, write; 2 children
-        "annih_bins": lambda S, L: H * S[L.ST_CUM_STEPS],                             # histogram walk
+        "annih_bins": walk,                                                           # histogram walk
         "annih_count": lambda S, L: PB * S[L.ST_CUM_ANNIH_IN],                       # read
         "annih_write": lambda S, L: PB * (S[L.ST_CUM_ANNIH_IN] + S[L.ST_CUM_KEPT]
                                           + S[L.ST_CUM_REGEN]),                      # read, write kept + placed
@@ -77,10 +77,11 @@ def kernel_bytes(PB: int, dim: int, hist_bytes: int):
 
 
 def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str = "regenerate",
-                  m_bytes=None):
+                  m_bytes=None, ms_ref=None):
     """A time-loop workload.  traced=True replays the identical (bit-exact, same seed) run with
     per-kernel events, used only for the per-kernel roofline; the reported value comes from
-    the untraced run.  m_bytes: momentum storage (default: the narrowest that fits)."""
+    the untraced run, whose time (ms_ref) the whole-step roofline uses.  m_bytes: momentum
+    storage (default: the narrowest that fits)."""
     import torch
     from paper_1806_00082_amd import _lib as L
     from paper_1806_00082_amd import ops
@@ -94,11 +95,24 @@ def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str 
     if traced:
         L.check(L.lib().wk_trace_enable(steps * 24 + 64), "wk_trace_enable")
     torch.cuda.synchronize()
+    # traced replica, 2-D: the blocks of bins each step's histogram holds counts in, which the
+    # bin pass of the annihilation reads (measured between the steps, on the GPU, outside the
+    # traced kernels)
+    walked = torch.zeros((), dtype=torch.int64, device=sim.dev) if traced and sim.dim == 2 else None
+    blk = 256
+    while -(-ops.n_bins(sim.md) // blk) > 65536:
+        blk *= 2
     t0, t1 = _events()
     wall0 = time.perf_counter()
     t0.record()
     for _ in range(steps):
         sim.step()
+        if walked is not None:
+            h = sim.hist.view(2, -1)
+            pad = (-h.shape[1]) % blk
+            if pad:
+                h = torch.nn.functional.pad(h, (0, pad))
+            walked += (h.view(2, -1, blk) != 0).any(dim=2).any(dim=0).sum()
     t1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -119,7 +133,10 @@ def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str 
     if not traced:
         return out
     L.check(L.lib().wk_trace_disable(), "wk_trace_disable")
-    KB = kernel_bytes(pbytes, dim, hist_bytes)
+    walked_bytes = None if walked is None else int(walked.item()) * blk * 2 * 4
+    out["walked_hist_fraction"] = (None if walked_bytes is None
+                                   else round(walked_bytes / (hist_bytes * steps), 4))
+    KB = kernel_bytes(pbytes, dim, hist_bytes, walked_bytes)
     kernels = {}
     for name in L.trace_names():
         tot, cnt = L.trace_read(name)
@@ -142,9 +159,10 @@ def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str 
                        "us_per_launch": kernels[dom]["us_avg"]}
     # the whole step against the sum of its kernels' algorithmic bytes
     tot_b = sum(KB[k](S, L) for k in KB)
+    ms_step = ms if ms_ref is None else ms_ref
     out["step_roofline"] = {"alg_GB_per_step": round(tot_b / steps / 1e9, 4),
-                            "achieved_GBps": round(tot_b / (ms * 1e-3) / 1e9, 1),
-                            "frac": round(tot_b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                            "achieved_GBps": round(tot_b / (ms_step * 1e-3) / 1e9, 1),
+                            "frac": round(tot_b / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     return out
 
 
@@ -383,7 +401,7 @@ def run_annihilation_modes():
         rec = {}
         for mode in ("regenerate", "pairs"):
             u = run_particles(cfg, steps, warm, traced=False, annihilation=mode)
-            r = run_particles(cfg, steps, warm, traced=True, annihilation=mode)
+            r = run_particles(cfg, steps, warm, traced=True, annihilation=mode, ms_ref=u["ms"])
             k = r["kernels"]
             annih = {n: v["us_avg"] for n, v in k.items()
                      if n.startswith(("annih", "pair", "radix", "hist_"))}
@@ -749,14 +767,14 @@ def main():
     h = run_particles(cfg, args.steps, args.warmup, traced=False, m_bytes=args.m_bytes)
     tr = h
     if not args.no_trace:
-        tr = run_particles(cfg, args.steps, args.warmup, traced=True, m_bytes=args.m_bytes)
+        tr = run_particles(cfg, args.steps, args.warmup, traced=True, m_bytes=args.m_bytes, ms_ref=h["ms"])
         assert tr["stats"][11:16] == h["stats"][11:16], "traced replica diverged from the timed run"
     forms = {}
     if not args.no_forms and not args.headline_1d:
         print("secondary: 1-D 1e7-particle run", file=sys.stderr, flush=True)
         c2 = inputs.config_c2()
         s1 = run_particles(c2, 390, 10, traced=False)
-        s1t = run_particles(c2, 390, 10, traced=True)
+        s1t = run_particles(c2, 390, 10, traced=True, ms_ref=s1["ms"])
         assert s1t["stats"][11:16] == s1["stats"][11:16], "traced replica diverged from the timed run"
         forms["workload_1d"] = {
             "workload": f"{c2.name}: 1-D, 400 cells x 80 m, 1e7 particles, 390 timed steps",
@@ -804,6 +822,7 @@ def main():
         "run": {"n_last": h["n_last"], "pairs_created": h["pairs"], "regenerated": h["regen"],
                 "kernel_rows_evaluated": h["rows"], "wall_s": round(h["wall_s"], 3),
                 "traced_replica_ms_per_step": round(tr["ms"] / args.steps, 4),
+                "histogram_fraction_walked": tr.get("walked_hist_fraction"),
                 "kernels": tr.get("kernels"), "step_roofline": tr.get("step_roofline")},
         "roofline": tr.get("roofline"),
         "cpu_baseline": cpu,

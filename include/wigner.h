@@ -257,7 +257,7 @@ int sp_init(const sp_geom* g, const int32_t* bin_counts, sp_particles* out, int6
  *   in, out  distinct buffers; *out->d_n receives n + 2 * pairs.
  *   hist  NULL, or [2][n_bins] int32 that receives the signed histogram of rule 1 (H+ then
  *         H-) of the particles after the step -- the input of the next sp_annihilate,
- *         which then need not build it (hist_ready = 1).
+ *         which then need not build it (hist_ready = 1, or 2 with this same workspace).
  * If out cannot hold n + 2 * pairs particles, d_stats[WK_ST_NEEDED] gets the required
  * capacity, the sticky WK_ST_OVERFLOW flag is set and `out` is invalid; `in` is never
  * written, and because the random stream is counter-based, re-running the step into a
@@ -277,8 +277,13 @@ int sp_step(const sp_geom* g, const int32_t* cell_slot, const uint32_t* n0, cons
  * only, unchanged and in input order.
  *   hist [2][n_bins] int32, caller-owned: with hist_ready = 0 it is rebuilt here from
  *   `in`; with hist_ready = 1 it must already hold the histogram of `in` (as sp_step
- *   leaves it).  Either way it is left holding H+ then H- of the input: the signed
- *   histogram of rule 1.  If the output would exceed out->capacity, d_stats gets the
+ *   leaves it, or as the caller wrote it); hist_ready = 2 promises more: the last call on
+ *   this same workspace that built a histogram (sp_step with hist, or an annihilation with
+ *   hist_ready = 0) built this one, and `hist` is unchanged since.  That call also left in
+ *   the workspace a map of the blocks of bins it added counts to, and the annihilation then
+ *   reads only those blocks of the histogram (the rest are zero).  Any other value is
+ *   refused (WK_EINVAL).  Either way `hist` is left holding H+ then H- of
+ *   the input: the signed histogram of rule 1.  If the output would exceed out->capacity, d_stats gets the
  *   needed size, the sticky overflow flag is set and `out` is invalid (`in` is untouched). */
 int sp_annihilate(const sp_geom* g, const sp_particles* in, sp_particles* out, int32_t* hist,
                   int32_t hist_ready, int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes,

@@ -34,11 +34,16 @@ struct Geo {
     long n_bins;
     long n_chunks;    // bin chunks of BC bins
     long gpb;         // bin chunks per bin workgroup (PB bin workgroups)
+    int bshift;       // bins per block of the block map: 2^bshift (a multiple of BC)
     double vdt;
     uint64_t seed;
 };
 
 constexpr int BC = PT;      // bins per bin chunk
+// The block map: one bit per block of consecutive bins (2^Geo::bshift bins, at least BC and
+// as many as keep the blocks within BMW * 32), set by the histogram builders wherever they add
+// counts.  The bin pass of the annihilation then reads only the histogram of marked blocks.
+constexpr int BMW = 2048;
 constexpr int WPB = PT / 64;  // waves per workgroup
 constexpr int NW = PB * WPB;  // wave chunks of the ordered passes
 // sp_step on large buffers: twice the chunk owners.  Per-chunk work varies (creation and
@@ -78,6 +83,8 @@ struct WS {
     uint8_t* occ;
     uint2* ctab;        // meshes above CT_MAX cells: (n0, thr) per cell, gathered each step
     uint32_t* mixbits;  // one bit per bin: set when the bin holds both signs (annih_bins)
+    uint32_t* blkmap;   // one bit per block of 2^bshift bins: set when the histogram builder
+                        // added counts there (BMW words)
 };
 
 static long n_chunks_for(long n_bins) { return (n_bins + BC - 1) / BC; }
@@ -101,6 +108,7 @@ static WS carve(void* ws, long n_bins, long n_cells) {
     w.ctab = reinterpret_cast<uint2*>((e + 7) & ~(uintptr_t)7);
     const uintptr_t f = reinterpret_cast<uintptr_t>(w.ctab) + sizeof(uint2) * (n_cells > CT_MAX ? (size_t)n_cells : 0);
     w.mixbits = reinterpret_cast<uint32_t*>((f + 15) & ~(uintptr_t)15);
+    w.blkmap = w.mixbits + 8 * (size_t)n_chunks_for(n_bins);
     return w;
 }
 
@@ -109,7 +117,8 @@ static size_t ws_bytes_for(long n_bins, long n_cells) {
            sizeof(int) * (size_t)(PLACE_WAVES + (n_chunks_for(n_bins) + 1) / 2 * 2) +
            2 * (size_t)n_cells +  // occupancy byte per cell, then its dilation along x
            8 + sizeof(uint2) * (n_cells > CT_MAX ? (size_t)n_cells : 0) +  // aligned ctab
-           16 + sizeof(uint32_t) * 8 * (size_t)n_chunks_for(n_bins);       // aligned mixbits
+           16 + sizeof(uint32_t) * 8 * (size_t)n_chunks_for(n_bins) +      // aligned mixbits
+           sizeof(uint32_t) * BMW;                                          // block map
 }
 
 constexpr int IT = 4;          // particles per lane in the streaming passes
@@ -517,12 +526,22 @@ __device__ void store_counts(const WS& w, long long wave_count, long long* redw)
 // probing, keys claimed by compare-and-swap), flushed once per workgroup; a key that finds
 // no slot within HPROBE probes goes to the global histogram.  Integer sums: the histogram
 // is the same whichever way a count travels.
-template <int W, bool HASH = false>
+template <int W, bool HASH = false, bool MARK = false>
 struct HistWindow {
     int* lh;  // [2][W] in LDS: window counts per sign, or (HASH) keys then counts
     long base;
     int32_t* hist;
     long n_bins;
+    uint32_t* bm;    // [BMW] in LDS: the workgroup's block map
+    uint32_t* gmap;  // [BMW] the block map in the workspace (OR-ed in by flush)
+    int bshift;
+
+    __device__ __forceinline__ void mark(long b) {
+        if constexpr (MARK) {
+            const uint32_t k = (uint32_t)(b >> bshift);
+            atomicOr(&bm[k >> 5], 1u << (k & 31u));
+        }
+    }
 
     static_assert(!HASH || (W & (W - 1)) == 0, "hash table size must be a power of two");
     // probes before a key gives up on the table: once it fills, long probes cost more LDS
@@ -553,13 +572,16 @@ struct HistWindow {
                 }
                 h = (h + 1) & (uint32_t)(W - 1);
             }
+            mark(b);
             atomicAdd(&hist[sg * n_bins + b], cnt);
         } else {
             const int k = (int)b - (int)base;  // bins and base are below 2^31
-            if ((unsigned)k < (unsigned)W)
+            if ((unsigned)k < (unsigned)W) {
                 atomicAdd(&lh[sg * W + k], cnt);
-            else
+            } else {
+                mark(b);
                 atomicAdd(&hist[sg * n_bins + b], cnt);
+            }
         }
     }
 
@@ -586,6 +608,8 @@ struct HistWindow {
     // smallest live bin among the block's candidates -> window base (uniform in the block)
     __device__ void init(long b_min_thread, long* wminw) {
         for (int k = threadIdx.x; k < 2 * W; k += PT) lh[k] = (HASH && k < W) ? (int)EMPTY : 0;
+        if constexpr (MARK)
+            for (int k = threadIdx.x; k < BMW; k += PT) bm[k] = 0u;
         long b0 = b_min_thread;
         for (int o = 32; o > 0; o >>= 1) b0 = min(b0, (long)__shfl_xor(b0, o, 64));
         if ((threadIdx.x & 63) == 0) wminw[threadIdx.x >> 6] = b0;
@@ -603,15 +627,24 @@ struct HistWindow {
             for (int k = threadIdx.x; k < W; k += PT) {
                 const uint32_t key = keys[k];
                 const int v = lh[W + k];
-                if (key != EMPTY && v != 0) atomicAdd(&hist[(long)(key & 1u) * n_bins + (long)(key >> 1)], v);
+                if (key != EMPTY && v != 0) {
+                    mark((long)(key >> 1));
+                    atomicAdd(&hist[(long)(key & 1u) * n_bins + (long)(key >> 1)], v);
+                }
             }
-            return;
+        } else {
+            for (int k = threadIdx.x; k < W; k += PT) {
+                const long b = base + k;
+                if (b >= n_bins) break;
+                if (lh[k] | lh[W + k]) mark(b);
+                if (lh[k]) atomicAdd(&hist[b], lh[k]);
+                if (lh[W + k]) atomicAdd(&hist[n_bins + b], lh[W + k]);
+            }
         }
-        for (int k = threadIdx.x; k < W; k += PT) {
-            const long b = base + k;
-            if (b >= n_bins) break;
-            if (lh[k]) atomicAdd(&hist[b], lh[k]);
-            if (lh[W + k]) atomicAdd(&hist[n_bins + b], lh[W + k]);
+        if constexpr (MARK) {
+            __syncthreads();
+            for (int k = threadIdx.x; k < BMW; k += PT)
+                if (bm[k]) atomicOr(&gmap[k], bm[k]);
         }
     }
 };
@@ -670,6 +703,8 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
     if (hist != nullptr) {
         const long nh = 2 * g.n_bins;
         for (long k = (long)blockIdx.x * PT + threadIdx.x; k < nh; k += (long)gridDim.x * PT) hist[k] = 0;
+        if (DIM == 2)
+            for (long k = (long)blockIdx.x * PT + threadIdx.x; k < BMW; k += (long)gridDim.x * PT) w.blkmap[k] = 0u;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         stats[WK_ST_ABS_X] = 0;
@@ -731,6 +766,7 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
     __shared__ long long red[PT / 64];
     __shared__ long wmin[PT / 64];
     __shared__ int lh[HIST ? 2 * HW_STEP : 1];
+    __shared__ uint32_t bmap[HIST && DIM == 2 ? BMW : 1];
     __shared__ uint32_t q_id[WPB][QN];
     __shared__ int q_o[WPB][QN];
     if (stats[WK_ST_OVERFLOW] != 0) return;
@@ -760,7 +796,7 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
     wave_chunk(n, (long)blockIdx.x * WPB + wv, &lo, &hi, (long)gridDim.x * WPB);
     const T vdt = (T)g.vdt;
     long long abs_x = 0, abs_m = 0;
-    HistWindow<HW_STEP, DIM == 2> hw{lh, 0, hist, g.n_bins};
+    HistWindow<HW_STEP, DIM == 2, DIM == 2> hw{lh, 0, hist, g.n_bins, bmap, w.blkmap, g.bshift};
     if (HIST) hw.init(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), wmin);
     auto absorbed = [&](T nx_, T ny_, int m, int my) -> int {
         bool outx = !inside<T>(nx_, g.nx);
@@ -970,15 +1006,17 @@ template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void annih_hist(Geo g, const T* x, const T* y, const MT* M,
                                                  const MT* My, const int8_t* s,
                                                  const long long* d_n, long long cap_in,
-                                                 int32_t* hist, const long long* stats) {
+                                                 int32_t* hist, uint32_t* blkmap,
+                                                 const long long* stats) {
     __shared__ int lh[2 * HW];
+    __shared__ uint32_t bmap[DIM == 2 ? BMW : 1];
     __shared__ long wmin[PT / 64];
     if (stats[WK_ST_OVERFLOW] != 0) return;
     const long n = (long)*d_n;
     if (n < 0 || n > cap_in) return;  // refused by annih_count
     long lo, hi;
     wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
-    HistWindow<HW, DIM == 2> hw{lh, 0, hist, g.n_bins};
+    HistWindow<HW, DIM == 2, DIM == 2> hw{lh, 0, hist, g.n_bins, bmap, blkmap, g.bshift};
     hw.init(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), wmin);
     Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
     load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
@@ -1037,7 +1075,7 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
 // words per chunk).  Per bin workgroup: the particles to place (bpart), its mixed bins
 // (bmixed) and work items (bitem).  place = 0 (pair removal): nothing is placed.
 __global__ __launch_bounds__(PT) void annih_bins(Geo g, BinCount bc, int place, const long long* stats,
-                                                 WS w) {
+                                                 WS w, const uint32_t* marked) {
     __shared__ long long red[PT / 64];
     if (stats[WK_ST_OVERFLOW] != 0) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1050,7 +1088,12 @@ __global__ __launch_bounds__(PT) void annih_bins(Geo g, BinCount bc, int place, 
         const long b0 = j * BC + 4 * lane;
         int cnt[4];
         uint32_t mb = 0;
-        if (vec && b0 + 3 < bc.n_bins) {
+        // a block the histogram builder never added to holds only zeros (wave-uniform test)
+        const long blk = (j * BC) >> g.bshift;
+        if (marked != nullptr && ((marked[blk >> 5] >> (blk & 31)) & 1u) == 0u) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cnt[k] = 0;
+        } else if (vec && b0 + 3 < bc.n_bins) {
             const int4 hp = *reinterpret_cast<const int4*>(bc.hist + b0);
             const int4 hm = *reinterpret_cast<const int4*>(bc.hist + bc.n_bins + b0);
             const int a[4] = {hp.x, hp.y, hp.z, hp.w}, m[4] = {hm.x, hm.y, hm.z, hm.w};
@@ -1839,11 +1882,18 @@ static void launch_pairs(const Geo& g, const sp_particles* in, sp_particles* out
     const long long cap_in = (long long)in->capacity;
     if (!hist_ready) {
         WK_LAUNCH("hist_clear", fill_i32, dim3(1024), dim3(256), 0, s, hist, 2 * g.n_bins, 0);
+        if (DIM == 2) {
+            WK_LAUNCH("map_clear", fill_i32, dim3(BMW / 256), dim3(256), 0, s,
+                      reinterpret_cast<int32_t*>(w.blkmap), (long)BMW, 0);
+        }
         WK_LAUNCH("annih_hist", (annih_hist<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
-                  in->s, d_n, cap_in, hist, stats);
+                  in->s, d_n, cap_in, hist, w.blkmap, stats);
     }
+    // the block map is valid when this call or the sp_step before it built the histogram (the
+    // 2-D builders mark it; a 1-D histogram is small enough to read whole)
+    const uint32_t* marked = hist_ready == 1 || DIM == 1 ? nullptr : w.blkmap;
     const BinCount bc{nullptr, hist, g.n_bins};
-    WK_LAUNCH("annih_bins", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, 0, stats, w);
+    WK_LAUNCH("annih_bins", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, 0, stats, w, marked);
     WK_LAUNCH("pair_count", (pair_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
               d_n, cap_in, stats, w);
     WK_LAUNCH("pair_scan", pair_scan, dim3(1), dim3(ST_THREADS), 0, s, stats, w, q);
@@ -1993,6 +2043,8 @@ static int make_geo(const sp_geom* gm, Geo* g) {
     g->n_bins = (long)gm->nx * gm->ny * gm->n_k * (gm->dim == 2 ? gm->n_k : 1);
     g->n_chunks = n_chunks_for(g->n_bins);
     g->gpb = (g->n_chunks + PB - 1) / PB;
+    g->bshift = __builtin_ctz(BC);
+    while (((g->n_bins + (1L << g->bshift) - 1) >> g->bshift) > 32L * BMW) ++g->bshift;
     g->vdt = gm->vdt;
     g->seed = gm->seed;
     WK_REQUIRE(g->n_bins < (1L << 31), "particles: too many bins");
@@ -2053,12 +2105,19 @@ static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp
     const long long cap_in = (long long)in->capacity;
     if (!hist_ready) {
         WK_LAUNCH("hist_clear", fill_i32, dim3(1024), dim3(256), 0, s, hist, 2 * g.n_bins, 0);
+        if (DIM == 2) {
+            WK_LAUNCH("map_clear", fill_i32, dim3(BMW / 256), dim3(256), 0, s,
+                      reinterpret_cast<int32_t*>(w.blkmap), (long)BMW, 0);
+        }
         WK_LAUNCH("annih_hist", (annih_hist<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My,
-                  in->s, d_n, cap_in, hist, stats);
+                  in->s, d_n, cap_in, hist, w.blkmap, stats);
     }
+    // the block map is valid when this call or the sp_step before it built the histogram (the
+    // 2-D builders mark it; a 1-D histogram is small enough to read whole)
+    const uint32_t* marked = hist_ready == 1 || DIM == 1 ? nullptr : w.blkmap;
     const BinCount bc{nullptr, hist, g.n_bins};
     long long* d_n_out = reinterpret_cast<long long*>(out->d_n);
-    WK_LAUNCH("annih_bins", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, 1, stats, w);
+    WK_LAUNCH("annih_bins", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, 1, stats, w, marked);
     WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
               d_n, cap_in, (const uint8_t*)nullptr, stats, w);
     WK_LAUNCH("annih_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 1, PLACE_BLOCKS, d_n,
@@ -2073,7 +2132,8 @@ template <typename T, typename MT, int DIM>
 static void launch_init(const Geo& g, const int32_t* counts, sp_particles* out, long long* stats,
                         WS w, hipStream_t s) {
     const BinCount bc{counts, nullptr, g.n_bins};
-    WK_LAUNCH("init_count", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, 1, stats, w);
+    WK_LAUNCH("init_count", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, 1, stats, w,
+              (const uint32_t*)nullptr);
     WK_LAUNCH("init_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 0, PLACE_BLOCKS,
               (const long long*)nullptr, reinterpret_cast<long long*>(out->d_n),
               (long long)out->capacity, stats, w);
@@ -2176,10 +2236,11 @@ extern "C" int sp_annihilate(const sp_geom* gm, const sp_particles* in, sp_parti
     WK_REQUIRE(in->x != out->x && in->M != out->M && in->s != out->s && in->d_n != out->d_n,
                "sp_annihilate: in and out must be different buffers");
     WK_REQUIRE(hist && d_stats, "sp_annihilate: NULL array");
+    WK_REQUIRE(hist_ready >= 0 && hist_ready <= 2, "sp_annihilate: hist_ready must be 0, 1 or 2");
     WK_REQUIRE(step >= 0 && step < (1LL << 32), "sp_annihilate: step must fit 32 bits");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_annihilate: workspace too small");
     WS w = carve(ws, g.n_bins, (long)g.nx * g.ny);
-    WK_DISPATCH(gm, launch_annih, g, (uint32_t)step, in, out, hist, (int)(hist_ready != 0),
+    WK_DISPATCH(gm, launch_annih, g, (uint32_t)step, in, out, hist, (int)hist_ready,
                 reinterpret_cast<long long*>(d_stats), w, as_stream(stream));
     return check_launch("sp_annihilate");
 }
@@ -2202,6 +2263,7 @@ extern "C" int sp_annihilate_pairs(const sp_geom* gm, const sp_particles* in, sp
     WK_REQUIRE(in->x != out->x && in->M != out->M && in->s != out->s && in->d_n != out->d_n,
                "sp_annihilate_pairs: in and out must be different buffers");
     WK_REQUIRE(hist && d_stats, "sp_annihilate_pairs: NULL array");
+    WK_REQUIRE(hist_ready >= 0 && hist_ready <= 2, "sp_annihilate_pairs: hist_ready must be 0, 1 or 2");
     WK_REQUIRE(2 * g.n_bins < (1L << 32), "sp_annihilate_pairs: too many bins for 32-bit keys");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny),
                "sp_annihilate_pairs: workspace too small");
@@ -2212,7 +2274,7 @@ extern "C" int sp_annihilate_pairs(const sp_geom* gm, const sp_particles* in, sp
     const int passes = (bits + RBITS - 1) / RBITS;
     WS w = carve(ws, g.n_bins, (long)g.nx * g.ny);
     const PairScratch q = pair_carve(scratch, (long)in->capacity);
-    WK_DISPATCH(gm, launch_pairs, g, in, out, hist, (int)(hist_ready != 0),
+    WK_DISPATCH(gm, launch_pairs, g, in, out, hist, (int)hist_ready,
                 reinterpret_cast<long long*>(d_stats), w, q, passes, as_stream(stream));
     return check_launch("sp_annihilate_pairs");
 }

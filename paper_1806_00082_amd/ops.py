@@ -302,12 +302,14 @@ def sp_step(mesh: dict, seed: int, cell_slot, n0, thr, cdf, pin: DeviceParticles
 
 def sp_annihilate(mesh: dict, seed: int, pin: DeviceParticles, pout: DeviceParticles,
                   hist: torch.Tensor, step: int, stats: torch.Tensor, ws: torch.Tensor,
-                  hist_ready: bool = False):
-    """hist_ready: `hist` already holds the histogram of `pin` (from sp_step)."""
+                  hist_ready: int = 0):
+    """hist_ready: 0 = build the histogram here; 1 (or True) = `hist` already holds the
+    histogram of `pin`; 2 = it is what the last sp_step on this workspace built, unchanged
+    (the annihilation then reads only the blocks that step marked)."""
     g = geom_struct(mesh, seed, _m_bytes(pin, pout))
     a, b = pin.struct(), pout.struct()
     L.check(L.lib().sp_annihilate(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _ptr(hist),
-                                  int(bool(hist_ready)), step, _ptr(stats), _ptr(ws), ws.numel(),
+                                  int(hist_ready), step, _ptr(stats), _ptr(ws), ws.numel(),
                                   _stream()), "sp_annihilate")
 
 
@@ -322,12 +324,13 @@ def sp_pairs_scratch(mesh: dict, capacity: int, device="cuda") -> torch.Tensor:
 
 def sp_annihilate_pairs(mesh: dict, pin: DeviceParticles, pout: DeviceParticles, hist: torch.Tensor,
                         stats: torch.Tensor, ws: torch.Tensor, scratch: torch.Tensor,
-                        hist_ready: bool = False):
-    """Rule 2 as literal pair removal (survivors keep their exact positions)."""
+                        hist_ready: int = 0):
+    """Rule 2 as literal pair removal (survivors keep their exact positions); hist_ready as
+    for sp_annihilate."""
     g = geom_struct(mesh, 0, _m_bytes(pin, pout))
     a, b = pin.struct(), pout.struct()
     L.check(L.lib().sp_annihilate_pairs(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _ptr(hist),
-                                        int(bool(hist_ready)), _ptr(stats), _ptr(ws), ws.numel(),
+                                        int(hist_ready), _ptr(stats), _ptr(ws), ws.numel(),
                                         _ptr(scratch), scratch.numel(), _stream()), "sp_annihilate_pairs")
 
 

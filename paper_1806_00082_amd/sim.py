@@ -186,10 +186,10 @@ class Simulator:
                     guide=self.guide)
         if self.annihilation == "pairs":
             ops.sp_annihilate_pairs(self.md, self.b, self.a, self.hist, self.stats, self.ws,
-                                    self.pair_scratch, hist_ready=self.hist_in_step)
+                                    self.pair_scratch, hist_ready=2 if self.hist_in_step else 0)
         else:
             ops.sp_annihilate(self.md, self.seed, self.b, self.a, self.hist, s, self.stats, self.ws,
-                              hist_ready=self.hist_in_step)
+                              hist_ready=2 if self.hist_in_step else 0)
         self.step_index += 1
 
     def run(self, steps: int, log=None):

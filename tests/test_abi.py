@@ -109,6 +109,12 @@ def test_particle_calls_reject_aliased_buffers_without_gpu():
     assert rc == _lib.WK_EINVAL and b"different buffers" in lib.wk_last_error()
     rc = lib.sp_annihilate(ctypes.byref(g), ctypes.byref(q), ctypes.byref(q), f, 0, 0, f, f, ws, None)
     assert rc == _lib.WK_EINVAL and b"different buffers" in lib.wk_last_error()
+    for bad in (-1, 3):
+        rc = lib.sp_annihilate(ctypes.byref(g), ctypes.byref(p), ctypes.byref(q), f, bad, 0, f, f, ws, None)
+        assert rc == _lib.WK_EINVAL and b"hist_ready" in lib.wk_last_error()
+        rc = lib.sp_annihilate_pairs(ctypes.byref(g), ctypes.byref(p), ctypes.byref(q), f, bad, f, f, ws,
+                                     f, 1 << 40, None)
+        assert rc == _lib.WK_EINVAL and b"hist_ready" in lib.wk_last_error()
     rc = lib.sp_step(ctypes.byref(g), f, f, f, f, f, 0, ctypes.byref(p), ctypes.byref(q), None,
                      0, f, f, ws, None)
     assert rc == _lib.WK_EINVAL and b"guide_len" in lib.wk_last_error()

@@ -114,7 +114,9 @@ def test_pair_removal_time_loop(orc, cfgname):
         ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, b, s, st, ws, hist=hist if fused else None)
         assert_particles_equal(b.view(), hp.view(), f"step {s}")
         hp, hh_p, hh_m, hst = orc.sp_annihilate_pairs(md, hp, capacity=cap)
-        ops.sp_annihilate_pairs(md, b, a, hist, st, ws, scratch, hist_ready=fused)
+        # the histogram sp_step just built: handed over as such (1) or with its block map (2)
+        ops.sp_annihilate_pairs(md, b, a, hist, st, ws, scratch,
+                                hist_ready=(2 if s % 4 == 1 else 1) if fused else 0)
         assert_particles_equal(a.view(), hp.view(), f"pair removal {s}")
         g = to_np(st)
         assert g[L.ST_N] == hst[orc.ST_N] and g[L.ST_MIXED] == hst[orc.ST_MIXED]

@@ -51,6 +51,12 @@ def test_init_overflow_reports_needed(orc):
     assert p.count() == 0
 
 
+def _ready(fused: bool, s: int) -> int:
+    """How a loop hands the histogram to sp_annihilate: built there (0, unfused steps), or
+    the one sp_step just built, as such (1) or with the block map of its workspace (2)."""
+    return (2 if s % 4 == 1 else 1) if fused else 0
+
+
 def _odd_word_hist(n):
     """A zeroed int32 histogram that starts 4 bytes into an 8-byte word (the flush pairs
     counters by their address in the caller's array)."""
@@ -92,7 +98,7 @@ def _run_both(orc, cfg, steps, N0_scale=1.0, check_every=1, m_bytes=None, odd_hi
             h = to_np(hist)
             nb = ops.n_bins(md)
             assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"step hist {s}"
-        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=fused)
+        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=_ready(fused, s))
         gst = to_np(st)
         for k in (L.ST_N, L.ST_KEPT, L.ST_REGEN, L.ST_MIXED):
             assert gst[k] == hst[k], (s, k, gst[k], hst[k])
@@ -281,7 +287,7 @@ def test_2d_step_and_annihilation(orc, nx, ny, odd_hist, m_bytes):
             h = to_np(hist)
             nb = ops.n_bins(md)
             assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"2-D step hist {s}"
-        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=fused)
+        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=_ready(fused, s))
         assert_particles_equal(a.view(), hp.view(), f"2-D annihilate {s}")
     assert hst[orc.ST_MIXED] > 0
 
@@ -368,7 +374,7 @@ def _c5_compare(orc, md, tables, slot, hp, seed, steps, first_step, label, m_byt
         if fused:
             h = to_np(hist)
             assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"{label} step hist {s}"
-        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=fused)
+        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=_ready(fused, s))
         gst = to_np(st)
         for k in (L.ST_N, L.ST_KEPT, L.ST_REGEN, L.ST_MIXED):
             assert gst[k] == hst[k], (label, s, k, gst[k], hst[k])
@@ -493,7 +499,7 @@ def test_histogram_hash_overflow_scattered(orc, large):
         keys = _max_keys_per_chunk_owner(hv, md, owners)
         assert keys > slots, (s, keys, slots)  # some workgroup's table must overflow
         hp, hh_p, hh_m, hst = orc.sp_annihilate(md, hp, step=s, seed=5, capacity=cap)
-        ops.sp_annihilate(md, 5, b, a, hist, s, st, ws, hist_ready=fused)
+        ops.sp_annihilate(md, 5, b, a, hist, s, st, ws, hist_ready=2 if fused else 0)
         h = to_np(hist)
         assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"scattered hist {s}"
         gst = to_np(st)
