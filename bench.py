@@ -47,8 +47,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # taken again.
 TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1348, "annih_bins": 0.0008,
                   "annih_count": 0.0619, "annih_write": 0.1245},
-           "2d": {"step_count": 1.1881, "step_apply": 2.1786, "annih_bins": 0.1212,
-                  "annih_count": 0.814, "annih_write": 1.6507}}
+           "2d": {"step_apply": 2.1786, "annih_bins": 0.1212, "annih_count": 0.814, "annih_write": 1.6507}}
 
 
 def _events():

@@ -258,6 +258,12 @@ int sp_init(const sp_geom* g, const int32_t* bin_counts, sp_particles* out, int6
  *   hist  NULL, or [2][n_bins] int32 that receives the signed histogram of rule 1 (H+ then
  *         H-) of the particles after the step -- the input of the next sp_annihilate,
  *         which then need not build it (hist_ready = 1, or 2 with this same workspace).
+ *   hist_mode  how `hist` is cleared first: 0 = every counter; 1 = a promise that the last
+ *         call on this workspace that built a 2-D histogram (this step's own kind, or an
+ *         annihilation with hist_ready = 0) built the one `hist` holds, unchanged since, so
+ *         only the blocks of bins that call marked in the workspace hold counts and only
+ *         they are cleared.  1-D histograms are always cleared whole.  Other values:
+ *         WK_EINVAL.
  * If out cannot hold n + 2 * pairs particles, d_stats[WK_ST_NEEDED] gets the required
  * capacity, the sticky WK_ST_OVERFLOW flag is set and `out` is invalid; `in` is never
  * written, and because the random stream is counter-based, re-running the step into a
@@ -266,8 +272,8 @@ int sp_init(const sp_geom* g, const int32_t* bin_counts, sp_particles* out, int6
  * workspace must not overlap). */
 int sp_step(const sp_geom* g, const int32_t* cell_slot, const uint32_t* n0, const uint32_t* thr,
             const uint64_t* cdf, const uint32_t* guide, int32_t guide_len,
-            const sp_particles* in, sp_particles* out, int32_t* hist, int64_t step,
-            int64_t* d_stats, void* ws, size_t ws_bytes, void* stream);
+            const sp_particles* in, sp_particles* out, int32_t* hist, int32_t hist_mode,
+            int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes, void* stream);
 
 /* sp_annihilate -- rule 2 of Sec. 2.1 on the (cell, momentum) grid, from `in` to `out`:
  * output = for each bin holding both signs, in ascending bin order, |H+ - H-| particles of

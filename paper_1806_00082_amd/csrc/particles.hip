@@ -686,8 +686,8 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
                                                  const MT* My, const int8_t* s,
                                                  const long long* d_n_in, long long cap_in,
                                                  T* xo, int8_t* so, long long cap_out,
-                                                 int32_t* hist, long long* stats, long long st,
-                                                 WS w) {
+                                                 int32_t* hist, int sparse, long long* stats,
+                                                 long long st, WS w) {
     __shared__ long long red[PT / 64];
     __shared__ uint2 ct_lds[CT_MAX];
     if (stats[WK_ST_OVERFLOW] != 0) return;
@@ -700,7 +700,25 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
         }
         return;
     }
-    if (hist != nullptr) {
+    if (hist != nullptr && DIM == 2 && sparse) {
+        // the histogram is zero outside the blocks the map marks: clear those blocks and the
+        // map; map word k and its 32 blocks belong to workgroup k mod gridDim.x alone
+        for (long k = blockIdx.x; k < BMW; k += gridDim.x) {
+            uint32_t bits = w.blkmap[k];  // the same value in every thread: uniform branches
+            while (bits) {
+                const int j = __builtin_ctz(bits);
+                bits &= bits - 1u;
+                const long b0 = (k * 32 + j) << g.bshift;
+                const long b1 = min(b0 + (1L << g.bshift), g.n_bins);
+                for (long b = b0 + threadIdx.x; b < b1; b += PT) {
+                    hist[b] = 0;
+                    hist[g.n_bins + b] = 0;
+                }
+            }
+            __syncthreads();  // every thread has read word k
+            if (threadIdx.x == 0) w.blkmap[k] = 0u;
+        }
+    } else if (hist != nullptr) {
         const long nh = 2 * g.n_bins;
         for (long k = (long)blockIdx.x * PT + threadIdx.x; k < nh; k += (long)gridDim.x * PT) hist[k] = 0;
         if (DIM == 2)
@@ -2065,7 +2083,7 @@ template <typename T, typename MT, int DIM>
 static void launch_step(const Geo& g, uint32_t step, const int32_t* cs, const uint32_t* n0,
                         const uint32_t* thr, const uint64_t* cdf, const uint32_t* guide,
                         int guide_len, const sp_particles* in, sp_particles* out, int32_t* hist,
-                        long long* stats, long long st, WS w, hipStream_t s) {
+                        int hist_mode, long long* stats, long long st, WS w, hipStream_t s) {
     const long long* d_n_in = reinterpret_cast<const long long*>(in->d_n);
     long long* d_n_out = reinterpret_cast<long long*>(out->d_n);
     const long long cap = (long long)out->capacity;
@@ -2083,7 +2101,8 @@ static void launch_step(const Geo& g, uint32_t step, const int32_t* cs, const ui
                   n_cells, cs, n0, thr, w.ctab);
     const unsigned sb = cap >= SB_LARGE ? SB_MAX : PB;  // chunk owners of both passes
     WK_LAUNCH("step_count", (step_count<T, MT, DIM>), dim3(sb), dim3(PT), 0, s, g, step, cs, n0, thr,
-              x, y, M, My, in->s, d_n_in, (long long)in->capacity, xo, out->s, cap, hist, stats, st, w);
+              x, y, M, My, in->s, d_n_in, (long long)in->capacity, xo, out->s, cap, hist, hist_mode,
+              stats, st, w);
     if (hist)
         WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, true>), dim3(sb), dim3(PT), 0, s, g, step, cs,
                   n0, thr, cdf, guide, guide_len, x, y, M, My, in->s, d_n_in, xo, yo, Mo, Myo,
@@ -2200,8 +2219,8 @@ extern "C" int sp_init(const sp_geom* gm, const int32_t* bin_counts, sp_particle
 extern "C" int sp_step(const sp_geom* gm, const int32_t* cell_slot, const uint32_t* n0,
                        const uint32_t* thr, const uint64_t* cdf, const uint32_t* guide,
                        int32_t guide_len, const sp_particles* in, sp_particles* out,
-                       int32_t* hist, int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes,
-                       void* stream) {
+                       int32_t* hist, int32_t hist_mode, int64_t step, int64_t* d_stats, void* ws,
+                       size_t ws_bytes, void* stream) {
     Geo g;
     int rc = make_geo(gm, &g);
     if (rc) return rc;
@@ -2212,13 +2231,14 @@ extern "C" int sp_step(const sp_geom* gm, const int32_t* cell_slot, const uint32
     WK_REQUIRE(in->x != out->x && in->M != out->M && in->s != out->s && in->d_n != out->d_n,
                "sp_step: in and out must be different buffers");
     WK_REQUIRE(cell_slot && n0 && thr && cdf && d_stats, "sp_step: NULL array");
+    WK_REQUIRE(hist_mode == 0 || hist_mode == 1, "sp_step: hist_mode must be 0 or 1");
     WK_REQUIRE(step >= 0 && step < (1LL << 32), "sp_step: step must fit 32 bits");
     WK_REQUIRE(guide == nullptr || (guide_len >= 1 && guide_len <= (1 << 20)),
                "sp_step: guide_len out of range");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_step: workspace too small");
     WS w = carve(ws, g.n_bins, (long)g.nx * g.ny);
     WK_DISPATCH(gm, launch_step, g, (uint32_t)step, cell_slot, n0, thr, cdf, guide, guide_len, in,
-                out, hist, reinterpret_cast<long long*>(d_stats), (long long)step, w,
+                out, hist, (int)hist_mode, reinterpret_cast<long long*>(d_stats), (long long)step, w,
                 as_stream(stream));
     return check_launch("sp_step");
 }

@@ -289,14 +289,17 @@ def sampling_guide(cdf: torch.Tensor, guide_len: int, out: torch.Tensor | None =
 
 def sp_step(mesh: dict, seed: int, cell_slot, n0, thr, cdf, pin: DeviceParticles,
             pout: DeviceParticles, step: int, stats: torch.Tensor, ws: torch.Tensor,
-            hist: torch.Tensor | None = None, guide: torch.Tensor | None = None):
+            hist: torch.Tensor | None = None, guide: torch.Tensor | None = None, hist_mode: int = 0):
     """One step from pin to pout.  hist (optional): receives the signed histogram of the
-    ensemble after the step.  guide (optional): sampling_guide() of the cdf rows."""
+    ensemble after the step; hist_mode 1: `hist` is unchanged since the last histogram
+    build on this workspace, so only its marked blocks need clearing.  guide (optional):
+    sampling_guide() of the cdf rows."""
     g = geom_struct(mesh, seed, _m_bytes(pin, pout))
     a, b = pin.struct(), pout.struct()
     glen = 0 if guide is None else guide.shape[1] - 1
     L.check(L.lib().sp_step(ctypes.byref(g), _ptr(cell_slot), _ptr(n0), _ptr(thr), _ptr(cdf),
-                            _ptr(guide), glen, ctypes.byref(a), ctypes.byref(b), _ptr(hist), step,
+                            _ptr(guide), glen, ctypes.byref(a), ctypes.byref(b), _ptr(hist),
+                            int(hist_mode), step,
                             _ptr(stats), _ptr(ws), ws.numel(), _stream()), "sp_step")
 
 

@@ -112,6 +112,9 @@ class Simulator:
         # the initial ensemble is single-signed: this pass only builds the histogram
         ops.sp_annihilate(md, self.seed, self.a, self.b, self.hist, 0xFFFFFFFF, self.stats, self.ws)
         self.a, self.b = self.b, self.a
+        # `hist` is what the last histogram build on `ws` left (its block map is valid), so the
+        # next step need clear only the marked blocks; false after a restore
+        self.hist_marked = True
         vmax = max(abs(md["M_min"]), abs(md["M_min"] + md["n_k"] - 1)) * abs(md["vdt"])
         self.margin = int(math.ceil(self.refresh_every * vmax)) + 1
         if mode == "all":
@@ -183,7 +186,7 @@ class Simulator:
             self.refresh()
         ops.sp_step(self.md, self.seed, self.cell_slot, self.n0, self.thr, self.cdf, self.a,
                     self.b, s, self.stats, self.ws, hist=self.hist if self.hist_in_step else None,
-                    guide=self.guide)
+                    guide=self.guide, hist_mode=1 if self.hist_marked else 0)
         if self.annihilation == "pairs":
             ops.sp_annihilate_pairs(self.md, self.b, self.a, self.hist, self.stats, self.ws,
                                     self.pair_scratch, hist_ready=2 if self.hist_in_step else 0)
@@ -191,6 +194,7 @@ class Simulator:
             ops.sp_annihilate(self.md, self.seed, self.b, self.a, self.hist, s, self.stats, self.ws,
                               hist_ready=2 if self.hist_in_step else 0)
         self.step_index += 1
+        self.hist_marked = True   # built by sp_step, or by the annihilation itself
 
     def run(self, steps: int, log=None):
         """`steps` time steps; with `log` (a writable text file) one JSON line of
@@ -281,3 +285,4 @@ class Simulator:
             getattr(self, name)[:r].copy_(state[name])
         self.n_rows = r
         self.step_index = int(state["step_index"])
+        self.hist_marked = False  # the workspace's block map does not describe the restored histogram

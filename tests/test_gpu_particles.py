@@ -280,7 +280,7 @@ def test_2d_step_and_annihilation(orc, nx, ny, odd_hist, m_bytes):
         fused = s % 2 == 1
         hp, hst = orc.sp_step(md, hp, tables[1:], slot, step=s, seed=seed)
         ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, b, s, st, ws, hist=hist if fused else None,
-                    guide=guide if s >= 2 else None)
+                    guide=guide if s >= 2 else None, hist_mode=1 if s == 3 else 0)
         assert_particles_equal(b.view(), hp.view(), f"2-D step {s}")
         hp, hh_p, hh_m, hst = orc.sp_annihilate(md, hp, step=s, seed=seed, capacity=cap)
         if fused:
@@ -362,7 +362,7 @@ def _c5_compare(orc, md, tables, slot, hp, seed, steps, first_step, label, m_byt
         print(f"{label}: step {s} ({hp.n} particles, histogram from sp_step: {fused})", flush=True)
         hp, hst = orc.sp_step(md, hp, tables, slot, step=s, seed=seed)
         ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, b, s, st, ws, hist=hist if fused else None,
-                    guide=guide if s % 2 == 0 else None)
+                    guide=guide if s % 2 == 0 else None, hist_mode=1 if fused else 0)
         gst = to_np(st)
         assert gst[L.ST_OVERFLOW] == 0
         for k in (L.ST_N, L.ST_PAIRS, L.ST_ABS_X, L.ST_ABS_M):
