@@ -47,7 +47,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # taken again.
 TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1348, "annih_bins": 0.0008,
                   "annih_count": 0.0619, "annih_write": 0.1245},
-           "2d": {"step_apply": 2.1786, "annih_bins": 0.1212, "annih_count": 0.814, "annih_write": 1.6507}}
+           "2d": {"step_count": 0.7616, "step_apply": 2.1788, "annih_bins": 0.1212,
+                  "annih_count": 0.8139, "annih_write": 1.6511}}
 
 
 def _events():
@@ -62,14 +63,17 @@ def _events():
 # clears or walks the signed histogram (2-D: 2 x 4 B x 67M bins, beyond every cache), that
 # histogram (the 1-bit mixed-bin map annih_bins writes, 1/64 of it, is not counted).  The 1-D histogram and all tables are L2-resident and not counted; neither are
 # the pair counts the two sp_step passes hand over (an implementation choice).
-def kernel_bytes(PB: int, dim: int, hist_bytes: int, walked_bytes=None):
+def kernel_bytes(PB: int, dim: int, hist_bytes: int, walked_bytes=None, cleared_bytes=None):
     """walked_bytes: histogram bytes the bin pass had to read over the run (2-D: the blocks
-    of bins that held counts, which the step marks; None = the whole histogram each step)."""
+    of bins that held counts, which the step marks); cleared_bytes: those the counting pass
+    had to clear (the blocks the previous step marked).  None = the whole histogram each
+    step."""
     pos = 4 * dim + 1            # what the counting pass reads: positions and sign
     H = hist_bytes if dim == 2 else 0
     walk = (lambda S, L: H * S[L.ST_CUM_STEPS]) if walked_bytes is None else (lambda S, L: walked_bytes)
+    clear = (lambda S, L: H * S[L.ST_CUM_STEPS]) if cleared_bytes is None else (lambda S, L: cleared_bytes)
     return {
-        "step_count": lambda S, L: pos * S[L.ST_CUM_N] + H * S[L.ST_CUM_STEPS],      # + histogram clear
+        "step_count": lambda S, L: pos * S[L.ST_CUM_N] + clear(S, L),                # + histogram clear
         "step_apply": lambda S, L: 2 * PB * (S[L.ST_CUM_N] + S[L.ST_CUM_PAIRS]),     # read, write; 2 children
         "annih_bins": walk,                                                           # histogram walk
         "annih_count": lambda S, L: PB * S[L.ST_CUM_ANNIH_IN],                       # read
@@ -104,17 +108,25 @@ def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str 
     blk = 256
     while -(-ops.n_bins(sim.md) // blk) > 65536:
         blk *= 2
+
+    def marked_blocks():
+        h = sim.hist.view(2, -1)
+        pad = (-h.shape[1]) % blk
+        if pad:
+            h = torch.nn.functional.pad(h, (0, pad))
+        return (h.view(2, -1, blk) != 0).any(dim=2).any(dim=0).sum()
+
+    # the first timed step clears what the last warm-up step built
+    first = marked_blocks() if walked is not None else None
+    last = None
     t0, t1 = _events()
     wall0 = time.perf_counter()
     t0.record()
     for _ in range(steps):
         sim.step()
         if walked is not None:
-            h = sim.hist.view(2, -1)
-            pad = (-h.shape[1]) % blk
-            if pad:
-                h = torch.nn.functional.pad(h, (0, pad))
-            walked += (h.view(2, -1, blk) != 0).any(dim=2).any(dim=0).sum()
+            last = marked_blocks()
+            walked += last
     t1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -136,9 +148,11 @@ def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str 
         return out
     L.check(L.lib().wk_trace_disable(), "wk_trace_disable")
     walked_bytes = None if walked is None else int(walked.item()) * blk * 2 * 4
+    cleared_bytes = (None if walked is None
+                     else int((walked + first - last).item()) * blk * 2 * 4)
     out["walked_hist_fraction"] = (None if walked_bytes is None
                                    else round(walked_bytes / (hist_bytes * steps), 4))
-    KB = kernel_bytes(pbytes, dim, hist_bytes, walked_bytes)
+    KB = kernel_bytes(pbytes, dim, hist_bytes, walked_bytes, cleared_bytes)
     kernels = {}
     for name in L.trace_names():
         tot, cnt = L.trace_read(name)

@@ -320,8 +320,10 @@ int sp_density(const sp_geom* g, const int32_t* hist, double N0, double* rho, vo
  * evaluated only on the phase-space cells the particles occupy): every cell within `margin`
  * cells per axis of a cell holding particles in `hist` (from sp_annihilate) whose
  * cell_slot is still -1, written in ascending order to new_cells [nx*ny] (int32), their
- * number to *d_count (device int64).  ws: sp_workspace_size() bytes. */
-int sp_cells_to_evaluate(const sp_geom* g, const int32_t* hist, int32_t margin,
+ * number to *d_count (device int64).  ws: sp_workspace_size() bytes.  hist_mode as for
+ * sp_step: 1 promises that `hist` is unchanged since the last 2-D histogram build on this
+ * workspace, and the cells under no marked block are then not read (2-D). */
+int sp_cells_to_evaluate(const sp_geom* g, const int32_t* hist, int32_t hist_mode, int32_t margin,
                          const int32_t* cell_slot, int32_t* new_cells, int64_t* d_count,
                          void* ws, size_t ws_bytes, void* stream);
 

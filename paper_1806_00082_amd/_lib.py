@@ -67,7 +67,7 @@ SIGNATURES = {
     "sp_pairs_scratch_size": (_sz, [_GP, _i64]),
     "sp_annihilate_pairs": (ctypes.c_int, [_GP, _PP, _PP, _P, _i32, _P, _P, _sz, _P, _sz, _P]),
     "sp_density": (ctypes.c_int, [_GP, _P, _f64, _P, _P]),
-    "sp_cells_to_evaluate": (ctypes.c_int, [_GP, _P, _i32, _P, _P, _P, _P, _sz, _P]),
+    "sp_cells_to_evaluate": (ctypes.c_int, [_GP, _P, _i32, _i32, _P, _P, _P, _P, _sz, _P]),
     "sp_assign_slots": (ctypes.c_int, [_P, _P, _i32, _i32, _P, _P]),
     "wk_surrogate_fwd_workspace": (_sz, [_MP, _i32]),
     "wk_surrogate_fwd": (ctypes.c_int, [_MP, _i32, _P, _P, _P, _P, _i32, _P, _i32, _i32, _P, _P, _sz, _P]),

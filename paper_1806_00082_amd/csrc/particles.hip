@@ -1953,10 +1953,20 @@ __global__ void density_kernel(const int32_t* hist, long n_cells, long per_cell,
 // ----------------------------------------------------------------------------- occupied cells
 // occ[c] = 1 if the histogram holds any particle in cell c (one wave per cell).
 __global__ void occupied_kernel(const int32_t* __restrict__ hist, long n_cells, long per_cell,
-                                long n_bins, uint8_t* __restrict__ occ) {
+                                long n_bins, const uint32_t* __restrict__ marked, int bshift,
+                                uint8_t* __restrict__ occ) {
     const long c = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (c >= n_cells) return;
+    if (marked != nullptr) {  // no marked block under the cell: its bins are all zero
+        bool any = false;
+        for (long k = (c * per_cell) >> bshift; k <= ((c + 1) * per_cell - 1) >> bshift && !any; ++k)
+            any = ((marked[k >> 5] >> (k & 31)) & 1u) != 0u;
+        if (!any) {
+            if (lane == 0) occ[c] = 0;
+            return;
+        }
+    }
     int o = 0;
     for (long k = lane; k < per_cell; k += 64) {
         const long b = c * per_cell + k;
@@ -2313,22 +2323,25 @@ extern "C" int sp_density(const sp_geom* gm, const int32_t* hist, double N0, dou
     return check_launch("sp_density");
 }
 
-extern "C" int sp_cells_to_evaluate(const sp_geom* gm, const int32_t* hist, int32_t margin,
-                                    const int32_t* cell_slot, int32_t* new_cells, int64_t* d_count,
-                                    void* ws, size_t ws_bytes, void* stream) {
+extern "C" int sp_cells_to_evaluate(const sp_geom* gm, const int32_t* hist, int32_t hist_mode,
+                                    int32_t margin, const int32_t* cell_slot, int32_t* new_cells,
+                                    int64_t* d_count, void* ws, size_t ws_bytes, void* stream) {
     Geo g;
     int rc = make_geo(gm, &g);
     if (rc) return rc;
     WK_REQUIRE(hist && cell_slot && new_cells && d_count, "sp_cells_to_evaluate: NULL array");
     WK_REQUIRE(margin >= 0, "sp_cells_to_evaluate: negative margin");
+    WK_REQUIRE(hist_mode == 0 || hist_mode == 1, "sp_cells_to_evaluate: hist_mode must be 0 or 1");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_cells_to_evaluate: workspace too small");
     const long n_cells = (long)g.nx * g.ny;
-    uint8_t* occ = carve(ws, g.n_bins, (long)g.nx * g.ny).occ;  // [n_cells] occupancy, then [n_cells] x-dilation
+    const WS w = carve(ws, g.n_bins, (long)g.nx * g.ny);
+    uint8_t* occ = w.occ;  // [n_cells] occupancy, then [n_cells] x-dilation
     uint8_t* occx = occ + n_cells;
     hipStream_t s = as_stream(stream);
     const dim3 cg((unsigned)((n_cells + 255) / 256));
     hipLaunchKernelGGL(occupied_kernel, dim3((unsigned)((n_cells * 64 + 255) / 256)), dim3(256), 0, s,
-                       hist, n_cells, g.n_bins / n_cells, g.n_bins, occ);
+                       hist, n_cells, g.n_bins / n_cells, g.n_bins,
+                       (const uint32_t*)(hist_mode == 1 && g.dim == 2 ? w.blkmap : nullptr), g.bshift, occ);
     hipLaunchKernelGGL(dilate_x_kernel, cg, dim3(256), 0, s, occ, g.nx, n_cells, margin, occx);
     hipLaunchKernelGGL(need_kernel, cg, dim3(256), 0, s, occx, g.dim, g.nx, g.ny, margin, cell_slot, occ);
     hipLaunchKernelGGL(cells_needed_kernel, dim3(1), dim3(1024), 0, s, occ, n_cells, new_cells,

@@ -167,7 +167,8 @@ class Simulator:
     def refresh(self) -> int:
         """Rows for the cells near occupied ones that have none yet (one host sync)."""
         g = ops.geom_struct(self.md, self.seed)
-        L.check(L.lib().sp_cells_to_evaluate(ctypes.byref(g), ops._ptr(self.hist), self.margin,
+        L.check(L.lib().sp_cells_to_evaluate(ctypes.byref(g), ops._ptr(self.hist),
+                                             1 if self.hist_marked else 0, self.margin,
                                              ops._ptr(self.cell_slot), ops._ptr(self.new_cells),
                                              ops._ptr(self.d_count), ops._ptr(self.ws),
                                              self.ws.numel(), ops._stream()), "sp_cells_to_evaluate")

@@ -271,9 +271,44 @@ def test_cells_to_evaluate_box(dim, nx, ny, margin):
     d_count = torch.zeros(1, dtype=torch.int64, device=dev())
     ws = ops.sp_workspace(md, 0, dev())
     g = ops.geom_struct(md, 0)
-    L.check(L.lib().sp_cells_to_evaluate(ctypes.byref(g), ops._ptr(d_hist), margin, ops._ptr(d_slot),
+    L.check(L.lib().sp_cells_to_evaluate(ctypes.byref(g), ops._ptr(d_hist), 0, margin, ops._ptr(d_slot),
                                          ops._ptr(new_cells), ops._ptr(d_count), ops._ptr(ws), ws.numel(),
                                          ops._stream()), "sp_cells_to_evaluate")
     count = int(d_count.item())
     assert count == len(want)
     assert to_np(new_cells[:count]).tolist() == want
+
+
+@pytest.mark.parametrize("nx,ny,n_m", [(256, 256, 32), (40, 36, 16)])
+def test_cells_to_evaluate_from_block_map(nx, ny, n_m):
+    """2-D, after simulator steps: the occupancy scan that skips the cells under unmarked blocks
+    of the workspace's block map (hist_mode 1) finds the same cells as the scan of the whole
+    histogram (hist_mode 0), with every cell's table row withdrawn so that all occupied
+    neighbourhoods count."""
+    if nx == 256:
+        cfg = inputs.config_c5(N0=5e6)
+    else:
+        mesh = inputs.Mesh2D(nx=nx, ny=ny, dx=0.5, n_m=n_m, pos_f64=False)
+        V = inputs.gaussian_dot_2d(mesh, 0.2, 1.5, 10.0, 9.0)
+        bc = inputs.packet_bin_counts_2d(mesh, 5e4, 6.0, 9.0, 1.2, inputs.k_for_energy(0.1), 0.0)
+        cfg = inputs.RunConfig("small2d", mesh, V, bc, int(bc.sum()), 0.5, 10, seed=5)
+    sim = Simulator(cfg)
+    sim.run(9)
+    assert sim.hist_marked
+    none = torch.full_like(sim.cell_slot, -1)
+    got = []
+    for mode in (0, 1, 0):
+        d_count = torch.zeros(1, dtype=torch.int64, device=dev())
+        new_cells = torch.full_like(sim.new_cells, -7)
+        g = ops.geom_struct(sim.md, sim.seed)
+        L.check(L.lib().sp_cells_to_evaluate(ctypes.byref(g), ops._ptr(sim.hist), mode, 2, ops._ptr(none),
+                                             ops._ptr(new_cells), ops._ptr(d_count), ops._ptr(sim.ws),
+                                             sim.ws.numel(), ops._stream()), "sp_cells_to_evaluate")
+        n = int(d_count.item())
+        got.append(to_np(new_cells[:n]).tolist())
+    assert got[0] == got[1] == got[2] and len(got[0]) > 0
+    # the cells found hold particles or neighbour one: every occupied cell is among them
+    per_cell = ops.n_bins(sim.md) // (nx * ny)
+    h = to_np(sim.hist).reshape(2, nx * ny, per_cell)
+    occupied = np.flatnonzero((h != 0).any(axis=(0, 2)))
+    assert set(occupied.tolist()) <= set(got[0])
