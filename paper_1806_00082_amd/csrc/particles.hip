@@ -66,7 +66,7 @@ constexpr int PIECE = 2048;
 // int64 ipre[PB] | int32 wstart[PLACE_WAVES] | int32 csum[n_chunks] | uint8 occ[n_cells] |
 // uint8 occx[n_cells] | uint2 ctab[n_cells] (8-byte aligned) | uint32 mixbits[8 n_chunks]
 // (16-byte aligned).
-enum { SC_GO = 0, SC_PLACED = 1, SC_KEPT = 2, SC_ITEMS = 3 };
+enum { SC_GO = 0, SC_PLACED = 1, SC_KEPT = 2, SC_ITEMS = 3, SC_KBITS = 4 };
 
 struct WS {
     long long* sc;
@@ -1055,7 +1055,8 @@ template <typename T, typename MT, int DIM>
 __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y, const MT* M,
                                                   const MT* My, const int8_t* s,
                                                   const long long* d_n_in, long long cap_in,
-                                                  const uint8_t* flags, long long* stats, WS w) {
+                                                  const uint8_t* flags, uint32_t* kbits,
+                                                  long long* stats, WS w) {
     __shared__ long long red[PT / 64];
     __shared__ uint32_t lw[KWW];
     __shared__ long wmin[PT / 64];
@@ -1068,6 +1069,7 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
         }
         return;
     }
+    const int lane = threadIdx.x & 63;
     long lo, hi;
     wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
     const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin,
@@ -1079,9 +1081,19 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
         const long id = t0 + IT * (threadIdx.x & 63);
         Part4<T, DIM> p = nxt;
         load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+        uint32_t nib = 0;
 #pragma unroll
         for (int k = 0; k < IT; ++k)
-            a += kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), id + k) ? 1 : 0;
+            nib |= kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), id + k) ? 1u << k : 0u;
+        a += __popc(nib);
+        if (kbits != nullptr) {
+            // one keep bit per particle: word q of the tile (ids t0 + 32q .. t0 + 32q + 31, t0 a
+            // multiple of 256) collects the 4-bit groups of lanes 8q .. 8q + 7
+            uint32_t word = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) word |= (uint32_t)__shfl((int)nib, 8 * (lane & 7) + i, 64) << (4 * i);
+            if (lane < 8) kbits[(t0 >> 5) + lane] = word;
+        }
     }
     store_counts(w, wave_sum_ll(a), red);
 }
@@ -1257,7 +1269,7 @@ constexpr int ST_THREADS = 1024;
 __global__ __launch_bounds__(ST_THREADS) void annih_scan(int mode, int place_blocks,
                                                          const long long* d_n_in,
                                                          long long* d_n_out, long long capacity,
-                                                         long long* stats, WS w) {
+                                                         long long kb_limit, long long* stats, WS w) {
     __shared__ long long bp[PB];
     __shared__ long long part[ST_THREADS];
     __shared__ long long tot[2];
@@ -1336,6 +1348,8 @@ __global__ __launch_bounds__(ST_THREADS) void annih_scan(int mode, int place_blo
     w.sc[SC_PLACED] = placed;
     w.sc[SC_KEPT] = kept;
     w.sc[SC_ITEMS] = n_items;
+    // the counting pass's keep bits sit past the output's positions when they fit there
+    w.sc[SC_KBITS] = mode == 1 && kb_limit >= 0 && n_out <= kb_limit;
     stats[WK_ST_N] = n_out;
     stats[WK_ST_NEEDED] = 0;
     if (mode == 1) {
@@ -1362,7 +1376,8 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
                                                   const MT* M, const MT* My, const int8_t* s,
                                                   const long long* d_n_in, T* xo, T* yo, MT* Mo,
                                                   MT* Myo, int8_t* so, long long capacity,
-                                                  const uint8_t* flags, WS w) {
+                                                  const uint8_t* flags, const uint32_t* kbits,
+                                                  WS w) {
     constexpr int STAGE = WT * (DIM * (int)sizeof(T) + DIM * (int)sizeof(int) + 1);  // per wave
     constexpr int KEEP_LDS = WPB * STAGE + KWW * (int)sizeof(uint32_t);
     constexpr int PLACE_LDS = WPB * PW_LDS * (int)sizeof(int);
@@ -1383,21 +1398,37 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
         int8_t* ssg = reinterpret_cast<int8_t*>(sm + DIM * WT);
         long lo, hi;
         wave_chunk((long)*d_n_in, (long)blockIdx.x * WPB + wv, &lo, &hi);
-        const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw,
-                                          wmin, w.mixbits, 8 * g.n_chunks, flags);
+        // with the counting pass's keep bits, a lane loads its four particles only when one of
+        // them survives (particles of mixed bins, about half, are never read again); without
+        // them the survivor test is redone from the positions and momenta
+        const bool bits = kbits != nullptr && w.sc[SC_KBITS] != 0;
+        KeepWindow kw{};
+        if (!bits)
+            kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin, w.mixbits,
+                             8 * g.n_chunks, flags);
+        // keep bits of lane `lane`'s four particles of the tile at t (t a multiple of 256)
+        auto nib_at = [&](long t) -> uint32_t {
+            return t < hi ? (kbits[(t >> 5) + (lane >> 3)] >> (4 * (lane & 7))) & 0xFu : 0u;
+        };
         long long run = placed + w.kpre[blockIdx.x];
         for (int j = 0; j < wv; ++j) run += w.wcnt[(long)blockIdx.x * WPB + j];
+        uint32_t nib_n = bits ? nib_at(lo) : 0xFu;  // the tile in flight, and the one after
         Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
-        load4<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
+        if (nib_n) load4<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
+        uint32_t nib_nn = bits ? nib_at(lo + WT) : 0xFu;
         for (long t0 = lo; t0 < hi; t0 += WT) {  // per wave, no workgroup barriers
             const long id = t0 + IT * lane;
             Part4<T, DIM> p = nxt;
-            load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+            const uint32_t nib = nib_n;
+            nib_n = nib_nn;
+            if (nib_n) load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+            if (bits) nib_nn = nib_at(t0 + 2 * WT);
             bool kp[IT];
             int kt = 0;
 #pragma unroll
             for (int k = 0; k < IT; ++k) {
-                kp[k] = kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), id + k);
+                kp[k] = bits ? ((nib >> k) & 1u) != 0u
+                             : kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), id + k);
                 kt += kp[k];
             }
             const int inc = wave_incl_scan(kt);
@@ -1889,6 +1920,24 @@ __global__ __launch_bounds__(PT) void pair_flags(const uint32_t* __restrict__ ke
     }
 }
 
+// The counting pass's keep bits (one per input slot, in whole 256-particle tiles) go to the
+// end of out->x, past every position the output can occupy when the output is short enough;
+// annih_scan checks that against the output count and the writing pass uses them only then.
+template <typename T>
+static void keep_bits_region(const sp_particles* in, const sp_particles* out, uint32_t** kbits,
+                             long long* kb_limit) {
+    const size_t bytes = (size_t)((in->capacity + 255) / 256) * 8 * sizeof(uint32_t);
+    const size_t end = (size_t)out->capacity * sizeof(T);
+    if (bytes + 256 > end) {
+        *kbits = nullptr;
+        *kb_limit = -1;
+        return;
+    }
+    const size_t off = (end - bytes) & ~(size_t)255;
+    *kbits = reinterpret_cast<uint32_t*>(static_cast<char*>(out->x) + off);
+    *kb_limit = (long long)(off / sizeof(T));
+}
+
 template <typename T, typename MT, int DIM>
 static void launch_pairs(const Geo& g, const sp_particles* in, sp_particles* out, int32_t* hist,
                          int hist_ready, long long* stats, WS w, PairScratch q, int passes, hipStream_t s) {
@@ -1927,14 +1976,18 @@ static void launch_pairs(const Geo& g, const sp_particles* in, sp_particles* out
     }
     WK_LAUNCH("pair_flags", pair_flags, dim3(PB), dim3(PT), 0, s, q.keys[passes & 1], q.vals[passes & 1], hist,
               g.n_bins, q);
+    uint32_t* kbits;
+    long long kb_limit;
+    keep_bits_region<T>(in, out, &kbits, &kb_limit);
     WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
-              d_n, cap_in, (const uint8_t*)q.flags, stats, w);
+              d_n, cap_in, (const uint8_t*)q.flags, kbits, stats, w);
     WK_LAUNCH("annih_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 1, PLACE_BLOCKS, d_n,
-              reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, stats, w);
+              reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, kb_limit, stats, w);
     WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(PB + PLACE_BLOCKS), dim3(PT), 0, s, g,
               PB, PLACE_BLOCKS, bc, 1, 0u, (uint32_t)TAG_ANNIH, x, y, M, My, in->s, d_n,
               static_cast<T*>(out->x), static_cast<T*>(out->y), static_cast<MT*>(out->M),
-              static_cast<MT*>(out->My), out->s, (long long)out->capacity, (const uint8_t*)q.flags, w);
+              static_cast<MT*>(out->My), out->s, (long long)out->capacity, (const uint8_t*)q.flags,
+              (const uint32_t*)kbits, w);
 }
 
 __global__ void density_kernel(const int32_t* hist, long n_cells, long per_cell, long n_bins,
@@ -2147,14 +2200,18 @@ static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp
     const BinCount bc{nullptr, hist, g.n_bins};
     long long* d_n_out = reinterpret_cast<long long*>(out->d_n);
     WK_LAUNCH("annih_bins", annih_bins, dim3(PB), dim3(PT), 0, s, g, bc, 1, stats, w, marked);
+    uint32_t* kbits;
+    long long kb_limit;
+    keep_bits_region<T>(in, out, &kbits, &kb_limit);
     WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
-              d_n, cap_in, (const uint8_t*)nullptr, stats, w);
+              d_n, cap_in, (const uint8_t*)nullptr, kbits, stats, w);
     WK_LAUNCH("annih_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 1, PLACE_BLOCKS, d_n,
-              d_n_out, (long long)out->capacity, stats, w);
+              d_n_out, (long long)out->capacity, kb_limit, stats, w);
     WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(PB + PLACE_BLOCKS), dim3(PT), 0, s, g,
               PB, PLACE_BLOCKS, bc, 1, step, (uint32_t)TAG_ANNIH, x, y, M, My, in->s, d_n,
               static_cast<T*>(out->x), static_cast<T*>(out->y), static_cast<MT*>(out->M),
-              static_cast<MT*>(out->My), out->s, (long long)out->capacity, (const uint8_t*)nullptr, w);
+              static_cast<MT*>(out->My), out->s, (long long)out->capacity, (const uint8_t*)nullptr,
+              (const uint32_t*)kbits, w);
 }
 
 template <typename T, typename MT, int DIM>
@@ -2165,13 +2222,13 @@ static void launch_init(const Geo& g, const int32_t* counts, sp_particles* out, 
               (const uint32_t*)nullptr);
     WK_LAUNCH("init_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 0, PLACE_BLOCKS,
               (const long long*)nullptr, reinterpret_cast<long long*>(out->d_n),
-              (long long)out->capacity, stats, w);
+              (long long)out->capacity, -1LL, stats, w);
     WK_LAUNCH("init_write", (annih_write<T, MT, DIM>), dim3(PLACE_BLOCKS), dim3(PT), 0, s, g, 0,
               PLACE_BLOCKS, bc, 0, 0xFFFFFFFFu, (uint32_t)TAG_INIT, (const T*)nullptr,
               (const T*)nullptr, (const MT*)nullptr, (const MT*)nullptr, (const int8_t*)nullptr,
               (const long long*)nullptr, static_cast<T*>(out->x), static_cast<T*>(out->y),
               static_cast<MT*>(out->M), static_cast<MT*>(out->My), out->s,
-              (long long)out->capacity, (const uint8_t*)nullptr, w);
+              (long long)out->capacity, (const uint8_t*)nullptr, (const uint32_t*)nullptr, w);
 }
 
 }  // namespace wk

@@ -140,3 +140,38 @@ def test_pair_removal_full_size_2d(orc):
     rst = _check_once(orc, md, hp, n1 + n2, False)
     print(f"kept {rst[orc.ST_N]} of {n1 + n2}, mixed bins {rst[orc.ST_MIXED]}", flush=True)
     assert rst[orc.ST_N] < n1 + n2
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+@pytest.mark.parametrize("mode", ["regenerate", "pairs"])
+def test_annihilation_output_filling_its_buffer(orc, dim, mode):
+    """The counting pass leaves one keep bit per input particle at the end of the output's
+    position array, and the writing pass reads them only if the output stops short of them.
+    An output buffer exactly as large as the output (the bits overwritten by the output's
+    positions: the survivor test is redone) and a roomy one (the bits used) give the oracle's
+    particles, bit for bit, both times."""
+    if dim == 2:
+        md = {"dim": 2, "nx": 8, "ny": 3, "n_m": 8, "n_k": 8, "M_min": -4, "pos_f64": False, "vdt": 0.1}
+    else:
+        md = {"dim": 1, "nx": 8, "ny": 1, "n_m": 8, "n_k": 16, "M_min": -8, "pos_f64": False, "vdt": 0.1}
+    n = 70000
+    hp = _mixed(orc, md, n, 11 + dim)
+    if mode == "pairs":
+        ref, _, _, rst = orc.sp_annihilate_pairs(md, hp, capacity=2 * n)
+    else:
+        ref, _, _, rst = orc.sp_annihilate(md, hp, step=3, seed=7, capacity=2 * n)
+    n_out = ref.n
+    assert 0 < n_out < n
+    for cap in (n_out, 2 * n):
+        a = _gpu(md, hp, n)
+        b = ops.DeviceParticles(md["dim"], cap, md["pos_f64"])
+        st = ops.new_stats()
+        ws = ops.sp_workspace(md, 7)
+        hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev())
+        if mode == "pairs":
+            ops.sp_annihilate_pairs(md, a, b, hist, st, ws, ops.sp_pairs_scratch(md, n))
+        else:
+            ops.sp_annihilate(md, 7, a, b, hist, 3, st, ws)
+        g = to_np(st)
+        assert g[L.ST_OVERFLOW] == 0 and g[L.ST_N] == n_out, (cap, g[L.ST_N], n_out)
+        assert_particles_equal(b.view(), ref.view(), f"{mode} output into {cap} slots")
