@@ -288,9 +288,11 @@ int sp_step(const sp_geom* g, const int32_t* cell_slot, const uint32_t* n0, cons
  *   hist_ready = 0) built this one, and `hist` is unchanged since.  That call also left in
  *   the workspace a map of the blocks of bins it added counts to, and the annihilation then
  *   reads only those blocks of the histogram (the rest are zero).  Any other value is
- *   refused (WK_EINVAL).  Either way `hist` is left holding H+ then H- of
- *   the input: the signed histogram of rule 1.  If the output would exceed out->capacity, d_stats gets the
- *   needed size, the sticky overflow flag is set and `out` is invalid (`in` is untouched). */
+ *   refused (WK_EINVAL).  Either way `hist` is left holding H+ then H- of the input: the
+ *   signed histogram of rule 1.
+ * If the output would exceed out->capacity, d_stats gets the needed size, the sticky
+ * overflow flag is set and `out` is invalid (`in` is untouched).  The slots of `out` past
+ * the output count serve as scratch during the call; their contents are unspecified. */
 int sp_annihilate(const sp_geom* g, const sp_particles* in, sp_particles* out, int32_t* hist,
                   int32_t hist_ready, int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes,
                   void* stream);
@@ -302,7 +304,8 @@ int sp_annihilate(const sp_geom* g, const sp_particles* in, sp_particles* out, i
  * conserved and no bin holds both signs afterwards.  The output histogram equals that of
  * sp_annihilate (which regenerates |H+ - H-| particles of a mixed bin instead).
  *   hist, hist_ready, ws, d_stats as sp_annihilate (WK_ST_REGEN = 0; WK_ST_KEPT = output
- *   count); out->capacity >= the input count always suffices.
+ *   count), and as there the slots of `out` past the output count are scratch; out->capacity
+ *   >= the input count always suffices.
  *   scratch  caller buffer of sp_pairs_scratch_size(g, in->capacity) bytes (the list of the
  *            particles of mixed bins and its radix-sort buffers, ~17 B per particle slot).
  * Requires 2 * n_bins < 2^32 (WK_EINVAL otherwise).  Calls sharing a workspace or scratch
