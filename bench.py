@@ -45,8 +45,10 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # by what the counters read for a 1 GiB device copy (fetch x2.0, write x1.0).  Taken for the
 # kernels as they are now; an entry is dropped when its kernel changes until the counters are
 # taken again.
-TRAFFIC = {"1d": {"step_apply": 0.1348, "annih_bins": 0.0008},
-           "2d": {"step_count": 0.7616, "step_apply": 2.1788, "annih_bins": 0.1212}}
+TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1348, "annih_bins": 0.0008,
+                  "annih_count": 0.0628, "annih_write": 0.1224},
+           "2d": {"step_count": 0.7616, "step_apply": 2.1787, "annih_bins": 0.1212,
+                  "annih_count": 0.8259, "annih_write": 1.273}}
 
 
 def _events():
@@ -57,10 +59,12 @@ def _events():
 # Algorithmic HBM bytes per launch of each particle kernel, from the running sums the
 # library keeps (S = stats): what the pass must move at minimum with PB-byte particles
 # (FP32 positions, 8-bit momenta: 1-D x 4 + M 1 + s 1 = 6; 2-D x 4 + y 4 + M 1 + My 1 + s 1
-# = 11) and, where the pass
-# clears or walks the signed histogram (2-D: 2 x 4 B x 67M bins, beyond every cache), that
-# histogram (the 1-bit mixed-bin map annih_bins writes, 1/64 of it, is not counted).  The 1-D histogram and all tables are L2-resident and not counted; neither are
-# the pair counts the two sp_step passes hand over (an implementation choice).
+# = 11), the annihilation's keep bits (one per input particle, written by the counting pass
+# and read by the writing pass, which then reads the kept particles only) and, where a pass
+# clears or walks the 2-D signed histogram (2 x 4 B x 67M bins, beyond every cache), the part
+# of it that pass touches.  Not counted: the 1-D histogram and all tables (L2-resident), the
+# 1-bit mixed-bin map (1/64 of the histogram) and the pair counts the two sp_step passes hand
+# over (an implementation choice).
 def kernel_bytes(PB: int, dim: int, hist_bytes: int, walked_bytes=None, cleared_bytes=None):
     """walked_bytes: histogram bytes the bin pass had to read over the run (2-D: the blocks
     of bins that held counts, which the step marks); cleared_bytes: those the counting pass
@@ -74,9 +78,11 @@ def kernel_bytes(PB: int, dim: int, hist_bytes: int, walked_bytes=None, cleared_
         "step_count": lambda S, L: pos * S[L.ST_CUM_N] + clear(S, L),                # + histogram clear
         "step_apply": lambda S, L: 2 * PB * (S[L.ST_CUM_N] + S[L.ST_CUM_PAIRS]),     # read, write; 2 children
         "annih_bins": walk,                                                           # histogram walk
-        "annih_count": lambda S, L: PB * S[L.ST_CUM_ANNIH_IN],                       # read
-        "annih_write": lambda S, L: PB * (S[L.ST_CUM_ANNIH_IN] + S[L.ST_CUM_KEPT]
-                                          + S[L.ST_CUM_REGEN]),                      # read, write kept + placed
+        # read, and one keep bit per particle written
+        "annih_count": lambda S, L: PB * S[L.ST_CUM_ANNIH_IN] + S[L.ST_CUM_ANNIH_IN] / 8,
+        # the keep bits and the kept particles read, kept + placed written
+        "annih_write": lambda S, L: (S[L.ST_CUM_ANNIH_IN] / 8 + PB * (2 * S[L.ST_CUM_KEPT]
+                                                                   + S[L.ST_CUM_REGEN])),
     }
 
 
