@@ -124,6 +124,14 @@ static size_t ws_bytes_for(long n_bins, long n_cells) {
 constexpr int IT = 4;          // particles per lane in the streaming passes
 constexpr int WT = 64 * IT;    // particles per wave tile
 
+// The 8 bits of b moved to bits 0, 4, 8, ..., 28.
+__device__ __forceinline__ uint32_t spread4(uint32_t b) {
+    b = (b | (b << 12)) & 0x000F000Fu;
+    b = (b | (b << 6)) & 0x03030303u;
+    b = (b | (b << 3)) & 0x11111111u;
+    return b;
+}
+
 // Wave chunk `wv` of nw: a whole number of wave tiles, the last ones possibly empty.
 __device__ __forceinline__ void wave_chunk(long n, long wv, long* lo, long* hi, long nw = NW) {
     long cs = (n + nw - 1) / nw;
@@ -1088,10 +1096,11 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
         a += __popc(nib);
         if (kbits != nullptr) {
             // one keep bit per particle: word q of the tile (ids t0 + 32q .. t0 + 32q + 31, t0 a
-            // multiple of 256) collects the 4-bit groups of lanes 8q .. 8q + 7
+            // multiple of 256) holds bit k of lane 8q + i at 4i + k, built from one ballot per k
             uint32_t word = 0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) word |= (uint32_t)__shfl((int)nib, 8 * (lane & 7) + i, 64) << (4 * i);
+            for (int k = 0; k < IT; ++k)
+                word |= spread4((uint32_t)(__ballot((nib >> k) & 1u) >> (8 * (lane & 7))) & 0xFFu) << k;
             if (lane < 8) kbits[(t0 >> 5) + lane] = word;
         }
     }
@@ -1149,10 +1158,11 @@ __global__ __launch_bounds__(PT) void annih_bins(Geo g, BinCount bc, int place, 
             items += (t + PIECE - 1) / PIECE;
         }
         if (bc.counts == nullptr) {
-            // word q of the chunk (bins 32q .. 32q+31) collects the 4-bit groups of lanes 8q .. 8q+7
+            // word q of the chunk (bins 32q .. 32q+31) holds bit k of lane 8q + i at 4i + k
             uint32_t word = 0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) word |= (uint32_t)__shfl((int)mb, 8 * (lane & 7) + i, 64) << (4 * i);
+            for (int k = 0; k < 4; ++k)
+                word |= spread4((uint32_t)(__ballot((mb >> k) & 1u) >> (8 * (lane & 7))) & 0xFFu) << k;
             if (lane < 8) w.mixbits[j * 8 + lane] = word;
         }
     }
