@@ -62,7 +62,7 @@ constexpr int PLACE_WAVES = PLACE_BLOCKS * WPB;
 constexpr int PIECE = 2048;
 
 // Workspace (sp_workspace_size): int64 scalars[16] | int64 bcnt[SB_MAX] | int64 wcnt[SB_MAX WPB] |
-// int64 bpart[PB] | int64 bmixed[PB] | int64 kpre[PB] | int64 bpre[PB] | int64 bitem[PB] |
+// int64 bpart[PB] | int64 bmixed[PB] | int64 kpre[SB_MAX] | int64 bpre[PB] | int64 bitem[PB] |
 // int64 ipre[PB] | int32 wstart[PLACE_WAVES] | int32 csum[n_chunks] | uint8 occ[n_cells] |
 // uint8 occx[n_cells] | uint2 ctab[n_cells] (8-byte aligned) | uint32 mixbits[8 n_chunks]
 // (16-byte aligned).
@@ -98,7 +98,7 @@ static WS carve(void* ws, long n_bins, long n_cells) {
     w.bpart = w.wcnt + (size_t)SB_MAX * WPB;
     w.bmixed = w.bpart + PB;
     w.kpre = w.bmixed + PB;
-    w.bpre = w.kpre + PB;
+    w.bpre = w.kpre + SB_MAX;
     w.bitem = w.bpre + PB;
     w.ipre = w.bitem + PB;
     w.wstart = reinterpret_cast<int*>(w.ipre + PB);
@@ -113,7 +113,7 @@ static WS carve(void* ws, long n_bins, long n_cells) {
 }
 
 static size_t ws_bytes_for(long n_bins, long n_cells) {
-    return sizeof(long long) * (16 + (size_t)SB_MAX * (1 + WPB) + 6 * (size_t)PB) +
+    return sizeof(long long) * (16 + (size_t)SB_MAX * (2 + WPB) + 5 * (size_t)PB) +
            sizeof(int) * (size_t)(PLACE_WAVES + (n_chunks_for(n_bins) + 1) / 2 * 2) +
            2 * (size_t)n_cells +  // occupancy byte per cell, then its dilation along x
            8 + sizeof(uint2) * (n_cells > CT_MAX ? (size_t)n_cells : 0) +  // aligned ctab
@@ -1079,7 +1079,7 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
     }
     const int lane = threadIdx.x & 63;
     long lo, hi;
-    wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
+    wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi, (long)gridDim.x * WPB);
     const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin,
                                       w.mixbits, 8 * g.n_chunks, flags);
     long long a = 0;
@@ -1275,11 +1275,13 @@ __device__ void place_chunk_wave(const Geo& g, const BinCount& bc, int mode, uin
 // and statistics, and for every placing workgroup the bin workgroup where its equal share of
 // output slots starts.
 constexpr int ST_THREADS = 1024;
+static_assert(PB % ST_THREADS == 0 && SB_MAX % ST_THREADS == 0, "scans take whole threads' shares");
 
 __global__ __launch_bounds__(ST_THREADS) void annih_scan(int mode, int place_blocks,
                                                          const long long* d_n_in,
                                                          long long* d_n_out, long long capacity,
-                                                         long long kb_limit, long long* stats, WS w) {
+                                                         long long kb_limit, int owners,
+                                                         long long* stats, WS w) {
     __shared__ long long bp[PB];
     __shared__ long long part[ST_THREADS];
     __shared__ long long tot[2];
@@ -1287,14 +1289,18 @@ __global__ __launch_bounds__(ST_THREADS) void annih_scan(int mode, int place_blo
         if (threadIdx.x == 0) w.sc[SC_GO] = 0;
         return;
     }
-    constexpr int per = PB / ST_THREADS;
+    constexpr int PER_MAX = SB_MAX / ST_THREADS;
     constexpr int NWS = ST_THREADS / 64;
-    // exclusive / inclusive scans of PB values, per thread `per` consecutive ones: thread sums
-    // scanned within each wave by shuffles, then across the waves' totals
-    auto scan = [&](const long long* in, long long* out_excl, long long* out_incl, long long* total) {
-        long long loc[per], acc = 0;
-        for (int k = 0; k < per; ++k) {
-            loc[k] = in[threadIdx.x * per + k];
+    // exclusive / inclusive scans of m values (PB, or the `owners` of the particle counts), per
+    // thread m / ST_THREADS consecutive ones: thread sums scanned within each wave by shuffles,
+    // then across the waves' totals
+    auto scan = [&](const long long* in, long long* out_excl, long long* out_incl, long long* total,
+                    int m) {
+        const int per = m / ST_THREADS;
+        long long loc[PER_MAX], acc = 0;
+#pragma unroll
+        for (int k = 0; k < PER_MAX; ++k) {
+            loc[k] = k < per ? in[threadIdx.x * per + k] : 0;
             acc += loc[k];
         }
         const long long inc = wave_incl_scan_ll(acc);
@@ -1309,7 +1315,9 @@ __global__ __launch_bounds__(ST_THREADS) void annih_scan(int mode, int place_blo
         }
         __syncthreads();
         long long run = base + inc - acc;
-        for (int k = 0; k < per; ++k) {
+#pragma unroll
+        for (int k = 0; k < PER_MAX; ++k) {
+            if (k >= per) break;
             if (out_excl) out_excl[threadIdx.x * per + k] = run;
             run += loc[k];
             if (out_incl) out_incl[threadIdx.x * per + k] = run;
@@ -1317,9 +1325,9 @@ __global__ __launch_bounds__(ST_THREADS) void annih_scan(int mode, int place_blo
         if (threadIdx.x == 0) *total = part[NWS];
         __syncthreads();
     };
-    scan(w.bpart, nullptr, bp, &tot[0]);
+    scan(w.bpart, nullptr, bp, &tot[0], PB);
     if (mode == 1) {
-        scan(w.bcnt, w.kpre, nullptr, &tot[1]);
+        scan(w.bcnt, w.kpre, nullptr, &tot[1], owners);
     } else if (threadIdx.x == 0) {
         tot[1] = 0;
     }
@@ -1334,7 +1342,7 @@ __global__ __launch_bounds__(ST_THREADS) void annih_scan(int mode, int place_blo
     // placement work items: prefix per bin workgroup, then every placing wave's first one
     __syncthreads();  // bp (the placed-particle prefix) has been copied out above
     __shared__ long long n_items;
-    scan(w.bitem, nullptr, bp, &n_items);
+    scan(w.bitem, nullptr, bp, &n_items, PB);
     for (int k = threadIdx.x; k < PB; k += ST_THREADS) w.ipre[k] = bp[k];
     const long long nw = (long long)place_blocks * WPB;
     const long long per_it = (n_items + nw - 1) / nw;
@@ -1407,7 +1415,7 @@ __global__ __launch_bounds__(PT) void annih_write(Geo g, int part_blocks, int pl
         int* smy = sm + (DIM == 2 ? WT : 0);
         int8_t* ssg = reinterpret_cast<int8_t*>(sm + DIM * WT);
         long lo, hi;
-        wave_chunk((long)*d_n_in, (long)blockIdx.x * WPB + wv, &lo, &hi);
+        wave_chunk((long)*d_n_in, (long)blockIdx.x * WPB + wv, &lo, &hi, (long)part_blocks * WPB);
         // with the counting pass's keep bits, a lane loads its four particles only when one of
         // them survives (particles of mixed bins, about half, are never read again); without
         // them the survivor test is redone from the positions and momenta
@@ -1930,6 +1938,12 @@ __global__ __launch_bounds__(PT) void pair_flags(const uint32_t* __restrict__ ke
     }
 }
 
+// Chunk owners of the annihilation's particle passes: as for sp_step, twice as many on large
+// buffers (the per-workgroup prologue amortised, the last residency round shorter).
+static int annih_owners(const sp_particles* in) {
+    return in->capacity >= SB_LARGE ? SB_MAX : PB;
+}
+
 // The counting pass's keep bits (one per input slot, in whole 256-particle tiles) go to the
 // end of out->x, past every position the output can occupy when the output is short enough;
 // annih_scan checks that against the output count and the writing pass uses them only then.
@@ -1989,12 +2003,13 @@ static void launch_pairs(const Geo& g, const sp_particles* in, sp_particles* out
     uint32_t* kbits;
     long long kb_limit;
     keep_bits_region<T>(in, out, &kbits, &kb_limit);
-    WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
+    const int own = annih_owners(in);
+    WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(own), dim3(PT), 0, s, g, x, y, M, My, in->s,
               d_n, cap_in, (const uint8_t*)q.flags, kbits, stats, w);
     WK_LAUNCH("annih_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 1, PLACE_BLOCKS, d_n,
-              reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, kb_limit, stats, w);
-    WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(PB + PLACE_BLOCKS), dim3(PT), 0, s, g,
-              PB, PLACE_BLOCKS, bc, 1, 0u, (uint32_t)TAG_ANNIH, x, y, M, My, in->s, d_n,
+              reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, kb_limit, own, stats, w);
+    WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(own + PLACE_BLOCKS), dim3(PT), 0, s, g,
+              own, PLACE_BLOCKS, bc, 1, 0u, (uint32_t)TAG_ANNIH, x, y, M, My, in->s, d_n,
               static_cast<T*>(out->x), static_cast<T*>(out->y), static_cast<MT*>(out->M),
               static_cast<MT*>(out->My), out->s, (long long)out->capacity, (const uint8_t*)q.flags,
               (const uint32_t*)kbits, w);
@@ -2213,12 +2228,13 @@ static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp
     uint32_t* kbits;
     long long kb_limit;
     keep_bits_region<T>(in, out, &kbits, &kb_limit);
-    WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(PB), dim3(PT), 0, s, g, x, y, M, My, in->s,
+    const int own = annih_owners(in);
+    WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(own), dim3(PT), 0, s, g, x, y, M, My, in->s,
               d_n, cap_in, (const uint8_t*)nullptr, kbits, stats, w);
     WK_LAUNCH("annih_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 1, PLACE_BLOCKS, d_n,
-              d_n_out, (long long)out->capacity, kb_limit, stats, w);
-    WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(PB + PLACE_BLOCKS), dim3(PT), 0, s, g,
-              PB, PLACE_BLOCKS, bc, 1, step, (uint32_t)TAG_ANNIH, x, y, M, My, in->s, d_n,
+              d_n_out, (long long)out->capacity, kb_limit, own, stats, w);
+    WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(own + PLACE_BLOCKS), dim3(PT), 0, s, g,
+              own, PLACE_BLOCKS, bc, 1, step, (uint32_t)TAG_ANNIH, x, y, M, My, in->s, d_n,
               static_cast<T*>(out->x), static_cast<T*>(out->y), static_cast<MT*>(out->M),
               static_cast<MT*>(out->My), out->s, (long long)out->capacity, (const uint8_t*)nullptr,
               (const uint32_t*)kbits, w);
@@ -2232,7 +2248,7 @@ static void launch_init(const Geo& g, const int32_t* counts, sp_particles* out, 
               (const uint32_t*)nullptr);
     WK_LAUNCH("init_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 0, PLACE_BLOCKS,
               (const long long*)nullptr, reinterpret_cast<long long*>(out->d_n),
-              (long long)out->capacity, -1LL, stats, w);
+              (long long)out->capacity, -1LL, PB, stats, w);
     WK_LAUNCH("init_write", (annih_write<T, MT, DIM>), dim3(PLACE_BLOCKS), dim3(PT), 0, s, g, 0,
               PLACE_BLOCKS, bc, 0, 0xFFFFFFFFu, (uint32_t)TAG_INIT, (const T*)nullptr,
               (const T*)nullptr, (const MT*)nullptr, (const MT*)nullptr, (const int8_t*)nullptr,
