@@ -45,10 +45,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # by what the counters read for a 1 GiB device copy (fetch x2.0, write x1.0).  Taken for the
 # kernels as they are now; an entry is dropped when its kernel changes until the counters are
 # taken again.
-TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1348, "annih_bins": 0.0008,
-                  "annih_count": 0.0633, "annih_write": 0.1225},
-           "2d": {"step_count": 0.7616, "step_apply": 2.1787, "annih_bins": 0.1212,
-                  "annih_count": 0.8282, "annih_write": 1.2757}}
+TRAFFIC = {"1d": {"step_count": 0.0611, "annih_bins": 0.0008, "annih_write": 0.1225},
+           "2d": {"step_count": 0.7616, "annih_bins": 0.1212, "annih_write": 1.2757}}
 
 
 def _events():
@@ -59,27 +57,34 @@ def _events():
 # Algorithmic HBM bytes per launch of each particle kernel, from the running sums the
 # library keeps (S = stats): what the pass must move at minimum with PB-byte particles
 # (FP32 positions, 8-bit momenta: 1-D x 4 + M 1 + s 1 = 6; 2-D x 4 + y 4 + M 1 + My 1 + s 1
-# = 11), the annihilation's keep bits (one per input particle, written by the counting pass
-# and read by the writing pass, which then reads the kept particles only) and, where a pass
+# = 11), the step's 4-byte histogram key of every output particle (read by the annihilation's
+# counting pass instead of the particle), the annihilation's keep bits (one per input
+# particle, written by the counting pass and read by the writing pass, which then reads the
+# kept particles only) and, where a pass
 # clears or walks the 2-D signed histogram (2 x 4 B x 67M bins, beyond every cache), the part
 # of it that pass touches.  Not counted: the 1-D histogram and all tables (L2-resident), the
 # 1-bit mixed-bin map (1/64 of the histogram) and the pair counts the two sp_step passes hand
 # over (an implementation choice).
-def kernel_bytes(PB: int, dim: int, hist_bytes: int, walked_bytes=None, cleared_bytes=None):
+def kernel_bytes(PB: int, dim: int, hist_bytes: int, walked_bytes=None, cleared_bytes=None,
+                 keys: bool = False):
     """walked_bytes: histogram bytes the bin pass had to read over the run (2-D: the blocks
     of bins that held counts, which the step marks); cleared_bytes: those the counting pass
     had to clear (the blocks the previous step marked).  None = the whole histogram each
-    step."""
+    step.  keys: the step writes every output particle's 4-byte histogram key and the
+    annihilation's counting pass reads those instead of the particles."""
+    KY = 4 if keys else 0
     pos = 4 * dim + 1            # what the counting pass reads: positions and sign
     H = hist_bytes if dim == 2 else 0
     walk = (lambda S, L: H * S[L.ST_CUM_STEPS]) if walked_bytes is None else (lambda S, L: walked_bytes)
     clear = (lambda S, L: H * S[L.ST_CUM_STEPS]) if cleared_bytes is None else (lambda S, L: cleared_bytes)
     return {
         "step_count": lambda S, L: pos * S[L.ST_CUM_N] + clear(S, L),                # + histogram clear
-        "step_apply": lambda S, L: 2 * PB * (S[L.ST_CUM_N] + S[L.ST_CUM_PAIRS]),     # read, write; 2 children
+        # read, write (2 children per pair), and the keys of the output
+        "step_apply": lambda S, L: (2 * PB * (S[L.ST_CUM_N] + S[L.ST_CUM_PAIRS])
+                                    + KY * (S[L.ST_CUM_N] + 2 * S[L.ST_CUM_PAIRS])),
         "annih_bins": walk,                                                           # histogram walk
         # read, and one keep bit per particle written
-        "annih_count": lambda S, L: PB * S[L.ST_CUM_ANNIH_IN] + S[L.ST_CUM_ANNIH_IN] / 8,
+        "annih_count": lambda S, L: (KY or PB) * S[L.ST_CUM_ANNIH_IN] + S[L.ST_CUM_ANNIH_IN] / 8,
         # the keep bits and the kept particles read, kept + placed written
         "annih_write": lambda S, L: (S[L.ST_CUM_ANNIH_IN] / 8 + PB * (2 * S[L.ST_CUM_KEPT]
                                                                    + S[L.ST_CUM_REGEN])),
@@ -87,7 +92,7 @@ def kernel_bytes(PB: int, dim: int, hist_bytes: int, walked_bytes=None, cleared_
 
 
 def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str = "regenerate",
-                  m_bytes=None, ms_ref=None):
+                  m_bytes=None, ms_ref=None, keys: bool = True):
     """A time-loop workload.  traced=True replays the identical (bit-exact, same seed) run with
     per-kernel events, used only for the per-kernel roofline; the reported value comes from
     the untraced run, whose time (ms_ref) the whole-step roofline uses.  m_bytes: momentum
@@ -98,7 +103,7 @@ def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str 
     from paper_1806_00082_amd.sim import Simulator
 
     sim = Simulator(cfg, kernel="exact", prec="fp64", mode="occupied", refresh_every=8,
-                    annihilation=annihilation, m_bytes=m_bytes)
+                    annihilation=annihilation, m_bytes=m_bytes, keys=keys)
     for _ in range(warmup):
         sim.step()
     sim.stats[L.ST_CUM_STEPS:L.ST_COUNT].zero_()
@@ -145,6 +150,7 @@ def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str 
     pbytes = (8 if sim.md["pos_f64"] else 4) * dim + sim.a.m_bytes * dim + 1
     out["particle_bytes"] = pbytes
     out["m_bytes"] = sim.a.m_bytes
+    use_keys = sim.keys is not None
     hist_bytes = 2 * 4 * ops.n_bins(sim.md)
     del sim
     torch.cuda.empty_cache()
@@ -156,7 +162,7 @@ def run_particles(cfg, steps: int, warmup: int, traced: bool, annihilation: str 
                      else int((walked + first - last).item()) * blk * 2 * 4)
     out["walked_hist_fraction"] = (None if walked_bytes is None
                                    else round(walked_bytes / (hist_bytes * steps), 4))
-    KB = kernel_bytes(pbytes, dim, hist_bytes, walked_bytes, cleared_bytes)
+    KB = kernel_bytes(pbytes, dim, hist_bytes, walked_bytes, cleared_bytes, keys=use_keys)
     kernels = {}
     for name in L.trace_names():
         tot, cnt = L.trace_read(name)
@@ -725,6 +731,8 @@ def main():
     ap.add_argument("--steps", type=int, default=190)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-keys", action="store_true",
+                    help="headline run without the step's histogram keys (the annihilation rereads the particles)")
     ap.add_argument("--m-bytes", type=int, default=None, choices=(1, 2, 4),
                     help="momentum storage of the headline run (default: the narrowest that fits)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -784,10 +792,11 @@ def main():
         return
     cfg = inputs.config_c2() if args.headline_1d else inputs.config_c5()
     print(f"headline: {cfg.name}, {args.warmup} + {args.steps} steps", file=sys.stderr, flush=True)
-    h = run_particles(cfg, args.steps, args.warmup, traced=False, m_bytes=args.m_bytes)
+    h = run_particles(cfg, args.steps, args.warmup, traced=False, m_bytes=args.m_bytes, keys=not args.no_keys)
     tr = h
     if not args.no_trace:
-        tr = run_particles(cfg, args.steps, args.warmup, traced=True, m_bytes=args.m_bytes, ms_ref=h["ms"])
+        tr = run_particles(cfg, args.steps, args.warmup, traced=True, m_bytes=args.m_bytes, ms_ref=h["ms"],
+                           keys=not args.no_keys)
         assert tr["stats"][11:16] == h["stats"][11:16], "traced replica diverged from the timed run"
     forms = {}
     if not args.no_forms and not args.headline_1d:

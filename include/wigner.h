@@ -264,6 +264,10 @@ int sp_init(const sp_geom* g, const int32_t* bin_counts, sp_particles* out, int6
  *         only the blocks of bins that call marked in the workspace hold counts and only
  *         they are cleared.  1-D histograms are always cleared whole.  Other values:
  *         WK_EINVAL.
+ *   keys  NULL, or uint32 [out->capacity] (16-byte aligned; needs hist) that receives each
+ *         output particle's histogram key: 2 * bin + 1 for a negative particle, 2 * bin for a
+ *         positive one, 0xFFFFFFFF for a particle outside the grid or absorbed.  Handed to
+ *         the next sp_annihilate, its counting pass reads them instead of the particles.
  * If out cannot hold n + 2 * pairs particles, d_stats[WK_ST_NEEDED] gets the required
  * capacity, the sticky WK_ST_OVERFLOW flag is set and `out` is invalid; `in` is never
  * written, and because the random stream is counter-based, re-running the step into a
@@ -273,7 +277,8 @@ int sp_init(const sp_geom* g, const int32_t* bin_counts, sp_particles* out, int6
 int sp_step(const sp_geom* g, const int32_t* cell_slot, const uint32_t* n0, const uint32_t* thr,
             const uint64_t* cdf, const uint32_t* guide, int32_t guide_len,
             const sp_particles* in, sp_particles* out, int32_t* hist, int32_t hist_mode,
-            int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes, void* stream);
+            uint32_t* keys, int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes,
+            void* stream);
 
 /* sp_annihilate -- rule 2 of Sec. 2.1 on the (cell, momentum) grid, from `in` to `out`:
  * output = for each bin holding both signs, in ascending bin order, |H+ - H-| particles of
@@ -290,12 +295,14 @@ int sp_step(const sp_geom* g, const int32_t* cell_slot, const uint32_t* n0, cons
  *   reads only those blocks of the histogram (the rest are zero).  Any other value is
  *   refused (WK_EINVAL).  Either way `hist` is left holding H+ then H- of the input: the
  *   signed histogram of rule 1.
+ *   keys  NULL, or the keys sp_step wrote for the particles of `in` (16-byte aligned),
+ *   unchanged since: the survivor test then reads them instead of the particles.
  * If the output would exceed out->capacity, d_stats gets the needed size, the sticky
  * overflow flag is set and `out` is invalid (`in` is untouched).  The slots of `out` past
  * the output count serve as scratch during the call; their contents are unspecified. */
 int sp_annihilate(const sp_geom* g, const sp_particles* in, sp_particles* out, int32_t* hist,
-                  int32_t hist_ready, int64_t step, int64_t* d_stats, void* ws, size_t ws_bytes,
-                  void* stream);
+                  int32_t hist_ready, const uint32_t* keys, int64_t step, int64_t* d_stats,
+                  void* ws, size_t ws_bytes, void* stream);
 
 /* sp_annihilate_pairs -- rule 2 of Sec. 2.1 read literally, as pair removal: in each
  * (cell, momentum) bin the k-th positive and the k-th negative particle in input order

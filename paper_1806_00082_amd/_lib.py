@@ -60,10 +60,10 @@ SIGNATURES = {
     "wk_gamma_tables": (ctypes.c_int, [_MP, _P, _i32, _i32, _i32, _f64, _P, _P, _P, _P, _P]),
     "sp_workspace_size": (_sz, [_GP]),
     "sp_init": (ctypes.c_int, [_GP, _P, _PP, _P, _P, _sz, _P]),
-    "sp_step": (ctypes.c_int, [_GP, _P, _P, _P, _P, _P, _i32, _PP, _PP, _P, _i32, _i64, _P, _P, _sz, _P]),
+    "sp_step": (ctypes.c_int, [_GP, _P, _P, _P, _P, _P, _i32, _PP, _PP, _P, _i32, _P, _i64, _P, _P, _sz, _P]),
     "wk_sampling_guide": (ctypes.c_int, [_P, _i32, _i32, _i32, _P, _P]),
     "wk_kernel_tables": (ctypes.c_int, [_MP, _P, _i32, _P, _i32, _i32, _f64, _P, _P, _P, _P, _P, _i32, _P]),
-    "sp_annihilate": (ctypes.c_int, [_GP, _PP, _PP, _P, _i32, _i64, _P, _P, _sz, _P]),
+    "sp_annihilate": (ctypes.c_int, [_GP, _PP, _PP, _P, _i32, _P, _i64, _P, _P, _sz, _P]),
     "sp_pairs_scratch_size": (_sz, [_GP, _i64]),
     "sp_annihilate_pairs": (ctypes.c_int, [_GP, _PP, _PP, _P, _i32, _P, _P, _sz, _P, _sz, _P]),
     "sp_density": (ctypes.c_int, [_GP, _P, _f64, _P, _P]),

@@ -169,6 +169,13 @@ __device__ __forceinline__ long bin_val(const Geo& g, T x, T y, int m, int my, i
     return (long)(((cy * g.nx + cx) * g.n_k + ky) * g.n_k + kx);
 }
 
+// A particle's (bin, sign) key of the signed histogram: 2 bin + 1 for negative particles,
+// HKEY_NONE when it has no bin (dead or outside the grid).  n_bins < 2^31.
+constexpr uint32_t HKEY_NONE = 0xFFFFFFFFu;
+__device__ __forceinline__ uint32_t hist_key(long b, int8_t s) {
+    return b < 0 ? HKEY_NONE : 2u * (uint32_t)b + (s > 0 ? 0u : 1u);
+}
+
 // Four consecutive particles (ids id .. id+3, id a multiple of 4) loaded with 16-byte
 // (positions, int32 momenta), 8-byte (int16 momenta) and 4-byte (int8 momenta, signs) accesses;
 // slots at or beyond hi read as dead.
@@ -251,6 +258,18 @@ __device__ __forceinline__ void load4(const T* x, const T* y, const MT* M, const
             p.y[k] = (T)0;
             p.my[k] = 0;
         }
+    }
+}
+
+// Histogram keys of four consecutive particles (id a multiple of 4); slots at or beyond hi
+// read as HKEY_NONE.
+__device__ __forceinline__ void load_keys4(const uint32_t* keys, long id, long hi, uint32_t* k4) {
+    if (id + IT <= hi) {
+        const uint4 t = *reinterpret_cast<const uint4*>(keys + id);
+        k4[0] = t.x; k4[1] = t.y; k4[2] = t.z; k4[3] = t.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) k4[k] = id + k < hi ? keys[id + k] : HKEY_NONE;
     }
 }
 
@@ -787,7 +806,7 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
                                                  const MT* M, const MT* My, const int8_t* s,
                                                  const long long* d_n_in, T* xo, T* yo, MT* Mo,
                                                  MT* Myo, int8_t* so, long long* d_n_out,
-                                                 long long cap_out, int32_t* hist,
+                                                 long long cap_out, int32_t* hist, uint32_t* keys,
                                                  long long* stats, long long st, WS w) {
     __shared__ long long red[PT / 64];
     __shared__ long wmin[PT / 64];
@@ -885,7 +904,11 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
                             }
                             so[o] = cs;
                         }
-                        if (HIST) hw.add_one(bin_val<T, DIM>(g, cx, cy, cm, cmy, cs), cs);
+                        if (HIST) {
+                            const long cb = bin_val<T, DIM>(g, cx, cy, cm, cmy, cs);
+                            if (keys != nullptr && o >= n && o < cap_out) keys[o] = hist_key(cb, cs);
+                            hw.add_one(cb, cs);
+                        }
                     }
                 }
             }
@@ -926,6 +949,7 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
         }
         // parents: drift, absorb, same index in `out` (n <= cap_out was checked)
         T nxv[IT], nyv[IT];
+        uint32_t kk[IT];
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
             nxv[k] = p.x[k];
@@ -938,9 +962,22 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
                 abs_m += a == 2;
                 if (a) p.s[k] = 0;
             }
-            if (HIST) hw.add_wave(bin_val<T, DIM>(g, nxv[k], nyv[k], p.m[k], p.my[k], p.s[k]), p.s[k]);
+            if (HIST) {
+                const long b = bin_val<T, DIM>(g, nxv[k], nyv[k], p.m[k], p.my[k], p.s[k]);
+                kk[k] = hist_key(b, p.s[k]);
+                hw.add_wave(b, p.s[k]);
+            }
         }
         store4<T, MT, DIM>(xo, yo, Mo, Myo, so, id, hi, nxv, nyv, p);
+        if (HIST && keys != nullptr) {
+            if (id + IT <= hi) {
+                *reinterpret_cast<uint4*>(keys + id) = make_uint4(kk[0], kk[1], kk[2], kk[3]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < IT; ++k)
+                    if (id + k < hi) keys[id + k] = kk[k];
+            }
+        }
         if (qlen > QN - WT) drain(QN - WT);  // room for the next tile
     }
     drain(0);
@@ -1064,7 +1101,7 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
                                                   const MT* My, const int8_t* s,
                                                   const long long* d_n_in, long long cap_in,
                                                   const uint8_t* flags, uint32_t* kbits,
-                                                  long long* stats, WS w) {
+                                                  const uint32_t* keys, long long* stats, WS w) {
     __shared__ long long red[PT / 64];
     __shared__ uint32_t lw[KWW];
     __shared__ long wmin[PT / 64];
@@ -1080,19 +1117,44 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
     const int lane = threadIdx.x & 63;
     long lo, hi;
     wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi, (long)gridDim.x * WPB);
-    const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin,
-                                      w.mixbits, 8 * g.n_chunks, flags);
-    long long a = 0;
-    Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
-    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
-    for (long t0 = lo; t0 < hi; t0 += WT) {
-        const long id = t0 + IT * (threadIdx.x & 63);
-        Part4<T, DIM> p = nxt;
-        load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
-        uint32_t nib = 0;
+    // with the keys sp_step wrote for `in`, a particle's bin is one 4-byte load
+    const bool use_keys = keys != nullptr;
+    long b_first = LONG_MAX;
+    if (use_keys) {
+        uint32_t k4[IT];
+        load_keys4(keys, lo + IT * lane, hi, k4);
 #pragma unroll
         for (int k = 0; k < IT; ++k)
-            nib |= kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), id + k) ? 1u << k : 0u;
+            if (k4[k] != HKEY_NONE) b_first = min(b_first, (long)(k4[k] >> 1));
+    } else {
+        b_first = first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi);
+    }
+    const KeepWindow kw = keep_window(b_first, lw, wmin, w.mixbits, 8 * g.n_chunks, flags);
+    long long a = 0;
+    Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
+    uint32_t knx[IT];
+    if (use_keys)
+        load_keys4(keys, lo + IT * lane, hi, knx);
+    else
+        load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
+    for (long t0 = lo; t0 < hi; t0 += WT) {
+        const long id = t0 + IT * (threadIdx.x & 63);
+        uint32_t nib = 0;
+        if (use_keys) {
+            uint32_t kc[IT];
+#pragma unroll
+            for (int k = 0; k < IT; ++k) kc[k] = knx[k];
+            load_keys4(keys, id + WT, hi, knx);
+#pragma unroll
+            for (int k = 0; k < IT; ++k)
+                nib |= kw.keeps(kc[k] == HKEY_NONE ? -1L : (long)(kc[k] >> 1), id + k) ? 1u << k : 0u;
+        } else {
+            Part4<T, DIM> p = nxt;
+            load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+#pragma unroll
+            for (int k = 0; k < IT; ++k)
+                nib |= kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), id + k) ? 1u << k : 0u;
+        }
         a += __popc(nib);
         if (kbits != nullptr) {
             // one keep bit per particle: word q of the tile (ids t0 + 32q .. t0 + 32q + 31, t0 a
@@ -2005,7 +2067,7 @@ static void launch_pairs(const Geo& g, const sp_particles* in, sp_particles* out
     keep_bits_region<T>(in, out, &kbits, &kb_limit);
     const int own = annih_owners(in);
     WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(own), dim3(PT), 0, s, g, x, y, M, My, in->s,
-              d_n, cap_in, (const uint8_t*)q.flags, kbits, stats, w);
+              d_n, cap_in, (const uint8_t*)q.flags, kbits, (const uint32_t*)nullptr, stats, w);
     WK_LAUNCH("annih_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 1, PLACE_BLOCKS, d_n,
               reinterpret_cast<long long*>(out->d_n), (long long)out->capacity, kb_limit, own, stats, w);
     WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(own + PLACE_BLOCKS), dim3(PT), 0, s, g,
@@ -2171,7 +2233,8 @@ template <typename T, typename MT, int DIM>
 static void launch_step(const Geo& g, uint32_t step, const int32_t* cs, const uint32_t* n0,
                         const uint32_t* thr, const uint64_t* cdf, const uint32_t* guide,
                         int guide_len, const sp_particles* in, sp_particles* out, int32_t* hist,
-                        int hist_mode, long long* stats, long long st, WS w, hipStream_t s) {
+                        int hist_mode, uint32_t* keys, long long* stats, long long st, WS w,
+                        hipStream_t s) {
     const long long* d_n_in = reinterpret_cast<const long long*>(in->d_n);
     long long* d_n_out = reinterpret_cast<long long*>(out->d_n);
     const long long cap = (long long)out->capacity;
@@ -2194,16 +2257,17 @@ static void launch_step(const Geo& g, uint32_t step, const int32_t* cs, const ui
     if (hist)
         WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, true>), dim3(sb), dim3(PT), 0, s, g, step, cs,
                   n0, thr, cdf, guide, guide_len, x, y, M, My, in->s, d_n_in, xo, yo, Mo, Myo,
-                  out->s, d_n_out, cap, hist, stats, st, w);
+                  out->s, d_n_out, cap, hist, keys, stats, st, w);
     else
         WK_LAUNCH("step_apply", (step_apply<T, MT, DIM, false>), dim3(sb), dim3(PT), 0, s, g, step, cs,
                   n0, thr, cdf, guide, guide_len, x, y, M, My, in->s, d_n_in, xo, yo, Mo, Myo,
-                  out->s, d_n_out, cap, hist, stats, st, w);
+                  out->s, d_n_out, cap, hist, (uint32_t*)nullptr, stats, st, w);
 }
 
 template <typename T, typename MT, int DIM>
 static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp_particles* out,
-                         int32_t* hist, int hist_ready, long long* stats, WS w, hipStream_t s) {
+                         int32_t* hist, int hist_ready, const uint32_t* keys, long long* stats, WS w,
+                         hipStream_t s) {
     const T* x = static_cast<const T*>(in->x);
     const T* y = static_cast<const T*>(in->y);
     const MT* M = static_cast<const MT*>(in->M);
@@ -2230,7 +2294,7 @@ static void launch_annih(const Geo& g, uint32_t step, const sp_particles* in, sp
     keep_bits_region<T>(in, out, &kbits, &kb_limit);
     const int own = annih_owners(in);
     WK_LAUNCH("annih_count", (annih_count<T, MT, DIM>), dim3(own), dim3(PT), 0, s, g, x, y, M, My, in->s,
-              d_n, cap_in, (const uint8_t*)nullptr, kbits, stats, w);
+              d_n, cap_in, (const uint8_t*)nullptr, kbits, keys, stats, w);
     WK_LAUNCH("annih_scan", annih_scan, dim3(1), dim3(ST_THREADS), 0, s, 1, PLACE_BLOCKS, d_n,
               d_n_out, (long long)out->capacity, kb_limit, own, stats, w);
     WK_LAUNCH("annih_write", (annih_write<T, MT, DIM>), dim3(own + PLACE_BLOCKS), dim3(PT), 0, s, g,
@@ -2312,8 +2376,8 @@ extern "C" int sp_init(const sp_geom* gm, const int32_t* bin_counts, sp_particle
 extern "C" int sp_step(const sp_geom* gm, const int32_t* cell_slot, const uint32_t* n0,
                        const uint32_t* thr, const uint64_t* cdf, const uint32_t* guide,
                        int32_t guide_len, const sp_particles* in, sp_particles* out,
-                       int32_t* hist, int32_t hist_mode, int64_t step, int64_t* d_stats, void* ws,
-                       size_t ws_bytes, void* stream) {
+                       int32_t* hist, int32_t hist_mode, uint32_t* keys, int64_t step,
+                       int64_t* d_stats, void* ws, size_t ws_bytes, void* stream) {
     Geo g;
     int rc = make_geo(gm, &g);
     if (rc) return rc;
@@ -2325,20 +2389,23 @@ extern "C" int sp_step(const sp_geom* gm, const int32_t* cell_slot, const uint32
                "sp_step: in and out must be different buffers");
     WK_REQUIRE(cell_slot && n0 && thr && cdf && d_stats, "sp_step: NULL array");
     WK_REQUIRE(hist_mode == 0 || hist_mode == 1, "sp_step: hist_mode must be 0 or 1");
+    WK_REQUIRE(keys == nullptr || hist != nullptr, "sp_step: keys come with the histogram (hist != NULL)");
+    WK_REQUIRE(keys == nullptr || (reinterpret_cast<uintptr_t>(keys) & 15) == 0,
+               "sp_step: keys must be 16-byte aligned");
     WK_REQUIRE(step >= 0 && step < (1LL << 32), "sp_step: step must fit 32 bits");
     WK_REQUIRE(guide == nullptr || (guide_len >= 1 && guide_len <= (1 << 20)),
                "sp_step: guide_len out of range");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_step: workspace too small");
     WS w = carve(ws, g.n_bins, (long)g.nx * g.ny);
     WK_DISPATCH(gm, launch_step, g, (uint32_t)step, cell_slot, n0, thr, cdf, guide, guide_len, in,
-                out, hist, (int)hist_mode, reinterpret_cast<long long*>(d_stats), (long long)step, w,
-                as_stream(stream));
+                out, hist, (int)hist_mode, keys, reinterpret_cast<long long*>(d_stats), (long long)step,
+                w, as_stream(stream));
     return check_launch("sp_step");
 }
 
 extern "C" int sp_annihilate(const sp_geom* gm, const sp_particles* in, sp_particles* out,
-                             int32_t* hist, int32_t hist_ready, int64_t step, int64_t* d_stats,
-                             void* ws, size_t ws_bytes, void* stream) {
+                             int32_t* hist, int32_t hist_ready, const uint32_t* keys, int64_t step,
+                             int64_t* d_stats, void* ws, size_t ws_bytes, void* stream) {
     Geo g;
     int rc = make_geo(gm, &g);
     if (rc) return rc;
@@ -2350,10 +2417,12 @@ extern "C" int sp_annihilate(const sp_geom* gm, const sp_particles* in, sp_parti
                "sp_annihilate: in and out must be different buffers");
     WK_REQUIRE(hist && d_stats, "sp_annihilate: NULL array");
     WK_REQUIRE(hist_ready >= 0 && hist_ready <= 2, "sp_annihilate: hist_ready must be 0, 1 or 2");
+    WK_REQUIRE(keys == nullptr || (reinterpret_cast<uintptr_t>(keys) & 15) == 0,
+               "sp_annihilate: keys must be 16-byte aligned");
     WK_REQUIRE(step >= 0 && step < (1LL << 32), "sp_annihilate: step must fit 32 bits");
     WK_REQUIRE(ws && ws_bytes >= ws_bytes_for(g.n_bins, (long)g.nx * g.ny), "sp_annihilate: workspace too small");
     WS w = carve(ws, g.n_bins, (long)g.nx * g.ny);
-    WK_DISPATCH(gm, launch_annih, g, (uint32_t)step, in, out, hist, (int)hist_ready,
+    WK_DISPATCH(gm, launch_annih, g, (uint32_t)step, in, out, hist, (int)hist_ready, keys,
                 reinterpret_cast<long long*>(d_stats), w, as_stream(stream));
     return check_launch("sp_annihilate");
 }

@@ -289,30 +289,33 @@ def sampling_guide(cdf: torch.Tensor, guide_len: int, out: torch.Tensor | None =
 
 def sp_step(mesh: dict, seed: int, cell_slot, n0, thr, cdf, pin: DeviceParticles,
             pout: DeviceParticles, step: int, stats: torch.Tensor, ws: torch.Tensor,
-            hist: torch.Tensor | None = None, guide: torch.Tensor | None = None, hist_mode: int = 0):
+            hist: torch.Tensor | None = None, guide: torch.Tensor | None = None, hist_mode: int = 0,
+            keys: torch.Tensor | None = None):
     """One step from pin to pout.  hist (optional): receives the signed histogram of the
     ensemble after the step; hist_mode 1: `hist` is unchanged since the last histogram
     build on this workspace, so only its marked blocks need clearing.  guide (optional):
-    sampling_guide() of the cdf rows."""
+    sampling_guide() of the cdf rows.  keys (optional, with hist): 32-bit [pout.capacity]
+    receiving every output particle's histogram key."""
     g = geom_struct(mesh, seed, _m_bytes(pin, pout))
     a, b = pin.struct(), pout.struct()
     glen = 0 if guide is None else guide.shape[1] - 1
     L.check(L.lib().sp_step(ctypes.byref(g), _ptr(cell_slot), _ptr(n0), _ptr(thr), _ptr(cdf),
                             _ptr(guide), glen, ctypes.byref(a), ctypes.byref(b), _ptr(hist),
-                            int(hist_mode), step,
+                            int(hist_mode), _ptr(keys), step,
                             _ptr(stats), _ptr(ws), ws.numel(), _stream()), "sp_step")
 
 
 def sp_annihilate(mesh: dict, seed: int, pin: DeviceParticles, pout: DeviceParticles,
                   hist: torch.Tensor, step: int, stats: torch.Tensor, ws: torch.Tensor,
-                  hist_ready: int = 0):
+                  hist_ready: int = 0, keys: torch.Tensor | None = None):
     """hist_ready: 0 = build the histogram here; 1 (or True) = `hist` already holds the
     histogram of `pin`; 2 = it is what the last sp_step on this workspace built, unchanged
-    (the annihilation then reads only the blocks that step marked)."""
+    (the annihilation then reads only the blocks that step marked).  keys: the keys sp_step
+    wrote for `pin` (optional)."""
     g = geom_struct(mesh, seed, _m_bytes(pin, pout))
     a, b = pin.struct(), pout.struct()
     L.check(L.lib().sp_annihilate(ctypes.byref(g), ctypes.byref(a), ctypes.byref(b), _ptr(hist),
-                                  int(hist_ready), step, _ptr(stats), _ptr(ws), ws.numel(),
+                                  int(hist_ready), _ptr(keys), step, _ptr(stats), _ptr(ws), ws.numel(),
                                   _stream()), "sp_annihilate")
 
 

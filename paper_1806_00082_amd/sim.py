@@ -40,7 +40,7 @@ class Simulator:
     def __init__(self, cfg, kernel: str = "exact", prec: str = "fp64", mode: str = "occupied",
                  refresh_every: int = 8, cap_factor: float = 3.0, weights=None, N: int = 2,
                  device="cuda", hist_in_step: bool = True, rows=None, m_bytes=None,
-                 fused_tables: bool = True, annihilation: str = "regenerate"):
+                 fused_tables: bool = True, annihilation: str = "regenerate", keys: bool = True):
         self.cfg = cfg
         self.md = cfg.mesh.as_dict(cfg.dt)
         md = self.md
@@ -105,6 +105,10 @@ class Simulator:
         self.stats = ops.new_stats(self.dev)
         self.ws = ops.sp_workspace(md, self.seed, self.dev)
         self.hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=self.dev)
+        # every particle's histogram key from sp_step, read back by the annihilation's counting
+        # pass in place of the particles (the rule-2 regeneration path)
+        self.keys = (torch.empty(self.capacity, dtype=torch.int32, device=self.dev)
+                     if keys and hist_in_step and annihilation == "regenerate" else None)
         self.pair_scratch = (ops.sp_pairs_scratch(md, self.capacity, self.dev)
                              if annihilation == "pairs" else None)
         ops.sp_init(md, self.seed, bc.to(self.dev), self.a, self.stats, self.ws)
@@ -187,13 +191,13 @@ class Simulator:
             self.refresh()
         ops.sp_step(self.md, self.seed, self.cell_slot, self.n0, self.thr, self.cdf, self.a,
                     self.b, s, self.stats, self.ws, hist=self.hist if self.hist_in_step else None,
-                    guide=self.guide, hist_mode=1 if self.hist_marked else 0)
+                    guide=self.guide, hist_mode=1 if self.hist_marked else 0, keys=self.keys)
         if self.annihilation == "pairs":
             ops.sp_annihilate_pairs(self.md, self.b, self.a, self.hist, self.stats, self.ws,
                                     self.pair_scratch, hist_ready=2 if self.hist_in_step else 0)
         else:
             ops.sp_annihilate(self.md, self.seed, self.b, self.a, self.hist, s, self.stats, self.ws,
-                              hist_ready=2 if self.hist_in_step else 0)
+                              hist_ready=2 if self.hist_in_step else 0, keys=self.keys)
         self.step_index += 1
         self.hist_marked = True   # built by sp_step, or by the annihilation itself
 

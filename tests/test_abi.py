@@ -105,26 +105,36 @@ def test_particle_calls_reject_aliased_buffers_without_gpu():
     ws = int(lib.sp_workspace_size(ctypes.byref(g)))
     f = 0x9000
     rc = lib.sp_step(ctypes.byref(g), f, f, f, f, None, 0, ctypes.byref(p), ctypes.byref(p), None,
-                     0, 0, f, f, ws, None)
+                     0, None, 0, f, f, ws, None)
     assert rc == _lib.WK_EINVAL and b"different buffers" in lib.wk_last_error()
-    rc = lib.sp_annihilate(ctypes.byref(g), ctypes.byref(q), ctypes.byref(q), f, 0, 0, f, f, ws, None)
+    rc = lib.sp_annihilate(ctypes.byref(g), ctypes.byref(q), ctypes.byref(q), f, 0, None, 0, f, f, ws, None)
     assert rc == _lib.WK_EINVAL and b"different buffers" in lib.wk_last_error()
     for bad in (-1, 3):
-        rc = lib.sp_annihilate(ctypes.byref(g), ctypes.byref(p), ctypes.byref(q), f, bad, 0, f, f, ws, None)
+        rc = lib.sp_annihilate(ctypes.byref(g), ctypes.byref(p), ctypes.byref(q), f, bad, None, 0, f, f, ws,
+                               None)
         assert rc == _lib.WK_EINVAL and b"hist_ready" in lib.wk_last_error()
         rc = lib.sp_annihilate_pairs(ctypes.byref(g), ctypes.byref(p), ctypes.byref(q), f, bad, f, f, ws,
                                      f, 1 << 40, None)
         assert rc == _lib.WK_EINVAL and b"hist_ready" in lib.wk_last_error()
     rc = lib.sp_step(ctypes.byref(g), f, f, f, f, f, 0, ctypes.byref(p), ctypes.byref(q), None,
-                     0, 0, f, f, ws, None)
+                     0, None, 0, f, f, ws, None)
     assert rc == _lib.WK_EINVAL and b"guide_len" in lib.wk_last_error()
     rc = lib.sp_step(ctypes.byref(g), f, f, f, f, None, 0, ctypes.byref(p), ctypes.byref(q), None,
-                     0, 0, f, f, ws - 1, None)
+                     0, None, 0, f, f, ws - 1, None)
     assert rc == _lib.WK_EINVAL and b"workspace" in lib.wk_last_error()
     for bad in (-1, 2):
         rc = lib.sp_step(ctypes.byref(g), f, f, f, f, None, 0, ctypes.byref(p), ctypes.byref(q), f,
-                         bad, 0, f, f, ws, None)
+                         bad, None, 0, f, f, ws, None)
         assert rc == _lib.WK_EINVAL and b"hist_mode" in lib.wk_last_error()
+    # keys come with a histogram and are 16-byte aligned
+    rc = lib.sp_step(ctypes.byref(g), f, f, f, f, None, 0, ctypes.byref(p), ctypes.byref(q), None,
+                     0, f, 0, f, f, ws, None)
+    assert rc == _lib.WK_EINVAL and b"keys" in lib.wk_last_error()
+    rc = lib.sp_step(ctypes.byref(g), f, f, f, f, None, 0, ctypes.byref(p), ctypes.byref(q), f,
+                     0, f + 4, 0, f, f, ws, None)
+    assert rc == _lib.WK_EINVAL and b"aligned" in lib.wk_last_error()
+    rc = lib.sp_annihilate(ctypes.byref(g), ctypes.byref(p), ctypes.byref(q), f, 0, f + 4, 0, f, f, ws, None)
+    assert rc == _lib.WK_EINVAL and b"aligned" in lib.wk_last_error()
 
 
 def test_struct_layouts_match_header(tmp_path):

@@ -51,6 +51,23 @@ def test_init_overflow_reports_needed(orc):
     assert p.count() == 0
 
 
+def _expected_keys(v, md):
+    """Histogram keys of a host particle view: 2 bin + 1 for negative particles, 0xFFFFFFFF
+    (as int32: -1) for dead or off-grid ones."""
+    nk, nx = md["n_k"], md["nx"]
+    cx = np.floor(v["x"].astype(np.float64)).astype(np.int64)
+    kx = v["M"].astype(np.int64) - md["M_min"]
+    ok = (v["s"] != 0) & (cx >= 0) & (cx < nx) & (kx >= 0) & (kx < nk)
+    if md["dim"] == 2:
+        cy = np.floor(v["y"].astype(np.float64)).astype(np.int64)
+        ky = v["My"].astype(np.int64) - md["M_min"]
+        ok &= (cy >= 0) & (cy < md["ny"]) & (ky >= 0) & (ky < nk)
+        b = ((cy * nx + cx) * nk + ky) * nk + kx
+    else:
+        b = cx * nk + kx
+    return np.where(ok, 2 * b + (v["s"] < 0), -1).astype(np.int64)
+
+
 def _ready(fused: bool, s: int) -> int:
     """How a loop hands the histogram to sp_annihilate: built there (0, unfused steps), or
     the one sp_step just built, as such (1) or with the block map of its workspace (2)."""
@@ -270,6 +287,7 @@ def test_2d_step_and_annihilation(orc, nx, ny, odd_hist, m_bytes):
     b = ops.DeviceParticles(2, cap, False, m_bytes=m_bytes)
     hist = (_odd_word_hist(2 * ops.n_bins(md)) if odd_hist
             else torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev()))
+    hkeys = torch.empty(cap, dtype=torch.int32, device=dev())
     slot = np.arange(nx * ny, dtype=np.int32)
     if nx * ny > 1024:
         slot[::7] = -1
@@ -279,15 +297,21 @@ def test_2d_step_and_annihilation(orc, nx, ny, odd_hist, m_bytes):
     for s in range(4):
         fused = s % 2 == 1
         hp, hst = orc.sp_step(md, hp, tables[1:], slot, step=s, seed=seed)
+        use_keys = s == 3    # the keys sp_step can hand to the annihilation, on one fused step
         ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, b, s, st, ws, hist=hist if fused else None,
-                    guide=guide if s >= 2 else None, hist_mode=1 if s == 3 else 0)
+                    guide=guide if s >= 2 else None, hist_mode=1 if s == 3 else 0,
+                    keys=hkeys if use_keys else None)
         assert_particles_equal(b.view(), hp.view(), f"2-D step {s}")
+        if use_keys:
+            got = to_np(hkeys[:hp.n]).astype(np.int64)
+            assert np.array_equal(np.where(got == -1, -1, got & 0xFFFFFFFF), _expected_keys(hp.view(), md))
         hp, hh_p, hh_m, hst = orc.sp_annihilate(md, hp, step=s, seed=seed, capacity=cap)
         if fused:
             h = to_np(hist)
             nb = ops.n_bins(md)
             assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"2-D step hist {s}"
-        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=_ready(fused, s))
+        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=_ready(fused, s),
+                          keys=hkeys if use_keys else None)
         assert_particles_equal(a.view(), hp.view(), f"2-D annihilate {s}")
     assert hst[orc.ST_MIXED] > 0
 
@@ -352,6 +376,7 @@ def _c5_compare(orc, md, tables, slot, hp, seed, steps, first_step, label, m_byt
     st = ops.new_stats()
     ws = ops.sp_workspace(md, seed)
     hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=dev())
+    hkeys = torch.empty(cap, dtype=torch.int32, device=dev())
     n0, thr, cdf = host_tables_to_device((None,) + tuple(tables))
     slot_d = torch.from_numpy(slot).to(dev())
     guide = ops.sampling_guide(cdf, 256)
@@ -362,7 +387,8 @@ def _c5_compare(orc, md, tables, slot, hp, seed, steps, first_step, label, m_byt
         print(f"{label}: step {s} ({hp.n} particles, histogram from sp_step: {fused})", flush=True)
         hp, hst = orc.sp_step(md, hp, tables, slot, step=s, seed=seed)
         ops.sp_step(md, seed, slot_d, n0, thr, cdf, a, b, s, st, ws, hist=hist if fused else None,
-                    guide=guide if s % 2 == 0 else None, hist_mode=1 if fused else 0)
+                    guide=guide if s % 2 == 0 else None, hist_mode=1 if fused else 0,
+                    keys=hkeys if fused else None)
         gst = to_np(st)
         assert gst[L.ST_OVERFLOW] == 0
         for k in (L.ST_N, L.ST_PAIRS, L.ST_ABS_X, L.ST_ABS_M):
@@ -374,7 +400,8 @@ def _c5_compare(orc, md, tables, slot, hp, seed, steps, first_step, label, m_byt
         if fused:
             h = to_np(hist)
             assert np.array_equal(h[:nb], hh_p) and np.array_equal(h[nb:], hh_m), f"{label} step hist {s}"
-        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=_ready(fused, s))
+        ops.sp_annihilate(md, seed, b, a, hist, s, st, ws, hist_ready=_ready(fused, s),
+                          keys=hkeys if fused else None)
         gst = to_np(st)
         for k in (L.ST_N, L.ST_KEPT, L.ST_REGEN, L.ST_MIXED):
             assert gst[k] == hst[k], (label, s, k, gst[k], hst[k])
