@@ -106,9 +106,10 @@ class Simulator:
         self.ws = ops.sp_workspace(md, self.seed, self.dev)
         self.hist = torch.zeros(2 * ops.n_bins(md), dtype=torch.int32, device=self.dev)
         # every particle's histogram key from sp_step, read back by the annihilation's counting
-        # pass in place of the particles (the rule-2 regeneration path)
+        # pass in place of the particles (the rule-2 regeneration path, 2-D: an 11-byte particle
+        # against a 4-byte key; a 1-D particle of 6 bytes gains nothing from it)
         self.keys = (torch.empty(self.capacity, dtype=torch.int32, device=self.dev)
-                     if keys and hist_in_step and annihilation == "regenerate" else None)
+                     if keys and self.dim == 2 and hist_in_step and annihilation == "regenerate" else None)
         self.pair_scratch = (ops.sp_pairs_scratch(md, self.capacity, self.dev)
                              if annihilation == "pairs" else None)
         ops.sp_init(md, self.seed, bc.to(self.dev), self.a, self.stats, self.ws)
