@@ -577,6 +577,7 @@ struct HistWindow {
     static constexpr uint32_t EMPTY = 0xFFFFFFFFu;  // never a key: 2 b + 1 < 2^32 - 1
 
     static constexpr int LOG2W = __builtin_ctz(W);
+    static constexpr int DPP_WAVE_SHR1 = 0x138;  // DPP control: lane i reads lane i - 1
 
     __device__ __forceinline__ void bump(long b, int sg, int cnt) {
         if constexpr (HASH) {
@@ -617,7 +618,10 @@ struct HistWindow {
     __device__ __forceinline__ void add_wave(long b, int8_t sv) {
         const int lane = threadIdx.x & 63;
         const uint32_t key = b < 0 ? EMPTY : 2u * (uint32_t)b + (sv > 0 ? 0u : 1u);
-        const uint32_t prev = (uint32_t)__shfl_up((int)key, 1, 64);
+        // the previous lane's key by a DPP wave shift (a VALU move; __shfl_up is an LDS
+        // permute with its round trip); lane 0 gets EMPTY and is a head anyway
+        const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int)EMPTY, (int)key, DPP_WAVE_SHR1,
+                                                                    0xf, 0xf, false);
         const bool head = lane == 0 || prev != key;
         const unsigned long long heads = __ballot(head);
         if (head && key != EMPTY) {

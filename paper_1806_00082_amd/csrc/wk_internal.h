@@ -123,15 +123,20 @@ inline int frac_bits_host(int n_max, int pos_f64) {
     return fb > 32 ? 32 : fb;
 }
 
-// Wave-level inclusive scan of an int (64 lanes) through DPP-free shuffles.
+// Wave-level inclusive scan of an int (64 lanes, all active): a Hillis-Steele scan inside each
+// row of 16 lanes by DPP row shifts (VALU moves; a shuffle is an LDS permute with its round
+// trip), then each row adds the totals of the rows below it, read from lanes 15, 31 and 47.
+// Lanes whose row-shift source lies outside their row add 0 (the `old` operand).
 __device__ __forceinline__ int wave_incl_scan(int v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
+    constexpr int ROW_SHR = 0x110;  // DPP control row_shr:n is ROW_SHR + n
+    v += __builtin_amdgcn_update_dpp(0, v, ROW_SHR + 1, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, ROW_SHR + 2, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, ROW_SHR + 4, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, ROW_SHR + 8, 0xf, 0xf, false);
+    const int row = (threadIdx.x & 63) >> 4;
+    const int t0 = __builtin_amdgcn_readlane(v, 15), t1 = __builtin_amdgcn_readlane(v, 31),
+              t2 = __builtin_amdgcn_readlane(v, 47);
+    return v + (row > 0 ? t0 : 0) + (row > 1 ? t1 : 0) + (row > 2 ? t2 : 0);
 }
 
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
