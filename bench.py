@@ -46,9 +46,9 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # kernels as they are now; an entry is dropped when its kernel changes until the counters are
 # taken again.
 TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1347, "annih_bins": 0.0008,
-                  "annih_count": 0.0627, "annih_write": 0.1224},
-           "2d": {"step_count": 0.7616, "step_apply": 2.4745, "annih_bins": 0.1211,
-                  "annih_count": 0.3129, "annih_write": 1.2751}}
+                  "annih_count": 0.0626, "annih_write": 0.1224},
+           "2d": {"step_count": 0.7616, "step_apply": 2.4744, "annih_bins": 0.1211,
+                  "annih_count": 0.3078, "annih_write": 1.2750}}
 
 
 def _events():

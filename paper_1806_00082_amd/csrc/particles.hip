@@ -1121,53 +1121,68 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
     const int lane = threadIdx.x & 63;
     long lo, hi;
     wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi, (long)gridDim.x * WPB);
-    // with the keys sp_step wrote for `in`, a particle's bin is one 4-byte load
-    const bool use_keys = keys != nullptr;
-    long b_first = LONG_MAX;
-    if (use_keys) {
-        uint32_t k4[IT];
-        load_keys4(keys, lo + IT * lane, hi, k4);
-#pragma unroll
-        for (int k = 0; k < IT; ++k)
-            if (k4[k] != HKEY_NONE) b_first = min(b_first, (long)(k4[k] >> 1));
-    } else {
-        b_first = first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi);
-    }
-    const KeepWindow kw = keep_window(b_first, lw, wmin, w.mixbits, 8 * g.n_chunks, flags);
     long long a = 0;
-    Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
-    uint32_t knx[IT];
-    if (use_keys)
-        load_keys4(keys, lo + IT * lane, hi, knx);
-    else
-        load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
-    for (long t0 = lo; t0 < hi; t0 += WT) {
-        const long id = t0 + IT * (threadIdx.x & 63);
-        uint32_t nib = 0;
-        if (use_keys) {
-            uint32_t kc[IT];
-#pragma unroll
-            for (int k = 0; k < IT; ++k) kc[k] = knx[k];
-            load_keys4(keys, id + WT, hi, knx);
-#pragma unroll
-            for (int k = 0; k < IT; ++k)
-                nib |= kw.keeps(kc[k] == HKEY_NONE ? -1L : (long)(kc[k] >> 1), id + k) ? 1u << k : 0u;
-        } else {
-            Part4<T, DIM> p = nxt;
-            load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
-#pragma unroll
-            for (int k = 0; k < IT; ++k)
-                nib |= kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), id + k) ? 1u << k : 0u;
-        }
+    // one keep bit per particle: word q of the tile (ids t0 + 32q .. t0 + 32q + 31, t0 a
+    // multiple of 256) holds bit k of lane 8q + i at 4i + k, built from one ballot per k
+    auto tile_done = [&](long t0, uint32_t nib) {
         a += __popc(nib);
         if (kbits != nullptr) {
-            // one keep bit per particle: word q of the tile (ids t0 + 32q .. t0 + 32q + 31, t0 a
-            // multiple of 256) holds bit k of lane 8q + i at 4i + k, built from one ballot per k
             uint32_t word = 0;
 #pragma unroll
             for (int k = 0; k < IT; ++k)
                 word |= spread4((uint32_t)(__ballot((nib >> k) & 1u) >> (8 * (lane & 7))) & 0xFFu) << k;
             if (lane < 8) kbits[(t0 >> 5) + lane] = word;
+        }
+    };
+    if (keys != nullptr && flags == nullptr) {
+        // With the keys sp_step wrote for `in`, a particle's mixed-bin word is one load that
+        // depends on one 4-byte load.  The wave takes KG tiles at a time: their keys were
+        // loaded during the previous group, and the words of all KG tiles are loaded together,
+        // so one round trip to the map serves KG tiles (4 measured best of 1, 2, 4, 8).  The
+        // words come straight from the map, with no LDS window to fill first; a dead particle
+        // or a slot past the chunk (HKEY_NONE) reads word 0 and ignores it.  The pair removal
+        // (flags) never passes keys; it takes the window path below.
+        constexpr int KG = 4;
+        uint32_t knx[KG][IT];
+#pragma unroll
+        for (int u = 0; u < KG; ++u) load_keys4(keys, lo + u * WT + IT * lane, hi, knx[u]);
+        for (long t0 = lo; t0 < hi; t0 += KG * WT) {  // per wave, no workgroup barriers
+            uint32_t kc[KG][IT], wd[KG][IT];
+#pragma unroll
+            for (int u = 0; u < KG; ++u)
+#pragma unroll
+                for (int k = 0; k < IT; ++k) kc[u][k] = knx[u][k];
+#pragma unroll
+            for (int u = 0; u < KG; ++u)
+#pragma unroll
+                for (int k = 0; k < IT; ++k) wd[u][k] = w.mixbits[kc[u][k] == HKEY_NONE ? 0u : kc[u][k] >> 6];
+#pragma unroll
+            for (int u = 0; u < KG; ++u) load_keys4(keys, t0 + (KG + u) * WT + IT * lane, hi, knx[u]);
+#pragma unroll
+            for (int u = 0; u < KG; ++u) {
+                if (t0 + u * WT >= hi) break;  // uniform in the wave
+                uint32_t nib = 0;
+#pragma unroll
+                for (int k = 0; k < IT; ++k)  // survives rule 2: its bin holds one sign
+                    nib |= kc[u][k] != HKEY_NONE && ((wd[u][k] >> ((kc[u][k] >> 1) & 31u)) & 1u) == 0u
+                               ? 1u << k : 0u;
+                tile_done(t0 + u * WT, nib);
+            }
+        }
+    } else {
+        const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin,
+                                          w.mixbits, 8 * g.n_chunks, flags);
+        Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
+        load4<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
+        for (long t0 = lo; t0 < hi; t0 += WT) {
+            const long id = t0 + IT * lane;
+            Part4<T, DIM> p = nxt;
+            load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+            uint32_t nib = 0;
+#pragma unroll
+            for (int k = 0; k < IT; ++k)
+                nib |= kw.keeps(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), id + k) ? 1u << k : 0u;
+            tile_done(t0, nib);
         }
     }
     store_counts(w, wave_sum_ll(a), red);
