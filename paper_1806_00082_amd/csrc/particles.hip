@@ -366,40 +366,26 @@ __device__ __forceinline__ int pairs_of(const Geo& g, uint32_t id, uint32_t step
     return (int)base + (w->v[0] < t ? 1 : 0);
 }
 
-// Pair count only (postulate II), with (n0, thr) of the particle's cell taken from a
-// per-workgroup LDS table when the mesh is small enough (ct != nullptr), else through
-// cell_slot from global memory.  Only the first Philox word is used.
-
+// The cell of a live particle inside the mesh (the index into a cell-indexed table), else -1.
 template <typename T, int DIM>
-__device__ __forceinline__ int pairs_count(const Geo& g, uint32_t id, uint32_t step, T px, T py,
-                                           int8_t sv, const uint2* ct,
-                                           const int32_t* __restrict__ cell_slot,
-                                           const uint32_t* __restrict__ n0,
-                                           const uint32_t* __restrict__ thr) {
-    if (sv == 0) return 0;
+__device__ __forceinline__ int live_cell(const Geo& g, T px, T py, int8_t sv) {
+    if (sv == 0) return -1;
     const int cx = cell_index<T>(px, g.nx);
-    if (cx < 0) return 0;
-    int c = cx;
-    if (DIM == 2) {
-        const int cy = cell_index<T>(py, g.ny);
-        if (cy < 0) return 0;
-        c = cy * g.nx + cx;
-    }
-    uint32_t base, t;
-    if (ct != nullptr) {
-        const uint2 e = ct[c];
-        base = e.x;
-        t = e.y;
-    } else {
-        const int sl = cell_slot[c];
-        if (sl < 0) return 0;
-        base = n0[sl];
-        t = thr[sl];
-    }
-    if (base == 0 && t == 0) return 0;
+    if (cx < 0) return -1;
+    if (DIM == 1) return cx;
+    const int cy = cell_index<T>(py, g.ny);
+    return cy < 0 ? -1 : cy * g.nx + cx;
+}
+
+// Pair count of a live particle (postulate II) in a cell whose creation-table entry is
+// e = (n0, thr): n0, plus one if the first Philox word of the particle's draw is below thr.
+// The entry comes from a per-workgroup LDS table on small meshes, else from the cell-indexed
+// table gathered each step (cells without a table row hold (0, 0): no pairs).
+__device__ __forceinline__ int pairs_of_entry(const Geo& g, uint32_t id, uint32_t step, uint2 e) {
+    if (e.x == 0 && e.y == 0) return 0;
     const u32x4 w = philox(id, step, 0u, TAG_CREATE, g.seed);
-    if (base >= (1u << 30)) return 1 << 30;
-    return (int)base + (w.v[0] < t ? 1 : 0);
+    if (e.x >= (1u << 30)) return 1 << 30;
+    return (int)e.x + (w.v[0] < e.y ? 1 : 0);
 }
 
 // Smallest t with u < T[t] (T non-decreasing, ending at 2^32 > u), searched in [lo, hi]:
@@ -771,18 +757,29 @@ __global__ __launch_bounds__(PT) void step_count(Geo g, uint32_t step, const int
     }
     long lo, hi;
     wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi, (long)gridDim.x * WPB);
+    const int lane = threadIdx.x & 63;
     long long cnt = 0;
+    // A particle's (n0, thr) entry depends on its position: the entries of a tile are requested
+    // (unconditionally: a particle without a cell reads entry 0 and ignores it) before the
+    // next tile's positions, and the draws follow.  (Taking two or four tiles per round trip
+    // raised the registers and was slower.)
     Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
-    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
-    for (long t0 = lo; t0 < hi; t0 += WT) {
-        const long id = t0 + IT * (threadIdx.x & 63);
-        Part4<T, DIM> p = nxt;
+    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
+    for (long t0 = lo; t0 < hi; t0 += WT) {  // per wave, no workgroup barriers
+        const long id = t0 + IT * lane;
+        uint2 e[IT];
+        int8_t sv[IT];
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int c = live_cell<T, DIM>(g, nxt.x[k], nxt.y[k], nxt.s[k]);
+            sv[k] = c < 0 ? (int8_t)0 : nxt.s[k];
+            e[k] = ct[c < 0 ? 0 : c];
+        }
         load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
         int np[IT];
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
-            np[k] = pairs_count<T, DIM>(g, (uint32_t)(id + k), step, p.x[k], p.y[k], p.s[k], ct,
-                                        cell_slot, n0, thr);
+            np[k] = sv[k] == 0 ? 0 : pairs_of_entry(g, (uint32_t)(id + k), step, e[k]);
             cnt += np[k];
         }
         store_np4<T>(xo, so, id, hi, np);  // for pass 2
