@@ -47,7 +47,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # taken again.
 TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1347, "annih_bins": 0.0008,
                   "annih_count": 0.0626, "annih_write": 0.1224},
-           "2d": {"step_count": 0.7616, "step_apply": 2.4744, "annih_bins": 0.1211,
+           "2d": {"step_count": 0.7616, "step_apply": 2.4744, "annih_bins": 0.1212,
                   "annih_count": 0.3077, "annih_write": 1.2751}}
 
 

@@ -429,6 +429,16 @@ __device__ __forceinline__ long long wave_incl_scan_ll(long long v) {
     return v;
 }
 
+// Sum over the wave of values in [0, 2^33), one per lane (all lanes active), exact: two 32-bit
+// DPP scans, of the low 24 bits (sum below 2^30) and of the rest (below 2^15), instead of
+// six rounds of 64-bit shuffles, each an LDS round trip.
+__device__ __forceinline__ long long wave_sum_nonneg33(long long v) {
+    const int lo = (int)(v & 0xFFFFFF), hi = (int)(v >> 24);
+    const int slo = __builtin_amdgcn_readlane(wave_incl_scan(lo), 63);
+    const int shi = __builtin_amdgcn_readlane(wave_incl_scan(hi), 63);
+    return ((long long)shi << 24) + slo;
+}
+
 // Sum over the block of one int64 per thread (PT threads); the result is valid in every
 // thread.
 __device__ __forceinline__ long long block_sum_ll(long long v, long long* redw) {
@@ -1228,7 +1238,9 @@ __global__ __launch_bounds__(PT) void annih_bins(Geo g, BinCount bc, int place, 
                 mb |= (b < g.n_bins && bc.mixed(b)) ? 1u << k : 0u;
             }
         }
-        const long long t = place ? wave_sum_ll((long long)cnt[0] + cnt[1] + cnt[2] + cnt[3]) : 0;
+        // the chunk's particles to place; from a histogram every lane's sum is in [0, 2^33)
+        const long long ls = (long long)cnt[0] + cnt[1] + cnt[2] + cnt[3];
+        const long long t = !place ? 0 : bc.counts == nullptr ? wave_sum_nonneg33(ls) : wave_sum_ll(ls);
         mixed += __popc(mb);
         if (lane == 0) {
             w.csum[j] = (int)t;  // < 2^31 whenever the capacity check passes
