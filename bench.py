@@ -45,10 +45,10 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # by what the counters read for a 1 GiB device copy (fetch x2.0, write x1.0).  Taken for the
 # kernels as they are now; an entry is dropped when its kernel changes until the counters are
 # taken again.
-TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1347, "annih_bins": 0.0008,
+TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1353, "annih_bins": 0.0008,
                   "annih_count": 0.0626, "annih_write": 0.1224},
-           "2d": {"step_count": 0.7616, "step_apply": 2.4744, "annih_bins": 0.1212,
-                  "annih_count": 0.3077, "annih_write": 1.2751}}
+           "2d": {"step_count": 0.7616, "step_apply": 2.4724, "annih_bins": 0.1212,
+                  "annih_count": 0.3085, "annih_write": 1.2751}}
 
 
 def _events():

@@ -261,6 +261,96 @@ __device__ __forceinline__ void load4(const T* x, const T* y, const MT* M, const
     }
 }
 
+// The same four particles as loaded, momenta and signs still packed in the words the loads
+// return.  A prefetch of the next tile is carried across the loop in this form: unpacking
+// (sign-extending) at the load would make the wave wait for the loads right there, while
+// unpack() at the top of the next iteration waits only when the values are needed.
+template <typename MT> struct Packed4;  // four MT in one load
+template <> struct Packed4<int8_t> { using type = uint32_t; };
+template <> struct Packed4<int16_t> { using type = uint2; };
+template <> struct Packed4<int32_t> { using type = int4; };
+
+template <typename T, typename MT, int DIM>
+struct Raw4 {
+    T x[IT], y[IT];
+    typename Packed4<MT>::type m, my;
+    uint32_t s;
+};
+
+template <typename T, typename MT, int DIM>
+__device__ __forceinline__ void load4r(const T* x, const T* y, const MT* M, const MT* My,
+                                       const int8_t* s, long id, long hi, Raw4<T, MT, DIM>& r) {
+    using PW = typename Packed4<MT>::type;
+    static_assert(sizeof(PW) == IT * sizeof(MT), "four momenta per packed word");
+    if (id + IT <= hi) {
+        ld4(x, id, r.x);
+        r.m = *reinterpret_cast<const PW*>(M + id);
+        r.s = *reinterpret_cast<const uint32_t*>(s + id);
+        if (DIM == 2) {
+            ld4(y, id, r.y);
+            r.my = *reinterpret_cast<const PW*>(My + id);
+        }
+    } else {
+        MT mm[IT], mmy[IT];
+        int8_t ss[IT];
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const bool v = id + k < hi;
+            r.x[k] = v ? x[id + k] : (T)0;
+            mm[k] = v ? M[id + k] : (MT)0;
+            ss[k] = v ? s[id + k] : (int8_t)0;
+            r.y[k] = (DIM == 2 && v) ? y[id + k] : (T)0;
+            mmy[k] = (DIM == 2 && v) ? My[id + k] : (MT)0;
+        }
+        __builtin_memcpy(&r.m, mm, sizeof(PW));
+        __builtin_memcpy(&r.my, mmy, sizeof(PW));
+        __builtin_memcpy(&r.s, ss, sizeof(uint32_t));
+    }
+    if (DIM == 1) {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) r.y[k] = (T)0;
+        __builtin_memset(&r.my, 0, sizeof(PW));
+    }
+}
+
+// An empty asm statement that takes a register and gives it back: the compiler cannot look
+// through it, so it keeps a packed word whole until this point instead of splitting it into
+// bytes right after its load (which waits for the load there).
+__device__ __forceinline__ void opaque(uint32_t& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void opaque(uint2& v) {
+    asm volatile("" : "+v"(v.x));
+    asm volatile("" : "+v"(v.y));
+}
+__device__ __forceinline__ void opaque(int4& v) {
+    asm volatile("" : "+v"(v.x));
+    asm volatile("" : "+v"(v.y));
+    asm volatile("" : "+v"(v.z));
+    asm volatile("" : "+v"(v.w));
+}
+
+// Part4 of what load4r loaded: the same values load4 gives.
+template <typename T, typename MT, int DIM>
+__device__ __forceinline__ Part4<T, DIM> unpack(Raw4<T, MT, DIM> r) {
+    Part4<T, DIM> p;
+    opaque(r.m);
+    opaque(r.s);
+    if (DIM == 2) opaque(r.my);
+    MT mm[IT], mmy[IT];
+    int8_t ss[IT];
+    __builtin_memcpy(mm, &r.m, sizeof(mm));
+    __builtin_memcpy(mmy, &r.my, sizeof(mmy));
+    __builtin_memcpy(ss, &r.s, sizeof(ss));
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        p.x[k] = r.x[k];
+        p.y[k] = r.y[k];
+        p.m[k] = mm[k];
+        p.my[k] = mmy[k];
+        p.s[k] = ss[k];
+    }
+    return p;
+}
+
 // Histogram keys of four consecutive particles (id a multiple of 4); slots at or beyond hi
 // read as HKEY_NONE.
 __device__ __forceinline__ void load_keys4(const uint32_t* keys, long id, long hi, uint32_t* k4) {
@@ -929,12 +1019,12 @@ __global__ __launch_bounds__(PT) void step_apply(Geo g, uint32_t step, const int
         }
         wave_lds_sync();  // the entries are reused by later particles
     };
-    Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
-    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
+    Raw4<T, MT, DIM> nxt;  // the next wave tile's loads stay in flight during this one
+    load4r<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
     for (long t0 = lo; t0 < hi; t0 += WT) {  // per wave, no workgroup barriers
         const long id = t0 + IT * lane;
-        Part4<T, DIM> p = nxt;
-        load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+        Part4<T, DIM> p = unpack(nxt);
+        load4r<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
         int np[IT];
         load_np4<T>(xo, so, id, hi, np);  // left by pass 1 (before the parents overwrite it below)
         // after the capacity check all pairs of the step number below 2^30: 32-bit sums
@@ -1092,12 +1182,12 @@ __global__ __launch_bounds__(PT) void annih_hist(Geo g, const T* x, const T* y, 
     wave_chunk(n, (long)blockIdx.x * WPB + (threadIdx.x >> 6), &lo, &hi);
     HistWindow<HW, DIM == 2, DIM == 2> hw{lh, 0, hist, g.n_bins, bmap, blkmap, g.bshift};
     hw.init(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), wmin);
-    Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
-    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
+    Raw4<T, MT, DIM> nxt;  // the next wave tile's loads stay in flight during this one
+    load4r<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
     for (long t0 = lo; t0 < hi; t0 += WT) {
         const long id = t0 + IT * (threadIdx.x & 63);
-        Part4<T, DIM> p = nxt;
-        load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+        Part4<T, DIM> p = unpack(nxt);
+        load4r<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
 #pragma unroll
         for (int k = 0; k < IT; ++k)
             hw.add_wave(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k]), p.s[k]);
@@ -1179,12 +1269,12 @@ __global__ __launch_bounds__(PT) void annih_count(Geo g, const T* x, const T* y,
     } else {
         const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin,
                                           w.mixbits, 8 * g.n_chunks, flags);
-        Part4<T, DIM> nxt;  // the next wave tile's loads stay in flight during this one
-        load4<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
+        Raw4<T, MT, DIM> nxt;  // the next wave tile's loads stay in flight during this one
+        load4r<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
         for (long t0 = lo; t0 < hi; t0 += WT) {
             const long id = t0 + IT * lane;
-            Part4<T, DIM> p = nxt;
-            load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+            Part4<T, DIM> p = unpack(nxt);
+            load4r<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
             uint32_t nib = 0;
 #pragma unroll
             for (int k = 0; k < IT; ++k)
@@ -1699,12 +1789,12 @@ __global__ __launch_bounds__(PT) void pair_count(Geo g, const T* x, const T* y, 
     const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin,
                                       w.mixbits, 8 * g.n_chunks, nullptr);
     long long a = 0;
-    Part4<T, DIM> nxt;
-    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
+    Raw4<T, MT, DIM> nxt;
+    load4r<T, MT, DIM>(x, y, M, My, s, lo + IT * (threadIdx.x & 63), hi, nxt);
     for (long t0 = lo; t0 < hi; t0 += WT) {
         const long id = t0 + IT * (threadIdx.x & 63);
-        Part4<T, DIM> p = nxt;
-        load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+        Part4<T, DIM> p = unpack(nxt);
+        load4r<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
 #pragma unroll
         for (int k = 0; k < IT; ++k)
             a += kw.mixed(bin_val<T, DIM>(g, p.x[k], p.y[k], p.m[k], p.my[k], p.s[k])) ? 1 : 0;
@@ -1754,12 +1844,12 @@ __global__ __launch_bounds__(PT) void pair_write(Geo g, const T* x, const T* y, 
     const KeepWindow kw = keep_window(first_bin<T, MT, DIM>(g, x, y, M, My, s, lo, hi), lw, wmin,
                                       w.mixbits, 8 * g.n_chunks, nullptr);
     long long run = q.woff[(long)blockIdx.x * WPB + (threadIdx.x >> 6)];
-    Part4<T, DIM> nxt;
-    load4<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
+    Raw4<T, MT, DIM> nxt;
+    load4r<T, MT, DIM>(x, y, M, My, s, lo + IT * lane, hi, nxt);
     for (long t0 = lo; t0 < hi; t0 += WT) {
         const long id = t0 + IT * lane;
-        Part4<T, DIM> p = nxt;
-        load4<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
+        Part4<T, DIM> p = unpack(nxt);
+        load4r<T, MT, DIM>(x, y, M, My, s, id + WT, hi, nxt);
         // every keep flag starts at 0 (coalesced here); pair_flags sets those of the kept ones
         if (id + IT <= hi) {
             *reinterpret_cast<uchar4*>(q.flags + id) = make_uchar4(0, 0, 0, 0);
