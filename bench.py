@@ -47,8 +47,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "
 # taken again.
 TRAFFIC = {"1d": {"step_count": 0.0611, "step_apply": 0.1353, "annih_bins": 0.0008,
                   "annih_count": 0.0626, "annih_write": 0.1224},
-           "2d": {"step_count": 0.7616, "step_apply": 2.4724, "annih_bins": 0.1212,
-                  "annih_count": 0.3085, "annih_write": 1.2751}}
+           "2d": {"step_count": 0.7616, "step_apply": 2.4723, "annih_bins": 0.1212,
+                  "annih_count": 0.3085, "annih_write": 1.2755}}
 
 
 def _events():

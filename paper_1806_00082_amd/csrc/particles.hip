@@ -1426,8 +1426,19 @@ __device__ void place_chunk_wave(const Geo& g, const BinCount& bc, int mode, uin
     }
     const int lo_c = (int)(max(s_lo, ch_start) - ch_start);            // slots of this chunk
     const int hi_c = (int)(min(s_hi, ch_start + cnt_ch) - ch_start);   // to fill: [lo_c, hi_c)
+    // A slot's bin is the first j with bo_in[j] > rel (bo_in[BC - 1] = cnt_ch exceeds every
+    // slot).  The last offsets of the first 15 groups of 16 bins, read once (the same for
+    // every lane), give a slot's group by compares; a search of its 16 entries follows: five
+    // dependent LDS reads per slot instead of nine.
+    static_assert(BC == 256, "16 groups of 16 bins");
+    int cb[15];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) cb[i] = __builtin_amdgcn_readfirstlane(bo_in[16 * i + 15]);
     for (int rel = lo_c + lane; rel < hi_c; rel += 64) {
-        const int j = upper_bound_lds(bo_in, BC, rel);
+        int gi = 0;
+#pragma unroll
+        for (int i = 0; i < 15; ++i) gi += cb[i] <= rel ? 1 : 0;
+        const int j = 16 * gi + upper_bound_lds(bo_in + 16 * gi, 16, rel);
         const int r = rel - (j ? bo_in[j - 1] : 0);
         const long bb = ch * BC + j;
         const long o = ch_start + rel;
